@@ -1,0 +1,201 @@
+/*
+ * dmrgtst.h -- C ABI of libdmrgtst.so: the hot path of time-step-targeting DMRG on one
+ * MI355X (gfx950) GPU.
+ *
+ * Scope (paper: Alvarez, Dias da Silva, Ponce, Dagotto, "Time Evolution with the DMRG
+ * Algorithm: A Generic Implementation for Strongly Correlated Electronic Systems"):
+ *   - the superblock Hamiltonian-vector product H_sb.psi, the "Hamiltonian connections between
+ *     system and environment" that Sec. IV names as the most expensive task;
+ *   - the Krylov (Lanczos) exponential of Sec. II.A, repeated for longer times as in Sec. II.C
+ *     (Eq. lanczosevolution2);
+ *   - the time-step-targeting vectors phi(t_x) and their weights (Sec. II.B and II.C).
+ *
+ * Superblock and vectors
+ *   The superblock is S (x) E: S = left block + site s1, E = site s2 + right block, fermion
+ *   modes of S ordered before those of E.  Both halves are split into symmetry sectors
+ *   labelled (N_up, N_dn).  A vector of the target sector (N_up, N_dn) is a set of blocks
+ *   Psi_p (dim_S(p) x dim_E(q), q = target - p), one per S sector p whose partner q exists.
+ *   Layout of one vector: 2n doubles, all real parts first, then all imaginary parts; inside
+ *   each plane the blocks follow ascending S-sector order and each block is column-major.
+ *   dmrg_psi_layout() reports n and the block table.
+ *
+ *   H_sb = H_S (x) 1 + 1 (x) H_E + sum_terms coef (A P_S^f) (x) B
+ *   where (A (x) B) acts on the coefficient matrix X as A X B^T and P_S is the fermion parity
+ *   of S (present when the term is fermionic).  A hopping bond -t sum_s (c+_a c_b + h.c.)
+ *   between an S site a and an E site b expands into the four terms
+ *     -t (C+_a P_S) (x) (C+_b)^T   and   +t ((C+_a)^T P_S) (x) C+_b      for s = up, down.
+ *   The library computes exp(-i tau H); the paper's exp(+iHt) is tau -> -tau.
+ *
+ * Memory
+ *   Problem data passed to dmrg_create() is host memory; it is deep-copied to device memory
+ *   owned by the handle and may be freed on return.  Vectors (x, y, phi, targets) are device
+ *   pointers owned by the caller.  All work is ordered on the handle's HIP stream (passed as
+ *   a void* hipStream_t; NULL = the default stream).
+ *
+ * Errors
+ *   Every function returns a dmrg_status (0 = success, negative = error).  No C++ exception
+ *   crosses the boundary.  dmrg_last_error() returns a description of the last failure on a
+ *   handle.  Lanczos breakdown is not an error: it is reported in dmrg_krylov_info and the
+ *   result is then exact.
+ *
+ * Threads: a handle is used by one host thread at a time.
+ */
+#ifndef DMRGTST_H
+#define DMRGTST_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dmrg_ctx* dmrg_handle;
+typedef struct dmrg_batch_ctx* dmrg_batch;
+
+enum dmrg_status {
+    DMRG_OK = 0,
+    DMRG_EINVAL = -1,     /* invalid argument or inconsistent problem description        */
+    DMRG_ENOMEM = -2,     /* device or host allocation failed                             */
+    DMRG_EHIP = -3,       /* a HIP runtime call failed                                    */
+    DMRG_ENONFINITE = -4, /* non-finite value met where finite input is required          */
+    DMRG_ESTATE = -5      /* call not valid in the handle's current state                 */
+};
+
+/* Arithmetic of the block products (the Lanczos recurrence, the reorthogonalisation, the
+ * tridiagonal eigen-decomposition and the combination always stay FP64). */
+enum dmrg_precision {
+    DMRG_FP64 = 0,        /* FP64 MFMA                                                    */
+    DMRG_FP32 = 1,        /* FP32 operands and FP32 MFMA accumulation, result promoted     */
+    DMRG_BF16X3 = 2       /* split bf16 hi/lo products a0b0 + a0b1 + a1b0, FP32 accumulate */
+};
+
+/* A block operator of one half that changes (N_up, N_dn) by dq.  blocks: for every source
+ * sector p in ascending order whose image p+dq is a sector of the half, one dense
+ * dim(p+dq) x dim(p) column-major block, all concatenated. */
+typedef struct {
+    int32_t dq[2];
+    const double* blocks;
+} dmrg_op;
+
+/* One superblock half.  qn: nsec pairs (N_up, N_dn), strictly increasing in lexicographic
+ * order; dim: nsec positive sizes; H: per-sector dim x dim symmetric blocks, column-major,
+ * concatenated in sector order; ops: nop block operators (typically the c+ of edge sites). */
+typedef struct {
+    int32_t nsec;
+    const int32_t* qn;
+    const int32_t* dim;
+    const double* H;
+    int32_t nop;
+    const dmrg_op* ops;
+} dmrg_half;
+
+/* Generic connection term coef (A P_S^fermionic) (x) B with A = S.ops[opS] (transposed when
+ * transS != 0) and B = E.ops[opE] (transposed when transE != 0).  The quantum-number changes
+ * of A and B must cancel. */
+typedef struct {
+    double coef;
+    int32_t opS, transS;
+    int32_t opE, transE;
+    int32_t fermionic;
+} dmrg_term;
+
+/* Hopping bond -t sum_s (c+_{a s} c_{b s} + h.c.): opS[s] = index of c+_{a s} in S.ops,
+ * opE[s] = index of c+_{b s} in E.ops (s = 0 up, 1 down). */
+typedef struct {
+    int32_t opS[2];
+    int32_t opE[2];
+    double t;
+} dmrg_bond;
+
+typedef struct {
+    dmrg_half S, E;
+    int32_t target[2];
+    int32_t nbond;
+    const dmrg_bond* bonds;
+    int32_t nterm;
+    const dmrg_term* terms;
+} dmrg_problem;
+
+/* Krylov diagnostics (host struct).  k_eff: Lanczos vectors used in the last step (kdim
+ * unless breakdown); k_eff_min over all steps; beta0 = ||x|| of the first step; beta_last =
+ * last computed beta of the last step; err_est = beta_k |c_{k-1}(tau)| of the last step (an
+ * upper estimate of the step's truncation error, 0 after breakdown); breakdown = 1 if any
+ * step broke down (invariant subspace found, result exact). */
+typedef struct {
+    int32_t k_eff;
+    int32_t k_eff_min;
+    double beta0;
+    double beta_last;
+    double err_est;
+    int32_t breakdown;
+} dmrg_krylov_info;
+
+/* Builds the sector tables, the block work lists and the packed device copies of all
+ * operators (Sec. IV: the Hamiltonian connections).  stream: hipStream_t or NULL.
+ * Errors: DMRG_EINVAL for malformed input (unsorted or repeated sectors, non-positive
+ * dims, out-of-range op indices, terms whose dq do not cancel, empty target sector),
+ * DMRG_ENOMEM, DMRG_EHIP.  On error *out is set to NULL. */
+int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out);
+
+/* Releases all device memory of the handle (waits for its stream).  NULL is ignored. */
+void dmrg_destroy(dmrg_handle h);
+
+/* Vector layout: *n = complex length (a vector is 2n doubles); *nblk = number of blocks.
+ * If the array pointers are non-NULL they receive, per block: off = offset inside a plane,
+ * rows = dim_S(p), cols = dim_E(q), secS = p, secE = q.  Any pointer may be NULL. */
+int dmrg_psi_layout(dmrg_handle h, int64_t* n, int32_t* nblk, int64_t* off, int32_t* rows,
+                    int32_t* cols, int32_t* secS, int32_t* secE);
+
+/* Algorithmic flops of one H_sb.psi for one complex vector: both real planes, two flops per
+ * multiply-add, non-zero blocks only, the contraction order the library uses. */
+int dmrg_flops(dmrg_handle h, double* flops);
+
+/* Selects the block-product arithmetic; converted operator copies are built on first use and
+ * cached.  DMRG_EINVAL for an unknown value. */
+int dmrg_set_precision(dmrg_handle h, int32_t precision);
+
+/* Changes the stream all later work of the handle is ordered on. */
+int dmrg_set_stream(dmrg_handle h, void* stream);
+
+/* y = H_sb x for nvec vectors stored back to back (2n doubles each), device pointers.
+ * x and y must not overlap.  Asynchronous on the handle's stream. */
+int dmrg_matvec(dmrg_handle h, const double* x, double* y, int32_t nvec);
+
+/* y = (exp(-i tau H_sb))^nsteps x: nsteps Krylov steps of size kdim (1 <= kdim <= 64), each
+ * from a fresh Lanczos basis of the current vector (Sec. II.A, Eq. lanczosevolution2).
+ * x, y: device vectors; y may equal x.  If info is non-NULL the call waits for the stream
+ * and fills it; otherwise it is asynchronous. */
+int dmrg_krylov_expm(dmrg_handle h, const double* x, double* y, double tau, int32_t kdim,
+                     int32_t nsteps, dmrg_krylov_info* info);
+
+/* Time-step targeting (Sec. II.B, II.C): from one Krylov basis of phi, the four vectors
+ * phi(t_x) = exp(-i t_x H) phi at t_x = 0, tau/3, 2tau/3, tau, written to targets (device,
+ * 4 x 2n doubles), and the five density-matrix weights [ground state, t_0, t_1, t_2, t_3] =
+ * [2W, 2W, W, W, 2W], W = 1/8 (host array, may be NULL).  The next interval starts from
+ * targets[3].  info as in dmrg_krylov_expm. */
+int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim,
+                     double* targets, double* weights, dmrg_krylov_info* info);
+
+/* Batched time-step targeting over independent superblocks (handles created beforehand; the
+ * batch keeps references, the handles must outlive it).  The batch runs on the first
+ * handle's stream. */
+int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out);
+void dmrg_batch_destroy(dmrg_batch b);
+
+/* phi[i], targets[i]: device pointers for superblock i (host arrays of count pointers).
+ * infos: NULL or a host array of count structs (then the call waits for the stream). */
+int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, int32_t kdim,
+                           double* const* targets, double* weights, dmrg_krylov_info* infos);
+
+/* Static description of a status code. */
+const char* dmrg_strerror(int status);
+
+/* Description of the last error on a handle (empty string if none; never NULL).  With
+ * h = NULL: the reason the calling thread's last dmrg_create() failed. */
+const char* dmrg_last_error(dmrg_handle h);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DMRGTST_H */

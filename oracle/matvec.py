@@ -64,18 +64,21 @@ def pack(pb, blocks: dict) -> np.ndarray:
 # ------------------------------------------------------------------------------------------
 # connection terms (hopping bonds)
 # ------------------------------------------------------------------------------------------
-def terms(pb):
+def terms(pb, extra_terms=()):
     """Expand every bond into its four Kronecker terms coef * (A P_S) (x) B.
 
     c+_a c_b   -> coef -t, A = C+_a,   B = C_b = (C+_b)^T
     c+_b c_a   -> (P_S C_a) (x) C+_b = -(C_a P_S) (x) C+_b  (C_a flips the parity of S),
                   so coef +t, A = (C+_a)^T, B = C+_b.
-    Each entry: (coef, S-op index, S transposed?, E-op index, E transposed?)."""
+    extra_terms: generic terms (coef, S-op, S transposed?, E-op, E transposed?, fermionic?).
+    Each entry: (coef, S-op index, S transposed?, E-op index, E transposed?, fermionic?)."""
     out = []
     for bd in pb.bonds:
         for s in (0, 1):
-            out.append((-bd.t, bd.opS[s], False, bd.opE[s], True))
-            out.append((+bd.t, bd.opS[s], True, bd.opE[s], False))
+            out.append((-bd.t, bd.opS[s], False, bd.opE[s], True, True))
+            out.append((+bd.t, bd.opS[s], True, bd.opE[s], False, True))
+    for t in extra_terms:
+        out.append((float(t[0]), int(t[1]), bool(t[2]), int(t[3]), bool(t[4]), bool(t[5])))
     return out
 
 
@@ -91,10 +94,11 @@ def _op_block(space, op, src: int, transposed: bool):
     return pre, op.blocks[pre].T
 
 
-def matvec_sector(pb, x: np.ndarray) -> np.ndarray:
+def matvec_sector(pb, x: np.ndarray, extra_terms=()) -> np.ndarray:
     """Y = H_sb X per symmetry block.  Source block p (E sector q) contributes
         Y_p           += H_S[p] X_p + X_p H_E[q]^T
-        Y_{p'}        += coef * (-1)^{N(p)} * A[p' <- p] X_p B[q' <- q]^T   for each term."""
+        Y_{p'}        += coef * (-1)^{N(p)} * A[p' <- p] X_p B[q' <- q]^T   for each term
+    (the sign only for fermionic terms)."""
     X = unpack(pb, x)
     lay, n = layout(pb)
     qof = {p: q for (p, q, r, c, off) in lay}
@@ -102,7 +106,7 @@ def matvec_sector(pb, x: np.ndarray) -> np.ndarray:
     for p, Xp in X.items():
         q = qof[p]
         Y[p] += pb.S.H[p] @ Xp + Xp @ pb.E.H[q].T
-    for (coef, a, ta, b, tb) in terms(pb):
+    for (coef, a, ta, b, tb, ferm) in terms(pb, extra_terms):
         for p, Xp in X.items():
             A = _op_block(pb.S.space, pb.S.ops[a], p, ta)
             B = _op_block(pb.E.space, pb.E.ops[b], qof[p], tb)
@@ -113,7 +117,8 @@ def matvec_sector(pb, x: np.ndarray) -> np.ndarray:
             if p2 not in Y:
                 continue
             assert qof[p2] == q2
-            Y[p2] += (coef * pb.S.space.parity(p)) * (Ab @ Xp @ Bb.T)
+            sign = pb.S.space.parity(p) if ferm else 1.0
+            Y[p2] += (coef * sign) * (Ab @ Xp @ Bb.T)
     return pack(pb, Y)
 
 
@@ -189,7 +194,7 @@ def flop_count(pb) -> int:
     F = 0
     for (p, q, r, c, off) in lay:
         F += 2 * (2 * r * r * c + 2 * r * c * c)
-    for (coef, a, ta, b, tb) in terms(pb):
+    for (coef, a, ta, b, tb, ferm) in terms(pb):
         for (p, q, r, c, off) in lay:
             A = _op_block(pb.S.space, pb.S.ops[a], p, ta)
             B = _op_block(pb.E.space, pb.E.ops[b], q, tb)

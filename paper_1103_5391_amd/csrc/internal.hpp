@@ -1,0 +1,94 @@
+// Internal types shared by the host planner and the gfx950 kernels of libdmrgtst.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace dmrg {
+
+constexpr int kMaxKrylov = 64;      // largest kdim accepted
+constexpr int kTile = 32;           // output tile edge of the block-product kernels
+constexpr int kChunk = 16;          // K depth of one register chunk (4 MFMA K-steps of 4)
+constexpr int kWaves = 4;           // waves per work group (split-K among them)
+constexpr int kVecThreads = 256;    // threads per block of the vector kernels
+constexpr int kMaxTimes = 4;        // time points evaluated from one Krylov basis
+
+// Element (r, c) of a matrix view inside a buffer.  Row-split views ("A" operands) place rows
+// r >= split in a second plane at +poff; column-split views ("B" operands and outputs) place
+// columns c >= split in a second plane at +poff.  split >= the extent means no second plane.
+struct View {
+    int64_t off;
+    int64_t poff;
+    int32_t ld;
+    int32_t split;
+};
+
+// Stage 1 (right products) of one source block b:  T_b = X_b * R_b
+//   X_b: 2d x e, rows 0..d-1 = real plane of Psi_b, rows d..2d-1 = imaginary plane
+//   R_b: e x N column-major, [H_E(q)^T | right factors of every term leaving b]
+//   T_b: 2d x N column-major (ld 2d), workspace
+struct S1Block {
+    int32_t M, K, N, prob;
+    View X;           // into the input vector
+    int64_t Roff;     // into the packed right-factor buffer (ld = K)
+    int64_t Toff;     // into the workspace (ld = M)
+};
+
+// Stage 2 (left products and sum) of one output block b':
+//   Y_b' (d' x 2e', columns e'.. = imaginary plane) = T0 + sum_seg Acat[:, seg] * B_seg
+//   Acat: d' x Kcat column-major, [H_S(p') | coef*sign*A of every term entering b']
+//   T0: the H_E columns of T_b'
+struct S2Block {
+    int32_t M, N, prob, nseg;
+    int32_t seg0, pad;
+    int64_t Aoff;     // packed left-factor buffer (ld = M)
+    View T0;          // into the workspace
+    View Y;           // into the output vector
+};
+
+// One K segment of a stage-2 block: rows kA.. of Acat times the source view B (K x N).
+struct Segment {
+    int32_t K, kA;
+    int32_t src;      // 0: the input vector (diagonal H_S term), 1: the workspace
+    int32_t pad;
+    View B;
+};
+
+// One 32 x 32 output tile of a stage.
+struct Tile {
+    int32_t blk, m0, n0, pad;
+};
+
+// Per-problem pointers for one launch of a stage (single problem: tables of length 1).
+struct ProbPtrs {
+    const double* x;        // input vector
+    double* y;              // output vector
+    double* T;              // workspace
+    const void* Lops;       // packed left factors (stage 2), precision dependent type
+    const void* Rops;       // packed right factors (stage 1)
+    const double* xscale;   // scale applied to x on load (nullptr = 1)
+    const int* skip;        // nonzero: skip all work of this problem (nullptr = never)
+};
+
+// Device state of one Krylov run on one problem.
+struct KState {
+    double alpha[kMaxKrylov];
+    double beta[kMaxKrylov + 1];      // beta[0] = ||x||
+    double scale[kMaxKrylov + 1];     // 1 / beta[j]: slot j of V holds beta[j] v_j
+    double h1[2 * kMaxKrylov];        // first projection coefficients (re, im interleaved)
+    double h2[2 * kMaxKrylov];        // second projection coefficients
+    double coef[kMaxTimes][2 * kMaxKrylov];  // c(t_x) = beta0 S exp(-i D t_x) S^T e_1
+    double bscale;                    // max(1, |alpha_i|, beta_i) for the breakdown test
+    double err_est;
+    double norm2_out;                 // ||y||^2 of the last combination (chained steps)
+    int32_t keff;
+    int32_t broken;                   // 1 after breakdown (or zero input)
+    int32_t kdim;
+    int32_t eig_fail;                 // tridiagonal QL did not converge
+    int32_t keff_min;                 // over all steps of one call
+    int32_t any_break;                // over all steps of one call
+    double beta0_first;               // ||x|| of the first step of one call
+    uint32_t counter[4];              // arrival counters of the reduction kernels
+};
+
+}  // namespace dmrg

@@ -1,0 +1,315 @@
+"""ctypes binding of libdmrgtst.so (C ABI in include/dmrgtst.h).
+
+Argument marshalling only: every step of H_sb.psi, the Krylov exponential and time-step
+targeting runs in the library's HIP kernels.  Vectors are torch tensors (float64, contiguous,
+on the GPU) used as plain device buffers; streams are torch's current HIP stream.  There is no
+CPU fallback: loading fails loudly when the library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libdmrgtst.so")
+
+DMRG_FP64, DMRG_FP32, DMRG_BF16X3 = 0, 1, 2
+STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP",
+          -4: "DMRG_ENONFINITE", -5: "DMRG_ESTATE"}
+
+# exported symbols (kept in sync with include/dmrgtst.h; checked by the CPU tests)
+SYMBOLS = [
+    "dmrg_create", "dmrg_destroy", "dmrg_psi_layout", "dmrg_flops", "dmrg_set_precision",
+    "dmrg_set_stream", "dmrg_matvec", "dmrg_krylov_expm", "dmrg_tst_targets",
+    "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_tst_targets", "dmrg_strerror",
+    "dmrg_last_error",
+]
+
+
+class dmrg_op(C.Structure):
+    _fields_ = [("dq", C.c_int32 * 2), ("blocks", C.POINTER(C.c_double))]
+
+
+class dmrg_half(C.Structure):
+    _fields_ = [("nsec", C.c_int32), ("qn", C.POINTER(C.c_int32)), ("dim", C.POINTER(C.c_int32)),
+                ("H", C.POINTER(C.c_double)), ("nop", C.c_int32), ("ops", C.POINTER(dmrg_op))]
+
+
+class dmrg_term(C.Structure):
+    _fields_ = [("coef", C.c_double), ("opS", C.c_int32), ("transS", C.c_int32),
+                ("opE", C.c_int32), ("transE", C.c_int32), ("fermionic", C.c_int32)]
+
+
+class dmrg_bond(C.Structure):
+    _fields_ = [("opS", C.c_int32 * 2), ("opE", C.c_int32 * 2), ("t", C.c_double)]
+
+
+class dmrg_problem(C.Structure):
+    _fields_ = [("S", dmrg_half), ("E", dmrg_half), ("target", C.c_int32 * 2),
+                ("nbond", C.c_int32), ("bonds", C.POINTER(dmrg_bond)),
+                ("nterm", C.c_int32), ("terms", C.POINTER(dmrg_term))]
+
+
+class dmrg_krylov_info(C.Structure):
+    _fields_ = [("k_eff", C.c_int32), ("k_eff_min", C.c_int32), ("beta0", C.c_double),
+                ("beta_last", C.c_double), ("err_est", C.c_double), ("breakdown", C.c_int32)]
+
+    def as_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Loads libdmrgtst.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} not found: build it with `python -m paper_1103_5391_amd.build`")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    P = C.POINTER
+    lib.dmrg_create.argtypes = [P(dmrg_problem), vp, P(vp)]
+    lib.dmrg_destroy.argtypes = [vp]
+    lib.dmrg_destroy.restype = None
+    lib.dmrg_psi_layout.argtypes = [vp, P(i64), P(i32), P(i64), P(i32), P(i32), P(i32), P(i32)]
+    lib.dmrg_flops.argtypes = [vp, P(dbl)]
+    lib.dmrg_set_precision.argtypes = [vp, i32]
+    lib.dmrg_set_stream.argtypes = [vp, vp]
+    lib.dmrg_matvec.argtypes = [vp, vp, vp, i32]
+    lib.dmrg_krylov_expm.argtypes = [vp, vp, vp, dbl, i32, i32, P(dmrg_krylov_info)]
+    lib.dmrg_tst_targets.argtypes = [vp, vp, dbl, i32, vp, P(dbl), P(dmrg_krylov_info)]
+    lib.dmrg_batch_create.argtypes = [P(vp), i32, P(vp)]
+    lib.dmrg_batch_destroy.argtypes = [vp]
+    lib.dmrg_batch_destroy.restype = None
+    lib.dmrg_batch_tst_targets.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl),
+                                           P(dmrg_krylov_info)]
+    lib.dmrg_strerror.argtypes = [i32]
+    lib.dmrg_strerror.restype = C.c_char_p
+    lib.dmrg_last_error.argtypes = [vp]
+    lib.dmrg_last_error.restype = C.c_char_p
+    for s in SYMBOLS:
+        if s not in ("dmrg_destroy", "dmrg_batch_destroy", "dmrg_strerror", "dmrg_last_error"):
+            getattr(lib, s).restype = C.c_int
+    _lib = lib
+    return lib
+
+
+class DmrgError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(rc: int, handle=None):
+    if rc != 0:
+        lib = load()
+        msg = lib.dmrg_last_error(handle).decode()
+        raise DmrgError(rc, msg or lib.dmrg_strerror(rc).decode())
+
+
+def _dptr(a: np.ndarray, ctype):
+    return a.ctypes.data_as(C.POINTER(ctype))
+
+
+def _stream_ptr(stream):
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(int(stream.cuda_stream) if hasattr(stream, "cuda_stream") else int(stream))
+
+
+def _half_to_c(half, keep: list) -> dmrg_half:
+    sp = half.space
+    qn = np.ascontiguousarray(sp.qn, dtype=np.int32).reshape(-1)
+    dim = np.ascontiguousarray(sp.dim, dtype=np.int32)
+    H = np.concatenate([np.asarray(h, dtype=np.float64).reshape(-1, order="F") for h in half.H])
+    ops = (dmrg_op * max(1, len(half.ops)))()
+    for i, op in enumerate(half.ops):
+        # the ABI wants one block for every source sector whose image exists (zeros if absent)
+        parts = []
+        for p in range(len(dim)):
+            p2 = sp.shift(p, op.dq)
+            if p2 is None:
+                continue
+            blk = op.blocks.get(p)
+            if blk is None:
+                blk = np.zeros((int(dim[p2]), int(dim[p])))
+            parts.append(np.asarray(blk, dtype=np.float64).reshape(-1, order="F"))
+        data = np.concatenate(parts) if parts else np.zeros(1)
+        keep.append(data)
+        ops[i].dq[0], ops[i].dq[1] = int(op.dq[0]), int(op.dq[1])
+        ops[i].blocks = _dptr(data, C.c_double)
+    keep.extend([qn, dim, H, ops])
+    h = dmrg_half()
+    h.nsec = len(dim)
+    h.qn = _dptr(qn, C.c_int32)
+    h.dim = _dptr(dim, C.c_int32)
+    h.H = _dptr(H, C.c_double)
+    h.nop = len(half.ops)
+    h.ops = ops
+    return h
+
+
+def problem_to_c(pb, extra_terms=()):
+    """C struct for an inputs.Problem (plus optional generic terms); returns (struct, keepalive)."""
+    keep = []
+    c = dmrg_problem()
+    c.S = _half_to_c(pb.S, keep)
+    c.E = _half_to_c(pb.E, keep)
+    c.target[0], c.target[1] = int(pb.target[0]), int(pb.target[1])
+    bonds = (dmrg_bond * max(1, len(pb.bonds)))()
+    for i, b in enumerate(pb.bonds):
+        bonds[i].opS[0], bonds[i].opS[1] = int(b.opS[0]), int(b.opS[1])
+        bonds[i].opE[0], bonds[i].opE[1] = int(b.opE[0]), int(b.opE[1])
+        bonds[i].t = float(b.t)
+    c.nbond = len(pb.bonds)
+    c.bonds = bonds
+    terms = (dmrg_term * max(1, len(extra_terms)))()
+    for i, t in enumerate(extra_terms):
+        terms[i].coef, terms[i].opS, terms[i].transS = float(t[0]), int(t[1]), int(t[2])
+        terms[i].opE, terms[i].transE, terms[i].fermionic = int(t[3]), int(t[4]), int(t[5])
+    c.nterm = len(extra_terms)
+    c.terms = terms
+    keep.extend([bonds, terms])
+    return c, keep
+
+
+def _tensor_ptr(t, n2: int, count: int = 1):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64
+            and t.is_contiguous() and t.numel() >= n2 * count):
+        raise ValueError("expected a contiguous float64 GPU tensor of at least "
+                         f"{n2 * count} elements")
+    return C.c_void_p(t.data_ptr())
+
+
+def dmrg_create(pb, stream=None, extra_terms=()):
+    """Creates a handle for an inputs.Problem; returns a Handle."""
+    lib = load()
+    cpb, keep = problem_to_c(pb, extra_terms)
+    h = C.c_void_p()
+    rc = lib.dmrg_create(C.byref(cpb), _stream_ptr(stream), C.byref(h))
+    if rc != 0:
+        raise DmrgError(rc, lib.dmrg_last_error(None).decode())
+    return Handle(h)
+
+
+class Handle:
+    def __init__(self, h: C.c_void_p):
+        self.h = h
+        self.lib = load()
+        n, nb = C.c_int64(), C.c_int32()
+        _check(self.lib.dmrg_psi_layout(h, C.byref(n), C.byref(nb), None, None, None, None, None), h)
+        self.n, self.nblk = int(n.value), int(nb.value)
+
+    def dmrg_destroy(self):
+        if self.h:
+            self.lib.dmrg_destroy(self.h)
+            self.h = None
+
+    destroy = dmrg_destroy
+
+    def __del__(self):
+        try:
+            self.dmrg_destroy()
+        except Exception:
+            pass
+
+    def dmrg_psi_layout(self):
+        nb = self.nblk
+        off = np.zeros(nb, np.int64)
+        arr = [np.zeros(nb, np.int32) for _ in range(4)]
+        _check(self.lib.dmrg_psi_layout(self.h, None, None, _dptr(off, C.c_int64),
+                                        *[_dptr(a, C.c_int32) for a in arr]), self.h)
+        return dict(n=self.n, off=off, rows=arr[0], cols=arr[1], secS=arr[2], secE=arr[3])
+
+    psi_layout = dmrg_psi_layout
+
+    def dmrg_flops(self) -> float:
+        f = C.c_double()
+        _check(self.lib.dmrg_flops(self.h, C.byref(f)), self.h)
+        return f.value
+
+    flops = dmrg_flops
+
+    def dmrg_set_precision(self, prec: int):
+        _check(self.lib.dmrg_set_precision(self.h, int(prec)), self.h)
+
+    set_precision = dmrg_set_precision
+
+    def dmrg_set_stream(self, stream):
+        _check(self.lib.dmrg_set_stream(self.h, _stream_ptr(stream)), self.h)
+
+    set_stream = dmrg_set_stream
+
+    def dmrg_matvec(self, x, y, nvec: int = 1):
+        n2 = 2 * self.n
+        _check(self.lib.dmrg_matvec(self.h, _tensor_ptr(x, n2, nvec), _tensor_ptr(y, n2, nvec),
+                                    int(nvec)), self.h)
+
+    matvec = dmrg_matvec
+
+    def dmrg_krylov_expm(self, x, y, tau: float, kdim: int, nsteps: int = 1, info: bool = True):
+        n2 = 2 * self.n
+        inf = dmrg_krylov_info()
+        _check(self.lib.dmrg_krylov_expm(self.h, _tensor_ptr(x, n2), _tensor_ptr(y, n2),
+                                         float(tau), int(kdim), int(nsteps),
+                                         C.byref(inf) if info else None), self.h)
+        return inf.as_dict() if info else None
+
+    krylov_expm = dmrg_krylov_expm
+
+    def dmrg_tst_targets(self, phi, tau: float, kdim: int, targets, info: bool = True):
+        n2 = 2 * self.n
+        w = np.zeros(5)
+        inf = dmrg_krylov_info()
+        _check(self.lib.dmrg_tst_targets(self.h, _tensor_ptr(phi, n2), float(tau), int(kdim),
+                                         _tensor_ptr(targets, n2, 4), _dptr(w, C.c_double),
+                                         C.byref(inf) if info else None), self.h)
+        return w, (inf.as_dict() if info else None)
+
+    tst_targets = dmrg_tst_targets
+
+
+class Batch:
+    """Batched time-step targeting over independent handles."""
+
+    def __init__(self, handles):
+        self.lib = load()
+        self.handles = list(handles)
+        arr = (C.c_void_p * len(self.handles))(*[h.h for h in self.handles])
+        b = C.c_void_p()
+        rc = self.lib.dmrg_batch_create(arr, len(self.handles), C.byref(b))
+        if rc != 0:
+            raise DmrgError(rc, "dmrg_batch_create")
+        self.b = b
+
+    def dmrg_batch_tst_targets(self, phis, tau: float, kdim: int, targets, info: bool = True):
+        cnt = len(self.handles)
+        ph = (C.c_void_p * cnt)(*[_tensor_ptr(p, 2 * h.n).value for p, h in zip(phis, self.handles)])
+        tg = (C.c_void_p * cnt)(*[_tensor_ptr(t, 2 * h.n, 4).value for t, h in zip(targets, self.handles)])
+        w = np.zeros(5)
+        infos = (dmrg_krylov_info * cnt)()
+        rc = self.lib.dmrg_batch_tst_targets(self.b, ph, float(tau), int(kdim), tg,
+                                             _dptr(w, C.c_double), infos if info else None)
+        if rc != 0:
+            raise DmrgError(rc, "dmrg_batch_tst_targets")
+        return w, ([i.as_dict() for i in infos] if info else None)
+
+    batch_tst_targets = dmrg_batch_tst_targets
+
+    def dmrg_batch_destroy(self):
+        if self.b:
+            self.lib.dmrg_batch_destroy(self.b)
+            self.b = None
+
+    def __del__(self):
+        try:
+            self.dmrg_batch_destroy()
+        except Exception:
+            pass

@@ -1,0 +1,287 @@
+"""GPU parity of the HIP library against the FP64 oracle (needs an MI355X).
+
+Every case is compared element by element on the same seeded inputs.  Tolerances:
+H_sb.psi <= 1e-12 relative (FP64 block products, sums of at most a few thousand terms), Krylov
+steps and time-step-targeting vectors <= 1e-10 relative (the FP64 target), as
+||gpu - oracle||_2 / ||oracle||_2 over the whole 2n-vector.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import krylov as K
+from oracle import matvec as M
+from paper_1103_5391_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+MV_TOL = 1e-12
+KR_TOL = 1e-10
+
+
+def say(*a):
+    print("[gpu-case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    from paper_1103_5391_amd import lib as L
+    L.load()
+    return torch, L
+
+
+def _dev(torch, x):
+    return torch.from_numpy(np.ascontiguousarray(x)).to("cuda")
+
+
+def _host(t):
+    return t.detach().cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+_PROBLEMS = {}
+
+
+def problem(name):
+    if name not in _PROBLEMS:
+        if name in I.WORKLOADS:
+            _PROBLEMS[name] = I.make_workload(name)
+        elif name == "chain12_m30":
+            _PROBLEMS[name] = I.synthetic_problem(12, 30, 4.0, I.chain_bonds(12), 7, name=name)
+        elif name == "ladder2x6_m40":
+            _PROBLEMS[name] = I.synthetic_problem(12, 40, 8.0, I.ladder_bonds(6), 8, name=name)
+        elif name == "chain14_m25_off":
+            _PROBLEMS[name] = I.synthetic_problem(14, 25, 2.0, I.chain_bonds(14), 9, name=name,
+                                                  target=(6, 8))
+        elif name == "chain20_m150":
+            _PROBLEMS[name] = I.synthetic_problem(20, 150, 4.0, I.chain_bonds(20), 12, name=name)
+        elif name == "ladder2x4_U10":
+            _PROBLEMS[name] = I.exact_problem(8, 10.0, (4, 4), bonds=I.ladder_bonds(4, 1.0, 0.5))
+        elif name == "chain4_exact":
+            _PROBLEMS[name] = I.exact_problem(4, 4.0, (2, 2))
+        elif name == "chain6_exact":
+            _PROBLEMS[name] = I.exact_problem(6, 4.0, (3, 3))
+        else:
+            raise KeyError(name)
+    return _PROBLEMS[name]
+
+
+MATVEC_CASES = ["chain4_exact", "chain8_exact", "ladder2x4_U10", "chain12_m30", "ladder2x6_m40",
+                "chain14_m25_off", "chain20_m150", "chain32_m400", "ladder16_m800",
+                "ladder16_m1000", "ladder32_m2000"]
+
+
+def test_layout_matches_oracle(env):
+    torch, L = env
+    for name in ["chain8_exact", "ladder2x6_m40", "chain14_m25_off"]:
+        say("layout", name)
+        pb = problem(name)
+        h = L.dmrg_create(pb)
+        lay = h.psi_layout()
+        ol, n = M.layout(pb)
+        assert h.n == n
+        assert [int(v) for v in lay["off"]] == [o[4] for o in ol]
+        assert [int(v) for v in lay["rows"]] == [o[2] for o in ol]
+        assert [int(v) for v in lay["cols"]] == [o[3] for o in ol]
+        assert [int(v) for v in lay["secS"]] == [o[0] for o in ol]
+        assert [int(v) for v in lay["secE"]] == [o[1] for o in ol]
+        h.destroy()
+
+
+@pytest.mark.parametrize("name", MATVEC_CASES)
+def test_matvec_parity(env, name):
+    torch, L = env
+    say("matvec", name)
+    pb = problem(name)
+    h = L.dmrg_create(pb)
+    n = h.n
+    x = I.random_psi(n, np.random.default_rng(I.SEED_BASE + 77))
+    xd = _dev(torch, x)
+    yd = torch.empty_like(xd)
+    h.matvec(xd, yd)
+    torch.cuda.synchronize()
+    y = _host(yd)
+    yref = M.matvec_sector(pb, x)
+    err = rel(y, yref)
+    say("  rel err", err)
+    assert err <= MV_TOL
+    # bitwise reproducible
+    yd2 = torch.empty_like(xd)
+    h.matvec(xd, yd2)
+    torch.cuda.synchronize()
+    assert torch.equal(yd, yd2)
+    h.destroy()
+
+
+def test_matvec_multi_vector_and_hermitian(env):
+    torch, L = env
+    say("matvec nvec=2 + hermiticity")
+    pb = problem("ladder2x6_m40")
+    h = L.dmrg_create(pb)
+    n = h.n
+    rng = np.random.default_rng(5)
+    xs = np.concatenate([I.random_psi(n, rng), I.random_psi(n, rng)])
+    xd = _dev(torch, xs)
+    yd = torch.empty_like(xd)
+    h.matvec(xd, yd, nvec=2)
+    torch.cuda.synchronize()
+    ys = _host(yd)
+    for v in range(2):
+        sl = slice(2 * n * v, 2 * n * (v + 1))
+        assert rel(ys[sl], M.matvec_sector(pb, xs[sl])) <= MV_TOL
+    z = [xs[2 * n * v:2 * n * v + n] + 1j * xs[2 * n * v + n:2 * n * (v + 1)] for v in range(2)]
+    hz = [ys[2 * n * v:2 * n * v + n] + 1j * ys[2 * n * v + n:2 * n * (v + 1)] for v in range(2)]
+    assert abs(np.vdot(z[0], hz[1]) - np.vdot(hz[0], z[1])) < 1e-12 * np.linalg.norm(hz[0])
+    h.destroy()
+
+
+def test_matvec_generic_terms(env):
+    """Generic connection terms (non-fermionic and transposed forms) next to the bonds."""
+    torch, L = env
+    say("matvec generic terms")
+    pb = problem("chain12_m30")
+    extra = [(0.37, 0, 0, 0, 1, 0), (-0.21, 1, 1, 1, 0, 1), (0.5, 0, 1, 0, 0, 0)]
+    h = L.dmrg_create(pb, extra_terms=extra)
+    x = I.random_psi(h.n, np.random.default_rng(6))
+    xd = _dev(torch, x)
+    yd = torch.empty_like(xd)
+    h.matvec(xd, yd)
+    torch.cuda.synchronize()
+    assert rel(_host(yd), M.matvec_sector(pb, x, extra_terms=extra)) <= MV_TOL
+    h.destroy()
+
+
+KRYLOV_CASES = [
+    # name, kdim, tau, nsteps
+    ("chain8_exact", 12, 0.1, 10),
+    ("chain12_m30", 15, 0.1, 3),
+    ("chain20_m150", 20, 0.05, 2),
+    ("chain32_m400", 15, 0.1, 2),
+    ("ladder16_m1000", 15, 0.05, 1),
+    ("ladder2x6_m40", 40, 0.3, 1),      # kdim > 32: unfused reorthogonalisation path
+]
+
+
+@pytest.mark.parametrize("name,kdim,tau,nsteps", KRYLOV_CASES)
+def test_krylov_parity(env, name, kdim, tau, nsteps):
+    torch, L = env
+    say("krylov", name, kdim, tau, nsteps)
+    pb = problem(name)
+    h = L.dmrg_create(pb)
+    x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 3))
+    xd = _dev(torch, x)
+    yd = torch.empty_like(xd)
+    info = h.krylov_expm(xd, yd, tau, kdim, nsteps)
+    y = _host(yd)
+    yref, oinfo = K.krylov_expm(lambda v: M.matvec_sector(pb, v), x, tau, kdim, nsteps)
+    err = rel(y, yref)
+    say("  rel err", err, info)
+    assert err <= KR_TOL
+    assert info["k_eff"] == oinfo.k_eff[-1]
+    assert abs(info["beta0"] - 1.0) < 1e-14
+    assert abs(np.linalg.norm(y) - 1.0) < 1e-10
+    h.destroy()
+
+
+@pytest.mark.parametrize("name,kdim,tau", [("chain8_exact", 12, 0.1), ("ladder16_m1000", 15, 0.05),
+                                           ("chain14_m25_off", 10, 0.2)])
+def test_tst_parity(env, name, kdim, tau):
+    torch, L = env
+    say("tst", name)
+    pb = problem(name)
+    h = L.dmrg_create(pb)
+    n = h.n
+    phi = I.random_psi(n, np.random.default_rng(I.SEED_BASE + 4))
+    pd = _dev(torch, phi)
+    td = torch.empty(8 * n, dtype=torch.float64, device="cuda")
+    w, info = h.tst_targets(pd, tau, kdim, td)
+    t = _host(td)
+    ys, wref, b = K.tst_targets(lambda v: M.matvec_sector(pb, v), phi, tau, kdim)
+    assert np.array_equal(w, wref)
+    for i in range(4):
+        err = rel(t[2 * n * i:2 * n * (i + 1)], ys[i])
+        say("  target", i, err)
+        assert err <= KR_TOL
+    h.destroy()
+
+
+def test_krylov_edge_cases(env):
+    torch, L = env
+    pb = problem("chain6_exact")
+    h = L.dmrg_create(pb)
+    n = h.n
+    # zero vector: zero result, k_eff 0, no error
+    say("edge zero vector")
+    zd = torch.zeros(2 * n, dtype=torch.float64, device="cuda")
+    yd = torch.full_like(zd, 7.0)
+    info = h.krylov_expm(zd, yd, 0.3, 10, 2)
+    assert torch.count_nonzero(yd).item() == 0 and info["k_eff"] == 0
+    # tau = 0: identity (to rounding)
+    say("edge tau 0")
+    x = I.random_psi(n, np.random.default_rng(8))
+    xd = _dev(torch, x)
+    info = h.krylov_expm(xd, yd, 0.0, 10, 1)
+    assert rel(_host(yd), x) < 1e-13
+    # kdim = 1
+    say("edge kdim 1")
+    info = h.krylov_expm(xd, yd, 0.05, 1, 3)
+    yref, _ = K.krylov_expm(lambda v: M.matvec_sector(pb, v), x, 0.05, 1, 3)
+    assert rel(_host(yd), yref) <= KR_TOL
+    # eigenvector input: breakdown after one vector, exact phase
+    say("edge eigenvector")
+    Hd = M.superblock_matrix(pb)
+    wv, vv = np.linalg.eigh(Hd)
+    ev = np.concatenate([vv[:, 3], np.zeros(n)])
+    ed = _dev(torch, ev)
+    info = h.krylov_expm(ed, yd, 0.7, 12, 1)
+    assert info["k_eff"] == 1 and info["breakdown"] == 1
+    z = np.exp(-0.7j * wv[3]) * vv[:, 3]
+    assert rel(_host(yd), np.concatenate([z.real, z.imag])) < 1e-12
+    # y aliases x
+    say("edge aliasing")
+    xd2 = xd.clone()
+    h.krylov_expm(xd2, xd2, 0.1, 8, 2)
+    yref, _ = K.krylov_expm(lambda v: M.matvec_sector(pb, v), x, 0.1, 8, 2)
+    assert rel(_host(xd2), yref) <= KR_TOL
+    h.destroy()
+
+
+def test_krylov_exhausts_small_space(env):
+    """kdim = 64 on a 36-dimensional sector: breakdown at the space dimension, exact result."""
+    torch, L = env
+    say("edge exhaust")
+    pb = problem("chain4_exact")
+    h = L.dmrg_create(pb)
+    n = h.n
+    x = I.random_psi(n, np.random.default_rng(10))
+    xd = _dev(torch, x)
+    yd = torch.empty_like(xd)
+    info = h.krylov_expm(xd, yd, 2.0, 64, 1)
+    import scipy.linalg as sla
+    Hd = M.superblock_matrix(pb)
+    z = sla.expm(-2.0j * Hd) @ (x[:n] + 1j * x[n:])
+    assert info["breakdown"] == 1 and info["k_eff"] <= n
+    assert rel(_host(yd), np.concatenate([z.real, z.imag])) < 1e-10
+    h.destroy()
+
+
+def test_chain8_against_dense_exponential(env):
+    """Config chain L=8, U=4, exact blocks: GPU Krylov (kdim 12, tau 0.1, 10 steps) against the
+    exponential of the ED Hamiltonian (scipy expm_multiply)."""
+    torch, L = env
+    say("chain8 vs ED")
+    from tests.helpers import exact_case, expm_flat
+    pb, sec, Hsp, perm = exact_case(8, 4.0, (4, 4))
+    h = L.dmrg_create(pb)
+    x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 1))
+    xd = _dev(torch, x)
+    yd = torch.empty_like(xd)
+    h.krylov_expm(xd, yd, 0.1, 12, 10)
+    assert rel(_host(yd), expm_flat(Hsp, x, 1.0)) < 1e-9
+    h.destroy()
