@@ -187,6 +187,11 @@ void dmrg_batch_destroy(dmrg_batch b);
 int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, int32_t kdim,
                            double* const* targets, double* weights, dmrg_krylov_info* infos);
 
+/* Measurement hook: runs reps products y = H_sb x (one vector) with HIP events around each of
+ * the two block-product launches and waits for them.  out[0], out[1]: average milliseconds of
+ * the right-product and left-product launches; out[2], out[3]: their algorithmic flops. */
+int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps, double* out);
+
 /* Static description of a status code. */
 const char* dmrg_strerror(int status);
 

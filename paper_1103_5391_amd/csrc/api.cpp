@@ -345,6 +345,44 @@ int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, i
     return DMRG_OK;
 }
 
+int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps, double* out) {
+    if (!h || !x || !y || !out || reps < 1) return DMRG_EINVAL;
+    const Plan& P = h->plan;
+    ProbPtrs pp;
+    pp.x = x;
+    pp.y = y;
+    pp.T = h->dT.as<double>();
+    pp.Lops = h->dA.p;
+    pp.Rops = h->dR.p;
+    pp.xscale = nullptr;
+    pp.skip = nullptr;
+    hipEvent_t ev[3];
+    for (auto& e : ev) HIP_TRY(h, hipEventCreate(&e));
+    double t1 = 0.0, t2 = 0.0;
+    for (int r = 0; r < reps; ++r) {
+        HIP_TRY(h, hipEventRecord(ev[0], h->stream));
+        HIP_TRY(h, launch_stage1_f64(h->dS1.as<S1Block>(), h->dT1.as<Tile>(),
+                                     (int)P.tiles1.size(), nullptr, pp, h->stream));
+        HIP_TRY(h, hipEventRecord(ev[1], h->stream));
+        HIP_TRY(h, launch_stage2_f64(h->dS2.as<S2Block>(), h->dSeg.as<Segment>(),
+                                     h->dT2.as<Tile>(), (int)P.tiles2.size(), nullptr, pp,
+                                     h->stream));
+        HIP_TRY(h, hipEventRecord(ev[2], h->stream));
+        HIP_TRY(h, hipEventSynchronize(ev[2]));
+        float a = 0.f, b = 0.f;
+        HIP_TRY(h, hipEventElapsedTime(&a, ev[0], ev[1]));
+        HIP_TRY(h, hipEventElapsedTime(&b, ev[1], ev[2]));
+        t1 += a;
+        t2 += b;
+    }
+    for (auto& e : ev) (void)hipEventDestroy(e);
+    out[0] = t1 / reps;
+    out[1] = t2 / reps;
+    out[2] = P.flops1;
+    out[3] = P.flops2;
+    return DMRG_OK;
+}
+
 const char* dmrg_strerror(int status) {
     switch (status) {
         case DMRG_OK: return "success";

@@ -236,6 +236,7 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
                 for (int k = 0; k < B.e; ++k) R[(int64_t)(ed.col + j) * B.e + k] = ed.b.at(j, k);
         }
         flops += 2.0 * s.M * (double)s.K * s.N;
+        P.flops1 += 2.0 * s.M * (double)s.K * s.N;
         P.s1.push_back(s);
         tile_list(P.tiles1, bi, s.M, s.N);
     }
@@ -292,6 +293,7 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
             kc += Bs.d;
         }
         flops += 2.0 * s.M * (double)s.N * kA;
+        P.flops2 += 2.0 * s.M * (double)s.N * kA;
         P.s2.push_back(s);
         tile_list(P.tiles2, bi, s.M, s.N);
     }

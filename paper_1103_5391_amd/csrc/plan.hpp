@@ -62,6 +62,7 @@ struct Plan {
     std::vector<Tile> tiles2;
     int64_t T_size = 0;                        // workspace doubles
     double flops = 0.0;                        // algorithmic flops per complex matvec
+    double flops1 = 0.0, flops2 = 0.0;         // of which stage 1 / stage 2
 };
 
 // Returns an empty string on success, else the reason the problem is invalid.

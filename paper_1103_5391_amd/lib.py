@@ -23,8 +23,8 @@ STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP",
 SYMBOLS = [
     "dmrg_create", "dmrg_destroy", "dmrg_psi_layout", "dmrg_flops", "dmrg_set_precision",
     "dmrg_set_stream", "dmrg_matvec", "dmrg_krylov_expm", "dmrg_tst_targets",
-    "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_tst_targets", "dmrg_strerror",
-    "dmrg_last_error",
+    "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_tst_targets", "dmrg_profile_matvec",
+    "dmrg_strerror", "dmrg_last_error",
 ]
 
 
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
     lib.dmrg_batch_destroy.restype = None
     lib.dmrg_batch_tst_targets.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl),
                                            P(dmrg_krylov_info)]
+    lib.dmrg_profile_matvec.argtypes = [vp, vp, vp, i32, P(dbl)]
     lib.dmrg_strerror.argtypes = [i32]
     lib.dmrg_strerror.restype = C.c_char_p
     lib.dmrg_last_error.argtypes = [vp]
@@ -274,6 +275,16 @@ class Handle:
         return w, (inf.as_dict() if info else None)
 
     tst_targets = dmrg_tst_targets
+
+    def dmrg_profile_matvec(self, x, y, reps: int = 10):
+        """Average ms of the two block-product launches and their algorithmic flops."""
+        n2 = 2 * self.n
+        out = np.zeros(4)
+        _check(self.lib.dmrg_profile_matvec(self.h, _tensor_ptr(x, n2), _tensor_ptr(y, n2),
+                                            int(reps), _dptr(out, C.c_double)), self.h)
+        return dict(ms_stage1=out[0], ms_stage2=out[1], flops_stage1=out[2], flops_stage2=out[3])
+
+    profile_matvec = dmrg_profile_matvec
 
 
 class Batch:
