@@ -8,10 +8,13 @@ namespace dmrg {
 
 constexpr int kMaxKrylov = 64;      // largest kdim accepted
 constexpr int kTile = 32;           // output tile edge of the block-product kernels
+constexpr int kTile1N = 64;         // stage-1 tiles are kTile x kTile1N (one per wavefront)
 constexpr int kChunk = 16;          // K depth of one register chunk (4 MFMA K-steps of 4)
 constexpr int kWaves = 4;           // waves per work group (split-K among them)
 constexpr int kVecThreads = 256;    // threads per block of the vector kernels
 constexpr int kMaxTimes = 4;        // time points evaluated from one Krylov basis
+constexpr int kXcd = 8;             // MI355X: 8 XCDs of 32 CUs, each with its own L2; work
+                                    // group i of a launch runs on XCD i mod 8
 
 // Element (r, c) of a matrix view inside a buffer.  Row-split views ("A" operands) place rows
 // r >= split in a second plane at +poff; column-split views ("B" operands and outputs) place
@@ -23,33 +26,44 @@ struct View {
     int32_t split;
 };
 
+// Operator factors are packed once, at creation, in the order the MFMA lanes consume them:
+// 16-row (or 16-column) panels, 16-deep K chunks, and inside a chunk [g][r][t] with
+// k = 4g + t, so lane (g, r) reads its four K values of one chunk as 32 contiguous bytes.
+// Rows (columns) are zero-padded to the 32-wide tile and K to a multiple of 16, so operator
+// loads never need bounds checks and padded products vanish.
+constexpr int kPanel = 16;                        // rows (columns) per packed panel
+constexpr int kChunkElems = kPanel * kChunk;      // doubles per packed chunk (256)
+
 // Stage 1 (right products) of one source block b:  T_b = X_b * R_b
 //   X_b: 2d x e, rows 0..d-1 = real plane of Psi_b, rows d..2d-1 = imaginary plane
-//   R_b: e x N column-major, [H_E(q)^T | right factors of every term leaving b]
-//   T_b: 2d x N column-major (ld 2d), workspace
+//   R_b: e x N, [H_E(q)^T | right factors of every term leaving b], packed (column panels)
+//   T_b: workspace, column-major with both planes padded to dpad = d rounded up to 4 rows
+//        (ld 2 dpad), so every column segment the left products read is 32-byte aligned
 struct S1Block {
     int32_t M, K, N, prob;
-    View X;           // into the input vector
-    int64_t Roff;     // into the packed right-factor buffer (ld = K)
-    int64_t Toff;     // into the workspace (ld = M)
+    int32_t nch, pad;   // K chunks of the packed factor
+    View X;             // into the input vector
+    int64_t Roff;       // into the packed right-factor buffer
+    View T;             // into the workspace (row split like X)
 };
 
 // Stage 2 (left products and sum) of one output block b':
 //   Y_b' (d' x 2e', columns e'.. = imaginary plane) = T0 + sum_seg Acat[:, seg] * B_seg
-//   Acat: d' x Kcat column-major, [H_S(p') | coef*sign*A of every term entering b']
+//   Acat: d' x Kcat, [H_S(p') | coef*sign*A of every term entering b'], packed (row panels,
+//         every segment padded to whole chunks)
 //   T0: the H_E columns of T_b'
 struct S2Block {
     int32_t M, N, prob, nseg;
-    int32_t seg0, pad;
-    int64_t Aoff;     // packed left-factor buffer (ld = M)
-    View T0;          // into the workspace
-    View Y;           // into the output vector
+    int32_t seg0, nch;  // first segment, total K chunks of the packed factor
+    int64_t Aoff;       // packed left-factor buffer
+    View T0;            // into the workspace
+    View Y;             // into the output vector
 };
 
-// One K segment of a stage-2 block: rows kA.. of Acat times the source view B (K x N).
+// One K segment of a stage-2 block: chunks ch0.. of Acat times the source view B (K x N).
 struct Segment {
-    int32_t K, kA;
-    int32_t src;      // 0: the input vector (diagonal H_S term), 1: the workspace
+    int32_t K, ch0;
+    int32_t src;        // 0: the input vector (diagonal H_S term), 1: the workspace
     int32_t pad;
     View B;
 };

@@ -115,9 +115,56 @@ OpRef op_from(const HalfTable& t, int opi, bool trans, int src) {
     return r;
 }
 
-void tile_list(std::vector<Tile>& out, int blk, int M, int N) {
-    for (int m0 = 0; m0 < M; m0 += kTile)
-        for (int n0 = 0; n0 < N; n0 += kTile) out.push_back(Tile{blk, m0, n0, 0});
+int round_up(int v, int m) { return (v + m - 1) / m * m; }
+
+// Offset of element (i, k) inside a packed factor: i = row (stage 2) or column (stage 1),
+// k = K index counted from the start of the packed K range, nch = K chunks per panel.
+int64_t packed_index(int i, int k, int nch) {
+    const int pnl = i / kPanel, r = i % kPanel;
+    const int ch = k / kChunk, g = (k % kChunk) / 4, t = k % 4;
+    return (((int64_t)pnl * nch + ch) * 4 + g) * (kPanel * 4) + r * 4 + t;
+}
+
+// Reorders a tile list (tiles of one block contiguous) for launch: work groups of `group`
+// consecutive tiles, work group i runs on XCD i mod kXcd.  Blocks are assigned to XCDs by
+// longest-processing-time on their weights; per XCD the blocks are ordered heaviest first;
+// the per-XCD lists are padded with empty tiles (blk = -1) to whole groups and equal length.
+std::vector<Tile> xcd_order(const std::vector<Tile>& tiles, const std::vector<double>& w,
+                            int group) {
+    const int nb = (int)w.size();
+    std::vector<std::vector<Tile>> of(nb);
+    for (const Tile& t : tiles) of[t.blk].push_back(t);
+    std::vector<int> order(nb);
+    for (int i = 0; i < nb; ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
+    std::vector<double> load(kXcd, 0.0);
+    std::vector<std::vector<Tile>> lists(kXcd);
+    for (int bi : order) {
+        if (of[bi].empty()) continue;
+        int x = 0;
+        for (int i = 1; i < kXcd; ++i)
+            if (load[i] < load[x]) x = i;
+        load[x] += w[bi];
+        lists[x].insert(lists[x].end(), of[bi].begin(), of[bi].end());
+    }
+    size_t groups = 0;
+    for (auto& l : lists) {
+        while (l.size() % group) l.push_back(Tile{-1, 0, 0, 0});
+        groups = std::max(groups, l.size() / group);
+    }
+    for (auto& l : lists)
+        while (l.size() < groups * group) l.push_back(Tile{-1, 0, 0, 0});
+    std::vector<Tile> out;
+    out.reserve(groups * group * kXcd);
+    for (size_t gi = 0; gi < groups; ++gi)
+        for (int x = 0; x < kXcd; ++x)
+            out.insert(out.end(), lists[x].begin() + gi * group, lists[x].begin() + (gi + 1) * group);
+    return out;
+}
+
+void tile_list(std::vector<Tile>& out, int blk, int M, int N, int tm, int tn) {
+    for (int m0 = 0; m0 < M; m0 += tm)
+        for (int n0 = 0; n0 < N; n0 += tn) out.push_back(Tile{blk, m0, n0, 0});
 }
 
 }  // namespace
@@ -219,26 +266,31 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
         s.K = B.e;
         s.N = N;
         s.prob = 0;
+        s.nch = (B.e + kChunk - 1) / kChunk;
+        s.pad = 0;
         s.X = View{B.off, P.n, B.d, B.d};
         s.Roff = (int64_t)P.R.size();
-        s.Toff = toff;
-        toff += (int64_t)s.M * N;
-        // pack R column-major (ld = K = e)
-        P.R.resize(P.R.size() + (size_t)B.e * N);
+        const int dpad = round_up(B.d, 4);
+        s.T = View{toff, dpad, 2 * dpad, B.d};
+        toff += (int64_t)2 * dpad * N;
+        // pack R (K x N) by column panels, zero padding to whole tiles and chunks
+        const int Npad = round_up(N, kTile1N);
+        P.R.resize(P.R.size() + (size_t)Npad * s.nch * kChunk, 0.0);
         double* R = P.R.data() + s.Roff;
         const double* HE = P.E.H.data() + P.E.hoff[B.q];
-        for (int j = 0; j < B.e; ++j)
-            for (int k = 0; k < B.e; ++k) R[(int64_t)j * B.e + k] = HE[(int64_t)k * B.e + j];
+        for (int j = 0; j < B.e; ++j)          // R(k, j) = H_E(q)(j, k)
+            for (int k = 0; k < B.e; ++k) R[packed_index(j, k, s.nch)] = HE[(int64_t)k * B.e + j];
         for (int ei : out_of[bi]) {
             const Edge& ed = edges[ei];
             const int e2 = P.blocks[ed.dst].e;
             for (int j = 0; j < e2; ++j)          // R(k, col + j) = B(j, k)
-                for (int k = 0; k < B.e; ++k) R[(int64_t)(ed.col + j) * B.e + k] = ed.b.at(j, k);
+                for (int k = 0; k < B.e; ++k)
+                    R[packed_index(ed.col + j, k, s.nch)] = ed.b.at(j, k);
         }
         flops += 2.0 * s.M * (double)s.K * s.N;
         P.flops1 += 2.0 * s.M * (double)s.K * s.N;
         P.s1.push_back(s);
-        tile_list(P.tiles1, bi, s.M, s.N);
+        tile_list(P.tiles1, bi, s.M, s.N, kTile, kTile1N);
     }
     P.T_size = toff;
 
@@ -250,67 +302,75 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
         s.N = 2 * B.e;
         s.prob = 0;
         s.seg0 = (int)P.segs.size();
-        s.pad = 0;
         s.Aoff = (int64_t)P.A.size();
-        s.T0 = View{P.s1[bi].Toff, B.d, 2 * B.d, B.e};
+        s.T0 = View{P.s1[bi].T.off, P.s1[bi].T.poff, P.s1[bi].T.ld, B.e};
         s.Y = View{B.off, P.n, B.d, B.e};
-        int kA = 0;
+        int kA = 0, nch = 0;
         // diagonal H_S term on the block itself
         Segment g0;
         g0.K = B.d;
-        g0.kA = 0;
+        g0.ch0 = 0;
         g0.src = 0;
         g0.pad = 0;
         g0.B = View{B.off, P.n, B.d, B.e};
         P.segs.push_back(g0);
         kA += B.d;
+        nch += (B.d + kChunk - 1) / kChunk;
         for (int ei : into[bi]) {
             const Edge& ed = edges[ei];
             const auto& Bs = P.blocks[ed.src];
             Segment g;
             g.K = Bs.d;
-            g.kA = kA;
+            g.ch0 = nch;
             g.src = 1;
             g.pad = 0;
-            g.B = View{P.s1[ed.src].Toff + (int64_t)ed.col * 2 * Bs.d, Bs.d, 2 * Bs.d, B.e};
+            const View& ts = P.s1[ed.src].T;
+            g.B = View{ts.off + (int64_t)ed.col * ts.ld, ts.poff, ts.ld, B.e};
             P.segs.push_back(g);
             kA += Bs.d;
+            nch += (Bs.d + kChunk - 1) / kChunk;
         }
         s.nseg = (int)P.segs.size() - s.seg0;
-        P.A.resize(P.A.size() + (size_t)B.d * kA);
+        s.nch = nch;
+        // pack Acat (d' x Kcat) by row panels, each segment starting on a fresh chunk
+        const int Mpad = round_up(B.d, kTile);
+        P.A.resize(P.A.size() + (size_t)Mpad * nch * kChunk, 0.0);
         double* A = P.A.data() + s.Aoff;
         const double* HS = P.S.H.data() + P.S.hoff[B.p];
         for (int k = 0; k < B.d; ++k)
-            for (int i = 0; i < B.d; ++i) A[(int64_t)k * B.d + i] = HS[(int64_t)k * B.d + i];
-        int kc = B.d;
+            for (int i = 0; i < B.d; ++i) A[packed_index(i, k, nch)] = HS[(int64_t)k * B.d + i];
+        int si = 1;
         for (int ei : into[bi]) {
             const Edge& ed = edges[ei];
             const auto& Bs = P.blocks[ed.src];
             const auto& t = P.terms[ed.term];
             const double c = t.coef * (t.fermionic ? P.S.parity(Bs.p) : 1);
+            const int kbase = P.segs[s.seg0 + si].ch0 * kChunk;
             for (int k = 0; k < Bs.d; ++k)
-                for (int i = 0; i < B.d; ++i) A[(int64_t)(kc + k) * B.d + i] = c * ed.a.at(i, k);
-            kc += Bs.d;
+                for (int i = 0; i < B.d; ++i) A[packed_index(i, kbase + k, nch)] = c * ed.a.at(i, k);
+            ++si;
         }
         flops += 2.0 * s.M * (double)s.N * kA;
         P.flops2 += 2.0 * s.M * (double)s.N * kA;
         P.s2.push_back(s);
-        tile_list(P.tiles2, bi, s.M, s.N);
+        tile_list(P.tiles2, bi, s.M, s.N, kTile, kTile);
     }
     P.flops = flops;
 
-    // longest tiles first so that the tail of each launch is made of short ones
-    std::stable_sort(P.tiles1.begin(), P.tiles1.end(), [&](const Tile& a, const Tile& b) {
-        return P.s1[a.blk].K > P.s1[b.blk].K;
-    });
-    std::vector<int> kcat(nb);
+    // XCD-aware launch order: every block's tiles go to one XCD (so its packed factor panels
+    // and source panels are shared in that XCD's L2), blocks are spread over the XCDs by
+    // longest-processing-time, heaviest first inside each XCD.
+    std::vector<double> w1(nb), w2(nb);
     for (int bi = 0; bi < nb; ++bi) {
         int k = 0;
         for (int s = 0; s < P.s2[bi].nseg; ++s) k += P.segs[P.s2[bi].seg0 + s].K;
-        kcat[bi] = k;
+        const double nt1 = (double)((P.s1[bi].M + kTile - 1) / kTile) * ((P.s1[bi].N + kTile1N - 1) / kTile1N);
+        const double nt2 = (double)((P.s2[bi].M + kTile - 1) / kTile) * ((P.s2[bi].N + kTile - 1) / kTile);
+        w1[bi] = nt1 * (P.s1[bi].nch + 1);
+        w2[bi] = nt2 * ((k + kChunk - 1) / kChunk + 2);
     }
-    std::stable_sort(P.tiles2.begin(), P.tiles2.end(),
-                     [&](const Tile& a, const Tile& b) { return kcat[a.blk] > kcat[b.blk]; });
+    P.tiles1 = xcd_order(P.tiles1, w1, kWaves);
+    P.tiles2 = xcd_order(P.tiles2, w2, 1);
     return "";
 }
 
