@@ -124,6 +124,43 @@ def main():
     ms_dom, fl_dom = prof[f"ms_stage{dom}"], prof[f"flops_stage{dom}"]
     achieved = fl_dom / (ms_dom * 1e-3) / 1e12
 
+    # mixed arithmetic of the block products (Lanczos, reorthogonalisation, exponential and
+    # combination stay FP64): same step, error against the FP64 targets of this run
+    ref = td.clone()
+    ref_mv = torch.empty_like(pd)
+    h.matvec(pd, ref_mv)
+    mixed = {}
+    for prec, label in ((L.DMRG_FP32, "fp32"), (L.DMRG_BF16X3, "bf16x3")):
+        h.set_precision(prec)
+        for _ in range(args.warmup):
+            h.tst_targets(pd, tau, kdim, td, info=False)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            h.tst_targets(pd, tau, kdim, td, info=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_p = e0.elapsed_time(e1) / args.steps
+        mv = torch.empty_like(pd)
+        h.matvec(pd, mv)
+        pm = h.profile_matvec(pd, yd, reps=10)
+        torch.cuda.synchronize()
+        tst_err = max(float(torch.linalg.vector_norm(td[2 * n * i:2 * n * (i + 1)] - ref[2 * n * i:2 * n * (i + 1)]))
+                      / float(torch.linalg.vector_norm(ref[2 * n * i:2 * n * (i + 1)])) for i in range(4))
+        drift = max(abs(float(torch.linalg.vector_norm(td[2 * n * i:2 * n * (i + 1)])) - 1.0) for i in range(4))
+        mixed[label] = {
+            "ms_per_step": round(ms_p, 5),
+            "krylov_steps_per_s": round(1000.0 / ms_p, 3),
+            "speedup_vs_fp64": round(ms_step / ms_p, 3),
+            "matvec_ms": round(pm["ms_stage1"] + pm["ms_stage2"], 5),
+            "matvec_speedup_vs_fp64": round(ms_mv / (pm["ms_stage1"] + pm["ms_stage2"]), 3),
+            "matvec_rel_err_vs_fp64": float(torch.linalg.vector_norm(mv - ref_mv) / torch.linalg.vector_norm(ref_mv)),
+            "tst_rel_err_vs_fp64": tst_err,
+            "norm_drift": drift,
+        }
+        print(f"[bench] {label}: {ms_p:.4f} ms/step, {mixed[label]}", file=sys.stderr, flush=True)
+    h.set_precision(L.DMRG_FP64)
+
     value = kdim * F / (ms_step * 1e-3) / 1e12
     out = {
         "metric": "H·ψ TFLOP/s + Krylov steps/s (ladder, m=1000) vs FP64 plain; % MFMA peak",
@@ -146,7 +183,8 @@ def main():
         "matvec_tflops": round(F / (ms_mv * 1e-3) / 1e12, 4),
         "matvec_ms": round(ms_mv, 5),
         "mfma_peak_frac_step": round(value / PEAK_FP64_TFLOPS, 4),
-        "roofline": {"bound": "mfma", "kernel": f"stage{dom}_f64",
+        "mixed_precision": mixed,
+        "roofline": {"bound": "mfma", "kernel": f"stage{dom} (fp64)",
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
                      "traffic": None},

@@ -16,10 +16,10 @@
 
 namespace dmrg {
 
-hipError_t launch_stage1_f64(const S1Block*, const Tile*, int, const ProbPtrs*, ProbPtrs,
-                             hipStream_t);
-hipError_t launch_stage2_f64(const S2Block*, const Segment*, const Tile*, int, const ProbPtrs*,
-                             ProbPtrs, hipStream_t);
+hipError_t launch_stage1(int, const S1Block*, const Tile*, int, const ProbPtrs*, ProbPtrs,
+                         hipStream_t);
+hipError_t launch_stage2(int, const S2Block*, const Segment*, const Tile*, int, const ProbPtrs*,
+                         ProbPtrs, hipStream_t);
 hipError_t launch_start(const double*, double*, int64_t, KState*, double*, int, int, hipStream_t);
 hipError_t launch_lanczos_iter(double*, int64_t, double*, int64_t, int, int, KState*, double*,
                                hipStream_t);
@@ -57,8 +57,10 @@ struct dmrg_ctx {
     hipStream_t stream = nullptr;
     int precision = DMRG_FP64;
     std::string last_error;
-    // device copies of the plan
-    DevBuf dA, dR, dS1, dS2, dSeg, dT1, dT2;
+    // device copies of the plan: stage descriptors per chunk depth (0: 16, 1: 32), packed
+    // operators per arithmetic (built on first use), tile lists
+    DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT2;
+    DevBuf dA[3], dR[3];
     // workspace
     DevBuf dT;          // stage-1 intermediate
     DevBuf dV;          // Krylov basis slots
@@ -117,21 +119,42 @@ int ensure_workspace(dmrg_handle h, int kdim) {
     return DMRG_OK;
 }
 
-// y = H_sb x for one vector; x scaled by *xscale on load when non-null; skipped when *skip.
-int matvec_one(dmrg_handle h, const double* x, double* y, const double* xscale, const int* skip) {
-    const Plan& P = h->plan;
+// Packed operators of one arithmetic on the device (built and cached on first use).
+int ensure_operators(dmrg_handle h, int prec) {
+    if (h->dA[prec].p) return DMRG_OK;
+    std::vector<uint8_t> A, R;
+    try {
+        pack_operators(h->plan, prec, A, R);
+    } catch (const std::bad_alloc&) {
+        return fail(h, DMRG_ENOMEM, "host memory for packed operators");
+    }
+    HIP_TRY(h, upload(h->dA[prec], A, h->stream));
+    HIP_TRY(h, upload(h->dR[prec], R, h->stream));
+    return DMRG_OK;
+}
+
+ProbPtrs make_ptrs(dmrg_handle h, const double* x, double* y, const double* xscale,
+                   const int* skip) {
     ProbPtrs pp;
     pp.x = x;
     pp.y = y;
-    pp.T = h->dT.as<double>();
-    pp.Lops = h->dA.p;
-    pp.Rops = h->dR.p;
+    pp.T = h->dT.p;
+    pp.Lops = h->dA[h->precision].p;
+    pp.Rops = h->dR[h->precision].p;
     pp.xscale = xscale;
     pp.skip = skip;
-    HIP_TRY(h, launch_stage1_f64(h->dS1.as<S1Block>(), h->dT1.as<Tile>(), (int)P.tiles1.size(),
-                                 nullptr, pp, h->stream));
-    HIP_TRY(h, launch_stage2_f64(h->dS2.as<S2Block>(), h->dSeg.as<Segment>(),
-                                 h->dT2.as<Tile>(), (int)P.tiles2.size(), nullptr, pp, h->stream));
+    return pp;
+}
+
+// y = H_sb x for one vector; x scaled by *xscale on load when non-null; skipped when *skip.
+int matvec_one(dmrg_handle h, const double* x, double* y, const double* xscale, const int* skip) {
+    const Plan& P = h->plan;
+    const int prec = h->precision, pk = prec == DMRG_BF16X3 ? 1 : 0;
+    const ProbPtrs pp = make_ptrs(h, x, y, xscale, skip);
+    HIP_TRY(h, launch_stage1(prec, h->dS1[pk].as<S1Block>(), h->dT1.as<Tile>(),
+                             (int)P.tiles1.size(), nullptr, pp, h->stream));
+    HIP_TRY(h, launch_stage2(prec, h->dS2[pk].as<S2Block>(), h->dSeg[pk].as<Segment>(),
+                             h->dT2.as<Tile>(), (int)P.tiles2.size(), nullptr, pp, h->stream));
     return DMRG_OK;
 }
 
@@ -191,17 +214,27 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
     h->stream = static_cast<hipStream_t>(stream);
     const Plan& P = h->plan;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = upload(h->dA, P.A, h->stream);
-    if (e == hipSuccess) e = upload(h->dR, P.R, h->stream);
-    if (e == hipSuccess) e = upload(h->dS1, P.s1, h->stream);
-    if (e == hipSuccess) e = upload(h->dS2, P.s2, h->stream);
-    if (e == hipSuccess) e = upload(h->dSeg, P.segs, h->stream);
+    if (e == hipSuccess) e = upload(h->dS1[0], P.pk16.s1, h->stream);
+    if (e == hipSuccess) e = upload(h->dS2[0], P.pk16.s2, h->stream);
+    if (e == hipSuccess) e = upload(h->dSeg[0], P.pk16.segs, h->stream);
+    if (e == hipSuccess) e = upload(h->dS1[1], P.pk32.s1, h->stream);
+    if (e == hipSuccess) e = upload(h->dS2[1], P.pk32.s2, h->stream);
+    if (e == hipSuccess) e = upload(h->dSeg[1], P.pk32.segs, h->stream);
     if (e == hipSuccess) e = upload(h->dT1, P.tiles1, h->stream);
     if (e == hipSuccess) e = upload(h->dT2, P.tiles2, h->stream);
     if (e == hipSuccess) e = h->dT.alloc(sizeof(double) * (size_t)P.T_size);
+    // the padding rows of the stage-1 workspace are read (times zero factors) but never
+    // written: they must hold finite values, so the workspace starts zeroed
+    if (e == hipSuccess) e = hipMemsetAsync(h->dT.p, 0, sizeof(double) * (size_t)P.T_size, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         delete h;
         return e == hipErrorOutOfMemory ? DMRG_ENOMEM : DMRG_EHIP;
+    }
+    if (ensure_operators(h, DMRG_FP64) != DMRG_OK) {
+        g_create_error = h->last_error;
+        delete h;
+        return DMRG_ENOMEM;
     }
     *out = h;
     return DMRG_OK;
@@ -237,7 +270,10 @@ int dmrg_flops(dmrg_handle h, double* flops) {
 
 int dmrg_set_precision(dmrg_handle h, int32_t precision) {
     if (!h) return DMRG_EINVAL;
-    if (precision != DMRG_FP64) return fail(h, DMRG_EINVAL, "precision not supported");
+    if (precision != DMRG_FP64 && precision != DMRG_FP32 && precision != DMRG_BF16X3)
+        return fail(h, DMRG_EINVAL, "unknown precision");
+    const int rc = ensure_operators(h, precision);
+    if (rc) return rc;
     h->precision = precision;
     return DMRG_OK;
 }
@@ -348,25 +384,18 @@ int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, i
 int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps, double* out) {
     if (!h || !x || !y || !out || reps < 1) return DMRG_EINVAL;
     const Plan& P = h->plan;
-    ProbPtrs pp;
-    pp.x = x;
-    pp.y = y;
-    pp.T = h->dT.as<double>();
-    pp.Lops = h->dA.p;
-    pp.Rops = h->dR.p;
-    pp.xscale = nullptr;
-    pp.skip = nullptr;
+    const int prec = h->precision, pk = prec == DMRG_BF16X3 ? 1 : 0;
+    const ProbPtrs pp = make_ptrs(h, x, y, nullptr, nullptr);
     hipEvent_t ev[3];
     for (auto& e : ev) HIP_TRY(h, hipEventCreate(&e));
     double t1 = 0.0, t2 = 0.0;
     for (int r = 0; r < reps; ++r) {
         HIP_TRY(h, hipEventRecord(ev[0], h->stream));
-        HIP_TRY(h, launch_stage1_f64(h->dS1.as<S1Block>(), h->dT1.as<Tile>(),
-                                     (int)P.tiles1.size(), nullptr, pp, h->stream));
+        HIP_TRY(h, launch_stage1(prec, h->dS1[pk].as<S1Block>(), h->dT1.as<Tile>(),
+                                 (int)P.tiles1.size(), nullptr, pp, h->stream));
         HIP_TRY(h, hipEventRecord(ev[1], h->stream));
-        HIP_TRY(h, launch_stage2_f64(h->dS2.as<S2Block>(), h->dSeg.as<Segment>(),
-                                     h->dT2.as<Tile>(), (int)P.tiles2.size(), nullptr, pp,
-                                     h->stream));
+        HIP_TRY(h, launch_stage2(prec, h->dS2[pk].as<S2Block>(), h->dSeg[pk].as<Segment>(),
+                                 h->dT2.as<Tile>(), (int)P.tiles2.size(), nullptr, pp, h->stream));
         HIP_TRY(h, hipEventRecord(ev[2], h->stream));
         HIP_TRY(h, hipEventSynchronize(ev[2]));
         float a = 0.f, b = 0.f;

@@ -1,93 +1,158 @@
-// Grouped block products of H_sb.psi on gfx950 FP64 MFMA (v_mfma_f64_16x16x4f64).
+// Grouped block products of H_sb.psi on gfx950 MFMA, in three arithmetics:
+//   FP64    v_mfma_f64_16x16x4f64, FP64 workspace
+//   FP32    v_mfma_f32_16x16x4f32, FP32 operands and workspace
+//   BF16x3  v_mfma_f32_16x16x32_bf16 on split operands a = a_hi + a_lo (bf16 each):
+//           a_hi b_hi + a_hi b_lo + a_lo b_hi accumulated in FP32, FP32 workspace
+// The result of the second stage is always written in FP64.
 //
 // The Hamiltonian connections (Sec. IV) are applied as psi' = A psi B^T over (N_up, N_dn)
-// symmetry blocks in two stages, each one launch over a list of 32 x 32 output tiles:
+// symmetry blocks in two stages, each one launch over a list of output tiles:
 //   stage 1  T_b  = X_b R_b        right products, X_b = [Re; Im] planes of the source block
 //   stage 2  Y_b' = T0 + Acat Bcat left products summed over all terms entering the block
-// Stage 1 gives each wavefront its own 32 x 64 tile.  In stage 2 a work group of four wavefronts owns
-// one tile and deals its K chunks round-robin to the waves; the four partial tiles are summed
-// in LDS in a fixed order (deterministic, no atomics).  Each wave holds 2 x 2 MFMA
-// accumulators (32 x 32).
+// Stage 1 gives each wavefront its own 32 x 64 tile.  In stage 2 a work group of four
+// wavefronts owns one 32 x 32 tile and deals its K chunks round-robin to the waves; the four
+// partial tiles are summed in LDS in a fixed order (deterministic, no atomics).
 //
-// Inside one 4-deep MFMA step the K index each lane group supplies is free as long as A and B
-// agree, so lane group g takes k = 4g + t at step t.  The operator factors are packed in
-// exactly that order (see internal.hpp), so lane (g, r) reads the four K values of a chunk as
-// 32 contiguous bytes, and they are zero-padded so no operator load needs a bounds check.
-// The data operands (the vector and the stage-1 workspace) are read in place: rows (stage 1)
-// or columns (stage 2) are contiguous in K, and out-of-range indices are clamped to a valid
-// element, whose product with the padded zeros vanishes.
+// Inside one MFMA the K index each lane group supplies is free as long as A and B agree, so
+// lane group g takes the KPL consecutive indices k = KPL g + t of a chunk.  The operator
+// factors are packed in exactly that order (see internal.hpp), so lane (g, r) reads its part
+// of a chunk as one contiguous piece, and they are zero-padded so no operator load needs a
+// bounds check.  The data operands are read in place: rows (stage 1) or columns (stage 2) are
+// contiguous in K.  The stage-1 workspace is zero-padded to whole chunks; for the input vector
+// out-of-range K indices are clamped to a valid element, whose product with the padded zeros
+// vanishes.
 #include "internal.hpp"
 
 namespace dmrg {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
-typedef const double __attribute__((address_space(1)))* gcptr;
-typedef const d4 __attribute__((address_space(1)))* gcptr4;
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 
-// Global-memory loads (the pointers come from descriptor tables, so the compiler would
-// otherwise emit flat loads).
-__device__ __forceinline__ double ldg(const double* p, int64_t i) { return ((gcptr)p)[i]; }
-__device__ __forceinline__ d4 ldg4(const double* p) { return *((gcptr4)p); }
+// Global-memory loads (pointers from descriptor tables would otherwise become flat loads).
+template <typename T>
+__device__ __forceinline__ T ldg(const T* p, int64_t i) {
+    return ((const __attribute__((address_space(1))) T*)p)[i];
+}
+template <typename V>
+__device__ __forceinline__ V ldgv(const void* p) {
+    return *((const __attribute__((address_space(1))) V*)p);
+}
 
-struct Frag {
-    d4 a[2];   // a[i][t]: rows 16 i + r, K index 4 g + t
-    d4 b[2];   // b[j][t]: columns 16 j + r, K index 4 g + t
+// ---------------------------------------------------------------------------------------
+// arithmetic traits
+// ---------------------------------------------------------------------------------------
+struct PF64 {
+    static constexpr int CK = 16, KPL = 4;
+    using op_t = double;          // packed operator element
+    using ws_t = double;          // workspace element
+    using acc_t = d4;
+    using frag_t = d4;            // one lane's operand values of one chunk
+    __device__ static frag_t from(const double (&v)[KPL]) { return (d4){v[0], v[1], v[2], v[3]}; }
+    __device__ static frag_t load_op(const op_t* p) { return ldgv<d4>(p); }
+    __device__ static acc_t mma(const frag_t& a, const frag_t& b, acc_t c) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[t], c, 0, 0, 0);
+        return c;
+    }
+    __device__ static int row(int g, int v) { return g + 4 * v; }   // result lane layout
 };
 
-__device__ __forceinline__ void mma_chunk(d4 (&acc)[2][2], const Frag& f) {
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-            for (int nj = 0; nj < 2; ++nj)
-                acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(f.a[mi][t], f.b[nj][t],
-                                                                   acc[mi][nj], 0, 0, 0);
-}
-
-// Runs chunks c0, c0 + step, ... (< nch) with two register buffers: the loads of the next
-// chunk are in flight while the MFMAs of the current one issue.
-template <class Load>
-__device__ __forceinline__ void kloop(d4 (&acc)[2][2], int c0, int step, int nch, Load load) {
-    if (c0 >= nch) return;
-    Frag f0, f1;
-    int c = c0;
-    load(c, f0);
-    while (true) {
-        const bool more = c + step < nch;
-        if (more) load(c + step, f1);
-        mma_chunk(acc, f0);
-        if (!more) break;
-        c += step;
-        const bool more2 = c + step < nch;
-        if (more2) load(c + step, f0);
-        mma_chunk(acc, f1);
-        if (!more2) break;
-        c += step;
+struct PF32 {
+    static constexpr int CK = 16, KPL = 4;
+    using op_t = float;
+    using ws_t = float;
+    using acc_t = f4;
+    using frag_t = f4;
+    __device__ static frag_t from(const double (&v)[KPL]) {
+        return (f4){(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
     }
+    __device__ static frag_t load_op(const op_t* p) { return ldgv<f4>(p); }
+    __device__ static acc_t mma(const frag_t& a, const frag_t& b, acc_t c) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[t], c, 0, 0, 0);
+        return c;
+    }
+    __device__ static int row(int g, int v) { return 4 * g + v; }
+};
+
+struct PBF3 {
+    static constexpr int CK = 32, KPL = 8;
+    using op_t = __bf16;          // packed as 8 hi then 8 lo per lane and chunk
+    using ws_t = float;
+    using acc_t = f4;
+    struct frag_t {
+        bf8 hi, lo;
+    };
+    __device__ static frag_t from(const double (&v)[KPL]) {
+        frag_t f;
+#pragma unroll
+        for (int t = 0; t < KPL; ++t) {
+            const float x = (float)v[t];
+            const __bf16 h = (__bf16)x;
+            f.hi[t] = h;
+            f.lo[t] = (__bf16)(x - (float)h);
+        }
+        return f;
+    }
+    __device__ static frag_t load_op(const op_t* p) {
+        frag_t f;
+        f.hi = ldgv<bf8>(p);
+        f.lo = ldgv<bf8>(p + 8);
+        return f;
+    }
+    __device__ static acc_t mma(const frag_t& a, const frag_t& b, acc_t c) {
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, c, 0, 0, 0);
+        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, c, 0, 0, 0);
+        return c;
+    }
+    __device__ static int row(int g, int v) { return 4 * g + v; }
+};
+
+// Elements of one packed panel chunk per lane (bf16 packs hi and lo) and per chunk.
+template <class P>
+constexpr int lane_elems() {
+    return sizeof(typename P::op_t) == 2 ? 2 * P::KPL : P::KPL;
+}
+template <class P>
+constexpr int chunk_elems() {
+    return kPanel * 4 * lane_elems<P>();
 }
 
-__device__ __forceinline__ void zero_acc(d4 (&acc)[2][2]) {
+template <class P>
+__device__ __forceinline__ void zero(typename P::acc_t& a) {
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-        for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = (d4){0.0, 0.0, 0.0, 0.0};
+    for (int v = 0; v < 4; ++v) a[v] = 0;
 }
 
-__device__ __forceinline__ void scale_acc(d4 (&acc)[2][2], double s) {
+// KPL consecutive data values v[t] = src[base + t] (workspace, zero-padded chunks)
+template <class P, typename T>
+__device__ __forceinline__ void load_run(const T* src, int64_t base, double (&v)[P::KPL]) {
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int t = 0; t < P::KPL; ++t) v[t] = (double)ldg(src, base + t);
+}
+// KPL values src[base + min(k0 + t, K - 1) * stride] (input vector, clamped)
+template <class P>
+__device__ __forceinline__ void load_clamped(const double* src, int64_t base, int k0, int K,
+                                             int64_t stride, double (&v)[P::KPL]) {
 #pragma unroll
-        for (int nj = 0; nj < 2; ++nj) acc[mi][nj] *= s;
+    for (int t = 0; t < P::KPL; ++t) v[t] = ldg(src, base + (int64_t)min(k0 + t, K - 1) * stride);
 }
 
-// Stage 1: the K depth is one E-sector dimension (often below 16), so each wavefront owns a
-// whole 32 x 64 tile (four tiles per work group, no split-K): the 32 rows of X it loads per
-// chunk feed four 16-column panels of R, and the accumulators are stored directly.
-__global__ __launch_bounds__(256, 2) void stage1_f64(const S1Block* __restrict__ blks,
-                                                  const Tile* __restrict__ tiles, int ntiles,
-                                                  const ProbPtrs* __restrict__ probs,
-                                                  ProbPtrs single) {
+// ---------------------------------------------------------------------------------------
+// stage 1: one 32 x 64 tile per wavefront
+// ---------------------------------------------------------------------------------------
+template <class P>
+__global__ __launch_bounds__(256, 2) void stage1(const S1Block* __restrict__ blks,
+                                                 const Tile* __restrict__ tiles, int ntiles,
+                                                 const ProbPtrs* __restrict__ probs,
+                                                 ProbPtrs single) {
+    using op_t = typename P::op_t;
+    using ws_t = typename P::ws_t;
+    using acc_t = typename P::acc_t;
+    using frag_t = typename P::frag_t;
+    constexpr int NJ = kTile1N / 16;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int ti = blockIdx.x * kWaves + wave;
@@ -95,13 +160,13 @@ __global__ __launch_bounds__(256, 2) void stage1_f64(const S1Block* __restrict__
     const Tile tl = tiles[ti];
     if (tl.blk < 0) return;   // padding of the XCD-ordered list
     const S1Block B = blks[tl.blk];
-    const ProbPtrs P = probs ? probs[B.prob] : single;
-    if (P.skip && *P.skip) return;
+    const ProbPtrs P_ = probs ? probs[B.prob] : single;
+    if (P_.skip && *P_.skip) return;
     const int g = lane >> 4, r = lane & 15;
-    const double xs = P.xscale ? *P.xscale : 1.0;
-    const double* __restrict__ X = P.x;
-    const int K = B.K, nch = B.nch;
-    constexpr int NJ = kTile1N / 16;
+    const double xs = P_.xscale ? *P_.xscale : 1.0;
+    const double* __restrict__ X = P_.x;
+    const int K = B.K;
+    const int nch = (K + P::CK - 1) / P::CK;
 
     int64_t arow[2];
 #pragma unroll
@@ -110,51 +175,46 @@ __global__ __launch_bounds__(256, 2) void stage1_f64(const S1Block* __restrict__
         const int pl = m >= B.X.split;
         arow[i] = B.X.off + pl * B.X.poff + (m - pl * B.X.split);
     }
-    const double* pb = static_cast<const double*>(P.Rops) + B.Roff +
-                       (((int64_t)(tl.n0 / kPanel) * nch) * 4 + g) * (kPanel * 4) + r * 4;
-    const int64_t panel = (int64_t)nch * kChunkElems;   // doubles per packed column panel
+    const op_t* pb = static_cast<const op_t*>(P_.Rops) + B.Roff +
+                     (((int64_t)(tl.n0 / kPanel) * nch) * 4 + g) * (kPanel * lane_elems<P>()) +
+                     r * lane_elems<P>();
+    const int64_t panel = (int64_t)nch * chunk_elems<P>();
     const int64_t ldx = B.X.ld;
-    d4 acc[2][NJ];
+    acc_t acc[2][NJ];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int nj = 0; nj < NJ; ++nj) acc[mi][nj] = (d4){0.0, 0.0, 0.0, 0.0};
-    d4 a[2][2], b[2][NJ];
-    auto load = [&](int c, d4 (&fa)[2], d4 (&fb)[NJ]) {
-        const int kb = c * kChunk + 4 * g;
+        for (int nj = 0; nj < NJ; ++nj) zero<P>(acc[mi][nj]);
+    frag_t a[2][2], b[2][NJ];
+    auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[NJ]) {
+        const int kb = c * P::CK + P::KPL * g;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int kk = min(kb + t, K - 1);
-#pragma unroll
-            for (int i = 0; i < 2; ++i) fa[i][t] = ldg(X, arow[i] + kk * ldx);
+        for (int i = 0; i < 2; ++i) {
+            double v[P::KPL];
+            load_clamped<P>(X, arow[i], kb, K, ldx, v);
+            fa[i] = P::from(v);
         }
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) fb[j] = ldg4(pb + j * panel + (int64_t)c * kChunkElems);
+        for (int j = 0; j < NJ; ++j) fb[j] = P::load_op(pb + j * panel + (int64_t)c * chunk_elems<P>());
     };
-    auto mma = [&](const d4 (&fa)[2], const d4 (&fb)[NJ]) {
+    auto mma = [&](const frag_t (&fa)[2], const frag_t (&fb)[NJ]) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                for (int nj = 0; nj < NJ; ++nj)
-                    acc[mi][nj] = __builtin_amdgcn_mfma_f64_16x16x4f64(fa[mi][t], fb[nj][t],
-                                                                       acc[mi][nj], 0, 0, 0);
+            for (int nj = 0; nj < NJ; ++nj) acc[mi][nj] = P::mma(fa[mi], fb[nj], acc[mi][nj]);
     };
+    // two register buffers; the prefetch is unconditional (chunk index clamped) so that no
+    // load sits under a branch and the compiler waits only for the buffer being consumed
     load(0, a[0], b[0]);
-    for (int c = 0;;) {
-        const bool more = c + 1 < nch;
-        if (more) load(c + 1, a[1], b[1]);
+    for (int c = 0;; c += 2) {
+        load(min(c + 1, nch - 1), a[1], b[1]);
         mma(a[0], b[0]);
-        if (!more) break;
-        ++c;
-        const bool more2 = c + 1 < nch;
-        if (more2) load(c + 1, a[0], b[0]);
+        if (c + 1 >= nch) break;
+        load(min(c + 2, nch - 1), a[0], b[0]);
         mma(a[1], b[1]);
-        if (!more2) break;
-        ++c;
+        if (c + 2 >= nch) break;
     }
-    double* __restrict__ T = P.T;
+    ws_t* __restrict__ T = static_cast<ws_t*>(P_.T);
     const View tv = B.T;
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -163,80 +223,130 @@ __global__ __launch_bounds__(256, 2) void stage1_f64(const S1Block* __restrict__
             const int n = tl.n0 + 16 * nj + r;
             if (n >= B.N) continue;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) {   // f64 16x16 MFMA result: row g + 4v, column r
-                const int m = tl.m0 + 16 * mi + g + 4 * v;
+            for (int v = 0; v < 4; ++v) {
+                const int m = tl.m0 + 16 * mi + P::row(g, v);
                 if (m < B.M) {
                     const int pl = m >= tv.split;
                     T[tv.off + pl * tv.poff + (int64_t)n * tv.ld + (m - pl * tv.split)] =
-                        acc[mi][nj][v] * xs;
+                        (ws_t)(acc[mi][nj][v] * xs);
                 }
             }
         }
 }
 
-__global__ __launch_bounds__(256) void stage2_f64(const S2Block* __restrict__ blks,
-                                                  const Segment* __restrict__ segs,
-                                                  const Tile* __restrict__ tiles,
-                                                  const ProbPtrs* __restrict__ probs,
-                                                  ProbPtrs single) {
+// ---------------------------------------------------------------------------------------
+// stage 2: one 32 x 32 tile per work group, K chunks dealt round-robin to the four waves
+// ---------------------------------------------------------------------------------------
+template <class P, class Load>
+__device__ __forceinline__ void kloop(typename P::acc_t (&acc)[2][2], int c0, int step, int nch,
+                                      Load load) {
+    using frag_t = typename P::frag_t;
+    if (c0 >= nch) return;
+    const int last = c0 + (nch - 1 - c0) / step * step;
+    frag_t a0[2], b0[2], a1[2], b1[2];
+    auto mma = [&](const frag_t (&fa)[2], const frag_t (&fb)[2]) {
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = P::mma(fa[mi], fb[nj], acc[mi][nj]);
+    };
+    // unconditional (clamped) prefetch, as in stage 1
+    load(c0, a0, b0);
+    for (int c = c0;; c += 2 * step) {
+        load(min(c + step, last), a1, b1);
+        mma(a0, b0);
+        if (c + step > last) break;
+        load(min(c + 2 * step, last), a0, b0);
+        mma(a1, b1);
+        if (c + 2 * step > last) break;
+    }
+}
+
+template <class P>
+__global__ __launch_bounds__(256, 3) void stage2(const S2Block* __restrict__ blks,
+                                                 const Segment* __restrict__ segs,
+                                                 const Tile* __restrict__ tiles,
+                                                 const ProbPtrs* __restrict__ probs,
+                                                 ProbPtrs single) {
+    using op_t = typename P::op_t;
+    using ws_t = typename P::ws_t;
+    using acc_t = typename P::acc_t;
+    using frag_t = typename P::frag_t;
     const Tile tl = tiles[blockIdx.x];
     if (tl.blk < 0) return;   // padding of the XCD-ordered list
     const S2Block B = blks[tl.blk];
-    const ProbPtrs P = probs ? probs[B.prob] : single;
-    if (P.skip && *P.skip) return;
+    const ProbPtrs P_ = probs ? probs[B.prob] : single;
+    if (P_.skip && *P_.skip) return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int g = lane >> 4, r = lane & 15;
-    const double xs = P.xscale ? *P.xscale : 1.0;
+    const double xs = P_.xscale ? *P_.xscale : 1.0;
     const int split = B.Y.split;   // columns per plane of the output and of every source
+    const ws_t* __restrict__ Tws = static_cast<const ws_t*>(P_.T);
 
-    const double* pa[2];
+    const op_t* pa[2];
     int pl[2], col[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int pnl = tl.m0 / kPanel + i;
-        pa[i] = static_cast<const double*>(P.Lops) + B.Aoff +
-                (((int64_t)pnl * B.nch) * 4 + g) * (kPanel * 4) + r * 4;
+        pa[i] = static_cast<const op_t*>(P_.Lops) + B.Aoff +
+                (((int64_t)pnl * B.nch) * 4 + g) * (kPanel * lane_elems<P>()) + r * lane_elems<P>();
         const int n = min(tl.n0 + 16 * i + r, B.N - 1);
         pl[i] = n >= split;
         col[i] = n - pl[i] * split;
     }
-    d4 acc[2][2];
-    zero_acc(acc);
+    acc_t acc[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) zero<P>(acc[mi][nj]);
     for (int s = 0; s < B.nseg; ++s) {
         const Segment sg = segs[B.seg0 + s];
-        const double* __restrict__ src = sg.src ? P.T : P.x;
         int64_t bcol[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
             bcol[i] = sg.B.off + pl[i] * sg.B.poff + (int64_t)col[i] * sg.B.ld;
         const int K = sg.K;
-        auto load = [&](int c, Frag& f) {
-            const int64_t ga = (int64_t)(sg.ch0 + c) * kChunkElems;
-#pragma unroll
-            for (int i = 0; i < 2; ++i) f.a[i] = ldg4(pa[i] + ga);
-            const int kb = c * kChunk + 4 * g;
-            if ((c + 1) * kChunk <= K) {   // full chunk: four consecutive doubles per lane
-#pragma unroll
-                for (int t = 0; t < 4; ++t)
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) f.b[i][t] = ldg(src, bcol[i] + kb + t);
-            } else {
-#pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int kk = min(kb + t, K - 1);
-#pragma unroll
-                    for (int i = 0; i < 2; ++i) f.b[i][t] = ldg(src, bcol[i] + kk);
-                }
-            }
-        };
-        const int nch = (K + kChunk - 1) / kChunk;
+        const int nch = (K + P::CK - 1) / P::CK;
         // chunk c of this segment is global chunk ch0 + c, owned by wave (ch0 + c) mod 4
         const int c0 = ((wave - sg.ch0) % kWaves + kWaves) % kWaves;
-        kloop(acc, c0, kWaves, nch, load);
-        // segment 0 (the diagonal H_S term) is the only one reading the input vector: its
-        // scale is applied to the accumulators before any other segment adds in
-        if (s == 0) scale_acc(acc, xs);
+        if (sg.src) {
+            auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[2]) {
+                const int64_t ga = (int64_t)(sg.ch0 + c) * chunk_elems<P>();
+#pragma unroll
+                for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
+                const int kb = c * P::CK + P::KPL * g;
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    double v[P::KPL];
+                    load_run<P>(Tws, bcol[i] + kb, v);
+                    fb[i] = P::from(v);
+                }
+            };
+            kloop<P>(acc, c0, kWaves, nch, load);
+        } else {
+            auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[2]) {
+                const int64_t ga = (int64_t)(sg.ch0 + c) * chunk_elems<P>();
+#pragma unroll
+                for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
+                const int kb = c * P::CK + P::KPL * g;
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    double v[P::KPL];
+                    load_clamped<P>(P_.x, bcol[i], kb, K, 1, v);
+                    fb[i] = P::from(v);
+                }
+            };
+            kloop<P>(acc, c0, kWaves, nch, load);
+            // segment 0 (the diagonal H_S term) is the only one reading the input vector:
+            // its scale is applied before any other segment adds in
+#pragma unroll
+            for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[mi][nj][v] *= xs;
+        }
     }
 
     __shared__ double red[kWaves][kTile][kTile + 1];
@@ -245,11 +355,10 @@ __global__ __launch_bounds__(256) void stage2_f64(const S2Block* __restrict__ bl
 #pragma unroll
         for (int nj = 0; nj < 2; ++nj)
 #pragma unroll
-            for (int v = 0; v < 4; ++v)   // f64 16x16 MFMA result: row g + 4v, column r
-                red[wave][16 * nj + r][16 * mi + g + 4 * v] = acc[mi][nj][v];
+            for (int v = 0; v < 4; ++v)
+                red[wave][16 * nj + r][16 * mi + P::row(g, v)] = (double)acc[mi][nj][v];
     __syncthreads();
-    const double* __restrict__ T = P.T;
-    double* __restrict__ Y = P.y;
+    double* __restrict__ Y = P_.y;
     const View t0 = B.T0, yv = B.Y;
     const int m = threadIdx.x & 31;
 #pragma unroll
@@ -260,27 +369,53 @@ __global__ __launch_bounds__(256) void stage2_f64(const S2Block* __restrict__ bl
             const double v = ((red[0][n][m] + red[1][n][m]) + red[2][n][m]) + red[3][n][m];
             const int p = gn >= split;
             const int c = gn - p * split;
-            const double init = T[t0.off + p * t0.poff + (int64_t)c * t0.ld + gm];
+            const double init = (double)Tws[t0.off + p * t0.poff + (int64_t)c * t0.ld + gm];
             Y[yv.off + p * yv.poff + (int64_t)c * yv.ld + gm] = init + v;
         }
     }
 }
 
-hipError_t launch_stage1_f64(const S1Block* blks, const Tile* tiles, int ntiles,
-                             const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
+// ---------------------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------------------
+namespace {
+
+template <class P>
+hipError_t launch1(const S1Block* blks, const Tile* tiles, int ntiles, const ProbPtrs* probs,
+                   ProbPtrs single, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
     const int nblk = (ntiles + kWaves - 1) / kWaves;
-    hipLaunchKernelGGL(stage1_f64, dim3(nblk), dim3(256), 0, st, blks, tiles, ntiles, probs,
-                       single);
+    hipLaunchKernelGGL(stage1<P>, dim3(nblk), dim3(256), 0, st, blks, tiles, ntiles, probs, single);
     return hipGetLastError();
 }
 
-hipError_t launch_stage2_f64(const S2Block* blks, const Segment* segs, const Tile* tiles,
-                             int ntiles, const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
+template <class P>
+hipError_t launch2(const S2Block* blks, const Segment* segs, const Tile* tiles, int ntiles,
+                   const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(stage2_f64, dim3(ntiles), dim3(256), 0, st, blks, segs, tiles, probs,
-                       single);
+    hipLaunchKernelGGL(stage2<P>, dim3(ntiles), dim3(256), 0, st, blks, segs, tiles, probs, single);
     return hipGetLastError();
+}
+
+}  // namespace
+
+// prec: 0 FP64, 1 FP32, 2 BF16x3 (the operator buffers and workspace must match)
+hipError_t launch_stage1(int prec, const S1Block* blks, const Tile* tiles, int ntiles,
+                         const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
+    switch (prec) {
+        case 0: return launch1<PF64>(blks, tiles, ntiles, probs, single, st);
+        case 1: return launch1<PF32>(blks, tiles, ntiles, probs, single, st);
+        default: return launch1<PBF3>(blks, tiles, ntiles, probs, single, st);
+    }
+}
+
+hipError_t launch_stage2(int prec, const S2Block* blks, const Segment* segs, const Tile* tiles,
+                         int ntiles, const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
+    switch (prec) {
+        case 0: return launch2<PF64>(blks, segs, tiles, ntiles, probs, single, st);
+        case 1: return launch2<PF32>(blks, segs, tiles, ntiles, probs, single, st);
+        default: return launch2<PBF3>(blks, segs, tiles, ntiles, probs, single, st);
+    }
 }
 
 }  // namespace dmrg

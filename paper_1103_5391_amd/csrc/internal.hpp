@@ -9,7 +9,8 @@ namespace dmrg {
 constexpr int kMaxKrylov = 64;      // largest kdim accepted
 constexpr int kTile = 32;           // output tile edge of the block-product kernels
 constexpr int kTile1N = 64;         // stage-1 tiles are kTile x kTile1N (one per wavefront)
-constexpr int kChunk = 16;          // K depth of one register chunk (4 MFMA K-steps of 4)
+constexpr int kChunk = 16;          // K depth of one FP64/FP32 chunk (4 MFMA K-steps of 4)
+constexpr int kChunkMax = 32;       // K depth of one BF16 chunk (one 16x16x32 MFMA)
 constexpr int kWaves = 4;           // waves per work group (split-K among them)
 constexpr int kVecThreads = 256;    // threads per block of the vector kernels
 constexpr int kMaxTimes = 4;        // time points evaluated from one Krylov basis
@@ -26,19 +27,20 @@ struct View {
     int32_t split;
 };
 
-// Operator factors are packed once, at creation, in the order the MFMA lanes consume them:
-// 16-row (or 16-column) panels, 16-deep K chunks, and inside a chunk [g][r][t] with
-// k = 4g + t, so lane (g, r) reads its four K values of one chunk as 32 contiguous bytes.
-// Rows (columns) are zero-padded to the 32-wide tile and K to a multiple of 16, so operator
-// loads never need bounds checks and padded products vanish.
+// Operator factors are packed once per arithmetic in the order the MFMA lanes consume them:
+// 16-row (or 16-column) panels, K chunks of depth CK (16 for FP64/FP32, 32 for BF16), and
+// inside a chunk [g][r][t] with k = KPL g + t, KPL = CK / 4, so lane (g, r) reads its KPL
+// values of one chunk as one contiguous piece (BF16: KPL hi values then KPL lo values).
+// Rows (columns) are zero-padded to the tile and K to whole chunks, so operator loads never
+// need bounds checks and padded products vanish.
 constexpr int kPanel = 16;                        // rows (columns) per packed panel
-constexpr int kChunkElems = kPanel * kChunk;      // doubles per packed chunk (256)
 
 // Stage 1 (right products) of one source block b:  T_b = X_b * R_b
 //   X_b: 2d x e, rows 0..d-1 = real plane of Psi_b, rows d..2d-1 = imaginary plane
 //   R_b: e x N, [H_E(q)^T | right factors of every term leaving b], packed (column panels)
-//   T_b: workspace, column-major with both planes padded to dpad = d rounded up to 4 rows
-//        (ld 2 dpad), so every column segment the left products read is 32-byte aligned
+//   T_b: workspace, column-major with both planes padded to dpad = d rounded up to a whole
+//        K chunk (ld 2 dpad); the padding rows are zeroed once and never written, so the left
+//        products read whole chunks of a column without bounds checks
 struct S1Block {
     int32_t M, K, N, prob;
     int32_t nch, pad;   // K chunks of the packed factor
@@ -77,11 +79,23 @@ struct Tile {
 struct ProbPtrs {
     const double* x;        // input vector
     double* y;              // output vector
-    double* T;              // workspace
+    void* T;                // workspace (FP64 or FP32 elements)
     const void* Lops;       // packed left factors (stage 2), precision dependent type
     const void* Rops;       // packed right factors (stage 1)
     const double* xscale;   // scale applied to x on load (nullptr = 1)
     const int* skip;        // nonzero: skip all work of this problem (nullptr = never)
+};
+
+// One problem of a vector pass (fixed per handle; a batch concatenates them).  Blocks
+// b0 .. b0 + nb - 1 of a launch work on this problem.
+struct VecProb {
+    double* V;            // basis slots: slot j at V + j * vstride
+    double* w;            // matvec output / work vector
+    double* part;         // block partial sums of this problem
+    struct KState* st;
+    int64_t n;            // complex length
+    int64_t vstride;      // doubles between slots (2n)
+    int32_t nb, b0;
 };
 
 // Device state of one Krylov run on one problem.

@@ -12,6 +12,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <sstream>
 
 namespace dmrg {
@@ -78,16 +79,6 @@ std::string load_half(const dmrg_half& h, HalfTable& t, const char* name) {
     return "";
 }
 
-// Block of an operator (or its transpose) leaving sector src.  Returns the destination sector
-// or -1; M(i, j) = element (i, j) of the (dst x src) block.
-struct OpRef {
-    int dst = -1;
-    const double* data = nullptr;
-    int ld = 0;         // leading dimension of the stored block
-    bool transposed = false;
-    double at(int i, int j) const { return transposed ? data[(int64_t)i * ld + j] : data[(int64_t)j * ld + i]; }
-};
-
 bool all_zero(const OpRef& r, int rows, int cols) {
     const int64_t cnt = (int64_t)rows * cols;
     for (int64_t i = 0; i < cnt; ++i)
@@ -117,12 +108,16 @@ OpRef op_from(const HalfTable& t, int opi, bool trans, int src) {
 
 int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
-// Offset of element (i, k) inside a packed factor: i = row (stage 2) or column (stage 1),
-// k = K index counted from the start of the packed K range, nch = K chunks per panel.
-int64_t packed_index(int i, int k, int nch) {
+// Element offset of (i, k) inside a packed factor with chunk depth ck: i = row (stage 2) or
+// column (stage 1), k = K index from the start of the packed K range, nch = chunks per panel,
+// per = elements per K index (2 for bf16 hi/lo pairs).  Layout [panel][chunk][g][r][t]
+// (hi values t then lo values KPL + t for bf16), KPL = ck / 4.
+int64_t packed_index(int i, int k, int nch, int ck, int per) {
+    const int kpl = ck / 4;
     const int pnl = i / kPanel, r = i % kPanel;
-    const int ch = k / kChunk, g = (k % kChunk) / 4, t = k % 4;
-    return (((int64_t)pnl * nch + ch) * 4 + g) * (kPanel * 4) + r * 4 + t;
+    const int ch = k / ck, g = (k % ck) / kpl, t = k % kpl;
+    const int le = kpl * per;
+    return (((int64_t)pnl * nch + ch) * 4 + g) * (kPanel * le) + r * le + t;
 }
 
 // Reorders a tile list (tiles of one block contiguous) for launch: work groups of `group`
@@ -225,14 +220,9 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
     if (P.blocks.empty()) return "the target sector is empty";
     const int nb = (int)P.blocks.size();
 
-    // outgoing terms per source block
-    struct Edge {
-        int src, dst, term;
-        OpRef a, b;
-        int col;          // first column of the right factor inside R_src
-    };
-    std::vector<Edge> edges;
-    std::vector<std::vector<int>> out_of(nb), into(nb);
+    // every (term, source block) pair with a non-zero contribution
+    P.out_of.assign(nb, {});
+    P.into.assign(nb, {});
     for (int bi = 0; bi < nb; ++bi) {
         const auto& B = P.blocks[bi];
         for (size_t ti = 0; ti < P.terms.size(); ++ti) {
@@ -245,133 +235,187 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
             if (dst < 0 || P.blocks[dst].q != b.dst) continue;
             // blocks that are exactly zero contribute nothing and are not counted as work
             if (all_zero(a, P.S.dim[a.dst], B.d) || all_zero(b, P.E.dim[b.dst], B.e)) continue;
-            edges.push_back(Edge{bi, dst, (int)ti, a, b, 0});
-            out_of[bi].push_back((int)edges.size() - 1);
-            into[dst].push_back((int)edges.size() - 1);
+            P.edges.push_back(Edge{bi, dst, (int)ti, a, b, 0});
+            P.out_of[bi].push_back((int)P.edges.size() - 1);
+            P.into[dst].push_back((int)P.edges.size() - 1);
         }
     }
 
-    // stage 1: R_b = [H_E(q)^T | B_1^T | ...], T_b = X_b R_b
-    double flops = 0.0;
+    // stage-1 columns, workspace views (planes padded to whole 32-deep chunks), flops, tiles
+    P.N1.assign(nb, 0);
+    P.Tview.assign(nb, View{});
     int64_t toff = 0;
     for (int bi = 0; bi < nb; ++bi) {
         const auto& B = P.blocks[bi];
         int N = B.e;
-        for (int ei : out_of[bi]) {
-            edges[ei].col = N;
-            N += P.blocks[edges[ei].dst].e;
+        for (int ei : P.out_of[bi]) {
+            P.edges[ei].col = N;
+            N += P.blocks[P.edges[ei].dst].e;
         }
-        S1Block s;
-        s.M = 2 * B.d;
-        s.K = B.e;
-        s.N = N;
-        s.prob = 0;
-        s.nch = (B.e + kChunk - 1) / kChunk;
-        s.pad = 0;
-        s.X = View{B.off, P.n, B.d, B.d};
-        s.Roff = (int64_t)P.R.size();
-        const int dpad = round_up(B.d, 4);
-        s.T = View{toff, dpad, 2 * dpad, B.d};
+        P.N1[bi] = N;
+        const int dpad = round_up(B.d, kChunkMax);
+        P.Tview[bi] = View{toff, dpad, 2 * dpad, B.d};
         toff += (int64_t)2 * dpad * N;
-        // pack R (K x N) by column panels, zero padding to whole tiles and chunks
-        const int Npad = round_up(N, kTile1N);
-        P.R.resize(P.R.size() + (size_t)Npad * s.nch * kChunk, 0.0);
-        double* R = P.R.data() + s.Roff;
-        const double* HE = P.E.H.data() + P.E.hoff[B.q];
-        for (int j = 0; j < B.e; ++j)          // R(k, j) = H_E(q)(j, k)
-            for (int k = 0; k < B.e; ++k) R[packed_index(j, k, s.nch)] = HE[(int64_t)k * B.e + j];
-        for (int ei : out_of[bi]) {
-            const Edge& ed = edges[ei];
-            const int e2 = P.blocks[ed.dst].e;
-            for (int j = 0; j < e2; ++j)          // R(k, col + j) = B(j, k)
-                for (int k = 0; k < B.e; ++k)
-                    R[packed_index(ed.col + j, k, s.nch)] = ed.b.at(j, k);
-        }
-        flops += 2.0 * s.M * (double)s.K * s.N;
-        P.flops1 += 2.0 * s.M * (double)s.K * s.N;
-        P.s1.push_back(s);
-        tile_list(P.tiles1, bi, s.M, s.N, kTile, kTile1N);
+        P.flops1 += 2.0 * (2 * B.d) * (double)B.e * N;
+        tile_list(P.tiles1, bi, 2 * B.d, N, kTile, kTile1N);
     }
     P.T_size = toff;
-
-    // stage 2: Y_b' = T0 + [H_S(p') | s A ...] [X_b' ; T parts]
+    std::vector<int> kcat(nb);
     for (int bi = 0; bi < nb; ++bi) {
         const auto& B = P.blocks[bi];
-        S2Block s;
-        s.M = B.d;
-        s.N = 2 * B.e;
-        s.prob = 0;
-        s.seg0 = (int)P.segs.size();
-        s.Aoff = (int64_t)P.A.size();
-        s.T0 = View{P.s1[bi].T.off, P.s1[bi].T.poff, P.s1[bi].T.ld, B.e};
-        s.Y = View{B.off, P.n, B.d, B.e};
-        int kA = 0, nch = 0;
-        // diagonal H_S term on the block itself
-        Segment g0;
-        g0.K = B.d;
-        g0.ch0 = 0;
-        g0.src = 0;
-        g0.pad = 0;
-        g0.B = View{B.off, P.n, B.d, B.e};
-        P.segs.push_back(g0);
-        kA += B.d;
-        nch += (B.d + kChunk - 1) / kChunk;
-        for (int ei : into[bi]) {
-            const Edge& ed = edges[ei];
-            const auto& Bs = P.blocks[ed.src];
-            Segment g;
-            g.K = Bs.d;
-            g.ch0 = nch;
-            g.src = 1;
-            g.pad = 0;
-            const View& ts = P.s1[ed.src].T;
-            g.B = View{ts.off + (int64_t)ed.col * ts.ld, ts.poff, ts.ld, B.e};
-            P.segs.push_back(g);
-            kA += Bs.d;
-            nch += (Bs.d + kChunk - 1) / kChunk;
-        }
-        s.nseg = (int)P.segs.size() - s.seg0;
-        s.nch = nch;
-        // pack Acat (d' x Kcat) by row panels, each segment starting on a fresh chunk
-        const int Mpad = round_up(B.d, kTile);
-        P.A.resize(P.A.size() + (size_t)Mpad * nch * kChunk, 0.0);
-        double* A = P.A.data() + s.Aoff;
-        const double* HS = P.S.H.data() + P.S.hoff[B.p];
-        for (int k = 0; k < B.d; ++k)
-            for (int i = 0; i < B.d; ++i) A[packed_index(i, k, nch)] = HS[(int64_t)k * B.d + i];
-        int si = 1;
-        for (int ei : into[bi]) {
-            const Edge& ed = edges[ei];
-            const auto& Bs = P.blocks[ed.src];
-            const auto& t = P.terms[ed.term];
-            const double c = t.coef * (t.fermionic ? P.S.parity(Bs.p) : 1);
-            const int kbase = P.segs[s.seg0 + si].ch0 * kChunk;
-            for (int k = 0; k < Bs.d; ++k)
-                for (int i = 0; i < B.d; ++i) A[packed_index(i, kbase + k, nch)] = c * ed.a.at(i, k);
-            ++si;
-        }
-        flops += 2.0 * s.M * (double)s.N * kA;
-        P.flops2 += 2.0 * s.M * (double)s.N * kA;
-        P.s2.push_back(s);
-        tile_list(P.tiles2, bi, s.M, s.N, kTile, kTile);
+        int k = B.d;
+        for (int ei : P.into[bi]) k += P.blocks[P.edges[ei].src].d;
+        kcat[bi] = k;
+        P.flops2 += 2.0 * B.d * (double)(2 * B.e) * k;
+        tile_list(P.tiles2, bi, B.d, 2 * B.e, kTile, kTile);
     }
-    P.flops = flops;
+    P.flops = P.flops1 + P.flops2;
+
+    // descriptors for both chunk depths
+    for (Packing* pk : {&P.pk16, &P.pk32}) {
+        pk->ck = (pk == &P.pk16) ? 16 : 32;
+        const int ck = pk->ck, per = (ck == 16) ? 1 : 2;
+        int64_t roff = 0, aoff = 0;
+        for (int bi = 0; bi < nb; ++bi) {
+            const auto& B = P.blocks[bi];
+            S1Block s;
+            s.M = 2 * B.d;
+            s.K = B.e;
+            s.N = P.N1[bi];
+            s.prob = 0;
+            s.nch = (B.e + ck - 1) / ck;
+            s.pad = 0;
+            s.X = View{B.off, P.n, B.d, B.d};
+            s.Roff = roff;
+            s.T = P.Tview[bi];
+            roff += (int64_t)round_up(s.N, kTile1N) * s.nch * ck * per;
+            pk->s1.push_back(s);
+        }
+        for (int bi = 0; bi < nb; ++bi) {
+            const auto& B = P.blocks[bi];
+            S2Block s;
+            s.M = B.d;
+            s.N = 2 * B.e;
+            s.prob = 0;
+            s.seg0 = (int)pk->segs.size();
+            s.Aoff = aoff;
+            s.T0 = View{P.Tview[bi].off, P.Tview[bi].poff, P.Tview[bi].ld, B.e};
+            s.Y = View{B.off, P.n, B.d, B.e};
+            int nch = 0;
+            // the diagonal H_S term reads the block itself from the input vector
+            pk->segs.push_back(Segment{B.d, 0, 0, 0, View{B.off, P.n, B.d, B.e}});
+            nch += (B.d + ck - 1) / ck;
+            for (int ei : P.into[bi]) {
+                const Edge& ed = P.edges[ei];
+                const auto& Bs = P.blocks[ed.src];
+                const View& ts = P.Tview[ed.src];
+                pk->segs.push_back(Segment{Bs.d, nch, 1, 0,
+                                           View{ts.off + (int64_t)ed.col * ts.ld, ts.poff, ts.ld, B.e}});
+                nch += (Bs.d + ck - 1) / ck;
+            }
+            s.nseg = (int)pk->segs.size() - s.seg0;
+            s.nch = nch;
+            aoff += (int64_t)round_up(B.d, kTile) * nch * ck * per;
+            pk->s2.push_back(s);
+        }
+        pk->R_elems = roff;
+        pk->A_elems = aoff;
+    }
 
     // XCD-aware launch order: every block's tiles go to one XCD (so its packed factor panels
     // and source panels are shared in that XCD's L2), blocks are spread over the XCDs by
     // longest-processing-time, heaviest first inside each XCD.
     std::vector<double> w1(nb), w2(nb);
     for (int bi = 0; bi < nb; ++bi) {
-        int k = 0;
-        for (int s = 0; s < P.s2[bi].nseg; ++s) k += P.segs[P.s2[bi].seg0 + s].K;
-        const double nt1 = (double)((P.s1[bi].M + kTile - 1) / kTile) * ((P.s1[bi].N + kTile1N - 1) / kTile1N);
-        const double nt2 = (double)((P.s2[bi].M + kTile - 1) / kTile) * ((P.s2[bi].N + kTile - 1) / kTile);
-        w1[bi] = nt1 * (P.s1[bi].nch + 1);
-        w2[bi] = nt2 * ((k + kChunk - 1) / kChunk + 2);
+        const auto& B = P.blocks[bi];
+        const double nt1 = (double)((2 * B.d + kTile - 1) / kTile) * ((P.N1[bi] + kTile1N - 1) / kTile1N);
+        const double nt2 = (double)((B.d + kTile - 1) / kTile) * ((2 * B.e + kTile - 1) / kTile);
+        w1[bi] = nt1 * ((B.e + 15) / 16 + 1);
+        w2[bi] = nt2 * ((kcat[bi] + 15) / 16 + 2);
     }
     P.tiles1 = xcd_order(P.tiles1, w1, kWaves);
     P.tiles2 = xcd_order(P.tiles2, w2, 1);
     return "";
+}
+
+namespace {
+
+uint16_t bf16_rne(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return (uint16_t)((u >> 16) | 0x40);   // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+float bf16_to_float(uint16_t h) {
+    const uint32_t u = (uint32_t)h << 16;
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// Writes value v at packed position (i, k) in the arithmetic `kind`.
+struct Writer {
+    int kind, ck, per;
+    uint8_t* base;
+    void put(int64_t blk_off, int i, int k, int nch, double v) const {
+        const int64_t o = blk_off + packed_index(i, k, nch, ck, per);
+        if (kind == 0) {
+            reinterpret_cast<double*>(base)[o] = v;
+        } else if (kind == 1) {
+            reinterpret_cast<float*>(base)[o] = (float)v;
+        } else {
+            const float x = (float)v;
+            const uint16_t hi = bf16_rne(x);
+            const uint16_t lo = bf16_rne(x - bf16_to_float(hi));
+            uint16_t* b = reinterpret_cast<uint16_t*>(base);
+            b[o] = hi;
+            b[o + ck / 4] = lo;
+        }
+    }
+};
+
+}  // namespace
+
+void pack_operators(const Plan& P, int kind, std::vector<uint8_t>& A, std::vector<uint8_t>& R) {
+    const Packing& pk = (kind == 2) ? P.pk32 : P.pk16;
+    const size_t esz = (kind == 0) ? 8 : (kind == 1 ? 4 : 2);
+    A.assign((size_t)pk.A_elems * esz, 0);
+    R.assign((size_t)pk.R_elems * esz, 0);
+    const int per = (kind == 2) ? 2 : 1;
+    const Writer wa{kind, pk.ck, per, A.data()}, wr{kind, pk.ck, per, R.data()};
+    const int nb = (int)P.blocks.size();
+    for (int bi = 0; bi < nb; ++bi) {
+        const auto& B = P.blocks[bi];
+        // R_b (K = e rows, N columns): R(k, j) = H_E(q)(j, k), then R(k, col + j) = B(j, k)
+        const S1Block& s1 = pk.s1[bi];
+        const double* HE = P.E.H.data() + P.E.hoff[B.q];
+        for (int j = 0; j < B.e; ++j)
+            for (int k = 0; k < B.e; ++k) wr.put(s1.Roff, j, k, s1.nch, HE[(int64_t)k * B.e + j]);
+        for (int ei : P.out_of[bi]) {
+            const Edge& ed = P.edges[ei];
+            const int e2 = P.blocks[ed.dst].e;
+            for (int j = 0; j < e2; ++j)
+                for (int k = 0; k < B.e; ++k) wr.put(s1.Roff, ed.col + j, k, s1.nch, ed.b.at(j, k));
+        }
+        // Acat_b (d rows): [H_S(p) | coef * sign * A per incoming term], segments chunk-aligned
+        const S2Block& s2 = pk.s2[bi];
+        const double* HS = P.S.H.data() + P.S.hoff[B.p];
+        for (int k = 0; k < B.d; ++k)
+            for (int i = 0; i < B.d; ++i) wa.put(s2.Aoff, i, k, s2.nch, HS[(int64_t)k * B.d + i]);
+        int si = 1;
+        for (int ei : P.into[bi]) {
+            const Edge& ed = P.edges[ei];
+            const auto& Bs = P.blocks[ed.src];
+            const auto& t = P.terms[ed.term];
+            const double c = t.coef * (t.fermionic ? P.S.parity(Bs.p) : 1);
+            const int kbase = pk.segs[s2.seg0 + si].ch0 * pk.ck;
+            for (int k = 0; k < Bs.d; ++k)
+                for (int i = 0; i < B.d; ++i) wa.put(s2.Aoff, i, kbase + k, s2.nch, c * ed.a.at(i, k));
+            ++si;
+        }
+    }
 }
 
 }  // namespace dmrg

@@ -1,5 +1,5 @@
-// Host planner of libdmrgtst: sector tables, connection-term expansion, packed operator
-// buffers and tile work lists for the two block-product stages of H_sb.psi.
+// Host planner of libdmrgtst: sector tables, connection-term expansion, tile work lists and
+// packed operator buffers for the two block-product stages of H_sb.psi.
 #pragma once
 
 #include <cstdint>
@@ -43,7 +43,35 @@ struct PsiBlock {
     int64_t off;
 };
 
-// Everything the device needs for H_sb.psi in one precision-independent form (FP64 data).
+// Block of an operator (or its transpose) leaving a sector: at(i, j) = element (i, j) of the
+// (destination x source) block.
+struct OpRef {
+    int dst = -1;
+    const double* data = nullptr;
+    int ld = 0;          // leading dimension of the stored block
+    bool transposed = false;
+    double at(int i, int j) const {
+        return transposed ? data[(int64_t)i * ld + j] : data[(int64_t)j * ld + i];
+    }
+};
+
+// One connection term applied to one source block.
+struct Edge {
+    int src, dst, term;
+    OpRef a, b;
+    int col;             // first column of its right factor inside R_src (stage-1 output)
+};
+
+// Descriptors of the two stages for one K-chunk depth (16 for FP64 and FP32, 32 for BF16x3):
+// the chunk structure decides the packed operator layout and sizes.
+struct Packing {
+    int ck = 0;
+    std::vector<S1Block> s1;
+    std::vector<S2Block> s2;
+    std::vector<Segment> segs;
+    int64_t A_elems = 0, R_elems = 0;          // packed operator elements
+};
+
 struct Plan {
     HalfTable S, E;
     int target[2] = {0, 0};
@@ -51,21 +79,22 @@ struct Plan {
     std::vector<PsiBlock> blocks;
     std::vector<int> block_of_S;               // S sector -> psi block or -1
     int64_t n = 0;                             // complex length
-    // stage 1
-    std::vector<S1Block> s1;
-    std::vector<double> R;                     // packed right factors
-    std::vector<Tile> tiles1;
-    // stage 2
-    std::vector<S2Block> s2;
-    std::vector<Segment> segs;
-    std::vector<double> A;                     // packed left factors
-    std::vector<Tile> tiles2;
-    int64_t T_size = 0;                        // workspace doubles
+    std::vector<Edge> edges;
+    std::vector<std::vector<int>> out_of, into;
+    std::vector<int> N1;                       // stage-1 columns per source block
+    std::vector<View> Tview;                   // stage-1 workspace view per block
+    int64_t T_size = 0;                        // workspace elements
+    std::vector<Tile> tiles1, tiles2;
+    Packing pk16, pk32;
     double flops = 0.0;                        // algorithmic flops per complex matvec
     double flops1 = 0.0, flops2 = 0.0;         // of which stage 1 / stage 2
 };
 
 // Returns an empty string on success, else the reason the problem is invalid.
 std::string build_plan(const dmrg_problem* pb, Plan& plan);
+
+// Packed operator buffers for one arithmetic (raw bytes): kind 0 FP64 and 1 FP32 use the
+// 16-deep packing, kind 2 (bf16 hi/lo pairs) the 32-deep one.
+void pack_operators(const Plan& plan, int kind, std::vector<uint8_t>& A, std::vector<uint8_t>& R);
 
 }  // namespace dmrg
