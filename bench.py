@@ -60,6 +60,55 @@ def cpu_baseline(pb, phi, kdim, tau, F, budget_s=12.0):
                       f"(kdim={kdim}, oracle FP64 NumPy/SciPy), {el:.1f} s timed"}
 
 
+def batch_section(L, I, torch, steps, warmup, count=64):
+    """Configuration of 64 independent chain superblocks (m 100..1000): the batched call (one
+    launch per pass for all problems, Lanczos iterations as one HIP graph) against the
+    per-problem launch loop, both on the same handles and inputs."""
+    import numpy as np
+    kdim, tau = 15, 0.05
+    pbs = I.batch_workloads(count)
+    stream = torch.cuda.current_stream()
+    hs = [L.dmrg_create(pb, stream) for pb in pbs]
+    F = sum(h.flops() for h in hs)
+    pds = [torch.from_numpy(I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 900 + i))).to("cuda")
+           for i, h in enumerate(hs)]
+    tds = [torch.empty(8 * h.n, dtype=torch.float64, device="cuda") for h in hs]
+    b = L.Batch(hs)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(steps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    def loop():
+        for h, p, t in zip(hs, pds, tds):
+            h.tst_targets(p, tau, kdim, t, info=False)
+
+    ms_loop = timed(loop)
+    out = {"problems": count, "kdim": kdim, "tau": tau, "n_total": int(sum(h.n for h in hs)),
+           "flops_per_step": F * kdim, "per_problem_loop_ms": round(ms_loop, 4)}
+    for graph in (False, True):
+        b.set_graph(graph)
+        ms = timed(lambda: b.batch_tst_targets(pds, tau, kdim, tds, info=False))
+        key = "batched_graph" if graph else "batched_eager"
+        out[key + "_ms"] = round(ms, 4)
+        out[key + "_speedup_vs_loop"] = round(ms_loop / ms, 3)
+    out["batched_graph_tflops"] = round(F * kdim / (out["batched_graph_ms"] * 1e-3) / 1e12, 4)
+    out["per_problem_loop_tflops"] = round(F * kdim / (ms_loop * 1e-3) / 1e12, 4)
+    b.destroy()
+    for h in hs:
+        h.destroy()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -67,6 +116,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="ladder16_m1000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -161,6 +211,12 @@ def main():
         print(f"[bench] {label}: {ms_p:.4f} ms/step, {mixed[label]}", file=sys.stderr, flush=True)
     h.set_precision(L.DMRG_FP64)
 
+    batched = None
+    if not args.no_batch:
+        print("[bench] batched configuration (64 superblocks)", file=sys.stderr, flush=True)
+        batched = batch_section(L, I, torch, max(3, args.steps // 5), 1)
+        print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
+
     value = kdim * F / (ms_step * 1e-3) / 1e12
     out = {
         "metric": "H·ψ TFLOP/s + Krylov steps/s (ladder, m=1000) vs FP64 plain; % MFMA peak",
@@ -184,6 +240,7 @@ def main():
         "matvec_ms": round(ms_mv, 5),
         "mfma_peak_frac_step": round(value / PEAK_FP64_TFLOPS, 4),
         "mixed_precision": mixed,
+        "batched_64": batched,
         "roofline": {"bound": "mfma", "kernel": f"stage{dom} (fp64)",
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),

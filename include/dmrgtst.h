@@ -151,7 +151,8 @@ int dmrg_psi_layout(dmrg_handle h, int64_t* n, int32_t* nblk, int64_t* off, int3
 int dmrg_flops(dmrg_handle h, double* flops);
 
 /* Selects the block-product arithmetic; converted operator copies are built on first use and
- * cached.  DMRG_EINVAL for an unknown value. */
+ * cached.  A change of arithmetic waits for the handle's stream (the intermediate workspace is
+ * cleared for the new element size).  DMRG_EINVAL for an unknown value. */
 int dmrg_set_precision(dmrg_handle h, int32_t precision);
 
 /* Changes the stream all later work of the handle is ordered on. */
@@ -176,14 +177,28 @@ int dmrg_krylov_expm(dmrg_handle h, const double* x, double* y, double tau, int3
 int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim,
                      double* targets, double* weights, dmrg_krylov_info* info);
 
-/* Batched time-step targeting over independent superblocks (handles created beforehand; the
- * batch keeps references, the handles must outlive it).  The batch runs on the first
- * handle's stream. */
+/* Runs the kdim Lanczos iterations of dmrg_krylov_expm and dmrg_tst_targets as one HIP graph
+ * (captured on first use per kdim on a private stream, launched on the handle's stream;
+ * re-captured after the workspace or the precision changes) instead of one launch per pass.
+ * Off by default.  Results are identical either way. */
+int dmrg_set_graph(dmrg_handle h, int32_t enable);
+
+/* Batched time-step targeting over independent superblocks (Sec. II.B applied to many
+ * superblocks at once; handles created beforehand, distinct, all set to one precision).  The
+ * batch merges the block-product work lists of all handles into one launch per stage and runs
+ * every Lanczos pass for all of them in one launch; the kdim iterations run as one HIP graph
+ * unless dmrg_batch_set_graph(b, 0).  The batch keeps references: the handles must outlive it
+ * and must not be used concurrently with it.  Its work is ordered on the stream of the first
+ * handle; errors of batch calls are described by dmrg_last_error of the first handle. */
 int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out);
 void dmrg_batch_destroy(dmrg_batch b);
+int dmrg_batch_set_graph(dmrg_batch b, int32_t enable);
 
-/* phi[i], targets[i]: device pointers for superblock i (host arrays of count pointers).
- * infos: NULL or a host array of count structs (then the call waits for the stream). */
+/* phi[i], targets[i]: device pointers for superblock i (host arrays of count pointers; the
+ * targets of superblock i are 4 x 2 n_i doubles).  Results equal those of dmrg_tst_targets on
+ * each handle.  weights as in dmrg_tst_targets.  infos: NULL or a host array of count structs
+ * (then the call waits for the stream).  DMRG_EINVAL if a pointer is NULL or the handles use
+ * different precisions. */
 int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, int32_t kdim,
                            double* const* targets, double* weights, dmrg_krylov_info* infos);
 

@@ -6,6 +6,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <new>
 #include <string>
 #include <vector>
@@ -20,12 +21,12 @@ hipError_t launch_stage1(int, const S1Block*, const Tile*, int, const ProbPtrs*,
                          hipStream_t);
 hipError_t launch_stage2(int, const S2Block*, const Segment*, const Tile*, int, const ProbPtrs*,
                          ProbPtrs, hipStream_t);
-hipError_t launch_start(const double*, double*, int64_t, KState*, double*, int, int, hipStream_t);
-hipError_t launch_lanczos_iter(double*, int64_t, double*, int64_t, int, int, KState*, double*,
-                               hipStream_t);
-hipError_t launch_tridiag(KState*, const double*, int, hipStream_t);
-hipError_t launch_combine(const double*, int64_t, double* const*, int, int64_t, int, KState*,
-                          double*, hipStream_t);
+hipError_t launch_start(const VecGroup&, const double*, const double* const*, int, int,
+                        hipStream_t);
+hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
+hipError_t launch_tridiag(const VecGroup&, const double*, int, hipStream_t);
+hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
+int vec_blocks(int64_t n);
 
 struct DevBuf {
     void* p = nullptr;
@@ -48,6 +49,37 @@ struct DevBuf {
     T* as() const { return static_cast<T*>(p); }
 };
 
+// Device tables that run the Krylov passes of one handle, or of a batch of handles in common
+// launches (one launch per pass for all problems), eagerly or as a captured HIP graph of the
+// kdim Lanczos iterations.
+struct Group {
+    std::vector<dmrg_ctx*> hs;
+    bool merged = false;                       // batch: own merged work lists
+    DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT2;  // merged work lists (batch only)
+    int ntiles1 = 0, ntiles2 = 0;
+    DevBuf dVP, dBmap, dProbs, dIO;            // VecProb, block map, ProbPtrs[kMaxKrylov][nprob], IO
+    VecGroup vg{};
+    int prec = -1;                             // precision the tables were built for
+    std::vector<uint64_t> gens;                // member workspace generations of the tables
+    void** io_host = nullptr;                  // pinned staging of the per-call pointer table
+    std::vector<const void*> io_last;          // content of the last upload
+    hipEvent_t io_ev = nullptr;                // completion of the last upload
+    bool use_graph = false;
+    hipStream_t cap = nullptr;                 // private capture stream
+    std::map<int, hipGraphExec_t> graphs;      // captured Lanczos iterations by kdim
+
+    void clear_graphs() {
+        for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+        graphs.clear();
+    }
+    ~Group() {
+        clear_graphs();
+        if (cap) (void)hipStreamDestroy(cap);
+        if (io_ev) (void)hipEventDestroy(io_ev);
+        if (io_host) (void)hipHostFree(io_host);
+    }
+};
+
 }  // namespace dmrg
 
 using namespace dmrg;
@@ -68,10 +100,12 @@ struct dmrg_ctx {
     DevBuf dPart;       // block partial sums
     DevBuf dState;      // KState
     int kcap = 0;       // basis slots allocated
+    uint64_t gen = 0;   // bumped whenever a workspace buffer is (re)allocated
+    Group self;         // tables of the handle's own Krylov runs
 };
 
 struct dmrg_batch_ctx {
-    std::vector<dmrg_handle> hs;
+    Group g;
 };
 
 namespace {
@@ -107,10 +141,11 @@ int ensure_workspace(dmrg_handle h, int kdim) {
     if (h->kcap >= kdim + 1 && h->dW.p) return DMRG_OK;
     const int64_t n2 = 2 * h->plan.n;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
+    ++h->gen;
     HIP_TRY(h, h->dV.alloc(sizeof(double) * (size_t)n2 * (kdim + 1)));
     h->kcap = kdim + 1;
     if (!h->dW.p) HIP_TRY(h, h->dW.alloc(sizeof(double) * (size_t)n2));
-    if (!h->dPart.p) HIP_TRY(h, h->dPart.alloc(sizeof(double) * 2 * kMaxKrylov * 1024));
+    if (!h->dPart.p) HIP_TRY(h, h->dPart.alloc(sizeof(double) * 2 * kMaxKrylov * kVecThreads));
     if (!h->dState.p) {
         HIP_TRY(h, h->dState.alloc(sizeof(KState)));
         HIP_TRY(h, hipMemsetAsync(h->dState.p, 0, sizeof(KState), h->stream));
@@ -133,24 +168,24 @@ int ensure_operators(dmrg_handle h, int prec) {
     return DMRG_OK;
 }
 
-ProbPtrs make_ptrs(dmrg_handle h, const double* x, double* y, const double* xscale,
+ProbPtrs make_ptrs(dmrg_handle h, int prec, const double* x, double* y, const double* xscale,
                    const int* skip) {
     ProbPtrs pp;
     pp.x = x;
     pp.y = y;
     pp.T = h->dT.p;
-    pp.Lops = h->dA[h->precision].p;
-    pp.Rops = h->dR[h->precision].p;
+    pp.Lops = h->dA[prec].p;
+    pp.Rops = h->dR[prec].p;
     pp.xscale = xscale;
     pp.skip = skip;
     return pp;
 }
 
-// y = H_sb x for one vector; x scaled by *xscale on load when non-null; skipped when *skip.
-int matvec_one(dmrg_handle h, const double* x, double* y, const double* xscale, const int* skip) {
+// y = H_sb x for one caller vector.
+int matvec_one(dmrg_handle h, const double* x, double* y) {
     const Plan& P = h->plan;
     const int prec = h->precision, pk = prec == DMRG_BF16X3 ? 1 : 0;
-    const ProbPtrs pp = make_ptrs(h, x, y, xscale, skip);
+    const ProbPtrs pp = make_ptrs(h, prec, x, y, nullptr, nullptr);
     HIP_TRY(h, launch_stage1(prec, h->dS1[pk].as<S1Block>(), h->dT1.as<Tile>(),
                              (int)P.tiles1.size(), nullptr, pp, h->stream));
     HIP_TRY(h, launch_stage2(prec, h->dS2[pk].as<S2Block>(), h->dSeg[pk].as<Segment>(),
@@ -158,18 +193,129 @@ int matvec_one(dmrg_handle h, const double* x, double* y, const double* xscale, 
     return DMRG_OK;
 }
 
-// One Lanczos basis of kdim vectors from the vector in slot 0 (already started).
-int lanczos_basis(dmrg_handle h, int kdim) {
-    const int64_t n = h->plan.n, vs = 2 * n;
-    double* V = h->dV.as<double>();
-    double* W = h->dW.as<double>();
-    KState* st = h->dState.as<KState>();
+// Makes the group's device tables match its members' workspaces for a run of size kdim.
+int group_prepare(Group& g, int kdim) {
+    dmrg_ctx* h0 = g.hs[0];
+    const int prec = h0->precision;
+    for (dmrg_ctx* h : g.hs)
+        if (h->precision != prec) return fail(h0, DMRG_EINVAL, "batch members use different precisions");
+    for (dmrg_ctx* h : g.hs) {
+        const int rc = ensure_workspace(h, kdim);
+        if (rc) return h == h0 ? rc : fail(h0, rc, h->last_error);
+    }
+    bool stale = g.prec != prec || g.gens.size() != g.hs.size() || !g.dVP.p;
+    for (size_t i = 0; !stale && i < g.hs.size(); ++i) stale = g.gens[i] != g.hs[i]->gen;
+    if (!stale) return DMRG_OK;
+
+    HIP_TRY(h0, hipStreamSynchronize(h0->stream));
+    g.clear_graphs();
+    const int np = (int)g.hs.size();
+    std::vector<VecProb> vp(np);
+    std::vector<int> bmap;
+    std::vector<ProbPtrs> pp((size_t)kMaxKrylov * np);
+    int b0 = 0;
+    for (int i = 0; i < np; ++i) {
+        dmrg_ctx* h = g.hs[i];
+        const int64_t n = h->plan.n;
+        double* V = h->dV.as<double>();
+        KState* st = h->dState.as<KState>();
+        const int nb = vec_blocks(n);
+        vp[i] = VecProb{V, h->dW.as<double>(), h->dPart.as<double>(), st, n, 2 * n, nb, b0};
+        bmap.insert(bmap.end(), nb, i);
+        b0 += nb;
+        for (int j = 0; j < kMaxKrylov; ++j)
+            pp[(size_t)j * np + i] = make_ptrs(h, prec, j < h->kcap ? V + (int64_t)j * 2 * n : nullptr,
+                                               h->dW.as<double>(), &st->scale[j], &st->broken);
+    }
+    HIP_TRY(h0, upload(g.dVP, vp, h0->stream));
+    if (np > 1) HIP_TRY(h0, upload(g.dBmap, bmap, h0->stream));
+    HIP_TRY(h0, upload(g.dProbs, pp, h0->stream));
+    g.vg = VecGroup{g.dVP.as<VecProb>(), np > 1 ? g.dBmap.as<int>() : nullptr, np, b0, 4};
+    g.prec = prec;
+    g.gens.resize(np);
+    for (int i = 0; i < np; ++i) g.gens[i] = g.hs[i]->gen;
+    return DMRG_OK;
+}
+
+// Both block-product launches of Lanczos iteration j for every problem of the group.
+int group_matvec(Group& g, int j, hipStream_t s) {
+    dmrg_ctx* h0 = g.hs[0];
+    const int prec = g.prec, pk = prec == DMRG_BF16X3 ? 1 : 0;
+    const ProbPtrs* probs = g.dProbs.as<ProbPtrs>() + (size_t)j * g.hs.size();
+    // a single handle runs its own work lists, a batch the merged ones
+    const DevBuf* S1 = g.merged ? g.dS1 : h0->dS1;
+    const DevBuf* S2 = g.merged ? g.dS2 : h0->dS2;
+    const DevBuf* Sg = g.merged ? g.dSeg : h0->dSeg;
+    const DevBuf& T1 = g.merged ? g.dT1 : h0->dT1;
+    const DevBuf& T2 = g.merged ? g.dT2 : h0->dT2;
+    const int n1 = g.merged ? g.ntiles1 : (int)h0->plan.tiles1.size();
+    const int n2 = g.merged ? g.ntiles2 : (int)h0->plan.tiles2.size();
+    HIP_TRY(h0, launch_stage1(prec, S1[pk].as<S1Block>(), T1.as<Tile>(), n1, probs, ProbPtrs{}, s));
+    HIP_TRY(h0, launch_stage2(prec, S2[pk].as<S2Block>(), Sg[pk].as<Segment>(), T2.as<Tile>(), n2,
+                              probs, ProbPtrs{}, s));
+    return DMRG_OK;
+}
+
+// The kdim Lanczos iterations from the started slot 0, launched one by one.
+int group_basis_eager(Group& g, int kdim, hipStream_t s) {
     for (int j = 0; j < kdim; ++j) {
-        int rc = matvec_one(h, V + (int64_t)j * vs, W, &st->scale[j], &st->broken);
+        const int rc = group_matvec(g, j, s);
         if (rc) return rc;
-        HIP_TRY(h, launch_lanczos_iter(V, vs, W, n, j, kdim, st, h->dPart.as<double>(), h->stream));
+        HIP_TRY(g.hs[0], launch_lanczos_iter(g.vg, j, kdim, s));
     }
     return DMRG_OK;
+}
+
+// The kdim Lanczos iterations: eager, or one launch of the graph captured for this kdim.
+int group_basis(Group& g, int kdim, hipStream_t s) {
+    if (!g.use_graph) return group_basis_eager(g, kdim, s);
+    dmrg_ctx* h0 = g.hs[0];
+    auto it = g.graphs.find(kdim);
+    if (it == g.graphs.end()) {
+        if (!g.cap) HIP_TRY(h0, hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
+        HIP_TRY(h0, hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal));
+        const int rc = group_basis_eager(g, kdim, g.cap);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(g.cap, &graph);
+        if (rc || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc ? rc : hip_fail(h0, e, "hipStreamEndCapture");
+        }
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return hip_fail(h0, ei, "hipGraphInstantiate");
+        it = g.graphs.emplace(kdim, ex).first;
+    }
+    HIP_TRY(h0, hipGraphLaunch(it->second, s));
+    return DMRG_OK;
+}
+
+// Uploads the per-call pointer table of a batch: xt[nprob] then yst[nprob][kMaxTimes].
+int group_io(Group& g, const std::vector<const void*>& io, hipStream_t s) {
+    dmrg_ctx* h0 = g.hs[0];
+    if (io == g.io_last) return DMRG_OK;
+    const size_t bytes = io.size() * sizeof(void*);
+    if (!g.io_host) {
+        HIP_TRY(h0, hipHostMalloc((void**)&g.io_host, bytes, hipHostMallocDefault));
+        HIP_TRY(h0, hipEventCreateWithFlags(&g.io_ev, hipEventDisableTiming));
+        HIP_TRY(h0, g.dIO.alloc(bytes));
+    }
+    HIP_TRY(h0, hipEventSynchronize(g.io_ev));   // the previous upload has left the staging
+    std::memcpy(g.io_host, io.data(), bytes);
+    HIP_TRY(h0, hipMemcpyAsync(g.dIO.p, g.io_host, bytes, hipMemcpyHostToDevice, s));
+    HIP_TRY(h0, hipEventRecord(g.io_ev, s));
+    g.io_last = io;
+    return DMRG_OK;
+}
+
+void fill_info(const KState& st, dmrg_krylov_info* info) {
+    info->k_eff = st.keff;
+    info->k_eff_min = st.keff_min > kMaxKrylov ? st.keff : st.keff_min;
+    info->beta0 = st.beta0_first;
+    info->beta_last = st.keff > 0 ? st.beta[st.keff] : 0.0;
+    info->err_est = st.err_est;
+    info->breakdown = st.any_break;
 }
 
 int read_info(dmrg_handle h, dmrg_krylov_info* info) {
@@ -177,13 +323,24 @@ int read_info(dmrg_handle h, dmrg_krylov_info* info) {
     KState st;
     HIP_TRY(h, hipMemcpyAsync(&st, h->dState.p, sizeof(KState), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    info->k_eff = st.keff;
-    info->k_eff_min = st.keff_min > kMaxKrylov ? st.keff : st.keff_min;
-    info->beta0 = st.beta0_first;
-    info->beta_last = st.keff > 0 ? st.beta[st.keff] : 0.0;
-    info->err_est = st.err_est;
-    info->breakdown = st.any_break;
+    fill_info(st, info);
     if (st.eig_fail) return fail(h, DMRG_ENONFINITE, "tridiagonal eigensolver did not converge");
+    return DMRG_OK;
+}
+
+void tst_weights(double* weights) {
+    if (!weights) return;
+    const double W = 1.0 / 8.0;
+    weights[0] = 2 * W;
+    weights[1] = 2 * W;
+    weights[2] = W;
+    weights[3] = W;
+    weights[4] = 2 * W;
+}
+
+int check_krylov_args(dmrg_handle h, double tau, int kdim) {
+    if (kdim < 1 || kdim > kMaxKrylov) return fail(h, DMRG_EINVAL, "kdim outside [1, 64]");
+    if (!std::isfinite(tau)) return fail(h, DMRG_ENONFINITE, "tau is not finite");
     return DMRG_OK;
 }
 
@@ -212,6 +369,7 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
         return DMRG_EINVAL;
     }
     h->stream = static_cast<hipStream_t>(stream);
+    h->self.hs.assign(1, h);
     const Plan& P = h->plan;
     hipError_t e = hipSuccess;
     if (e == hipSuccess) e = upload(h->dS1[0], P.pk16.s1, h->stream);
@@ -274,6 +432,14 @@ int dmrg_set_precision(dmrg_handle h, int32_t precision) {
         return fail(h, DMRG_EINVAL, "unknown precision");
     const int rc = ensure_operators(h, precision);
     if (rc) return rc;
+    if (precision != h->precision) {
+        // FP64 and the FP32-workspace arithmetics lay the stage-1 intermediate out with
+        // different element sizes: padding positions of the new layout may hold bytes of the
+        // old one, and they must be finite (they meet zero factors), so start from zeros again
+        const size_t bytes = sizeof(double) * (size_t)h->plan.T_size;
+        HIP_TRY(h, hipMemsetAsync(h->dT.p, 0, bytes, h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    }
     h->precision = precision;
     return DMRG_OK;
 }
@@ -289,7 +455,7 @@ int dmrg_matvec(dmrg_handle h, const double* x, double* y, int32_t nvec) {
     if (nvec < 0 || (nvec > 0 && (!x || !y))) return fail(h, DMRG_EINVAL, "bad vectors");
     const int64_t vs = 2 * h->plan.n;
     for (int v = 0; v < nvec; ++v) {
-        int rc = matvec_one(h, x + v * vs, y + v * vs, nullptr, nullptr);
+        int rc = matvec_one(h, x + v * vs, y + v * vs);
         if (rc) return rc;
     }
     return DMRG_OK;
@@ -299,28 +465,26 @@ int dmrg_krylov_expm(dmrg_handle h, const double* x, double* y, double tau, int3
                      int32_t nsteps, dmrg_krylov_info* info) {
     if (!h) return DMRG_EINVAL;
     if (!x || !y) return fail(h, DMRG_EINVAL, "NULL vector");
-    if (kdim < 1 || kdim > kMaxKrylov) return fail(h, DMRG_EINVAL, "kdim outside [1, 64]");
     if (nsteps < 0) return fail(h, DMRG_EINVAL, "negative nsteps");
-    if (!std::isfinite(tau)) return fail(h, DMRG_ENONFINITE, "tau is not finite");
-    int rc = ensure_workspace(h, kdim);
+    int rc = check_krylov_args(h, tau, kdim);
     if (rc) return rc;
-    const int64_t n = h->plan.n;
-    double* V = h->dV.as<double>();
-    KState* st = h->dState.as<KState>();
-    double* part = h->dPart.as<double>();
     if (nsteps == 0) {
-        HIP_TRY(h, hipMemcpyAsync(y, x, sizeof(double) * 2 * n, hipMemcpyDeviceToDevice, h->stream));
+        HIP_TRY(h, hipMemcpyAsync(y, x, sizeof(double) * 2 * h->plan.n, hipMemcpyDeviceToDevice,
+                                  h->stream));
         if (info) *info = dmrg_krylov_info{0, 0, 0.0, 0.0, 0.0, 0};
         return DMRG_OK;
     }
-    HIP_TRY(h, launch_start(x, V, n, st, part, kdim, 1, h->stream));
+    Group& g = h->self;
+    rc = group_prepare(g, kdim);
+    if (rc) return rc;
+    HIP_TRY(h, launch_start(g.vg, x, nullptr, kdim, 1, h->stream));
     for (int s = 0; s < nsteps; ++s) {
-        rc = lanczos_basis(h, kdim);
+        rc = group_basis(g, kdim, h->stream);
         if (rc) return rc;
-        HIP_TRY(h, launch_tridiag(st, &tau, 1, h->stream));
+        HIP_TRY(h, launch_tridiag(g.vg, &tau, 1, h->stream));
         const bool last = s == nsteps - 1;
-        double* out[1] = {last ? y : V};
-        HIP_TRY(h, launch_combine(V, 2 * n, out, 1, n, last ? 0 : 1, st, part, h->stream));
+        double* out[1] = {y};
+        HIP_TRY(h, launch_combine(g.vg, last ? out : nullptr, nullptr, 1, last ? 0 : 1, h->stream));
     }
     return read_info(h, info);
 }
@@ -329,30 +493,27 @@ int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim,
                      double* weights, dmrg_krylov_info* info) {
     if (!h) return DMRG_EINVAL;
     if (!phi || !targets) return fail(h, DMRG_EINVAL, "NULL vector");
-    if (kdim < 1 || kdim > kMaxKrylov) return fail(h, DMRG_EINVAL, "kdim outside [1, 64]");
-    if (!std::isfinite(tau)) return fail(h, DMRG_ENONFINITE, "tau is not finite");
-    int rc = ensure_workspace(h, kdim);
+    int rc = check_krylov_args(h, tau, kdim);
+    if (rc) return rc;
+    Group& g = h->self;
+    rc = group_prepare(g, kdim);
     if (rc) return rc;
     const int64_t n = h->plan.n;
-    double* V = h->dV.as<double>();
-    KState* st = h->dState.as<KState>();
-    double* part = h->dPart.as<double>();
-    HIP_TRY(h, launch_start(phi, V, n, st, part, kdim, 1, h->stream));
-    rc = lanczos_basis(h, kdim);
+    HIP_TRY(h, launch_start(g.vg, phi, nullptr, kdim, 1, h->stream));
+    rc = group_basis(g, kdim, h->stream);
     if (rc) return rc;
     const double times[4] = {0.0, tau / 3.0, 2.0 * tau / 3.0, tau};
-    HIP_TRY(h, launch_tridiag(st, times, 4, h->stream));
+    HIP_TRY(h, launch_tridiag(g.vg, times, 4, h->stream));
     double* out[4] = {targets, targets + 2 * n, targets + 4 * n, targets + 6 * n};
-    HIP_TRY(h, launch_combine(V, 2 * n, out, 4, n, 0, st, part, h->stream));
-    if (weights) {
-        const double W = 1.0 / 8.0;
-        weights[0] = 2 * W;
-        weights[1] = 2 * W;
-        weights[2] = W;
-        weights[3] = W;
-        weights[4] = 2 * W;
-    }
+    HIP_TRY(h, launch_combine(g.vg, out, nullptr, 4, 0, h->stream));
+    tst_weights(weights);
     return read_info(h, info);
+}
+
+int dmrg_set_graph(dmrg_handle h, int32_t enable) {
+    if (!h) return DMRG_EINVAL;
+    h->self.use_graph = enable != 0;
+    return DMRG_OK;
 }
 
 int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out) {
@@ -361,23 +522,93 @@ int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out
     if (!handles || count <= 0) return DMRG_EINVAL;
     for (int i = 0; i < count; ++i)
         if (!handles[i]) return DMRG_EINVAL;
+    for (int i = 0; i < count; ++i)
+        for (int k = 0; k < i; ++k)
+            if (handles[k] == handles[i]) return fail(handles[0], DMRG_EINVAL, "handle repeated in a batch");
     dmrg_batch_ctx* b = new (std::nothrow) dmrg_batch_ctx();
     if (!b) return DMRG_ENOMEM;
-    b->hs.assign(handles, handles + count);
+    Group& g = b->g;
+    g.hs.assign(handles, handles + count);
+    g.merged = true;
+    g.use_graph = true;
+    dmrg_ctx* h0 = g.hs[0];
+    try {
+        std::vector<const Plan*> plans;
+        for (dmrg_ctx* h : g.hs) plans.push_back(&h->plan);
+        Merged M;
+        merge_plans(plans, M);
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+            e = upload(g.dS1[k], M.s1[k], h0->stream);
+            if (e == hipSuccess) e = upload(g.dS2[k], M.s2[k], h0->stream);
+            if (e == hipSuccess) e = upload(g.dSeg[k], M.segs[k], h0->stream);
+        }
+        if (e == hipSuccess) e = upload(g.dT1, M.tiles1, h0->stream);
+        if (e == hipSuccess) e = upload(g.dT2, M.tiles2, h0->stream);
+        if (e != hipSuccess) {
+            delete b;
+            return fail(h0, e == hipErrorOutOfMemory ? DMRG_ENOMEM : DMRG_EHIP, hipGetErrorString(e));
+        }
+        g.ntiles1 = (int)M.tiles1.size();
+        g.ntiles2 = (int)M.tiles2.size();
+    } catch (const std::bad_alloc&) {
+        delete b;
+        return DMRG_ENOMEM;
+    }
     *out = b;
     return DMRG_OK;
 }
 
-void dmrg_batch_destroy(dmrg_batch b) { delete b; }
+void dmrg_batch_destroy(dmrg_batch b) {
+    if (!b) return;
+    (void)hipStreamSynchronize(b->g.hs[0]->stream);
+    delete b;
+}
+
+int dmrg_batch_set_graph(dmrg_batch b, int32_t enable) {
+    if (!b) return DMRG_EINVAL;
+    b->g.use_graph = enable != 0;
+    return DMRG_OK;
+}
 
 int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, int32_t kdim,
                            double* const* targets, double* weights, dmrg_krylov_info* infos) {
     if (!b || !phi || !targets) return DMRG_EINVAL;
-    for (size_t i = 0; i < b->hs.size(); ++i) {
-        int rc = dmrg_tst_targets(b->hs[i], phi[i], tau, kdim, targets[i], weights,
-                                  infos ? infos + i : nullptr);
-        if (rc) return rc;
+    Group& g = b->g;
+    dmrg_ctx* h0 = g.hs[0];
+    const int np = (int)g.hs.size();
+    for (int i = 0; i < np; ++i)
+        if (!phi[i] || !targets[i]) return fail(h0, DMRG_EINVAL, "NULL vector in a batch");
+    int rc = check_krylov_args(h0, tau, kdim);
+    if (rc) return rc;
+    rc = group_prepare(g, kdim);
+    if (rc) return rc;
+    hipStream_t s = h0->stream;
+    std::vector<const void*> io((size_t)np * (1 + kMaxTimes));
+    for (int i = 0; i < np; ++i) {
+        const int64_t n = g.hs[i]->plan.n;
+        io[i] = phi[i];
+        for (int x = 0; x < kMaxTimes; ++x) io[np + (size_t)i * kMaxTimes + x] = targets[i] + 2 * n * x;
     }
+    rc = group_io(g, io, s);
+    if (rc) return rc;
+    const double* const* xt = g.dIO.as<const double*>();
+    double* const* yst = g.dIO.as<double*>() + np;
+    HIP_TRY(h0, launch_start(g.vg, nullptr, xt, kdim, 1, s));
+    rc = group_basis(g, kdim, s);
+    if (rc) return rc;
+    const double times[4] = {0.0, tau / 3.0, 2.0 * tau / 3.0, tau};
+    HIP_TRY(h0, launch_tridiag(g.vg, times, 4, s));
+    HIP_TRY(h0, launch_combine(g.vg, nullptr, yst, 4, 0, s));
+    tst_weights(weights);
+    if (!infos) return DMRG_OK;
+    std::vector<KState> st(np);
+    for (int i = 0; i < np; ++i)
+        HIP_TRY(h0, hipMemcpyAsync(&st[i], g.hs[i]->dState.p, sizeof(KState), hipMemcpyDeviceToHost, s));
+    HIP_TRY(h0, hipStreamSynchronize(s));
+    for (int i = 0; i < np; ++i) fill_info(st[i], &infos[i]);
+    for (int i = 0; i < np; ++i)
+        if (st[i].eig_fail) return fail(h0, DMRG_ENONFINITE, "tridiagonal eigensolver did not converge");
     return DMRG_OK;
 }
 
@@ -385,7 +616,7 @@ int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps,
     if (!h || !x || !y || !out || reps < 1) return DMRG_EINVAL;
     const Plan& P = h->plan;
     const int prec = h->precision, pk = prec == DMRG_BF16X3 ? 1 : 0;
-    const ProbPtrs pp = make_ptrs(h, x, y, nullptr, nullptr);
+    const ProbPtrs pp = make_ptrs(h, prec, x, y, nullptr, nullptr);
     hipEvent_t ev[3];
     for (auto& e : ev) HIP_TRY(h, hipEventCreate(&e));
     double t1 = 0.0, t2 = 0.0;

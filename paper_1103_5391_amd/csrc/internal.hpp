@@ -98,6 +98,14 @@ struct VecProb {
     int32_t nb, b0;
 };
 
+// Launch description of the vector passes over a group of problems.
+struct VecGroup {
+    const VecProb* vp;    // device table [nprob]
+    const int* bmap;      // device map block -> problem [nblk], nullptr for one problem
+    int nprob, nblk;      // problems, blocks of a pass (sum of nb)
+    int combine_mult;     // blocks per pass block of the non-chained combination
+};
+
 // Device state of one Krylov run on one problem.
 struct KState {
     double alpha[kMaxKrylov];
@@ -108,7 +116,6 @@ struct KState {
     double coef[kMaxTimes][2 * kMaxKrylov];  // c(t_x) = beta0 S exp(-i D t_x) S^T e_1
     double bscale;                    // max(1, |alpha_i|, beta_i) for the breakdown test
     double err_est;
-    double norm2_out;                 // ||y||^2 of the last combination (chained steps)
     int32_t keff;
     int32_t broken;                   // 1 after breakdown (or zero input)
     int32_t kdim;
@@ -116,7 +123,6 @@ struct KState {
     int32_t keff_min;                 // over all steps of one call
     int32_t any_break;                // over all steps of one call
     double beta0_first;               // ||x|| of the first step of one call
-    uint32_t counter[4];              // arrival counters of the reduction kernels
 };
 
 }  // namespace dmrg

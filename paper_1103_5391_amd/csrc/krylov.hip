@@ -15,9 +15,12 @@
 // basis and their coefficients are exactly alpha_j and the j-1 entry of h), so it is not a
 // separate pass; in exact arithmetic the result equals update-then-two-sweeps.
 //
-// Grid-wide sums are deterministic: every block of a pass writes its partial sums and a
-// one-block finalise kernel adds them in a fixed order (the kernel boundary orders the two;
-// no device-wide fences or atomics inside the bandwidth-bound passes).
+// Every kernel runs over a table of problems (one entry for a single superblock, many for a
+// batch): block b of a pass works on problem bmap[b] (problem 0 when there is no map), as block
+// b - b0 of that problem's nb blocks; the one-block finalise kernels run one block per problem.
+// Grid-wide sums are deterministic: every block writes its partial sums and the finalise block
+// adds them in a fixed order (the kernel boundary orders the two; no device-wide fences or
+// atomics inside the bandwidth-bound passes).
 #include <array>
 #include <utility>
 
@@ -58,10 +61,24 @@ __device__ __forceinline__ double wave_sum(double v) {
     return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
-// Block-level sums of NV per-thread values; writes the block partials to
-// part[blockIdx.x * NV + v].
+// Where block blockIdx.x of a pass works: problem bmap[blockIdx.x / mult] (0 without a map),
+// block lb of the nbt = nb * mult blocks that pass gives that problem.
+struct Where {
+    VecProb p;
+    int prob, lb, nbt;
+};
+__device__ __forceinline__ Where locate(const VecProb* vp, const int* bmap, int mult) {
+    Where w;
+    w.prob = bmap ? bmap[blockIdx.x / mult] : 0;
+    w.p = vp[w.prob];
+    w.lb = (int)blockIdx.x - w.p.b0 * mult;
+    w.nbt = w.p.nb * mult;
+    return w;
+}
+
+// Block-level sums of NV per-thread values; writes the block partials to part[lb * NV + v].
 template <int NV>
-__device__ __forceinline__ void block_partials(const double (&vals)[NV], double* part) {
+__device__ __forceinline__ void block_partials(const double (&vals)[NV], double* part, int lb) {
     __shared__ double red[NV][kVecThreads / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -74,18 +91,19 @@ __device__ __forceinline__ void block_partials(const double (&vals)[NV], double*
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < kVecThreads / 64; ++w) s += red[v][w];
-        part[(int64_t)blockIdx.x * NV + v] = s;
+        part[(int64_t)lb * NV + v] = s;
     }
 }
 
-// Finalise kernels run as one block of kVecThreads: totals[v] = sum_b part[b * NV + v] (fixed
-// order: row b in thread b, then the block reduction of block_partials; nb <= kVecThreads).
+// Finalise kernels run one block of kVecThreads per problem: totals[v] = sum_b part[b * NV + v]
+// (fixed order: row b in thread b, then the block reduction of block_partials;
+// nb <= kVecThreads).
 template <int NV>
 __device__ void final_sums(const double* part, int nb, double* totals_lds) {
     __shared__ double red[NV][kVecThreads / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double acc[NV];
-    const int b = threadIdx.x < nb ? threadIdx.x : nb - 1;   // nb <= kVecThreads
+    const int b = threadIdx.x < nb ? threadIdx.x : nb - 1;
     const double keep = threadIdx.x < nb ? 1.0 : 0.0;
     const double* row = part + (int64_t)b * NV;
 #pragma unroll
@@ -125,26 +143,31 @@ __device__ void begin_step(KState* st, double norm2, int kdim) {
 }  // namespace
 
 // ---------------------------------------------------------------------------------------
-// start: slot 0 <- x, partial ||x||^2
+// start: slot 0 <- x, partial ||x||^2.  x is x1 (one problem) or xt[problem] (a batch).
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kVecThreads) void k_start(const double* __restrict__ x,
-                                                       double* __restrict__ u0, int64_t n,
-                                                       double* part) {
+__global__ __launch_bounds__(kVecThreads) void k_start(const VecProb* vp, const int* bmap,
+                                                       const double* x1,
+                                                       const double* const* xt) {
+    const Where W = locate(vp, bmap, 1);
+    const double* __restrict__ x = xt ? xt[W.prob] : x1;
+    double* __restrict__ u0 = W.p.V;
+    const int64_t n = W.p.n;
     double acc[1] = {0.0};
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t stride = (int64_t)W.nbt * blockDim.x;
+    for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double re = x[i], im = x[n + i];
         u0[i] = re;
         u0[n + i] = im;
         acc[0] += re * re + im * im;
     }
-    block_partials<1>(acc, part);
+    block_partials<1>(acc, W.p.part, W.lb);
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_fin_start(KState* st, const double* part, int nb,
-                                                           int kdim, int first) {
+__global__ __launch_bounds__(kVecThreads) void k_fin_start(const VecProb* vp, int kdim, int first) {
+    const VecProb P = vp[blockIdx.x];
+    KState* st = P.st;
     __shared__ double tot[1];
-    final_sums<1>(part, nb, tot);
+    final_sums<1>(P.part, P.nb, tot);
     if (threadIdx.x == 0) {
         begin_step(st, tot[0], kdim);
         st->err_est = 0.0;
@@ -163,17 +186,18 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_start(KState* st, const dou
 // data-dependent branch (which would force a wait on every outstanding load).
 // ---------------------------------------------------------------------------------------
 template <int NC>
-__global__ __launch_bounds__(kVecThreads) void k_project(const double* __restrict__ V,
-                                                         int64_t vstride,
-                                                         const double* __restrict__ w, int64_t n,
-                                                         int c0, const KState* st, double* part) {
-    if (st->broken) return;
+__global__ __launch_bounds__(kVecThreads) void k_project(const VecProb* vp, const int* bmap,
+                                                         int c0) {
+    const Where W = locate(vp, bmap, 1);
+    if (W.p.st->broken) return;
+    const double* __restrict__ V0 = W.p.V + (int64_t)c0 * W.p.vstride;
+    const double* __restrict__ w = W.p.w;
+    const int64_t n = W.p.n, vstride = W.p.vstride;
     double acc[2 * NC];
 #pragma unroll
     for (int c = 0; c < 2 * NC; ++c) acc[c] = 0.0;
-    const double* __restrict__ V0 = V + (int64_t)c0 * vstride;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t stride = (int64_t)W.nbt * blockDim.x;
+    for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double wr = w[i], wi = w[n + i];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -183,16 +207,18 @@ __global__ __launch_bounds__(kVecThreads) void k_project(const double* __restric
             acc[2 * c + 1] += ur * wi - ui * wr;
         }
     }
-    block_partials<2 * NC>(acc, part);
+    block_partials<2 * NC>(acc, W.p.part, W.lb);
 }
 
 // h1 (which = 1) or h2 (which = 2) entries c0..c0+NC-1 = scale_c * sums; alpha_j = Re h1_j.
 template <int NC>
-__global__ __launch_bounds__(kVecThreads) void k_fin_project(KState* st, const double* part,
-                                                             int nb, int j, int c0, int which) {
+__global__ __launch_bounds__(kVecThreads) void k_fin_project(const VecProb* vp, int j, int c0,
+                                                             int which) {
+    const VecProb P = vp[blockIdx.x];
+    KState* st = P.st;
     if (st->broken) return;
     __shared__ double tot[2 * NC];
-    final_sums<2 * NC>(part, nb, tot);
+    final_sums<2 * NC>(P.part, P.nb, tot);
     double* h = which == 1 ? st->h1 : st->h2;
     for (int c = threadIdx.x; c < NC; c += blockDim.x) {
         const double s = st->scale[c0 + c];
@@ -207,10 +233,13 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_project(KState* st, const d
 // read of each basis element comes right after the first (cache hit).
 // ---------------------------------------------------------------------------------------
 template <int NC>
-__global__ __launch_bounds__(kVecThreads) void k_reorth1(const double* V, int64_t vstride, double* w,
-                                                         int64_t n, const KState* st,
-                                                         double* part) {
+__global__ __launch_bounds__(kVecThreads) void k_reorth1(const VecProb* vp, const int* bmap) {
+    const Where W = locate(vp, bmap, 1);
+    const KState* st = W.p.st;
     if (st->broken) return;
+    const double* V = W.p.V;
+    double* w = W.p.w;
+    const int64_t n = W.p.n, vstride = W.p.vstride;
     __shared__ double hs[2 * NC];
     for (int c = threadIdx.x; c < NC; c += blockDim.x) {
         const double s = st->scale[c];
@@ -221,8 +250,8 @@ __global__ __launch_bounds__(kVecThreads) void k_reorth1(const double* V, int64_
     double acc[2 * NC];
 #pragma unroll
     for (int c = 0; c < 2 * NC; ++c) acc[c] = 0.0;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t stride = (int64_t)W.nbt * blockDim.x;
+    for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
         double wr = w[i], wi = w[n + i];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -244,15 +273,18 @@ __global__ __launch_bounds__(kVecThreads) void k_reorth1(const double* V, int64_
             acc[2 * c + 1] += ur * wi - ui * wr;
         }
     }
-    block_partials<2 * NC>(acc, part);
+    block_partials<2 * NC>(acc, W.p.part, W.lb);
 }
 
 // Unfused update (j+1 beyond the register capacity of k_reorth1): w <- w - sum_c h1_c v_c.
-__global__ __launch_bounds__(kVecThreads) void k_update(const double* __restrict__ V,
-                                                        int64_t vstride, double* __restrict__ w,
-                                                        int64_t n, int j, const KState* st) {
+__global__ __launch_bounds__(kVecThreads) void k_update(const VecProb* vp, const int* bmap, int j) {
+    const Where W = locate(vp, bmap, 1);
+    const KState* st = W.p.st;
     if (st->broken) return;
     const int nc = j + 1;
+    const double* __restrict__ V = W.p.V;
+    double* __restrict__ w = W.p.w;
+    const int64_t n = W.p.n, vstride = W.p.vstride;
     __shared__ double hs[2 * kMaxKrylov];
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         const double s = st->scale[c];
@@ -260,12 +292,13 @@ __global__ __launch_bounds__(kVecThreads) void k_update(const double* __restrict
         hs[2 * c + 1] = st->h1[2 * c + 1] * s;
     }
     __syncthreads();
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t stride = (int64_t)W.nbt * blockDim.x;
+    for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
         double wr = w[i], wi = w[n + i];
+#pragma unroll 8
         for (int c = 0; c < nc; ++c) {
             const double* u = V + (int64_t)c * vstride;
-            const double ur = u[i], ui = u[n + i];
+            const double ur = ldv(u, i), ui = ldv(u, n + i);
             const double hr = hs[2 * c], hi = hs[2 * c + 1];
             wr -= hr * ur - hi * ui;
             wi -= hr * ui + hi * ur;
@@ -276,14 +309,19 @@ __global__ __launch_bounds__(kVecThreads) void k_update(const double* __restrict
 }
 
 // ---------------------------------------------------------------------------------------
-// reorth2: u = w - sum_c h2_c v_c -> dst (slot j+1, or w itself after the last iteration),
+// reorth2: u = w - sum_c h2_c v_c -> slot j+1 (or w itself after the last iteration),
 // partial ||u||^2
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kVecThreads) void k_reorth2(const double* V, int64_t vstride,
-                                                         const double* w, double* dst, int64_t n,
-                                                         int j, const KState* st, double* part) {
+__global__ __launch_bounds__(kVecThreads) void k_reorth2(const VecProb* vp, const int* bmap, int j,
+                                                         int to_slot) {
+    const Where W = locate(vp, bmap, 1);
+    const KState* st = W.p.st;
     if (st->broken) return;
     const int nc = j + 1;
+    const double* V = W.p.V;
+    const double* w = W.p.w;
+    double* dst = to_slot ? W.p.V + (int64_t)(j + 1) * W.p.vstride : W.p.w;
+    const int64_t n = W.p.n, vstride = W.p.vstride;
     __shared__ double hs[2 * kMaxKrylov];
     for (int c = threadIdx.x; c < nc; c += blockDim.x) {
         const double s = st->scale[c];
@@ -292,12 +330,13 @@ __global__ __launch_bounds__(kVecThreads) void k_reorth2(const double* V, int64_
     }
     __syncthreads();
     double acc[1] = {0.0};
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t stride = (int64_t)W.nbt * blockDim.x;
+    for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
         double wr = w[i], wi = w[n + i];
+#pragma unroll 8
         for (int c = 0; c < nc; ++c) {
             const double* u = V + (int64_t)c * vstride;
-            const double ur = u[i], ui = u[n + i];
+            const double ur = ldv(u, i), ui = ldv(u, n + i);
             const double hr = hs[2 * c], hi = hs[2 * c + 1];
             wr -= hr * ur - hi * ui;
             wi -= hr * ui + hi * ur;
@@ -306,15 +345,16 @@ __global__ __launch_bounds__(kVecThreads) void k_reorth2(const double* V, int64_
         dst[n + i] = wi;
         acc[0] += wr * wr + wi * wi;
     }
-    block_partials<1>(acc, part);
+    block_partials<1>(acc, W.p.part, W.lb);
 }
 
 // beta_{j+1} = ||u||, breakdown test beta <= 1e-12 max(1, |alpha_i|, beta_i), scale[j+1].
-__global__ __launch_bounds__(kVecThreads) void k_fin_reorth2(KState* st, const double* part,
-                                                             int nb, int j) {
+__global__ __launch_bounds__(kVecThreads) void k_fin_reorth2(const VecProb* vp, int j) {
+    const VecProb P = vp[blockIdx.x];
+    KState* st = P.st;
     if (st->broken) return;
     __shared__ double tot[1];
-    final_sums<1>(part, nb, tot);
+    final_sums<1>(P.part, P.nb, tot);
     if (threadIdx.x == 0) {
         const double beta = sqrt(tot[0]);
         st->beta[j + 1] = beta;
@@ -335,7 +375,8 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_reorth2(KState* st, const d
 }
 
 // ---------------------------------------------------------------------------------------
-// Tridiagonal eigen-decomposition T = S D S^T by implicit QL with shifts, in one wavefront:
+// Tridiagonal eigen-decomposition T = S D S^T by implicit QL with shifts, one wavefront per
+// problem:
 // lane i holds d_i and e_i (the chase reads them with readlane, so every lane follows the same
 // scalar recursion) and row i of S in LDS; then c(t_x) = beta0 S exp(-i D t_x) S^T e_1 and the
 // error estimate beta_k |c_{k-1}(t_last)|.
@@ -355,8 +396,9 @@ __device__ __forceinline__ double pythag(double f, double g) {
 
 }  // namespace
 
-__global__ __launch_bounds__(64) void k_tridiag_expm(KState* st, double t0, double t1, double t2,
-                                                     double t3, int ntimes) {
+__global__ __launch_bounds__(64) void k_tridiag_expm(const VecProb* vp, double t0, double t1,
+                                                     double t2, double t3, int ntimes) {
+    KState* st = vp[blockIdx.x].st;
     __shared__ double Z[kMaxKrylov][kMaxKrylov + 1];
     __shared__ double ecs[kMaxTimes][kMaxKrylov], esn[kMaxTimes][kMaxKrylov];
     const int r = threadIdx.x;
@@ -466,13 +508,17 @@ __global__ __launch_bounds__(64) void k_tridiag_expm(KState* st, double t0, doub
 
 // ---------------------------------------------------------------------------------------
 // combine: y_x = sum_{c < keff} coef_x[c] scale_c u_c for x < ntimes.  With chain != 0 the
-// single output y_0 is written to slot 0 in place and its norm seeds the next step.
+// single output is slot 0 itself (in place) and its norm seeds the next step.  Outputs of a
+// batch come from the table yst[problem * kMaxTimes + x].  Without chaining a pass may give
+// each problem mult blocks per block of the other passes (no partial sums to collect).
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kVecThreads) void k_combine(const double* V, int64_t vstride,
-                                                         double* y0, double* y1, double* y2,
-                                                         double* y3, int64_t n, int ntimes,
-                                                         int chain, const KState* st,
-                                                         double* part) {
+__global__ __launch_bounds__(kVecThreads) void k_combine(const VecProb* vp, const int* bmap,
+                                                         int mult, double* y0, double* y1,
+                                                         double* y2, double* y3,
+                                                         double* const* yst, int ntimes,
+                                                         int chain) {
+    const Where W = locate(vp, bmap, mult);
+    const KState* st = W.p.st;
     __shared__ double cs[kMaxTimes][2 * kMaxKrylov];
     const int k = st->keff;
     for (int idx = threadIdx.x; idx < ntimes * k; idx += blockDim.x) {
@@ -481,14 +527,29 @@ __global__ __launch_bounds__(kVecThreads) void k_combine(const double* V, int64_
         cs[x][2 * c + 1] = st->coef[x][2 * c + 1] * st->scale[c];
     }
     __syncthreads();
-    double* ys[kMaxTimes] = {y0, y1, y2, y3};
+    double* ys[kMaxTimes];
+    if (chain) {
+        ys[0] = W.p.V;
+        ys[1] = ys[2] = ys[3] = nullptr;
+    } else if (yst) {
+#pragma unroll
+        for (int x = 0; x < kMaxTimes; ++x) ys[x] = yst[W.prob * kMaxTimes + x];
+    } else {
+        ys[0] = y0;
+        ys[1] = y1;
+        ys[2] = y2;
+        ys[3] = y3;
+    }
+    const double* V = W.p.V;
+    const int64_t n = W.p.n, vstride = W.p.vstride;
     double acc[1] = {0.0};
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t stride = (int64_t)W.nbt * blockDim.x;
+    for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
         double yr[kMaxTimes] = {0.0, 0.0, 0.0, 0.0}, yi[kMaxTimes] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
         for (int c = 0; c < k; ++c) {
             const double* u = V + (int64_t)c * vstride;
-            const double ur = u[i], ui = u[n + i];
+            const double ur = ldv(u, i), ui = ldv(u, n + i);
 #pragma unroll
             for (int x = 0; x < kMaxTimes; ++x) {
                 if (x < ntimes) {
@@ -507,19 +568,22 @@ __global__ __launch_bounds__(kVecThreads) void k_combine(const double* V, int64_
         }
         acc[0] += yr[0] * yr[0] + yi[0] * yi[0];
     }
-    if (chain) block_partials<1>(acc, part);
+    if (chain) block_partials<1>(acc, W.p.part, W.lb);
 }
 
-__global__ __launch_bounds__(kVecThreads) void k_fin_chain(KState* st, const double* part, int nb) {
+__global__ __launch_bounds__(kVecThreads) void k_fin_chain(const VecProb* vp) {
+    const VecProb P = vp[blockIdx.x];
     __shared__ double tot[1];
-    final_sums<1>(part, nb, tot);
-    if (threadIdx.x == 0) begin_step(st, tot[0], st->kdim);
+    final_sums<1>(P.part, P.nb, tot);
+    if (threadIdx.x == 0) begin_step(P.st, tot[0], P.st->kdim);
 }
 
 // ---------------------------------------------------------------------------------------
-// launchers
+// launchers.  vp: device table of nprob problems; bmap: block -> problem map of the nblk
+// blocks of a pass (nullptr for a single problem).
 // ---------------------------------------------------------------------------------------
-// Blocks of a vector pass: at most one row of partial sums per thread of the finalise block.
+// Blocks of a vector pass for one problem: at most one row of partial sums per thread of the
+// finalise block.
 int vec_blocks(int64_t n) {
     int64_t nb = (n + kVecThreads - 1) / kVecThreads;
     if (nb < 1) nb = 1;
@@ -527,11 +591,10 @@ int vec_blocks(int64_t n) {
     return (int)nb;
 }
 
-hipError_t launch_start(const double* x, double* u0, int64_t n, KState* st, double* part,
-                        int kdim, int first, hipStream_t s) {
-    const int nb = vec_blocks(n);
-    hipLaunchKernelGGL(k_start, dim3(nb), dim3(kVecThreads), 0, s, x, u0, n, part);
-    hipLaunchKernelGGL(k_fin_start, dim3(1), dim3(kVecThreads), 0, s, st, part, nb, kdim, first);
+hipError_t launch_start(const VecGroup& g, const double* x1, const double* const* xt, int kdim,
+                        int first, hipStream_t s) {
+    hipLaunchKernelGGL(k_start, dim3(g.nblk), dim3(kVecThreads), 0, s, g.vp, g.bmap, x1, xt);
+    hipLaunchKernelGGL(k_fin_start, dim3(g.nprob), dim3(kVecThreads), 0, s, g.vp, kdim, first);
     return hipGetLastError();
 }
 
@@ -540,9 +603,9 @@ namespace {
 constexpr int kProjMax = 32;     // vectors per fused projection launch
 constexpr int kReorthMax = 24;   // basis size up to which reorth1 is fused
 
-typedef void (*ProjFn)(const double*, int64_t, const double*, int64_t, int, const KState*, double*);
-typedef void (*FinFn)(KState*, const double*, int, int, int, int);
-typedef void (*ReoFn)(const double*, int64_t, double*, int64_t, const KState*, double*);
+typedef void (*ProjFn)(const VecProb*, const int*, int);
+typedef void (*FinFn)(const VecProb*, int, int, int);
+typedef void (*ReoFn)(const VecProb*, const int*);
 
 template <int... I>
 constexpr auto proj_table(std::integer_sequence<int, I...>) {
@@ -557,67 +620,63 @@ constexpr auto reo_table(std::integer_sequence<int, I...>) {
     return std::array<ReoFn, sizeof...(I)>{&k_reorth1<I + 1>...};
 }
 
-void fin_project(KState* st, const double* part, int nb, int j, int c0, int nc, int which,
-                 hipStream_t s) {
-    static const auto tab = fin_table(std::make_integer_sequence<int, kProjMax>{});
-    hipLaunchKernelGGL(tab[nc - 1], dim3(1), dim3(kVecThreads), 0, s, st, part, nb, j, c0, which);
-}
+const auto kProjTab = proj_table(std::make_integer_sequence<int, kProjMax>{});
+const auto kFinTab = fin_table(std::make_integer_sequence<int, kProjMax>{});
+const auto kReoTab = reo_table(std::make_integer_sequence<int, kReorthMax>{});
 
 // Projection sums of w against slots [0, nc) into h1 or h2, in register-sized pieces.
-void project(const double* V, int64_t vstride, const double* w, int64_t n, int j, int nc,
-             int which, KState* st, double* part, hipStream_t s) {
-    static const auto tab = proj_table(std::make_integer_sequence<int, kProjMax>{});
-    const int nb = vec_blocks(n);
+void project(const VecGroup& g, int j, int nc, int which, hipStream_t s) {
     for (int c0 = 0; c0 < nc; c0 += kProjMax) {
         const int m = min(kProjMax, nc - c0);
-        hipLaunchKernelGGL(tab[m - 1], dim3(nb), dim3(kVecThreads), 0, s, V, vstride, w, n, c0, st,
-                           part);
-        fin_project(st, part, nb, j, c0, m, which, s);
+        hipLaunchKernelGGL(kProjTab[m - 1], dim3(g.nblk), dim3(kVecThreads), 0, s, g.vp, g.bmap,
+                           c0);
+        hipLaunchKernelGGL(kFinTab[m - 1], dim3(g.nprob), dim3(kVecThreads), 0, s, g.vp, j, c0,
+                           which);
     }
 }
 
 }  // namespace
 
-// Runs the reduction passes of Lanczos iteration j.
-hipError_t launch_lanczos_iter(double* V, int64_t vstride, double* w, int64_t n, int j, int kdim,
-                               KState* st, double* part, hipStream_t s) {
-    static const auto reo = reo_table(std::make_integer_sequence<int, kReorthMax>{});
-    const int nb = vec_blocks(n);
-    const dim3 grid(nb), blk(kVecThreads);
+// Runs the reduction passes of Lanczos iteration j on every problem of the group.
+hipError_t launch_lanczos_iter(const VecGroup& g, int j, int kdim, hipStream_t s) {
+    const dim3 grid(g.nblk), blk(kVecThreads), one(g.nprob);
     const int nc = j + 1;
     // first sweep: h1 = V^H w (alpha_j = Re h1_j)
-    project(V, vstride, w, n, j, nc, 1, st, part, s);
+    project(g, j, nc, 1, s);
     // second sweep: w -= V h1, h2 = V^H w
     if (nc <= kReorthMax) {
-        hipLaunchKernelGGL(reo[nc - 1], grid, blk, 0, s, V, vstride, w, n, st, part);
-        fin_project(st, part, nb, j, 0, nc, 2, s);
+        hipLaunchKernelGGL(kReoTab[nc - 1], grid, blk, 0, s, g.vp, g.bmap);
+        hipLaunchKernelGGL(kFinTab[nc - 1], one, blk, 0, s, g.vp, j, 0, 2);
     } else {
-        hipLaunchKernelGGL(k_update, grid, blk, 0, s, V, vstride, w, n, j, st);
-        project(V, vstride, w, n, j, nc, 2, st, part, s);
+        hipLaunchKernelGGL(k_update, grid, blk, 0, s, g.vp, g.bmap, j);
+        project(g, j, nc, 2, s);
     }
     // third pass: u = w - V h2 -> slot j+1, beta_{j+1}
-    double* dst = (j + 1 < kdim) ? V + (int64_t)(j + 1) * vstride : w;
-    hipLaunchKernelGGL(k_reorth2, grid, blk, 0, s, V, vstride, w, dst, n, j, st, part);
-    hipLaunchKernelGGL(k_fin_reorth2, dim3(1), blk, 0, s, st, part, nb, j);
+    hipLaunchKernelGGL(k_reorth2, grid, blk, 0, s, g.vp, g.bmap, j, (j + 1 < kdim) ? 1 : 0);
+    hipLaunchKernelGGL(k_fin_reorth2, one, blk, 0, s, g.vp, j);
     return hipGetLastError();
 }
 
-hipError_t launch_tridiag(KState* st, const double* times, int ntimes, hipStream_t s) {
+hipError_t launch_tridiag(const VecGroup& g, const double* times, int ntimes, hipStream_t s) {
     double t[kMaxTimes] = {0, 0, 0, 0};
     for (int i = 0; i < ntimes; ++i) t[i] = times[i];
-    hipLaunchKernelGGL(k_tridiag_expm, dim3(1), dim3(64), 0, s, st, t[0], t[1], t[2], t[3],
+    hipLaunchKernelGGL(k_tridiag_expm, dim3(g.nprob), dim3(64), 0, s, g.vp, t[0], t[1], t[2], t[3],
                        ntimes);
     return hipGetLastError();
 }
 
-hipError_t launch_combine(const double* V, int64_t vstride, double* const* ys, int ntimes,
-                          int64_t n, int chain, KState* st, double* part, hipStream_t s) {
+// ys: ntimes output pointers of a single problem, or nullptr with yst, the batch table
+// [nprob][kMaxTimes].  chain: write slot 0 in place and start the next step from it.
+hipError_t launch_combine(const VecGroup& g, double* const* ys, double* const* yst, int ntimes,
+                          int chain, hipStream_t s) {
     double* y[kMaxTimes] = {nullptr, nullptr, nullptr, nullptr};
-    for (int i = 0; i < ntimes; ++i) y[i] = ys[i];
-    const int nb = vec_blocks(n);
-    hipLaunchKernelGGL(k_combine, dim3(nb), dim3(kVecThreads), 0, s, V, vstride, y[0], y[1], y[2],
-                       y[3], n, ntimes, chain, st, part);
-    if (chain) hipLaunchKernelGGL(k_fin_chain, dim3(1), dim3(kVecThreads), 0, s, st, part, nb);
+    if (ys)
+        for (int i = 0; i < ntimes; ++i) y[i] = ys[i];
+    const int mult = chain ? 1 : g.combine_mult;
+    hipLaunchKernelGGL(k_combine, dim3(g.nblk * mult), dim3(kVecThreads), 0, s, g.vp,
+                       g.bmap, mult, y[0], y[1], y[2], y[3], yst, ntimes,
+                       chain);
+    if (chain) hipLaunchKernelGGL(k_fin_chain, dim3(g.nprob), dim3(kVecThreads), 0, s, g.vp);
     return hipGetLastError();
 }
 

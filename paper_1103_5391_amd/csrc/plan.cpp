@@ -335,7 +335,42 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
     }
     P.tiles1 = xcd_order(P.tiles1, w1, kWaves);
     P.tiles2 = xcd_order(P.tiles2, w2, 1);
+    P.w1 = std::move(w1);
+    P.w2 = std::move(w2);
     return "";
+}
+
+void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
+    out = Merged{};
+    std::vector<Tile> t1, t2;
+    std::vector<double> w1, w2;
+    int boff = 0;
+    for (size_t i = 0; i < plans.size(); ++i) {
+        const Plan& P = *plans[i];
+        const Packing* pks[2] = {&P.pk16, &P.pk32};
+        for (int k = 0; k < 2; ++k) {
+            const int soff = (int)out.segs[k].size();
+            for (S1Block b : pks[k]->s1) {
+                b.prob = (int)i;
+                out.s1[k].push_back(b);
+            }
+            for (S2Block b : pks[k]->s2) {
+                b.prob = (int)i;
+                b.seg0 += soff;
+                out.s2[k].push_back(b);
+            }
+            out.segs[k].insert(out.segs[k].end(), pks[k]->segs.begin(), pks[k]->segs.end());
+        }
+        for (Tile t : P.tiles1)
+            if (t.blk >= 0) t1.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
+        for (Tile t : P.tiles2)
+            if (t.blk >= 0) t2.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
+        w1.insert(w1.end(), P.w1.begin(), P.w1.end());
+        w2.insert(w2.end(), P.w2.begin(), P.w2.end());
+        boff += (int)P.blocks.size();
+    }
+    out.tiles1 = xcd_order(t1, w1, kWaves);
+    out.tiles2 = xcd_order(t2, w2, 1);
 }
 
 namespace {

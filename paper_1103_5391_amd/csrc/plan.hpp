@@ -85,6 +85,7 @@ struct Plan {
     std::vector<View> Tview;                   // stage-1 workspace view per block
     int64_t T_size = 0;                        // workspace elements
     std::vector<Tile> tiles1, tiles2;
+    std::vector<double> w1, w2;                // per-block work estimates of the two stages
     Packing pk16, pk32;
     double flops = 0.0;                        // algorithmic flops per complex matvec
     double flops1 = 0.0, flops2 = 0.0;         // of which stage 1 / stage 2
@@ -92,6 +93,16 @@ struct Plan {
 
 // Returns an empty string on success, else the reason the problem is invalid.
 std::string build_plan(const dmrg_problem* pb, Plan& plan);
+
+// Work lists of several plans merged into one launch per stage: problem i is plans[i] (its
+// descriptors carry prob = i, its segments and blocks are renumbered), tiles in XCD order.
+struct Merged {
+    std::vector<S1Block> s1[2];               // per chunk depth (0: 16, 1: 32)
+    std::vector<S2Block> s2[2];
+    std::vector<Segment> segs[2];
+    std::vector<Tile> tiles1, tiles2;
+};
+void merge_plans(const std::vector<const Plan*>& plans, Merged& out);
 
 // Packed operator buffers for one arithmetic (raw bytes): kind 0 FP64 and 1 FP32 use the
 // 16-deep packing, kind 2 (bf16 hi/lo pairs) the 32-deep one.

@@ -22,8 +22,9 @@ STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP",
 # exported symbols (kept in sync with include/dmrgtst.h; checked by the CPU tests)
 SYMBOLS = [
     "dmrg_create", "dmrg_destroy", "dmrg_psi_layout", "dmrg_flops", "dmrg_set_precision",
-    "dmrg_set_stream", "dmrg_matvec", "dmrg_krylov_expm", "dmrg_tst_targets",
-    "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_tst_targets", "dmrg_profile_matvec",
+    "dmrg_set_stream", "dmrg_matvec", "dmrg_krylov_expm", "dmrg_tst_targets", "dmrg_set_graph",
+    "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_set_graph", "dmrg_batch_tst_targets",
+    "dmrg_profile_matvec",
     "dmrg_strerror", "dmrg_last_error",
 ]
 
@@ -83,7 +84,9 @@ def load(path: str = LIB_PATH):
     lib.dmrg_matvec.argtypes = [vp, vp, vp, i32]
     lib.dmrg_krylov_expm.argtypes = [vp, vp, vp, dbl, i32, i32, P(dmrg_krylov_info)]
     lib.dmrg_tst_targets.argtypes = [vp, vp, dbl, i32, vp, P(dbl), P(dmrg_krylov_info)]
+    lib.dmrg_set_graph.argtypes = [vp, i32]
     lib.dmrg_batch_create.argtypes = [P(vp), i32, P(vp)]
+    lib.dmrg_batch_set_graph.argtypes = [vp, i32]
     lib.dmrg_batch_destroy.argtypes = [vp]
     lib.dmrg_batch_destroy.restype = None
     lib.dmrg_batch_tst_targets.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl),
@@ -276,6 +279,11 @@ class Handle:
 
     tst_targets = dmrg_tst_targets
 
+    def dmrg_set_graph(self, enable: bool):
+        _check(self.lib.dmrg_set_graph(self.h, int(bool(enable))), self.h)
+
+    set_graph = dmrg_set_graph
+
     def dmrg_profile_matvec(self, x, y, reps: int = 10):
         """Average ms of the two block-product launches and their algorithmic flops."""
         n2 = 2 * self.n
@@ -297,8 +305,13 @@ class Batch:
         b = C.c_void_p()
         rc = self.lib.dmrg_batch_create(arr, len(self.handles), C.byref(b))
         if rc != 0:
-            raise DmrgError(rc, "dmrg_batch_create")
+            _check(rc, self.handles[0].h)
         self.b = b
+
+    def dmrg_batch_set_graph(self, enable: bool):
+        _check(self.lib.dmrg_batch_set_graph(self.b, int(bool(enable))), self.handles[0].h)
+
+    set_graph = dmrg_batch_set_graph
 
     def dmrg_batch_tst_targets(self, phis, tau: float, kdim: int, targets, info: bool = True):
         cnt = len(self.handles)
@@ -309,7 +322,7 @@ class Batch:
         rc = self.lib.dmrg_batch_tst_targets(self.b, ph, float(tau), int(kdim), tg,
                                              _dptr(w, C.c_double), infos if info else None)
         if rc != 0:
-            raise DmrgError(rc, "dmrg_batch_tst_targets")
+            _check(rc, self.handles[0].h)
         return w, ([i.as_dict() for i in infos] if info else None)
 
     batch_tst_targets = dmrg_batch_tst_targets
@@ -318,6 +331,8 @@ class Batch:
         if self.b:
             self.lib.dmrg_batch_destroy(self.b)
             self.b = None
+
+    destroy = dmrg_batch_destroy
 
     def __del__(self):
         try:

@@ -342,3 +342,152 @@ def test_krylov_mixed_precision_norm_and_error(env, prec):
     assert abs(np.linalg.norm(y) - 1.0) <= 1e-8
     assert err <= 10 * MIXED_TOL[prec]
     h.destroy()
+
+
+# ---------------------------------------------------------------------------------------------
+# batching and graphs: one launch per pass for many superblocks, captured Lanczos iterations.
+# Both run the same kernels on the same per-problem data as the single-handle eager path, so
+# the results must agree bit for bit; the small batch is also checked against the oracle.
+# ---------------------------------------------------------------------------------------------
+def _batch_setup(torch, L, pbs, seed):
+    hs = [L.dmrg_create(pb) for pb in pbs]
+    phis = [I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + seed + i)) for i, h in enumerate(hs)]
+    pds = [_dev(torch, p) for p in phis]
+    tds = [torch.full((8 * h.n,), float("nan"), dtype=torch.float64, device="cuda") for h in hs]
+    return hs, phis, pds, tds
+
+
+def test_batch_tst_parity_small(env):
+    """Eight chain superblocks (m 100..300, L 16..48): batched targets against the oracle
+    (<= 1e-10) and bit for bit against each handle's own call."""
+    torch, L = env
+    say("batch small")
+    pbs = I.batch_workloads(8, seed_offset=300, m_lo=100, m_hi=300)
+    hs, phis, pds, tds = _batch_setup(torch, L, pbs, 500)
+    tau, kdim = 0.05, 15
+    b = L.Batch(hs)
+    w, infos = b.batch_tst_targets(pds, tau, kdim, tds)
+    for i, (pb, h) in enumerate(zip(pbs, hs)):
+        n = h.n
+        t = _host(tds[i])
+        ys, wref, _ = K.tst_targets(lambda v: M.matvec_sector(pb, v), phis[i], tau, kdim)
+        assert np.array_equal(w, wref)
+        errs = [rel(t[2 * n * x:2 * n * (x + 1)], ys[x]) for x in range(4)]
+        say("  problem", i, "n", n, "max rel err", max(errs), infos[i])
+        assert max(errs) <= KR_TOL
+        one = torch.empty_like(tds[i])
+        _, inf1 = h.tst_targets(pds[i], tau, kdim, one)
+        assert torch.equal(one, tds[i])
+        assert inf1 == infos[i]
+    b.destroy()
+    for h in hs:
+        h.destroy()
+
+
+def test_batch64_matches_per_problem(env):
+    """The 64-superblock workload (chains, m 100..1000): batched with graphs, batched without,
+    and the per-problem loop agree bit for bit; a second call with other inputs and a call with
+    another kdim (new graph) agree too."""
+    torch, L = env
+    say("batch 64")
+    pbs = I.batch_workloads(64)
+    hs, phis, pds, tds = _batch_setup(torch, L, pbs, 600)
+    b = L.Batch(hs)
+    for call, (kdim, tau) in enumerate([(15, 0.05), (15, 0.05), (10, 0.1)]):
+        say("  call", call, kdim, tau)
+        if call == 1:
+            for p in pds:
+                p.mul_(-0.5)
+        b.set_graph(True)
+        _, inf_g = b.batch_tst_targets(pds, tau, kdim, tds)
+        ref = [torch.empty_like(t) for t in tds]
+        for h, p, r in zip(hs, pds, ref):
+            h.tst_targets(p, tau, kdim, r, info=False)
+        torch.cuda.synchronize()
+        for i in range(len(hs)):
+            assert torch.equal(tds[i], ref[i]), i
+        b.set_graph(False)
+        for t in tds:
+            t.fill_(float("nan"))
+        _, inf_e = b.batch_tst_targets(pds, tau, kdim, tds)
+        assert inf_e == inf_g
+        for i in range(len(hs)):
+            assert torch.equal(tds[i], ref[i]), i
+        norms = [float(torch.linalg.vector_norm(t[:2 * h.n])) for t, h in zip(tds, hs)]
+        assert all(abs(x - (1.0 if call == 0 else 0.5)) < 1e-12 for x in norms)
+    b.destroy()
+    for h in hs:
+        h.destroy()
+
+
+def test_graph_replays_match_eager(env):
+    """A single handle with captured Lanczos iterations: several replays, with eager work and
+    synchronisations between them, each equal to the eager result; chained Krylov steps and a
+    new kdim (second graph) too."""
+    torch, L = env
+    say("graph replays")
+    pb = problem("chain32_m400")
+    h = L.dmrg_create(pb)
+    n = h.n
+    xs = [_dev(torch, I.random_psi(n, np.random.default_rng(I.SEED_BASE + 700 + i))) for i in range(3)]
+    eager = []
+    for x in xs:
+        t = torch.empty(8 * n, dtype=torch.float64, device="cuda")
+        h.tst_targets(x, 0.05, 15, t, info=False)
+        eager.append(t)
+    ye = torch.empty_like(xs[0])
+    inf_e = h.krylov_expm(xs[0], ye, 0.1, 12, 3)
+    h.set_graph(True)
+    tmp = torch.empty_like(xs[0])
+    for rep in range(2):
+        for i, x in enumerate(xs):
+            t = torch.full((8 * n,), float("nan"), dtype=torch.float64, device="cuda")
+            h.tst_targets(x, 0.05, 15, t, info=False)
+            h.matvec(x, tmp)                      # eager work between replays
+            torch.cuda.synchronize()
+            say("  replay", rep, i)
+            assert torch.equal(t, eager[i])
+    yg = torch.full_like(xs[0], float("nan"))
+    inf_g = h.krylov_expm(xs[0], yg, 0.1, 12, 3)
+    assert torch.equal(yg, ye) and inf_g == inf_e
+    h.set_graph(False)
+    h.destroy()
+
+
+def test_batch_rejects_mixed_precisions(env):
+    torch, L = env
+    say("batch precision check")
+    hs = [L.dmrg_create(problem("chain12_m30")), L.dmrg_create(problem("chain14_m25_off"))]
+    b = L.Batch(hs)
+    hs[1].set_precision(L.DMRG_FP32)
+    pds = [torch.zeros(2 * h.n, dtype=torch.float64, device="cuda") for h in hs]
+    tds = [torch.zeros(8 * h.n, dtype=torch.float64, device="cuda") for h in hs]
+    with pytest.raises(L.DmrgError) as e:
+        b.batch_tst_targets(pds, 0.1, 8, tds)
+    assert "precision" in str(e.value)
+    hs[1].set_precision(L.DMRG_FP64)
+    b.batch_tst_targets(pds, 0.1, 8, tds)          # zero inputs: zero targets, no error
+    assert all(torch.count_nonzero(t).item() == 0 for t in tds)
+    b.destroy()
+    for h in hs:
+        h.destroy()
+
+
+def test_precision_switch_after_fp64_runs(env):
+    """Switching arithmetic on a handle that already ran FP64 products (and back) keeps every
+    result finite and within its tolerance: the workspace is re-laid out for the element size."""
+    torch, L = env
+    say("precision switch")
+    pb = problem("chain32_m400")
+    h = L.dmrg_create(pb)
+    x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 41))
+    xd = _dev(torch, x)
+    yd = torch.empty_like(xd)
+    yref = M.matvec_sector(pb, x)
+    for prec in (L.DMRG_FP64, L.DMRG_FP32, L.DMRG_BF16X3, L.DMRG_FP64, L.DMRG_BF16X3, L.DMRG_FP32):
+        h.set_precision(prec)
+        h.matvec(xd, yd)
+        err = rel(_host(yd), yref)
+        say("  prec", prec, err)
+        assert err <= (MV_TOL if prec == L.DMRG_FP64 else MIXED_TOL[prec])
+    h.destroy()
