@@ -180,7 +180,7 @@ def main():
     ref_mv = torch.empty_like(pd)
     h.matvec(pd, ref_mv)
     mixed = {}
-    for prec, label in ((L.DMRG_FP32, "fp32"), (L.DMRG_BF16X3, "bf16x3")):
+    for prec, label in ((L.DMRG_FP32, "fp32"), (L.DMRG_BF16X3, "bf16x3"), (L.DMRG_BF16X6, "bf16x6")):
         h.set_precision(prec)
         for _ in range(args.warmup):
             h.tst_targets(pd, tau, kdim, td, info=False)

@@ -62,11 +62,16 @@ enum dmrg_status {
 };
 
 /* Arithmetic of the block products (the Lanczos recurrence, the reorthogonalisation, the
- * tridiagonal eigen-decomposition and the combination always stay FP64). */
+ * small tridiagonal exponential and the combination always stay FP64).  In the split bf16
+ * forms every operand value is a sum of bf16 pieces a = a0 + a1 (+ a2), each piece the bf16
+ * rounding of what the previous ones leave of the FP32 value. */
 enum dmrg_precision {
     DMRG_FP64 = 0,        /* FP64 MFMA                                                    */
     DMRG_FP32 = 1,        /* FP32 operands and FP32 MFMA accumulation, result promoted     */
-    DMRG_BF16X3 = 2       /* split bf16 hi/lo products a0b0 + a0b1 + a1b0, FP32 accumulate */
+    DMRG_BF16X3 = 2,      /* two pieces, products a0b0 + a0b1 + a1b0, FP32 accumulation:
+                             relative error about 2^-16                                   */
+    DMRG_BF16X6 = 3       /* three pieces, the six products a_i b_j with i + j <= 2, FP32
+                             accumulation: relative error about 2^-24, like FP32          */
 };
 
 /* A block operator of one half that changes (N_up, N_dn) by dq.  blocks: for every source

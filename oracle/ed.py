@@ -1,7 +1,8 @@
 """Exact diagonalisation of the Hubbard model in a bit-string Fock basis (oracle, test only).
 
 H = -sum_<ij> sum_s t_ij (c+_is c_js + h.c.) + U sum_i n_i,up n_i,dn   (model of Sec. III.B;
-the hopping sign reading is listed in the design doc).
+the paper writes the hopping with a plus sign and symmetric t_ij: on the bipartite chain and
+ladder the two signs are related by c_j -> (-1)^j c_j, so densities do not depend on it).
 
 Fermion mode of (site i, spin s) is bit 2*i + s (s = 0 up, 1 down); basis states are
 normal-ordered products of creation operators in increasing mode order.  Written without

@@ -3,8 +3,10 @@
 Sec. II.A: start the Lanczos recursion from phi itself, so H ~ V^T T V with the first Lanczos
 vector proportional to phi; diagonalise the small tridiagonal T = S D S^T and use
     phi(t) ~ V^T exp(-i T t) V phi = beta0 V^T S exp(-i D t) S^T e_1
-(the library evolves with exp(-i tau H); the paper's exp(+iHt) is tau -> -tau; the factors
-T and T^dagger printed inside Eq. (lanczosevolution) are not used).
+(the library evolves with exp(-i tau H); the paper's exp(+iHt) is tau -> -tau.  Eq.
+(lanczosevolution) as printed also carries factors T^dagger and T around the exponential, which
+would not give the evolution of phi; the form above, the one the text states before it, is
+used).
 Sec. II.C: larger times by repeating the step from the evolved vector, Eq. (lanczosevolution2).
 Sec. II.B/II.C: time-step targeting keeps n_v = 4 equally spaced times 0, tau/3, 2tau/3, tau
 from one Krylov basis, with weights 2W for the ground state and the first and last time

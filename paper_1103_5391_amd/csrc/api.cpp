@@ -92,7 +92,7 @@ struct dmrg_ctx {
     // device copies of the plan: stage descriptors per chunk depth (0: 16, 1: 32), packed
     // operators per arithmetic (built on first use), tile lists
     DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT2;
-    DevBuf dA[3], dR[3];
+    DevBuf dA[4], dR[4];
     // workspace
     DevBuf dT;          // stage-1 intermediate
     DevBuf dV;          // Krylov basis slots
@@ -145,7 +145,7 @@ int ensure_workspace(dmrg_handle h, int kdim) {
     HIP_TRY(h, h->dV.alloc(sizeof(double) * (size_t)n2 * (kdim + 1)));
     h->kcap = kdim + 1;
     if (!h->dW.p) HIP_TRY(h, h->dW.alloc(sizeof(double) * (size_t)n2));
-    if (!h->dPart.p) HIP_TRY(h, h->dPart.alloc(sizeof(double) * 2 * kMaxKrylov * kVecThreads));
+    if (!h->dPart.p) HIP_TRY(h, h->dPart.alloc(sizeof(double) * 2 * kMaxKrylov * kVecMaxBlocks));
     if (!h->dState.p) {
         HIP_TRY(h, h->dState.alloc(sizeof(KState)));
         HIP_TRY(h, hipMemsetAsync(h->dState.p, 0, sizeof(KState), h->stream));
@@ -184,7 +184,7 @@ ProbPtrs make_ptrs(dmrg_handle h, int prec, const double* x, double* y, const do
 // y = H_sb x for one caller vector.
 int matvec_one(dmrg_handle h, const double* x, double* y) {
     const Plan& P = h->plan;
-    const int prec = h->precision, pk = prec == DMRG_BF16X3 ? 1 : 0;
+    const int prec = h->precision, pk = prec >= DMRG_BF16X3 ? 1 : 0;
     const ProbPtrs pp = make_ptrs(h, prec, x, y, nullptr, nullptr);
     HIP_TRY(h, launch_stage1(prec, h->dS1[pk].as<S1Block>(), h->dT1.as<Tile>(),
                              (int)P.tiles1.size(), nullptr, pp, h->stream));
@@ -240,7 +240,7 @@ int group_prepare(Group& g, int kdim) {
 // Both block-product launches of Lanczos iteration j for every problem of the group.
 int group_matvec(Group& g, int j, hipStream_t s) {
     dmrg_ctx* h0 = g.hs[0];
-    const int prec = g.prec, pk = prec == DMRG_BF16X3 ? 1 : 0;
+    const int prec = g.prec, pk = prec >= DMRG_BF16X3 ? 1 : 0;
     const ProbPtrs* probs = g.dProbs.as<ProbPtrs>() + (size_t)j * g.hs.size();
     // a single handle runs its own work lists, a batch the merged ones
     const DevBuf* S1 = g.merged ? g.dS1 : h0->dS1;
@@ -324,7 +324,7 @@ int read_info(dmrg_handle h, dmrg_krylov_info* info) {
     HIP_TRY(h, hipMemcpyAsync(&st, h->dState.p, sizeof(KState), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     fill_info(st, info);
-    if (st.eig_fail) return fail(h, DMRG_ENONFINITE, "tridiagonal eigensolver did not converge");
+    if (st.exp_fail) return fail(h, DMRG_ENONFINITE, "Krylov exponential coefficients are not finite");
     return DMRG_OK;
 }
 
@@ -428,7 +428,7 @@ int dmrg_flops(dmrg_handle h, double* flops) {
 
 int dmrg_set_precision(dmrg_handle h, int32_t precision) {
     if (!h) return DMRG_EINVAL;
-    if (precision != DMRG_FP64 && precision != DMRG_FP32 && precision != DMRG_BF16X3)
+    if (precision < DMRG_FP64 || precision > DMRG_BF16X6)
         return fail(h, DMRG_EINVAL, "unknown precision");
     const int rc = ensure_operators(h, precision);
     if (rc) return rc;
@@ -608,14 +608,14 @@ int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, i
     HIP_TRY(h0, hipStreamSynchronize(s));
     for (int i = 0; i < np; ++i) fill_info(st[i], &infos[i]);
     for (int i = 0; i < np; ++i)
-        if (st[i].eig_fail) return fail(h0, DMRG_ENONFINITE, "tridiagonal eigensolver did not converge");
+        if (st[i].exp_fail) return fail(h0, DMRG_ENONFINITE, "Krylov exponential coefficients are not finite");
     return DMRG_OK;
 }
 
 int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps, double* out) {
     if (!h || !x || !y || !out || reps < 1) return DMRG_EINVAL;
     const Plan& P = h->plan;
-    const int prec = h->precision, pk = prec == DMRG_BF16X3 ? 1 : 0;
+    const int prec = h->precision, pk = prec >= DMRG_BF16X3 ? 1 : 0;
     const ProbPtrs pp = make_ptrs(h, prec, x, y, nullptr, nullptr);
     hipEvent_t ev[3];
     for (auto& e : ev) HIP_TRY(h, hipEventCreate(&e));

@@ -1,8 +1,11 @@
-// Grouped block products of H_sb.psi on gfx950 MFMA, in three arithmetics:
+// Grouped block products of H_sb.psi on gfx950 MFMA, in four arithmetics:
 //   FP64    v_mfma_f64_16x16x4f64, FP64 workspace
 //   FP32    v_mfma_f32_16x16x4f32, FP32 operands and workspace
-//   BF16x3  v_mfma_f32_16x16x32_bf16 on split operands a = a_hi + a_lo (bf16 each):
-//           a_hi b_hi + a_hi b_lo + a_lo b_hi accumulated in FP32, FP32 workspace
+//   BF16x3  v_mfma_f32_16x16x32_bf16 on split operands a = a0 + a1 (bf16 pieces, each the
+//           rounding of what the previous leave): a0 b0 + a0 b1 + a1 b0 accumulated in FP32
+//           (relative error about 2^-16), FP32 workspace
+//   BF16x6  three pieces a = a0 + a1 + a2, the six products of total order <= 2
+//           (about 2^-24, FP32-like), FP32 workspace
 // The result of the second stage is always written in FP64.
 //
 // The Hamiltonian connections (Sec. IV) are applied as psi' = A psi B^T over (N_up, N_dn)
@@ -43,7 +46,7 @@ __device__ __forceinline__ V ldgv(const void* p) {
 // arithmetic traits
 // ---------------------------------------------------------------------------------------
 struct PF64 {
-    static constexpr int CK = 16, KPL = 4;
+    static constexpr int CK = 16, KPL = 4, PER = 1;   // PER: packed pieces per value
     using op_t = double;          // packed operator element
     using ws_t = double;          // workspace element
     using acc_t = d4;
@@ -59,7 +62,7 @@ struct PF64 {
 };
 
 struct PF32 {
-    static constexpr int CK = 16, KPL = 4;
+    static constexpr int CK = 16, KPL = 4, PER = 1;
     using op_t = float;
     using ws_t = float;
     using acc_t = f4;
@@ -76,44 +79,54 @@ struct PF32 {
     __device__ static int row(int g, int v) { return 4 * g + v; }
 };
 
-struct PBF3 {
-    static constexpr int CK = 32, KPL = 8;
-    using op_t = __bf16;          // packed as 8 hi then 8 lo per lane and chunk
+// Split bf16 operands: NP pieces per value; the products of total order below NP (pieces
+// i + j < NP) are accumulated, smallest orders last.
+template <int NP>
+struct PSplit {
+    static constexpr int CK = 32, KPL = 8, PER = NP;
+    using op_t = __bf16;          // packed as KPL values of piece 0, then piece 1, ... per lane
     using ws_t = float;
     using acc_t = f4;
     struct frag_t {
-        bf8 hi, lo;
+        bf8 p[NP];
     };
     __device__ static frag_t from(const double (&v)[KPL]) {
         frag_t f;
 #pragma unroll
         for (int t = 0; t < KPL; ++t) {
-            const float x = (float)v[t];
-            const __bf16 h = (__bf16)x;
-            f.hi[t] = h;
-            f.lo[t] = (__bf16)(x - (float)h);
+            float rest = (float)v[t];
+#pragma unroll
+            for (int q = 0; q < NP; ++q) {
+                const __bf16 h = (__bf16)rest;
+                f.p[q][t] = h;
+                rest -= (float)h;
+            }
         }
         return f;
     }
     __device__ static frag_t load_op(const op_t* p) {
         frag_t f;
-        f.hi = ldgv<bf8>(p);
-        f.lo = ldgv<bf8>(p + 8);
+#pragma unroll
+        for (int q = 0; q < NP; ++q) f.p[q] = ldgv<bf8>(p + q * KPL);
         return f;
     }
     __device__ static acc_t mma(const frag_t& a, const frag_t& b, acc_t c) {
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.hi, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.hi, b.lo, c, 0, 0, 0);
-        c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.lo, b.hi, c, 0, 0, 0);
+#pragma unroll
+        for (int o = 0; o < NP; ++o)
+#pragma unroll
+            for (int i = 0; i <= o; ++i)
+                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[i], b.p[o - i], c, 0, 0, 0);
         return c;
     }
     __device__ static int row(int g, int v) { return 4 * g + v; }
 };
+using PBF3 = PSplit<2>;
+using PBF6 = PSplit<3>;
 
-// Elements of one packed panel chunk per lane (bf16 packs hi and lo) and per chunk.
+// Elements of one packed panel chunk per lane (all pieces of a split value) and per chunk.
 template <class P>
 constexpr int lane_elems() {
-    return sizeof(typename P::op_t) == 2 ? 2 * P::KPL : P::KPL;
+    return P::KPL * P::PER;
 }
 template <class P>
 constexpr int chunk_elems() {
@@ -175,7 +188,7 @@ __global__ __launch_bounds__(256, 2) void stage1(const S1Block* __restrict__ blk
         const int pl = m >= B.X.split;
         arow[i] = B.X.off + pl * B.X.poff + (m - pl * B.X.split);
     }
-    const op_t* pb = static_cast<const op_t*>(P_.Rops) + B.Roff +
+    const op_t* pb = static_cast<const op_t*>(P_.Rops) + B.Roff * P::PER +
                      (((int64_t)(tl.n0 / kPanel) * nch) * 4 + g) * (kPanel * lane_elems<P>()) +
                      r * lane_elems<P>();
     const int64_t panel = (int64_t)nch * chunk_elems<P>();
@@ -289,7 +302,7 @@ __global__ __launch_bounds__(256, 3) void stage2(const S2Block* __restrict__ blk
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int pnl = tl.m0 / kPanel + i;
-        pa[i] = static_cast<const op_t*>(P_.Lops) + B.Aoff +
+        pa[i] = static_cast<const op_t*>(P_.Lops) + B.Aoff * P::PER +
                 (((int64_t)pnl * B.nch) * 4 + g) * (kPanel * lane_elems<P>()) + r * lane_elems<P>();
         const int n = min(tl.n0 + 16 * i + r, B.N - 1);
         pl[i] = n >= split;
@@ -399,13 +412,14 @@ hipError_t launch2(const S2Block* blks, const Segment* segs, const Tile* tiles, 
 
 }  // namespace
 
-// prec: 0 FP64, 1 FP32, 2 BF16x3 (the operator buffers and workspace must match)
+// prec: 0 FP64, 1 FP32, 2 BF16x3, 3 BF16x6 (the operator buffers and workspace must match)
 hipError_t launch_stage1(int prec, const S1Block* blks, const Tile* tiles, int ntiles,
                          const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
     switch (prec) {
         case 0: return launch1<PF64>(blks, tiles, ntiles, probs, single, st);
         case 1: return launch1<PF32>(blks, tiles, ntiles, probs, single, st);
-        default: return launch1<PBF3>(blks, tiles, ntiles, probs, single, st);
+        case 2: return launch1<PBF3>(blks, tiles, ntiles, probs, single, st);
+        default: return launch1<PBF6>(blks, tiles, ntiles, probs, single, st);
     }
 }
 
@@ -414,7 +428,8 @@ hipError_t launch_stage2(int prec, const S2Block* blks, const Segment* segs, con
     switch (prec) {
         case 0: return launch2<PF64>(blks, segs, tiles, ntiles, probs, single, st);
         case 1: return launch2<PF32>(blks, segs, tiles, ntiles, probs, single, st);
-        default: return launch2<PBF3>(blks, segs, tiles, ntiles, probs, single, st);
+        case 2: return launch2<PBF3>(blks, segs, tiles, ntiles, probs, single, st);
+        default: return launch2<PBF6>(blks, segs, tiles, ntiles, probs, single, st);
     }
 }
 

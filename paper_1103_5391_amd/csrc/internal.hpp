@@ -13,6 +13,7 @@ constexpr int kChunk = 16;          // K depth of one FP64/FP32 chunk (4 MFMA K-
 constexpr int kChunkMax = 32;       // K depth of one BF16 chunk (one 16x16x32 MFMA)
 constexpr int kWaves = 4;           // waves per work group (split-K among them)
 constexpr int kVecThreads = 256;    // threads per block of the vector kernels
+constexpr int kVecMaxBlocks = 1024; // blocks per problem of a vector pass (rows of partial sums)
 constexpr int kMaxTimes = 4;        // time points evaluated from one Krylov basis
 constexpr int kXcd = 8;             // MI355X: 8 XCDs of 32 CUs, each with its own L2; work
                                     // group i of a launch runs on XCD i mod 8
@@ -113,13 +114,13 @@ struct KState {
     double scale[kMaxKrylov + 1];     // 1 / beta[j]: slot j of V holds beta[j] v_j
     double h1[2 * kMaxKrylov];        // first projection coefficients (re, im interleaved)
     double h2[2 * kMaxKrylov];        // second projection coefficients
-    double coef[kMaxTimes][2 * kMaxKrylov];  // c(t_x) = beta0 S exp(-i D t_x) S^T e_1
+    double coef[kMaxTimes][2 * kMaxKrylov];  // c(t_x) = beta0 exp(-i T t_x) e_1
     double bscale;                    // max(1, |alpha_i|, beta_i) for the breakdown test
     double err_est;
     int32_t keff;
     int32_t broken;                   // 1 after breakdown (or zero input)
     int32_t kdim;
-    int32_t eig_fail;                 // tridiagonal QL did not converge
+    int32_t exp_fail;                 // small exponential gave non-finite coefficients
     int32_t keff_min;                 // over all steps of one call
     int32_t any_break;                // over all steps of one call
     double beta0_first;               // ||x|| of the first step of one call

@@ -96,18 +96,24 @@ __device__ __forceinline__ void block_partials(const double (&vals)[NV], double*
 }
 
 // Finalise kernels run one block of kVecThreads per problem: totals[v] = sum_b part[b * NV + v]
-// (fixed order: row b in thread b, then the block reduction of block_partials;
-// nb <= kVecThreads).
+// in a fixed order (thread t adds rows t, t + kVecThreads, ... in turn, then the block
+// reduction of block_partials; nb <= kVecMaxBlocks).
 template <int NV>
 __device__ void final_sums(const double* part, int nb, double* totals_lds) {
     __shared__ double red[NV][kVecThreads / 64];
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     double acc[NV];
-    const int b = threadIdx.x < nb ? threadIdx.x : nb - 1;
-    const double keep = threadIdx.x < nb ? 1.0 : 0.0;
-    const double* row = part + (int64_t)b * NV;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) acc[v] = row[v] * keep;
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll
+    for (int q = 0; q < kVecMaxBlocks / kVecThreads; ++q) {
+        const int b0 = q * kVecThreads + threadIdx.x;
+        const int b = b0 < nb ? b0 : nb - 1;
+        const double keep = b0 < nb ? 1.0 : 0.0;
+        const double* row = part + (int64_t)b * NV;
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += row[v] * keep;
+    }
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         const double t = wave_sum(acc[v]);
@@ -171,7 +177,7 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_start(const VecProb* vp, in
     if (threadIdx.x == 0) {
         begin_step(st, tot[0], kdim);
         st->err_est = 0.0;
-        st->eig_fail = 0;
+        st->exp_fail = 0;
         if (first) {
             st->keff_min = kMaxKrylov + 1;
             st->any_break = 0;
@@ -375,23 +381,26 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_reorth2(const VecProb* vp, 
 }
 
 // ---------------------------------------------------------------------------------------
-// Tridiagonal eigen-decomposition T = S D S^T by implicit QL with shifts, one wavefront per
-// problem:
-// lane i holds d_i and e_i (the chase reads them with readlane, so every lane follows the same
-// scalar recursion) and row i of S in LDS; then c(t_x) = beta0 S exp(-i D t_x) S^T e_1 and the
-// error estimate beta_k |c_{k-1}(t_last)|.
+// Small exponential: c(t_x) = beta0 exp(-i T t_x) e_1 for the k x k Lanczos matrix T
+// (diagonal alpha, off-diagonal beta_1..beta_{k-1}), one wavefront per problem, lane r holding
+// component r.  This is the quantity Sec. II.A obtains from T = S D S^T; on the device it is
+// evaluated without the eigen-decomposition (a serial QL chase keeps one wavefront busy for
+// ~1e5 cycles): T is shifted by the centre sigma of its Gershgorin interval (radius rho bounds
+// ||T - sigma||_2), the vector is advanced from one target time to the next in s substeps of
+// length h with rho |h| <= 2, each by the Taylor series of exp(-i h (T - sigma)) to order 30
+// (remainder below 2^31 / 31! e^2 ~ 2e-24 relative; the largest term is at most 2, so no
+// cancellation), and the phase exp(-i sigma t_x) is applied to the output.  Every term costs one
+// tridiagonal product: two neighbour exchanges and three multiply-adds per lane.
+// Also the error estimate beta_k |c_{k-1}(t_last)|.
 // ---------------------------------------------------------------------------------------
 namespace {
 
-__device__ __forceinline__ double lane_get(double v, int lane) {
-    const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-    return __hiloint2double(hi, lo);
-}
+constexpr int kTaylorOrder = 30;
+constexpr double kTaylorRadius = 2.0;
 
-__device__ __forceinline__ double pythag(double f, double g) {
-    const double t = fma(f, f, g * g);
-    return (t > 1e-290 && t < 1e290) ? sqrt(t) : hypot(f, g);
+__device__ __forceinline__ double wave_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
 }
 
 }  // namespace
@@ -399,11 +408,8 @@ __device__ __forceinline__ double pythag(double f, double g) {
 __global__ __launch_bounds__(64) void k_tridiag_expm(const VecProb* vp, double t0, double t1,
                                                      double t2, double t3, int ntimes) {
     KState* st = vp[blockIdx.x].st;
-    __shared__ double Z[kMaxKrylov][kMaxKrylov + 1];
-    __shared__ double ecs[kMaxTimes][kMaxKrylov], esn[kMaxTimes][kMaxKrylov];
     const int r = threadIdx.x;
     const int k = st->keff;
-    const double times[kMaxTimes] = {t0, t1, t2, t3};
     if (k <= 0) {
         for (int x = 0; x < ntimes; ++x) {
             st->coef[x][2 * r] = 0.0;
@@ -416,91 +422,56 @@ __global__ __launch_bounds__(64) void k_tridiag_expm(const VecProb* vp, double t
         }
         return;
     }
-    double d = (r < k) ? st->alpha[r] : 0.0;
-    double e = (r + 1 < k) ? st->beta[r + 1] : 0.0;
-    if (r < k)
-        for (int c = 0; c < k; ++c) Z[r][c] = (c == r) ? 1.0 : 0.0;
-    const double eps = 2.220446049250313e-16;
-    int fail = 0;
-    for (int l = 0; l < k && !fail; ++l) {
-        int iter = 0;
-        while (true) {
-            // m = first index >= l with a negligible off-diagonal (or k-1)
-            const double dn = __shfl_down(d, 1, 64);
-            const bool small = (r >= l) && (r < k - 1) && (fabs(e) <= eps * (fabs(d) + fabs(dn)));
-            const uint64_t mask = (uint64_t)__ballot(small || r == k - 1) >> l;
-            const int m = l + __ffsll((long long)mask) - 1;
-            if (m == l) break;
-            if (++iter > 60) {
-                fail = 1;
-                break;
-            }
-            const double dl = lane_get(d, l), el = lane_get(e, l);
-            double g = (lane_get(d, l + 1) - dl) / (2.0 * el);
-            double rr = pythag(g, 1.0);
-            g = lane_get(d, m) - dl + el / (g + copysign(rr, g));
-            double s = 1.0, c = 1.0, p = 0.0;
-            bool deflated = false;
-            double carry = (r < k) ? Z[r][m] : 0.0;   // current column i+1 of this lane's row
-            int i = m - 1;
-            for (; i >= l; --i) {
-                const double ei = lane_get(e, i);
-                const double f = s * ei;
-                const double b = c * ei;
-                rr = pythag(f, g);
-                e = (r == i + 1) ? rr : e;
-                if (rr == 0.0) {          // exact deflation inside the sweep
-                    const double di1 = lane_get(d, i + 1);
-                    d = (r == i + 1) ? di1 - p : d;
-                    e = (r == m) ? 0.0 : e;
-                    deflated = true;
-                    break;
-                }
-                const double inv = 1.0 / rr;
-                s = f * inv;
-                c = g * inv;
-                g = lane_get(d, i + 1) - p;
-                rr = (lane_get(d, i) - g) * s + 2.0 * c * b;
-                p = s * rr;
-                d = (r == i + 1) ? g + p : d;
-                g = c * rr - b;
-                if (r < k) {              // rotate columns i, i+1 of S in this lane's row
-                    const double zi = Z[r][i];
-                    Z[r][i + 1] = s * zi + c * carry;
-                    carry = c * zi - s * carry;
-                }
-            }
-            if (r < k) Z[r][i + 1] = carry;   // column where the sweep stopped
-            if (deflated) continue;
-            const double dl2 = lane_get(d, l);
-            d = (r == l) ? dl2 - p : d;
-            e = (r == l) ? g : e;
-            e = (r == m) ? 0.0 : e;
-        }
-    }
-    // lane q evaluates exp(-i d_q t_x) for its own eigenvalue
-    if (r < k)
-        for (int x = 0; x < ntimes; ++x) sincos(-d * times[x], &esn[x][r], &ecs[x][r]);
-    __syncthreads();
-    const double beta0 = st->beta[0];
+    const bool in = r < k;
+    const double a = in ? st->alpha[r] : 0.0;
+    const double bl = (in && r >= 1) ? st->beta[r] : 0.0;     // couples r-1 and r
+    const double bu = (r + 1 < k) ? st->beta[r + 1] : 0.0;    // couples r and r+1
+    const double reach = fabs(bl) + fabs(bu);
+    const double hi = wave_max(in ? a + reach : -INFINITY);
+    const double lo = -wave_max(in ? reach - a : -INFINITY);
+    const double sigma = 0.5 * (hi + lo), rho = 0.5 * (hi - lo);
+    const double d = in ? a - sigma : 0.0;
+    const double times[kMaxTimes] = {t0, t1, t2, t3};
+    double vr = (r == 0) ? st->beta[0] : 0.0, vi = 0.0;
+    double tprev = 0.0, lastr = 0.0, lasti = 0.0;
+    int bad = 0;
     for (int x = 0; x < ntimes; ++x) {
-        double cr = 0.0, ci = 0.0;
-        if (r < k) {
-            for (int q = 0; q < k; ++q) {
-                const double w = Z[r][q] * Z[0][q];
-                cr += w * ecs[x][q];
-                ci += w * esn[x][q];
+        const double dt = times[x] - tprev;
+        const double need = rho * fabs(dt) / kTaylorRadius;
+        const int64_t nsub = dt == 0.0 ? 0 : (need <= 1.0 ? 1 : (int64_t)ceil(need));
+        const double h = nsub ? dt / (double)nsub : 0.0;
+        for (int64_t sub = 0; sub < nsub; ++sub) {
+            // sum_m (-i h (T - sigma))^m v / m!
+            double sr = vr, si = vi, tr = vr, ti = vi;
+            for (int m = 1; m <= kTaylorOrder; ++m) {
+                const double trm = __shfl_up(tr, 1, 64), tim = __shfl_up(ti, 1, 64);
+                const double trp = __shfl_down(tr, 1, 64), tip = __shfl_down(ti, 1, 64);
+                const double ur = d * tr + bl * trm + bu * trp;
+                const double ui = d * ti + bl * tim + bu * tip;
+                const double f = h / (double)m;
+                tr = f * ui;        // -i f (ur + i ui)
+                ti = -f * ur;
+                sr += tr;
+                si += ti;
             }
+            vr = sr;
+            vi = si;
         }
-        st->coef[x][2 * r] = beta0 * cr;
-        st->coef[x][2 * r + 1] = beta0 * ci;
+        tprev = times[x];
+        double sn, cs;
+        sincos(sigma * times[x], &sn, &cs);     // exp(-i sigma t) = cs - i sn
+        const double cr = vr * cs + vi * sn, ci = vi * cs - vr * sn;
+        if (!isfinite(cr) || !isfinite(ci)) bad = 1;
+        st->coef[x][2 * r] = in ? cr : 0.0;
+        st->coef[x][2 * r + 1] = in ? ci : 0.0;
+        lastr = cr;
+        lasti = ci;
     }
-    __syncthreads();
+    const int fail = __any(bad);
+    const double cr = lane_read(lastr, k - 1), ci = lane_read(lasti, k - 1);
     if (r == 0) {
-        const int last = ntimes - 1;
-        const double cr = st->coef[last][2 * (k - 1)], ci = st->coef[last][2 * (k - 1) + 1];
         st->err_est = st->broken ? 0.0 : st->beta[k] * sqrt(cr * cr + ci * ci);
-        st->eig_fail = fail;
+        st->exp_fail = fail;
         st->keff_min = min(st->keff_min, k);
         st->any_break = st->any_break | st->broken;
     }
@@ -582,12 +553,13 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_chain(const VecProb* vp) {
 // launchers.  vp: device table of nprob problems; bmap: block -> problem map of the nblk
 // blocks of a pass (nullptr for a single problem).
 // ---------------------------------------------------------------------------------------
-// Blocks of a vector pass for one problem: at most one row of partial sums per thread of the
-// finalise block.
+// Blocks of a vector pass for one problem: about one element per thread (enough waves in flight
+// to cover the memory latency of these streaming passes), at most kVecMaxBlocks rows of partial
+// sums.
 int vec_blocks(int64_t n) {
     int64_t nb = (n + kVecThreads - 1) / kVecThreads;
     if (nb < 1) nb = 1;
-    if (nb > kVecThreads) nb = kVecThreads;
+    if (nb > kVecMaxBlocks) nb = kVecMaxBlocks;
     return (int)nb;
 }
 

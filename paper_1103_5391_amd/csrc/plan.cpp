@@ -110,8 +110,8 @@ int round_up(int v, int m) { return (v + m - 1) / m * m; }
 
 // Element offset of (i, k) inside a packed factor with chunk depth ck: i = row (stage 2) or
 // column (stage 1), k = K index from the start of the packed K range, nch = chunks per panel,
-// per = elements per K index (2 for bf16 hi/lo pairs).  Layout [panel][chunk][g][r][t]
-// (hi values t then lo values KPL + t for bf16), KPL = ck / 4.
+// per = elements per K index (the bf16 pieces of a split value).  Layout
+// [panel][chunk][g][r][piece][t], KPL = ck / 4.
 int64_t packed_index(int i, int k, int nch, int ck, int per) {
     const int kpl = ck / 4;
     const int pnl = i / kPanel, r = i % kPanel;
@@ -274,7 +274,7 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
     // descriptors for both chunk depths
     for (Packing* pk : {&P.pk16, &P.pk32}) {
         pk->ck = (pk == &P.pk16) ? 16 : 32;
-        const int ck = pk->ck, per = (ck == 16) ? 1 : 2;
+        const int ck = pk->ck;
         int64_t roff = 0, aoff = 0;
         for (int bi = 0; bi < nb; ++bi) {
             const auto& B = P.blocks[bi];
@@ -288,7 +288,7 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
             s.X = View{B.off, P.n, B.d, B.d};
             s.Roff = roff;
             s.T = P.Tview[bi];
-            roff += (int64_t)round_up(s.N, kTile1N) * s.nch * ck * per;
+            roff += (int64_t)round_up(s.N, kTile1N) * s.nch * ck;
             pk->s1.push_back(s);
         }
         for (int bi = 0; bi < nb; ++bi) {
@@ -315,7 +315,7 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
             }
             s.nseg = (int)pk->segs.size() - s.seg0;
             s.nch = nch;
-            aoff += (int64_t)round_up(B.d, kTile) * nch * ck * per;
+            aoff += (int64_t)round_up(B.d, kTile) * nch * ck;
             pk->s2.push_back(s);
         }
         pk->R_elems = roff;
@@ -390,23 +390,27 @@ float bf16_to_float(uint16_t h) {
     return f;
 }
 
-// Writes value v at packed position (i, k) in the arithmetic `kind`.
+// Writes value v at packed position (i, k) in the arithmetic `kind` (offsets of the
+// descriptors count one element per K index; a split value occupies `per` elements).
 struct Writer {
     int kind, ck, per;
     uint8_t* base;
     void put(int64_t blk_off, int i, int k, int nch, double v) const {
-        const int64_t o = blk_off + packed_index(i, k, nch, ck, per);
-        if (kind == 0) {
+        const int64_t o = blk_off * per + packed_index(i, k, nch, ck, per);
+        if (kind == DMRG_FP64) {
             reinterpret_cast<double*>(base)[o] = v;
-        } else if (kind == 1) {
+        } else if (kind == DMRG_FP32) {
             reinterpret_cast<float*>(base)[o] = (float)v;
         } else {
-            const float x = (float)v;
-            const uint16_t hi = bf16_rne(x);
-            const uint16_t lo = bf16_rne(x - bf16_to_float(hi));
+            // x = piece_0 + piece_1 (+ piece_2) + residual, each piece the bf16 rounding of
+            // what the previous ones leave
+            float rest = (float)v;
             uint16_t* b = reinterpret_cast<uint16_t*>(base);
-            b[o] = hi;
-            b[o + ck / 4] = lo;
+            for (int q = 0; q < per; ++q) {
+                const uint16_t h = bf16_rne(rest);
+                b[o + q * (ck / 4)] = h;
+                rest -= bf16_to_float(h);
+            }
         }
     }
 };
@@ -414,11 +418,12 @@ struct Writer {
 }  // namespace
 
 void pack_operators(const Plan& P, int kind, std::vector<uint8_t>& A, std::vector<uint8_t>& R) {
-    const Packing& pk = (kind == 2) ? P.pk32 : P.pk16;
-    const size_t esz = (kind == 0) ? 8 : (kind == 1 ? 4 : 2);
-    A.assign((size_t)pk.A_elems * esz, 0);
-    R.assign((size_t)pk.R_elems * esz, 0);
-    const int per = (kind == 2) ? 2 : 1;
+    const bool split = kind == DMRG_BF16X3 || kind == DMRG_BF16X6;
+    const Packing& pk = split ? P.pk32 : P.pk16;
+    const size_t esz = (kind == DMRG_FP64) ? 8 : (kind == DMRG_FP32 ? 4 : 2);
+    const int per = kind == DMRG_BF16X3 ? 2 : (kind == DMRG_BF16X6 ? 3 : 1);
+    A.assign((size_t)pk.A_elems * per * esz, 0);
+    R.assign((size_t)pk.R_elems * per * esz, 0);
     const Writer wa{kind, pk.ck, per, A.data()}, wr{kind, pk.ck, per, R.data()};
     const int nb = (int)P.blocks.size();
     for (int bi = 0; bi < nb; ++bi) {

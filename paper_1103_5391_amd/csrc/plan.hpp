@@ -62,14 +62,16 @@ struct Edge {
     int col;             // first column of its right factor inside R_src (stage-1 output)
 };
 
-// Descriptors of the two stages for one K-chunk depth (16 for FP64 and FP32, 32 for BF16x3):
-// the chunk structure decides the packed operator layout and sizes.
+// Descriptors of the two stages for one K-chunk depth (16 for FP64 and FP32, 32 for the split
+// bf16 arithmetics): the chunk structure decides the packed operator layout and sizes.  Offsets
+// and sizes count one element per K index; an arithmetic that stores a value as `per` pieces
+// scales them by per.
 struct Packing {
     int ck = 0;
     std::vector<S1Block> s1;
     std::vector<S2Block> s2;
     std::vector<Segment> segs;
-    int64_t A_elems = 0, R_elems = 0;          // packed operator elements
+    int64_t A_elems = 0, R_elems = 0;          // packed operator values
 };
 
 struct Plan {
@@ -104,8 +106,9 @@ struct Merged {
 };
 void merge_plans(const std::vector<const Plan*>& plans, Merged& out);
 
-// Packed operator buffers for one arithmetic (raw bytes): kind 0 FP64 and 1 FP32 use the
-// 16-deep packing, kind 2 (bf16 hi/lo pairs) the 32-deep one.
+// Packed operator buffers for one arithmetic (raw bytes), kind = a dmrg_precision value: FP64
+// and FP32 use the 16-deep packing, the split bf16 arithmetics (2 or 3 pieces per value) the
+// 32-deep one.
 void pack_operators(const Plan& plan, int kind, std::vector<uint8_t>& A, std::vector<uint8_t>& R);
 
 }  // namespace dmrg

@@ -377,7 +377,7 @@ def _largest_remainder(w: np.ndarray, m: int, cap: np.ndarray) -> np.ndarray:
 
 def synthetic_block(l: int, m: int, sites, edge_sites, rng, width: float = 8.0,
                     spread: float = 32.0) -> Block:
-    """Truncated block of l sites with about m states (survey recipe, stated in the design doc):
+    """Truncated block of l sites with about m states, synthetic:
     sector weights exp(-|n - l/2|^2 / width), largest-remainder rounding capped by the true
     sector size; per-sector H = Q diag(lambda) Q^T with lambda ~ U[-spread, spread] and Haar Q;
     c+ blocks between adjacent sectors ~ N(0, 1/m)."""

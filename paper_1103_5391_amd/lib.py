@@ -15,7 +15,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdmrgtst.so")
 
-DMRG_FP64, DMRG_FP32, DMRG_BF16X3 = 0, 1, 2
+DMRG_FP64, DMRG_FP32, DMRG_BF16X3, DMRG_BF16X6 = 0, 1, 2, 3
 STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP",
           -4: "DMRG_ENONFINITE", -5: "DMRG_ESTATE"}
 

@@ -288,16 +288,19 @@ def test_chain8_against_dense_exponential(env):
 
 
 # ---------------------------------------------------------------------------------------------
-# mixed precision: FP32 and BF16x3 block products, FP64 Lanczos / reorthogonalisation / expm
+# mixed precision: FP32 and split-bf16 block products, FP64 Lanczos / reorthogonalisation / expm
 # ---------------------------------------------------------------------------------------------
-# FP32: products rounded at 2^-24 and accumulated in FP32 over K <= ~2500 terms: the north-star
-# 1e-6 relative bound.  BF16x3: a = hi + lo with bf16 parts leaves a 2^-16-relative residual per
-# operand (the dropped lo*lo term is 2^-32): per-element errors of a few 1e-5 averaging down to
-# a few 1e-6 over a vector; the test bound 3e-5 is that model, the measured value is printed.
-MIXED_TOL = {1: 1e-6, 2: 3e-5}
+# FP32: products rounded at 2^-24 and accumulated in FP32 over K <= ~2500 terms: the 1e-6
+# relative bound of the mixed path.  BF16x3: a = a0 + a1 with bf16 pieces leaves a residual of
+# about 2^-16 of each operand, and the dropped a1*b1 term is of the same order: per-element
+# errors of a few 1e-5 averaging down to a few 1e-6 over a vector; the bound 3e-5 is that model.
+# BF16x6: three pieces, the dropped terms of order 3 and the residual are about 2^-24: FP32-like,
+# the 1e-6 bound.  Measured values are printed.
+MIXED_TOL = {1: 1e-6, 2: 3e-5, 3: 1e-6}
+MIXED = pytest.mark.parametrize("prec", [1, 2, 3], ids=["fp32", "bf16x3", "bf16x6"])
 
 
-@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16x3"])
+@MIXED
 @pytest.mark.parametrize("name", ["chain8_exact", "chain14_m25_off", "chain32_m400",
                                   "ladder16_m1000", "ladder32_m2000"])
 def test_matvec_mixed_precision(env, name, prec):
@@ -322,7 +325,7 @@ def test_matvec_mixed_precision(env, name, prec):
     h.destroy()
 
 
-@pytest.mark.parametrize("prec", [1, 2], ids=["fp32", "bf16x3"])
+@MIXED
 def test_krylov_mixed_precision_norm_and_error(env, prec):
     """Mixed block products inside an FP64 Lanczos: the norm is kept to 1e-8 (the basis and the
     combination are FP64) and the result stays within the matvec error scale of the oracle."""
@@ -340,7 +343,7 @@ def test_krylov_mixed_precision_norm_and_error(env, prec):
     err = rel(y, yref)
     say("  rel err", err, "norm drift", abs(np.linalg.norm(y) - 1.0))
     assert abs(np.linalg.norm(y) - 1.0) <= 1e-8
-    assert err <= 10 * MIXED_TOL[prec]
+    assert err <= MIXED_TOL[prec]
     h.destroy()
 
 
@@ -484,7 +487,7 @@ def test_precision_switch_after_fp64_runs(env):
     xd = _dev(torch, x)
     yd = torch.empty_like(xd)
     yref = M.matvec_sector(pb, x)
-    for prec in (L.DMRG_FP64, L.DMRG_FP32, L.DMRG_BF16X3, L.DMRG_FP64, L.DMRG_BF16X3, L.DMRG_FP32):
+    for prec in (L.DMRG_FP64, L.DMRG_FP32, L.DMRG_BF16X3, L.DMRG_FP64, L.DMRG_BF16X6, L.DMRG_FP32):
         h.set_precision(prec)
         h.matvec(xd, yd)
         err = rel(_host(yd), yref)
