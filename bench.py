@@ -27,6 +27,32 @@ import time
 PEAK_FP64_TFLOPS = 78.6          # MI355X dense FP64 MFMA
 PEAK_HBM_GBS = 8000.0
 
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
+# bench on this workload, scaled by the readings of a plain 512 MiB copy (summary and commands
+# in profiles/).  Valid only for the kernel source they were taken on: reported as null once
+# the source differs.
+MEASURED_TRAFFIC = {
+    "kernel": "stage2<PF64>",
+    "workload": "ladder16_m1000",
+    "source": "paper_1103_5391_amd/csrc/gemm.hip",
+    "source_sha256": "1fdde390ad199ec8e973e1f7b026249e11b4797f4815eca14ea55e9d544bb6e6",
+    "bytes": 82.10e6 + 5.06e6,
+    "profile": "profiles/stage2_fp64_ladder16_m1000_kernel_stats.txt",
+}
+
+
+def measured_traffic(workload: str):
+    import hashlib
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), MEASURED_TRAFFIC["source"])
+    try:
+        with open(src, "rb") as f:
+            sha = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if sha != MEASURED_TRAFFIC["source_sha256"] or workload != MEASURED_TRAFFIC["workload"]:
+        return None
+    return MEASURED_TRAFFIC["bytes"]
+
 
 def _cpu_threads() -> int:
     try:
@@ -117,6 +143,10 @@ def main():
     ap.add_argument("--workload", default="ladder16_m1000")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true", help="FP64 only (no mixed-arithmetic runs)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="copy a buffer of MIB MiB once before the run: a plain copy kernel of "
+                         "known traffic that hardware-counter runs use as the byte scale")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -136,6 +166,13 @@ def main():
     pb = I.make_workload(args.workload)
     torch.cuda.init()
     stream = torch.cuda.current_stream()
+    if args.copy_calibration > 0:
+        nel = args.copy_calibration * (1 << 20) // 8
+        src = torch.ones(nel, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     h = L.dmrg_create(pb, stream)
     F = h.flops()
     n = h.n
@@ -180,7 +217,9 @@ def main():
     ref_mv = torch.empty_like(pd)
     h.matvec(pd, ref_mv)
     mixed = {}
-    for prec, label in ((L.DMRG_FP32, "fp32"), (L.DMRG_BF16X3, "bf16x3"), (L.DMRG_BF16X6, "bf16x6")):
+    arithmetics = [] if args.no_mixed else [(L.DMRG_FP32, "fp32"), (L.DMRG_BF16X3, "bf16x3"),
+                                            (L.DMRG_BF16X6, "bf16x6")]
+    for prec, label in arithmetics:
         h.set_precision(prec)
         for _ in range(args.warmup):
             h.tst_targets(pd, tau, kdim, td, info=False)
@@ -241,10 +280,13 @@ def main():
         "mfma_peak_frac_step": round(value / PEAK_FP64_TFLOPS, 4),
         "mixed_precision": mixed,
         "batched_64": batched,
-        "roofline": {"bound": "mfma", "kernel": f"stage{dom} (fp64)",
+        "roofline": {"bound": "mfma", "kernel": f"stage{dom}<PF64>",
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                     "traffic": None},
+                     "traffic": measured_traffic(args.workload) if dom == 2 else None,
+                     "traffic_unit": "bytes per launch",
+                     "algorithmic_flop_per_launch": fl_dom,
+                     "ms_per_launch": round(ms_dom, 5)},
     }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

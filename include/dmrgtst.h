@@ -207,9 +207,11 @@ int dmrg_batch_set_graph(dmrg_batch b, int32_t enable);
 int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, int32_t kdim,
                            double* const* targets, double* weights, dmrg_krylov_info* infos);
 
-/* Measurement hook: runs reps products y = H_sb x (one vector) with HIP events around each of
- * the two block-product launches and waits for them.  out[0], out[1]: average milliseconds of
- * the right-product and left-product launches; out[2], out[3]: their algorithmic flops. */
+/* Measurement hook: one product y = H_sb x (one vector), then reps launches of the right-product
+ * stage back to back and reps launches of the left-product stage back to back, with HIP events
+ * on the handle's stream around each run; waits for them.  out[0], out[1]: average
+ * milliseconds per launch of the two stages; out[2], out[3]: their algorithmic flops.  y holds
+ * H_sb x afterwards. */
 int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps, double* out);
 
 /* Static description of a status code. */

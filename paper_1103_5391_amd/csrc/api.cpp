@@ -617,27 +617,31 @@ int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps,
     const Plan& P = h->plan;
     const int prec = h->precision, pk = prec >= DMRG_BF16X3 ? 1 : 0;
     const ProbPtrs pp = make_ptrs(h, prec, x, y, nullptr, nullptr);
+    auto s1 = [&] {
+        return launch_stage1(prec, h->dS1[pk].as<S1Block>(), h->dT1.as<Tile>(),
+                             (int)P.tiles1.size(), nullptr, pp, h->stream);
+    };
+    auto s2 = [&] {
+        return launch_stage2(prec, h->dS2[pk].as<S2Block>(), h->dSeg[pk].as<Segment>(),
+                             h->dT2.as<Tile>(), (int)P.tiles2.size(), nullptr, pp, h->stream);
+    };
+    // each stage repeated back to back (both are idempotent: stage 1 rewrites the intermediate
+    // from x, stage 2 rewrites y from x and the intermediate), one event pair around each run
     hipEvent_t ev[3];
     for (auto& e : ev) HIP_TRY(h, hipEventCreate(&e));
-    double t1 = 0.0, t2 = 0.0;
-    for (int r = 0; r < reps; ++r) {
-        HIP_TRY(h, hipEventRecord(ev[0], h->stream));
-        HIP_TRY(h, launch_stage1(prec, h->dS1[pk].as<S1Block>(), h->dT1.as<Tile>(),
-                                 (int)P.tiles1.size(), nullptr, pp, h->stream));
-        HIP_TRY(h, hipEventRecord(ev[1], h->stream));
-        HIP_TRY(h, launch_stage2(prec, h->dS2[pk].as<S2Block>(), h->dSeg[pk].as<Segment>(),
-                                 h->dT2.as<Tile>(), (int)P.tiles2.size(), nullptr, pp, h->stream));
-        HIP_TRY(h, hipEventRecord(ev[2], h->stream));
-        HIP_TRY(h, hipEventSynchronize(ev[2]));
-        float a = 0.f, b = 0.f;
-        HIP_TRY(h, hipEventElapsedTime(&a, ev[0], ev[1]));
-        HIP_TRY(h, hipEventElapsedTime(&b, ev[1], ev[2]));
-        t1 += a;
-        t2 += b;
-    }
+    HIP_TRY(h, s1());
+    HIP_TRY(h, hipEventRecord(ev[0], h->stream));
+    for (int r = 0; r < reps; ++r) HIP_TRY(h, s1());
+    HIP_TRY(h, hipEventRecord(ev[1], h->stream));
+    for (int r = 0; r < reps; ++r) HIP_TRY(h, s2());
+    HIP_TRY(h, hipEventRecord(ev[2], h->stream));
+    HIP_TRY(h, hipEventSynchronize(ev[2]));
+    float a = 0.f, b = 0.f;
+    HIP_TRY(h, hipEventElapsedTime(&a, ev[0], ev[1]));
+    HIP_TRY(h, hipEventElapsedTime(&b, ev[1], ev[2]));
     for (auto& e : ev) (void)hipEventDestroy(e);
-    out[0] = t1 / reps;
-    out[1] = t2 / reps;
+    out[0] = a / reps;
+    out[1] = b / reps;
     out[2] = P.flops1;
     out[3] = P.flops2;
     return DMRG_OK;
