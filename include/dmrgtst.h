@@ -74,6 +74,16 @@ enum dmrg_precision {
                              accumulation: relative error about 2^-24, like FP32          */
 };
 
+/* Kernel families of the two block-product stages (bits of a variant).  Without the bit a stage
+ * runs register-tiled (stage 1: a 32 x 64 tile per wavefront; stage 2: a 32 x 32 tile per work
+ * group whose K chunks are dealt to its four wavefronts); with it LDS-tiled (64 x 64 tiles per
+ * work group, four wavefronts sharing every K chunk through LDS; stage 2 splits long K into
+ * slices summed by a reduction launch).  Results agree to rounding. */
+enum dmrg_gemm {
+    DMRG_GEMM_STAGE1_LDS = 1,
+    DMRG_GEMM_STAGE2_LDS = 2
+};
+
 /* A block operator of one half that changes (N_up, N_dn) by dq.  blocks: for every source
  * sector p in ascending order whose image p+dq is a sector of the half, one dense
  * dim(p+dq) x dim(p) column-major block, all concatenated. */
@@ -160,6 +170,18 @@ int dmrg_flops(dmrg_handle h, double* flops);
  * cleared for the new element size).  DMRG_EINVAL for an unknown value. */
 int dmrg_set_precision(dmrg_handle h, int32_t precision);
 
+/* Selects the kernel families (dmrg_gemm bits; both register-tiled after dmrg_create).  DMRG_EINVAL
+ * for unknown bits. */
+int dmrg_set_gemm(dmrg_handle h, int32_t variant);
+int dmrg_get_gemm(dmrg_handle h, int32_t* variant);
+
+/* Autotuner: times both kernel families of each stage on the handle's problem in its current
+ * arithmetic (reps back-to-back launches each, on zeroed scratch vectors the handle owns) and
+ * keeps the faster of each.  out: NULL or 4 doubles receiving milliseconds per launch of
+ * [stage 1 register-tiled, stage 1 LDS-tiled, stage 2 register-tiled, stage 2 LDS-tiled].
+ * Waits for the handle's stream. */
+int dmrg_autotune(dmrg_handle h, int32_t reps, double* out);
+
 /* Changes the stream all later work of the handle is ordered on. */
 int dmrg_set_stream(dmrg_handle h, void* stream);
 
@@ -198,6 +220,11 @@ int dmrg_set_graph(dmrg_handle h, int32_t enable);
 int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out);
 void dmrg_batch_destroy(dmrg_batch b);
 int dmrg_batch_set_graph(dmrg_batch b, int32_t enable);
+
+/* Kernel families of the batch's merged launches (initially those of the first handle), and
+ * their autotuner (as dmrg_autotune, on the merged work lists of all handles). */
+int dmrg_batch_set_gemm(dmrg_batch b, int32_t variant);
+int dmrg_batch_autotune(dmrg_batch b, int32_t reps, double* out);
 
 /* phi[i], targets[i]: device pointers for superblock i (host arrays of count pointers; the
  * targets of superblock i are 4 x 2 n_i doubles).  Results equal those of dmrg_tst_targets on

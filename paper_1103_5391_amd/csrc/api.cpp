@@ -21,12 +21,20 @@ hipError_t launch_stage1(int, const S1Block*, const Tile*, int, const ProbPtrs*,
                          hipStream_t);
 hipError_t launch_stage2(int, const S2Block*, const Segment*, const Tile*, int, const ProbPtrs*,
                          ProbPtrs, hipStream_t);
+hipError_t launch_stage1_lds(int, const S1Block*, const LItem1*, int, const ProbPtrs*, ProbPtrs,
+                             hipStream_t);
+hipError_t launch_stage2_lds(int, const S2Block*, const Segment*, const LItem2*, int, const LRed*,
+                             int, const ProbPtrs*, ProbPtrs, double*, hipStream_t);
 hipError_t launch_start(const VecGroup&, const double*, const double* const*, int, int,
                         hipStream_t);
 hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
 hipError_t launch_tridiag(const VecGroup&, const double*, int, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 int vec_blocks(int64_t n);
+
+// Kernel families used until the autotuner or the caller chooses: register-tiled for both
+// stages (the faster at the sizes measured so far).
+constexpr int DMRG_GEMM_DEFAULT = 0;
 
 struct DevBuf {
     void* p = nullptr;
@@ -49,14 +57,130 @@ struct DevBuf {
     T* as() const { return static_cast<T*>(p); }
 };
 
+// Device copies of the block-product work lists of one launch set (one handle, or the merged
+// lists of a batch): stage descriptors per chunk depth (0: 16, 1: 32), tile lists of the
+// register-tiled kernels (gemm.hip), tile lists of the LDS-tiled kernels (gemm_lds.hip) and
+// their partial-tile workspace.
+struct Lists {
+    DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT2, dL1, dL2[2], dLred[2], dPart;
+    int nt1 = 0, nt2 = 0, nl1 = 0, nl2[2] = {0, 0}, nred[2] = {0, 0};
+    int variant = 0;    // DMRG_GEMM_* bits: which kernel family runs each stage
+};
+
+// Device copy of a host vector (synchronous on s).
+template <typename T>
+hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
+    hipError_t e = b.alloc(v.size() * sizeof(T));
+    if (e != hipSuccess) return e;
+    if (v.empty()) return hipSuccess;
+    e = hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+// Uploads the work lists of one launch set; k indexes the chunk depth (0: 16, 1: 32).
+hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vector<S2Block>* s2,
+                        const std::vector<Segment>* segs, const std::vector<Tile>& t1,
+                        const std::vector<Tile>& t2, const std::vector<LItem1>& l1,
+                        const std::vector<LItem2>* l2, const std::vector<LRed>* lred,
+                        const int* nslots, hipStream_t st) {
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < 2 && e == hipSuccess; ++k) {
+        e = upload(W.dS1[k], s1[k], st);
+        if (e == hipSuccess) e = upload(W.dS2[k], s2[k], st);
+        if (e == hipSuccess) e = upload(W.dSeg[k], segs[k], st);
+        if (e == hipSuccess) e = upload(W.dL2[k], l2[k], st);
+        if (e == hipSuccess) e = upload(W.dLred[k], lred[k], st);
+    }
+    if (e == hipSuccess) e = upload(W.dT1, t1, st);
+    if (e == hipSuccess) e = upload(W.dT2, t2, st);
+    if (e == hipSuccess) e = upload(W.dL1, l1, st);
+    const int slots = std::max(nslots[0], nslots[1]);
+    if (e == hipSuccess) e = W.dPart.alloc(sizeof(double) * (size_t)slots * kLTile * kLTile);
+    W.nt1 = (int)t1.size();
+    W.nt2 = (int)t2.size();
+    W.nl1 = (int)l1.size();
+    for (int k = 0; k < 2; ++k) {
+        W.nl2[k] = (int)l2[k].size();
+        W.nred[k] = (int)lred[k].size();
+    }
+    return e;
+}
+
+// One block-product stage (1 or 2) of one product for every problem of a launch set, with the
+// kernel family the set's variant selects.
+hipError_t run_stage(const Lists& W, int stage, int variant, int prec, const ProbPtrs* probs,
+                     ProbPtrs single, hipStream_t s) {
+    const int pk = prec >= DMRG_BF16X3 ? 1 : 0;
+    if (stage == 1) {
+        if (variant & DMRG_GEMM_STAGE1_LDS)
+            return launch_stage1_lds(prec, W.dS1[pk].as<S1Block>(), W.dL1.as<LItem1>(), W.nl1,
+                                     probs, single, s);
+        return launch_stage1(prec, W.dS1[pk].as<S1Block>(), W.dT1.as<Tile>(), W.nt1, probs,
+                             single, s);
+    }
+    if (variant & DMRG_GEMM_STAGE2_LDS)
+        return launch_stage2_lds(prec, W.dS2[pk].as<S2Block>(), W.dSeg[pk].as<Segment>(),
+                                 W.dL2[pk].as<LItem2>(), W.nl2[pk], W.dLred[pk].as<LRed>(),
+                                 W.nred[pk], probs, single, W.dPart.as<double>(), s);
+    return launch_stage2(prec, W.dS2[pk].as<S2Block>(), W.dSeg[pk].as<Segment>(),
+                         W.dT2.as<Tile>(), W.nt2, probs, single, s);
+}
+
+// Both block-product launches of one product.
+hipError_t run_stages(const Lists& W, int prec, const ProbPtrs* probs, ProbPtrs single,
+                      hipStream_t s) {
+    const hipError_t e = run_stage(W, 1, W.variant, prec, probs, single, s);
+    if (e != hipSuccess) return e;
+    return run_stage(W, 2, W.variant, prec, probs, single, s);
+}
+
+// Average milliseconds of `reps` back-to-back launches of one stage (after one untimed launch).
+hipError_t time_stage(const Lists& W, int stage, int variant, int prec, const ProbPtrs* probs,
+                      ProbPtrs single, hipStream_t s, int reps, double* ms) {
+    hipEvent_t ev[2];
+    hipError_t e = hipEventCreate(&ev[0]);
+    if (e != hipSuccess) return e;
+    e = hipEventCreate(&ev[1]);
+    if (e == hipSuccess) e = run_stage(W, stage, variant, prec, probs, single, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[0], s);
+    for (int r = 0; r < reps && e == hipSuccess; ++r)
+        e = run_stage(W, stage, variant, prec, probs, single, s);
+    if (e == hipSuccess) e = hipEventRecord(ev[1], s);
+    if (e == hipSuccess) e = hipEventSynchronize(ev[1]);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, ev[0], ev[1]);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    *ms = (double)t / reps;
+    return e;
+}
+
+// Autotuner of a launch set: each stage's kernel families timed in turn (stage 1 first, its
+// output feeds stage 2), the fastest kept.  out: NULL or [s1 register, s1 LDS, s2 register,
+// s2 LDS] ms.
+hipError_t autotune_lists(Lists& W, int prec, const ProbPtrs* probs, ProbPtrs single,
+                          hipStream_t s, int reps, double* out) {
+    double t[4];
+    hipError_t e = hipSuccess;
+    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
+        const int stage = 1 + i / 2;
+        const int bit = stage == 1 ? DMRG_GEMM_STAGE1_LDS : DMRG_GEMM_STAGE2_LDS;
+        e = time_stage(W, stage, (i & 1) ? bit : 0, prec, probs, single, s, reps, &t[i]);
+    }
+    if (e != hipSuccess) return e;
+    W.variant = (t[1] < t[0] ? DMRG_GEMM_STAGE1_LDS : 0) | (t[3] < t[2] ? DMRG_GEMM_STAGE2_LDS : 0);
+    if (out)
+        for (int i = 0; i < 4; ++i) out[i] = t[i];
+    return hipSuccess;
+}
+
 // Device tables that run the Krylov passes of one handle, or of a batch of handles in common
 // launches (one launch per pass for all problems), eagerly or as a captured HIP graph of the
 // kdim Lanczos iterations.
 struct Group {
     std::vector<dmrg_ctx*> hs;
-    bool merged = false;                       // batch: own merged work lists
-    DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT2;  // merged work lists (batch only)
-    int ntiles1 = 0, ntiles2 = 0;
+    Lists* lists = nullptr;                    // the handle's own, or the batch's merged lists
     DevBuf dVP, dBmap, dProbs, dIO;            // VecProb, block map, ProbPtrs[kMaxKrylov][nprob], IO
     VecGroup vg{};
     int prec = -1;                             // precision the tables were built for
@@ -66,7 +190,7 @@ struct Group {
     hipEvent_t io_ev = nullptr;                // completion of the last upload
     bool use_graph = false;
     hipStream_t cap = nullptr;                 // private capture stream
-    std::map<int, hipGraphExec_t> graphs;      // captured Lanczos iterations by kdim
+    std::map<std::pair<int, int>, hipGraphExec_t> graphs;  // captured iterations by (kdim, variant)
 
     void clear_graphs() {
         for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -89,9 +213,9 @@ struct dmrg_ctx {
     hipStream_t stream = nullptr;
     int precision = DMRG_FP64;
     std::string last_error;
-    // device copies of the plan: stage descriptors per chunk depth (0: 16, 1: 32), packed
-    // operators per arithmetic (built on first use), tile lists
-    DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT2;
+    // device copies of the plan's work lists, packed operators per arithmetic (built on
+    // first use)
+    Lists lists;
     DevBuf dA[4], dR[4];
     // workspace
     DevBuf dT;          // stage-1 intermediate
@@ -105,6 +229,7 @@ struct dmrg_ctx {
 };
 
 struct dmrg_batch_ctx {
+    Lists lists;        // merged work lists of all handles
     Group g;
 };
 
@@ -127,15 +252,6 @@ int hip_fail(dmrg_handle h, hipError_t e, const char* where) {
         if (_e != hipSuccess) return hip_fail((h), _e, #expr); \
     } while (0)
 
-template <typename T>
-hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
-    hipError_t e = b.alloc(v.size() * sizeof(T));
-    if (e != hipSuccess) return e;
-    if (v.empty()) return hipSuccess;
-    e = hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
-    return hipStreamSynchronize(s);
-}
 
 int ensure_workspace(dmrg_handle h, int kdim) {
     if (h->kcap >= kdim + 1 && h->dW.p) return DMRG_OK;
@@ -183,13 +299,8 @@ ProbPtrs make_ptrs(dmrg_handle h, int prec, const double* x, double* y, const do
 
 // y = H_sb x for one caller vector.
 int matvec_one(dmrg_handle h, const double* x, double* y) {
-    const Plan& P = h->plan;
-    const int prec = h->precision, pk = prec >= DMRG_BF16X3 ? 1 : 0;
-    const ProbPtrs pp = make_ptrs(h, prec, x, y, nullptr, nullptr);
-    HIP_TRY(h, launch_stage1(prec, h->dS1[pk].as<S1Block>(), h->dT1.as<Tile>(),
-                             (int)P.tiles1.size(), nullptr, pp, h->stream));
-    HIP_TRY(h, launch_stage2(prec, h->dS2[pk].as<S2Block>(), h->dSeg[pk].as<Segment>(),
-                             h->dT2.as<Tile>(), (int)P.tiles2.size(), nullptr, pp, h->stream));
+    const ProbPtrs pp = make_ptrs(h, h->precision, x, y, nullptr, nullptr);
+    HIP_TRY(h, run_stages(h->lists, h->precision, nullptr, pp, h->stream));
     return DMRG_OK;
 }
 
@@ -239,20 +350,8 @@ int group_prepare(Group& g, int kdim) {
 
 // Both block-product launches of Lanczos iteration j for every problem of the group.
 int group_matvec(Group& g, int j, hipStream_t s) {
-    dmrg_ctx* h0 = g.hs[0];
-    const int prec = g.prec, pk = prec >= DMRG_BF16X3 ? 1 : 0;
     const ProbPtrs* probs = g.dProbs.as<ProbPtrs>() + (size_t)j * g.hs.size();
-    // a single handle runs its own work lists, a batch the merged ones
-    const DevBuf* S1 = g.merged ? g.dS1 : h0->dS1;
-    const DevBuf* S2 = g.merged ? g.dS2 : h0->dS2;
-    const DevBuf* Sg = g.merged ? g.dSeg : h0->dSeg;
-    const DevBuf& T1 = g.merged ? g.dT1 : h0->dT1;
-    const DevBuf& T2 = g.merged ? g.dT2 : h0->dT2;
-    const int n1 = g.merged ? g.ntiles1 : (int)h0->plan.tiles1.size();
-    const int n2 = g.merged ? g.ntiles2 : (int)h0->plan.tiles2.size();
-    HIP_TRY(h0, launch_stage1(prec, S1[pk].as<S1Block>(), T1.as<Tile>(), n1, probs, ProbPtrs{}, s));
-    HIP_TRY(h0, launch_stage2(prec, S2[pk].as<S2Block>(), Sg[pk].as<Segment>(), T2.as<Tile>(), n2,
-                              probs, ProbPtrs{}, s));
+    HIP_TRY(g.hs[0], run_stages(*g.lists, g.prec, probs, ProbPtrs{}, s));
     return DMRG_OK;
 }
 
@@ -270,7 +369,8 @@ int group_basis_eager(Group& g, int kdim, hipStream_t s) {
 int group_basis(Group& g, int kdim, hipStream_t s) {
     if (!g.use_graph) return group_basis_eager(g, kdim, s);
     dmrg_ctx* h0 = g.hs[0];
-    auto it = g.graphs.find(kdim);
+    const std::pair<int, int> key(kdim, g.lists->variant);
+    auto it = g.graphs.find(key);
     if (it == g.graphs.end()) {
         if (!g.cap) HIP_TRY(h0, hipStreamCreateWithFlags(&g.cap, hipStreamNonBlocking));
         HIP_TRY(h0, hipStreamBeginCapture(g.cap, hipStreamCaptureModeThreadLocal));
@@ -285,7 +385,7 @@ int group_basis(Group& g, int kdim, hipStream_t s) {
         const hipError_t ei = hipGraphInstantiate(&ex, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (ei != hipSuccess) return hip_fail(h0, ei, "hipGraphInstantiate");
-        it = g.graphs.emplace(kdim, ex).first;
+        it = g.graphs.emplace(key, ex).first;
     }
     HIP_TRY(h0, hipGraphLaunch(it->second, s));
     return DMRG_OK;
@@ -372,14 +472,17 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
     h->self.hs.assign(1, h);
     const Plan& P = h->plan;
     hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = upload(h->dS1[0], P.pk16.s1, h->stream);
-    if (e == hipSuccess) e = upload(h->dS2[0], P.pk16.s2, h->stream);
-    if (e == hipSuccess) e = upload(h->dSeg[0], P.pk16.segs, h->stream);
-    if (e == hipSuccess) e = upload(h->dS1[1], P.pk32.s1, h->stream);
-    if (e == hipSuccess) e = upload(h->dS2[1], P.pk32.s2, h->stream);
-    if (e == hipSuccess) e = upload(h->dSeg[1], P.pk32.segs, h->stream);
-    if (e == hipSuccess) e = upload(h->dT1, P.tiles1, h->stream);
-    if (e == hipSuccess) e = upload(h->dT2, P.tiles2, h->stream);
+    h->self.lists = &h->lists;
+    h->lists.variant = DMRG_GEMM_DEFAULT;
+    {
+        const std::vector<S1Block> s1[2] = {P.pk16.s1, P.pk32.s1};
+        const std::vector<S2Block> s2[2] = {P.pk16.s2, P.pk32.s2};
+        const std::vector<Segment> sg[2] = {P.pk16.segs, P.pk32.segs};
+        const std::vector<LItem2> l2[2] = {P.pk16.l2, P.pk32.l2};
+        const std::vector<LRed> lr[2] = {P.pk16.lred, P.pk32.lred};
+        const int ns[2] = {P.pk16.nslots, P.pk32.nslots};
+        e = upload_lists(h->lists, s1, s2, sg, P.tiles1, P.tiles2, P.l1, l2, lr, ns, h->stream);
+    }
     if (e == hipSuccess) e = h->dT.alloc(sizeof(double) * (size_t)P.T_size);
     // the padding rows of the stage-1 workspace are read (times zero factors) but never
     // written: they must hold finite values, so the workspace starts zeroed
@@ -529,7 +632,7 @@ int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out
     if (!b) return DMRG_ENOMEM;
     Group& g = b->g;
     g.hs.assign(handles, handles + count);
-    g.merged = true;
+    g.lists = &b->lists;
     g.use_graph = true;
     dmrg_ctx* h0 = g.hs[0];
     try {
@@ -537,20 +640,13 @@ int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out
         for (dmrg_ctx* h : g.hs) plans.push_back(&h->plan);
         Merged M;
         merge_plans(plans, M);
-        hipError_t e = hipSuccess;
-        for (int k = 0; k < 2 && e == hipSuccess; ++k) {
-            e = upload(g.dS1[k], M.s1[k], h0->stream);
-            if (e == hipSuccess) e = upload(g.dS2[k], M.s2[k], h0->stream);
-            if (e == hipSuccess) e = upload(g.dSeg[k], M.segs[k], h0->stream);
-        }
-        if (e == hipSuccess) e = upload(g.dT1, M.tiles1, h0->stream);
-        if (e == hipSuccess) e = upload(g.dT2, M.tiles2, h0->stream);
+        b->lists.variant = h0->lists.variant;
+        const hipError_t e = upload_lists(b->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles2, M.l1,
+                                          M.l2, M.lred, M.nslots, h0->stream);
         if (e != hipSuccess) {
             delete b;
             return fail(h0, e == hipErrorOutOfMemory ? DMRG_ENOMEM : DMRG_EHIP, hipGetErrorString(e));
         }
-        g.ntiles1 = (int)M.tiles1.size();
-        g.ntiles2 = (int)M.tiles2.size();
     } catch (const std::bad_alloc&) {
         delete b;
         return DMRG_ENOMEM;
@@ -614,36 +710,64 @@ int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, i
 
 int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps, double* out) {
     if (!h || !x || !y || !out || reps < 1) return DMRG_EINVAL;
-    const Plan& P = h->plan;
-    const int prec = h->precision, pk = prec >= DMRG_BF16X3 ? 1 : 0;
+    const int prec = h->precision;
     const ProbPtrs pp = make_ptrs(h, prec, x, y, nullptr, nullptr);
-    auto s1 = [&] {
-        return launch_stage1(prec, h->dS1[pk].as<S1Block>(), h->dT1.as<Tile>(),
-                             (int)P.tiles1.size(), nullptr, pp, h->stream);
-    };
-    auto s2 = [&] {
-        return launch_stage2(prec, h->dS2[pk].as<S2Block>(), h->dSeg[pk].as<Segment>(),
-                             h->dT2.as<Tile>(), (int)P.tiles2.size(), nullptr, pp, h->stream);
-    };
-    // each stage repeated back to back (both are idempotent: stage 1 rewrites the intermediate
-    // from x, stage 2 rewrites y from x and the intermediate), one event pair around each run
-    hipEvent_t ev[3];
-    for (auto& e : ev) HIP_TRY(h, hipEventCreate(&e));
-    HIP_TRY(h, s1());
-    HIP_TRY(h, hipEventRecord(ev[0], h->stream));
-    for (int r = 0; r < reps; ++r) HIP_TRY(h, s1());
-    HIP_TRY(h, hipEventRecord(ev[1], h->stream));
-    for (int r = 0; r < reps; ++r) HIP_TRY(h, s2());
-    HIP_TRY(h, hipEventRecord(ev[2], h->stream));
-    HIP_TRY(h, hipEventSynchronize(ev[2]));
-    float a = 0.f, b = 0.f;
-    HIP_TRY(h, hipEventElapsedTime(&a, ev[0], ev[1]));
-    HIP_TRY(h, hipEventElapsedTime(&b, ev[1], ev[2]));
-    for (auto& e : ev) (void)hipEventDestroy(e);
-    out[0] = a / reps;
-    out[1] = b / reps;
-    out[2] = P.flops1;
-    out[3] = P.flops2;
+    const int v = h->lists.variant;
+    // stage 1 and stage 2 are idempotent (stage 1 rewrites the intermediate from x, stage 2
+    // rewrites y from x and the intermediate): each is timed over back-to-back launches
+    HIP_TRY(h, time_stage(h->lists, 1, v, prec, nullptr, pp, h->stream, reps, &out[0]));
+    HIP_TRY(h, time_stage(h->lists, 2, v, prec, nullptr, pp, h->stream, reps, &out[1]));
+    out[2] = h->plan.flops1;
+    out[3] = h->plan.flops2;
+    return DMRG_OK;
+}
+
+int dmrg_set_gemm(dmrg_handle h, int32_t variant) {
+    if (!h) return DMRG_EINVAL;
+    if (variant & ~(DMRG_GEMM_STAGE1_LDS | DMRG_GEMM_STAGE2_LDS))
+        return fail(h, DMRG_EINVAL, "unknown kernel variant bits");
+    h->lists.variant = variant;
+    return DMRG_OK;
+}
+
+int dmrg_get_gemm(dmrg_handle h, int32_t* variant) {
+    if (!h || !variant) return DMRG_EINVAL;
+    *variant = h->lists.variant;
+    return DMRG_OK;
+}
+
+int dmrg_autotune(dmrg_handle h, int32_t reps, double* out) {
+    if (!h || reps < 1) return DMRG_EINVAL;
+    int rc = ensure_workspace(h, 1);
+    if (rc) return rc;
+    // timing inputs: basis slot 0 (zeroed) into the work vector
+    const size_t bytes = sizeof(double) * 2 * (size_t)h->plan.n;
+    HIP_TRY(h, hipMemsetAsync(h->dV.p, 0, bytes, h->stream));
+    const ProbPtrs pp = make_ptrs(h, h->precision, h->dV.as<double>(), h->dW.as<double>(), nullptr,
+                                  nullptr);
+    HIP_TRY(h, autotune_lists(h->lists, h->precision, nullptr, pp, h->stream, reps, out));
+    return DMRG_OK;
+}
+
+int dmrg_batch_set_gemm(dmrg_batch b, int32_t variant) {
+    if (!b) return DMRG_EINVAL;
+    if (variant & ~(DMRG_GEMM_STAGE1_LDS | DMRG_GEMM_STAGE2_LDS))
+        return fail(b->g.hs[0], DMRG_EINVAL, "unknown kernel variant bits");
+    b->lists.variant = variant;
+    return DMRG_OK;
+}
+
+int dmrg_batch_autotune(dmrg_batch b, int32_t reps, double* out) {
+    if (!b || reps < 1) return DMRG_EINVAL;
+    Group& g = b->g;
+    dmrg_ctx* h0 = g.hs[0];
+    int rc = group_prepare(g, 1);
+    if (rc) return rc;
+    for (dmrg_ctx* h : g.hs)
+        HIP_TRY(h0, hipMemsetAsync(h->dV.p, 0, sizeof(double) * 2 * (size_t)h->plan.n, h0->stream));
+    // row 0 of the product table: basis slot 0 into the work vector of every problem
+    HIP_TRY(h0, autotune_lists(b->lists, g.prec, g.dProbs.as<ProbPtrs>(), ProbPtrs{}, h0->stream,
+                               reps, out));
     return DMRG_OK;
 }
 

@@ -16,148 +16,20 @@
 // wavefronts owns one 32 x 32 tile and deals its K chunks round-robin to the waves; the four
 // partial tiles are summed in LDS in a fixed order (deterministic, no atomics).
 //
-// Inside one MFMA the K index each lane group supplies is free as long as A and B agree, so
-// lane group g takes the KPL consecutive indices k = KPL g + t of a chunk.  The operator
-// factors are packed in exactly that order (see internal.hpp), so lane (g, r) reads its part
-// of a chunk as one contiguous piece, and they are zero-padded so no operator load needs a
-// bounds check.  The data operands are read in place: rows (stage 1) or columns (stage 2) are
-// contiguous in K.  The stage-1 workspace is zero-padded to whole chunks; for the input vector
-// out-of-range K indices are clamped to a valid element, whose product with the padded zeros
-// vanishes.
-#include "internal.hpp"
+// The operator factors are packed in MFMA lane order (mfma.hpp) and zero-padded so no operator
+// load needs a bounds check.  The data operands are read in place: rows (stage 1) or columns
+// (stage 2) are contiguous in K.  The stage-1 workspace is zero-padded to whole chunks; for the
+// input vector out-of-range K indices are clamped to a valid element, whose product with the
+// padded zeros vanishes.
+#include "mfma.hpp"
 
 namespace dmrg {
-
-typedef double d4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-
-// Global-memory loads (pointers from descriptor tables would otherwise become flat loads).
-template <typename T>
-__device__ __forceinline__ T ldg(const T* p, int64_t i) {
-    return ((const __attribute__((address_space(1))) T*)p)[i];
-}
-template <typename V>
-__device__ __forceinline__ V ldgv(const void* p) {
-    return *((const __attribute__((address_space(1))) V*)p);
-}
-
-// ---------------------------------------------------------------------------------------
-// arithmetic traits
-// ---------------------------------------------------------------------------------------
-struct PF64 {
-    static constexpr int CK = 16, KPL = 4, PER = 1;   // PER: packed pieces per value
-    using op_t = double;          // packed operator element
-    using ws_t = double;          // workspace element
-    using acc_t = d4;
-    using frag_t = d4;            // one lane's operand values of one chunk
-    __device__ static frag_t from(const double (&v)[KPL]) { return (d4){v[0], v[1], v[2], v[3]}; }
-    __device__ static frag_t load_op(const op_t* p) { return ldgv<d4>(p); }
-    __device__ static acc_t mma(const frag_t& a, const frag_t& b, acc_t c) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[t], b[t], c, 0, 0, 0);
-        return c;
-    }
-    __device__ static int row(int g, int v) { return g + 4 * v; }   // result lane layout
-};
-
-struct PF32 {
-    static constexpr int CK = 16, KPL = 4, PER = 1;
-    using op_t = float;
-    using ws_t = float;
-    using acc_t = f4;
-    using frag_t = f4;
-    __device__ static frag_t from(const double (&v)[KPL]) {
-        return (f4){(float)v[0], (float)v[1], (float)v[2], (float)v[3]};
-    }
-    __device__ static frag_t load_op(const op_t* p) { return ldgv<f4>(p); }
-    __device__ static acc_t mma(const frag_t& a, const frag_t& b, acc_t c) {
-#pragma unroll
-        for (int t = 0; t < 4; ++t) c = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t], b[t], c, 0, 0, 0);
-        return c;
-    }
-    __device__ static int row(int g, int v) { return 4 * g + v; }
-};
-
-// Split bf16 operands: NP pieces per value; the products of total order below NP (pieces
-// i + j < NP) are accumulated, smallest orders last.
-template <int NP>
-struct PSplit {
-    static constexpr int CK = 32, KPL = 8, PER = NP;
-    using op_t = __bf16;          // packed as KPL values of piece 0, then piece 1, ... per lane
-    using ws_t = float;
-    using acc_t = f4;
-    struct frag_t {
-        bf8 p[NP];
-    };
-    __device__ static frag_t from(const double (&v)[KPL]) {
-        frag_t f;
-#pragma unroll
-        for (int t = 0; t < KPL; ++t) {
-            float rest = (float)v[t];
-#pragma unroll
-            for (int q = 0; q < NP; ++q) {
-                const __bf16 h = (__bf16)rest;
-                f.p[q][t] = h;
-                rest -= (float)h;
-            }
-        }
-        return f;
-    }
-    __device__ static frag_t load_op(const op_t* p) {
-        frag_t f;
-#pragma unroll
-        for (int q = 0; q < NP; ++q) f.p[q] = ldgv<bf8>(p + q * KPL);
-        return f;
-    }
-    __device__ static acc_t mma(const frag_t& a, const frag_t& b, acc_t c) {
-#pragma unroll
-        for (int o = 0; o < NP; ++o)
-#pragma unroll
-            for (int i = 0; i <= o; ++i)
-                c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.p[i], b.p[o - i], c, 0, 0, 0);
-        return c;
-    }
-    __device__ static int row(int g, int v) { return 4 * g + v; }
-};
-using PBF3 = PSplit<2>;
-using PBF6 = PSplit<3>;
-
-// Elements of one packed panel chunk per lane (all pieces of a split value) and per chunk.
-template <class P>
-constexpr int lane_elems() {
-    return P::KPL * P::PER;
-}
-template <class P>
-constexpr int chunk_elems() {
-    return kPanel * 4 * lane_elems<P>();
-}
-
-template <class P>
-__device__ __forceinline__ void zero(typename P::acc_t& a) {
-#pragma unroll
-    for (int v = 0; v < 4; ++v) a[v] = 0;
-}
-
-// KPL consecutive data values v[t] = src[base + t] (workspace, zero-padded chunks)
-template <class P, typename T>
-__device__ __forceinline__ void load_run(const T* src, int64_t base, double (&v)[P::KPL]) {
-#pragma unroll
-    for (int t = 0; t < P::KPL; ++t) v[t] = (double)ldg(src, base + t);
-}
-// KPL values src[base + min(k0 + t, K - 1) * stride] (input vector, clamped)
-template <class P>
-__device__ __forceinline__ void load_clamped(const double* src, int64_t base, int k0, int K,
-                                             int64_t stride, double (&v)[P::KPL]) {
-#pragma unroll
-    for (int t = 0; t < P::KPL; ++t) v[t] = ldg(src, base + (int64_t)min(k0 + t, K - 1) * stride);
-}
 
 // ---------------------------------------------------------------------------------------
 // stage 1: one 32 x 64 tile per wavefront
 // ---------------------------------------------------------------------------------------
 template <class P>
-__global__ __launch_bounds__(256, 2) void stage1(const S1Block* __restrict__ blks,
+__global__ __launch_bounds__(256, 3) void stage1(const S1Block* __restrict__ blks,
                                                  const Tile* __restrict__ tiles, int ntiles,
                                                  const ProbPtrs* __restrict__ probs,
                                                  ProbPtrs single) {
@@ -250,6 +122,7 @@ __global__ __launch_bounds__(256, 2) void stage1(const S1Block* __restrict__ blk
 // ---------------------------------------------------------------------------------------
 // stage 2: one 32 x 32 tile per work group, K chunks dealt round-robin to the four waves
 // ---------------------------------------------------------------------------------------
+constexpr int kChunkTab = 256;   // workspace chunks of a block addressed through the LDS table
 template <class P, class Load>
 __device__ __forceinline__ void kloop(typename P::acc_t (&acc)[2][2], int c0, int step, int nch,
                                       Load load) {
@@ -313,17 +186,77 @@ __global__ __launch_bounds__(256, 3) void stage2(const S2Block* __restrict__ blk
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
         for (int nj = 0; nj < 2; ++nj) zero<P>(acc[mi][nj]);
-    for (int s = 0; s < B.nseg; ++s) {
-        const Segment sg = segs[B.seg0 + s];
+    // pass 1: segment 0, the diagonal H_S term, reads the block itself from the input vector;
+    // its scale is applied before anything else adds in
+    const Segment s0 = segs[B.seg0];
+    const int nch0 = (s0.K + P::CK - 1) / P::CK;
+    {
         int64_t bcol[2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
-            bcol[i] = sg.B.off + pl[i] * sg.B.poff + (int64_t)col[i] * sg.B.ld;
-        const int K = sg.K;
-        const int nch = (K + P::CK - 1) / P::CK;
-        // chunk c of this segment is global chunk ch0 + c, owned by wave (ch0 + c) mod 4
-        const int c0 = ((wave - sg.ch0) % kWaves + kWaves) % kWaves;
-        if (sg.src) {
+            bcol[i] = s0.B.off + pl[i] * s0.B.poff + (int64_t)col[i] * s0.B.ld;
+        auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[2]) {
+            const int64_t ga = (int64_t)c * chunk_elems<P>();
+#pragma unroll
+            for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
+            const int kb = c * P::CK + P::KPL * g;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                double v[P::KPL];
+                load_clamped<P>(P_.x, bcol[i], kb, s0.K, 1, v);
+                fb[i] = P::from(v);
+            }
+        };
+        kloop<P>(acc, wave, kWaves, nch0, load);
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < 2; ++nj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) acc[mi][nj][v] *= xs;
+    }
+    // pass 2: every workspace chunk of segments 1.. in one pipelined stream per wave (global
+    // chunk c goes to wave c mod 4), its source view read from a per-chunk table in LDS (built
+    // once per work group) instead of restarting the pipeline at every segment
+    __shared__ int64_t ctab[kChunkTab][3];   // per workspace chunk: off - ch0 CK, poff, ld
+    const int nT = B.nch - nch0;
+    if (nT > 0 && nT <= kChunkTab) {
+        for (int t = threadIdx.x; t < nT; t += blockDim.x) {
+            const int c = nch0 + t;
+            int si = 1;
+            Segment sg = segs[B.seg0 + 1];
+            while (c >= sg.ch0 + (sg.K + P::CK - 1) / P::CK) sg = segs[B.seg0 + ++si];
+            ctab[t][0] = sg.B.off - (int64_t)sg.ch0 * P::CK;
+            ctab[t][1] = sg.B.poff;
+            ctab[t][2] = sg.B.ld;
+        }
+        __syncthreads();
+        auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[2]) {
+            const int64_t ga = (int64_t)c * chunk_elems<P>();
+#pragma unroll
+            for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
+            const int64_t* e = ctab[c - nch0];
+            const int64_t kb = (int64_t)c * P::CK + P::KPL * g;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                double v[P::KPL];
+                load_run<P>(Tws, e[0] + pl[i] * e[1] + (int64_t)col[i] * e[2] + kb, v);
+                fb[i] = P::from(v);
+            }
+        };
+        // first chunk >= nch0 owned by this wave
+        const int cw = nch0 + ((wave - nch0) % kWaves + kWaves) % kWaves;
+        kloop<P>(acc, cw, kWaves, B.nch, load);
+    } else {
+        // very long K: one pipeline per segment
+        for (int s = 1; s < B.nseg; ++s) {
+            const Segment sg = segs[B.seg0 + s];
+            int64_t bcol[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i)
+                bcol[i] = sg.B.off + pl[i] * sg.B.poff + (int64_t)col[i] * sg.B.ld;
+            const int nch = (sg.K + P::CK - 1) / P::CK;
+            const int c0 = ((wave - sg.ch0) % kWaves + kWaves) % kWaves;
             auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[2]) {
                 const int64_t ga = (int64_t)(sg.ch0 + c) * chunk_elems<P>();
 #pragma unroll
@@ -337,28 +270,6 @@ __global__ __launch_bounds__(256, 3) void stage2(const S2Block* __restrict__ blk
                 }
             };
             kloop<P>(acc, c0, kWaves, nch, load);
-        } else {
-            auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[2]) {
-                const int64_t ga = (int64_t)(sg.ch0 + c) * chunk_elems<P>();
-#pragma unroll
-                for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
-                const int kb = c * P::CK + P::KPL * g;
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    double v[P::KPL];
-                    load_clamped<P>(P_.x, bcol[i], kb, K, 1, v);
-                    fb[i] = P::from(v);
-                }
-            };
-            kloop<P>(acc, c0, kWaves, nch, load);
-            // segment 0 (the diagonal H_S term) is the only one reading the input vector:
-            // its scale is applied before any other segment adds in
-#pragma unroll
-            for (int mi = 0; mi < 2; ++mi)
-#pragma unroll
-                for (int nj = 0; nj < 2; ++nj)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[mi][nj][v] *= xs;
         }
     }
 

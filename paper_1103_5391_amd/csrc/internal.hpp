@@ -76,6 +76,30 @@ struct Tile {
     int32_t blk, m0, n0, pad;
 };
 
+// Work of the LDS-tiled block-product kernels: 64 x 64 output tiles, four wavefronts of 32 x 32
+// sharing every K chunk of both operands through LDS.
+constexpr int kLTile = 64;
+constexpr int kLSlice = 16;         // most K chunks one stage-2 work group takes (16-deep chunks;
+                                    // 8 of the 32-deep ones)
+
+// Stage-1 tile: rows m0.., columns n0.. of block blk.
+struct LItem1 {
+    int32_t blk, m0, n0, pad;
+};
+
+// Stage-2 tile slice: K chunks [kc0, kc1) of the concatenated K of block blk for the output tile
+// (m0, n0).  slot < 0: the slice is the whole K and the tile is written to y (plus T0); else
+// the product is written to partial tile `slot` and summed by a reduction item.
+struct LItem2 {
+    int32_t blk, m0, n0, kc0, kc1, slot;
+};
+
+// Reduction of a split stage-2 tile: y = T0 + sum of partial tiles slot0 .. slot0 + nslice - 1
+// (in that order).
+struct LRed {
+    int32_t blk, m0, n0, slot0, nslice, pad;
+};
+
 // Per-problem pointers for one launch of a stage (single problem: tables of length 1).
 struct ProbPtrs {
     const double* x;        // input vector

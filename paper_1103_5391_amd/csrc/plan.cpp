@@ -124,16 +124,16 @@ int64_t packed_index(int i, int k, int nch, int ck, int per) {
 // consecutive tiles, work group i runs on XCD i mod kXcd.  Blocks are assigned to XCDs by
 // longest-processing-time on their weights; per XCD the blocks are ordered heaviest first;
 // the per-XCD lists are padded with empty tiles (blk = -1) to whole groups and equal length.
-std::vector<Tile> xcd_order(const std::vector<Tile>& tiles, const std::vector<double>& w,
-                            int group) {
+template <class T>
+std::vector<T> xcd_order(const std::vector<T>& tiles, const std::vector<double>& w, int group) {
     const int nb = (int)w.size();
-    std::vector<std::vector<Tile>> of(nb);
-    for (const Tile& t : tiles) of[t.blk].push_back(t);
+    std::vector<std::vector<T>> of(nb);
+    for (const T& t : tiles) of[t.blk].push_back(t);
     std::vector<int> order(nb);
     for (int i = 0; i < nb; ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return w[a] > w[b]; });
     std::vector<double> load(kXcd, 0.0);
-    std::vector<std::vector<Tile>> lists(kXcd);
+    std::vector<std::vector<T>> lists(kXcd);
     for (int bi : order) {
         if (of[bi].empty()) continue;
         int x = 0;
@@ -142,14 +142,16 @@ std::vector<Tile> xcd_order(const std::vector<Tile>& tiles, const std::vector<do
         load[x] += w[bi];
         lists[x].insert(lists[x].end(), of[bi].begin(), of[bi].end());
     }
+    T pad{};
+    pad.blk = -1;
     size_t groups = 0;
     for (auto& l : lists) {
-        while (l.size() % group) l.push_back(Tile{-1, 0, 0, 0});
+        while (l.size() % group) l.push_back(pad);
         groups = std::max(groups, l.size() / group);
     }
     for (auto& l : lists)
-        while (l.size() < groups * group) l.push_back(Tile{-1, 0, 0, 0});
-    std::vector<Tile> out;
+        while (l.size() < groups * group) l.push_back(pad);
+    std::vector<T> out;
     out.reserve(groups * group * kXcd);
     for (size_t gi = 0; gi < groups; ++gi)
         for (int x = 0; x < kXcd; ++x)
@@ -163,6 +165,8 @@ void tile_list(std::vector<Tile>& out, int blk, int M, int N, int tm, int tn) {
 }
 
 }  // namespace
+
+void lds_lists(Plan& P);
 
 std::string build_plan(const dmrg_problem* pb, Plan& P) {
     if (!pb) return "problem is NULL";
@@ -337,13 +341,62 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
     P.tiles2 = xcd_order(P.tiles2, w2, 1);
     P.w1 = std::move(w1);
     P.w2 = std::move(w2);
+    lds_lists(P);
     return "";
+}
+
+// Work lists of the LDS-tiled kernels: 64 x 64 tiles; stage-2 tiles whose K exceeds a slice
+// are cut into about equal slices of at most `slice` chunks (partial tiles plus a reduction).
+void lds_lists(Plan& P) {
+    const int nb = (int)P.blocks.size();
+    auto panels = [](int v) { return (v + kPanel - 1) / kPanel; };
+    std::vector<double> w(nb, 0.0);
+    P.l1.clear();
+    for (int bi = 0; bi < nb; ++bi) {
+        const S1Block& s = P.pk16.s1[bi];
+        for (int m0 = 0; m0 < s.M; m0 += kLTile)
+            for (int n0 = 0; n0 < s.N; n0 += kLTile) {
+                P.l1.push_back(LItem1{bi, m0, n0, 0});
+                w[bi] += (double)std::min(4, panels(s.M - m0)) * std::min(4, panels(s.N - n0)) *
+                         (s.nch + 1);
+            }
+    }
+    P.l1 = xcd_order(P.l1, w, 1);
+    for (Packing* pk : {&P.pk16, &P.pk32}) {
+        pk->slice = pk->ck == 16 ? kLSlice : kLSlice / 2;   // chunks: K = 256 either way
+        pk->l2.clear();
+        pk->lred.clear();
+        pk->nslots = 0;
+        std::fill(w.begin(), w.end(), 0.0);
+        for (int bi = 0; bi < nb; ++bi) {
+            const S2Block& s = pk->s2[bi];
+            const int nsl = std::max(1, (s.nch + pk->slice - 1) / pk->slice);
+            for (int m0 = 0; m0 < s.M; m0 += kLTile)
+                for (int n0 = 0; n0 < s.N; n0 += kLTile) {
+                    const double area = (double)std::min(4, panels(s.M - m0)) *
+                                        std::min(4, panels(s.N - n0));
+                    if (nsl == 1) {
+                        pk->l2.push_back(LItem2{bi, m0, n0, 0, s.nch, -1});
+                    } else {
+                        pk->lred.push_back(LRed{bi, m0, n0, pk->nslots, nsl, 0});
+                        for (int q = 0; q < nsl; ++q)
+                            pk->l2.push_back(LItem2{bi, m0, n0, (int)((int64_t)s.nch * q / nsl),
+                                                    (int)((int64_t)s.nch * (q + 1) / nsl),
+                                                    pk->nslots++});
+                    }
+                    w[bi] += area * (s.nch + nsl);
+                }
+        }
+        pk->l2 = xcd_order(pk->l2, w, 1);
+    }
 }
 
 void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
     out = Merged{};
     std::vector<Tile> t1, t2;
     std::vector<double> w1, w2;
+    std::vector<LItem1> l1;
+    std::vector<LItem2> l2[2];
     int boff = 0;
     for (size_t i = 0; i < plans.size(); ++i) {
         const Plan& P = *plans[i];
@@ -367,10 +420,39 @@ void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
             if (t.blk >= 0) t2.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
         w1.insert(w1.end(), P.w1.begin(), P.w1.end());
         w2.insert(w2.end(), P.w2.begin(), P.w2.end());
+        for (LItem1 t : P.l1)
+            if (t.blk >= 0) {
+                t.blk += boff;
+                l1.push_back(t);
+            }
+        for (int k = 0; k < 2; ++k) {
+            const int soff = out.nslots[k];
+            for (LItem2 t : pks[k]->l2)
+                if (t.blk >= 0) {
+                    t.blk += boff;
+                    if (t.slot >= 0) t.slot += soff;
+                    l2[k].push_back(t);
+                }
+            for (LRed r : pks[k]->lred) {
+                r.blk += boff;
+                r.slot0 += soff;
+                out.lred[k].push_back(r);
+            }
+            out.nslots[k] += pks[k]->nslots;
+        }
         boff += (int)P.blocks.size();
     }
     out.tiles1 = xcd_order(t1, w1, kWaves);
     out.tiles2 = xcd_order(t2, w2, 1);
+    // the LDS lists keep each problem's block order: weights by tiles of the merged lists
+    std::vector<double> wl(boff, 0.0);
+    for (const LItem1& t : l1) wl[t.blk] += 1.0;
+    out.l1 = xcd_order(l1, wl, 1);
+    for (int k = 0; k < 2; ++k) {
+        std::fill(wl.begin(), wl.end(), 0.0);
+        for (const LItem2& t : l2[k]) wl[t.blk] += (double)(t.kc1 - t.kc0 + 1);
+        out.l2[k] = xcd_order(l2[k], wl, 1);
+    }
 }
 
 namespace {

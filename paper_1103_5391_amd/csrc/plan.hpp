@@ -72,6 +72,11 @@ struct Packing {
     std::vector<S2Block> s2;
     std::vector<Segment> segs;
     int64_t A_elems = 0, R_elems = 0;          // packed operator values
+    // LDS-tiled stage 2: slice length (chunks), tile slices, reductions of split tiles
+    int slice = 0;
+    std::vector<LItem2> l2;
+    std::vector<LRed> lred;
+    int nslots = 0;                            // partial tiles
 };
 
 struct Plan {
@@ -87,6 +92,7 @@ struct Plan {
     std::vector<View> Tview;                   // stage-1 workspace view per block
     int64_t T_size = 0;                        // workspace elements
     std::vector<Tile> tiles1, tiles2;
+    std::vector<LItem1> l1;                    // LDS-tiled stage-1 tiles (both packings)
     std::vector<double> w1, w2;                // per-block work estimates of the two stages
     Packing pk16, pk32;
     double flops = 0.0;                        // algorithmic flops per complex matvec
@@ -103,6 +109,10 @@ struct Merged {
     std::vector<S2Block> s2[2];
     std::vector<Segment> segs[2];
     std::vector<Tile> tiles1, tiles2;
+    std::vector<LItem1> l1;
+    std::vector<LItem2> l2[2];
+    std::vector<LRed> lred[2];
+    int nslots[2] = {0, 0};
 };
 void merge_plans(const std::vector<const Plan*>& plans, Merged& out);
 

@@ -16,6 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libdmrgtst.so")
 
 DMRG_FP64, DMRG_FP32, DMRG_BF16X3, DMRG_BF16X6 = 0, 1, 2, 3
+DMRG_GEMM_STAGE1_LDS, DMRG_GEMM_STAGE2_LDS = 1, 2
 STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP",
           -4: "DMRG_ENONFINITE", -5: "DMRG_ESTATE"}
 
@@ -23,8 +24,9 @@ STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP",
 SYMBOLS = [
     "dmrg_create", "dmrg_destroy", "dmrg_psi_layout", "dmrg_flops", "dmrg_set_precision",
     "dmrg_set_stream", "dmrg_matvec", "dmrg_krylov_expm", "dmrg_tst_targets", "dmrg_set_graph",
+    "dmrg_set_gemm", "dmrg_get_gemm", "dmrg_autotune",
     "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_set_graph", "dmrg_batch_tst_targets",
-    "dmrg_profile_matvec",
+    "dmrg_batch_set_gemm", "dmrg_batch_autotune", "dmrg_profile_matvec",
     "dmrg_strerror", "dmrg_last_error",
 ]
 
@@ -85,6 +87,11 @@ def load(path: str = LIB_PATH):
     lib.dmrg_krylov_expm.argtypes = [vp, vp, vp, dbl, i32, i32, P(dmrg_krylov_info)]
     lib.dmrg_tst_targets.argtypes = [vp, vp, dbl, i32, vp, P(dbl), P(dmrg_krylov_info)]
     lib.dmrg_set_graph.argtypes = [vp, i32]
+    lib.dmrg_set_gemm.argtypes = [vp, i32]
+    lib.dmrg_get_gemm.argtypes = [vp, P(i32)]
+    lib.dmrg_autotune.argtypes = [vp, i32, P(dbl)]
+    lib.dmrg_batch_set_gemm.argtypes = [vp, i32]
+    lib.dmrg_batch_autotune.argtypes = [vp, i32, P(dbl)]
     lib.dmrg_batch_create.argtypes = [P(vp), i32, P(vp)]
     lib.dmrg_batch_set_graph.argtypes = [vp, i32]
     lib.dmrg_batch_destroy.argtypes = [vp]
@@ -284,6 +291,28 @@ class Handle:
 
     set_graph = dmrg_set_graph
 
+    def dmrg_set_gemm(self, variant: int):
+        _check(self.lib.dmrg_set_gemm(self.h, int(variant)), self.h)
+
+    set_gemm = dmrg_set_gemm
+
+    def dmrg_get_gemm(self) -> int:
+        v = C.c_int32()
+        _check(self.lib.dmrg_get_gemm(self.h, C.byref(v)), self.h)
+        return v.value
+
+    get_gemm = dmrg_get_gemm
+
+    def dmrg_autotune(self, reps: int = 10):
+        """Times both kernel families of each stage, keeps the faster; returns the timings (ms)
+        and the chosen variant bits."""
+        out = np.zeros(4)
+        _check(self.lib.dmrg_autotune(self.h, int(reps), _dptr(out, C.c_double)), self.h)
+        return dict(stage1_register=out[0], stage1_lds=out[1], stage2_register=out[2],
+                    stage2_lds=out[3], variant=self.get_gemm())
+
+    autotune = dmrg_autotune
+
     def dmrg_profile_matvec(self, x, y, reps: int = 10):
         """Average ms of the two block-product launches and their algorithmic flops."""
         n2 = 2 * self.n
@@ -312,6 +341,20 @@ class Batch:
         _check(self.lib.dmrg_batch_set_graph(self.b, int(bool(enable))), self.handles[0].h)
 
     set_graph = dmrg_batch_set_graph
+
+    def dmrg_batch_set_gemm(self, variant: int):
+        _check(self.lib.dmrg_batch_set_gemm(self.b, int(variant)), self.handles[0].h)
+
+    set_gemm = dmrg_batch_set_gemm
+
+    def dmrg_batch_autotune(self, reps: int = 5):
+        out = np.zeros(4)
+        _check(self.lib.dmrg_batch_autotune(self.b, int(reps), _dptr(out, C.c_double)),
+               self.handles[0].h)
+        return dict(stage1_register=out[0], stage1_lds=out[1], stage2_register=out[2],
+                    stage2_lds=out[3])
+
+    autotune = dmrg_batch_autotune
 
     def dmrg_batch_tst_targets(self, phis, tau: float, kdim: int, targets, info: bool = True):
         cnt = len(self.handles)

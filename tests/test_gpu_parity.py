@@ -94,12 +94,19 @@ def test_layout_matches_oracle(env):
         h.destroy()
 
 
+GEMM_VARIANTS = pytest.mark.parametrize("variant", [0, 1, 2, 3],
+                                        ids=["reg-reg", "lds-reg", "reg-lds", "lds-lds"])
+
+
+@GEMM_VARIANTS
 @pytest.mark.parametrize("name", MATVEC_CASES)
-def test_matvec_parity(env, name):
+def test_matvec_parity(env, name, variant):
+    """Both kernel families of each stage (register-tiled, LDS-tiled with K slices)."""
     torch, L = env
-    say("matvec", name)
+    say("matvec", name, "variant", variant)
     pb = problem(name)
     h = L.dmrg_create(pb)
+    h.set_gemm(variant)
     n = h.n
     x = I.random_psi(n, np.random.default_rng(I.SEED_BASE + 77))
     xd = _dev(torch, x)
@@ -493,4 +500,34 @@ def test_precision_switch_after_fp64_runs(env):
         err = rel(_host(yd), yref)
         say("  prec", prec, err)
         assert err <= (MV_TOL if prec == L.DMRG_FP64 else MIXED_TOL[prec])
+    h.destroy()
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2, 3], ids=["fp64", "fp32", "bf16x3", "bf16x6"])
+def test_autotune_and_variants_agree(env, prec):
+    """The autotuner keeps the faster family of each stage; every family gives the product to
+    the arithmetic's tolerance on the headline ladder, and the Krylov step is unchanged beyond
+    rounding."""
+    torch, L = env
+    say("autotune", prec)
+    pb = problem("ladder16_m1000")
+    h = L.dmrg_create(pb)
+    h.set_precision(prec)
+    t = h.autotune(reps=3)
+    say("  ", t)
+    assert all(t[k] > 0 for k in ("stage1_register", "stage1_lds", "stage2_register", "stage2_lds"))
+    want = (L.DMRG_GEMM_STAGE1_LDS if t["stage1_lds"] < t["stage1_register"] else 0) | \
+           (L.DMRG_GEMM_STAGE2_LDS if t["stage2_lds"] < t["stage2_register"] else 0)
+    assert t["variant"] == want
+    x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 91))
+    xd = _dev(torch, x)
+    yref = M.matvec_sector(pb, x)
+    tol = MV_TOL if prec == 0 else MIXED_TOL[prec]
+    for v in range(4):
+        h.set_gemm(v)
+        yd = torch.empty_like(xd)
+        h.matvec(xd, yd)
+        err = rel(_host(yd), yref)
+        say("  variant", v, err)
+        assert err <= tol
     h.destroy()
