@@ -261,7 +261,9 @@ int ensure_workspace(dmrg_handle h, int kdim) {
     HIP_TRY(h, h->dV.alloc(sizeof(double) * (size_t)n2 * (kdim + 1)));
     h->kcap = kdim + 1;
     if (!h->dW.p) HIP_TRY(h, h->dW.alloc(sizeof(double) * (size_t)n2));
-    if (!h->dPart.p) HIP_TRY(h, h->dPart.alloc(sizeof(double) * 2 * kMaxKrylov * kVecMaxBlocks));
+    if (!h->dPart.p)
+        HIP_TRY(h, h->dPart.alloc(sizeof(double) * (size_t)kDVals * kVecMaxBlocks *
+                                  ((kMaxKrylov + kDSlots - 1) / kDSlots)));
     if (!h->dState.p) {
         HIP_TRY(h, h->dState.alloc(sizeof(KState)));
         HIP_TRY(h, hipMemsetAsync(h->dState.p, 0, sizeof(KState), h->stream));
@@ -335,8 +337,9 @@ int group_prepare(Group& g, int kdim) {
         bmap.insert(bmap.end(), nb, i);
         b0 += nb;
         for (int j = 0; j < kMaxKrylov; ++j)
+            // the products take slot j as it is (not yet normalised): no input scale
             pp[(size_t)j * np + i] = make_ptrs(h, prec, j < h->kcap ? V + (int64_t)j * 2 * n : nullptr,
-                                               h->dW.as<double>(), &st->scale[j], &st->broken);
+                                               h->dW.as<double>(), nullptr, &st->broken);
     }
     HIP_TRY(h0, upload(g.dVP, vp, h0->stream));
     if (np > 1) HIP_TRY(h0, upload(g.dBmap, bmap, h0->stream));

@@ -14,6 +14,8 @@ constexpr int kChunkMax = 32;       // K depth of one BF16 chunk (one 16x16x32 M
 constexpr int kWaves = 4;           // waves per work group (split-K among them)
 constexpr int kVecThreads = 256;    // threads per block of the vector kernels
 constexpr int kVecMaxBlocks = 1024; // blocks per problem of a vector pass (rows of partial sums)
+constexpr int kDSlots = 16;         // basis slots per Lanczos reduction launch
+constexpr int kDVals = 4 * kDSlots + 4;   // values per partial row of a reduction launch
 constexpr int kMaxTimes = 4;        // time points evaluated from one Krylov basis
 constexpr int kXcd = 8;             // MI355X: 8 XCDs of 32 CUs, each with its own L2; work
                                     // group i of a launch runs on XCD i mod 8
@@ -136,8 +138,9 @@ struct KState {
     double alpha[kMaxKrylov];
     double beta[kMaxKrylov + 1];      // beta[0] = ||x||
     double scale[kMaxKrylov + 1];     // 1 / beta[j]: slot j of V holds beta[j] v_j
-    double h1[2 * kMaxKrylov];        // first projection coefficients (re, im interleaved)
-    double h2[2 * kMaxKrylov];        // second projection coefficients
+    double h1[2 * kMaxKrylov];        // h: coefficients of w = H v_j in the basis (re, im)
+    double h2[2 * kMaxKrylov];        // t = T a: the basis coefficients of H V a
+    double dela[2 * kMaxKrylov];      // a: the delayed second-sweep coefficients of slot j
     double coef[kMaxTimes][2 * kMaxKrylov];  // c(t_x) = beta0 exp(-i T t_x) e_1
     double bscale;                    // max(1, |alpha_i|, beta_i) for the breakdown test
     double err_est;

@@ -6,14 +6,23 @@
 // normalisation) and the state keeps scale[j] = 1/beta_j, so no separate normalisation pass
 // is needed; every consumer multiplies by scale[j] on load.
 //
-// Per Lanczos iteration j (after w = H v_j):
-//   project   h  = V^H w,           alpha_j = Re h_j                      (one pass)
-//   reorth1   w1 = w - V h,         h' = V^H w1                           (one pass)
-//   reorth2   u  = w1 - V h',       beta_{j+1} = ||u||, u -> slot j+1     (one pass)
-// Two classical Gram-Schmidt sweeps against the whole basis.  The three-term update
-// w -= alpha_j v_j + beta_j v_{j-1} is contained in the first sweep (both vectors are in the
-// basis and their coefficients are exactly alpha_j and the j-1 entry of h), so it is not a
-// separate pass; in exact arithmetic the result equals update-then-two-sweeps.
+// Orthogonalisation: full reorthogonalisation by two classical Gram-Schmidt sweeps against
+// the whole basis, with the second sweep of each new vector delayed into the next iteration so
+// that one iteration is one reduction pass, one one-block finalise and one update pass.  Slot j
+// holds u1, the new vector after its first sweep, when iteration j starts; the block products
+// are applied to that slot as it is (w_raw = H u1).  Then
+//   reduce    a = V^H u1, b = V^H w_raw (slots c < j), c = u1^H w_raw, d = ||u1||^2,
+//             e = ||w_raw||^2                                             (one pass)
+//   finalise  second sweep of u1: u = u1 - V a, beta_j^2 = d - |a|^2, v_j = u / beta_j;
+//             H u = w_raw - H V a, where H V a = V T a up to second order in the loss of
+//             orthogonality (T: the Lanczos matrix so far), so w = H v_j is known in the basis:
+//             h_c = v_c^H w = (b_c - t_c) / beta_j (c < j), t = T a,
+//             h_j = (c - a^H b) / beta_j^2 - t_j / beta_j, alpha_j = Re h_j
+//   update    slot j <- u; slot j+1 <- w - sum_c h_c v_c (first sweep of the next vector;
+//             it contains the three-term recurrence, whose coefficients are h_j and h_{j-1})
+//                                                                          (one pass)
+// In exact arithmetic this is the two-sweep recurrence; the dropped terms are products of two
+// quantities of the order of the loss of orthogonality.
 //
 // Every kernel runs over a table of problems (one entry for a single superblock, many for a
 // batch): block b of a pass works on problem bmap[b] (problem 0 when there is no map), as block
@@ -27,6 +36,8 @@
 #include "internal.hpp"
 
 namespace dmrg {
+
+constexpr int kFinThreads = 512;   // threads of the Lanczos finalise block (two rows each)
 
 namespace {
 
@@ -76,54 +87,72 @@ __device__ __forceinline__ Where locate(const VecProb* vp, const int* bmap, int 
     return w;
 }
 
-// Block-level sums of NV per-thread values; writes the block partials to part[lb * NV + v].
+// Block-level sums of NV per-thread values; writes the block partials value-major,
+// part[v * kVecMaxBlocks + lb], so that the finalise block reads each value's rows contiguously.
 template <int NV>
 __device__ __forceinline__ void block_partials(const double (&vals)[NV], double* part, int lb) {
     __shared__ double red[NV][kVecThreads / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wave = threadIdx.x >> 6;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double s = wave_sum(vals[v]);
-        if (lane == 0) red[v][wave] = s;
-    }
+    for (int v = 0; v < NV; ++v) red[v][wave] = wave_sum(vals[v]);   // every lane holds the sum
     __syncthreads();
     for (int v = threadIdx.x; v < NV; v += blockDim.x) {
         double s = 0.0;
 #pragma unroll
         for (int w = 0; w < kVecThreads / 64; ++w) s += red[v][w];
-        part[(int64_t)lb * NV + v] = s;
+        part[(int64_t)v * kVecMaxBlocks + lb] = s;
     }
 }
 
-// Finalise kernels run one block of kVecThreads per problem: totals[v] = sum_b part[b * NV + v]
-// in a fixed order (thread t adds rows t, t + kVecThreads, ... in turn, then the block
-// reduction of block_partials; nb <= kVecMaxBlocks).
-template <int NV>
+// As block_partials for NV values, then zeros for values NV .. ROW-1.
+template <int NV, int ROW>
+__device__ __forceinline__ void block_partials_row(const double (&vals)[NV > 0 ? NV : 1],
+                                                   double* part, int lb) {
+    __shared__ double red[NV > 0 ? NV : 1][kVecThreads / 64];
+    const int wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) red[v][wave] = wave_sum(vals[v]);   // every lane holds the sum
+    __syncthreads();
+    for (int v = threadIdx.x; v < ROW; v += blockDim.x) {
+        double s = 0.0;
+        if (v < NV) {
+#pragma unroll
+            for (int w = 0; w < kVecThreads / 64; ++w) s += red[v][w];
+        }
+        part[(int64_t)v * kVecMaxBlocks + lb] = s;
+    }
+}
+
+// Finalise kernels run one block of FT threads per problem: totals[v] = sum_b part[v][b] for
+// v < NV in a fixed order (thread t adds rows t, t + FT, ... in turn, then the block reduction
+// of block_partials; nb <= kVecMaxBlocks, value-major layout as written by block_partials).
+template <int NV, int FT = kVecThreads>
 __device__ void final_sums(const double* part, int nb, double* totals_lds) {
-    __shared__ double red[NV][kVecThreads / 64];
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    __shared__ double red[NV][FT / 64];
+    const int wave = threadIdx.x >> 6;
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-#pragma unroll
-    for (int q = 0; q < kVecMaxBlocks / kVecThreads; ++q) {
-        const int b0 = q * kVecThreads + threadIdx.x;
+    // global-address-space loads: all NV of a row group are requested before the first use
+    const gcptr gp = (gcptr)part;
+#pragma unroll 1
+    for (int q = 0; q < kVecMaxBlocks / FT; ++q) {
+        const int b0 = q * FT + threadIdx.x;
         const int b = b0 < nb ? b0 : nb - 1;
         const double keep = b0 < nb ? 1.0 : 0.0;
-        const double* row = part + (int64_t)b * NV;
+        double x[NV];
 #pragma unroll
-        for (int v = 0; v < NV; ++v) acc[v] += row[v] * keep;
+        for (int v = 0; v < NV; ++v) x[v] = gp[(int64_t)v * kVecMaxBlocks + b];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) acc[v] += x[v] * keep;
     }
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-        const double t = wave_sum(acc[v]);
-        if (lane == 0) red[v][wave] = t;
-    }
+    for (int v = 0; v < NV; ++v) red[v][wave] = wave_sum(acc[v]);   // every lane holds the sum
     __syncthreads();
-    for (int v = threadIdx.x; v < NV; v += blockDim.x) {
+    for (int v = threadIdx.x; v < NV; v += FT) {
         double t = 0.0;
 #pragma unroll
-        for (int w = 0; w < kVecThreads / 64; ++w) t += red[v][w];
+        for (int w = 0; w < FT / 64; ++w) t += red[v][w];
         totals_lds[v] = t;
     }
     __syncthreads();
@@ -187,195 +216,229 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_start(const VecProb* vp, in
 }
 
 // ---------------------------------------------------------------------------------------
-// project: partials of sum conj(u_c) w for c = c0 .. c0+NC-1.  The count is a template
-// parameter so the per-vector accumulators stay in registers and no load sits under a
-// data-dependent branch (which would force a wait on every outstanding load).
+// Lanczos iteration j: reduction pass.  Launch q covers slots c0 .. c0+NC-1 (NC <= kDSlots);
+// the first launch also accumulates u1^H w_raw, ||u1||^2 and ||w_raw||^2.  Partial rows of
+// launch q: kDVals values (a_c, b_c per slot, then c, d, e), unused values zero.
 // ---------------------------------------------------------------------------------------
-template <int NC>
-__global__ __launch_bounds__(kVecThreads) void k_project(const VecProb* vp, const int* bmap,
-                                                         int c0) {
+template <int NC, bool FIRST>
+__global__ __launch_bounds__(kVecThreads) void k_dreduce(const VecProb* vp, const int* bmap, int j,
+                                                         int c0, int q) {
+    constexpr int NV = 4 * NC + (FIRST ? 4 : 0);
     const Where W = locate(vp, bmap, 1);
     if (W.p.st->broken) return;
     const double* __restrict__ V0 = W.p.V + (int64_t)c0 * W.p.vstride;
+    const double* __restrict__ u1 = W.p.V + (int64_t)j * W.p.vstride;
     const double* __restrict__ w = W.p.w;
     const int64_t n = W.p.n, vstride = W.p.vstride;
-    double acc[2 * NC];
+    double acc[NV > 0 ? NV : 1];
 #pragma unroll
-    for (int c = 0; c < 2 * NC; ++c) acc[c] = 0.0;
+    for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     const int64_t stride = (int64_t)W.nbt * blockDim.x;
     for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double wr = w[i], wi = w[n + i];
+        const double ur = u1[i], ui = u1[n + i], wr = w[i], wi = w[n + i];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
-            const double* u = V0 + (int64_t)c * vstride;
-            const double ur = ldv(u, i), ui = ldv(u, n + i);
-            acc[2 * c] += ur * wr + ui * wi;
-            acc[2 * c + 1] += ur * wi - ui * wr;
+            const double* v = V0 + (int64_t)c * vstride;
+            const double vr = ldv(v, i), vi = ldv(v, n + i);
+            acc[4 * c] += vr * ur + vi * ui;
+            acc[4 * c + 1] += vr * ui - vi * ur;
+            acc[4 * c + 2] += vr * wr + vi * wi;
+            acc[4 * c + 3] += vr * wi - vi * wr;
+        }
+        if (FIRST) {
+            acc[4 * NC] += ur * wr + ui * wi;
+            acc[4 * NC + 1] += ur * wi - ui * wr;
+            acc[4 * NC + 2] += ur * ur + ui * ui;
+            acc[4 * NC + 3] += wr * wr + wi * wi;
         }
     }
-    block_partials<2 * NC>(acc, W.p.part, W.lb);
+    block_partials_row<NV, kDVals>(acc, W.p.part + (int64_t)q * kVecMaxBlocks * kDVals, W.lb);
 }
 
-// h1 (which = 1) or h2 (which = 2) entries c0..c0+NC-1 = scale_c * sums; alpha_j = Re h1_j.
-template <int NC>
-__global__ __launch_bounds__(kVecThreads) void k_fin_project(const VecProb* vp, int j, int c0,
-                                                             int which) {
+// Lanczos iteration j: finalise (one block per problem).  Sums the partial rows of the nq
+// reduction launches (row layout as above; the first launch has NC0 slots), then the small
+// algebra of the iteration (see the top of this file) into the state: dela = a, h2 = t,
+// h1 = h, alpha_j, beta_j, scale_j, the breakdown test, and on the last iteration beta_{j+1}
+// from ||w||^2 - |h|^2 for the error estimate.
+template <int NC0>
+__global__ __launch_bounds__(kFinThreads) void k_dfin(const VecProb* vp, int j, int kdim, int nq) {
     const VecProb P = vp[blockIdx.x];
     KState* st = P.st;
-    if (st->broken) return;
-    __shared__ double tot[2 * NC];
-    final_sums<2 * NC>(P.part, P.nb, tot);
-    double* h = which == 1 ? st->h1 : st->h2;
-    for (int c = threadIdx.x; c < NC; c += blockDim.x) {
-        const double s = st->scale[c0 + c];
-        h[2 * (c0 + c)] = s * tot[2 * c];
-        h[2 * (c0 + c) + 1] = s * tot[2 * c + 1];
-        if (which == 1 && c0 + c == j) st->alpha[j] = s * tot[2 * c];
+    const int tid = threadIdx.x;
+    // the state this iteration needs, read once in parallel
+    __shared__ double al[kMaxKrylov], be[kMaxKrylov + 1], sc[kMaxKrylov];
+    __shared__ double misc[2];   // bscale, beta_0
+    __shared__ int broken_s;
+    for (int c = tid; c < j; c += kFinThreads) {
+        const double a = ((gcptr)st->alpha)[c], b = ((gcptr)st->beta)[c], d = ((gcptr)st->scale)[c];
+        al[c] = a;
+        be[c] = b;
+        sc[c] = d;
     }
-}
-
-// ---------------------------------------------------------------------------------------
-// reorth1: w <- w - sum_c h1_c v_c (c < NC = j+1), partials of sum conj(u_c) w.  The second
-// read of each basis element comes right after the first (cache hit).
-// ---------------------------------------------------------------------------------------
-template <int NC>
-__global__ __launch_bounds__(kVecThreads) void k_reorth1(const VecProb* vp, const int* bmap) {
-    const Where W = locate(vp, bmap, 1);
-    const KState* st = W.p.st;
-    if (st->broken) return;
-    const double* V = W.p.V;
-    double* w = W.p.w;
-    const int64_t n = W.p.n, vstride = W.p.vstride;
-    __shared__ double hs[2 * NC];
-    for (int c = threadIdx.x; c < NC; c += blockDim.x) {
-        const double s = st->scale[c];
-        hs[2 * c] = st->h1[2 * c] * s;
-        hs[2 * c + 1] = st->h1[2 * c + 1] * s;
+    if (tid == 0) {
+        const double bs = ((gcptr)&st->bscale)[0], b0 = ((gcptr)st->beta)[0];
+        broken_s = ((const int __attribute__((address_space(1)))*)&st->broken)[0];
+        misc[0] = bs;
+        misc[1] = b0;
     }
     __syncthreads();
-    double acc[2 * NC];
-#pragma unroll
-    for (int c = 0; c < 2 * NC; ++c) acc[c] = 0.0;
-    const int64_t stride = (int64_t)W.nbt * blockDim.x;
-    for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double wr = w[i], wi = w[n + i];
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double* u = V + (int64_t)c * vstride;
-            const double ur = ldv(u, i), ui = ldv(u, n + i);
-            const double hr = hs[2 * c], hi = hs[2 * c + 1];
-            wr -= hr * ur - hi * ui;
-            wi -= hr * ui + hi * ur;
-        }
-        w[i] = wr;
-        w[n + i] = wi;
-        // reload the basis slice (cache hits) instead of holding 2 NC values in registers
-        __asm__ volatile("" ::: "memory");
-#pragma unroll
-        for (int c = 0; c < NC; ++c) {
-            const double* u = V + (int64_t)c * vstride;
-            const double ur = ldv(u, i), ui = ldv(u, n + i);
-            acc[2 * c] += ur * wr + ui * wi;
-            acc[2 * c + 1] += ur * wi - ui * wr;
-        }
+    if (broken_s) return;
+    __shared__ double tot[kDVals];
+    __shared__ double A[2 * kMaxKrylov], Bv[2 * kMaxKrylov], T[2 * kMaxKrylov + 2];
+    __shared__ double cde[4], out_s[4];
+    final_sums<4 * NC0 + 4, kFinThreads>(P.part, P.nb, tot);
+    for (int c = tid; c < NC0; c += kFinThreads) {
+        A[2 * c] = sc[c] * tot[4 * c];
+        A[2 * c + 1] = sc[c] * tot[4 * c + 1];
+        Bv[2 * c] = sc[c] * tot[4 * c + 2];
+        Bv[2 * c + 1] = sc[c] * tot[4 * c + 3];
     }
-    block_partials<2 * NC>(acc, W.p.part, W.lb);
-}
-
-// Unfused update (j+1 beyond the register capacity of k_reorth1): w <- w - sum_c h1_c v_c.
-__global__ __launch_bounds__(kVecThreads) void k_update(const VecProb* vp, const int* bmap, int j) {
-    const Where W = locate(vp, bmap, 1);
-    const KState* st = W.p.st;
-    if (st->broken) return;
-    const int nc = j + 1;
-    const double* __restrict__ V = W.p.V;
-    double* __restrict__ w = W.p.w;
-    const int64_t n = W.p.n, vstride = W.p.vstride;
-    __shared__ double hs[2 * kMaxKrylov];
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        const double s = st->scale[c];
-        hs[2 * c] = st->h1[2 * c] * s;
-        hs[2 * c + 1] = st->h1[2 * c + 1] * s;
-    }
+    if (tid < 4) cde[tid] = tot[4 * NC0 + tid];
     __syncthreads();
-    const int64_t stride = (int64_t)W.nbt * blockDim.x;
-    for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double wr = w[i], wi = w[n + i];
-#pragma unroll 8
-        for (int c = 0; c < nc; ++c) {
-            const double* u = V + (int64_t)c * vstride;
-            const double ur = ldv(u, i), ui = ldv(u, n + i);
-            const double hr = hs[2 * c], hi = hs[2 * c + 1];
-            wr -= hr * ur - hi * ui;
-            wi -= hr * ui + hi * ur;
+    for (int q = 1; q < nq; ++q) {
+        final_sums<4 * kDSlots, kFinThreads>(P.part + (int64_t)q * kVecMaxBlocks * kDVals, P.nb,
+                                             tot);
+        const int cb = q * kDSlots;
+        for (int c = tid; c < kDSlots && cb + c < j; c += kFinThreads) {
+            A[2 * (cb + c)] = sc[cb + c] * tot[4 * c];
+            A[2 * (cb + c) + 1] = sc[cb + c] * tot[4 * c + 1];
+            Bv[2 * (cb + c)] = sc[cb + c] * tot[4 * c + 2];
+            Bv[2 * (cb + c) + 1] = sc[cb + c] * tot[4 * c + 3];
         }
-        w[i] = wr;
-        w[n + i] = wi;
+        __syncthreads();
     }
-}
-
-// ---------------------------------------------------------------------------------------
-// reorth2: u = w - sum_c h2_c v_c -> slot j+1 (or w itself after the last iteration),
-// partial ||u||^2
-// ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(kVecThreads) void k_reorth2(const VecProb* vp, const int* bmap, int j,
-                                                         int to_slot) {
-    const Where W = locate(vp, bmap, 1);
-    const KState* st = W.p.st;
-    if (st->broken) return;
-    const int nc = j + 1;
-    const double* V = W.p.V;
-    const double* w = W.p.w;
-    double* dst = to_slot ? W.p.V + (int64_t)(j + 1) * W.p.vstride : W.p.w;
-    const int64_t n = W.p.n, vstride = W.p.vstride;
-    __shared__ double hs[2 * kMaxKrylov];
-    for (int c = threadIdx.x; c < nc; c += blockDim.x) {
-        const double s = st->scale[c];
-        hs[2 * c] = st->h2[2 * c] * s;
-        hs[2 * c + 1] = st->h2[2 * c + 1] * s;
-    }
-    __syncthreads();
-    double acc[1] = {0.0};
-    const int64_t stride = (int64_t)W.nbt * blockDim.x;
-    for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
-        double wr = w[i], wi = w[n + i];
-#pragma unroll 8
-        for (int c = 0; c < nc; ++c) {
-            const double* u = V + (int64_t)c * vstride;
-            const double ur = ldv(u, i), ui = ldv(u, n + i);
-            const double hr = hs[2 * c], hi = hs[2 * c + 1];
-            wr -= hr * ur - hi * ui;
-            wi -= hr * ui + hi * ur;
-        }
-        dst[i] = wr;
-        dst[n + i] = wi;
-        acc[0] += wr * wr + wi * wi;
-    }
-    block_partials<1>(acc, W.p.part, W.lb);
-}
-
-// beta_{j+1} = ||u||, breakdown test beta <= 1e-12 max(1, |alpha_i|, beta_i), scale[j+1].
-__global__ __launch_bounds__(kVecThreads) void k_fin_reorth2(const VecProb* vp, int j) {
-    const VecProb P = vp[blockIdx.x];
-    KState* st = P.st;
-    if (st->broken) return;
-    __shared__ double tot[1];
-    final_sums<1>(P.part, P.nb, tot);
-    if (threadIdx.x == 0) {
-        const double beta = sqrt(tot[0]);
-        st->beta[j + 1] = beta;
-        double sc = fmax(st->bscale, fabs(st->alpha[j]));
-        if (j > 0) sc = fmax(sc, st->beta[j]);
-        st->bscale = sc;
-        if (j < st->kdim - 1) {
-            if (beta <= 1e-12 * sc) {
+    if (tid == 0) {
+        // second sweep of u1: beta_j^2 = ||u1||^2 - |a|^2 (beta_0 = ||x|| is kept from the start)
+        double bj = misc[1];
+        if (j > 0) {
+            double a2 = 0.0;
+            for (int c = 0; c < j; ++c) a2 += A[2 * c] * A[2 * c] + A[2 * c + 1] * A[2 * c + 1];
+            bj = sqrt(fmax(cde[2] - a2, 0.0));
+            st->beta[j] = bj;
+            if (bj <= 1e-12 * misc[0]) {
                 st->broken = 1;
-                st->keff = j + 1;
+                st->keff = j;
+                bj = 0.0;
             } else {
-                st->scale[j + 1] = 1.0 / beta;
+                st->scale[j] = 1.0 / bj;
             }
-        } else {
-            st->keff = st->kdim;
+        }
+        out_s[0] = bj;
+        be[j] = bj;
+    }
+    __syncthreads();
+    const double bj = out_s[0];
+    if (bj == 0.0) return;
+    // t = T a (m = 0 .. j): T[m][m] = alpha_m, T[m][m-1] = beta_m, T[m][m+1] = beta_{m+1}
+    for (int m = tid; m <= j; m += kFinThreads) {
+        double tr = 0.0, ti = 0.0;
+        if (m < j) {
+            tr += al[m] * A[2 * m];
+            ti += al[m] * A[2 * m + 1];
+        }
+        if (m >= 1) {
+            tr += be[m] * A[2 * (m - 1)];
+            ti += be[m] * A[2 * (m - 1) + 1];
+        }
+        if (m + 1 < j) {
+            tr += be[m + 1] * A[2 * (m + 1)];
+            ti += be[m + 1] * A[2 * (m + 1) + 1];
+        }
+        T[2 * m] = tr;
+        T[2 * m + 1] = ti;
+    }
+    __syncthreads();
+    const double ib = 1.0 / bj;
+    for (int m = tid; m < j; m += kFinThreads) {
+        st->dela[2 * m] = A[2 * m];
+        st->dela[2 * m + 1] = A[2 * m + 1];
+        st->h1[2 * m] = (Bv[2 * m] - T[2 * m]) * ib;
+        st->h1[2 * m + 1] = (Bv[2 * m + 1] - T[2 * m + 1]) * ib;
+    }
+    for (int m = tid; m <= j; m += kFinThreads) {
+        st->h2[2 * m] = T[2 * m];
+        st->h2[2 * m + 1] = T[2 * m + 1];
+    }
+    if (tid == 0) {
+        // u^H w_raw = c - a^H b
+        double ur = cde[0], ui = cde[1];
+        for (int c = 0; c < j; ++c) {
+            ur -= A[2 * c] * Bv[2 * c] + A[2 * c + 1] * Bv[2 * c + 1];
+            ui -= A[2 * c] * Bv[2 * c + 1] - A[2 * c + 1] * Bv[2 * c];
+        }
+        const double hr = ur * ib * ib - T[2 * j] * ib, hi = ui * ib * ib - T[2 * j + 1] * ib;
+        st->h1[2 * j] = hr;
+        st->h1[2 * j + 1] = hi;
+        st->alpha[j] = hr;
+        double bsc = fmax(misc[0], fabs(hr));
+        if (j > 0) bsc = fmax(bsc, bj);
+        st->bscale = bsc;
+        if (j == kdim - 1) {
+            // ||w||^2 = (e - 2 Re(t^H V^H w_raw) + |t|^2) / beta_j^2, V^H w_raw = (b, (c - a^H b) / beta_j)
+            double tw = T[2 * j] * ur * ib + T[2 * j + 1] * ui * ib, t2 = 0.0;
+            for (int m = 0; m < j; ++m) tw += T[2 * m] * Bv[2 * m] + T[2 * m + 1] * Bv[2 * m + 1];
+            for (int m = 0; m <= j; ++m) t2 += T[2 * m] * T[2 * m] + T[2 * m + 1] * T[2 * m + 1];
+            const double w2 = (cde[3] - 2.0 * tw + t2) * ib * ib;
+            double h2 = hr * hr + hi * hi;
+            for (int m = 0; m < j; ++m) {
+                const double xr = (Bv[2 * m] - T[2 * m]) * ib, xi = (Bv[2 * m + 1] - T[2 * m + 1]) * ib;
+                h2 += xr * xr + xi * xi;
+            }
+            st->beta[j + 1] = sqrt(fmax(w2 - h2, 0.0));
+            st->keff = kdim;
+        }
+    }
+}
+
+// Lanczos iteration j: update pass.  slot j <- u = u1 - sum_c a_c v_c; with v_j = u scale_j and
+// w = (w_raw - sum_{c<j} t_c v_c - t_j v_j) scale_j: slot j+1 <- w - sum_{c<j} h_c v_c - h_j v_j
+// (skipped after the last iteration).
+__global__ __launch_bounds__(kVecThreads) void k_dupdate(const VecProb* vp, const int* bmap, int j,
+                                                         int last) {
+    const Where W = locate(vp, bmap, 1);
+    const KState* st = W.p.st;
+    if (st->broken) return;
+    __shared__ double co[3][2 * kMaxKrylov];   // a_c, t_c, h_c times scale_c (c < j)
+    for (int c = threadIdx.x; c < j; c += blockDim.x) {
+        const double s = st->scale[c];
+        co[0][2 * c] = st->dela[2 * c] * s;
+        co[0][2 * c + 1] = st->dela[2 * c + 1] * s;
+        co[1][2 * c] = st->h2[2 * c] * s;
+        co[1][2 * c + 1] = st->h2[2 * c + 1] * s;
+        co[2][2 * c] = st->h1[2 * c] * s;
+        co[2][2 * c + 1] = st->h1[2 * c + 1] * s;
+    }
+    __syncthreads();
+    const double sj = st->scale[j];
+    const double tjr = st->h2[2 * j] * sj, tji = st->h2[2 * j + 1] * sj;
+    const double hjr = st->h1[2 * j] * sj, hji = st->h1[2 * j + 1] * sj;
+    double* __restrict__ uj = W.p.V + (int64_t)j * W.p.vstride;
+    double* __restrict__ un = W.p.V + (int64_t)(j + 1) * W.p.vstride;
+    const double* __restrict__ V = W.p.V;
+    const double* __restrict__ w = W.p.w;
+    const int64_t n = W.p.n, vstride = W.p.vstride;
+    const int64_t stride = (int64_t)W.nbt * blockDim.x;
+    for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
+        double ar = 0.0, ai = 0.0, tr = 0.0, ti = 0.0, hr = 0.0, hi = 0.0;
+#pragma unroll 4
+        for (int c = 0; c < j; ++c) {
+            const double* v = V + (int64_t)c * vstride;
+            const double vr = ldv(v, i), vi = ldv(v, n + i);
+            ar += co[0][2 * c] * vr - co[0][2 * c + 1] * vi;
+            ai += co[0][2 * c] * vi + co[0][2 * c + 1] * vr;
+            tr += co[1][2 * c] * vr - co[1][2 * c + 1] * vi;
+            ti += co[1][2 * c] * vi + co[1][2 * c + 1] * vr;
+            hr += co[2][2 * c] * vr - co[2][2 * c + 1] * vi;
+            hi += co[2][2 * c] * vi + co[2][2 * c + 1] * vr;
+        }
+        const double ur = uj[i] - ar, ui = uj[n + i] - ai;
+        const double wr = (w[i] - tr - (tjr * ur - tji * ui)) * sj;
+        const double wi = (w[n + i] - ti - (tjr * ui + tji * ur)) * sj;
+        uj[i] = ur;
+        uj[n + i] = ui;
+        if (!last) {
+            un[i] = wr - hr - (hjr * ur - hji * ui);
+            un[n + i] = wi - hi - (hjr * ui + hji * ur);
         }
     }
 }
@@ -572,60 +635,36 @@ hipError_t launch_start(const VecGroup& g, const double* x1, const double* const
 
 namespace {
 
-constexpr int kProjMax = 32;     // vectors per fused projection launch
-constexpr int kReorthMax = 24;   // basis size up to which reorth1 is fused
+typedef void (*RedFn)(const VecProb*, const int*, int, int, int);
+typedef void (*DFinFn)(const VecProb*, int, int, int);
 
-typedef void (*ProjFn)(const VecProb*, const int*, int);
-typedef void (*FinFn)(const VecProb*, int, int, int);
-typedef void (*ReoFn)(const VecProb*, const int*);
-
-template <int... I>
-constexpr auto proj_table(std::integer_sequence<int, I...>) {
-    return std::array<ProjFn, sizeof...(I)>{&k_project<I + 1>...};
+template <bool FIRST, int... I>
+constexpr auto red_table(std::integer_sequence<int, I...>) {
+    return std::array<RedFn, sizeof...(I)>{&k_dreduce<I, FIRST>...};
 }
 template <int... I>
-constexpr auto fin_table(std::integer_sequence<int, I...>) {
-    return std::array<FinFn, sizeof...(I)>{&k_fin_project<I + 1>...};
-}
-template <int... I>
-constexpr auto reo_table(std::integer_sequence<int, I...>) {
-    return std::array<ReoFn, sizeof...(I)>{&k_reorth1<I + 1>...};
+constexpr auto dfin_table(std::integer_sequence<int, I...>) {
+    return std::array<DFinFn, sizeof...(I)>{&k_dfin<I>...};
 }
 
-const auto kProjTab = proj_table(std::make_integer_sequence<int, kProjMax>{});
-const auto kFinTab = fin_table(std::make_integer_sequence<int, kProjMax>{});
-const auto kReoTab = reo_table(std::make_integer_sequence<int, kReorthMax>{});
-
-// Projection sums of w against slots [0, nc) into h1 or h2, in register-sized pieces.
-void project(const VecGroup& g, int j, int nc, int which, hipStream_t s) {
-    for (int c0 = 0; c0 < nc; c0 += kProjMax) {
-        const int m = min(kProjMax, nc - c0);
-        hipLaunchKernelGGL(kProjTab[m - 1], dim3(g.nblk), dim3(kVecThreads), 0, s, g.vp, g.bmap,
-                           c0);
-        hipLaunchKernelGGL(kFinTab[m - 1], dim3(g.nprob), dim3(kVecThreads), 0, s, g.vp, j, c0,
-                           which);
-    }
-}
+const auto kRedFirst = red_table<true>(std::make_integer_sequence<int, kDSlots + 1>{});
+const auto kRedMore = red_table<false>(std::make_integer_sequence<int, kDSlots + 1>{});
+const auto kDFin = dfin_table(std::make_integer_sequence<int, kDSlots + 1>{});
 
 }  // namespace
 
-// Runs the reduction passes of Lanczos iteration j on every problem of the group.
+// Runs Lanczos iteration j (after the block products of slot j) on every problem of the group.
 hipError_t launch_lanczos_iter(const VecGroup& g, int j, int kdim, hipStream_t s) {
     const dim3 grid(g.nblk), blk(kVecThreads), one(g.nprob);
-    const int nc = j + 1;
-    // first sweep: h1 = V^H w (alpha_j = Re h1_j)
-    project(g, j, nc, 1, s);
-    // second sweep: w -= V h1, h2 = V^H w
-    if (nc <= kReorthMax) {
-        hipLaunchKernelGGL(kReoTab[nc - 1], grid, blk, 0, s, g.vp, g.bmap);
-        hipLaunchKernelGGL(kFinTab[nc - 1], one, blk, 0, s, g.vp, j, 0, 2);
-    } else {
-        hipLaunchKernelGGL(k_update, grid, blk, 0, s, g.vp, g.bmap, j);
-        project(g, j, nc, 2, s);
+    const int nq = j > kDSlots ? (j + kDSlots - 1) / kDSlots : 1;
+    const int nc0 = min(j, kDSlots);
+    hipLaunchKernelGGL(kRedFirst[nc0], grid, blk, 0, s, g.vp, g.bmap, j, 0, 0);
+    for (int q = 1; q < nq; ++q) {
+        const int nc = min(kDSlots, j - q * kDSlots);
+        hipLaunchKernelGGL(kRedMore[nc], grid, blk, 0, s, g.vp, g.bmap, j, q * kDSlots, q);
     }
-    // third pass: u = w - V h2 -> slot j+1, beta_{j+1}
-    hipLaunchKernelGGL(k_reorth2, grid, blk, 0, s, g.vp, g.bmap, j, (j + 1 < kdim) ? 1 : 0);
-    hipLaunchKernelGGL(k_fin_reorth2, one, blk, 0, s, g.vp, j);
+    hipLaunchKernelGGL(kDFin[nc0], one, dim3(kFinThreads), 0, s, g.vp, j, kdim, nq);
+    hipLaunchKernelGGL(k_dupdate, grid, blk, 0, s, g.vp, g.bmap, j, j == kdim - 1 ? 1 : 0);
     return hipGetLastError();
 }
 
