@@ -35,8 +35,8 @@ MEASURED_TRAFFIC = {
     "kernel": "stage2<PF64>",
     "workload": "ladder16_m1000",
     "source": "paper_1103_5391_amd/csrc/gemm.hip",
-    "source_sha256": "1fdde390ad199ec8e973e1f7b026249e11b4797f4815eca14ea55e9d544bb6e6",
-    "bytes": 82.10e6 + 5.06e6,
+    "source_sha256": "f94be671af094b9bfcfd91180b511d35ab52bf442eee8fada72e0b6b69e778ea",
+    "bytes": 85.00e6 + 4.98e6,
     "profile": "profiles/stage2_fp64_ladder16_m1000_kernel_stats.txt",
 }
 
@@ -100,6 +100,7 @@ def batch_section(L, I, torch, steps, warmup, count=64):
            for i, h in enumerate(hs)]
     tds = [torch.empty(8 * h.n, dtype=torch.float64, device="cuda") for h in hs]
     b = L.Batch(hs)
+    btune = b.autotune(reps=3)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
 
@@ -120,6 +121,7 @@ def batch_section(L, I, torch, steps, warmup, count=64):
 
     ms_loop = timed(loop)
     out = {"problems": count, "kdim": kdim, "tau": tau, "n_total": int(sum(h.n for h in hs)),
+           "autotune_ms": {k: round(float(v), 4) for k, v in btune.items()},
            "flops_per_step": F * kdim, "per_problem_loop_ms": round(ms_loop, 4)}
     for graph in (False, True):
         b.set_graph(graph)
@@ -174,6 +176,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     h = L.dmrg_create(pb, stream)
+    # the library's autotuner picks the kernel family of each block-product stage
+    tune64 = h.autotune(reps=10)
     F = h.flops()
     n = h.n
     phi = I.random_psi(n, np.random.default_rng(I.SEED_BASE + w["seed"] + 1000))
@@ -221,6 +225,7 @@ def main():
                                             (L.DMRG_BF16X6, "bf16x6")]
     for prec, label in arithmetics:
         h.set_precision(prec)
+        tune = h.autotune(reps=10)
         for _ in range(args.warmup):
             h.tst_targets(pd, tau, kdim, td, info=False)
         torch.cuda.synchronize()
@@ -246,9 +251,11 @@ def main():
             "matvec_rel_err_vs_fp64": float(torch.linalg.vector_norm(mv - ref_mv) / torch.linalg.vector_norm(ref_mv)),
             "tst_rel_err_vs_fp64": tst_err,
             "norm_drift": drift,
+            "gemm_variant": int(tune["variant"]),
         }
         print(f"[bench] {label}: {ms_p:.4f} ms/step, {mixed[label]}", file=sys.stderr, flush=True)
     h.set_precision(L.DMRG_FP64)
+    h.set_gemm(tune64["variant"])
 
     batched = None
     if not args.no_batch:
@@ -273,7 +280,9 @@ def main():
         "config": {"workload": args.workload, "lattice": w["lattice"], "L": w["L"],
                    "m": w.get("m"), "U": w["U"], "kdim": kdim, "tau": tau, "n_complex": n,
                    "flops_per_matvec": F, "precision": "fp64", "step": "time-step targeting: "
-                   "Krylov basis + tridiagonal exp at 4 times + combination"},
+                   "Krylov basis + tridiagonal exp at 4 times + combination",
+                   "gemm_variant": int(tune64["variant"]),
+                   "autotune_ms": {k: round(float(v), 5) for k, v in tune64.items() if k != "variant"}},
         "krylov_steps_per_s": round(1000.0 / ms_step, 3),
         "matvec_tflops": round(F / (ms_mv * 1e-3) / 1e12, 4),
         "matvec_ms": round(ms_mv, 5),
