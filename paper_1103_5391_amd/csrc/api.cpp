@@ -31,6 +31,7 @@ hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
 hipError_t launch_tridiag(const VecGroup&, const double*, int, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 int vec_blocks(int64_t n);
+int red_blocks(int64_t n);
 
 // Kernel families used until the autotuner or the caller chooses: register-tiled for both
 // stages (the faster at the sizes measured so far).
@@ -181,7 +182,8 @@ hipError_t autotune_lists(Lists& W, int prec, const ProbPtrs* probs, ProbPtrs si
 struct Group {
     std::vector<dmrg_ctx*> hs;
     Lists* lists = nullptr;                    // the handle's own, or the batch's merged lists
-    DevBuf dVP, dBmap, dProbs, dIO;            // VecProb, block map, ProbPtrs[kMaxKrylov][nprob], IO
+    DevBuf dVP, dBmap, dBmapR, dProbs, dIO;    // VecProb, block maps (streaming, reduction passes),
+                                               // ProbPtrs[kMaxKrylov][nprob], IO
     VecGroup vg{};
     int prec = -1;                             // precision the tables were built for
     std::vector<uint64_t> gens;                // member workspace generations of the tables
@@ -324,18 +326,21 @@ int group_prepare(Group& g, int kdim) {
     g.clear_graphs();
     const int np = (int)g.hs.size();
     std::vector<VecProb> vp(np);
-    std::vector<int> bmap;
+    std::vector<int> bmap, bmapr;
     std::vector<ProbPtrs> pp((size_t)kMaxKrylov * np);
-    int b0 = 0;
+    int b0 = 0, b0r = 0;
     for (int i = 0; i < np; ++i) {
         dmrg_ctx* h = g.hs[i];
         const int64_t n = h->plan.n;
         double* V = h->dV.as<double>();
         KState* st = h->dState.as<KState>();
-        const int nb = vec_blocks(n);
-        vp[i] = VecProb{V, h->dW.as<double>(), h->dPart.as<double>(), st, n, 2 * n, nb, b0};
+        const int nb = vec_blocks(n), nbr = red_blocks(n);
+        vp[i] = VecProb{V, h->dW.as<double>(), h->dPart.as<double>(), st, n, 2 * n, nb, b0,
+                        nbr, b0r};
         bmap.insert(bmap.end(), nb, i);
+        bmapr.insert(bmapr.end(), nbr, i);
         b0 += nb;
+        b0r += nbr;
         for (int j = 0; j < kMaxKrylov; ++j)
             // the products take slot j as it is (not yet normalised): no input scale
             pp[(size_t)j * np + i] = make_ptrs(h, prec, j < h->kcap ? V + (int64_t)j * 2 * n : nullptr,
@@ -343,8 +348,10 @@ int group_prepare(Group& g, int kdim) {
     }
     HIP_TRY(h0, upload(g.dVP, vp, h0->stream));
     if (np > 1) HIP_TRY(h0, upload(g.dBmap, bmap, h0->stream));
+    if (np > 1) HIP_TRY(h0, upload(g.dBmapR, bmapr, h0->stream));
     HIP_TRY(h0, upload(g.dProbs, pp, h0->stream));
-    g.vg = VecGroup{g.dVP.as<VecProb>(), np > 1 ? g.dBmap.as<int>() : nullptr, np, b0, 4};
+    g.vg = VecGroup{g.dVP.as<VecProb>(), np > 1 ? g.dBmap.as<int>() : nullptr,
+                    np > 1 ? g.dBmapR.as<int>() : nullptr, np, b0, b0r, 4};
     g.prec = prec;
     g.gens.resize(np);
     for (int i = 0; i < np; ++i) g.gens[i] = g.hs[i]->gen;

@@ -16,6 +16,11 @@ constexpr int kVecThreads = 256;    // threads per block of the vector kernels
 constexpr int kVecMaxBlocks = 1024; // blocks per problem of a vector pass (rows of partial sums)
 constexpr int kDSlots = 16;         // basis slots per Lanczos reduction launch
 constexpr int kDVals = 4 * kDSlots + 4;   // values per partial row of a reduction launch
+constexpr int kDMaxQ = (kMaxKrylov + kDSlots - 1) / kDSlots;   // reduction launches per iteration
+#ifndef DMRG_RED_ELEMS
+#define DMRG_RED_ELEMS 2
+#endif
+constexpr int kRedElems = DMRG_RED_ELEMS;  // complex elements per thread of a reduction pass
 constexpr int kMaxTimes = 4;        // time points evaluated from one Krylov basis
 constexpr int kXcd = 8;             // MI355X: 8 XCDs of 32 CUs, each with its own L2; work
                                     // group i of a launch runs on XCD i mod 8
@@ -122,14 +127,17 @@ struct VecProb {
     struct KState* st;
     int64_t n;            // complex length
     int64_t vstride;      // doubles between slots (2n)
-    int32_t nb, b0;
+    int32_t nb, b0;       // blocks of a streaming pass, first of them in the group's grid
+    int32_t nbr, b0r;     // the same for the Lanczos reduction pass
 };
 
 // Launch description of the vector passes over a group of problems.
 struct VecGroup {
     const VecProb* vp;    // device table [nprob]
     const int* bmap;      // device map block -> problem [nblk], nullptr for one problem
+    const int* bmapr;     // the same for the reduction pass [nblkr]
     int nprob, nblk;      // problems, blocks of a pass (sum of nb)
+    int nblkr;            // blocks of a reduction pass (sum of nbr)
     int combine_mult;     // blocks per pass block of the non-chained combination
 };
 
@@ -141,6 +149,7 @@ struct KState {
     double h1[2 * kMaxKrylov];        // h: coefficients of w = H v_j in the basis (re, im)
     double h2[2 * kMaxKrylov];        // t = T a: the basis coefficients of H V a
     double dela[2 * kMaxKrylov];      // a: the delayed second-sweep coefficients of slot j
+    double red[kDMaxQ * kDVals];      // totals of the reduction launches of one iteration
     double coef[kMaxTimes][2 * kMaxKrylov];  // c(t_x) = beta0 exp(-i T t_x) e_1
     double bscale;                    // max(1, |alpha_i|, beta_i) for the breakdown test
     double err_est;

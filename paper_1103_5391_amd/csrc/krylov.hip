@@ -37,7 +37,8 @@
 
 namespace dmrg {
 
-constexpr int kFinThreads = 512;   // threads of the Lanczos finalise block (two rows each)
+constexpr int kFinThreads = 256;   // threads of the Lanczos finalise block
+static_assert(kDVals % (kVecThreads / 64) == 0, "k_dsum: whole blocks of values");
 
 namespace {
 
@@ -84,6 +85,17 @@ __device__ __forceinline__ Where locate(const VecProb* vp, const int* bmap, int 
     w.p = vp[w.prob];
     w.lb = (int)blockIdx.x - w.p.b0 * mult;
     w.nbt = w.p.nb * mult;
+    return w;
+}
+
+// The same for the reduction pass, which has its own block decomposition (nbr blocks per problem,
+// several elements per thread, so that the per-block sums of its many values are amortised).
+__device__ __forceinline__ Where locate_red(const VecProb* vp, const int* bmapr) {
+    Where w;
+    w.prob = bmapr ? bmapr[blockIdx.x] : 0;
+    w.p = vp[w.prob];
+    w.lb = (int)blockIdx.x - w.p.b0r;
+    w.nbt = w.p.nbr;
     return w;
 }
 
@@ -224,7 +236,7 @@ template <int NC, bool FIRST>
 __global__ __launch_bounds__(kVecThreads) void k_dreduce(const VecProb* vp, const int* bmap, int j,
                                                          int c0, int q) {
     constexpr int NV = 4 * NC + (FIRST ? 4 : 0);
-    const Where W = locate(vp, bmap, 1);
+    const Where W = locate_red(vp, bmap);
     if (W.p.st->broken) return;
     const double* __restrict__ V0 = W.p.V + (int64_t)c0 * W.p.vstride;
     const double* __restrict__ u1 = W.p.V + (int64_t)j * W.p.vstride;
@@ -255,13 +267,37 @@ __global__ __launch_bounds__(kVecThreads) void k_dreduce(const VecProb* vp, cons
     block_partials_row<NV, kDVals>(acc, W.p.part + (int64_t)q * kVecMaxBlocks * kDVals, W.lb);
 }
 
-// Lanczos iteration j: finalise (one block per problem).  Sums the partial rows of the nq
-// reduction launches (row layout as above; the first launch has NC0 slots), then the small
-// algebra of the iteration (see the top of this file) into the state: dela = a, h2 = t,
+// Lanczos iteration j: totals of the reduction launches.  Wave w of block (x, problem) sums
+// value v = 4 x + w of the nq * kDVals values over the nbr partial rows (fixed order: lane l
+// adds rows l, l + 64, ... in turn, then the wavefront sum) into the state; many blocks, so the
+// partial rows are read in parallel across the chip rather than through one compute unit.
+__global__ __launch_bounds__(kVecThreads) void k_dsum(const VecProb* vp) {
+    const VecProb P = vp[blockIdx.y];
+    KState* st = P.st;
+    if (((const int __attribute__((address_space(1)))*)&st->broken)[0]) return;
+    const int lane = threadIdx.x & 63;
+    const int v = blockIdx.x * (kVecThreads / 64) + (threadIdx.x >> 6);
+    const gcptr row = (gcptr)(P.part + (int64_t)v * kVecMaxBlocks);
+    const int nbr = P.nbr;
+    double x[kVecMaxBlocks / 64];
+#pragma unroll
+    for (int k = 0; k < kVecMaxBlocks / 64; ++k) {
+        const int b = lane + 64 * k;
+        x[k] = row[b < nbr ? b : nbr - 1] * (b < nbr ? 1.0 : 0.0);
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int k = 0; k < kVecMaxBlocks / 64; ++k) acc += x[k];
+    acc = wave_sum(acc);
+    if (lane == 0) st->red[v] = acc;
+}
+
+// Lanczos iteration j: finalise (one block per problem).  Reads the totals of the nq reduction
+// launches (row layout as above; the first launch has nc0 = min(j, kDSlots) slots), then the
+// small algebra of the iteration (see the top of this file) into the state: dela = a, h2 = t,
 // h1 = h, alpha_j, beta_j, scale_j, the breakdown test, and on the last iteration beta_{j+1}
 // from ||w||^2 - |h|^2 for the error estimate.
-template <int NC0>
-__global__ __launch_bounds__(kFinThreads) void k_dfin(const VecProb* vp, int j, int kdim, int nq) {
+__global__ __launch_bounds__(kFinThreads) void k_dfin(const VecProb* vp, int j, int kdim, int nc0) {
     const VecProb P = vp[blockIdx.x];
     KState* st = P.st;
     const int tid = threadIdx.x;
@@ -283,30 +319,19 @@ __global__ __launch_bounds__(kFinThreads) void k_dfin(const VecProb* vp, int j, 
     }
     __syncthreads();
     if (broken_s) return;
-    __shared__ double tot[kDVals];
     __shared__ double A[2 * kMaxKrylov], Bv[2 * kMaxKrylov], T[2 * kMaxKrylov + 2];
     __shared__ double cde[4], out_s[4];
-    final_sums<4 * NC0 + 4, kFinThreads>(P.part, P.nb, tot);
-    for (int c = tid; c < NC0; c += kFinThreads) {
-        A[2 * c] = sc[c] * tot[4 * c];
-        A[2 * c + 1] = sc[c] * tot[4 * c + 1];
-        Bv[2 * c] = sc[c] * tot[4 * c + 2];
-        Bv[2 * c + 1] = sc[c] * tot[4 * c + 3];
+    const gcptr red = (gcptr)st->red;
+    for (int c = tid; c < j; c += kFinThreads) {
+        const int base = (c / kDSlots) * kDVals + 4 * (c % kDSlots);
+        const double s = sc[c];
+        A[2 * c] = s * red[base];
+        A[2 * c + 1] = s * red[base + 1];
+        Bv[2 * c] = s * red[base + 2];
+        Bv[2 * c + 1] = s * red[base + 3];
     }
-    if (tid < 4) cde[tid] = tot[4 * NC0 + tid];
+    if (tid < 4) cde[tid] = red[4 * nc0 + tid];
     __syncthreads();
-    for (int q = 1; q < nq; ++q) {
-        final_sums<4 * kDSlots, kFinThreads>(P.part + (int64_t)q * kVecMaxBlocks * kDVals, P.nb,
-                                             tot);
-        const int cb = q * kDSlots;
-        for (int c = tid; c < kDSlots && cb + c < j; c += kFinThreads) {
-            A[2 * (cb + c)] = sc[cb + c] * tot[4 * c];
-            A[2 * (cb + c) + 1] = sc[cb + c] * tot[4 * c + 1];
-            Bv[2 * (cb + c)] = sc[cb + c] * tot[4 * c + 2];
-            Bv[2 * (cb + c) + 1] = sc[cb + c] * tot[4 * c + 3];
-        }
-        __syncthreads();
-    }
     if (tid == 0) {
         // second sweep of u1: beta_j^2 = ||u1||^2 - |a|^2 (beta_0 = ||x|| is kept from the start)
         double bj = misc[1];
@@ -626,6 +651,15 @@ int vec_blocks(int64_t n) {
     return (int)nb;
 }
 
+// Blocks of the Lanczos reduction pass: kRedElems elements per thread, at most kVecMaxBlocks.
+int red_blocks(int64_t n) {
+    const int64_t per = (int64_t)kVecThreads * kRedElems;
+    int64_t nb = (n + per - 1) / per;
+    if (nb < 1) nb = 1;
+    if (nb > kVecMaxBlocks) nb = kVecMaxBlocks;
+    return (int)nb;
+}
+
 hipError_t launch_start(const VecGroup& g, const double* x1, const double* const* xt, int kdim,
                         int first, hipStream_t s) {
     hipLaunchKernelGGL(k_start, dim3(g.nblk), dim3(kVecThreads), 0, s, g.vp, g.bmap, x1, xt);
@@ -636,34 +670,29 @@ hipError_t launch_start(const VecGroup& g, const double* x1, const double* const
 namespace {
 
 typedef void (*RedFn)(const VecProb*, const int*, int, int, int);
-typedef void (*DFinFn)(const VecProb*, int, int, int);
 
 template <bool FIRST, int... I>
 constexpr auto red_table(std::integer_sequence<int, I...>) {
     return std::array<RedFn, sizeof...(I)>{&k_dreduce<I, FIRST>...};
 }
-template <int... I>
-constexpr auto dfin_table(std::integer_sequence<int, I...>) {
-    return std::array<DFinFn, sizeof...(I)>{&k_dfin<I>...};
-}
 
 const auto kRedFirst = red_table<true>(std::make_integer_sequence<int, kDSlots + 1>{});
 const auto kRedMore = red_table<false>(std::make_integer_sequence<int, kDSlots + 1>{});
-const auto kDFin = dfin_table(std::make_integer_sequence<int, kDSlots + 1>{});
 
 }  // namespace
 
 // Runs Lanczos iteration j (after the block products of slot j) on every problem of the group.
 hipError_t launch_lanczos_iter(const VecGroup& g, int j, int kdim, hipStream_t s) {
-    const dim3 grid(g.nblk), blk(kVecThreads), one(g.nprob);
+    const dim3 grid(g.nblk), gridr(g.nblkr), blk(kVecThreads), one(g.nprob);
     const int nq = j > kDSlots ? (j + kDSlots - 1) / kDSlots : 1;
     const int nc0 = min(j, kDSlots);
-    hipLaunchKernelGGL(kRedFirst[nc0], grid, blk, 0, s, g.vp, g.bmap, j, 0, 0);
+    hipLaunchKernelGGL(kRedFirst[nc0], gridr, blk, 0, s, g.vp, g.bmapr, j, 0, 0);
     for (int q = 1; q < nq; ++q) {
         const int nc = min(kDSlots, j - q * kDSlots);
-        hipLaunchKernelGGL(kRedMore[nc], grid, blk, 0, s, g.vp, g.bmap, j, q * kDSlots, q);
+        hipLaunchKernelGGL(kRedMore[nc], gridr, blk, 0, s, g.vp, g.bmapr, j, q * kDSlots, q);
     }
-    hipLaunchKernelGGL(kDFin[nc0], one, dim3(kFinThreads), 0, s, g.vp, j, kdim, nq);
+    hipLaunchKernelGGL(k_dsum, dim3(nq * kDVals / (kVecThreads / 64), g.nprob), blk, 0, s, g.vp);
+    hipLaunchKernelGGL(k_dfin, one, dim3(kFinThreads), 0, s, g.vp, j, kdim, nc0);
     hipLaunchKernelGGL(k_dupdate, grid, blk, 0, s, g.vp, g.bmap, j, j == kdim - 1 ? 1 : 0);
     return hipGetLastError();
 }
