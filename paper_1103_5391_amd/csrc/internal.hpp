@@ -18,7 +18,7 @@ constexpr int kDSlots = 16;         // basis slots per Lanczos reduction launch
 constexpr int kDVals = 4 * kDSlots + 4;   // values per partial row of a reduction launch
 constexpr int kDMaxQ = (kMaxKrylov + kDSlots - 1) / kDSlots;   // reduction launches per iteration
 #ifndef DMRG_RED_ELEMS
-#define DMRG_RED_ELEMS 2
+#define DMRG_RED_ELEMS 1
 #endif
 constexpr int kRedElems = DMRG_RED_ELEMS;  // complex elements per thread of a reduction pass
 constexpr int kMaxTimes = 4;        // time points evaluated from one Krylov basis
@@ -146,12 +146,8 @@ struct KState {
     double alpha[kMaxKrylov];
     double beta[kMaxKrylov + 1];      // beta[0] = ||x||
     double scale[kMaxKrylov + 1];     // 1 / beta[j]: slot j of V holds beta[j] v_j
-    double h1[2 * kMaxKrylov];        // h: coefficients of w = H v_j in the basis (re, im)
-    double h2[2 * kMaxKrylov];        // t = T a: the basis coefficients of H V a
-    double dela[2 * kMaxKrylov];      // a: the delayed second-sweep coefficients of slot j
     double red[kDMaxQ * kDVals];      // totals of the reduction launches of one iteration
     double coef[kMaxTimes][2 * kMaxKrylov];  // c(t_x) = beta0 exp(-i T t_x) e_1
-    double bscale;                    // max(1, |alpha_i|, beta_i) for the breakdown test
     double err_est;
     int32_t keff;
     int32_t broken;                   // 1 after breakdown (or zero input)

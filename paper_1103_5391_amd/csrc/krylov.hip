@@ -8,12 +8,13 @@
 //
 // Orthogonalisation: full reorthogonalisation by two classical Gram-Schmidt sweeps against
 // the whole basis, with the second sweep of each new vector delayed into the next iteration so
-// that one iteration is one reduction pass, one one-block finalise and one update pass.  Slot j
+// that one iteration is one reduction pass, a small totals kernel and one update pass.  Slot j
 // holds u1, the new vector after its first sweep, when iteration j starts; the block products
 // are applied to that slot as it is (w_raw = H u1).  Then
 //   reduce    a = V^H u1, b = V^H w_raw (slots c < j), c = u1^H w_raw, d = ||u1||^2,
 //             e = ||w_raw||^2                                             (one pass)
-//   finalise  second sweep of u1: u = u1 - V a, beta_j^2 = d - |a|^2, v_j = u / beta_j;
+//   algebra   (O(j) work, repeated by every block of the update pass)
+//             second sweep of u1: u = u1 - V a, beta_j^2 = d - |a|^2, v_j = u / beta_j;
 //             H u = w_raw - H V a, where H V a = V T a up to second order in the loss of
 //             orthogonality (T: the Lanczos matrix so far), so w = H v_j is known in the basis:
 //             h_c = v_c^H w = (b_c - t_c) / beta_j (c < j), t = T a,
@@ -26,10 +27,10 @@
 //
 // Every kernel runs over a table of problems (one entry for a single superblock, many for a
 // batch): block b of a pass works on problem bmap[b] (problem 0 when there is no map), as block
-// b - b0 of that problem's nb blocks; the one-block finalise kernels run one block per problem.
-// Grid-wide sums are deterministic: every block writes its partial sums and the finalise block
-// adds them in a fixed order (the kernel boundary orders the two; no device-wide fences or
-// atomics inside the bandwidth-bound passes).
+// b - b0 of that problem's nb blocks; the small kernels run one block (or a few) per problem.
+// Grid-wide sums are deterministic: every block writes its partial sums and a later kernel adds
+// them in a fixed order (the kernel boundary orders the two; no device-wide fences or atomics:
+// on this chip a device-scope release writes back the XCD's L2 and costs more than a launch).
 #include <array>
 #include <utility>
 
@@ -37,7 +38,6 @@
 
 namespace dmrg {
 
-constexpr int kFinThreads = 256;   // threads of the Lanczos finalise block
 static_assert(kDVals % (kVecThreads / 64) == 0, "k_dsum: whole blocks of values");
 
 namespace {
@@ -174,7 +174,6 @@ __device__ void final_sums(const double* part, int nb, double* totals_lds) {
 __device__ void begin_step(KState* st, double norm2, int kdim) {
     const double b0 = sqrt(norm2);
     st->beta[0] = b0;
-    st->bscale = 1.0;
     st->kdim = kdim;
     if (b0 > 0.0) {
         st->scale[0] = 1.0 / b0;
@@ -247,15 +246,22 @@ __global__ __launch_bounds__(kVecThreads) void k_dreduce(const VecProb* vp, cons
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     const int64_t stride = (int64_t)W.nbt * blockDim.x;
     for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const double ur = u1[i], ui = u1[n + i], wr = w[i], wi = w[n + i];
+        // every load of the element first, then the arithmetic (one memory round trip)
+        double vr[NC > 0 ? NC : 1], vi[NC > 0 ? NC : 1];
+        const double ur = ldv(u1, i), ui = ldv(u1, n + i), wr = ldv(w, i), wi = ldv(w, n + i);
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
             const double* v = V0 + (int64_t)c * vstride;
-            const double vr = ldv(v, i), vi = ldv(v, n + i);
-            acc[4 * c] += vr * ur + vi * ui;
-            acc[4 * c + 1] += vr * ui - vi * ur;
-            acc[4 * c + 2] += vr * wr + vi * wi;
-            acc[4 * c + 3] += vr * wi - vi * wr;
+            vr[c] = ldv(v, i);
+            vi[c] = ldv(v, n + i);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+            acc[4 * c] += vr[c] * ur + vi[c] * ui;
+            acc[4 * c + 1] += vr[c] * ui - vi[c] * ur;
+            acc[4 * c + 2] += vr[c] * wr + vi[c] * wi;
+            acc[4 * c + 3] += vr[c] * wi - vi[c] * wr;
         }
         if (FIRST) {
             acc[4 * NC] += ur * wr + ui * wi;
@@ -292,39 +298,30 @@ __global__ __launch_bounds__(kVecThreads) void k_dsum(const VecProb* vp) {
     if (lane == 0) st->red[v] = acc;
 }
 
-// Lanczos iteration j: finalise (one block per problem).  Reads the totals of the nq reduction
-// launches (row layout as above; the first launch has nc0 = min(j, kDSlots) slots), then the
-// small algebra of the iteration (see the top of this file) into the state: dela = a, h2 = t,
-// h1 = h, alpha_j, beta_j, scale_j, the breakdown test, and on the last iteration beta_{j+1}
-// from ||w||^2 - |h|^2 for the error estimate.
-__global__ __launch_bounds__(kFinThreads) void k_dfin(const VecProb* vp, int j, int kdim, int nc0) {
-    const VecProb P = vp[blockIdx.x];
-    KState* st = P.st;
-    const int tid = threadIdx.x;
-    // the state this iteration needs, read once in parallel
-    __shared__ double al[kMaxKrylov], be[kMaxKrylov + 1], sc[kMaxKrylov];
-    __shared__ double misc[2];   // bscale, beta_0
-    __shared__ int broken_s;
-    for (int c = tid; c < j; c += kFinThreads) {
-        const double a = ((gcptr)st->alpha)[c], b = ((gcptr)st->beta)[c], d = ((gcptr)st->scale)[c];
-        al[c] = a;
-        be[c] = b;
-        sc[c] = d;
-    }
-    if (tid == 0) {
-        const double bs = ((gcptr)&st->bscale)[0], b0 = ((gcptr)st->beta)[0];
-        broken_s = ((const int __attribute__((address_space(1)))*)&st->broken)[0];
-        misc[0] = bs;
-        misc[1] = b0;
-    }
-    __syncthreads();
-    if (broken_s) return;
-    __shared__ double A[2 * kMaxKrylov], Bv[2 * kMaxKrylov], T[2 * kMaxKrylov + 2];
-    __shared__ double cde[4], out_s[4];
+// Lanczos iteration j: the small algebra of the iteration (see the top of this file), run by
+// every block of the update pass from the totals of the reduction launches (row layout as
+// above; the first launch has nc0 = min(j, kDSlots) slots) and the Lanczos matrix so far, so
+// that no one-block launch sits between the reduction and the update.  Every block computes
+// the same values in the same order; block 0 of the problem (`writer`) stores alpha_j, beta_j,
+// scale_j, the breakdown flag and, on the last iteration, beta_{j+1} from ||w||^2 - |h|^2 for
+// the error estimate.  The other blocks read only entries < j of the state, which no block
+// writes here.  Result in LDS: co[0][c] = a_c scale_c, co[1][c] = t_c scale_c,
+// co[2][c] = h_c scale_c (c < j, zero up to j8), cj = {scale_j, t_j scale_j, h_j scale_j}.
+// Returns false (block-uniform) when the basis has broken down.
+__device__ bool iteration_coefficients(KState* st, int j, int kdim, int nc0, bool writer, int j8,
+                                       double (&co)[3][2 * kMaxKrylov], double (&cj)[5]) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    __shared__ double al[kMaxKrylov], be[kMaxKrylov + 1];
+    __shared__ double A[2 * kMaxKrylov], Bv[2 * kMaxKrylov], T[2 * kMaxKrylov + 2], sc[kMaxKrylov];
+    __shared__ double cde[4], sh[4];
+    __shared__ int ok;
     const gcptr red = (gcptr)st->red;
-    for (int c = tid; c < j; c += kFinThreads) {
+    for (int c = tid; c < j; c += blockDim.x) {
+        const double s = ((gcptr)st->scale)[c];
+        al[c] = ((gcptr)st->alpha)[c];
+        be[c] = ((gcptr)st->beta)[c];
+        sc[c] = s;
         const int base = (c / kDSlots) * kDVals + 4 * (c % kDSlots);
-        const double s = sc[c];
         A[2 * c] = s * red[base];
         A[2 * c + 1] = s * red[base + 1];
         Bv[2 * c] = s * red[base + 2];
@@ -332,30 +329,47 @@ __global__ __launch_bounds__(kFinThreads) void k_dfin(const VecProb* vp, int j, 
     }
     if (tid < 4) cde[tid] = red[4 * nc0 + tid];
     __syncthreads();
-    if (tid == 0) {
-        // second sweep of u1: beta_j^2 = ||u1||^2 - |a|^2 (beta_0 = ||x|| is kept from the start)
-        double bj = misc[1];
-        if (j > 0) {
-            double a2 = 0.0;
-            for (int c = 0; c < j; ++c) a2 += A[2 * c] * A[2 * c] + A[2 * c + 1] * A[2 * c + 1];
-            bj = sqrt(fmax(cde[2] - a2, 0.0));
-            st->beta[j] = bj;
-            if (bj <= 1e-12 * misc[0]) {
-                st->broken = 1;
-                st->keff = j;
-                bj = 0.0;
-            } else {
-                st->scale[j] = 1.0 / bj;
+    if (tid < 64) {
+        // wave 0: |a|^2, u^H w_raw = c - a^H b, and the breakdown scale max(1, |alpha_c|, beta_c)
+        // over the iterations before j (lane c holds slot c; j <= kMaxKrylov = 64)
+        const bool in = lane < j;
+        const double ar = in ? A[2 * lane] : 0.0, ai = in ? A[2 * lane + 1] : 0.0;
+        const double br = in ? Bv[2 * lane] : 0.0, bi = in ? Bv[2 * lane + 1] : 0.0;
+        const double a2 = wave_sum(ar * ar + ai * ai);
+        const double abr = wave_sum(ar * br + ai * bi), abi = wave_sum(ar * bi - ai * br);
+        double m = in ? fabs(al[lane]) : 0.0;
+        if (in && lane >= 1) m = fmax(m, be[lane]);
+        for (int o = 32; o > 0; o >>= 1) m = fmax(m, __shfl_xor(m, o, 64));
+        if (lane == 0) {
+            const double bscale = fmax(1.0, m);
+            // second sweep of u1: beta_j^2 = ||u1||^2 - |a|^2 (beta_0 = ||x|| from the start)
+            double bj = ((gcptr)st->beta)[0];
+            int good = 1;
+            if (j > 0) {
+                bj = sqrt(fmax(cde[2] - a2, 0.0));
+                if (bj <= 1e-12 * bscale) good = 0;
             }
+            if (writer && j > 0) {
+                st->beta[j] = bj;
+                if (good) {
+                    st->scale[j] = 1.0 / bj;
+                } else {
+                    st->broken = 1;
+                    st->keff = j;
+                }
+            }
+            be[j] = bj;
+            sh[0] = bj;
+            sh[1] = cde[0] - abr;   // u^H w_raw
+            sh[2] = cde[1] - abi;
+            ok = good;
         }
-        out_s[0] = bj;
-        be[j] = bj;
     }
     __syncthreads();
-    const double bj = out_s[0];
-    if (bj == 0.0) return;
+    if (!ok) return false;
+    const double bj = sh[0], ib = 1.0 / bj;
     // t = T a (m = 0 .. j): T[m][m] = alpha_m, T[m][m-1] = beta_m, T[m][m+1] = beta_{m+1}
-    for (int m = tid; m <= j; m += kFinThreads) {
+    for (int m = tid; m <= j; m += blockDim.x) {
         double tr = 0.0, ti = 0.0;
         if (m < j) {
             tr += al[m] * A[2 * m];
@@ -373,70 +387,62 @@ __global__ __launch_bounds__(kFinThreads) void k_dfin(const VecProb* vp, int j, 
         T[2 * m + 1] = ti;
     }
     __syncthreads();
-    const double ib = 1.0 / bj;
-    for (int m = tid; m < j; m += kFinThreads) {
-        st->dela[2 * m] = A[2 * m];
-        st->dela[2 * m + 1] = A[2 * m + 1];
-        st->h1[2 * m] = (Bv[2 * m] - T[2 * m]) * ib;
-        st->h1[2 * m + 1] = (Bv[2 * m + 1] - T[2 * m + 1]) * ib;
+    for (int c = tid; c < j8; c += blockDim.x) {
+        const bool in = c < j;
+        const double s = in ? sc[c] : 0.0;
+        co[0][2 * c] = in ? A[2 * c] * s : 0.0;
+        co[0][2 * c + 1] = in ? A[2 * c + 1] * s : 0.0;
+        co[1][2 * c] = in ? T[2 * c] * s : 0.0;
+        co[1][2 * c + 1] = in ? T[2 * c + 1] * s : 0.0;
+        co[2][2 * c] = in ? (Bv[2 * c] - T[2 * c]) * ib * s : 0.0;
+        co[2][2 * c + 1] = in ? (Bv[2 * c + 1] - T[2 * c + 1]) * ib * s : 0.0;
     }
-    for (int m = tid; m <= j; m += kFinThreads) {
-        st->h2[2 * m] = T[2 * m];
-        st->h2[2 * m + 1] = T[2 * m + 1];
-    }
-    if (tid == 0) {
-        // u^H w_raw = c - a^H b
-        double ur = cde[0], ui = cde[1];
-        for (int c = 0; c < j; ++c) {
-            ur -= A[2 * c] * Bv[2 * c] + A[2 * c + 1] * Bv[2 * c + 1];
-            ui -= A[2 * c] * Bv[2 * c + 1] - A[2 * c + 1] * Bv[2 * c];
-        }
+    if (tid < 64) {
+        const double ur = sh[1], ui = sh[2];
         const double hr = ur * ib * ib - T[2 * j] * ib, hi = ui * ib * ib - T[2 * j + 1] * ib;
-        st->h1[2 * j] = hr;
-        st->h1[2 * j + 1] = hi;
-        st->alpha[j] = hr;
-        double bsc = fmax(misc[0], fabs(hr));
-        if (j > 0) bsc = fmax(bsc, bj);
-        st->bscale = bsc;
         if (j == kdim - 1) {
-            // ||w||^2 = (e - 2 Re(t^H V^H w_raw) + |t|^2) / beta_j^2, V^H w_raw = (b, (c - a^H b) / beta_j)
-            double tw = T[2 * j] * ur * ib + T[2 * j + 1] * ui * ib, t2 = 0.0;
-            for (int m = 0; m < j; ++m) tw += T[2 * m] * Bv[2 * m] + T[2 * m + 1] * Bv[2 * m + 1];
-            for (int m = 0; m <= j; ++m) t2 += T[2 * m] * T[2 * m] + T[2 * m + 1] * T[2 * m + 1];
+            // ||w||^2 = (e - 2 Re(t^H V^H w_raw) + |t|^2) / beta_j^2, V^H w_raw = (b, (u^H w_raw) / beta_j)
+            const bool in = lane < j;
+            const double tr = in ? T[2 * lane] : 0.0, ti = in ? T[2 * lane + 1] : 0.0;
+            const double br = in ? Bv[2 * lane] : 0.0, bi = in ? Bv[2 * lane + 1] : 0.0;
+            const double xr = (br - tr) * ib, xi = (bi - ti) * ib;
+            const double tw = wave_sum(tr * br + ti * bi) + T[2 * j] * ur * ib + T[2 * j + 1] * ui * ib;
+            const double t2 = wave_sum(tr * tr + ti * ti) + T[2 * j] * T[2 * j] + T[2 * j + 1] * T[2 * j + 1];
+            const double h2 = wave_sum(xr * xr + xi * xi) + hr * hr + hi * hi;
             const double w2 = (cde[3] - 2.0 * tw + t2) * ib * ib;
-            double h2 = hr * hr + hi * hi;
-            for (int m = 0; m < j; ++m) {
-                const double xr = (Bv[2 * m] - T[2 * m]) * ib, xi = (Bv[2 * m + 1] - T[2 * m + 1]) * ib;
-                h2 += xr * xr + xi * xi;
+            if (writer && lane == 0) {
+                st->beta[j + 1] = sqrt(fmax(w2 - h2, 0.0));
+                st->keff = kdim;
             }
-            st->beta[j + 1] = sqrt(fmax(w2 - h2, 0.0));
-            st->keff = kdim;
+        }
+        if (lane == 0) {
+            if (writer) st->alpha[j] = hr;
+            cj[0] = ib;
+            cj[1] = T[2 * j] * ib;
+            cj[2] = T[2 * j + 1] * ib;
+            cj[3] = hr * ib;
+            cj[4] = hi * ib;
         }
     }
+    __syncthreads();
+    return true;
 }
 
 // Lanczos iteration j: update pass.  slot j <- u = u1 - sum_c a_c v_c; with v_j = u scale_j and
 // w = (w_raw - sum_{c<j} t_c v_c - t_j v_j) scale_j: slot j+1 <- w - sum_{c<j} h_c v_c - h_j v_j
 // (skipped after the last iteration).
 __global__ __launch_bounds__(kVecThreads) void k_dupdate(const VecProb* vp, const int* bmap, int j,
-                                                         int last) {
+                                                         int kdim, int nc0) {
     const Where W = locate(vp, bmap, 1);
-    const KState* st = W.p.st;
-    if (st->broken) return;
-    __shared__ double co[3][2 * kMaxKrylov];   // a_c, t_c, h_c times scale_c (c < j)
-    for (int c = threadIdx.x; c < j; c += blockDim.x) {
-        const double s = st->scale[c];
-        co[0][2 * c] = st->dela[2 * c] * s;
-        co[0][2 * c + 1] = st->dela[2 * c + 1] * s;
-        co[1][2 * c] = st->h2[2 * c] * s;
-        co[1][2 * c + 1] = st->h2[2 * c + 1] * s;
-        co[2][2 * c] = st->h1[2 * c] * s;
-        co[2][2 * c + 1] = st->h1[2 * c + 1] * s;
-    }
-    __syncthreads();
-    const double sj = st->scale[j];
-    const double tjr = st->h2[2 * j] * sj, tji = st->h2[2 * j + 1] * sj;
-    const double hjr = st->h1[2 * j] * sj, hji = st->h1[2 * j + 1] * sj;
+    KState* st = W.p.st;
+    if (((const int __attribute__((address_space(1)))*)&st->broken)[0]) return;
+    constexpr int G = 8;                       // basis slots loaded per round trip
+    const int j8 = (j + G - 1) / G * G;
+    __shared__ double co[3][2 * kMaxKrylov];
+    __shared__ double cj[5];
+    if (!iteration_coefficients(st, j, kdim, nc0, W.lb == 0, j8, co, cj)) return;
+    const bool last = j == kdim - 1;
+    const double sj = cj[0], tjr = cj[1], tji = cj[2], hjr = cj[3], hji = cj[4];
     double* __restrict__ uj = W.p.V + (int64_t)j * W.p.vstride;
     double* __restrict__ un = W.p.V + (int64_t)(j + 1) * W.p.vstride;
     const double* __restrict__ V = W.p.V;
@@ -444,21 +450,32 @@ __global__ __launch_bounds__(kVecThreads) void k_dupdate(const VecProb* vp, cons
     const int64_t n = W.p.n, vstride = W.p.vstride;
     const int64_t stride = (int64_t)W.nbt * blockDim.x;
     for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const double u0r = ldv(uj, i), u0i = ldv(uj, n + i), w0r = ldv(w, i), w0i = ldv(w, n + i);
         double ar = 0.0, ai = 0.0, tr = 0.0, ti = 0.0, hr = 0.0, hi = 0.0;
-#pragma unroll 4
-        for (int c = 0; c < j; ++c) {
-            const double* v = V + (int64_t)c * vstride;
-            const double vr = ldv(v, i), vi = ldv(v, n + i);
-            ar += co[0][2 * c] * vr - co[0][2 * c + 1] * vi;
-            ai += co[0][2 * c] * vi + co[0][2 * c + 1] * vr;
-            tr += co[1][2 * c] * vr - co[1][2 * c + 1] * vi;
-            ti += co[1][2 * c] * vi + co[1][2 * c + 1] * vr;
-            hr += co[2][2 * c] * vr - co[2][2 * c + 1] * vi;
-            hi += co[2][2 * c] * vi + co[2][2 * c + 1] * vr;
+        for (int c0 = 0; c0 < j; c0 += G) {
+            // G slots per round trip (slots past j - 1 re-read slot j - 1, zero coefficients)
+            double vr[G], vi[G];
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const double* v = V + (int64_t)min(c0 + k, j - 1) * vstride;
+                vr[k] = ldv(v, i);
+                vi[k] = ldv(v, n + i);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const int c = c0 + k;
+                ar += co[0][2 * c] * vr[k] - co[0][2 * c + 1] * vi[k];
+                ai += co[0][2 * c] * vi[k] + co[0][2 * c + 1] * vr[k];
+                tr += co[1][2 * c] * vr[k] - co[1][2 * c + 1] * vi[k];
+                ti += co[1][2 * c] * vi[k] + co[1][2 * c + 1] * vr[k];
+                hr += co[2][2 * c] * vr[k] - co[2][2 * c + 1] * vi[k];
+                hi += co[2][2 * c] * vi[k] + co[2][2 * c + 1] * vr[k];
+            }
         }
-        const double ur = uj[i] - ar, ui = uj[n + i] - ai;
-        const double wr = (w[i] - tr - (tjr * ur - tji * ui)) * sj;
-        const double wi = (w[n + i] - ti - (tjr * ui + tji * ur)) * sj;
+        const double ur = u0r - ar, ui = u0i - ai;
+        const double wr = (w0r - tr - (tjr * ur - tji * ui)) * sj;
+        const double wi = (w0i - ti - (tjr * ui + tji * ur)) * sj;
         uj[i] = ur;
         uj[n + i] = ui;
         if (!last) {
@@ -683,7 +700,7 @@ const auto kRedMore = red_table<false>(std::make_integer_sequence<int, kDSlots +
 
 // Runs Lanczos iteration j (after the block products of slot j) on every problem of the group.
 hipError_t launch_lanczos_iter(const VecGroup& g, int j, int kdim, hipStream_t s) {
-    const dim3 grid(g.nblk), gridr(g.nblkr), blk(kVecThreads), one(g.nprob);
+    const dim3 grid(g.nblk), gridr(g.nblkr), blk(kVecThreads);
     const int nq = j > kDSlots ? (j + kDSlots - 1) / kDSlots : 1;
     const int nc0 = min(j, kDSlots);
     hipLaunchKernelGGL(kRedFirst[nc0], gridr, blk, 0, s, g.vp, g.bmapr, j, 0, 0);
@@ -692,8 +709,7 @@ hipError_t launch_lanczos_iter(const VecGroup& g, int j, int kdim, hipStream_t s
         hipLaunchKernelGGL(kRedMore[nc], gridr, blk, 0, s, g.vp, g.bmapr, j, q * kDSlots, q);
     }
     hipLaunchKernelGGL(k_dsum, dim3(nq * kDVals / (kVecThreads / 64), g.nprob), blk, 0, s, g.vp);
-    hipLaunchKernelGGL(k_dfin, one, dim3(kFinThreads), 0, s, g.vp, j, kdim, nc0);
-    hipLaunchKernelGGL(k_dupdate, grid, blk, 0, s, g.vp, g.bmap, j, j == kdim - 1 ? 1 : 0);
+    hipLaunchKernelGGL(k_dupdate, grid, blk, 0, s, g.vp, g.bmap, j, kdim, nc0);
     return hipGetLastError();
 }
 
