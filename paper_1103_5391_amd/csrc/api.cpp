@@ -17,7 +17,7 @@
 
 namespace dmrg {
 
-hipError_t launch_stage1(int, const S1Block*, const Tile*, int, const ProbPtrs*, ProbPtrs,
+hipError_t launch_stage1(int, int, const S1Block*, const Tile*, int, const ProbPtrs*, ProbPtrs,
                          hipStream_t);
 hipError_t launch_stage2(int, const S2Block*, const Segment*, const Tile*, int, const ProbPtrs*,
                          ProbPtrs, hipStream_t);
@@ -63,8 +63,8 @@ struct DevBuf {
 // register-tiled kernels (gemm.hip), tile lists of the LDS-tiled kernels (gemm_lds.hip) and
 // their partial-tile workspace.
 struct Lists {
-    DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT2, dL1, dL2[2], dLred[2], dPart;
-    int nt1 = 0, nt2 = 0, nl1 = 0, nl2[2] = {0, 0}, nred[2] = {0, 0};
+    DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT1n, dT2, dL1, dL2[2], dLred[2], dPart;
+    int nt1 = 0, nt1n = 0, nt2 = 0, nl1 = 0, nl2[2] = {0, 0}, nred[2] = {0, 0};
     int variant = 0;    // DMRG_GEMM_* bits: which kernel family runs each stage
 };
 
@@ -82,7 +82,8 @@ hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
 // Uploads the work lists of one launch set; k indexes the chunk depth (0: 16, 1: 32).
 hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vector<S2Block>* s2,
                         const std::vector<Segment>* segs, const std::vector<Tile>& t1,
-                        const std::vector<Tile>& t2, const std::vector<LItem1>& l1,
+                        const std::vector<Tile>& t1n, const std::vector<Tile>& t2,
+                        const std::vector<LItem1>& l1,
                         const std::vector<LItem2>* l2, const std::vector<LRed>* lred,
                         const int* nslots, hipStream_t st) {
     hipError_t e = hipSuccess;
@@ -94,11 +95,13 @@ hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vec
         if (e == hipSuccess) e = upload(W.dLred[k], lred[k], st);
     }
     if (e == hipSuccess) e = upload(W.dT1, t1, st);
+    if (e == hipSuccess) e = upload(W.dT1n, t1n, st);
     if (e == hipSuccess) e = upload(W.dT2, t2, st);
     if (e == hipSuccess) e = upload(W.dL1, l1, st);
     const int slots = std::max(nslots[0], nslots[1]);
     if (e == hipSuccess) e = W.dPart.alloc(sizeof(double) * (size_t)slots * kLTile * kLTile);
     W.nt1 = (int)t1.size();
+    W.nt1n = (int)t1n.size();
     W.nt2 = (int)t2.size();
     W.nl1 = (int)l1.size();
     for (int k = 0; k < 2; ++k) {
@@ -117,7 +120,10 @@ hipError_t run_stage(const Lists& W, int stage, int variant, int prec, const Pro
         if (variant & DMRG_GEMM_STAGE1_LDS)
             return launch_stage1_lds(prec, W.dS1[pk].as<S1Block>(), W.dL1.as<LItem1>(), W.nl1,
                                      probs, single, s);
-        return launch_stage1(prec, W.dS1[pk].as<S1Block>(), W.dT1.as<Tile>(), W.nt1, probs,
+        if (variant & DMRG_GEMM_STAGE1_NARROW)
+            return launch_stage1(prec, 1, W.dS1[pk].as<S1Block>(), W.dT1n.as<Tile>(), W.nt1n,
+                                 probs, single, s);
+        return launch_stage1(prec, 0, W.dS1[pk].as<S1Block>(), W.dT1.as<Tile>(), W.nt1, probs,
                              single, s);
     }
     if (variant & DMRG_GEMM_STAGE2_LDS)
@@ -159,21 +165,30 @@ hipError_t time_stage(const Lists& W, int stage, int variant, int prec, const Pr
 
 // Autotuner of a launch set: each stage's kernel families timed in turn (stage 1 first, its
 // output feeds stage 2), the fastest kept.  out: NULL or [s1 register, s1 LDS, s2 register,
-// s2 LDS] ms.
+// s2 LDS, s1 register narrow] ms.
 hipError_t autotune_lists(Lists& W, int prec, const ProbPtrs* probs, ProbPtrs single,
                           hipStream_t s, int reps, double* out) {
-    double t[4];
+    const int cand[5] = {0, DMRG_GEMM_STAGE1_LDS, 0, DMRG_GEMM_STAGE2_LDS, DMRG_GEMM_STAGE1_NARROW};
+    const int stage[5] = {1, 1, 2, 2, 1};
+    double t[5];
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 4 && e == hipSuccess; ++i) {
-        const int stage = 1 + i / 2;
-        const int bit = stage == 1 ? DMRG_GEMM_STAGE1_LDS : DMRG_GEMM_STAGE2_LDS;
-        e = time_stage(W, stage, (i & 1) ? bit : 0, prec, probs, single, s, reps, &t[i]);
-    }
+    for (int i = 0; i < 5 && e == hipSuccess; ++i)
+        e = time_stage(W, stage[i], cand[i], prec, probs, single, s, reps, &t[i]);
     if (e != hipSuccess) return e;
-    W.variant = (t[1] < t[0] ? DMRG_GEMM_STAGE1_LDS : 0) | (t[3] < t[2] ? DMRG_GEMM_STAGE2_LDS : 0);
+    int s1 = 0;
+    if (t[4] < t[s1]) s1 = 4;
+    if (t[1] < t[s1]) s1 = 1;
+    W.variant = cand[s1] | (t[3] < t[2] ? DMRG_GEMM_STAGE2_LDS : 0);
     if (out)
-        for (int i = 0; i < 4; ++i) out[i] = t[i];
+        for (int i = 0; i < 5; ++i) out[i] = t[i];
     return hipSuccess;
+}
+
+// Whether a dmrg_gemm variant is valid: known bits, at most one stage-1 family.
+bool valid_variant(int32_t variant) {
+    constexpr int32_t known = DMRG_GEMM_STAGE1_LDS | DMRG_GEMM_STAGE2_LDS | DMRG_GEMM_STAGE1_NARROW;
+    if (variant & ~known) return false;
+    return !((variant & DMRG_GEMM_STAGE1_LDS) && (variant & DMRG_GEMM_STAGE1_NARROW));
 }
 
 // Device tables that run the Krylov passes of one handle, or of a batch of handles in common
@@ -491,7 +506,8 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
         const std::vector<LItem2> l2[2] = {P.pk16.l2, P.pk32.l2};
         const std::vector<LRed> lr[2] = {P.pk16.lred, P.pk32.lred};
         const int ns[2] = {P.pk16.nslots, P.pk32.nslots};
-        e = upload_lists(h->lists, s1, s2, sg, P.tiles1, P.tiles2, P.l1, l2, lr, ns, h->stream);
+        e = upload_lists(h->lists, s1, s2, sg, P.tiles1, P.tiles1n, P.tiles2, P.l1, l2, lr, ns,
+                         h->stream);
     }
     if (e == hipSuccess) e = h->dT.alloc(sizeof(double) * (size_t)P.T_size);
     // the padding rows of the stage-1 workspace are read (times zero factors) but never
@@ -651,7 +667,7 @@ int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out
         Merged M;
         merge_plans(plans, M);
         b->lists.variant = h0->lists.variant;
-        const hipError_t e = upload_lists(b->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles2, M.l1,
+        const hipError_t e = upload_lists(b->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles1n, M.tiles2, M.l1,
                                           M.l2, M.lred, M.nslots, h0->stream);
         if (e != hipSuccess) {
             delete b;
@@ -734,7 +750,7 @@ int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps,
 
 int dmrg_set_gemm(dmrg_handle h, int32_t variant) {
     if (!h) return DMRG_EINVAL;
-    if (variant & ~(DMRG_GEMM_STAGE1_LDS | DMRG_GEMM_STAGE2_LDS))
+    if (!valid_variant(variant))
         return fail(h, DMRG_EINVAL, "unknown kernel variant bits");
     h->lists.variant = variant;
     return DMRG_OK;
@@ -761,7 +777,7 @@ int dmrg_autotune(dmrg_handle h, int32_t reps, double* out) {
 
 int dmrg_batch_set_gemm(dmrg_batch b, int32_t variant) {
     if (!b) return DMRG_EINVAL;
-    if (variant & ~(DMRG_GEMM_STAGE1_LDS | DMRG_GEMM_STAGE2_LDS))
+    if (!valid_variant(variant))
         return fail(b->g.hs[0], DMRG_EINVAL, "unknown kernel variant bits");
     b->lists.variant = variant;
     return DMRG_OK;

@@ -12,7 +12,9 @@
 // symmetry blocks in two stages, each one launch over a list of output tiles:
 //   stage 1  T_b  = X_b R_b        right products, X_b = [Re; Im] planes of the source block
 //   stage 2  Y_b' = T0 + Acat Bcat left products summed over all terms entering the block
-// Stage 1 gives each wavefront its own 32 x 64 tile.  In stage 2 a work group of four
+// Stage 1 gives each tile of 32 x 64 (or 32 x 32: twice the tiles, for better balance on small
+// problems) to a work group of one wavefront (single-wave work groups let the dispatcher
+// balance the compute units at the end of the launch).  In stage 2 a work group of four
 // wavefronts owns one 32 x 32 tile and deals its K chunks round-robin to the waves; the four
 // partial tiles are summed in LDS in a fixed order (deterministic, no atomics).
 //
@@ -26,10 +28,10 @@
 namespace dmrg {
 
 // ---------------------------------------------------------------------------------------
-// stage 1: one 32 x 64 tile per wavefront
+// stage 1: one 32 x 16 NJ tile (NJ = 4 wide, 2 narrow) per single-wavefront work group
 // ---------------------------------------------------------------------------------------
-template <class P>
-__global__ __launch_bounds__(256, 3) void stage1(const S1Block* __restrict__ blks,
+template <class P, int NJ>
+__global__ __launch_bounds__(64, 3) void stage1(const S1Block* __restrict__ blks,
                                                  const Tile* __restrict__ tiles, int ntiles,
                                                  const ProbPtrs* __restrict__ probs,
                                                  ProbPtrs single) {
@@ -37,10 +39,8 @@ __global__ __launch_bounds__(256, 3) void stage1(const S1Block* __restrict__ blk
     using ws_t = typename P::ws_t;
     using acc_t = typename P::acc_t;
     using frag_t = typename P::frag_t;
-    constexpr int NJ = kTile1N / 16;
-    const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
-    const int ti = blockIdx.x * kWaves + wave;
+    const int lane = threadIdx.x;
+    const int ti = blockIdx.x;
     if (ti >= ntiles) return;
     const Tile tl = tiles[ti];
     if (tl.blk < 0) return;   // padding of the XCD-ordered list
@@ -305,11 +305,15 @@ __global__ __launch_bounds__(256, 3) void stage2(const S2Block* __restrict__ blk
 namespace {
 
 template <class P>
-hipError_t launch1(const S1Block* blks, const Tile* tiles, int ntiles, const ProbPtrs* probs,
-                   ProbPtrs single, hipStream_t st) {
+hipError_t launch1(int narrow, const S1Block* blks, const Tile* tiles, int ntiles,
+                   const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
-    const int nblk = (ntiles + kWaves - 1) / kWaves;
-    hipLaunchKernelGGL(stage1<P>, dim3(nblk), dim3(256), 0, st, blks, tiles, ntiles, probs, single);
+    if (narrow)
+        hipLaunchKernelGGL((stage1<P, kTile1NN / 16>), dim3(ntiles), dim3(64), 0, st, blks, tiles,
+                           ntiles, probs, single);
+    else
+        hipLaunchKernelGGL((stage1<P, kTile1N / 16>), dim3(ntiles), dim3(64), 0, st, blks, tiles,
+                           ntiles, probs, single);
     return hipGetLastError();
 }
 
@@ -323,14 +327,15 @@ hipError_t launch2(const S2Block* blks, const Segment* segs, const Tile* tiles, 
 
 }  // namespace
 
-// prec: 0 FP64, 1 FP32, 2 BF16x3, 3 BF16x6 (the operator buffers and workspace must match)
-hipError_t launch_stage1(int prec, const S1Block* blks, const Tile* tiles, int ntiles,
+// prec: 0 FP64, 1 FP32, 2 BF16x3, 3 BF16x6 (the operator buffers and workspace must match);
+// narrow: the tiles are kTile x kTile1NN (else kTile x kTile1N)
+hipError_t launch_stage1(int prec, int narrow, const S1Block* blks, const Tile* tiles, int ntiles,
                          const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
     switch (prec) {
-        case 0: return launch1<PF64>(blks, tiles, ntiles, probs, single, st);
-        case 1: return launch1<PF32>(blks, tiles, ntiles, probs, single, st);
-        case 2: return launch1<PBF3>(blks, tiles, ntiles, probs, single, st);
-        default: return launch1<PBF6>(blks, tiles, ntiles, probs, single, st);
+        case 0: return launch1<PF64>(narrow, blks, tiles, ntiles, probs, single, st);
+        case 1: return launch1<PF32>(narrow, blks, tiles, ntiles, probs, single, st);
+        case 2: return launch1<PBF3>(narrow, blks, tiles, ntiles, probs, single, st);
+        default: return launch1<PBF6>(narrow, blks, tiles, ntiles, probs, single, st);
     }
 }
 

@@ -262,6 +262,7 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
         toff += (int64_t)2 * dpad * N;
         P.flops1 += 2.0 * (2 * B.d) * (double)B.e * N;
         tile_list(P.tiles1, bi, 2 * B.d, N, kTile, kTile1N);
+        tile_list(P.tiles1n, bi, 2 * B.d, N, kTile, kTile1NN);
     }
     P.T_size = toff;
     std::vector<int> kcat(nb);
@@ -337,7 +338,8 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
         w1[bi] = nt1 * ((B.e + 15) / 16 + 1);
         w2[bi] = nt2 * ((kcat[bi] + 15) / 16 + 2);
     }
-    P.tiles1 = xcd_order(P.tiles1, w1, kWaves);
+    P.tiles1 = xcd_order(P.tiles1, w1, 1);
+    P.tiles1n = xcd_order(P.tiles1n, w1, 1);
     P.tiles2 = xcd_order(P.tiles2, w2, 1);
     P.w1 = std::move(w1);
     P.w2 = std::move(w2);
@@ -393,7 +395,7 @@ void lds_lists(Plan& P) {
 
 void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
     out = Merged{};
-    std::vector<Tile> t1, t2;
+    std::vector<Tile> t1, t1n, t2;
     std::vector<double> w1, w2;
     std::vector<LItem1> l1;
     std::vector<LItem2> l2[2];
@@ -416,6 +418,8 @@ void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
         }
         for (Tile t : P.tiles1)
             if (t.blk >= 0) t1.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
+        for (Tile t : P.tiles1n)
+            if (t.blk >= 0) t1n.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
         for (Tile t : P.tiles2)
             if (t.blk >= 0) t2.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
         w1.insert(w1.end(), P.w1.begin(), P.w1.end());
@@ -442,7 +446,8 @@ void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
         }
         boff += (int)P.blocks.size();
     }
-    out.tiles1 = xcd_order(t1, w1, kWaves);
+    out.tiles1 = xcd_order(t1, w1, 1);
+    out.tiles1n = xcd_order(t1n, w1, 1);
     out.tiles2 = xcd_order(t2, w2, 1);
     // the LDS lists keep each problem's block order: weights by tiles of the merged lists
     std::vector<double> wl(boff, 0.0);

@@ -94,8 +94,9 @@ def test_layout_matches_oracle(env):
         h.destroy()
 
 
-GEMM_VARIANTS = pytest.mark.parametrize("variant", [0, 1, 2, 3],
-                                        ids=["reg-reg", "lds-reg", "reg-lds", "lds-lds"])
+GEMM_VARIANTS = pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 6],
+                                        ids=["reg-reg", "lds-reg", "reg-lds", "lds-lds",
+                                             "narrow-reg", "narrow-lds"])
 
 
 @GEMM_VARIANTS
@@ -515,19 +516,23 @@ def test_autotune_and_variants_agree(env, prec):
     h.set_precision(prec)
     t = h.autotune(reps=3)
     say("  ", t)
-    assert all(t[k] > 0 for k in ("stage1_register", "stage1_lds", "stage2_register", "stage2_lds"))
-    want = (L.DMRG_GEMM_STAGE1_LDS if t["stage1_lds"] < t["stage1_register"] else 0) | \
-           (L.DMRG_GEMM_STAGE2_LDS if t["stage2_lds"] < t["stage2_register"] else 0)
+    assert all(t[k] > 0 for k in ("stage1_register", "stage1_lds", "stage2_register", "stage2_lds",
+                                  "stage1_narrow"))
+    s1 = min([(t["stage1_register"], 0), (t["stage1_narrow"], L.DMRG_GEMM_STAGE1_NARROW),
+              (t["stage1_lds"], L.DMRG_GEMM_STAGE1_LDS)], key=lambda p: p[0])[1]
+    want = s1 | (L.DMRG_GEMM_STAGE2_LDS if t["stage2_lds"] < t["stage2_register"] else 0)
     assert t["variant"] == want
     x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 91))
     xd = _dev(torch, x)
     yref = M.matvec_sector(pb, x)
     tol = MV_TOL if prec == 0 else MIXED_TOL[prec]
-    for v in range(4):
+    for v in (0, 1, 2, 3, 4, 6):
         h.set_gemm(v)
         yd = torch.empty_like(xd)
         h.matvec(xd, yd)
         err = rel(_host(yd), yref)
         say("  variant", v, err)
         assert err <= tol
+    with pytest.raises(L.DmrgError):
+        h.set_gemm(L.DMRG_GEMM_STAGE1_LDS | L.DMRG_GEMM_STAGE1_NARROW)
     h.destroy()
