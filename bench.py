@@ -41,7 +41,19 @@ MEASURED_TRAFFIC = {
 }
 
 
-def measured_traffic(workload: str):
+def kernel_name(stage: int, variant: int) -> str:
+    """Name of the FP64 kernel that runs a stage under a dmrg_gemm variant (as profilers show it,
+    without the namespace)."""
+    if stage == 1:
+        if variant & 1:
+            return "stage1_lds<PF64>"
+        return "stage1<PF64, 2>" if variant & 4 else "stage1<PF64, 4>"
+    if variant & 2:
+        return "stage2_lds<PF64>"
+    return "stage2<PF64, 1, 4>" if variant & 8 else "stage2<PF64, 2, 4>"
+
+
+def measured_traffic(workload: str, kernel: str):
     import hashlib
     src = os.path.join(os.path.dirname(os.path.abspath(__file__)), MEASURED_TRAFFIC["source"])
     try:
@@ -49,7 +61,8 @@ def measured_traffic(workload: str):
             sha = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if sha != MEASURED_TRAFFIC["source_sha256"] or workload != MEASURED_TRAFFIC["workload"]:
+    if (sha != MEASURED_TRAFFIC["source_sha256"] or workload != MEASURED_TRAFFIC["workload"]
+            or kernel != MEASURED_TRAFFIC["kernel"]):
         return None
     return MEASURED_TRAFFIC["bytes"]
 
@@ -289,10 +302,10 @@ def main():
         "mfma_peak_frac_step": round(value / PEAK_FP64_TFLOPS, 4),
         "mixed_precision": mixed,
         "batched_64": batched,
-        "roofline": {"bound": "mfma", "kernel": f"stage{dom}<PF64>",
+        "roofline": {"bound": "mfma", "kernel": kernel_name(dom, int(tune64["variant"])),
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
-                     "traffic": measured_traffic(args.workload) if dom == 2 else None,
+                     "traffic": measured_traffic(args.workload, kernel_name(dom, int(tune64["variant"]))),
                      "traffic_unit": "bytes per launch",
                      "algorithmic_flop_per_launch": fl_dom,
                      "ms_per_launch": round(ms_dom, 5)},

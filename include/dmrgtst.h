@@ -76,15 +76,17 @@ enum dmrg_precision {
 
 /* Kernel families of the two block-product stages (bits of a variant).  Without the bits a stage
  * runs register-tiled (stage 1: a 32 x 64 tile per single-wavefront work group; stage 2: a
- * 32 x 32 tile per work group whose K chunks are dealt to its four wavefronts).  STAGE1_NARROW:
- * stage 1 register-tiled with 32 x 32 tiles (twice as many, for balance on small problems).
+ * 32 x 32 tile per work group whose K chunks are dealt to its four wavefronts).  STAGE1_NARROW,
+ * STAGE2_NARROW: register-tiled with tiles half as wide (stage 1: 32 x 32, stage 2: 32 x 16;
+ * twice as many tiles, for balance on small problems).
  * STAGE1_LDS / STAGE2_LDS: LDS-tiled (64 x 64 tiles per work group, four wavefronts sharing
  * every K chunk through LDS; stage 2 splits long K into slices summed by a reduction launch).
- * STAGE1_NARROW and STAGE1_LDS exclude each other.  Results agree to rounding. */
+ * The NARROW and LDS bits of one stage exclude each other.  Results agree to rounding. */
 enum dmrg_gemm {
     DMRG_GEMM_STAGE1_LDS = 1,
     DMRG_GEMM_STAGE2_LDS = 2,
-    DMRG_GEMM_STAGE1_NARROW = 4
+    DMRG_GEMM_STAGE1_NARROW = 4,
+    DMRG_GEMM_STAGE2_NARROW = 8
 };
 
 /* A block operator of one half that changes (N_up, N_dn) by dq.  blocks: for every source
@@ -174,15 +176,15 @@ int dmrg_flops(dmrg_handle h, double* flops);
 int dmrg_set_precision(dmrg_handle h, int32_t precision);
 
 /* Selects the kernel families (dmrg_gemm bits; both register-tiled after dmrg_create).  DMRG_EINVAL
- * for unknown bits or both stage-1 bits. */
+ * for unknown bits or two families for one stage. */
 int dmrg_set_gemm(dmrg_handle h, int32_t variant);
 int dmrg_get_gemm(dmrg_handle h, int32_t* variant);
 
 /* Autotuner: times the kernel families of each stage on the handle's problem in its current
  * arithmetic (reps back-to-back launches each, on zeroed scratch vectors the handle owns) and
- * keeps the fastest of each.  out: NULL or 5 doubles receiving milliseconds per launch of
+ * keeps the fastest of each.  out: NULL or 6 doubles receiving milliseconds per launch of
  * [stage 1 register-tiled, stage 1 LDS-tiled, stage 2 register-tiled, stage 2 LDS-tiled,
- *  stage 1 register-tiled narrow].
+ *  stage 1 register-tiled narrow, stage 2 register-tiled narrow].
  * Waits for the handle's stream. */
 int dmrg_autotune(dmrg_handle h, int32_t reps, double* out);
 

@@ -19,8 +19,8 @@ namespace dmrg {
 
 hipError_t launch_stage1(int, int, const S1Block*, const Tile*, int, const ProbPtrs*, ProbPtrs,
                          hipStream_t);
-hipError_t launch_stage2(int, const S2Block*, const Segment*, const Tile*, int, const ProbPtrs*,
-                         ProbPtrs, hipStream_t);
+hipError_t launch_stage2(int, int, const S2Block*, const Segment*, const Tile*, int,
+                         const ProbPtrs*, ProbPtrs, hipStream_t);
 hipError_t launch_stage1_lds(int, const S1Block*, const LItem1*, int, const ProbPtrs*, ProbPtrs,
                              hipStream_t);
 hipError_t launch_stage2_lds(int, const S2Block*, const Segment*, const LItem2*, int, const LRed*,
@@ -63,8 +63,8 @@ struct DevBuf {
 // register-tiled kernels (gemm.hip), tile lists of the LDS-tiled kernels (gemm_lds.hip) and
 // their partial-tile workspace.
 struct Lists {
-    DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT1n, dT2, dL1, dL2[2], dLred[2], dPart;
-    int nt1 = 0, nt1n = 0, nt2 = 0, nl1 = 0, nl2[2] = {0, 0}, nred[2] = {0, 0};
+    DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT1n, dT2, dT2n, dL1, dL2[2], dLred[2], dPart;
+    int nt1 = 0, nt1n = 0, nt2 = 0, nt2n = 0, nl1 = 0, nl2[2] = {0, 0}, nred[2] = {0, 0};
     int variant = 0;    // DMRG_GEMM_* bits: which kernel family runs each stage
 };
 
@@ -83,7 +83,7 @@ hipError_t upload(DevBuf& b, const std::vector<T>& v, hipStream_t s) {
 hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vector<S2Block>* s2,
                         const std::vector<Segment>* segs, const std::vector<Tile>& t1,
                         const std::vector<Tile>& t1n, const std::vector<Tile>& t2,
-                        const std::vector<LItem1>& l1,
+                        const std::vector<Tile>& t2n, const std::vector<LItem1>& l1,
                         const std::vector<LItem2>* l2, const std::vector<LRed>* lred,
                         const int* nslots, hipStream_t st) {
     hipError_t e = hipSuccess;
@@ -97,12 +97,14 @@ hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vec
     if (e == hipSuccess) e = upload(W.dT1, t1, st);
     if (e == hipSuccess) e = upload(W.dT1n, t1n, st);
     if (e == hipSuccess) e = upload(W.dT2, t2, st);
+    if (e == hipSuccess) e = upload(W.dT2n, t2n, st);
     if (e == hipSuccess) e = upload(W.dL1, l1, st);
     const int slots = std::max(nslots[0], nslots[1]);
     if (e == hipSuccess) e = W.dPart.alloc(sizeof(double) * (size_t)slots * kLTile * kLTile);
     W.nt1 = (int)t1.size();
     W.nt1n = (int)t1n.size();
     W.nt2 = (int)t2.size();
+    W.nt2n = (int)t2n.size();
     W.nl1 = (int)l1.size();
     for (int k = 0; k < 2; ++k) {
         W.nl2[k] = (int)l2[k].size();
@@ -130,7 +132,10 @@ hipError_t run_stage(const Lists& W, int stage, int variant, int prec, const Pro
         return launch_stage2_lds(prec, W.dS2[pk].as<S2Block>(), W.dSeg[pk].as<Segment>(),
                                  W.dL2[pk].as<LItem2>(), W.nl2[pk], W.dLred[pk].as<LRed>(),
                                  W.nred[pk], probs, single, W.dPart.as<double>(), s);
-    return launch_stage2(prec, W.dS2[pk].as<S2Block>(), W.dSeg[pk].as<Segment>(),
+    if (variant & DMRG_GEMM_STAGE2_NARROW)
+        return launch_stage2(prec, 1, W.dS2[pk].as<S2Block>(), W.dSeg[pk].as<Segment>(),
+                             W.dT2n.as<Tile>(), W.nt2n, probs, single, s);
+    return launch_stage2(prec, 0, W.dS2[pk].as<S2Block>(), W.dSeg[pk].as<Segment>(),
                          W.dT2.as<Tile>(), W.nt2, probs, single, s);
 }
 
@@ -165,30 +170,34 @@ hipError_t time_stage(const Lists& W, int stage, int variant, int prec, const Pr
 
 // Autotuner of a launch set: each stage's kernel families timed in turn (stage 1 first, its
 // output feeds stage 2), the fastest kept.  out: NULL or [s1 register, s1 LDS, s2 register,
-// s2 LDS, s1 register narrow] ms.
+// s2 LDS, s1 register narrow, s2 register narrow] ms.
 hipError_t autotune_lists(Lists& W, int prec, const ProbPtrs* probs, ProbPtrs single,
                           hipStream_t s, int reps, double* out) {
-    const int cand[5] = {0, DMRG_GEMM_STAGE1_LDS, 0, DMRG_GEMM_STAGE2_LDS, DMRG_GEMM_STAGE1_NARROW};
-    const int stage[5] = {1, 1, 2, 2, 1};
-    double t[5];
+    constexpr int kCand = 6;
+    const int cand[kCand] = {0, DMRG_GEMM_STAGE1_LDS, 0, DMRG_GEMM_STAGE2_LDS,
+                             DMRG_GEMM_STAGE1_NARROW, DMRG_GEMM_STAGE2_NARROW};
+    const int stage[kCand] = {1, 1, 2, 2, 1, 2};
+    double t[kCand];
     hipError_t e = hipSuccess;
-    for (int i = 0; i < 5 && e == hipSuccess; ++i)
+    for (int i = 0; i < kCand && e == hipSuccess; ++i)
         e = time_stage(W, stage[i], cand[i], prec, probs, single, s, reps, &t[i]);
     if (e != hipSuccess) return e;
-    int s1 = 0;
-    if (t[4] < t[s1]) s1 = 4;
-    if (t[1] < t[s1]) s1 = 1;
-    W.variant = cand[s1] | (t[3] < t[2] ? DMRG_GEMM_STAGE2_LDS : 0);
+    int best[2] = {0, 2};   // fastest candidate of each stage (ties keep the register-tiled one)
+    for (int i = 0; i < kCand; ++i)
+        if (t[i] < t[best[stage[i] - 1]]) best[stage[i] - 1] = i;
+    W.variant = cand[best[0]] | cand[best[1]];
     if (out)
-        for (int i = 0; i < 5; ++i) out[i] = t[i];
+        for (int i = 0; i < kCand; ++i) out[i] = t[i];
     return hipSuccess;
 }
 
-// Whether a dmrg_gemm variant is valid: known bits, at most one stage-1 family.
+// Whether a dmrg_gemm variant is valid: known bits, at most one family per stage.
 bool valid_variant(int32_t variant) {
-    constexpr int32_t known = DMRG_GEMM_STAGE1_LDS | DMRG_GEMM_STAGE2_LDS | DMRG_GEMM_STAGE1_NARROW;
+    constexpr int32_t known = DMRG_GEMM_STAGE1_LDS | DMRG_GEMM_STAGE2_LDS |
+                              DMRG_GEMM_STAGE1_NARROW | DMRG_GEMM_STAGE2_NARROW;
     if (variant & ~known) return false;
-    return !((variant & DMRG_GEMM_STAGE1_LDS) && (variant & DMRG_GEMM_STAGE1_NARROW));
+    if ((variant & DMRG_GEMM_STAGE1_LDS) && (variant & DMRG_GEMM_STAGE1_NARROW)) return false;
+    return !((variant & DMRG_GEMM_STAGE2_LDS) && (variant & DMRG_GEMM_STAGE2_NARROW));
 }
 
 // Device tables that run the Krylov passes of one handle, or of a batch of handles in common
@@ -506,7 +515,8 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
         const std::vector<LItem2> l2[2] = {P.pk16.l2, P.pk32.l2};
         const std::vector<LRed> lr[2] = {P.pk16.lred, P.pk32.lred};
         const int ns[2] = {P.pk16.nslots, P.pk32.nslots};
-        e = upload_lists(h->lists, s1, s2, sg, P.tiles1, P.tiles1n, P.tiles2, P.l1, l2, lr, ns,
+        e = upload_lists(h->lists, s1, s2, sg, P.tiles1, P.tiles1n, P.tiles2, P.tiles2n, P.l1, l2,
+                         lr, ns,
                          h->stream);
     }
     if (e == hipSuccess) e = h->dT.alloc(sizeof(double) * (size_t)P.T_size);
@@ -667,7 +677,8 @@ int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out
         Merged M;
         merge_plans(plans, M);
         b->lists.variant = h0->lists.variant;
-        const hipError_t e = upload_lists(b->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles1n, M.tiles2, M.l1,
+        const hipError_t e = upload_lists(b->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles1n, M.tiles2,
+                                          M.tiles2n, M.l1,
                                           M.l2, M.lred, M.nslots, h0->stream);
         if (e != hipSuccess) {
             delete b;

@@ -15,8 +15,8 @@
 // Stage 1 gives each tile of 32 x 64 (or 32 x 32: twice the tiles, for better balance on small
 // problems) to a work group of one wavefront (single-wave work groups let the dispatcher
 // balance the compute units at the end of the launch).  In stage 2 a work group of four
-// wavefronts owns one 32 x 32 tile and deals its K chunks round-robin to the waves; the four
-// partial tiles are summed in LDS in a fixed order (deterministic, no atomics).
+// wavefronts owns one 32 x 32 tile (or 32 x 16, narrow) and deals its K chunks round-robin to the
+// waves; the four partial tiles are summed in LDS in a fixed order (deterministic, no atomics).
 //
 // The operator factors are packed in MFMA lane order (mfma.hpp) and zero-padded so no operator
 // load needs a bounds check.  The data operands are read in place: rows (stage 1) or columns
@@ -120,21 +120,21 @@ __global__ __launch_bounds__(64, 3) void stage1(const S1Block* __restrict__ blks
 }
 
 // ---------------------------------------------------------------------------------------
-// stage 2: one 32 x 32 tile per work group, K chunks dealt round-robin to the four waves
+// stage 2: one 32 x 32 (or 32 x 16) tile per work group, K chunks dealt round-robin to its waves
 // ---------------------------------------------------------------------------------------
 constexpr int kChunkTab = 256;   // workspace chunks of a block addressed through the LDS table
-template <class P, class Load>
-__device__ __forceinline__ void kloop(typename P::acc_t (&acc)[2][2], int c0, int step, int nch,
+template <class P, int NJ, class Load>
+__device__ __forceinline__ void kloop(typename P::acc_t (&acc)[2][NJ], int c0, int step, int nch,
                                       Load load) {
     using frag_t = typename P::frag_t;
     if (c0 >= nch) return;
     const int last = c0 + (nch - 1 - c0) / step * step;
-    frag_t a0[2], b0[2], a1[2], b1[2];
-    auto mma = [&](const frag_t (&fa)[2], const frag_t (&fb)[2]) {
+    frag_t a0[2], b0[NJ], a1[2], b1[NJ];
+    auto mma = [&](const frag_t (&fa)[2], const frag_t (&fb)[NJ]) {
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int nj = 0; nj < 2; ++nj) acc[mi][nj] = P::mma(fa[mi], fb[nj], acc[mi][nj]);
+            for (int nj = 0; nj < NJ; ++nj) acc[mi][nj] = P::mma(fa[mi], fb[nj], acc[mi][nj]);
     };
     // unconditional (clamped) prefetch, as in stage 1
     load(c0, a0, b0);
@@ -148,16 +148,18 @@ __device__ __forceinline__ void kloop(typename P::acc_t (&acc)[2][2], int c0, in
     }
 }
 
-template <class P>
-__global__ __launch_bounds__(256, 3) void stage2(const S2Block* __restrict__ blks,
-                                                 const Segment* __restrict__ segs,
-                                                 const Tile* __restrict__ tiles,
-                                                 const ProbPtrs* __restrict__ probs,
-                                                 ProbPtrs single) {
+// One 32 x 16 NJ output tile per work group of NW wavefronts (K chunks dealt round-robin).
+template <class P, int NJ, int NW>
+__global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__ blks,
+                                                     const Segment* __restrict__ segs,
+                                                     const Tile* __restrict__ tiles,
+                                                     const ProbPtrs* __restrict__ probs,
+                                                     ProbPtrs single) {
     using op_t = typename P::op_t;
     using ws_t = typename P::ws_t;
     using acc_t = typename P::acc_t;
     using frag_t = typename P::frag_t;
+    constexpr int TN = 16 * NJ;
     const Tile tl = tiles[blockIdx.x];
     if (tl.blk < 0) return;   // padding of the XCD-ordered list
     const S2Block B = blks[tl.blk];
@@ -171,52 +173,55 @@ __global__ __launch_bounds__(256, 3) void stage2(const S2Block* __restrict__ blk
     const ws_t* __restrict__ Tws = static_cast<const ws_t*>(P_.T);
 
     const op_t* pa[2];
-    int pl[2], col[2];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
         const int pnl = tl.m0 / kPanel + i;
         pa[i] = static_cast<const op_t*>(P_.Lops) + B.Aoff * P::PER +
                 (((int64_t)pnl * B.nch) * 4 + g) * (kPanel * lane_elems<P>()) + r * lane_elems<P>();
-        const int n = min(tl.n0 + 16 * i + r, B.N - 1);
-        pl[i] = n >= split;
-        col[i] = n - pl[i] * split;
     }
-    acc_t acc[2][2];
+    int pl[NJ], col[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int n = min(tl.n0 + 16 * j + r, B.N - 1);
+        pl[j] = n >= split;
+        col[j] = n - pl[j] * split;
+    }
+    acc_t acc[2][NJ];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int nj = 0; nj < 2; ++nj) zero<P>(acc[mi][nj]);
+        for (int nj = 0; nj < NJ; ++nj) zero<P>(acc[mi][nj]);
     // pass 1: segment 0, the diagonal H_S term, reads the block itself from the input vector;
     // its scale is applied before anything else adds in
     const Segment s0 = segs[B.seg0];
     const int nch0 = (s0.K + P::CK - 1) / P::CK;
     {
-        int64_t bcol[2];
+        int64_t bcol[NJ];
 #pragma unroll
-        for (int i = 0; i < 2; ++i)
-            bcol[i] = s0.B.off + pl[i] * s0.B.poff + (int64_t)col[i] * s0.B.ld;
-        auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[2]) {
+        for (int j = 0; j < NJ; ++j)
+            bcol[j] = s0.B.off + pl[j] * s0.B.poff + (int64_t)col[j] * s0.B.ld;
+        auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[NJ]) {
             const int64_t ga = (int64_t)c * chunk_elems<P>();
 #pragma unroll
             for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
             const int kb = c * P::CK + P::KPL * g;
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int j = 0; j < NJ; ++j) {
                 double v[P::KPL];
-                load_clamped<P>(P_.x, bcol[i], kb, s0.K, 1, v);
-                fb[i] = P::from(v);
+                load_clamped<P>(P_.x, bcol[j], kb, s0.K, 1, v);
+                fb[j] = P::from(v);
             }
         };
-        kloop<P>(acc, wave, kWaves, nch0, load);
+        kloop<P, NJ>(acc, wave, NW, nch0, load);
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-            for (int nj = 0; nj < 2; ++nj)
+            for (int nj = 0; nj < NJ; ++nj)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) acc[mi][nj][v] *= xs;
     }
     // pass 2: every workspace chunk of segments 1.. in one pipelined stream per wave (global
-    // chunk c goes to wave c mod 4), its source view read from a per-chunk table in LDS (built
+    // chunk c goes to wave c mod NW), its source view read from a per-chunk table in LDS (built
     // once per work group) instead of restarting the pipeline at every segment
     __shared__ int64_t ctab[kChunkTab][3];   // per workspace chunk: off - ch0 CK, poff, ld
     const int nT = B.nch - nch0;
@@ -231,53 +236,53 @@ __global__ __launch_bounds__(256, 3) void stage2(const S2Block* __restrict__ blk
             ctab[t][2] = sg.B.ld;
         }
         __syncthreads();
-        auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[2]) {
+        auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[NJ]) {
             const int64_t ga = (int64_t)c * chunk_elems<P>();
 #pragma unroll
             for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
             const int64_t* e = ctab[c - nch0];
             const int64_t kb = (int64_t)c * P::CK + P::KPL * g;
 #pragma unroll
-            for (int i = 0; i < 2; ++i) {
+            for (int j = 0; j < NJ; ++j) {
                 double v[P::KPL];
-                load_run<P>(Tws, e[0] + pl[i] * e[1] + (int64_t)col[i] * e[2] + kb, v);
-                fb[i] = P::from(v);
+                load_run<P>(Tws, e[0] + pl[j] * e[1] + (int64_t)col[j] * e[2] + kb, v);
+                fb[j] = P::from(v);
             }
         };
         // first chunk >= nch0 owned by this wave
-        const int cw = nch0 + ((wave - nch0) % kWaves + kWaves) % kWaves;
-        kloop<P>(acc, cw, kWaves, B.nch, load);
+        const int cw = nch0 + ((wave - nch0) % NW + NW) % NW;
+        kloop<P, NJ>(acc, cw, NW, B.nch, load);
     } else {
         // very long K: one pipeline per segment
         for (int s = 1; s < B.nseg; ++s) {
             const Segment sg = segs[B.seg0 + s];
-            int64_t bcol[2];
+            int64_t bcol[NJ];
 #pragma unroll
-            for (int i = 0; i < 2; ++i)
-                bcol[i] = sg.B.off + pl[i] * sg.B.poff + (int64_t)col[i] * sg.B.ld;
+            for (int j = 0; j < NJ; ++j)
+                bcol[j] = sg.B.off + pl[j] * sg.B.poff + (int64_t)col[j] * sg.B.ld;
             const int nch = (sg.K + P::CK - 1) / P::CK;
-            const int c0 = ((wave - sg.ch0) % kWaves + kWaves) % kWaves;
-            auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[2]) {
+            const int c0 = ((wave - sg.ch0) % NW + NW) % NW;
+            auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[NJ]) {
                 const int64_t ga = (int64_t)(sg.ch0 + c) * chunk_elems<P>();
 #pragma unroll
                 for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
                 const int kb = c * P::CK + P::KPL * g;
 #pragma unroll
-                for (int i = 0; i < 2; ++i) {
+                for (int j = 0; j < NJ; ++j) {
                     double v[P::KPL];
-                    load_run<P>(Tws, bcol[i] + kb, v);
-                    fb[i] = P::from(v);
+                    load_run<P>(Tws, bcol[j] + kb, v);
+                    fb[j] = P::from(v);
                 }
             };
-            kloop<P>(acc, c0, kWaves, nch, load);
+            kloop<P, NJ>(acc, c0, NW, nch, load);
         }
     }
 
-    __shared__ double red[kWaves][kTile][kTile + 1];
+    __shared__ double red[NW][TN][kTile + 1];
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
-        for (int nj = 0; nj < 2; ++nj)
+        for (int nj = 0; nj < NJ; ++nj)
 #pragma unroll
             for (int v = 0; v < 4; ++v)
                 red[wave][16 * nj + r][16 * mi + P::row(g, v)] = (double)acc[mi][nj][v];
@@ -285,12 +290,15 @@ __global__ __launch_bounds__(256, 3) void stage2(const S2Block* __restrict__ blk
     double* __restrict__ Y = P_.y;
     const View t0 = B.T0, yv = B.Y;
     const int m = threadIdx.x & 31;
+    constexpr int kCols = 2 * NW;   // columns handled per pass of the work group
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int n = (threadIdx.x >> 5) + 8 * q;
+    for (int q = 0; q < TN / kCols; ++q) {
+        const int n = (threadIdx.x >> 5) + kCols * q;
         const int gm = tl.m0 + m, gn = tl.n0 + n;
         if (gm < B.M && gn < B.N) {
-            const double v = ((red[0][n][m] + red[1][n][m]) + red[2][n][m]) + red[3][n][m];
+            double v = red[0][n][m];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) v += red[w][n][m];
             const int p = gn >= split;
             const int c = gn - p * split;
             const double init = (double)Tws[t0.off + p * t0.poff + (int64_t)c * t0.ld + gm];
@@ -318,10 +326,15 @@ hipError_t launch1(int narrow, const S1Block* blks, const Tile* tiles, int ntile
 }
 
 template <class P>
-hipError_t launch2(const S2Block* blks, const Segment* segs, const Tile* tiles, int ntiles,
-                   const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
+hipError_t launch2(int narrow, const S2Block* blks, const Segment* segs, const Tile* tiles,
+                   int ntiles, const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL(stage2<P>, dim3(ntiles), dim3(256), 0, st, blks, segs, tiles, probs, single);
+    if (narrow)
+        hipLaunchKernelGGL((stage2<P, kTile2NN / 16, kWaves>), dim3(ntiles), dim3(64 * kWaves), 0,
+                           st, blks, segs, tiles, probs, single);
+    else
+        hipLaunchKernelGGL((stage2<P, kTile / 16, kWaves>), dim3(ntiles), dim3(64 * kWaves), 0, st,
+                           blks, segs, tiles, probs, single);
     return hipGetLastError();
 }
 
@@ -339,13 +352,15 @@ hipError_t launch_stage1(int prec, int narrow, const S1Block* blks, const Tile* 
     }
 }
 
-hipError_t launch_stage2(int prec, const S2Block* blks, const Segment* segs, const Tile* tiles,
-                         int ntiles, const ProbPtrs* probs, ProbPtrs single, hipStream_t st) {
+// narrow: the tiles are kTile x kTile2NN (else kTile x kTile)
+hipError_t launch_stage2(int prec, int narrow, const S2Block* blks, const Segment* segs,
+                         const Tile* tiles, int ntiles, const ProbPtrs* probs, ProbPtrs single,
+                         hipStream_t st) {
     switch (prec) {
-        case 0: return launch2<PF64>(blks, segs, tiles, ntiles, probs, single, st);
-        case 1: return launch2<PF32>(blks, segs, tiles, ntiles, probs, single, st);
-        case 2: return launch2<PBF3>(blks, segs, tiles, ntiles, probs, single, st);
-        default: return launch2<PBF6>(blks, segs, tiles, ntiles, probs, single, st);
+        case 0: return launch2<PF64>(narrow, blks, segs, tiles, ntiles, probs, single, st);
+        case 1: return launch2<PF32>(narrow, blks, segs, tiles, ntiles, probs, single, st);
+        case 2: return launch2<PBF3>(narrow, blks, segs, tiles, ntiles, probs, single, st);
+        default: return launch2<PBF6>(narrow, blks, segs, tiles, ntiles, probs, single, st);
     }
 }
 

@@ -10,6 +10,7 @@ constexpr int kMaxKrylov = 64;      // largest kdim accepted
 constexpr int kTile = 32;           // output tile edge of the block-product kernels
 constexpr int kTile1N = 64;         // stage-1 tiles are kTile x kTile1N (one per wavefront),
 constexpr int kTile1NN = 32;        // or kTile x kTile1NN (narrow: twice the tiles, each shorter)
+constexpr int kTile2NN = 16;        // narrow stage-2 tiles are kTile x kTile2NN
 constexpr int kChunk = 16;          // K depth of one FP64/FP32 chunk (4 MFMA K-steps of 4)
 constexpr int kChunkMax = 32;       // K depth of one BF16 chunk (one 16x16x32 MFMA)
 constexpr int kWaves = 4;           // waves per work group (split-K among them)

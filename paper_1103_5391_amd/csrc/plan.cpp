@@ -273,6 +273,7 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
         kcat[bi] = k;
         P.flops2 += 2.0 * B.d * (double)(2 * B.e) * k;
         tile_list(P.tiles2, bi, B.d, 2 * B.e, kTile, kTile);
+        tile_list(P.tiles2n, bi, B.d, 2 * B.e, kTile, kTile2NN);
     }
     P.flops = P.flops1 + P.flops2;
 
@@ -341,6 +342,7 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
     P.tiles1 = xcd_order(P.tiles1, w1, 1);
     P.tiles1n = xcd_order(P.tiles1n, w1, 1);
     P.tiles2 = xcd_order(P.tiles2, w2, 1);
+    P.tiles2n = xcd_order(P.tiles2n, w2, 1);
     P.w1 = std::move(w1);
     P.w2 = std::move(w2);
     lds_lists(P);
@@ -395,7 +397,7 @@ void lds_lists(Plan& P) {
 
 void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
     out = Merged{};
-    std::vector<Tile> t1, t1n, t2;
+    std::vector<Tile> t1, t1n, t2, t2n;
     std::vector<double> w1, w2;
     std::vector<LItem1> l1;
     std::vector<LItem2> l2[2];
@@ -422,6 +424,8 @@ void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
             if (t.blk >= 0) t1n.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
         for (Tile t : P.tiles2)
             if (t.blk >= 0) t2.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
+        for (Tile t : P.tiles2n)
+            if (t.blk >= 0) t2n.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
         w1.insert(w1.end(), P.w1.begin(), P.w1.end());
         w2.insert(w2.end(), P.w2.begin(), P.w2.end());
         for (LItem1 t : P.l1)
@@ -449,6 +453,7 @@ void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
     out.tiles1 = xcd_order(t1, w1, 1);
     out.tiles1n = xcd_order(t1n, w1, 1);
     out.tiles2 = xcd_order(t2, w2, 1);
+    out.tiles2n = xcd_order(t2n, w2, 1);
     // the LDS lists keep each problem's block order: weights by tiles of the merged lists
     std::vector<double> wl(boff, 0.0);
     for (const LItem1& t : l1) wl[t.blk] += 1.0;

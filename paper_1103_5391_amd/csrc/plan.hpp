@@ -91,7 +91,7 @@ struct Plan {
     std::vector<int> N1;                       // stage-1 columns per source block
     std::vector<View> Tview;                   // stage-1 workspace view per block
     int64_t T_size = 0;                        // workspace elements
-    std::vector<Tile> tiles1, tiles1n, tiles2; // register-tiled lists (stage 1: wide, narrow)
+    std::vector<Tile> tiles1, tiles1n, tiles2, tiles2n;   // register-tiled lists (wide, narrow)
     std::vector<LItem1> l1;                    // LDS-tiled stage-1 tiles (both packings)
     std::vector<double> w1, w2;                // per-block work estimates of the two stages
     Packing pk16, pk32;
@@ -108,7 +108,7 @@ struct Merged {
     std::vector<S1Block> s1[2];               // per chunk depth (0: 16, 1: 32)
     std::vector<S2Block> s2[2];
     std::vector<Segment> segs[2];
-    std::vector<Tile> tiles1, tiles1n, tiles2;
+    std::vector<Tile> tiles1, tiles1n, tiles2, tiles2n;
     std::vector<LItem1> l1;
     std::vector<LItem2> l2[2];
     std::vector<LRed> lred[2];

@@ -94,9 +94,10 @@ def test_layout_matches_oracle(env):
         h.destroy()
 
 
-GEMM_VARIANTS = pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 6],
+GEMM_VARIANTS = pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 6, 8, 9, 12],
                                         ids=["reg-reg", "lds-reg", "reg-lds", "lds-lds",
-                                             "narrow-reg", "narrow-lds"])
+                                             "narrow-reg", "narrow-lds", "reg-narrow",
+                                             "lds-narrow", "narrow-narrow"])
 
 
 @GEMM_VARIANTS
@@ -517,22 +518,26 @@ def test_autotune_and_variants_agree(env, prec):
     t = h.autotune(reps=3)
     say("  ", t)
     assert all(t[k] > 0 for k in ("stage1_register", "stage1_lds", "stage2_register", "stage2_lds",
-                                  "stage1_narrow"))
-    s1 = min([(t["stage1_register"], 0), (t["stage1_narrow"], L.DMRG_GEMM_STAGE1_NARROW),
-              (t["stage1_lds"], L.DMRG_GEMM_STAGE1_LDS)], key=lambda p: p[0])[1]
-    want = s1 | (L.DMRG_GEMM_STAGE2_LDS if t["stage2_lds"] < t["stage2_register"] else 0)
+                                  "stage1_narrow", "stage2_narrow"))
+    s1 = min([(t["stage1_register"], 0), (t["stage1_lds"], L.DMRG_GEMM_STAGE1_LDS),
+              (t["stage1_narrow"], L.DMRG_GEMM_STAGE1_NARROW)], key=lambda p: p[0])[1]
+    s2 = min([(t["stage2_register"], 0), (t["stage2_lds"], L.DMRG_GEMM_STAGE2_LDS),
+              (t["stage2_narrow"], L.DMRG_GEMM_STAGE2_NARROW)], key=lambda p: p[0])[1]
+    want = s1 | s2
     assert t["variant"] == want
     x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 91))
     xd = _dev(torch, x)
     yref = M.matvec_sector(pb, x)
     tol = MV_TOL if prec == 0 else MIXED_TOL[prec]
-    for v in (0, 1, 2, 3, 4, 6):
+    for v in (0, 1, 2, 3, 4, 6, 8, 9, 12):
         h.set_gemm(v)
         yd = torch.empty_like(xd)
         h.matvec(xd, yd)
         err = rel(_host(yd), yref)
         say("  variant", v, err)
         assert err <= tol
-    with pytest.raises(L.DmrgError):
-        h.set_gemm(L.DMRG_GEMM_STAGE1_LDS | L.DMRG_GEMM_STAGE1_NARROW)
+    for bad in (L.DMRG_GEMM_STAGE1_LDS | L.DMRG_GEMM_STAGE1_NARROW,
+                L.DMRG_GEMM_STAGE2_LDS | L.DMRG_GEMM_STAGE2_NARROW, 16):
+        with pytest.raises(L.DmrgError):
+            h.set_gemm(bad)
     h.destroy()
