@@ -16,7 +16,8 @@ constexpr int kChunkMax = 32;       // K depth of one BF16 chunk (one 16x16x32 M
 constexpr int kWaves = 4;           // waves per work group (split-K among them)
 constexpr int kVecThreads = 256;    // threads per block of the vector kernels
 constexpr int kVecMaxBlocks = 1024; // blocks per problem of a vector pass (rows of partial sums)
-constexpr int kDSlots = 16;         // basis slots per Lanczos reduction launch
+constexpr int kDSlots = 15;         // basis slots per Lanczos reduction launch (4 values each,
+                                    // plus 4: a row of 64, one per lane)
 constexpr int kDVals = 4 * kDSlots + 4;   // values per partial row of a reduction launch
 constexpr int kDMaxQ = (kMaxKrylov + kDSlots - 1) / kDSlots;   // reduction launches per iteration
 #ifndef DMRG_RED_ELEMS

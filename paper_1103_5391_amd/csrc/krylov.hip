@@ -135,6 +135,73 @@ __device__ __forceinline__ void block_partials_row(const double (&vals)[NV > 0 ?
     }
 }
 
+// Exchange partner for the reduce-scatter step on lane bit B: lane ^ B for the bits that cross
+// rows of 16 (through the LDS permute network), otherwise a DPP move within the row whose
+// partner differs in bit B (and possibly lower bits, which are not yet reduced).
+template <int B>
+__device__ __forceinline__ double partner(double v) {
+    if constexpr (B >= 16) return __shfl_xor(v, B, 64);
+    else if constexpr (B == 8) return dpp<0x140>(v);   // row_mirror: lane i <-> 15 - i
+    else if constexpr (B == 4) return dpp<0x141>(v);   // row_half_mirror: i <-> 7 - i
+    else if constexpr (B == 2) return dpp<0x4E>(v);    // quad_perm [2,3,0,1]
+    else return dpp<0xB1>(v);                          // quad_perm [1,0,3,2]
+}
+
+// Reduce-scatter of P (a power of two, <= 64) per-lane values over the wavefront by recursive
+// halving: at the step on lane bit B a lane keeps the half of its remaining values selected by
+// that bit and adds its partner's copy of the same half; after log2 P steps each lane holds one
+// value, the wavefront sum of value index lane >> (6 - log2 P), and the remaining lane bits are
+// summed by plain butterflies.  P - 1 + 6 - log2 P exchanges instead of 6 P for P wave sums.
+template <int P, int B = 32>
+__device__ __forceinline__ void halve(double (&v)[P], int lane) {
+    if constexpr (P > 1) {
+        constexpr int H = P / 2;
+        const bool upper = lane & B;
+        double keep[H];
+#pragma unroll
+        for (int i = 0; i < H; ++i) {
+            const double give = upper ? v[i] : v[i + H];
+            const double mine = upper ? v[i + H] : v[i];
+            keep[i] = mine + partner<B>(give);
+        }
+        double (&w)[H] = *reinterpret_cast<double(*)[H]>(v);
+#pragma unroll
+        for (int i = 0; i < H; ++i) w[i] = keep[i];
+        halve<H, B / 2>(w, lane);
+    } else if constexpr (B >= 1) {
+        v[0] += partner<B>(v[0]);
+        halve<1, B / 2>(v, lane);
+    }
+}
+
+// Block-level sums of NV <= 64 per-thread values by wavefront reduce-scatter, written as a row
+// of ROW values (zeros past NV), value-major: part[v * kVecMaxBlocks + lb].
+template <int NV, int ROW>
+__device__ __forceinline__ void block_partials_scatter(const double (&vals)[NV > 0 ? NV : 1],
+                                                       double* part, int lb) {
+    static_assert(NV <= 64 && ROW <= 64, "one value per lane");
+    constexpr int P = NV <= 1 ? 1 : NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : NV <= 16 ? 16
+                                                         : NV <= 32 ? 32 : 64;
+    constexpr int SHIFT = P == 1 ? 6 : P == 2 ? 5 : P == 4 ? 4 : P == 8 ? 3 : P == 16 ? 2
+                                                   : P == 32 ? 1 : 0;
+    __shared__ double red[kVecThreads / 64][64];
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    double v[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) v[i] = i < NV ? vals[i] : 0.0;
+    halve<P>(v, lane);
+    if ((lane & ((1 << SHIFT) - 1)) == 0) red[wave][lane >> SHIFT] = v[0];
+    __syncthreads();
+    for (int i = threadIdx.x; i < ROW; i += blockDim.x) {
+        double s = 0.0;
+        if (i < NV) {
+#pragma unroll
+            for (int w = 0; w < kVecThreads / 64; ++w) s += red[w][i];
+        }
+        part[(int64_t)i * kVecMaxBlocks + lb] = s;
+    }
+}
+
 // Finalise kernels run one block of FT threads per problem: totals[v] = sum_b part[v][b] for
 // v < NV in a fixed order (thread t adds rows t, t + FT, ... in turn, then the block reduction
 // of block_partials; nb <= kVecMaxBlocks, value-major layout as written by block_partials).
@@ -270,7 +337,7 @@ __global__ __launch_bounds__(kVecThreads) void k_dreduce(const VecProb* vp, cons
             acc[4 * NC + 3] += wr * wr + wi * wi;
         }
     }
-    block_partials_row<NV, kDVals>(acc, W.p.part + (int64_t)q * kVecMaxBlocks * kDVals, W.lb);
+    block_partials_scatter<NV, kDVals>(acc, W.p.part + (int64_t)q * kVecMaxBlocks * kDVals, W.lb);
 }
 
 // Lanczos iteration j: totals of the reduction launches.  Wave w of block (x, problem) sums
