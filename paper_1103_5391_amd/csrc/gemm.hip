@@ -28,34 +28,25 @@
 namespace dmrg {
 
 // ---------------------------------------------------------------------------------------
-// stage 1: one 32 x 16 NJ tile (NJ = 4 wide, 2 narrow) per single-wavefront work group
+// stage 1: one 16 MI x 16 NJ tile (MI = 2, or 1 for a half-height tile; NJ = 4 wide, 2 narrow)
+// per single-wavefront work group
 // ---------------------------------------------------------------------------------------
-template <class P, int NJ>
-__global__ __launch_bounds__(64, 3) void stage1(const S1Block* __restrict__ blks,
-                                                 const Tile* __restrict__ tiles, int ntiles,
-                                                 const ProbPtrs* __restrict__ probs,
-                                                 ProbPtrs single) {
+template <class P, int MI, int NJ>
+__device__ __forceinline__ void stage1_tile(const Tile& tl, const S1Block& B, const ProbPtrs& P_) {
     using op_t = typename P::op_t;
     using ws_t = typename P::ws_t;
     using acc_t = typename P::acc_t;
     using frag_t = typename P::frag_t;
     const int lane = threadIdx.x;
-    const int ti = blockIdx.x;
-    if (ti >= ntiles) return;
-    const Tile tl = tiles[ti];
-    if (tl.blk < 0) return;   // padding of the XCD-ordered list
-    const S1Block B = blks[tl.blk];
-    const ProbPtrs P_ = probs ? probs[B.prob] : single;
-    if (P_.skip && *P_.skip) return;
     const int g = lane >> 4, r = lane & 15;
     const double xs = P_.xscale ? *P_.xscale : 1.0;
     const double* __restrict__ X = P_.x;
     const int K = B.K;
     const int nch = (K + P::CK - 1) / P::CK;
 
-    int64_t arow[2];
+    int64_t arow[MI];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < MI; ++i) {
         const int m = min(tl.m0 + 16 * i + r, B.M - 1);
         const int pl = m >= B.X.split;
         arow[i] = B.X.off + pl * B.X.poff + (m - pl * B.X.split);
@@ -65,16 +56,16 @@ __global__ __launch_bounds__(64, 3) void stage1(const S1Block* __restrict__ blks
                      r * lane_elems<P>();
     const int64_t panel = (int64_t)nch * chunk_elems<P>();
     const int64_t ldx = B.X.ld;
-    acc_t acc[2][NJ];
+    acc_t acc[MI][NJ];
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
         for (int nj = 0; nj < NJ; ++nj) zero<P>(acc[mi][nj]);
-    frag_t a[2][2], b[2][NJ];
-    auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[NJ]) {
+    frag_t a[2][MI], b[2][NJ];
+    auto load = [&](int c, frag_t (&fa)[MI], frag_t (&fb)[NJ]) {
         const int kb = c * P::CK + P::KPL * g;
 #pragma unroll
-        for (int i = 0; i < 2; ++i) {
+        for (int i = 0; i < MI; ++i) {
             double v[P::KPL];
             load_clamped<P>(X, arow[i], kb, K, ldx, v);
             fa[i] = P::from(v);
@@ -82,9 +73,9 @@ __global__ __launch_bounds__(64, 3) void stage1(const S1Block* __restrict__ blks
 #pragma unroll
         for (int j = 0; j < NJ; ++j) fb[j] = P::load_op(pb + j * panel + (int64_t)c * chunk_elems<P>());
     };
-    auto mma = [&](const frag_t (&fa)[2], const frag_t (&fb)[NJ]) {
+    auto mma = [&](const frag_t (&fa)[MI], const frag_t (&fb)[NJ]) {
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
             for (int nj = 0; nj < NJ; ++nj) acc[mi][nj] = P::mma(fa[mi], fb[nj], acc[mi][nj]);
     };
@@ -102,7 +93,7 @@ __global__ __launch_bounds__(64, 3) void stage1(const S1Block* __restrict__ blks
     ws_t* __restrict__ T = static_cast<ws_t*>(P_.T);
     const View tv = B.T;
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
         for (int nj = 0; nj < NJ; ++nj) {
             const int n = tl.n0 + 16 * nj + r;
@@ -119,20 +110,38 @@ __global__ __launch_bounds__(64, 3) void stage1(const S1Block* __restrict__ blks
         }
 }
 
+template <class P, int NJ>
+__global__ __launch_bounds__(64, 3) void stage1(const S1Block* __restrict__ blks,
+                                                 const Tile* __restrict__ tiles, int ntiles,
+                                                 const ProbPtrs* __restrict__ probs,
+                                                 ProbPtrs single) {
+    const int ti = blockIdx.x;
+    if (ti >= ntiles) return;
+    const Tile tl = tiles[ti];
+    if (tl.blk < 0) return;   // padding of the XCD-ordered list
+    const S1Block B = blks[tl.blk];
+    const ProbPtrs P_ = probs ? probs[B.prob] : single;
+    if (P_.skip && *P_.skip) return;
+    if (tl.half)
+        stage1_tile<P, 1, NJ>(tl, B, P_);
+    else
+        stage1_tile<P, 2, NJ>(tl, B, P_);
+}
+
 // ---------------------------------------------------------------------------------------
 // stage 2: one 32 x 32 (or 32 x 16) tile per work group, K chunks dealt round-robin to its waves
 // ---------------------------------------------------------------------------------------
 constexpr int kChunkTab = 256;   // workspace chunks of a block addressed through the LDS table
-template <class P, int NJ, class Load>
-__device__ __forceinline__ void kloop(typename P::acc_t (&acc)[2][NJ], int c0, int step, int nch,
+template <class P, int MI, int NJ, class Load>
+__device__ __forceinline__ void kloop(typename P::acc_t (&acc)[MI][NJ], int c0, int step, int nch,
                                       Load load) {
     using frag_t = typename P::frag_t;
     if (c0 >= nch) return;
     const int last = c0 + (nch - 1 - c0) / step * step;
-    frag_t a0[2], b0[NJ], a1[2], b1[NJ];
-    auto mma = [&](const frag_t (&fa)[2], const frag_t (&fb)[NJ]) {
+    frag_t a0[MI], b0[NJ], a1[MI], b1[NJ];
+    auto mma = [&](const frag_t (&fa)[MI], const frag_t (&fb)[NJ]) {
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
             for (int nj = 0; nj < NJ; ++nj) acc[mi][nj] = P::mma(fa[mi], fb[nj], acc[mi][nj]);
     };
@@ -148,23 +157,18 @@ __device__ __forceinline__ void kloop(typename P::acc_t (&acc)[2][NJ], int c0, i
     }
 }
 
-// One 32 x 16 NJ output tile per work group of NW wavefronts (K chunks dealt round-robin).
-template <class P, int NJ, int NW>
-__global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__ blks,
-                                                     const Segment* __restrict__ segs,
-                                                     const Tile* __restrict__ tiles,
-                                                     const ProbPtrs* __restrict__ probs,
-                                                     ProbPtrs single) {
+// One 16 MI x 16 NJ output tile (MI = 2, or 1 for a half-height tile) per work group of NW
+// wavefronts (K chunks dealt round-robin); ctab and red live in the kernel's LDS.
+template <class P, int MI, int NJ, int NW>
+__device__ __forceinline__ void stage2_tile(const Tile& tl, const S2Block& B,
+                                            const Segment* __restrict__ segs, const ProbPtrs& P_,
+                                            int64_t (&ctab)[kChunkTab][3],
+                                            double (&red)[NW][16 * NJ][kTile + 1]) {
     using op_t = typename P::op_t;
     using ws_t = typename P::ws_t;
     using acc_t = typename P::acc_t;
     using frag_t = typename P::frag_t;
     constexpr int TN = 16 * NJ;
-    const Tile tl = tiles[blockIdx.x];
-    if (tl.blk < 0) return;   // padding of the XCD-ordered list
-    const S2Block B = blks[tl.blk];
-    const ProbPtrs P_ = probs ? probs[B.prob] : single;
-    if (P_.skip && *P_.skip) return;
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int g = lane >> 4, r = lane & 15;
@@ -172,9 +176,9 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
     const int split = B.Y.split;   // columns per plane of the output and of every source
     const ws_t* __restrict__ Tws = static_cast<const ws_t*>(P_.T);
 
-    const op_t* pa[2];
+    const op_t* pa[MI];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) {
+    for (int i = 0; i < MI; ++i) {
         const int pnl = tl.m0 / kPanel + i;
         pa[i] = static_cast<const op_t*>(P_.Lops) + B.Aoff * P::PER +
                 (((int64_t)pnl * B.nch) * 4 + g) * (kPanel * lane_elems<P>()) + r * lane_elems<P>();
@@ -186,9 +190,9 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
         pl[j] = n >= split;
         col[j] = n - pl[j] * split;
     }
-    acc_t acc[2][NJ];
+    acc_t acc[MI][NJ];
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
         for (int nj = 0; nj < NJ; ++nj) zero<P>(acc[mi][nj]);
     // pass 1: segment 0, the diagonal H_S term, reads the block itself from the input vector;
@@ -200,10 +204,10 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
 #pragma unroll
         for (int j = 0; j < NJ; ++j)
             bcol[j] = s0.B.off + pl[j] * s0.B.poff + (int64_t)col[j] * s0.B.ld;
-        auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[NJ]) {
+        auto load = [&](int c, frag_t (&fa)[MI], frag_t (&fb)[NJ]) {
             const int64_t ga = (int64_t)c * chunk_elems<P>();
 #pragma unroll
-            for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
+            for (int i = 0; i < MI; ++i) fa[i] = P::load_op(pa[i] + ga);
             const int kb = c * P::CK + P::KPL * g;
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
@@ -212,9 +216,9 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
                 fb[j] = P::from(v);
             }
         };
-        kloop<P, NJ>(acc, wave, NW, nch0, load);
+        kloop<P, MI, NJ>(acc, wave, NW, nch0, load);
 #pragma unroll
-        for (int mi = 0; mi < 2; ++mi)
+        for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
             for (int nj = 0; nj < NJ; ++nj)
 #pragma unroll
@@ -223,7 +227,7 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
     // pass 2: every workspace chunk of segments 1.. in one pipelined stream per wave (global
     // chunk c goes to wave c mod NW), its source view read from a per-chunk table in LDS (built
     // once per work group) instead of restarting the pipeline at every segment
-    __shared__ int64_t ctab[kChunkTab][3];   // per workspace chunk: off - ch0 CK, poff, ld
+    // ctab: per workspace chunk off - ch0 CK, poff, ld
     const int nT = B.nch - nch0;
     if (nT > 0 && nT <= kChunkTab) {
         for (int t = threadIdx.x; t < nT; t += blockDim.x) {
@@ -236,10 +240,10 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
             ctab[t][2] = sg.B.ld;
         }
         __syncthreads();
-        auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[NJ]) {
+        auto load = [&](int c, frag_t (&fa)[MI], frag_t (&fb)[NJ]) {
             const int64_t ga = (int64_t)c * chunk_elems<P>();
 #pragma unroll
-            for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
+            for (int i = 0; i < MI; ++i) fa[i] = P::load_op(pa[i] + ga);
             const int64_t* e = ctab[c - nch0];
             const int64_t kb = (int64_t)c * P::CK + P::KPL * g;
 #pragma unroll
@@ -251,7 +255,7 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
         };
         // first chunk >= nch0 owned by this wave
         const int cw = nch0 + ((wave - nch0) % NW + NW) % NW;
-        kloop<P, NJ>(acc, cw, NW, B.nch, load);
+        kloop<P, MI, NJ>(acc, cw, NW, B.nch, load);
     } else {
         // very long K: one pipeline per segment
         for (int s = 1; s < B.nseg; ++s) {
@@ -262,10 +266,10 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
                 bcol[j] = sg.B.off + pl[j] * sg.B.poff + (int64_t)col[j] * sg.B.ld;
             const int nch = (sg.K + P::CK - 1) / P::CK;
             const int c0 = ((wave - sg.ch0) % NW + NW) % NW;
-            auto load = [&](int c, frag_t (&fa)[2], frag_t (&fb)[NJ]) {
+            auto load = [&](int c, frag_t (&fa)[MI], frag_t (&fb)[NJ]) {
                 const int64_t ga = (int64_t)(sg.ch0 + c) * chunk_elems<P>();
 #pragma unroll
-                for (int i = 0; i < 2; ++i) fa[i] = P::load_op(pa[i] + ga);
+                for (int i = 0; i < MI; ++i) fa[i] = P::load_op(pa[i] + ga);
                 const int kb = c * P::CK + P::KPL * g;
 #pragma unroll
                 for (int j = 0; j < NJ; ++j) {
@@ -274,13 +278,12 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
                     fb[j] = P::from(v);
                 }
             };
-            kloop<P, NJ>(acc, c0, NW, nch, load);
+            kloop<P, MI, NJ>(acc, c0, NW, nch, load);
         }
     }
 
-    __shared__ double red[NW][TN][kTile + 1];
 #pragma unroll
-    for (int mi = 0; mi < 2; ++mi)
+    for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
         for (int nj = 0; nj < NJ; ++nj)
 #pragma unroll
@@ -305,6 +308,25 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
             Y[yv.off + p * yv.poff + (int64_t)c * yv.ld + gm] = init + v;
         }
     }
+}
+
+template <class P, int NJ, int NW>
+__global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__ blks,
+                                                     const Segment* __restrict__ segs,
+                                                     const Tile* __restrict__ tiles,
+                                                     const ProbPtrs* __restrict__ probs,
+                                                     ProbPtrs single) {
+    const Tile tl = tiles[blockIdx.x];
+    if (tl.blk < 0) return;   // padding of the XCD-ordered list
+    const S2Block B = blks[tl.blk];
+    const ProbPtrs P_ = probs ? probs[B.prob] : single;
+    if (P_.skip && *P_.skip) return;
+    __shared__ int64_t ctab[kChunkTab][3];
+    __shared__ double red[NW][16 * NJ][kTile + 1];
+    if (tl.half)
+        stage2_tile<P, 1, NJ, NW>(tl, B, segs, P_, ctab, red);
+    else
+        stage2_tile<P, 2, NJ, NW>(tl, B, segs, P_, ctab, red);
 }
 
 // ---------------------------------------------------------------------------------------

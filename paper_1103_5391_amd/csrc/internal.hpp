@@ -81,9 +81,10 @@ struct Segment {
     View B;
 };
 
-// One 32 x 32 output tile of a stage.
+// One output tile of a register-tiled stage: rows m0.., columns n0.. of block blk; half: the
+// tile has 16 rows instead of 32 (the last rows of a block, 16 or fewer).
 struct Tile {
-    int32_t blk, m0, n0, pad;
+    int32_t blk, m0, n0, half;
 };
 
 // Work of the LDS-tiled block-product kernels: 64 x 64 output tiles, four wavefronts of 32 x 32

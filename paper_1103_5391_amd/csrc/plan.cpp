@@ -159,9 +159,11 @@ std::vector<T> xcd_order(const std::vector<T>& tiles, const std::vector<double>&
     return out;
 }
 
+// Tiles of tm x tn over an M x N block; a last row of tiles with tm / 2 rows or fewer is marked
+// half-height (the kernels then run half the row fragments).
 void tile_list(std::vector<Tile>& out, int blk, int M, int N, int tm, int tn) {
     for (int m0 = 0; m0 < M; m0 += tm)
-        for (int n0 = 0; n0 < N; n0 += tn) out.push_back(Tile{blk, m0, n0, 0});
+        for (int n0 = 0; n0 < N; n0 += tn) out.push_back(Tile{blk, m0, n0, M - m0 <= tm / 2});
 }
 
 }  // namespace
@@ -419,13 +421,13 @@ void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
             out.segs[k].insert(out.segs[k].end(), pks[k]->segs.begin(), pks[k]->segs.end());
         }
         for (Tile t : P.tiles1)
-            if (t.blk >= 0) t1.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
+            if (t.blk >= 0) t1.push_back(Tile{t.blk + boff, t.m0, t.n0, t.half});
         for (Tile t : P.tiles1n)
-            if (t.blk >= 0) t1n.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
+            if (t.blk >= 0) t1n.push_back(Tile{t.blk + boff, t.m0, t.n0, t.half});
         for (Tile t : P.tiles2)
-            if (t.blk >= 0) t2.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
+            if (t.blk >= 0) t2.push_back(Tile{t.blk + boff, t.m0, t.n0, t.half});
         for (Tile t : P.tiles2n)
-            if (t.blk >= 0) t2n.push_back(Tile{t.blk + boff, t.m0, t.n0, 0});
+            if (t.blk >= 0) t2n.push_back(Tile{t.blk + boff, t.m0, t.n0, t.half});
         w1.insert(w1.end(), P.w1.begin(), P.w1.end());
         w2.insert(w2.end(), P.w2.begin(), P.w2.end());
         for (LItem1 t : P.l1)
