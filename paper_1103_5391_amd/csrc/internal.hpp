@@ -21,7 +21,7 @@ constexpr int kDSlots = 15;         // basis slots per Lanczos reduction launch 
 constexpr int kDVals = 4 * kDSlots + 4;   // values per partial row of a reduction launch
 constexpr int kDMaxQ = (kMaxKrylov + kDSlots - 1) / kDSlots;   // reduction launches per iteration
 #ifndef DMRG_RED_ELEMS
-#define DMRG_RED_ELEMS 1
+#define DMRG_RED_ELEMS 2
 #endif
 constexpr int kRedElems = DMRG_RED_ELEMS;  // complex elements per thread of a reduction pass
 constexpr int kMaxTimes = 4;        // time points evaluated from one Krylov basis

@@ -44,6 +44,15 @@ namespace {
 
 typedef const double __attribute__((address_space(1)))* gcptr;
 
+typedef double d2v __attribute__((ext_vector_type(2)));
+// Elements i, i + 1 (i even, p 16-byte aligned) of the slot starting at p.
+__device__ __forceinline__ d2v ld2(const double* p, int64_t i) {
+    return *((const d2v __attribute__((address_space(1)))*)(p + i));
+}
+__device__ __forceinline__ void st2(double* p, int64_t i, d2v v) {
+    *((d2v __attribute__((address_space(1)))*)(p + i)) = v;
+}
+
 // Load of element i of the basis slot starting at p (global address space: the uniform slot
 // base can live in scalar registers, the lane offset in one vector register).
 __device__ __forceinline__ double ldv(const double* p, int64_t i) { return ((gcptr)p)[i]; }
@@ -312,6 +321,35 @@ __global__ __launch_bounds__(kVecThreads) void k_dreduce(const VecProb* vp, cons
 #pragma unroll
     for (int v = 0; v < NV; ++v) acc[v] = 0.0;
     const int64_t stride = (int64_t)W.nbt * blockDim.x;
+    if ((n & 1) == 0) {
+        for (int64_t i = 2 * ((int64_t)W.lb * blockDim.x + threadIdx.x); i < n; i += 2 * stride) {
+            d2v vr[NC > 0 ? NC : 1], vi[NC > 0 ? NC : 1];
+            const d2v ur = ld2(u1, i), ui = ld2(u1, n + i), wr = ld2(w, i), wi = ld2(w, n + i);
+#pragma unroll
+            for (int c = 0; c < NC; ++c) {
+                const double* v = V0 + (int64_t)c * vstride;
+                vr[c] = ld2(v, i);
+                vi[c] = ld2(v, n + i);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+#pragma unroll
+                for (int c = 0; c < NC; ++c) {
+                    acc[4 * c] += vr[c][h] * ur[h] + vi[c][h] * ui[h];
+                    acc[4 * c + 1] += vr[c][h] * ui[h] - vi[c][h] * ur[h];
+                    acc[4 * c + 2] += vr[c][h] * wr[h] + vi[c][h] * wi[h];
+                    acc[4 * c + 3] += vr[c][h] * wi[h] - vi[c][h] * wr[h];
+                }
+                if (FIRST) {
+                    acc[4 * NC] += ur[h] * wr[h] + ui[h] * wi[h];
+                    acc[4 * NC + 1] += ur[h] * wi[h] - ui[h] * wr[h];
+                    acc[4 * NC + 2] += ur[h] * ur[h] + ui[h] * ui[h];
+                    acc[4 * NC + 3] += wr[h] * wr[h] + wi[h] * wi[h];
+                }
+            }
+        }
+    } else
     for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
         // every load of the element first, then the arithmetic (one memory round trip)
         double vr[NC > 0 ? NC : 1], vi[NC > 0 ? NC : 1];
@@ -516,6 +554,42 @@ __global__ __launch_bounds__(kVecThreads) void k_dupdate(const VecProb* vp, cons
     const double* __restrict__ w = W.p.w;
     const int64_t n = W.p.n, vstride = W.p.vstride;
     const int64_t stride = (int64_t)W.nbt * blockDim.x;
+    if ((n & 1) == 0) {
+        for (int64_t i = 2 * ((int64_t)W.lb * blockDim.x + threadIdx.x); i < n; i += 2 * stride) {
+            const d2v u0r = ld2(uj, i), u0i = ld2(uj, n + i), w0r = ld2(w, i), w0i = ld2(w, n + i);
+            d2v ar = 0.0, ai = 0.0, tr = 0.0, ti = 0.0, hr = 0.0, hi = 0.0;
+            for (int c0 = 0; c0 < j; c0 += G) {
+                d2v vr[G], vi[G];
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const double* v = V + (int64_t)min(c0 + k, j - 1) * vstride;
+                    vr[k] = ld2(v, i);
+                    vi[k] = ld2(v, n + i);
+                }
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < G; ++k) {
+                    const int c = c0 + k;
+                    ar += co[0][2 * c] * vr[k] - co[0][2 * c + 1] * vi[k];
+                    ai += co[0][2 * c] * vi[k] + co[0][2 * c + 1] * vr[k];
+                    tr += co[1][2 * c] * vr[k] - co[1][2 * c + 1] * vi[k];
+                    ti += co[1][2 * c] * vi[k] + co[1][2 * c + 1] * vr[k];
+                    hr += co[2][2 * c] * vr[k] - co[2][2 * c + 1] * vi[k];
+                    hi += co[2][2 * c] * vi[k] + co[2][2 * c + 1] * vr[k];
+                }
+            }
+            const d2v ur = u0r - ar, ui = u0i - ai;
+            const d2v wr = (w0r - tr - (tjr * ur - tji * ui)) * sj;
+            const d2v wi = (w0i - ti - (tjr * ui + tji * ur)) * sj;
+            st2(uj, i, ur);
+            st2(uj, n + i, ui);
+            if (!last) {
+                st2(un, i, wr - hr - (hjr * ur - hji * ui));
+                st2(un, n + i, wi - hi - (hjr * ui + hji * ur));
+            }
+        }
+        return;
+    }
     for (int64_t i = (int64_t)W.lb * blockDim.x + threadIdx.x; i < n; i += stride) {
         const double u0r = ldv(uj, i), u0i = ldv(uj, n + i), w0r = ldv(w, i), w0i = ldv(w, n + i);
         double ar = 0.0, ai = 0.0, tr = 0.0, ti = 0.0, hr = 0.0, hi = 0.0;
@@ -729,7 +803,7 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_chain(const VecProb* vp) {
 // to cover the memory latency of these streaming passes), at most kVecMaxBlocks rows of partial
 // sums.
 int vec_blocks(int64_t n) {
-    int64_t nb = (n + kVecThreads - 1) / kVecThreads;
+    int64_t nb = (n / 2 + kVecThreads - 1) / kVecThreads;
     if (nb < 1) nb = 1;
     if (nb > kVecMaxBlocks) nb = kVecMaxBlocks;
     return (int)nb;

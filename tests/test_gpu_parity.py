@@ -59,6 +59,8 @@ def problem(name):
         elif name == "chain14_m25_off":
             _PROBLEMS[name] = I.synthetic_problem(14, 25, 2.0, I.chain_bonds(14), 9, name=name,
                                                   target=(6, 8))
+        elif name == "chain8_m17_odd":   # odd vector length: the scalar path of the vector passes
+            _PROBLEMS[name] = I.synthetic_problem(8, 17, 4.0, I.chain_bonds(8), 47, name=name)
         elif name == "chain20_m150":
             _PROBLEMS[name] = I.synthetic_problem(20, 150, 4.0, I.chain_bonds(20), 12, name=name)
         elif name == "ladder2x4_U10":
@@ -73,6 +75,7 @@ def problem(name):
 
 
 MATVEC_CASES = ["chain4_exact", "chain8_exact", "ladder2x4_U10", "chain12_m30", "ladder2x6_m40",
+                "chain8_m17_odd",
                 "chain14_m25_off", "chain20_m150", "chain32_m400", "ladder16_m800",
                 "ladder16_m1000", "ladder32_m2000"]
 
@@ -170,6 +173,7 @@ KRYLOV_CASES = [
     # name, kdim, tau, nsteps
     ("chain8_exact", 12, 0.1, 10),
     ("chain12_m30", 15, 0.1, 3),
+    ("chain8_m17_odd", 12, 0.1, 3),     # odd n
     ("chain20_m150", 20, 0.05, 2),
     ("chain32_m400", 15, 0.1, 2),
     ("ladder16_m1000", 15, 0.05, 1),
@@ -370,11 +374,11 @@ def _batch_setup(torch, L, pbs, seed):
 
 
 def test_batch_tst_parity_small(env):
-    """Eight chain superblocks (m 100..300, L 16..48): batched targets against the oracle
-    (<= 1e-10) and bit for bit against each handle's own call."""
+    """Eight chain superblocks (m 100..300, L 16..48) and one of odd vector length: batched
+    targets against the oracle (<= 1e-10) and bit for bit against each handle's own call."""
     torch, L = env
     say("batch small")
-    pbs = I.batch_workloads(8, seed_offset=300, m_lo=100, m_hi=300)
+    pbs = I.batch_workloads(8, seed_offset=300, m_lo=100, m_hi=300) + [problem("chain8_m17_odd")]
     hs, phis, pds, tds = _batch_setup(torch, L, pbs, 500)
     tau, kdim = 0.05, 15
     b = L.Batch(hs)
