@@ -25,6 +25,8 @@ import sys
 import time
 
 PEAK_FP64_TFLOPS = 78.6          # MI355X dense FP64 MFMA
+PEAK_FP32_TFLOPS = 157.3         # dense FP32 MFMA
+PEAK_BF16_TFLOPS = 2500.0        # dense BF16 MFMA (no sparsity)
 PEAK_HBM_GBS = 8000.0
 
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
@@ -104,7 +106,7 @@ def batch_section(L, I, torch, steps, warmup, count=64):
     launch per pass for all problems, Lanczos iterations as one HIP graph) against the
     per-problem launch loop, both on the same handles and inputs."""
     import numpy as np
-    kdim, tau = 15, 0.05
+    kdim, tau = 15, 0.1
     pbs = I.batch_workloads(count)
     stream = torch.cuda.current_stream()
     hs = [L.dmrg_create(pb, stream) for pb in pbs]
@@ -150,6 +152,57 @@ def batch_section(L, I, torch, steps, warmup, count=64):
     return out
 
 
+def drift_section(L, I, torch, name="ladder32_m2000", steps=50):
+    """Config-5 drift: the ladder 2x32 at m = 2000 evolved by `steps` Krylov steps (kdim 20,
+    tau 0.05) in every arithmetic from the same normalised complex psi; per step the norm and
+    the energy Re <psi|H|psi> (FP64 products).  Reports the largest drift from step 0 and the
+    largest deviation from the FP64 run."""
+    import numpy as np
+    w = I.WORKLOADS[name]
+    pb = I.make_workload(name)
+    he = L.dmrg_create(pb)                    # FP64 energies
+    hp = L.dmrg_create(pb)
+    n = hp.n
+    psi0 = torch.from_numpy(I.random_psi(n, np.random.default_rng(I.SEED_BASE + w["seed"] + 1000))).cuda()
+    hv = torch.empty_like(psi0)
+
+    def energy(v):
+        he.matvec(v, hv)
+        return float(torch.dot(v, hv))        # Re <v|H v> for the real/imaginary split layout
+
+    out, ref_states, ref_e = {}, [], []
+    for prec, label in [(L.DMRG_FP64, "fp64"), (L.DMRG_FP32, "fp32"), (L.DMRG_BF16X3, "bf16x3"),
+                        (L.DMRG_BF16X6, "bf16x6")]:
+        hp.set_precision(prec)
+        hp.autotune(reps=3)
+        psi = psi0.clone()
+        e0 = energy(psi)
+        dn = de = dev_psi = dev_e = 0.0
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            hp.krylov_expm(psi, psi, w["tau"], w["kdim"], 1, info=False)
+            nrm = float(torch.linalg.vector_norm(psi))
+            e = energy(psi)
+            dn = max(dn, abs(nrm - 1.0))
+            de = max(de, abs(e - e0) / abs(e0))
+            if prec == L.DMRG_FP64:
+                ref_states.append(psi.clone())
+                ref_e.append(e)
+            else:
+                dev_psi = max(dev_psi, float(torch.linalg.vector_norm(psi - ref_states[s])))
+                dev_e = max(dev_e, abs(e - ref_e[s]) / abs(e0))
+        torch.cuda.synchronize()
+        out[label] = {"max_norm_drift": dn, "max_rel_energy_drift": de,
+                      "max_state_dev_vs_fp64": dev_psi, "max_rel_energy_dev_vs_fp64": dev_e,
+                      "ms_per_step_incl_energy": round((time.perf_counter() - t0) * 1e3 / steps, 3)}
+        print(f"[bench] drift {label}: {out[label]}", file=sys.stderr, flush=True)
+    hp.destroy()
+    he.destroy()
+    return {"workload": name, "steps": steps, "kdim": w["kdim"], "tau": w["tau"], "energy0": e0,
+            "per_arithmetic": out}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -159,6 +212,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="FP64 only (no mixed-arithmetic runs)")
+    ap.add_argument("--no-drift", action="store_true", help="skip the 50-step m = 2000 drift run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a buffer of MIB MiB once before the run: a plain copy kernel of "
                          "known traffic that hardware-counter runs use as the byte scale")
@@ -255,8 +309,16 @@ def main():
         tst_err = max(float(torch.linalg.vector_norm(td[2 * n * i:2 * n * (i + 1)] - ref[2 * n * i:2 * n * (i + 1)]))
                       / float(torch.linalg.vector_norm(ref[2 * n * i:2 * n * (i + 1)])) for i in range(4))
         drift = max(abs(float(torch.linalg.vector_norm(td[2 * n * i:2 * n * (i + 1)])) - 1.0) for i in range(4))
+        ms_mv_p = pm["ms_stage1"] + pm["ms_stage2"]
+        tf_p = F / (ms_mv_p * 1e-3) / 1e12
+        # split arithmetics issue pieces x F MFMA work (3 or 6 products per value product)
+        issued = {"fp32": 1, "bf16x3": 3, "bf16x6": 6}[label]
+        peak = PEAK_FP32_TFLOPS if label == "fp32" else PEAK_BF16_TFLOPS
         mixed[label] = {
             "ms_per_step": round(ms_p, 5),
+            "matvec_tflops": round(tf_p, 4),
+            "mfma_peak_frac": round(tf_p / peak, 5),
+            "issued_mfma_frac": round(issued * tf_p / peak, 5),
             "krylov_steps_per_s": round(1000.0 / ms_p, 3),
             "speedup_vs_fp64": round(ms_step / ms_p, 3),
             "matvec_ms": round(pm["ms_stage1"] + pm["ms_stage2"], 5),
@@ -275,6 +337,11 @@ def main():
         print("[bench] batched configuration (64 superblocks)", file=sys.stderr, flush=True)
         batched = batch_section(L, I, torch, max(3, args.steps // 5), 1)
         print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
+
+    drift = None
+    if not args.no_drift:
+        print("[bench] drift (ladder 2x32, m = 2000, 50 steps)", file=sys.stderr, flush=True)
+        drift = drift_section(L, I, torch)
 
     value = kdim * F / (ms_step * 1e-3) / 1e12
     out = {
@@ -302,6 +369,7 @@ def main():
         "mfma_peak_frac_step": round(value / PEAK_FP64_TFLOPS, 4),
         "mixed_precision": mixed,
         "batched_64": batched,
+        "drift_m2000": drift,
         "roofline": {"bound": "mfma", "kernel": kernel_name(dom, int(tune64["variant"])),
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
                      "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP64_TFLOPS, 4),
