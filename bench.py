@@ -146,6 +146,25 @@ def batch_section(L, I, torch, steps, warmup, count=64):
         out[key + "_speedup_vs_loop"] = round(ms_loop / ms, 3)
     out["batched_graph_tflops"] = round(F * kdim / (out["batched_graph_ms"] * 1e-3) / 1e12, 4)
     out["per_problem_loop_tflops"] = round(F * kdim / (ms_loop * 1e-3) / 1e12, 4)
+
+    # 4-RHS (per-target) mode: each problem's four targets as four chains advanced by tau, all
+    # 256 chains in common launches, against the loop of per-problem 4-chain calls
+    cx = [t[2 * h.n * k:2 * h.n * (k + 1)] for h, t in zip(hs, tds) for k in range(4)]
+    cy = [torch.empty_like(x) for x in cx]
+
+    def chain_loop():
+        for i, h in enumerate(hs):
+            h.tst_chains(cx[4 * i:4 * i + 4], tau, kdim, cy[4 * i:4 * i + 4], info=False)
+
+    for h in hs:
+        h.set_gemm(h.autotune(reps=3)["variant"])
+    ms_cloop = timed(chain_loop)
+    b.set_graph(True)
+    ms_c = timed(lambda: b.batch_tst_chains(cx, tau, kdim, cy, info=False))
+    out["rhs4"] = {"chains": 4 * count, "flops_per_step": 4 * F * kdim,
+                   "per_problem_loop_ms": round(ms_cloop, 4), "batched_graph_ms": round(ms_c, 4),
+                   "batched_speedup_vs_loop": round(ms_cloop / ms_c, 3),
+                   "batched_tflops": round(4 * F * kdim / (ms_c * 1e-3) / 1e12, 4)}
     b.destroy()
     for h in hs:
         h.destroy()
@@ -274,6 +293,25 @@ def main():
     tn = [float(torch.linalg.vector_norm(td[2 * n * i:2 * n * (i + 1)])) for i in range(4)]
     assert all(abs(x - 1.0) < 1e-9 for x in tn), tn
 
+    # 4-RHS (per-target) mode on the same workload: the four targets as four chains advanced
+    # by tau in common launches
+    cx = [td[2 * n * k:2 * n * (k + 1)].clone() for k in range(4)]
+    cy = [torch.empty_like(x) for x in cx]
+    for _ in range(args.warmup):
+        h.tst_chains(cx, tau, kdim, cy, info=False)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    for _ in range(args.steps):
+        h.tst_chains(cx, tau, kdim, cy, info=False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms_rhs4 = e0.elapsed_time(e1) / args.steps
+    rhs4 = {"ms_per_step": round(ms_rhs4, 5), "chains": 4,
+            "tflops": round(4 * kdim * F / (ms_rhs4 * 1e-3) / 1e12, 4),
+            "chain_steps_per_s": round(4000.0 / ms_rhs4, 3),
+            "per_chain_speedup_vs_single": round(4 * ms_step / ms_rhs4, 3)}
+    print(f"[bench] 4-RHS mode: {rhs4}", file=sys.stderr, flush=True)
+
     # product-only rate and the dominant kernel (HIP events around each launch)
     yd = torch.empty_like(pd)
     prof = h.profile_matvec(pd, yd, reps=20)
@@ -367,6 +405,7 @@ def main():
         "matvec_tflops": round(F / (ms_mv * 1e-3) / 1e12, 4),
         "matvec_ms": round(ms_mv, 5),
         "mfma_peak_frac_step": round(value / PEAK_FP64_TFLOPS, 4),
+        "rhs4_mode": rhs4,
         "mixed_precision": mixed,
         "batched_64": batched,
         "drift_m2000": drift,

@@ -210,6 +210,18 @@ int dmrg_krylov_expm(dmrg_handle h, const double* x, double* y, double tau, int3
 int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim,
                      double* targets, double* weights, dmrg_krylov_info* info);
 
+/* 4-RHS (per-target) mode of time-step targeting: the four targets are kept as four independent
+ * chains, each advanced by exp(-i tau H) with a Krylov basis of its own (kdim vectors, Sec. II.A)
+ * instead of one basis evaluated at four times (the variant of the seeding of the next
+ * interval, Sec. II.C; it agrees with dmrg_tst_targets only to Krylov error).  The four chains
+ * share every block-product and vector-pass launch.  phi, targets: host arrays of 4 device
+ * pointers (2n doubles each); targets[k] = exp(-i tau H) phi[k], and targets[k] may equal
+ * phi[k].  weights as in dmrg_tst_targets.  infos: NULL or a host array of 4 structs (then the
+ * call waits for the stream).  The first call allocates three more workspaces of the handle's
+ * size (intermediate, basis, vectors). */
+int dmrg_tst_chains(dmrg_handle h, const double* const* phi, double tau, int32_t kdim,
+                    double* const* targets, double* weights, dmrg_krylov_info* infos);
+
 /* Runs the kdim Lanczos iterations of dmrg_krylov_expm and dmrg_tst_targets as one HIP graph
  * (captured on first use per kdim on a private stream, launched on the handle's stream;
  * re-captured after the workspace or the precision changes) instead of one launch per pass.
@@ -239,6 +251,12 @@ int dmrg_batch_autotune(dmrg_batch b, int32_t reps, double* out);
  * different precisions. */
 int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, int32_t kdim,
                            double* const* targets, double* weights, dmrg_krylov_info* infos);
+
+/* The 4-RHS mode for every superblock of the batch in common launches: phi, targets: host
+ * arrays of 4 x count device pointers, chain k of superblock i at [4 i + k].  Results equal those
+ * of dmrg_tst_chains on each handle.  infos: NULL or 4 x count structs. */
+int dmrg_batch_tst_chains(dmrg_batch b, const double* const* phi, double tau, int32_t kdim,
+                          double* const* targets, double* weights, dmrg_krylov_info* infos);
 
 /* Measurement hook: one product y = H_sb x (one vector), then reps launches of the right-product
  * stage back to back and reps launches of the left-product stage back to back, with HIP events

@@ -11,6 +11,9 @@ Sec. II.C: larger times by repeating the step from the evolved vector, Eq. (lanc
 Sec. II.B/II.C: time-step targeting keeps n_v = 4 equally spaced times 0, tau/3, 2tau/3, tau
 from one Krylov basis, with weights 2W for the ground state and the first and last time
 vector and W for the others, W = 1/(n + 3), n = 5 targets including the ground state.
+Per-target (4-RHS) variant of the seeding of the next interval (Sec. II.C leaves it open): each
+target is its own chain, advanced by one Krylov step exp(-i tau H) from its current vector; it
+agrees with the shared-basis targets only to Krylov error, so it has its own oracle function.
 
 The recursion, step by step, on complex vectors (flat [Re | Im] layout outside):
   beta0 = ||x||; v_0 = x / beta0
@@ -162,3 +165,14 @@ def tst_targets(apply_h, phi: np.ndarray, tau: float, kdim: int, nv: int = 4):
     c = tridiag_coeffs(b, tst_times(tau, nv))
     ys = [combine(b, c[i]) if b.k_eff > 0 else np.zeros_like(phi) for i in range(nv)]
     return ys, tst_weights(nv), b
+
+
+def tst_chains(apply_h, phis, tau: float, kdim: int):
+    """Per-target chains: each vector advanced by one Krylov step exp(-i tau H) with a basis of
+    its own (the 4-RHS variant of Sec. II.C), and the time-step-targeting weights."""
+    ys, infos = [], []
+    for phi in phis:
+        y, info = krylov_expm(apply_h, phi, tau, kdim)
+        ys.append(y)
+        infos.append(info)
+    return ys, tst_weights(len(phis)), infos

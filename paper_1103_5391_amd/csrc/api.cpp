@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <new>
 #include <string>
 #include <vector>
@@ -204,7 +205,8 @@ bool valid_variant(int32_t variant) {
 // launches (one launch per pass for all problems), eagerly or as a captured HIP graph of the
 // kdim Lanczos iterations.
 struct Group {
-    std::vector<dmrg_ctx*> hs;
+    std::vector<dmrg_ctx*> hs;                 // member handles
+    std::vector<int> rhs;                      // workspace of each member (chain index)
     Lists* lists = nullptr;                    // the handle's own, or the batch's merged lists
     DevBuf dVP, dBmap, dBmapR, dProbs, dIO;    // VecProb, block maps (streaming, reduction passes),
                                                // ProbPtrs[kMaxKrylov][nprob], IO
@@ -234,6 +236,31 @@ struct Group {
 
 using namespace dmrg;
 
+namespace dmrg {
+
+constexpr int kChains = 4;   // per-target chains of the 4-RHS mode (one per time-step target)
+
+// Device workspace of one Krylov run: stage-1 intermediate, basis slots, work vector, partial
+// sums, state.  A handle owns one per chain of the 4-RHS mode (the first also serves its
+// single-chain calls); the others are allocated on first use.
+struct Workspace {
+    DevBuf dT;          // stage-1 intermediate
+    DevBuf dV;          // Krylov basis slots
+    DevBuf dW;          // matvec output / work vector
+    DevBuf dPart;       // block partial sums
+    DevBuf dState;      // KState
+    int kcap = 0;       // basis slots allocated
+    uint64_t gen = 0;   // bumped whenever a buffer is (re)allocated
+};
+
+}  // namespace dmrg
+
+struct dmrg_batch_ctx {
+    Lists lists;        // merged work lists of all members
+    Group g;
+    std::unique_ptr<dmrg_batch_ctx> chains;   // the 4-RHS mode: every member's four chains
+};
+
 struct dmrg_ctx {
     Plan plan;
     hipStream_t stream = nullptr;
@@ -243,20 +270,9 @@ struct dmrg_ctx {
     // first use)
     Lists lists;
     DevBuf dA[4], dR[4];
-    // workspace
-    DevBuf dT;          // stage-1 intermediate
-    DevBuf dV;          // Krylov basis slots
-    DevBuf dW;          // matvec output / work vector
-    DevBuf dPart;       // block partial sums
-    DevBuf dState;      // KState
-    int kcap = 0;       // basis slots allocated
-    uint64_t gen = 0;   // bumped whenever a workspace buffer is (re)allocated
+    Workspace ws[kChains];
     Group self;         // tables of the handle's own Krylov runs
-};
-
-struct dmrg_batch_ctx {
-    Lists lists;        // merged work lists of all handles
-    Group g;
+    std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
 };
 
 namespace {
@@ -279,22 +295,33 @@ int hip_fail(dmrg_handle h, hipError_t e, const char* where) {
     } while (0)
 
 
-int ensure_workspace(dmrg_handle h, int kdim) {
-    if (h->kcap >= kdim + 1 && h->dW.p) return DMRG_OK;
+// Workspace r of a handle sized for kdim basis vectors (the stage-1 intermediate of workspace 0
+// is allocated by dmrg_create; the padding rows of every intermediate are read (times zero
+// factors) but never written, so intermediates start zeroed).
+int ensure_workspace(dmrg_handle h, int kdim, int r = 0) {
+    Workspace& W = h->ws[r];
+    if (W.kcap >= kdim + 1 && W.dW.p && W.dT.p) return DMRG_OK;
     const int64_t n2 = 2 * h->plan.n;
     HIP_TRY(h, hipStreamSynchronize(h->stream));
-    ++h->gen;
-    HIP_TRY(h, h->dV.alloc(sizeof(double) * (size_t)n2 * (kdim + 1)));
-    h->kcap = kdim + 1;
-    if (!h->dW.p) HIP_TRY(h, h->dW.alloc(sizeof(double) * (size_t)n2));
-    if (!h->dPart.p)
-        HIP_TRY(h, h->dPart.alloc(sizeof(double) * (size_t)kDVals * kVecMaxBlocks *
-                                  ((kMaxKrylov + kDSlots - 1) / kDSlots)));
-    if (!h->dState.p) {
-        HIP_TRY(h, h->dState.alloc(sizeof(KState)));
-        HIP_TRY(h, hipMemsetAsync(h->dState.p, 0, sizeof(KState), h->stream));
-        HIP_TRY(h, hipStreamSynchronize(h->stream));
+    ++W.gen;
+    if (!W.dT.p) {
+        const size_t bytes = sizeof(double) * (size_t)h->plan.T_size;
+        HIP_TRY(h, W.dT.alloc(bytes));
+        HIP_TRY(h, hipMemsetAsync(W.dT.p, 0, bytes, h->stream));
     }
+    if (W.kcap < kdim + 1) {
+        HIP_TRY(h, W.dV.alloc(sizeof(double) * (size_t)n2 * (kdim + 1)));
+        W.kcap = kdim + 1;
+    }
+    if (!W.dW.p) HIP_TRY(h, W.dW.alloc(sizeof(double) * (size_t)n2));
+    if (!W.dPart.p)
+        HIP_TRY(h, W.dPart.alloc(sizeof(double) * (size_t)kDVals * kVecMaxBlocks *
+                                 ((kMaxKrylov + kDSlots - 1) / kDSlots)));
+    if (!W.dState.p) {
+        HIP_TRY(h, W.dState.alloc(sizeof(KState)));
+        HIP_TRY(h, hipMemsetAsync(W.dState.p, 0, sizeof(KState), h->stream));
+    }
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
     return DMRG_OK;
 }
 
@@ -313,11 +340,11 @@ int ensure_operators(dmrg_handle h, int prec) {
 }
 
 ProbPtrs make_ptrs(dmrg_handle h, int prec, const double* x, double* y, const double* xscale,
-                   const int* skip) {
+                   const int* skip, int r = 0) {
     ProbPtrs pp;
     pp.x = x;
     pp.y = y;
-    pp.T = h->dT.p;
+    pp.T = h->ws[r].dT.p;
     pp.Lops = h->dA[prec].p;
     pp.Rops = h->dR[prec].p;
     pp.xscale = xscale;
@@ -338,12 +365,13 @@ int group_prepare(Group& g, int kdim) {
     const int prec = h0->precision;
     for (dmrg_ctx* h : g.hs)
         if (h->precision != prec) return fail(h0, DMRG_EINVAL, "batch members use different precisions");
-    for (dmrg_ctx* h : g.hs) {
-        const int rc = ensure_workspace(h, kdim);
+    for (size_t i = 0; i < g.hs.size(); ++i) {
+        dmrg_ctx* h = g.hs[i];
+        const int rc = ensure_workspace(h, kdim, g.rhs[i]);
         if (rc) return h == h0 ? rc : fail(h0, rc, h->last_error);
     }
     bool stale = g.prec != prec || g.gens.size() != g.hs.size() || !g.dVP.p;
-    for (size_t i = 0; !stale && i < g.hs.size(); ++i) stale = g.gens[i] != g.hs[i]->gen;
+    for (size_t i = 0; !stale && i < g.hs.size(); ++i) stale = g.gens[i] != g.hs[i]->ws[g.rhs[i]].gen;
     if (!stale) return DMRG_OK;
 
     HIP_TRY(h0, hipStreamSynchronize(h0->stream));
@@ -355,11 +383,13 @@ int group_prepare(Group& g, int kdim) {
     int b0 = 0, b0r = 0;
     for (int i = 0; i < np; ++i) {
         dmrg_ctx* h = g.hs[i];
+        const int r = g.rhs[i];
+        Workspace& W = h->ws[r];
         const int64_t n = h->plan.n;
-        double* V = h->dV.as<double>();
-        KState* st = h->dState.as<KState>();
+        double* V = W.dV.as<double>();
+        KState* st = W.dState.as<KState>();
         const int nb = vec_blocks(n), nbr = red_blocks(n);
-        vp[i] = VecProb{V, h->dW.as<double>(), h->dPart.as<double>(), st, n, 2 * n, nb, b0,
+        vp[i] = VecProb{V, W.dW.as<double>(), W.dPart.as<double>(), st, n, 2 * n, nb, b0,
                         nbr, b0r};
         bmap.insert(bmap.end(), nb, i);
         bmapr.insert(bmapr.end(), nbr, i);
@@ -367,8 +397,8 @@ int group_prepare(Group& g, int kdim) {
         b0r += nbr;
         for (int j = 0; j < kMaxKrylov; ++j)
             // the products take slot j as it is (not yet normalised): no input scale
-            pp[(size_t)j * np + i] = make_ptrs(h, prec, j < h->kcap ? V + (int64_t)j * 2 * n : nullptr,
-                                               h->dW.as<double>(), nullptr, &st->broken);
+            pp[(size_t)j * np + i] = make_ptrs(h, prec, j < W.kcap ? V + (int64_t)j * 2 * n : nullptr,
+                                               W.dW.as<double>(), nullptr, &st->broken, r);
     }
     HIP_TRY(h0, upload(g.dVP, vp, h0->stream));
     if (np > 1) HIP_TRY(h0, upload(g.dBmap, bmap, h0->stream));
@@ -378,7 +408,7 @@ int group_prepare(Group& g, int kdim) {
                     np > 1 ? g.dBmapR.as<int>() : nullptr, np, b0, b0r, 4};
     g.prec = prec;
     g.gens.resize(np);
-    for (int i = 0; i < np; ++i) g.gens[i] = g.hs[i]->gen;
+    for (int i = 0; i < np; ++i) g.gens[i] = g.hs[i]->ws[g.rhs[i]].gen;
     return DMRG_OK;
 }
 
@@ -455,7 +485,7 @@ void fill_info(const KState& st, dmrg_krylov_info* info) {
 int read_info(dmrg_handle h, dmrg_krylov_info* info) {
     if (!info) return DMRG_OK;
     KState st;
-    HIP_TRY(h, hipMemcpyAsync(&st, h->dState.p, sizeof(KState), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipMemcpyAsync(&st, h->ws[0].dState.p, sizeof(KState), hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     fill_info(st, info);
     if (st.exp_fail) return fail(h, DMRG_ENONFINITE, "Krylov exponential coefficients are not finite");
@@ -470,6 +500,78 @@ void tst_weights(double* weights) {
     weights[2] = W;
     weights[3] = W;
     weights[4] = 2 * W;
+}
+
+// The launch set of the 4-RHS mode over `owners`: member 4 i + r is chain r of owners[i], with
+// its own workspace; the work lists are the owners' plans, each repeated for its four chains, so
+// every block-product launch carries all chains.  Built on first use.
+int chains_set(std::unique_ptr<dmrg_batch_ctx>& cs, const std::vector<dmrg_ctx*>& owners) {
+    if (cs) return DMRG_OK;
+    dmrg_ctx* h0 = owners[0];
+    std::unique_ptr<dmrg_batch_ctx> c(new (std::nothrow) dmrg_batch_ctx());
+    if (!c) return fail(h0, DMRG_ENOMEM, "host memory for the chain tables");
+    Group& g = c->g;
+    g.lists = &c->lists;
+    try {
+        std::vector<const Plan*> plans;
+        for (dmrg_ctx* h : owners)
+            for (int r = 0; r < kChains; ++r) {
+                g.hs.push_back(h);
+                g.rhs.push_back(r);
+                plans.push_back(&h->plan);
+            }
+        Merged M;
+        merge_plans(plans, M);
+        const hipError_t e = upload_lists(c->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles1n,
+                                          M.tiles2, M.tiles2n, M.l1, M.l2, M.lred, M.nslots,
+                                          h0->stream);
+        if (e != hipSuccess)
+            return fail(h0, e == hipErrorOutOfMemory ? DMRG_ENOMEM : DMRG_EHIP, hipGetErrorString(e));
+    } catch (const std::bad_alloc&) {
+        return fail(h0, DMRG_ENOMEM, "host memory for the chain tables");
+    }
+    cs = std::move(c);
+    return DMRG_OK;
+}
+
+// One step of every chain of a 4-RHS launch set: targets[k] = exp(-i tau H) phi[k] (Krylov
+// basis of kdim vectors from phi[k]; targets[k] may alias phi[k]).
+int run_chains(dmrg_batch_ctx& cs, int variant, bool graph, const double* const* phi, double tau,
+               int kdim, double* const* targets, dmrg_krylov_info* infos) {
+    Group& g = cs.g;
+    dmrg_ctx* h0 = g.hs[0];
+    const int np = (int)g.hs.size();
+    for (int i = 0; i < np; ++i)
+        if (!phi[i] || !targets[i]) return fail(h0, DMRG_EINVAL, "NULL vector among the chains");
+    cs.lists.variant = variant;
+    g.use_graph = graph;
+    int rc = group_prepare(g, kdim);
+    if (rc) return rc;
+    hipStream_t s = h0->stream;
+    std::vector<const void*> io((size_t)np * (1 + kMaxTimes));
+    for (int i = 0; i < np; ++i) {
+        io[i] = phi[i];
+        for (int x = 0; x < kMaxTimes; ++x) io[np + (size_t)i * kMaxTimes + x] = targets[i];
+    }
+    rc = group_io(g, io, s);
+    if (rc) return rc;
+    const double* const* xt = g.dIO.as<const double*>();
+    double* const* yst = g.dIO.as<double*>() + np;
+    HIP_TRY(h0, launch_start(g.vg, nullptr, xt, kdim, 1, s));
+    rc = group_basis(g, kdim, s);
+    if (rc) return rc;
+    HIP_TRY(h0, launch_tridiag(g.vg, &tau, 1, s));
+    HIP_TRY(h0, launch_combine(g.vg, nullptr, yst, 1, 0, s));
+    if (!infos) return DMRG_OK;
+    std::vector<KState> st(np);
+    for (int i = 0; i < np; ++i)
+        HIP_TRY(h0, hipMemcpyAsync(&st[i], g.hs[i]->ws[g.rhs[i]].dState.p, sizeof(KState),
+                                   hipMemcpyDeviceToHost, s));
+    HIP_TRY(h0, hipStreamSynchronize(s));
+    for (int i = 0; i < np; ++i) fill_info(st[i], &infos[i]);
+    for (int i = 0; i < np; ++i)
+        if (st[i].exp_fail) return fail(h0, DMRG_ENONFINITE, "Krylov exponential coefficients are not finite");
+    return DMRG_OK;
 }
 
 int check_krylov_args(dmrg_handle h, double tau, int kdim) {
@@ -504,6 +606,7 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
     }
     h->stream = static_cast<hipStream_t>(stream);
     h->self.hs.assign(1, h);
+    h->self.rhs.assign(1, 0);
     const Plan& P = h->plan;
     hipError_t e = hipSuccess;
     h->self.lists = &h->lists;
@@ -519,10 +622,11 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
                          lr, ns,
                          h->stream);
     }
-    if (e == hipSuccess) e = h->dT.alloc(sizeof(double) * (size_t)P.T_size);
+    if (e == hipSuccess) e = h->ws[0].dT.alloc(sizeof(double) * (size_t)P.T_size);
     // the padding rows of the stage-1 workspace are read (times zero factors) but never
     // written: they must hold finite values, so the workspace starts zeroed
-    if (e == hipSuccess) e = hipMemsetAsync(h->dT.p, 0, sizeof(double) * (size_t)P.T_size, h->stream);
+    if (e == hipSuccess)
+        e = hipMemsetAsync(h->ws[0].dT.p, 0, sizeof(double) * (size_t)P.T_size, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
         delete h;
@@ -576,7 +680,8 @@ int dmrg_set_precision(dmrg_handle h, int32_t precision) {
         // different element sizes: padding positions of the new layout may hold bytes of the
         // old one, and they must be finite (they meet zero factors), so start from zeros again
         const size_t bytes = sizeof(double) * (size_t)h->plan.T_size;
-        HIP_TRY(h, hipMemsetAsync(h->dT.p, 0, bytes, h->stream));
+        for (Workspace& W : h->ws)
+            if (W.dT.p) HIP_TRY(h, hipMemsetAsync(W.dT.p, 0, bytes, h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
     }
     h->precision = precision;
@@ -649,6 +754,20 @@ int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim,
     return read_info(h, info);
 }
 
+int dmrg_tst_chains(dmrg_handle h, const double* const* phi, double tau, int32_t kdim,
+                    double* const* targets, double* weights, dmrg_krylov_info* infos) {
+    if (!h) return DMRG_EINVAL;
+    if (!phi || !targets) return fail(h, DMRG_EINVAL, "NULL pointer array");
+    int rc = check_krylov_args(h, tau, kdim);
+    if (rc) return rc;
+    rc = chains_set(h->chains, std::vector<dmrg_ctx*>(1, h));
+    if (rc) return rc;
+    rc = run_chains(*h->chains, h->lists.variant, h->self.use_graph, phi, tau, kdim, targets, infos);
+    if (rc) return rc;
+    tst_weights(weights);
+    return DMRG_OK;
+}
+
 int dmrg_set_graph(dmrg_handle h, int32_t enable) {
     if (!h) return DMRG_EINVAL;
     h->self.use_graph = enable != 0;
@@ -668,6 +787,7 @@ int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out
     if (!b) return DMRG_ENOMEM;
     Group& g = b->g;
     g.hs.assign(handles, handles + count);
+    g.rhs.assign(count, 0);
     g.lists = &b->lists;
     g.use_graph = true;
     dmrg_ctx* h0 = g.hs[0];
@@ -737,11 +857,26 @@ int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, i
     if (!infos) return DMRG_OK;
     std::vector<KState> st(np);
     for (int i = 0; i < np; ++i)
-        HIP_TRY(h0, hipMemcpyAsync(&st[i], g.hs[i]->dState.p, sizeof(KState), hipMemcpyDeviceToHost, s));
+        HIP_TRY(h0, hipMemcpyAsync(&st[i], g.hs[i]->ws[g.rhs[i]].dState.p, sizeof(KState),
+                                   hipMemcpyDeviceToHost, s));
     HIP_TRY(h0, hipStreamSynchronize(s));
     for (int i = 0; i < np; ++i) fill_info(st[i], &infos[i]);
     for (int i = 0; i < np; ++i)
         if (st[i].exp_fail) return fail(h0, DMRG_ENONFINITE, "Krylov exponential coefficients are not finite");
+    return DMRG_OK;
+}
+
+int dmrg_batch_tst_chains(dmrg_batch b, const double* const* phi, double tau, int32_t kdim,
+                          double* const* targets, double* weights, dmrg_krylov_info* infos) {
+    if (!b || !phi || !targets) return DMRG_EINVAL;
+    dmrg_ctx* h0 = b->g.hs[0];
+    int rc = check_krylov_args(h0, tau, kdim);
+    if (rc) return rc;
+    rc = chains_set(b->chains, b->g.hs);
+    if (rc) return rc;
+    rc = run_chains(*b->chains, b->lists.variant, b->g.use_graph, phi, tau, kdim, targets, infos);
+    if (rc) return rc;
+    tst_weights(weights);
     return DMRG_OK;
 }
 
@@ -779,9 +914,9 @@ int dmrg_autotune(dmrg_handle h, int32_t reps, double* out) {
     if (rc) return rc;
     // timing inputs: basis slot 0 (zeroed) into the work vector
     const size_t bytes = sizeof(double) * 2 * (size_t)h->plan.n;
-    HIP_TRY(h, hipMemsetAsync(h->dV.p, 0, bytes, h->stream));
-    const ProbPtrs pp = make_ptrs(h, h->precision, h->dV.as<double>(), h->dW.as<double>(), nullptr,
-                                  nullptr);
+    HIP_TRY(h, hipMemsetAsync(h->ws[0].dV.p, 0, bytes, h->stream));
+    const ProbPtrs pp = make_ptrs(h, h->precision, h->ws[0].dV.as<double>(), h->ws[0].dW.as<double>(),
+                                  nullptr, nullptr);
     HIP_TRY(h, autotune_lists(h->lists, h->precision, nullptr, pp, h->stream, reps, out));
     return DMRG_OK;
 }
@@ -801,7 +936,7 @@ int dmrg_batch_autotune(dmrg_batch b, int32_t reps, double* out) {
     int rc = group_prepare(g, 1);
     if (rc) return rc;
     for (dmrg_ctx* h : g.hs)
-        HIP_TRY(h0, hipMemsetAsync(h->dV.p, 0, sizeof(double) * 2 * (size_t)h->plan.n, h0->stream));
+        HIP_TRY(h0, hipMemsetAsync(h->ws[0].dV.p, 0, sizeof(double) * 2 * (size_t)h->plan.n, h0->stream));
     // row 0 of the product table: basis slot 0 into the work vector of every problem
     HIP_TRY(h0, autotune_lists(b->lists, g.prec, g.dProbs.as<ProbPtrs>(), ProbPtrs{}, h0->stream,
                                reps, out));

@@ -28,6 +28,7 @@ SYMBOLS = [
     "dmrg_set_gemm", "dmrg_get_gemm", "dmrg_autotune",
     "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_set_graph", "dmrg_batch_tst_targets",
     "dmrg_batch_set_gemm", "dmrg_batch_autotune", "dmrg_profile_matvec",
+    "dmrg_tst_chains", "dmrg_batch_tst_chains",
     "dmrg_strerror", "dmrg_last_error",
 ]
 
@@ -100,6 +101,9 @@ def load(path: str = LIB_PATH):
     lib.dmrg_batch_tst_targets.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl),
                                            P(dmrg_krylov_info)]
     lib.dmrg_profile_matvec.argtypes = [vp, vp, vp, i32, P(dbl)]
+    lib.dmrg_tst_chains.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl), P(dmrg_krylov_info)]
+    lib.dmrg_batch_tst_chains.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl),
+                                          P(dmrg_krylov_info)]
     lib.dmrg_strerror.argtypes = [i32]
     lib.dmrg_strerror.restype = C.c_char_p
     lib.dmrg_last_error.argtypes = [vp]
@@ -287,6 +291,20 @@ class Handle:
 
     tst_targets = dmrg_tst_targets
 
+    def dmrg_tst_chains(self, phis, tau: float, kdim: int, targets, info: bool = True):
+        """4-RHS mode: targets[k] = exp(-i tau H) phis[k] for four device vectors, in common
+        launches."""
+        n2 = 2 * self.n
+        ph = (C.c_void_p * 4)(*[_tensor_ptr(p, n2).value for p in phis])
+        tg = (C.c_void_p * 4)(*[_tensor_ptr(t, n2).value for t in targets])
+        w = np.zeros(5)
+        infos = (dmrg_krylov_info * 4)()
+        _check(self.lib.dmrg_tst_chains(self.h, ph, float(tau), int(kdim), tg, _dptr(w, C.c_double),
+                                        infos if info else None), self.h)
+        return w, ([i.as_dict() for i in infos] if info else None)
+
+    tst_chains = dmrg_tst_chains
+
     def dmrg_set_graph(self, enable: bool):
         _check(self.lib.dmrg_set_graph(self.h, int(bool(enable))), self.h)
 
@@ -370,6 +388,23 @@ class Batch:
         return w, ([i.as_dict() for i in infos] if info else None)
 
     batch_tst_targets = dmrg_batch_tst_targets
+
+    def dmrg_batch_tst_chains(self, phis, tau: float, kdim: int, targets, info: bool = True):
+        """4-RHS mode of every superblock: phis, targets: 4 x count device vectors, chain k of
+        superblock i at [4 i + k]."""
+        cnt = 4 * len(self.handles)
+        hs = [h for h in self.handles for _ in range(4)]
+        ph = (C.c_void_p * cnt)(*[_tensor_ptr(p, 2 * h.n).value for p, h in zip(phis, hs)])
+        tg = (C.c_void_p * cnt)(*[_tensor_ptr(t, 2 * h.n).value for t, h in zip(targets, hs)])
+        w = np.zeros(5)
+        infos = (dmrg_krylov_info * cnt)()
+        rc = self.lib.dmrg_batch_tst_chains(self.b, ph, float(tau), int(kdim), tg,
+                                            _dptr(w, C.c_double), infos if info else None)
+        if rc != 0:
+            _check(rc, self.handles[0].h)
+        return w, ([i.as_dict() for i in infos] if info else None)
+
+    batch_tst_chains = dmrg_batch_tst_chains
 
     def dmrg_batch_destroy(self):
         if self.b:

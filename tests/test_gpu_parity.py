@@ -365,6 +365,68 @@ def test_krylov_mixed_precision_norm_and_error(env, prec):
 # Both run the same kernels on the same per-problem data as the single-handle eager path, so
 # the results must agree bit for bit; the small batch is also checked against the oracle.
 # ---------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("name,kdim,tau", [("chain12_m30", 15, 0.1), ("chain8_m17_odd", 12, 0.1),
+                                           ("ladder16_m1000", 15, 0.05)])
+def test_tst_chains_parity(env, name, kdim, tau):
+    """4-RHS mode: four different vectors, each advanced by tau with its own basis, against the
+    oracle's per-target chains; in place (targets = inputs) gives the same vectors; graph mode
+    gives the same bits."""
+    torch, L = env
+    say("tst chains", name)
+    pb = problem(name)
+    h = L.dmrg_create(pb)
+    n = h.n
+    xs = [I.random_psi(n, np.random.default_rng(I.SEED_BASE + 40 + k)) for k in range(4)]
+    xds = [_dev(torch, x) for x in xs]
+    yds = [torch.full((2 * n,), float("nan"), dtype=torch.float64, device="cuda") for _ in range(4)]
+    w, infos = h.tst_chains(xds, tau, kdim, yds)
+    ys, wref, oinfos = K.tst_chains(lambda v: M.matvec_sector(pb, v), xs, tau, kdim)
+    assert np.array_equal(w, wref)
+    for k in range(4):
+        err = rel(_host(yds[k]), ys[k])
+        say("  chain", k, "rel err", err, infos[k])
+        assert err <= KR_TOL
+        assert infos[k]["k_eff"] == oinfos[k].k_eff[-1]
+    h.set_graph(True)
+    zds = [torch.full_like(xds[0], float("nan")) for _ in range(4)]
+    h.tst_chains(xds, tau, kdim, zds)
+    assert all(torch.equal(z, y) for z, y in zip(zds, yds))
+    inplace = [x.clone() for x in xds]
+    h.tst_chains(inplace, tau, kdim, inplace)
+    assert all(torch.equal(a, y) for a, y in zip(inplace, yds))
+    h.destroy()
+
+
+def test_batch_tst_chains_matches_per_handle(env):
+    """4-RHS mode of a batch (odd and even lengths, 12 chains in common launches): bit for bit
+    the per-handle chains, and the oracle to 1e-10."""
+    torch, L = env
+    say("batch chains")
+    pbs = [problem("chain12_m30"), problem("chain8_m17_odd"), problem("chain14_m25_off")]
+    hs = [L.dmrg_create(pb) for pb in pbs]
+    tau, kdim = 0.1, 12
+    xs, xds, yds = [], [], []
+    for i, h in enumerate(hs):
+        for k in range(4):
+            x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 600 + 4 * i + k))
+            xs.append(x)
+            xds.append(_dev(torch, x))
+            yds.append(torch.full((2 * h.n,), float("nan"), dtype=torch.float64, device="cuda"))
+    b = L.Batch(hs)
+    w, infos = b.batch_tst_chains(xds, tau, kdim, yds)
+    for i, (pb, h) in enumerate(zip(pbs, hs)):
+        own = [torch.empty_like(xds[4 * i + k]) for k in range(4)]
+        _, inf1 = h.tst_chains(xds[4 * i:4 * i + 4], tau, kdim, own)
+        ys, _, _ = K.tst_chains(lambda v: M.matvec_sector(pb, v), xs[4 * i:4 * i + 4], tau, kdim)
+        for k in range(4):
+            assert torch.equal(own[k], yds[4 * i + k])
+            assert inf1[k] == infos[4 * i + k]
+            assert rel(_host(yds[4 * i + k]), ys[k]) <= KR_TOL
+    b.destroy()
+    for h in hs:
+        h.destroy()
+
+
 def _batch_setup(torch, L, pbs, seed):
     hs = [L.dmrg_create(pb) for pb in pbs]
     phis = [I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + seed + i)) for i, h in enumerate(hs)]

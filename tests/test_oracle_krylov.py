@@ -160,6 +160,26 @@ def test_tst_targets_and_weights():
         assert np.linalg.norm(x - expm_flat(H, phi, t)) < 1e-10
 
 
+def test_tst_chains_against_dense_expm():
+    """The per-target chains: four different vectors (here the shared-basis targets), each
+    advanced by tau, against the dense exponential; chains are independent of each other (the
+    same vector gives the same result whatever the others are)."""
+    pb, sec, H, perm = exact_case(8, 4.0, (4, 4))
+    lay, n = M.layout(pb)
+    phi = I.random_psi(n, np.random.default_rng(13))
+    tau = 0.1
+    starts, _, _ = K.tst_targets(_apply(pb), phi, tau, kdim=12)
+    ys, w, infos = K.tst_chains(_apply(pb), starts, tau, kdim=12)
+    assert np.array_equal(w * 8, np.array(GOLDEN["tst_weights"]["weights_times_8"], dtype=float))
+    for x0, y, info in zip(starts, ys, infos):
+        assert np.linalg.norm(y - expm_flat(H, x0, tau)) < 1e-10
+        assert abs(np.linalg.norm(y) - np.linalg.norm(x0)) < 1e-13
+        assert info.err_est < 1e-8
+    other = [starts[0], phi, phi, phi]
+    ys2, _, _ = K.tst_chains(_apply(pb), other, tau, kdim=12)
+    assert np.array_equal(ys2[0], ys[0])
+
+
 def test_error_estimate_bounds_true_error():
     pb, sec, H, perm = exact_case(8, 4.0, (4, 4))
     lay, n = M.layout(pb)
