@@ -34,11 +34,11 @@ PEAK_HBM_GBS = 8000.0
 # in profiles/).  Valid only for the kernel source they were taken on: reported as null once
 # the source differs.
 MEASURED_TRAFFIC = {
-    "kernel": "stage2<PF64>",
+    "kernel": "stage2<PF64, 1, 4>",
     "workload": "ladder16_m1000",
     "source": "paper_1103_5391_amd/csrc/gemm.hip",
-    "source_sha256": "f94be671af094b9bfcfd91180b511d35ab52bf442eee8fada72e0b6b69e778ea",
-    "bytes": 85.00e6 + 4.98e6,
+    "source_sha256": "b77e06c0d246e917d715002a31ca0250cf2d152dac785479a1a2835ae704666d",
+    "bytes": 83.27e6 + 5.13e6,
     "profile": "profiles/stage2_fp64_ladder16_m1000_kernel_stats.txt",
 }
 
@@ -252,6 +252,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-mixed", action="store_true", help="FP64 only (no mixed-arithmetic runs)")
     ap.add_argument("--no-drift", action="store_true", help="skip the 50-step m = 2000 drift run")
+    ap.add_argument("--no-rhs4", action="store_true", help="skip the 4-RHS (per-target) mode run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a buffer of MIB MiB once before the run: a plain copy kernel of "
                          "known traffic that hardware-counter runs use as the byte scale")
@@ -315,22 +316,24 @@ def main():
 
     # 4-RHS (per-target) mode on the same workload: the four targets as four chains advanced
     # by tau in common launches
-    cx = [td[2 * n * k:2 * n * (k + 1)].clone() for k in range(4)]
-    cy = [torch.empty_like(x) for x in cx]
-    for _ in range(args.warmup):
-        h.tst_chains(cx, tau, kdim, cy, info=False)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    for _ in range(args.steps):
-        h.tst_chains(cx, tau, kdim, cy, info=False)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    ms_rhs4 = e0.elapsed_time(e1) / args.steps
-    rhs4 = {"ms_per_step": round(ms_rhs4, 5), "chains": 4,
-            "tflops": round(4 * kdim * F / (ms_rhs4 * 1e-3) / 1e12, 4),
-            "chain_steps_per_s": round(4000.0 / ms_rhs4, 3),
-            "per_chain_speedup_vs_single": round(4 * ms_step / ms_rhs4, 3)}
-    print(f"[bench] 4-RHS mode: {rhs4}", file=sys.stderr, flush=True)
+    rhs4 = None
+    cx = [] if args.no_rhs4 else [td[2 * n * k:2 * n * (k + 1)].clone() for k in range(4)]
+    if not args.no_rhs4:
+        cy = [torch.empty_like(x) for x in cx]
+        for _ in range(args.warmup):
+            h.tst_chains(cx, tau, kdim, cy, info=False)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(args.steps):
+            h.tst_chains(cx, tau, kdim, cy, info=False)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_rhs4 = e0.elapsed_time(e1) / args.steps
+        rhs4 = {"ms_per_step": round(ms_rhs4, 5), "chains": 4,
+                "tflops": round(4 * kdim * F / (ms_rhs4 * 1e-3) / 1e12, 4),
+                "chain_steps_per_s": round(4000.0 / ms_rhs4, 3),
+                "per_chain_speedup_vs_single": round(4 * ms_step / ms_rhs4, 3)}
+        print(f"[bench] 4-RHS mode: {rhs4}", file=sys.stderr, flush=True)
 
     # product-only rate and the dominant kernel (HIP events around each launch)
     yd = torch.empty_like(pd)
