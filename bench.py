@@ -253,6 +253,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true", help="FP64 only (no mixed-arithmetic runs)")
     ap.add_argument("--no-drift", action="store_true", help="skip the 50-step m = 2000 drift run")
     ap.add_argument("--no-rhs4", action="store_true", help="skip the 4-RHS (per-target) mode run")
+    ap.add_argument("--no-gs", action="store_true", help="skip the ground-state run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a buffer of MIB MiB once before the run: a plain copy kernel of "
                          "known traffic that hardware-counter runs use as the byte scale")
@@ -334,6 +335,25 @@ def main():
                 "chain_steps_per_s": round(4000.0 / ms_rhs4, 3),
                 "per_chain_speedup_vs_single": round(4 * ms_step / ms_rhs4, 3)}
         print(f"[bench] 4-RHS mode: {rhs4}", file=sys.stderr, flush=True)
+
+    # ground state of the same superblock by restarted Lanczos (kdim 40, to a relative residual
+    # of 1e-6 or 60 bases; the synthetic spectrum is dense at the bottom, so restarts converge
+    # slowly)
+    gs = None
+    if not args.no_gs:
+        gd = pd.clone()
+        yg = torch.empty_like(gd)
+        h.ground_state(gd, yg, 40, 1, 0.0, info=False)      # warm-up (tables sized for kdim 40)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        e_gs, used, ginfo = h.ground_state(gd, yg, 40, 60, 1e-6)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        gs = {"kdim": 40, "tol": 1e-6, "energy": e_gs, "bases": used,
+              "residual_est": ginfo["err_est"], "ms_total": round(el * 1e3, 3),
+              "ms_per_basis": round(el * 1e3 / used, 4),
+              "tflops": round(40 * used * F / el / 1e12, 4)}
+        print(f"[bench] ground state: {gs}", file=sys.stderr, flush=True)
 
     # product-only rate and the dominant kernel (HIP events around each launch)
     yd = torch.empty_like(pd)
@@ -429,6 +449,7 @@ def main():
         "matvec_ms": round(ms_mv, 5),
         "mfma_peak_frac_step": round(value / PEAK_FP64_TFLOPS, 4),
         "rhs4_mode": rhs4,
+        "ground_state": gs,
         "mixed_precision": mixed,
         "batched_64": batched,
         "drift_m2000": drift,

@@ -210,6 +210,19 @@ int dmrg_krylov_expm(dmrg_handle h, const double* x, double* y, double tau, int3
 int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim,
                      double* targets, double* weights, dmrg_krylov_info* info);
 
+/* Ground state of H_sb by restarted Lanczos (the ground-state target of Sec. II.B, weight 2W;
+ * the same Krylov basis as dmrg_krylov_expm, Sec. II.A, with the lowest eigenpair of the
+ * Lanczos matrix T in place of its exponential): up to max_restarts bases of kdim vectors, each
+ * started from the previous Ritz vector (the first from x0), until the residual estimate
+ * beta_kdim |z_{kdim-1}| = ||H y - E y|| is at most tol max(1, |E|).  y: the unit Ritz vector
+ * (device, 2n doubles; may equal x0).  energy, restarts: NULL or host scalars receiving E and the
+ * bases used; info as in dmrg_krylov_expm (err_est is the last residual estimate).  The call
+ * waits for the stream after every basis (to test convergence).  DMRG_EINVAL for kdim outside
+ * [1, 64], max_restarts < 1 or a negative tol. */
+int dmrg_ground_state(dmrg_handle h, const double* x0, double* y, int32_t kdim,
+                      int32_t max_restarts, double tol, double* energy, int32_t* restarts,
+                      dmrg_krylov_info* info);
+
 /* 4-RHS (per-target) mode of time-step targeting: the four targets are kept as four independent
  * chains, each advanced by exp(-i tau H) with a Krylov basis of its own (kdim vectors, Sec. II.A)
  * instead of one basis evaluated at four times (the variant of the seeding of the next

@@ -11,6 +11,9 @@ Sec. II.C: larger times by repeating the step from the evolved vector, Eq. (lanc
 Sec. II.B/II.C: time-step targeting keeps n_v = 4 equally spaced times 0, tau/3, 2tau/3, tau
 from one Krylov basis, with weights 2W for the ground state and the first and last time
 vector and W for the others, W = 1/(n + 3), n = 5 targets including the ground state.
+Ground-state targeting (Sec. II.B, the ground state is a target of weight 2W): the same
+Lanczos basis, with the lowest eigenpair of T in place of its exponential, restarted from the
+Ritz vector until the residual estimate beta_k |z_{k-1}| is small.
 Per-target (4-RHS) variant of the seeding of the next interval (Sec. II.C leaves it open): each
 target is its own chain, advanced by one Krylov step exp(-i tau H) from its current vector; it
 agrees with the shared-basis targets only to Krylov error, so it has its own oracle function.
@@ -176,3 +179,29 @@ def tst_chains(apply_h, phis, tau: float, kdim: int):
         ys.append(y)
         infos.append(info)
     return ys, tst_weights(len(phis)), infos
+
+
+@dataclass
+class GroundInfo:
+    energy: float
+    restarts: int
+    residual_est: float
+    k_eff: int
+
+
+def ground_state(apply_h, x0: np.ndarray, kdim: int, max_restarts: int = 20, tol: float = 1e-10):
+    """Lowest eigenpair of H by restarted Lanczos: basis of kdim vectors from the current vector,
+    the lowest eigenpair (lam, z) of T (z real, unit, its largest entry positive), Ritz vector
+    y = V^T z; restart from y until beta_k |z_{k-1}| <= tol max(1, |lam|) or max_restarts bases."""
+    x = x0
+    for r in range(max_restarts):
+        b = lanczos(apply_h, x, kdim)
+        k = b.k_eff
+        D, S = eigh_tridiagonal(b.alpha[:k], b.beta[1:k])
+        z = S[:, 0]
+        z = z * (1.0 if z[np.argmax(np.abs(z))] > 0 else -1.0)
+        y = combine(b, z.astype(complex))
+        res = 0.0 if b.breakdown else float(b.beta[k] * abs(z[-1]))
+        if res <= tol * max(1.0, abs(D[0])) or r == max_restarts - 1 or b.breakdown:
+            return y, GroundInfo(float(D[0]), r + 1, res, k)
+        x = y

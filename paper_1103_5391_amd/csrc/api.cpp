@@ -30,6 +30,7 @@ hipError_t launch_start(const VecGroup&, const double*, const double* const*, in
                         hipStream_t);
 hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
 hipError_t launch_tridiag(const VecGroup&, const double*, int, hipStream_t);
+hipError_t launch_lowest(const VecGroup&, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 int vec_blocks(int64_t n);
 int red_blocks(int64_t n);
@@ -752,6 +753,46 @@ int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim,
     HIP_TRY(h, launch_combine(g.vg, out, nullptr, 4, 0, h->stream));
     tst_weights(weights);
     return read_info(h, info);
+}
+
+int dmrg_ground_state(dmrg_handle h, const double* x0, double* y, int32_t kdim,
+                      int32_t max_restarts, double tol, double* energy, int32_t* restarts,
+                      dmrg_krylov_info* info) {
+    if (!h) return DMRG_EINVAL;
+    if (!x0 || !y) return fail(h, DMRG_EINVAL, "NULL vector");
+    if (max_restarts < 1) return fail(h, DMRG_EINVAL, "max_restarts < 1");
+    if (!(tol >= 0.0)) return fail(h, DMRG_EINVAL, "tol must be a non-negative number");
+    int rc = check_krylov_args(h, 0.0, kdim);
+    if (rc) return rc;
+    Group& g = h->self;
+    rc = group_prepare(g, kdim);
+    if (rc) return rc;
+    HIP_TRY(h, launch_start(g.vg, x0, nullptr, kdim, 1, h->stream));
+    KState st;
+    int used = 0;
+    for (int r = 0; r < max_restarts; ++r) {
+        rc = group_basis(g, kdim, h->stream);
+        if (rc) return rc;
+        HIP_TRY(h, launch_lowest(g.vg, h->stream));
+        ++used;
+        HIP_TRY(h, hipMemcpyAsync(&st, h->ws[0].dState.p, sizeof(KState), hipMemcpyDeviceToHost,
+                                  h->stream));
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        if (st.exp_fail) return fail(h, DMRG_ENONFINITE, "ground-state eigenpair is not finite");
+        const bool done = st.err_est <= tol * std::max(1.0, std::fabs(st.eig)) ||
+                          r == max_restarts - 1 || st.keff <= 0;
+        double* out[1] = {y};
+        // converged (or out of restarts): the Ritz vector into y; else into slot 0, restart
+        HIP_TRY(h, launch_combine(g.vg, done ? out : nullptr, nullptr, 1, done ? 0 : 1, h->stream));
+        if (done) break;
+    }
+    if (energy) *energy = st.eig;
+    if (restarts) *restarts = used;
+    if (info) {
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        fill_info(st, info);
+    }
+    return DMRG_OK;
 }
 
 int dmrg_tst_chains(dmrg_handle h, const double* const* phi, double tau, int32_t kdim,

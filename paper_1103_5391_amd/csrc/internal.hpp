@@ -160,6 +160,7 @@ struct KState {
     int32_t keff_min;                 // over all steps of one call
     int32_t any_break;                // over all steps of one call
     double beta0_first;               // ||x|| of the first step of one call
+    double eig;                       // lowest eigenvalue of the Lanczos matrix (ground state)
 };
 
 }  // namespace dmrg

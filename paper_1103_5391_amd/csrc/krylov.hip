@@ -724,6 +724,138 @@ __global__ __launch_bounds__(64) void k_tridiag_expm(const VecProb* vp, double t
 }
 
 // ---------------------------------------------------------------------------------------
+// Ground-state targeting (the same Lanczos basis, with the lowest eigenpair of T in place of
+// the exponential): one wavefront per problem.  The lowest eigenvalue lambda of the k x k
+// tridiagonal T is found by multisection of its Gershgorin interval: each round, lane l counts
+// the eigenvalues below the l-th of 64 interior points (Sturm sequence of the LDL^T pivots) and
+// the interval shrinks to the first gap that holds lambda, 65 times narrower.  Its eigenvector z
+// then comes from three steps of inverse iteration on T - lambda, solved by Gaussian
+// elimination with partial pivoting (lane 0, O(k) per solve, tiny pivots replaced by a floor).
+// Output: coef[0] = z (real, unit norm; the combination gives the unit Ritz vector V z),
+// eig = lambda, err_est = beta_k |z_{k-1}| (the residual norm ||H V z - lambda V z||).
+// ---------------------------------------------------------------------------------------
+__global__ __launch_bounds__(64) void k_tridiag_lowest(const VecProb* vp) {
+    KState* st = vp[blockIdx.x].st;
+    const int r = threadIdx.x;
+    const int k = st->keff;
+    if (k <= 0) {
+        st->coef[0][2 * r] = 0.0;
+        st->coef[0][2 * r + 1] = 0.0;
+        if (r == 0) {
+            st->err_est = 0.0;
+            st->eig = 0.0;
+            st->keff_min = 0;
+            st->any_break = 1;
+        }
+        return;
+    }
+    __shared__ double al[kMaxKrylov], bt[kMaxKrylov];   // alpha_i; beta_i couples i - 1 and i
+    const bool in = r < k;
+    const double a = in ? st->alpha[r] : 0.0;
+    const double bl = (in && r >= 1) ? st->beta[r] : 0.0;
+    const double bu = (r + 1 < k) ? st->beta[r + 1] : 0.0;
+    al[r] = a;
+    bt[r] = bl;
+    const double reach = fabs(bl) + fabs(bu);
+    double hi = wave_max(in ? a + reach : -INFINITY);
+    double lo = -wave_max(in ? reach - a : -INFINITY);
+    const double tnorm = fmax(fabs(hi), fabs(lo));
+    const double pivmin = 1e-290 * fmax(1.0, tnorm * tnorm);
+    __syncthreads();
+    // multisection: count(x) = number of eigenvalues below x
+    for (int it = 0; it < 16; ++it) {
+        const double x = lo + (hi - lo) * (double)(r + 1) / 65.0;
+        int cnt = 0;
+        double d = 1.0;
+        for (int i = 0; i < k; ++i) {
+            d = (al[i] - x) - (i ? bt[i] * bt[i] / d : 0.0);
+            if (fabs(d) < pivmin) d = -pivmin;
+            cnt += d < 0.0;
+        }
+        const unsigned long long m = __ballot(cnt >= 1);
+        const int f = m ? __ffsll(m) - 1 : 64;     // first point above lambda (64: the top end)
+        const double nlo = f == 0 ? lo : lo + (hi - lo) * (double)f / 65.0;
+        const double nhi = f == 64 ? hi : lo + (hi - lo) * (double)(f + 1) / 65.0;
+        lo = nlo;
+        hi = nhi;
+        if (hi - lo <= 4.0 * 2.220446049250313e-16 * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+    }
+    const double lam = 0.5 * (lo + hi);
+    // factors of T - lam and the iterate, in LDS (lane 0 works on them serially)
+    __shared__ double d[kMaxKrylov], du[kMaxKrylov], du2[kMaxKrylov], dl[kMaxKrylov], z[kMaxKrylov];
+    __shared__ bool piv[kMaxKrylov];
+    if (r == 0) {
+        // inverse iteration: (T - lam) z = b, elimination with partial pivoting (rows i, i + 1)
+        const double floor = fmax(pivmin, 2.220446049250313e-16 * tnorm);
+        for (int i = 0; i < k; ++i) {
+            d[i] = al[i] - lam;
+            du[i] = i + 1 < k ? bt[i + 1] : 0.0;
+            dl[i] = i + 1 < k ? bt[i + 1] : 0.0;
+            du2[i] = 0.0;
+            z[i] = 1.0;
+        }
+        for (int i = 0; i + 1 < k; ++i) {
+            if (fabs(d[i]) >= fabs(dl[i])) {
+                piv[i] = false;
+                if (fabs(d[i]) < floor) d[i] = floor;
+                const double f = dl[i] / d[i];
+                dl[i] = f;
+                d[i + 1] -= f * du[i];
+            } else {
+                piv[i] = true;
+                const double f = d[i] / dl[i];
+                d[i] = dl[i];
+                dl[i] = f;
+                const double t = du[i];
+                du[i] = d[i + 1];
+                d[i + 1] = t - f * d[i + 1];
+                if (i + 2 < k) {
+                    du2[i] = du[i + 1];
+                    du[i + 1] = -f * du[i + 1];
+                }
+            }
+        }
+        if (fabs(d[k - 1]) < floor) d[k - 1] = floor;
+        for (int it = 0; it < 3; ++it) {
+            for (int i = 0; i + 1 < k; ++i) {       // apply the row operations to z
+                if (piv[i]) {
+                    const double t = z[i];
+                    z[i] = z[i + 1];
+                    z[i + 1] = t - dl[i] * z[i + 1];
+                } else {
+                    z[i + 1] -= dl[i] * z[i];
+                }
+            }
+            for (int i = k - 1; i >= 0; --i) {     // back substitution with U (three diagonals)
+                double t = z[i];
+                if (i + 1 < k) t -= du[i] * z[i + 1];
+                if (i + 2 < k) t -= du2[i] * z[i + 2];
+                z[i] = t / d[i];
+            }
+            double nrm = 0.0, big = 0.0;
+            int ib = 0;
+            for (int i = 0; i < k; ++i) {
+                nrm += z[i] * z[i];
+                if (fabs(z[i]) > big) {
+                    big = fabs(z[i]);
+                    ib = i;
+                }
+            }
+            const double s = (z[ib] < 0.0 ? -1.0 : 1.0) / sqrt(nrm);   // largest entry positive
+            for (int i = 0; i < k; ++i) z[i] *= s;
+        }
+        st->eig = lam;
+        st->err_est = st->broken ? 0.0 : fabs(st->beta[k] * z[k - 1]);
+        st->exp_fail = !isfinite(lam) || !isfinite(z[k - 1]);
+        st->keff_min = min(st->keff_min, k);
+        st->any_break = st->any_break | st->broken;
+    }
+    __syncthreads();
+    st->coef[0][2 * r] = in ? z[r] : 0.0;
+    st->coef[0][2 * r + 1] = 0.0;
+}
+
+// ---------------------------------------------------------------------------------------
 // combine: y_x = sum_{c < keff} coef_x[c] scale_c u_c for x < ntimes.  With chain != 0 the
 // single output is slot 0 itself (in place) and its norm seeds the next step.  Outputs of a
 // batch come from the table yst[problem * kMaxTimes + x].  Without chaining a pass may give
@@ -851,6 +983,11 @@ hipError_t launch_lanczos_iter(const VecGroup& g, int j, int kdim, hipStream_t s
     }
     hipLaunchKernelGGL(k_dsum, dim3(nq * kDVals / (kVecThreads / 64), g.nprob), blk, 0, s, g.vp);
     hipLaunchKernelGGL(k_dupdate, grid, blk, 0, s, g.vp, g.bmap, j, kdim, nc0);
+    return hipGetLastError();
+}
+
+hipError_t launch_lowest(const VecGroup& g, hipStream_t s) {
+    hipLaunchKernelGGL(k_tridiag_lowest, dim3(g.nprob), dim3(64), 0, s, g.vp);
     return hipGetLastError();
 }
 

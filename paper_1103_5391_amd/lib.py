@@ -28,7 +28,7 @@ SYMBOLS = [
     "dmrg_set_gemm", "dmrg_get_gemm", "dmrg_autotune",
     "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_set_graph", "dmrg_batch_tst_targets",
     "dmrg_batch_set_gemm", "dmrg_batch_autotune", "dmrg_profile_matvec",
-    "dmrg_tst_chains", "dmrg_batch_tst_chains",
+    "dmrg_tst_chains", "dmrg_batch_tst_chains", "dmrg_ground_state",
     "dmrg_strerror", "dmrg_last_error",
 ]
 
@@ -102,6 +102,7 @@ def load(path: str = LIB_PATH):
                                            P(dmrg_krylov_info)]
     lib.dmrg_profile_matvec.argtypes = [vp, vp, vp, i32, P(dbl)]
     lib.dmrg_tst_chains.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl), P(dmrg_krylov_info)]
+    lib.dmrg_ground_state.argtypes = [vp, vp, vp, i32, i32, dbl, P(dbl), P(i32), P(dmrg_krylov_info)]
     lib.dmrg_batch_tst_chains.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl),
                                           P(dmrg_krylov_info)]
     lib.dmrg_strerror.argtypes = [i32]
@@ -304,6 +305,21 @@ class Handle:
         return w, ([i.as_dict() for i in infos] if info else None)
 
     tst_chains = dmrg_tst_chains
+
+    def dmrg_ground_state(self, x0, y, kdim: int, max_restarts: int = 20, tol: float = 1e-10,
+                          info: bool = True):
+        """Restarted Lanczos ground state: y = unit Ritz vector; returns (energy, bases used,
+        info)."""
+        n2 = 2 * self.n
+        e = C.c_double()
+        used = C.c_int32()
+        inf = dmrg_krylov_info()
+        _check(self.lib.dmrg_ground_state(self.h, _tensor_ptr(x0, n2), _tensor_ptr(y, n2), int(kdim),
+                                          int(max_restarts), float(tol), C.byref(e), C.byref(used),
+                                          C.byref(inf) if info else None), self.h)
+        return e.value, used.value, (inf.as_dict() if info else None)
+
+    ground_state = dmrg_ground_state
 
     def dmrg_set_graph(self, enable: bool):
         _check(self.lib.dmrg_set_graph(self.h, int(bool(enable))), self.h)

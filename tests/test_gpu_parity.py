@@ -427,6 +427,54 @@ def test_batch_tst_chains_matches_per_handle(env):
         h.destroy()
 
 
+@pytest.mark.parametrize("name,kdim,restarts", [("chain8_exact", 20, 6), ("chain8_m17_odd", 12, 5),
+                                               ("chain12_m30", 16, 4), ("ladder16_m1000", 15, 3)])
+def test_ground_state_parity(env, name, kdim, restarts):
+    """Restarted Lanczos ground state with a fixed number of bases (tol 0): energy and Ritz
+    vector against the oracle's restarted Lanczos."""
+    torch, L = env
+    say("ground state", name)
+    pb = problem(name)
+    h = L.dmrg_create(pb)
+    x0 = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 70))
+    xd = _dev(torch, x0)
+    yd = torch.full_like(xd, float("nan"))
+    e, used, info = h.ground_state(xd, yd, kdim, restarts, 0.0)
+    yref, oinfo = K.ground_state(lambda v: M.matvec_sector(pb, v), x0, kdim, restarts, 0.0)
+    err = rel(_host(yd), yref)
+    say("  E", e, "oracle", oinfo.energy, "vector rel err", err, "bases", used, info)
+    assert used == oinfo.restarts
+    assert abs(e - oinfo.energy) <= 1e-10 * max(1.0, abs(oinfo.energy))
+    assert err <= 1e-8
+    assert abs(info["err_est"] - oinfo.residual_est) <= 1e-8 * max(1.0, oinfo.residual_est)
+    h.destroy()
+
+
+def test_ground_state_converges_to_exact(env):
+    """Exact-block chain (L = 8, U = 4): converged to tol 1e-11 in place (y = x0); the energy
+    against the lowest eigenvalue of the ED matrix (ARPACK) and the residual ||H y - E y||
+    through the library's own product."""
+    import scipy.sparse.linalg as spla
+    from tests.helpers import exact_case
+    torch, L = env
+    say("ground state converged")
+    pb, sec, H, perm = exact_case(8, 4.0, (4, 4))
+    h = L.dmrg_create(pb)
+    x0 = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 71))
+    xd = _dev(torch, x0)
+    e, used, info = h.ground_state(xd, xd, 30, 80, 1e-11)
+    e0 = float(np.sort(spla.eigsh(H, k=2, which="SA", tol=1e-14)[0])[0])
+    hy = torch.empty_like(xd)
+    h.matvec(xd, hy)
+    resid = float(torch.linalg.vector_norm(hy - e * xd))
+    say("  E", e, "exact", e0, "bases", used, "residual", resid)
+    assert used < 80
+    assert abs(e - e0) <= 1e-10 * abs(e0)
+    assert resid <= 1e-9 * max(1.0, abs(e0))
+    assert abs(float(torch.linalg.vector_norm(xd)) - 1.0) < 1e-12
+    h.destroy()
+
+
 def _batch_setup(torch, L, pbs, seed):
     hs = [L.dmrg_create(pb) for pb in pbs]
     phis = [I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + seed + i)) for i, h in enumerate(hs)]

@@ -180,6 +180,32 @@ def test_tst_chains_against_dense_expm():
     assert np.array_equal(ys2[0], ys[0])
 
 
+def test_ground_state_against_sparse_eigensolver_and_closed_form():
+    """Restarted Lanczos ground state: the exact-block chain (L = 8, U = 4, sector (4,4))
+    against ARPACK's lowest eigenpair of the sector Hamiltonian (a library routine on the ED
+    matrix); at U = 0 against the closed form 2 sum_{k<=4} -2 cos(k pi / 9); the Ritz residual."""
+    import scipy.sparse.linalg as spla
+    for U in (4.0, 0.0):
+        pb, sec, H, perm = exact_case(8, U, (4, 4))
+        lay, n = M.layout(pb)
+        x0 = I.random_psi(n, np.random.default_rng(14))
+        y, info = K.ground_state(_apply(pb), x0, kdim=30, max_restarts=60, tol=1e-12)
+        evals, evecs = spla.eigsh(H, k=2, which="SA", tol=1e-14)
+        order = np.argsort(evals)
+        evals, evecs = evals[order], evecs[:, order]
+        assert abs(info.energy - evals[0]) < 1e-10 * max(1.0, abs(evals[0]))
+        hy = M.matvec_sector(pb, y)
+        assert np.linalg.norm(hy - info.energy * y) < 1e-8
+        assert abs(np.linalg.norm(y) - 1.0) < 1e-12
+        if U == 0.0:
+            closed = 2.0 * sum(-2.0 * np.cos(k * np.pi / 9.0) for k in range(1, 5))
+            assert abs(info.energy - closed) < 1e-10
+        else:
+            assert evals[1] - evals[0] > 1e-3        # non-degenerate: the vector is unique
+            yc = y[:n] + 1j * y[n:]
+            assert abs(abs(np.vdot(evecs[:, 0], yc)) - 1.0) < 1e-8
+
+
 def test_error_estimate_bounds_true_error():
     pb, sec, H, perm = exact_case(8, 4.0, (4, 4))
     lay, n = M.layout(pb)
