@@ -80,10 +80,11 @@ def _cpu_threads() -> int:
     return os.cpu_count() or 1
 
 
-def cpu_baseline(pb, phi, kdim, tau, F, budget_s=12.0):
+def cpu_baseline(pb, phi, kdim, tau, F, budget_s=12.0, dens=None):
     """The FP64 oracle (unchanged) timed on the host: whole time-step-targeting steps, repeated
     until about budget_s seconds of work have been timed (at least one; per-step times, median
-    reported), then the oracle product alone on one BLAS thread for about budget_s / 3."""
+    reported), then the oracle product alone on one BLAS thread for about budget_s / 3, and the
+    oracle density matrix + truncation on dens = (vectors, weights, keep) if given."""
     import numpy as np
     from oracle import krylov as K
     from oracle import matvec as M
@@ -118,6 +119,17 @@ def cpu_baseline(pb, phi, kdim, tau, F, budget_s=12.0):
                                 "sample": f"{len(mv)} oracle products (median) on 1 BLAS thread"}
     except ImportError:
         pass
+    if dens is not None:
+        from oracle import density as D
+        vecs, wts, keep = dens
+        dt = []
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s / 6 or not dt:
+            t1 = time.perf_counter()
+            D.truncate(pb, vecs, wts, keep)
+            dt.append(time.perf_counter() - t1)
+        out["density_truncate"] = {"ms_per_call": round(1e3 * float(np.median(dt)), 3),
+                                   "sample": f"{len(dt)} oracle calls (median), same 5 vectors"}
     return out
 
 
@@ -254,6 +266,8 @@ def main():
     ap.add_argument("--no-drift", action="store_true", help="skip the 50-step m = 2000 drift run")
     ap.add_argument("--no-rhs4", action="store_true", help="skip the 4-RHS (per-target) mode run")
     ap.add_argument("--no-gs", action="store_true", help="skip the ground-state run")
+    ap.add_argument("--no-density", action="store_true",
+                    help="skip the density-matrix + truncation run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a buffer of MIB MiB once before the run: a plain copy kernel of "
                          "known traffic that hardware-counter runs use as the byte scale")
@@ -355,6 +369,33 @@ def main():
               "tflops": round(40 * used * F / el / 1e12, 4)}
         print(f"[bench] ground state: {gs}", file=sys.stderr, flush=True)
 
+    # density matrix of the five targets (ground state or the start vector, and the four time
+    # vectors) with the time-step-targeting weights, and its truncation to m states
+    dens, dens_host = None, None
+    if not args.no_density:
+        gsv = yg if gs is not None else pd
+        dv = [gsv] + [td[2 * n * k:2 * n * (k + 1)] for k in range(4)]
+        wts = [float(x) for x in h.tst_targets(pd, tau, kdim, td, info=False)[0]]
+        keep = int(w.get("m") or 1000)
+        rows = [int(r) for r in h.psi_layout()["rows"]]
+        evd = torch.empty(sum(rows), dtype=torch.float64, device="cuda")
+        vcd = torch.empty(sum(2 * r * r for r in rows), dtype=torch.float64, device="cuda")
+        h.density_truncate(dv, wts, keep, evd, vcd)
+        torch.cuda.synchronize()
+        reps = 5
+        e0.record(stream)
+        for _ in range(reps):
+            kept, terr = h.density_truncate(dv, wts, keep, evd, vcd)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_d = e0.elapsed_time(e1) / reps
+        dens = {"ms_per_call": round(ms_d, 4), "vectors": 5, "keep": keep,
+                "sectors": len(rows), "largest_sector": max(rows), "states": sum(rows),
+                "kept_states": int(sum(kept)), "trunc_err": terr,
+                "input_bytes": 5 * 2 * n * 8}
+        dens_host = ([x.cpu().numpy() for x in dv], wts, keep)
+        print(f"[bench] density + truncation: {dens}", file=sys.stderr, flush=True)
+
     # product-only rate and the dominant kernel (HIP events around each launch)
     yd = torch.empty_like(pd)
     prof = h.profile_matvec(pd, yd, reps=20)
@@ -450,6 +491,7 @@ def main():
         "mfma_peak_frac_step": round(value / PEAK_FP64_TFLOPS, 4),
         "rhs4_mode": rhs4,
         "ground_state": gs,
+        "density_truncate": dens,
         "mixed_precision": mixed,
         "batched_64": batched,
         "drift_m2000": drift,
@@ -463,7 +505,7 @@ def main():
     }
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(pb, phi, kdim, tau, F, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(pb, phi, kdim, tau, F, args.cpu_budget, dens_host)
     print(json.dumps(out), flush=True)
 
 

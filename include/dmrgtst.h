@@ -223,6 +223,25 @@ int dmrg_ground_state(dmrg_handle h, const double* x0, double* y, int32_t kdim,
                       int32_t max_restarts, double tol, double* energy, int32_t* restarts,
                       dmrg_krylov_info* info);
 
+/* Reduced density matrix of the targets and its truncation (Sec. II.B): with every target in
+ * the handle's sector, rho is block diagonal over the system sectors p,
+ *   rho_p = sum_l weights[l] Psi_{l,p} Psi_{l,p}^H      (Psi_{l,p}: block p of vecs[l]),
+ * and the keep eigenvectors with the largest eigenvalues over all sectors are kept (equal values
+ * ranked by sector, then by position).  vecs: host array of nvec (1..16) device vectors;
+ * weights: host array of nvec (the TST weights of dmrg_tst_targets for the ground state and the
+ * four targets).  Outputs, per system sector in the order of dmrg_psi_layout (d = rows there):
+ *   evals   device, sum of d doubles: eigenvalues of rho_p in descending order;
+ *   evecs   device, sum of 2 d^2 doubles: per sector the d x d eigenvector matrix, column-major,
+ *           real parts then imaginary parts, columns in the order of evals;
+ *   kept    host int32 per sector: how many of its leading eigenvectors are kept;
+ *   trunc_err  host (may be NULL): the sum of the discarded eigenvalues.
+ * The eigen-decomposition is cyclic complex Jacobi per sector.  The call waits for the stream.
+ * DMRG_EINVAL for NULL arguments, nvec outside [1, 16], keep < 0 or a system sector larger than
+ * 1024 states; DMRG_ENONFINITE for a weight that is not finite. */
+int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double* weights,
+                          int32_t nvec, int32_t keep, double* evals, double* evecs, int32_t* kept,
+                          double* trunc_err);
+
 /* 4-RHS (per-target) mode of time-step targeting: the four targets are kept as four independent
  * chains, each advanced by exp(-i tau H) with a Krylov basis of its own (kdim vectors, Sec. II.A)
  * instead of one basis evaluated at four times (the variant of the seeding of the next

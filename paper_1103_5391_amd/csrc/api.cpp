@@ -31,6 +31,9 @@ hipError_t launch_start(const VecGroup&, const double*, const double* const*, in
 hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
 hipError_t launch_tridiag(const VecGroup&, const double*, int, hipStream_t);
 hipError_t launch_lowest(const VecGroup&, hipStream_t);
+hipError_t launch_density(const DBlock*, int, const DTile*, int, const double* const*, const double*,
+                          int, int64_t, void*, void*, double*, int, int, int*, double*, double*,
+                          int*, double*, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 int vec_blocks(int64_t n);
 int red_blocks(int64_t n);
@@ -273,6 +276,10 @@ struct dmrg_ctx {
     DevBuf dA[4], dR[4];
     Workspace ws[kChains];
     Group self;         // tables of the handle's own Krylov runs
+    // density matrix and truncation (built on first use): sectors, tiles, matrices, results
+    DevBuf dDBlk, dDTile, dDA, dDV, dDEv, dDKept, dDNk, dDSums, dDVecs, dDW;
+    int dens_ntiles = 0, dens_ntot = 0;
+    int64_t dens_nmat = 0;
     std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
 };
 
@@ -792,6 +799,71 @@ int dmrg_ground_state(dmrg_handle h, const double* x0, double* y, int32_t kdim,
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         fill_info(st, info);
     }
+    return DMRG_OK;
+}
+
+int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double* weights,
+                          int32_t nvec, int32_t keep, double* evals, double* evecs, int32_t* kept,
+                          double* trunc_err) {
+    if (!h) return DMRG_EINVAL;
+    if (!vecs || !weights || !evals || !evecs || !kept) return fail(h, DMRG_EINVAL, "NULL pointer");
+    if (nvec < 1 || nvec > kDensMaxVec) return fail(h, DMRG_EINVAL, "nvec outside [1, 16]");
+    if (keep < 0) return fail(h, DMRG_EINVAL, "negative keep");
+    for (int l = 0; l < nvec; ++l) {
+        if (!vecs[l]) return fail(h, DMRG_EINVAL, "NULL vector");
+        if (!std::isfinite(weights[l])) return fail(h, DMRG_ENONFINITE, "weight is not finite");
+    }
+    const Plan& P = h->plan;
+    const int nb = (int)P.blocks.size();
+    hipStream_t s = h->stream;
+    if (!h->dDBlk.p) {
+        std::vector<DBlock> blks(nb);
+        std::vector<DTile> tiles;
+        int64_t aoff = 0, eoff = 0;
+        for (int b = 0; b < nb; ++b) {
+            const PsiBlock& pbk = P.blocks[b];
+            if (pbk.d > kDensMaxDim) return fail(h, DMRG_EINVAL, "system sector larger than 1024");
+            blks[b] = DBlock{pbk.d, pbk.e, pbk.off, aoff, eoff};
+            for (int i0 = 0; i0 < pbk.d; i0 += 16)
+                for (int j0 = 0; j0 < pbk.d; j0 += 16) tiles.push_back(DTile{b, i0, j0, 0});
+            aoff += (int64_t)pbk.d * pbk.d;
+            eoff += pbk.d;
+        }
+        h->dens_ntiles = (int)tiles.size();
+        h->dens_ntot = (int)eoff;
+        h->dens_nmat = aoff;
+        HIP_TRY(h, upload(h->dDBlk, blks, s));
+        HIP_TRY(h, upload(h->dDTile, tiles, s));
+        HIP_TRY(h, h->dDA.alloc(2 * sizeof(double) * (size_t)aoff));
+        HIP_TRY(h, h->dDV.alloc(2 * sizeof(double) * (size_t)aoff));
+        HIP_TRY(h, h->dDEv.alloc(sizeof(double) * (size_t)eoff));
+        HIP_TRY(h, h->dDKept.alloc(sizeof(int) * (size_t)eoff));
+        HIP_TRY(h, h->dDNk.alloc(sizeof(int) * (size_t)nb));
+        HIP_TRY(h, h->dDSums.alloc(2 * sizeof(double) * (size_t)nb));
+        HIP_TRY(h, h->dDVecs.alloc(sizeof(void*) * kDensMaxVec));
+        HIP_TRY(h, h->dDW.alloc(sizeof(double) * kDensMaxVec));
+    }
+    // per-call pointers and weights (synchronous copies; the call waits for its results)
+    HIP_TRY(h, hipMemcpyAsync(h->dDVecs.p, vecs, sizeof(void*) * nvec, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemcpyAsync(h->dDW.p, weights, sizeof(double) * nvec, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, launch_density(h->dDBlk.as<DBlock>(), nb, h->dDTile.as<DTile>(), h->dens_ntiles,
+                              h->dDVecs.as<const double*>(), h->dDW.as<double>(), nvec, P.n,
+                              h->dDA.p, h->dDV.p, h->dDEv.as<double>(), h->dens_ntot, keep,
+                              h->dDKept.as<int>(), evals, evecs, h->dDNk.as<int>(),
+                              h->dDSums.as<double>(), s));
+    std::vector<int> nk(nb);
+    std::vector<double> sums(2 * (size_t)nb);
+    HIP_TRY(h, hipMemcpyAsync(nk.data(), h->dDNk.p, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(sums.data(), h->dDSums.p, sizeof(double) * 2 * nb,
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    double all = 0.0, kept_sum = 0.0;
+    for (int b = 0; b < nb; ++b) {
+        kept[b] = nk[b];
+        all += sums[2 * (size_t)b];
+        kept_sum += sums[2 * (size_t)b + 1];
+    }
+    if (trunc_err) *trunc_err = all - kept_sum;
     return DMRG_OK;
 }
 

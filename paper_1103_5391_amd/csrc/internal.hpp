@@ -145,6 +145,20 @@ struct VecGroup {
     int combine_mult;     // blocks per pass block of the non-chained combination
 };
 
+// Reduced density matrix and truncation: one system sector (psi block) of the step.
+struct DBlock {
+    int32_t d, e;         // system states (rows of the psi block), environment states (columns)
+    int64_t off;          // psi block offset in a vector (complex elements)
+    int64_t aoff;         // its d x d complex matrices in the workspace (complex elements)
+    int64_t eoff;         // its eigenvalues (sum of d over earlier sectors)
+};
+struct DTile {            // 16 x 16 tile of one sector's density matrix
+    int32_t blk, i0, j0, pad;
+};
+constexpr int kDensMaxDim = 1024;   // largest system sector the Jacobi kernel accepts
+constexpr int kDensMaxVec = 16;     // most target vectors of one density matrix
+constexpr int kDensSweeps = 40;     // Jacobi sweeps at most (convergence ends it earlier)
+
 // Device state of one Krylov run on one problem.
 struct KState {
     double alpha[kMaxKrylov];

@@ -28,7 +28,7 @@ SYMBOLS = [
     "dmrg_set_gemm", "dmrg_get_gemm", "dmrg_autotune",
     "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_set_graph", "dmrg_batch_tst_targets",
     "dmrg_batch_set_gemm", "dmrg_batch_autotune", "dmrg_profile_matvec",
-    "dmrg_tst_chains", "dmrg_batch_tst_chains", "dmrg_ground_state",
+    "dmrg_tst_chains", "dmrg_batch_tst_chains", "dmrg_ground_state", "dmrg_density_truncate",
     "dmrg_strerror", "dmrg_last_error",
 ]
 
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
     lib.dmrg_profile_matvec.argtypes = [vp, vp, vp, i32, P(dbl)]
     lib.dmrg_tst_chains.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl), P(dmrg_krylov_info)]
     lib.dmrg_ground_state.argtypes = [vp, vp, vp, i32, i32, dbl, P(dbl), P(i32), P(dmrg_krylov_info)]
+    lib.dmrg_density_truncate.argtypes = [vp, P(vp), P(dbl), i32, i32, vp, vp, P(i32), P(dbl)]
     lib.dmrg_batch_tst_chains.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl),
                                           P(dmrg_krylov_info)]
     lib.dmrg_strerror.argtypes = [i32]
@@ -320,6 +321,24 @@ class Handle:
         return e.value, used.value, (inf.as_dict() if info else None)
 
     ground_state = dmrg_ground_state
+
+    def dmrg_density_truncate(self, vecs, weights, keep: int, evals, evecs):
+        """Density matrix of the targets and its truncation to `keep` states: fills the device
+        buffers evals (sum d) and evecs (sum 2 d^2); returns (kept per sector, truncation error)."""
+        n2 = 2 * self.n
+        lay = self.psi_layout()
+        rows = [int(r) for r in lay["rows"]]
+        ne, nv2 = sum(rows), sum(2 * r * r for r in rows)
+        ph = (C.c_void_p * len(vecs))(*[_tensor_ptr(v, n2).value for v in vecs])
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        kept = np.zeros(len(rows), dtype=np.int32)
+        err = C.c_double()
+        _check(self.lib.dmrg_density_truncate(self.h, ph, _dptr(w, C.c_double), len(vecs), int(keep),
+                                              _tensor_ptr(evals, ne), _tensor_ptr(evecs, nv2),
+                                              _dptr(kept, C.c_int32), C.byref(err)), self.h)
+        return kept, err.value
+
+    density_truncate = dmrg_density_truncate
 
     def dmrg_set_graph(self, enable: bool):
         _check(self.lib.dmrg_set_graph(self.h, int(bool(enable))), self.h)

@@ -475,6 +475,67 @@ def test_ground_state_converges_to_exact(env):
     h.destroy()
 
 
+@pytest.mark.parametrize("name", ["chain12_m30", "chain8_exact", "chain8_m17_odd", "ladder16_m1000"])
+def test_density_truncate_parity(env, name):
+    """Density matrix of five weighted targets and its truncation against the oracle: every
+    eigenvalue, the kept count of every sector and the truncation error; eigen-pairs (residual
+    against the oracle's rho, orthonormality); the kept subspace of every sector (its
+    projector), which is unique where the kept and discarded eigenvalues are apart."""
+    from oracle import density as Dn
+    torch, L = env
+    say("density", name)
+    pb = problem(name)
+    h = L.dmrg_create(pb)
+    n = h.n
+    rng = np.random.default_rng(I.SEED_BASE + 80)
+    vecs = [I.random_psi(n, rng) for _ in range(5)]
+    w = K.tst_weights()
+    rows = [int(r) for r in h.psi_layout()["rows"]]
+    total = sum(rows)
+    # a cut with a clear gap, near a quarter of the states
+    ref_all = Dn.truncate(pb, vecs, w, keep=total)
+    allv = np.sort(np.concatenate([ref_all.evals[p] for p in ref_all.sectors]))[::-1]
+    lo, hi = max(1, total // 8), max(2, total // 3)
+    gaps = (allv[lo - 1:hi - 1] - allv[lo:hi]) / allv[0]
+    keep = lo + int(np.argmax(gaps))
+    assert gaps.max() > 1e-6
+    ref = Dn.truncate(pb, vecs, w, keep=keep)
+    rho = Dn.density_blocks(pb, vecs, w)
+    evd = torch.full((total,), float("nan"), dtype=torch.float64, device="cuda")
+    vcd = torch.full((sum(2 * r * r for r in rows),), float("nan"), dtype=torch.float64, device="cuda")
+    xds = [_dev(torch, v) for v in vecs]
+    kept, err = h.density_truncate(xds, w, keep, evd, vcd)
+    ev, vc = _host(evd), _host(vcd)
+    scale = allv[0]
+    eo = vo = 0
+    worst = 0.0
+    for b, p in enumerate(ref.sectors):
+        d = rows[b]
+        lam = ev[eo:eo + d]
+        U = vc[vo:vo + d * d].reshape(d, d).T + 1j * vc[vo + d * d:vo + 2 * d * d].reshape(d, d).T
+        assert np.max(np.abs(lam - ref.evals[p])) <= 1e-12 * scale, (p, lam, ref.evals[p])
+        assert kept[b] == ref.kept[p]
+        assert np.linalg.norm(U.conj().T @ U - np.eye(d)) <= 1e-11 * d
+        assert np.linalg.norm(rho[p] @ U - U * lam[None, :]) <= 1e-11 * scale * d
+        k = int(kept[b])
+        if 0 < k < d and (lam[k - 1] - lam[k]) > 1e-6 * scale:
+            Pg = U[:, :k] @ U[:, :k].conj().T
+            Pr = ref.evecs[p][:, :k] @ ref.evecs[p][:, :k].conj().T
+            worst = max(worst, np.linalg.norm(Pg - Pr))
+        eo += d
+        vo += 2 * d * d
+    say("  keep", keep, "trunc err", err, ref.trunc_err, "worst projector diff", worst)
+    assert abs(err - ref.trunc_err) <= 1e-12
+    assert worst <= 1e-8
+    # a second call gives the same bits (fixed-order arithmetic throughout)
+    ev2 = torch.full_like(evd, float("nan"))
+    vc2 = torch.full_like(vcd, float("nan"))
+    kept2, err2 = h.density_truncate(xds, w, keep, ev2, vc2)
+    assert np.array_equal(_host(ev2), ev) and np.array_equal(_host(vc2), vc)
+    assert np.array_equal(kept2, kept) and err2 == err
+    h.destroy()
+
+
 def _batch_setup(torch, L, pbs, seed):
     hs = [L.dmrg_create(pb) for pb in pbs]
     phis = [I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + seed + i)) for i, h in enumerate(hs)]
