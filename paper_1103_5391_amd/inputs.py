@@ -128,6 +128,10 @@ class Block:
     H: list                          # per-sector dense symmetric matrices
     cdag: dict                       # site -> (BlockOp up, BlockOp dn)
     sites: list                      # lattice sites contained, in mode order
+    # enlarged blocks: the two factors (first, second) and the composition
+    # (sector of the first factor, sector of the second) -> (sector, offset in it)
+    parts: tuple | None = None
+    comp: dict | None = None
 
 
 class _Product:
@@ -261,7 +265,8 @@ def _enlarge(block: Block, site: int, U: float, bonds, site_first: bool, keep_si
         elif s in block.cdag:
             cdag[s] = tuple(on_block(block.cdag[s][spin], True) for spin in (UP, DN))
     sites = ([site] + block.sites) if site_first else (block.sites + [site])
-    return Block(space, H, cdag, sites)
+    parts = (sS, block) if site_first else (block, sS)
+    return Block(space, H, cdag, sites, parts=parts, comp=dict(prod.sub_off))
 
 
 def _site_block(site: int, U: float) -> Block:
@@ -321,6 +326,8 @@ class Problem:
     L: int = 0
     U: float = 0.0
     lattice_bonds: list = field(default_factory=list)
+    Sblk: Block | None = None        # the blocks the halves were built from
+    Eblk: Block | None = None
 
 
 def _half_from_block(blk: Block, edge_sites) -> Half:
@@ -346,7 +353,8 @@ def _assemble(Sblk: Block, Eblk: Block, lattice_bonds, target, name, L, U) -> Pr
         a = S.op_label.index((i, UP))
         b = E.op_label.index((j, UP))
         bonds.append(Bond((a, a + 1), (b, b + 1), float(t), (i, j)))
-    return Problem(S, E, tuple(target), bonds, name=name, L=L, U=U, lattice_bonds=lattice_bonds)
+    return Problem(S, E, tuple(target), bonds, name=name, L=L, U=U, lattice_bonds=lattice_bonds,
+                   Sblk=Sblk, Eblk=Eblk)
 
 
 def exact_problem(L: int, U: float, target, bonds=None, name="") -> Problem:
@@ -436,6 +444,83 @@ def synthetic_problem(L: int, m: int, U: float, lattice_bonds, seed: int, name="
     if target is None:
         target = (L // 2, L // 2)
     return _assemble(S, E, lattice_bonds, target, name, L, U)
+
+
+# --------------------------------------------------------------------------------------------
+# moving the centre one site to the right: the bases involved (wave-function transformation)
+# --------------------------------------------------------------------------------------------
+@dataclass
+class WftMove:
+    """Bases of a move of the centre one site to the right, for a superblock
+    S (x) E = (A (x) s1) (x) (s2 (x) R):
+
+      new system       S' = A' (x) s2, A' the kept states of S (per psi-layout sector of S, the
+                       first kept[b] columns of its eigenvector matrix U_b);
+      new environment  E' = s3 (x) R'', R expressed in it by W_r (d_E'(r) x d_R(r), one per
+                       sector r of R; the identity for exact blocks, where R = s3 (x) R'').
+
+    esub: (q, a, r, col offset) per sub-block of E = s2 (x) R (q: E sector, a: site state of s2,
+    r: R sector); ssub: {(b, a): (p', row offset)} per sub-block of S' (b: psi-layout block of
+    the kept S sector, a: site state of s2); layout: a Problem with the new halves' spaces and
+    the same target (its block operators are empty: it only carries the vector layout)."""
+    kept: list
+    esub: list
+    ssub: dict
+    r_dim: list
+    r_to_enew: list
+    W: list
+    layout: Problem
+    exact: bool
+
+
+def _haar_isometry(rows: int, cols: int, rng) -> np.ndarray:
+    g = rng.standard_normal((rows, cols)) + 1j * rng.standard_normal((rows, cols))
+    q, r = np.linalg.qr(g)
+    ph = np.diag(r) / np.abs(np.diag(r))
+    return q * ph[None, :]
+
+
+def wft_move(pb: Problem, kept, seed: int = 0) -> WftMove:
+    """The bases of the move for pb (built by exact_problem or synthetic_problem) with kept[b]
+    states of psi-layout block b.  Synthetic problems get a synthetic R'' (as many states as R,
+    doubled until every sector of R fits) and Haar-random isometries W_r (seeded)."""
+    S, E = pb.Sblk, pb.Eblk
+    assert S is not None and E is not None and S.comp is not None and E.comp is not None
+    R = E.parts[1]
+    blocks = psi_blocks(pb)
+    assert len(kept) == len(blocks)
+    # old environment E = s2 (x) R
+    esub = sorted((q, a, r, off) for (a, r), (q, off) in E.comp.items())
+    # new system S' = A' (x) s2
+    kb = [b for b in range(len(blocks)) if kept[b] > 0]
+    Aqn = np.array([S.space.qn[blocks[b][0]] for b in kb], dtype=np.int32).reshape(-1, 2)
+    Adim = np.array([kept[b] for b in kb], dtype=np.int32)
+    prodS = _Product(Space(Aqn, Adim), _site_space())
+    ssub = {(kb[i], a): so for (i, a), so in prodS.sub_off.items()}
+    Snew = Space(prodS.space_qn, prodS.space_dim)
+    # new environment E' = s3 (x) R''
+    rng = np.random.default_rng(SEED_BASE + 7000 + seed)
+    if R.comp is not None:                       # exact: R is s3 (x) R'' itself
+        Enew = R.space
+        W = [np.eye(int(d), dtype=complex) for d in R.space.dim]
+        r_to_enew = list(range(R.space.nsec))
+        exact = True
+    else:
+        nsites = len(R.sites) - 1
+        m2 = int(R.space.total)
+        while True:
+            Rpp = synthetic_block(nsites, m2, R.sites[1:], [], rng)
+            prodE = _Product(_site_space(), Rpp.space)
+            Enew = Space(prodE.space_qn, prodE.space_dim)
+            r_to_enew = [Enew.index.get((int(a), int(b))) for (a, b) in R.space.qn]
+            if all(j is not None and Enew.dim[j] >= R.space.dim[r] for r, j in enumerate(r_to_enew)):
+                break
+            m2 *= 2
+        W = [_haar_isometry(int(Enew.dim[j]), int(R.space.dim[r]), rng) for r, j in enumerate(r_to_enew)]
+        exact = False
+    lay = Problem(Half(Snew, [], [], [], []), Half(Enew, [], [], [], []), pb.target, [],
+                  name=pb.name + "_moved", L=pb.L, U=pb.U)
+    return WftMove(list(kept), esub, ssub, [int(d) for d in R.space.dim], r_to_enew, W, lay, exact)
 
 
 # --------------------------------------------------------------------------------------------
