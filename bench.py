@@ -267,7 +267,8 @@ def main():
     ap.add_argument("--no-rhs4", action="store_true", help="skip the 4-RHS (per-target) mode run")
     ap.add_argument("--no-gs", action="store_true", help="skip the ground-state run")
     ap.add_argument("--no-density", action="store_true",
-                    help="skip the density-matrix + truncation run")
+                    help="skip the density-matrix + truncation run (and the transformation)")
+    ap.add_argument("--no-wft", action="store_true", help="skip the wave-function transformation")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a buffer of MIB MiB once before the run: a plain copy kernel of "
                          "known traffic that hardware-counter runs use as the byte scale")
@@ -396,6 +397,31 @@ def main():
         dens_host = ([x.cpu().numpy() for x in dv], wts, keep)
         print(f"[bench] density + truncation: {dens}", file=sys.stderr, flush=True)
 
+    # wave-function transformation of the five targets for a move of the centre one site to
+    # the right, with the kept states just computed (synthetic stored basis of the environment)
+    wft = None
+    if dens is not None and not args.no_wft:
+        mv = I.wft_move(pb, [int(k) for k in kept], seed=w["seed"])
+        Wd = [torch.from_numpy(np.concatenate([x.real.T.reshape(-1), x.imag.T.reshape(-1)])).to("cuda")
+              for x in mv.W]
+        wf = h.wft_create(mv, Wd)
+        ys = [torch.empty(2 * wf.n_new, dtype=torch.float64, device="cuda") for _ in dv]
+        fl = wf.apply(vcd, dv, ys)
+        torch.cuda.synchronize()
+        reps = 10
+        e0.record(stream)
+        for _ in range(reps):
+            wf.apply(vcd, dv, ys)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_w = e0.elapsed_time(e1) / reps
+        wft = {"ms_per_call": round(ms_w, 4), "vectors": len(dv), "n_new": wf.n_new,
+               "flops": fl, "tflops": round(fl / (ms_w * 1e-3) / 1e12, 4),
+               "mfma_peak_frac": round(fl / (ms_w * 1e-3) / 1e12 / PEAK_FP64_TFLOPS, 4),
+               "norms": [round(float(torch.linalg.vector_norm(y)), 12) for y in ys]}
+        wf.destroy()
+        print(f"[bench] wave-function transformation: {wft}", file=sys.stderr, flush=True)
+
     # product-only rate and the dominant kernel (HIP events around each launch)
     yd = torch.empty_like(pd)
     prof = h.profile_matvec(pd, yd, reps=20)
@@ -492,6 +518,7 @@ def main():
         "rhs4_mode": rhs4,
         "ground_state": gs,
         "density_truncate": dens,
+        "wave_function_transformation": wft,
         "mixed_precision": mixed,
         "batched_64": batched,
         "drift_m2000": drift,

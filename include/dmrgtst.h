@@ -242,6 +242,62 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
                           int32_t nvec, int32_t keep, double* evals, double* evecs, int32_t* kept,
                           double* trunc_err);
 
+/* Wave-function transformation for a move of the centre one site to the right (Sec. II.B: the
+ * targets are carried to the new superblock basis when the central sites change).  The
+ * handle's superblock is (A x s1) x (s2 x R); the new one is S' x E' = (A' x s2) x (s3 x R''),
+ * A' the kept states of each system sector (the first kept[b] eigenvectors of its density
+ * matrix), R expressed in s3 x R'' by one matrix W_r per sector r of R:
+ *   psi'[(alpha', a), gamma] = sum_{alpha, beta} conj(U[alpha, alpha']) psi[alpha, (a, beta)] W_r[gamma, beta].
+ * The move is described by sector tables (all host arrays, copied by dmrg_wft_create):
+ *   esub      [n_esub][4]: per sub-block of E = s2 x R: E sector q, site state a of s2 (0..3),
+ *             R sector r, first column of the sub-block in sector q (its width is r_dim[r]);
+ *   r_dim     [nr]: states of R sector r;  r_to_enew [nr]: the E' sector with r's quantum numbers;
+ *   kept      [psi blocks of the handle, dmrg_psi_layout order]: states kept of that system
+ *             sector (0 drops it; at most its d);
+ *   ssub      [n_ssub][4]: per sub-block of S' = A' x s2: psi block b, site state a, S' sector,
+ *             first row of the sub-block in it (its height is kept[b]);
+ *   s_new_qn  [ns_new][2], s_new_dim [ns_new]: sectors of S' (sorted, distinct);
+ *   e_new_qn  [ne_new][2], e_new_dim [ne_new]: sectors of E' (sorted, distinct).
+ * The new vector has the handle's target sector and the layout dmrg_psi_layout would give S'
+ * and E' (blocks in S' sector order, column-major, real parts then imaginary parts). */
+typedef struct {
+    int32_t n_esub;
+    const int32_t* esub;
+    int32_t nr;
+    const int32_t* r_dim;
+    const int32_t* r_to_enew;
+    const int32_t* kept;
+    int32_t n_ssub;
+    const int32_t* ssub;
+    int32_t ns_new;
+    const int32_t* s_new_qn;
+    const int32_t* s_new_dim;
+    int32_t ne_new;
+    const int32_t* e_new_qn;
+    const int32_t* e_new_dim;
+} dmrg_wft_desc;
+
+typedef struct dmrg_wft_ctx* dmrg_wft;
+
+/* Plans a move for handle h.  W: host array of nr device pointers, W[r] holding the complex
+ * d_E'(r_to_enew[r]) x r_dim[r] matrix W_r, column-major, real parts then imaginary parts; the
+ * matrices are copied (the caller may free them after the call).  n_new (may be NULL): complex
+ * length of the new vector.  DMRG_EINVAL for a description that is out of range or
+ * inconsistent (a sub-block outside its sector, quantum numbers that do not add up to the
+ * target, S' rows covered twice). */
+int dmrg_wft_create(dmrg_handle h, const dmrg_wft_desc* desc, const double* const* W, dmrg_wft* out,
+                    int64_t* n_new);
+
+/* Transforms nvec (1..16) vectors: x[v] (device, 2n doubles of the handle's layout) to y[v]
+ * (device, 2 n_new doubles; must not overlap x).  U: device, the eigenvector array written by
+ * dmrg_density_truncate for the handle (per sector, d x d, real then imaginary planes).  The
+ * intermediate is allocated on first use for the largest nvec seen.  Asynchronous on the
+ * handle's stream.  flops (may be NULL): algorithmic flops of the call. */
+int dmrg_wft_apply(dmrg_wft w, const double* U, int32_t nvec, const double* const* x,
+                   double* const* y, double* flops);
+
+int dmrg_wft_destroy(dmrg_wft w);
+
 /* 4-RHS (per-target) mode of time-step targeting: the four targets are kept as four independent
  * chains, each advanced by exp(-i tau H) with a Krylov basis of its own (kdim vectors, Sec. II.A)
  * instead of one basis evaluated at four times (the variant of the seeding of the next

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdmrgtst.so")
 SOURCES = ["csrc/api.cpp", "csrc/plan.cpp", "csrc/gemm.hip", "csrc/gemm_lds.hip", "csrc/krylov.hip",
-           "csrc/density.hip"]
+           "csrc/density.hip", "csrc/wft.hip"]
 ARCH = os.environ.get("DMRG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

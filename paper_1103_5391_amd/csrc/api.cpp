@@ -35,6 +35,8 @@ hipError_t launch_density(const DBlock*, int, const DTile*, int, const double* c
                           int, int64_t, void*, void*, double*, int, int, int*, double*, double*,
                           int*, double*, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
+hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const ZPtrs&, int, int64_t,
+                      hipStream_t);
 int vec_blocks(int64_t n);
 int red_blocks(int64_t n);
 
@@ -281,6 +283,19 @@ struct dmrg_ctx {
     int dens_ntiles = 0, dens_ntot = 0;
     int64_t dens_nmat = 0;
     std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
+};
+
+// A planned move of the centre (wave-function transformation): tile lists of its two stages,
+// the matrices W_r, and the intermediate.
+struct dmrg_wft_ctx {
+    dmrg_handle h = nullptr;
+    DevBuf dTA, dTB, dW, dPhi;
+    int nA = 0, nB = 0;
+    int64_t nphi = 0;          // complex length of the intermediate of one vector
+    int64_t n_new = 0;         // complex length of the new vector
+    int phi_vecs = 0;          // vectors the intermediate is allocated for
+    bool phi_zero = false;     // some intermediate rows are not written by stage A
+    double flops_vec = 0.0;    // algorithmic flops per vector
 };
 
 namespace {
@@ -582,6 +597,157 @@ int run_chains(dmrg_batch_ctx& cs, int variant, bool graph, const double* const*
     return DMRG_OK;
 }
 
+// Validates a move description against the handle and builds the tile lists of both stages
+// (host side of dmrg_wft_create).
+int plan_wft(dmrg_handle h, const dmrg_wft_desc& D, std::vector<ZTile>& tA, std::vector<ZTile>& tB,
+             std::vector<int64_t>& woff, dmrg_wft_ctx& w) {
+    const Plan& P = h->plan;
+    const int nb = (int)P.blocks.size();
+    auto bad = [&](const char* why) { return fail(h, DMRG_EINVAL, std::string("wft: ") + why); };
+    if (D.n_esub < 0 || D.nr < 0 || D.n_ssub < 0 || D.ns_new < 0 || D.ne_new < 0) return bad("negative count");
+    if ((D.n_esub && !D.esub) || (D.nr && (!D.r_dim || !D.r_to_enew)) || (nb && !D.kept) ||
+        (D.n_ssub && !D.ssub) || (D.ns_new && (!D.s_new_qn || !D.s_new_dim)) ||
+        (D.ne_new && (!D.e_new_qn || !D.e_new_dim)))
+        return bad("NULL table");
+    for (int b = 0; b < nb; ++b)
+        if (D.kept[b] < 0 || D.kept[b] > P.blocks[b].d) return bad("kept outside [0, d]");
+    for (int r = 0; r < D.nr; ++r) {
+        if (D.r_dim[r] < 0) return bad("negative R dimension");
+        if (D.r_to_enew[r] < 0 || D.r_to_enew[r] >= D.ne_new) return bad("R sector maps outside E'");
+        for (int r2 = 0; r2 < r; ++r2)
+            if (D.r_to_enew[r2] == D.r_to_enew[r]) return bad("two R sectors map to one E' sector");
+    }
+    for (int i = 0; i < D.ns_new; ++i)
+        if (D.s_new_dim[i] < 0) return bad("negative S' dimension");
+    std::map<std::pair<int, int>, int> enew;
+    for (int i = 0; i < D.ne_new; ++i) {
+        if (D.e_new_dim[i] < 0) return bad("negative E' dimension");
+        if (!enew.emplace(std::make_pair(D.e_new_qn[2 * i], D.e_new_qn[2 * i + 1]), i).second)
+            return bad("repeated E' sector");
+    }
+    // W offsets (doubles): W_r is d_E'(r) x r_dim[r], two planes
+    woff.assign(D.nr + 1, 0);
+    for (int r = 0; r < D.nr; ++r)
+        woff[r + 1] = woff[r] + 2 * (int64_t)D.e_new_dim[D.r_to_enew[r]] * D.r_dim[r];
+    std::vector<int> r_of_enew(D.ne_new, -1);
+    for (int r = 0; r < D.nr; ++r) r_of_enew[D.r_to_enew[r]] = r;
+    // new layout: blocks (p', r') in S' order, r' the E' sector completing the target
+    std::vector<int> col_of(D.ns_new, -1);
+    std::vector<int64_t> new_off(D.ns_new, 0), phi_off(D.ns_new, -1);
+    int64_t n_new = 0, nphi = 0;
+    for (int i = 0; i < D.ns_new; ++i) {
+        auto it = enew.find({P.target[0] - D.s_new_qn[2 * i], P.target[1] - D.s_new_qn[2 * i + 1]});
+        if (it == enew.end()) continue;
+        col_of[i] = it->second;
+        new_off[i] = n_new;
+        n_new += (int64_t)D.s_new_dim[i] * D.e_new_dim[it->second];
+        const int r = r_of_enew[it->second];
+        if (r >= 0) {
+            phi_off[i] = nphi;
+            nphi += (int64_t)D.s_new_dim[i] * D.r_dim[r];
+        }
+    }
+    // sub-blocks of S': (b, a) -> (p', first row); rows covered at most once
+    std::map<std::pair<int, int>, std::pair<int, int>> ssub;
+    std::vector<std::vector<char>> used(D.ns_new);
+    for (int i = 0; i < D.ns_new; ++i) used[i].assign(D.s_new_dim[i], 0);
+    for (int i = 0; i < D.n_ssub; ++i) {
+        const int* e = D.ssub + 4 * i;
+        const int b = e[0], a = e[1], pp = e[2], roff = e[3];
+        if (b < 0 || b >= nb || a < 0 || a > 3 || pp < 0 || pp >= D.ns_new || roff < 0 ||
+            roff + D.kept[b] > D.s_new_dim[pp])
+            return bad("S' sub-block outside its sector");
+        if (!ssub.emplace(std::make_pair(b, a), std::make_pair(pp, roff)).second)
+            return bad("repeated S' sub-block");
+        for (int k = 0; k < D.kept[b]; ++k) {
+            if (used[pp][roff + k]) return bad("S' rows covered twice");
+            used[pp][roff + k] = 1;
+        }
+    }
+    // stage A: one product per (kept block b, sub-block (a, r) of its E sector)
+    std::vector<int64_t> uoff(nb + 1, 0);
+    for (int b = 0; b < nb; ++b) uoff[b + 1] = uoff[b] + 2 * (int64_t)P.blocks[b].d * P.blocks[b].d;
+    std::vector<int64_t> phi_rows(D.ns_new, 0);
+    double flops = 0.0;
+    auto tiles = [](std::vector<ZTile>& out, ZTile t) {
+        for (int m0 = 0; m0 < std::max(t.M, 1); m0 += kZTile)
+            for (int n0 = 0; n0 < t.N; n0 += kZTile) {
+                t.m0 = m0;
+                t.n0 = n0;
+                out.push_back(t);
+            }
+    };
+    for (int i = 0; i < D.n_esub; ++i) {
+        const int* e = D.esub + 4 * i;
+        const int q = e[0], a = e[1], r = e[2], coff = e[3];
+        if (q < 0 || q >= P.E.nsec || a < 0 || a > 3 || r < 0 || r >= D.nr || coff < 0 ||
+            coff + D.r_dim[r] > P.E.dim[q])
+            return bad("E sub-block outside its sector");
+        for (int b = 0; b < nb; ++b) {
+            const PsiBlock& B = P.blocks[b];
+            if (B.q != q || D.kept[b] == 0) continue;
+            auto it = ssub.find({b, a});
+            if (it == ssub.end()) return bad("kept sector without an S' sub-block for a site state");
+            const int pp = it->second.first, roff = it->second.second;
+            const int rr = D.r_to_enew[r];
+            if (col_of[pp] != rr) return bad("quantum numbers do not add up to the target");
+            // the site state moves the same quantum numbers on both sides
+            if (P.E.nup[q] - D.e_new_qn[2 * rr] != D.s_new_qn[2 * pp] - P.S.nup[B.p] ||
+                P.E.ndn[q] - D.e_new_qn[2 * rr + 1] != D.s_new_qn[2 * pp + 1] - P.S.ndn[B.p])
+                return bad("site state with different quantum numbers on the two sides");
+            ZTile t{};
+            t.M = D.kept[b];
+            t.N = D.r_dim[r];
+            t.K = B.d;
+            t.amode = 1;
+            t.aoff = uoff[b];
+            t.aim = (int64_t)B.d * B.d;
+            t.lda = B.d;
+            t.bmode = 0;
+            t.boff = B.off + (int64_t)coff * B.d;
+            t.bim = P.n;
+            t.ldb = B.d;
+            t.coff = phi_off[pp] + roff;
+            t.cim = 0;                    // set once the intermediate size is known
+            t.ldc = D.s_new_dim[pp];
+            if (t.N > 0 && t.M > 0) tiles(tA, t);
+            flops += 8.0 * t.M * t.N * t.K;
+            phi_rows[pp] += t.M;
+        }
+    }
+    bool zero = false;
+    for (int i = 0; i < D.ns_new; ++i)
+        if (phi_off[i] >= 0 && D.r_dim[r_of_enew[col_of[i]]] > 0 && phi_rows[i] != D.s_new_dim[i]) zero = true;
+    for (ZTile& t : tA) t.cim = nphi;
+    // stage B: every new block, K = 0 where E' has no image of an R sector
+    for (int i = 0; i < D.ns_new; ++i) {
+        if (col_of[i] < 0) continue;
+        const int rr = col_of[i], r = r_of_enew[rr];
+        ZTile t{};
+        t.M = D.s_new_dim[i];
+        t.N = D.e_new_dim[rr];
+        t.K = r >= 0 ? D.r_dim[r] : 0;
+        t.amode = 0;
+        t.aoff = r >= 0 ? phi_off[i] : 0;
+        t.aim = nphi;
+        t.lda = std::max(1, D.s_new_dim[i]);
+        t.bmode = 1;
+        t.boff = r >= 0 ? woff[r] : 0;
+        t.bim = r >= 0 ? (int64_t)D.e_new_dim[rr] * D.r_dim[r] : 0;
+        t.ldb = std::max(1, D.e_new_dim[rr]);
+        t.coff = new_off[i];
+        t.cim = n_new;
+        t.ldc = std::max(1, D.s_new_dim[i]);
+        if (t.M > 0 && t.N > 0) tiles(tB, t);
+        flops += 8.0 * t.M * t.N * t.K;
+    }
+    w.nphi = nphi;
+    w.n_new = n_new;
+    w.phi_zero = zero;
+    w.flops_vec = flops;
+    return DMRG_OK;
+}
+
 int check_krylov_args(dmrg_handle h, double tau, int kdim) {
     if (kdim < 1 || kdim > kMaxKrylov) return fail(h, DMRG_EINVAL, "kdim outside [1, 64]");
     if (!std::isfinite(tau)) return fail(h, DMRG_ENONFINITE, "tau is not finite");
@@ -864,6 +1030,77 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
         kept_sum += sums[2 * (size_t)b + 1];
     }
     if (trunc_err) *trunc_err = all - kept_sum;
+    return DMRG_OK;
+}
+
+int dmrg_wft_create(dmrg_handle h, const dmrg_wft_desc* desc, const double* const* W, dmrg_wft* out,
+                    int64_t* n_new) {
+    if (!out) return DMRG_EINVAL;
+    *out = nullptr;
+    if (!h) return DMRG_EINVAL;
+    if (!desc) return fail(h, DMRG_EINVAL, "wft: NULL description");
+    if (desc->nr > 0 && !W) return fail(h, DMRG_EINVAL, "wft: NULL W array");
+    std::unique_ptr<dmrg_wft_ctx> w(new (std::nothrow) dmrg_wft_ctx());
+    if (!w) return DMRG_ENOMEM;
+    w->h = h;
+    std::vector<ZTile> tA, tB;
+    std::vector<int64_t> woff;
+    int rc = plan_wft(h, *desc, tA, tB, woff, *w);
+    if (rc) return rc;
+    for (int r = 0; r < desc->nr; ++r)
+        if (woff[r + 1] > woff[r] && !W[r]) return fail(h, DMRG_EINVAL, "wft: NULL W matrix");
+    hipStream_t s = h->stream;
+    HIP_TRY(h, upload(w->dTA, tA, s));
+    HIP_TRY(h, upload(w->dTB, tB, s));
+    w->nA = (int)tA.size();
+    w->nB = (int)tB.size();
+    HIP_TRY(h, w->dW.alloc(sizeof(double) * (size_t)std::max<int64_t>(woff.back(), 1)));
+    for (int r = 0; r < desc->nr; ++r)
+        if (woff[r + 1] > woff[r])
+            HIP_TRY(h, hipMemcpyAsync(w->dW.as<double>() + woff[r], W[r],
+                                      sizeof(double) * (size_t)(woff[r + 1] - woff[r]),
+                                      hipMemcpyDeviceToDevice, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    if (n_new) *n_new = w->n_new;
+    *out = w.release();
+    return DMRG_OK;
+}
+
+int dmrg_wft_apply(dmrg_wft w, const double* U, int32_t nvec, const double* const* x,
+                   double* const* y, double* flops) {
+    if (!w || !w->h) return DMRG_EINVAL;
+    dmrg_handle h = w->h;
+    if (nvec < 1 || nvec > kWftMaxVec) return fail(h, DMRG_EINVAL, "wft: nvec outside [1, 16]");
+    if (!U || !x || !y) return fail(h, DMRG_EINVAL, "wft: NULL pointer");
+    for (int v = 0; v < nvec; ++v)
+        if (!x[v] || !y[v]) return fail(h, DMRG_EINVAL, "wft: NULL vector");
+    hipStream_t s = h->stream;
+    if (w->phi_vecs < nvec) {
+        HIP_TRY(h, hipStreamSynchronize(s));
+        HIP_TRY(h, w->dPhi.alloc(sizeof(double) * 2 * (size_t)std::max<int64_t>(w->nphi, 1) * nvec));
+        w->phi_vecs = nvec;
+    }
+    ZPtrs pA{}, pB{};
+    double* phi = w->dPhi.as<double>();
+    const int64_t stride = 2 * std::max<int64_t>(w->nphi, 1);
+    for (int v = 0; v < nvec; ++v) {
+        pA.a[v] = U;
+        pA.b[v] = x[v];
+        pA.c[v] = phi + v * stride;
+        pB.a[v] = phi + v * stride;
+        pB.b[v] = w->dW.as<double>();
+        pB.c[v] = y[v];
+    }
+    HIP_TRY(h, launch_wft(w->dTA.as<ZTile>(), w->nA, pA, w->dTB.as<ZTile>(), w->nB, pB, nvec,
+                          w->phi_zero ? stride : 0, s));
+    if (flops) *flops = w->flops_vec * nvec;
+    return DMRG_OK;
+}
+
+int dmrg_wft_destroy(dmrg_wft w) {
+    if (!w) return DMRG_EINVAL;
+    if (w->h) (void)hipStreamSynchronize(w->h->stream);
+    delete w;
     return DMRG_OK;
 }
 

@@ -159,6 +159,24 @@ constexpr int kDensMaxDim = 1024;   // largest system sector the Jacobi kernel a
 constexpr int kDensMaxVec = 16;     // most target vectors of one density matrix
 constexpr int kDensSweeps = 40;     // Jacobi sweeps at most (convergence ends it earlier)
 
+// One 32 x 32 tile of a complex product C = A B (FP64; both planes of every operand: real
+// parts at off, imaginary parts at off + im).  A modes: 0 column-major, A(i, k) at i + k lda;
+// 1 conjugate transpose of a column-major X, A(i, k) = conj(X(k, i)) at k + i lda.  B modes:
+// 0 column-major, B(k, j) at k + j ldb; 1 transpose of a column-major X, B(k, j) = X(j, k) at
+// j + k ldb.  C is column-major (ldc).  K = 0 writes a zero tile.
+struct ZTile {
+    int32_t M, N, K, m0, n0;
+    int32_t amode, bmode, lda, ldb, ldc;
+    int64_t aoff, aim, boff, bim, coff, cim;
+};
+constexpr int kZTile = 32;
+constexpr int kWftMaxVec = 16;      // vectors of one wave-function transformation call
+struct ZPtrs {                      // per vector: the A, B and C buffers of one launch
+    const double* a[kWftMaxVec];
+    const double* b[kWftMaxVec];
+    double* c[kWftMaxVec];
+};
+
 // Device state of one Krylov run on one problem.
 struct KState {
     double alpha[kMaxKrylov];

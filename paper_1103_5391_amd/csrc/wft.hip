@@ -1,0 +1,138 @@
+// Wave-function transformation (FP64, gfx950): products of complex matrices on the FP64 MFMA.
+//
+// Sec. II.B: when the centre moves one site to the right, a target psi on
+// (A x s1) x (s2 x R) is carried to (A' x s2) x (s3 x R'') by
+//   stage A   Phi[(alpha', a), beta] = sum_alpha conj(U[alpha, alpha']) psi[alpha, (a, beta)]
+//             (U: the kept eigenvectors of the system's density matrix; one product per
+//             sub-block (kept sector, site state a, R sector), written into the rows of the new
+//             system sector that the sub-block occupies: the regrouping of s2 is the write
+//             address, with no sign since the bases are normal-ordered)
+//   stage B   psi'[(alpha', a), gamma] = sum_beta Phi[(alpha', a), beta] W[gamma, beta]
+//             (W_r: the states of R sector r in the product basis of s3 x R'')
+// Both stages are one launch over a list of 32 x 32 output tiles, one wavefront per tile, every
+// vector of the call in the second grid dimension.  A tile runs 2 x 2 MFMA 16x16x4 blocks, each
+// with two accumulators: Re C += Re A Re B - Im A Im B and Im C += Re A Im B + Im A Re B.
+#include <algorithm>
+#include <cstdint>
+
+#include "internal.hpp"
+
+namespace dmrg {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Element k of a lane's four consecutive K values: both planes of one operand element, zero
+// outside the matrix.
+__device__ __forceinline__ void load_a(const ZTile& t, const double* __restrict__ A, int i, int k,
+                                       double& re, double& im) {
+    re = 0.0;
+    im = 0.0;
+    if (i < t.M && k < t.K) {
+        const int64_t at = t.amode == 0 ? t.aoff + (int64_t)k * t.lda + i : t.aoff + (int64_t)i * t.lda + k;
+        re = A[at];
+        im = t.amode == 0 ? A[at + t.aim] : -A[at + t.aim];
+    }
+}
+
+__device__ __forceinline__ void load_b(const ZTile& t, const double* __restrict__ B, int k, int j,
+                                       double& re, double& im) {
+    re = 0.0;
+    im = 0.0;
+    if (j < t.N && k < t.K) {
+        const int64_t at = t.bmode == 0 ? t.boff + (int64_t)j * t.ldb + k : t.boff + (int64_t)k * t.ldb + j;
+        re = B[at];
+        im = B[at + t.bim];
+    }
+}
+
+__device__ __forceinline__ d4 mma4(const double (&a)[4], const double (&b)[4], d4 c) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) c = __builtin_amdgcn_mfma_f64_16x16x4f64(a[u], b[u], c, 0, 0, 0);
+    return c;
+}
+
+}  // namespace
+
+// One wavefront per output tile; vector v = blockIdx.y.  Lane (g, r) = (lane / 16, lane % 16)
+// supplies rows (columns) r of the 16-row (16-column) blocks and the K indices 4 g + u of a
+// chunk of 16 (the u-th MFMA of the chunk takes index 4 g + u from lane group g, the same for
+// A and B); result element (g + 4 v, r) of a 16 x 16 block is accumulator component v.
+__global__ __launch_bounds__(64) void k_zgemm(const ZTile* __restrict__ tiles, ZPtrs ptr) {
+    const ZTile t = tiles[blockIdx.x];
+    const int v = blockIdx.y;
+    const double* __restrict__ A = ptr.a[v];
+    const double* __restrict__ B = ptr.b[v];
+    double* __restrict__ C = ptr.c[v];
+    const int lane = threadIdx.x, g = lane >> 4, r = lane & 15;
+    d4 cre[2][2], cim[2][2];
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) {
+            cre[mi][nj] = (d4){0.0, 0.0, 0.0, 0.0};
+            cim[mi][nj] = (d4){0.0, 0.0, 0.0, 0.0};
+        }
+    for (int k0 = 0; k0 < t.K; k0 += 16) {
+        double ar[2][4], ai[2][4], an[2][4], br[2][4], bi[2][4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int k = k0 + 4 * g + u;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                load_a(t, A, t.m0 + 16 * h + r, k, ar[h][u], ai[h][u]);
+                an[h][u] = -ai[h][u];
+                load_b(t, B, k, t.n0 + 16 * h + r, br[h][u], bi[h][u]);
+            }
+        }
+#pragma unroll
+        for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < 2; ++nj) {
+                cre[mi][nj] = mma4(ar[mi], br[nj], cre[mi][nj]);
+                cre[mi][nj] = mma4(an[mi], bi[nj], cre[mi][nj]);
+                cim[mi][nj] = mma4(ar[mi], bi[nj], cim[mi][nj]);
+                cim[mi][nj] = mma4(ai[mi], br[nj], cim[mi][nj]);
+            }
+    }
+#pragma unroll
+    for (int mi = 0; mi < 2; ++mi)
+#pragma unroll
+        for (int nj = 0; nj < 2; ++nj) {
+            const int j = t.n0 + 16 * nj + r;
+            if (j >= t.N) continue;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = t.m0 + 16 * mi + g + 4 * q;
+                if (i >= t.M) continue;
+                const int64_t at = t.coff + (int64_t)j * t.ldc + i;
+                C[at] = cre[mi][nj][q];
+                C[at + t.cim] = cim[mi][nj][q];
+            }
+        }
+}
+
+__global__ __launch_bounds__(256) void k_zero(double* __restrict__ x, int64_t n) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+         i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = 0.0;
+}
+
+// Stage A then stage B for nvec vectors; zero_n > 0 first clears the intermediate (nvec
+// consecutive pieces of zero_n doubles from pA.c[0]), for moves whose sub-blocks leave rows of
+// it unwritten.
+hipError_t launch_wft(const ZTile* tA, int nA, const ZPtrs& pA, const ZTile* tB, int nB,
+                      const ZPtrs& pB, int nvec, int64_t zero_n, hipStream_t s) {
+    if (nvec < 1 || nvec > kWftMaxVec) return hipErrorInvalidValue;
+    if (zero_n > 0) {
+        const int64_t tot = zero_n * nvec;
+        const int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, pA.c[0], tot);
+    }
+    if (nA > 0) hipLaunchKernelGGL(k_zgemm, dim3(nA, nvec), dim3(64), 0, s, tA, pA);
+    if (nB > 0) hipLaunchKernelGGL(k_zgemm, dim3(nB, nvec), dim3(64), 0, s, tB, pB);
+    return hipGetLastError();
+}
+
+}  // namespace dmrg

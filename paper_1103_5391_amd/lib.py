@@ -29,6 +29,7 @@ SYMBOLS = [
     "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_set_graph", "dmrg_batch_tst_targets",
     "dmrg_batch_set_gemm", "dmrg_batch_autotune", "dmrg_profile_matvec",
     "dmrg_tst_chains", "dmrg_batch_tst_chains", "dmrg_ground_state", "dmrg_density_truncate",
+    "dmrg_wft_create", "dmrg_wft_apply", "dmrg_wft_destroy",
     "dmrg_strerror", "dmrg_last_error",
 ]
 
@@ -55,6 +56,16 @@ class dmrg_problem(C.Structure):
     _fields_ = [("S", dmrg_half), ("E", dmrg_half), ("target", C.c_int32 * 2),
                 ("nbond", C.c_int32), ("bonds", C.POINTER(dmrg_bond)),
                 ("nterm", C.c_int32), ("terms", C.POINTER(dmrg_term))]
+
+
+class dmrg_wft_desc(C.Structure):
+    _fields_ = [("n_esub", C.c_int32), ("esub", C.POINTER(C.c_int32)), ("nr", C.c_int32),
+                ("r_dim", C.POINTER(C.c_int32)), ("r_to_enew", C.POINTER(C.c_int32)),
+                ("kept", C.POINTER(C.c_int32)), ("n_ssub", C.c_int32),
+                ("ssub", C.POINTER(C.c_int32)), ("ns_new", C.c_int32),
+                ("s_new_qn", C.POINTER(C.c_int32)), ("s_new_dim", C.POINTER(C.c_int32)),
+                ("ne_new", C.c_int32), ("e_new_qn", C.POINTER(C.c_int32)),
+                ("e_new_dim", C.POINTER(C.c_int32))]
 
 
 class dmrg_krylov_info(C.Structure):
@@ -106,6 +117,9 @@ def load(path: str = LIB_PATH):
     lib.dmrg_density_truncate.argtypes = [vp, P(vp), P(dbl), i32, i32, vp, vp, P(i32), P(dbl)]
     lib.dmrg_batch_tst_chains.argtypes = [vp, P(vp), dbl, i32, P(vp), P(dbl),
                                           P(dmrg_krylov_info)]
+    lib.dmrg_wft_create.argtypes = [vp, P(dmrg_wft_desc), P(vp), P(vp), P(i64)]
+    lib.dmrg_wft_apply.argtypes = [vp, vp, i32, P(vp), P(vp), P(dbl)]
+    lib.dmrg_wft_destroy.argtypes = [vp]
     lib.dmrg_strerror.argtypes = [i32]
     lib.dmrg_strerror.restype = C.c_char_p
     lib.dmrg_last_error.argtypes = [vp]
@@ -340,6 +354,14 @@ class Handle:
 
     density_truncate = dmrg_density_truncate
 
+    def dmrg_wft_create(self, mv, W):
+        """Plans a move of the centre (wave-function transformation) described by mv (an
+        inputs.WftMove: sector tables of the move); W: per R sector a device tensor of
+        2 d_E' d_R doubles (W_r column-major, real then imaginary parts)."""
+        return Wft(self, mv, W)
+
+    wft_create = dmrg_wft_create
+
     def dmrg_set_graph(self, enable: bool):
         _check(self.lib.dmrg_set_graph(self.h, int(bool(enable))), self.h)
 
@@ -453,3 +475,47 @@ class Batch:
             self.dmrg_batch_destroy()
         except Exception:
             pass
+
+
+def _i32(rows) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(rows, dtype=np.int32).reshape(-1))
+
+
+class Wft:
+    """A planned move of the centre (dmrg_wft_create / dmrg_wft_apply / dmrg_wft_destroy)."""
+
+    def __init__(self, handle: "Handle", mv, W):
+        self.handle, self.lib, self.w = handle, handle.lib, C.c_void_p()
+        S, E = mv.layout.S.space, mv.layout.E.space
+        ssub = [(b, a, pp, off) for (b, a), (pp, off) in sorted(mv.ssub.items())]
+        self._keep = t = {
+            "esub": _i32(mv.esub), "r_dim": _i32(mv.r_dim), "r_to_enew": _i32(mv.r_to_enew),
+            "kept": _i32(mv.kept), "ssub": _i32(ssub), "s_qn": _i32(S.qn), "s_dim": _i32(S.dim),
+            "e_qn": _i32(E.qn), "e_dim": _i32(E.dim)}
+        d = dmrg_wft_desc(len(mv.esub), _dptr(t["esub"], C.c_int32), len(mv.r_dim),
+                          _dptr(t["r_dim"], C.c_int32), _dptr(t["r_to_enew"], C.c_int32),
+                          _dptr(t["kept"], C.c_int32), len(ssub), _dptr(t["ssub"], C.c_int32),
+                          len(S.dim), _dptr(t["s_qn"], C.c_int32), _dptr(t["s_dim"], C.c_int32),
+                          len(E.dim), _dptr(t["e_qn"], C.c_int32), _dptr(t["e_dim"], C.c_int32))
+        wp = (C.c_void_p * max(1, len(W)))(*[_tensor_ptr(x, x.numel()).value for x in W])
+        n_new = C.c_int64()
+        _check(self.lib.dmrg_wft_create(handle.h, C.byref(d), wp, C.byref(self.w), C.byref(n_new)),
+               handle.h)
+        self.n_new = n_new.value
+
+    def apply(self, U, xs, ys) -> float:
+        """y[v] = transformation of x[v] (device tensors of 2n and 2 n_new doubles), with U the
+        eigenvector buffer of density_truncate; returns the algorithmic flops."""
+        n2, m2 = 2 * self.handle.n, 2 * self.n_new
+        px = (C.c_void_p * len(xs))(*[_tensor_ptr(x, n2).value for x in xs])
+        py = (C.c_void_p * len(ys))(*[_tensor_ptr(y, m2).value for y in ys])
+        fl = C.c_double()
+        nu = sum(2 * int(r) * int(r) for r in self.handle.psi_layout()["rows"])
+        _check(self.lib.dmrg_wft_apply(self.w, _tensor_ptr(U, nu), len(xs), px, py, C.byref(fl)),
+               self.handle.h)
+        return fl.value
+
+    def destroy(self):
+        if self.w:
+            self.lib.dmrg_wft_destroy(self.w)
+            self.w = C.c_void_p()

@@ -536,6 +536,123 @@ def test_density_truncate_parity(env, name):
     h.destroy()
 
 
+def _evecs_layout(rows, evecs_by_block):
+    """Eigenvector matrices (complex d x d per psi block) in the layout of density_truncate."""
+    parts = []
+    for d, U in zip(rows, evecs_by_block):
+        parts.append(np.asarray(U.real).T.reshape(-1))
+        parts.append(np.asarray(U.imag).T.reshape(-1))
+    return np.concatenate(parts)
+
+
+def _w_device(torch, mv):
+    return [_dev(torch, np.concatenate([w.real.T.reshape(-1), w.imag.T.reshape(-1)])) for w in mv.W]
+
+
+@pytest.mark.parametrize("name,frac", [("chain8_exact", 1.0), ("chain8_exact", 0.3),
+                                       ("chain12_m30", 0.5), ("chain8_m17_odd", 0.4),
+                                       ("ladder16_m1000", 0.25)])
+def test_wft_parity(env, name, frac):
+    """Wave-function transformation of five targets against the oracle, with the oracle's
+    eigenvectors and kept counts (a global cut at frac of the states) as the input U."""
+    from oracle import density as Dn
+    from oracle import wft as Wo
+    torch, L = env
+    say("wft", name, frac)
+    pb = problem(name)
+    h = L.dmrg_create(pb)
+    n = h.n
+    rng = np.random.default_rng(I.SEED_BASE + 90)
+    vecs = [I.random_psi(n, rng) for _ in range(5)]
+    rows = [int(r) for r in h.psi_layout()["rows"]]
+    keep = max(1, int(frac * sum(rows)))
+    tr = Dn.truncate(pb, vecs, K.tst_weights(), keep)
+    kept = [int(tr.kept[p]) for p in tr.sectors]
+    mv = I.wft_move(pb, kept, seed=5)
+    w = h.wft_create(mv, _w_device(torch, mv))
+    assert w.n_new == I.psi_size(mv.layout)
+    Ud = _dev(torch, _evecs_layout(rows, [tr.evecs[p] for p in tr.sectors]))
+    xs = [_dev(torch, v) for v in vecs]
+    ys = [torch.full((2 * w.n_new,), float("nan"), dtype=torch.float64, device="cuda") for _ in vecs]
+    fl = w.apply(Ud, xs, ys)
+    assert fl > 0
+    worst = 0.0
+    for v, y in zip(vecs, ys):
+        ref = Wo.wft_right(pb, mv, tr.evecs, v)
+        got = _host(y)
+        assert np.all(np.isfinite(got))
+        worst = max(worst, float(np.max(np.abs(got - ref)) / max(np.max(np.abs(ref)), 1e-300)))
+    say("  n", n, "n_new", w.n_new, "kept", sum(kept), "max rel err", worst)
+    assert worst <= 1e-12
+    # one vector at a time gives the same bits as the five together
+    y1 = torch.full_like(ys[0], float("nan"))
+    w.apply(Ud, xs[2:3], [y1])
+    assert torch.equal(y1, ys[2])
+    w.destroy()
+    h.destroy()
+
+
+def test_wft_after_gpu_density(env):
+    """The GPU's own density eigenvectors feed the GPU transformation: the result depends on
+    the basis of the kept states only through its norm, which must equal the weight of each
+    target on the kept subspace (the oracle's projector; the cut sits at a clear gap)."""
+    from oracle import density as Dn
+    torch, L = env
+    name = "chain12_m30"
+    say("wft after density", name)
+    pb = problem(name)
+    h = L.dmrg_create(pb)
+    n = h.n
+    rng = np.random.default_rng(I.SEED_BASE + 91)
+    vecs = [I.random_psi(n, rng) for _ in range(5)]
+    w8 = K.tst_weights()
+    rows = [int(r) for r in h.psi_layout()["rows"]]
+    total = sum(rows)
+    allv = np.sort(np.concatenate(list(Dn.truncate(pb, vecs, w8, total).evals.values())))[::-1]
+    gaps = allv[total // 4:total // 2] - allv[total // 4 + 1:total // 2 + 1]
+    keep = total // 4 + 1 + int(np.argmax(gaps))
+    tr = Dn.truncate(pb, vecs, w8, keep)
+    xs = [_dev(torch, v) for v in vecs]
+    evd = torch.empty(total, dtype=torch.float64, device="cuda")
+    vcd = torch.empty(sum(2 * r * r for r in rows), dtype=torch.float64, device="cuda")
+    kept, _ = h.density_truncate(xs, w8, keep, evd, vcd)
+    assert [int(k) for k in kept] == [int(tr.kept[p]) for p in tr.sectors]
+    mv = I.wft_move(pb, [int(k) for k in kept], seed=6)
+    w = h.wft_create(mv, _w_device(torch, mv))
+    ys = [torch.empty(2 * w.n_new, dtype=torch.float64, device="cuda") for _ in vecs]
+    w.apply(vcd, xs, ys)
+    for v, y in zip(vecs, ys):
+        blocks = M.unpack(pb, v)
+        want = sum(np.linalg.norm(tr.evecs[p][:, :tr.kept[p]].conj().T @ blocks[p]) ** 2
+                   for p in tr.sectors)
+        got = float(torch.linalg.vector_norm(y)) ** 2
+        assert abs(got - want) <= 1e-12, (got, want)
+    w.destroy()
+    h.destroy()
+
+
+def test_wft_rejects_inconsistent_moves(env):
+    torch, L = env
+    pb = problem("chain12_m30")
+    h = L.dmrg_create(pb)
+    rows = [int(r) for r in h.psi_layout()["rows"]]
+    kept = [max(1, r // 2) for r in rows]
+    mv = I.wft_move(pb, kept, seed=7)
+    Wd = _w_device(torch, mv)
+    bad = I.wft_move(pb, kept, seed=7)
+    bad.kept = [r + 1 for r in rows]                      # more than the sector holds
+    with pytest.raises(L.DmrgError):
+        h.wft_create(bad, Wd)
+    bad = I.wft_move(pb, kept, seed=7)
+    (b, a), (pp, off) = next(iter(bad.ssub.items()))
+    bad.ssub[(b, a)] = (pp, int(bad.layout.S.space.dim[pp]))   # rows outside the sector
+    with pytest.raises(L.DmrgError):
+        h.wft_create(bad, Wd)
+    w = h.wft_create(mv, Wd)
+    w.destroy()
+    h.destroy()
+
+
 def _batch_setup(torch, L, pbs, seed):
     hs = [L.dmrg_create(pb) for pb in pbs]
     phis = [I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + seed + i)) for i, h in enumerate(hs)]
