@@ -447,6 +447,61 @@ def synthetic_problem(L: int, m: int, U: float, lattice_bonds, seed: int, name="
 
 
 # --------------------------------------------------------------------------------------------
+# local operators of the halves (operator application and observables)
+# --------------------------------------------------------------------------------------------
+def _op_mul(A: BlockOp, B: BlockOp, sp: Space) -> BlockOp:
+    """The block operator A B (B applied first) on one space."""
+    out = BlockOp((A.dq[0] + B.dq[0], A.dq[1] + B.dq[1]))
+    for p, b in B.blocks.items():
+        p2 = sp.shift(p, B.dq)
+        if p2 is not None and p2 in A.blocks:
+            out.blocks[p] = A.blocks[p2] @ b
+    return out
+
+
+def _op_add(A: BlockOp, B: BlockOp, sb: float = 1.0) -> BlockOp:
+    """A + sb B for operators with the same dq."""
+    assert A.dq == B.dq
+    out = BlockOp(A.dq, {p: b.copy() for p, b in A.blocks.items()})
+    for p, b in B.blocks.items():
+        out.blocks[p] = out.blocks[p] + sb * b if p in out.blocks else sb * b
+    return out
+
+
+def site_ops(blk: Block, site: int) -> dict:
+    """Operators of one lattice site carried by a block (exact blocks carry every site), as
+    block operators of the block's space: cdag_s, c_s, n_s (s = 0 up, 1 down), n (both
+    spins), nn = n_up n_dn, holon_s = c_s (1 - n_sbar) and doublon_s = c+_s n_sbar (the two
+    factors of the holon-doublon operator, Sec. III.B)."""
+    sp = blk.space
+    out = {}
+    for s in (UP, DN):
+        cd = blk.cdag[site][s]
+        out[f"cdag_{s}"] = cd
+        out[f"c_{s}"] = _transpose(cd, sp)
+        out[f"n_{s}"] = _op_mul(cd, out[f"c_{s}"], sp)
+    out["n"] = _op_add(out["n_0"], out["n_1"])
+    out["nn"] = _op_mul(out["n_0"], out["n_1"], sp)
+    for s in (UP, DN):
+        sb = 1 - s
+        out[f"holon_{s}"] = _op_add(out[f"c_{s}"], _op_mul(out[f"c_{s}"], out[f"n_{sb}"], sp), -1.0)
+        out[f"doublon_{s}"] = _op_mul(out[f"cdag_{s}"], out[f"n_{sb}"], sp)
+    return out
+
+
+def with_ops(pb: Problem, extra_S=(), extra_E=(), target=None) -> tuple:
+    """A copy of pb whose halves also carry the given block operators (after the operators of
+    its bonds), optionally for another target sector; returns (problem, indices of extra_S in
+    S.ops, indices of extra_E in E.ops)."""
+    S, E = pb.S, pb.E
+    S2 = Half(S.space, S.H, list(S.ops) + list(extra_S), list(S.op_label) + [("x", k) for k in range(len(extra_S))], S.sites)
+    E2 = Half(E.space, E.H, list(E.ops) + list(extra_E), list(E.op_label) + [("x", k) for k in range(len(extra_E))], E.sites)
+    out = Problem(S2, E2, tuple(target) if target is not None else pb.target, pb.bonds, name=pb.name,
+                  L=pb.L, U=pb.U, lattice_bonds=pb.lattice_bonds, Sblk=pb.Sblk, Eblk=pb.Eblk)
+    return out, list(range(len(S.ops), len(S2.ops))), list(range(len(E.ops), len(E2.ops)))
+
+
+# --------------------------------------------------------------------------------------------
 # moving the centre one site to the right: the bases involved (wave-function transformation)
 # --------------------------------------------------------------------------------------------
 @dataclass
