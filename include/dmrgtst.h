@@ -298,6 +298,26 @@ int dmrg_wft_apply(dmrg_wft w, const double* U, int32_t nvec, const double* cons
 
 int dmrg_wft_destroy(dmrg_wft w);
 
+/* Local operators on the superblock (Sec. II.B, Eq. (b): the operators B applied to the ground
+ * state to form phi; Sec. III.B: the measured densities n_p and double occupations): with the
+ * same halves in both handles,
+ *   y = sum_t terms[t].coef (A_t P_S^f_t (x) B_t) x,
+ * A_t = src's S.ops[opS] (transposed if transS; opS = -1: the identity), B_t = src's E.ops[opE]
+ * likewise, P_S the fermion parity of the system (f_t = terms[t].fermionic: set it when B_t is
+ * odd, since B_t then passes the system's modes).  x: device, src's layout; y: device, dst's
+ * layout (dst's target = src's target plus the quantum numbers the terms add); y is
+ * overwritten and must not be x.  Operator blocks of src that have no image in dst's sector
+ * contribute nothing.  Asynchronous on src's stream.  DMRG_EINVAL for different halves, an
+ * operator index out of range or a term that does not map src's target to dst's. */
+int dmrg_apply_local(dmrg_handle src, dmrg_handle dst, int32_t nterm, const dmrg_term* terms,
+                     const double* x, double* y);
+
+/* <x| sum_t terms[t] |x> for terms that keep the handle's sector (as in dmrg_apply_local with
+ * src = dst = h): re, im (host, may be NULL) receive its real and imaginary parts.  Fixed-order
+ * reduction; the call waits for the stream. */
+int dmrg_expect_local(dmrg_handle h, int32_t nterm, const dmrg_term* terms, const double* x,
+                      double* re, double* im);
+
 /* 4-RHS (per-target) mode of time-step targeting: the four targets are kept as four independent
  * chains, each advanced by exp(-i tau H) with a Krylov basis of its own (kdim vectors, Sec. II.A)
  * instead of one basis evaluated at four times (the variant of the seeding of the next

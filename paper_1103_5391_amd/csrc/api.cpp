@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -37,6 +38,10 @@ hipError_t launch_density(const DBlock*, int, const DTile*, int, const double* c
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const ZPtrs&, int, int64_t,
                       hipStream_t);
+hipError_t launch_zgemm(const ZTile*, int, const ZPtrs&, int, hipStream_t);
+hipError_t launch_zero(double*, int64_t, hipStream_t);
+hipError_t launch_zdot(const double*, const double*, int64_t, double*, int, hipStream_t);
+constexpr int kDotBlocks = 256;     // partial sums of one inner product
 int vec_blocks(int64_t n);
 int red_blocks(int64_t n);
 
@@ -283,6 +288,10 @@ struct dmrg_ctx {
     int dens_ntiles = 0, dens_ntot = 0;
     int64_t dens_nmat = 0;
     std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
+    // local operators (built on first use): raw operator blocks of both halves, the product
+    // intermediate, the tile list and the inner-product partials
+    DevBuf dOpS, dOpE, dLocT, dLocZ, dLocTiles, dLocPart;
+    std::vector<int64_t> opS_base, opE_base;
 };
 
 // A planned move of the centre (wave-function transformation): tile lists of its two stages,
@@ -696,14 +705,15 @@ int plan_wft(dmrg_handle h, const dmrg_wft_desc& D, std::vector<ZTile>& tA, std:
                 P.E.ndn[q] - D.e_new_qn[2 * rr + 1] != D.s_new_qn[2 * pp + 1] - P.S.ndn[B.p])
                 return bad("site state with different quantum numbers on the two sides");
             ZTile t{};
+            t.alpha = 1.0;
             t.M = D.kept[b];
             t.N = D.r_dim[r];
             t.K = B.d;
-            t.amode = 1;
+            t.amode = ZM_CT;
             t.aoff = uoff[b];
             t.aim = (int64_t)B.d * B.d;
             t.lda = B.d;
-            t.bmode = 0;
+            t.bmode = ZM_COL;
             t.boff = B.off + (int64_t)coff * B.d;
             t.bim = P.n;
             t.ldb = B.d;
@@ -724,14 +734,15 @@ int plan_wft(dmrg_handle h, const dmrg_wft_desc& D, std::vector<ZTile>& tA, std:
         if (col_of[i] < 0) continue;
         const int rr = col_of[i], r = r_of_enew[rr];
         ZTile t{};
+        t.alpha = 1.0;
         t.M = D.s_new_dim[i];
         t.N = D.e_new_dim[rr];
         t.K = r >= 0 ? D.r_dim[r] : 0;
-        t.amode = 0;
+        t.amode = ZM_COL;
         t.aoff = r >= 0 ? phi_off[i] : 0;
         t.aim = nphi;
         t.lda = std::max(1, D.s_new_dim[i]);
-        t.bmode = 1;
+        t.bmode = ZM_CT;
         t.boff = r >= 0 ? woff[r] : 0;
         t.bim = r >= 0 ? (int64_t)D.e_new_dim[rr] * D.r_dim[r] : 0;
         t.ldb = std::max(1, D.e_new_dim[rr]);
@@ -745,6 +756,188 @@ int plan_wft(dmrg_handle h, const dmrg_wft_desc& D, std::vector<ZTile>& tA, std:
     w.n_new = n_new;
     w.phi_zero = zero;
     w.flops_vec = flops;
+    return DMRG_OK;
+}
+
+// Device copy of the raw operator blocks of both halves (first use of local operators).
+int ensure_local_ops(dmrg_handle h) {
+    if (h->dOpS.p && h->dOpE.p) return DMRG_OK;
+    for (int side = 0; side < 2; ++side) {
+        const HalfTable& T = side == 0 ? h->plan.S : h->plan.E;
+        std::vector<double> all;
+        std::vector<int64_t>& base = side == 0 ? h->opS_base : h->opE_base;
+        base.clear();
+        for (const HalfTable::Op& op : T.ops) {
+            base.push_back((int64_t)all.size());
+            all.insert(all.end(), op.data.begin(), op.data.end());
+        }
+        HIP_TRY(h, upload(side == 0 ? h->dOpS : h->dOpE, all, h->stream));
+    }
+    return DMRG_OK;
+}
+
+// One factor of a local term on one half: the block that maps sector p (as source) and where
+// it goes.  op < 0 is the identity.  Returns false if the factor has no block leaving p.
+struct Factor {
+    int dst;          // destination sector
+    int mode;         // ZM_RCOL (op block), ZM_RT (transposed block), ZM_ID
+    int64_t off;      // block offset (doubles) in the device copy
+    int ld;           // leading dimension of the stored block
+};
+
+bool factor_of(const HalfTable& T, const std::vector<int64_t>& base, int op, int trans, int p,
+               Factor& f) {
+    if (op < 0) {
+        f = Factor{p, ZM_ID, 0, 1};
+        return true;
+    }
+    const HalfTable::Op& o = T.ops[op];
+    if (!trans) {
+        if (o.boff[p] < 0) return false;
+        const int d = T.find(T.nup[p] + o.dq[0], T.ndn[p] + o.dq[1]);
+        f = Factor{d, ZM_RCOL, base[op] + o.boff[p], T.dim[d]};
+        return true;
+    }
+    // transposed: the block of op whose destination is p, from source p - dq
+    const int src = T.find(T.nup[p] - o.dq[0], T.ndn[p] - o.dq[1]);
+    if (src < 0 || o.boff[src] < 0) return false;
+    f = Factor{src, ZM_RT, base[op] + o.boff[src], T.dim[p]};
+    return true;
+}
+
+// Tile lists of y = sum_t coef_t (A_t P_S^f_t (x) B_t) x (src layout -> dst layout): per term,
+// the right products T = X B^T (terms with an environment factor) then the left products
+// y += alpha A T; launches[i] = (first tile, count, which product).
+int plan_local(dmrg_handle hs, dmrg_handle hd, int nterm, const dmrg_term* terms,
+               std::vector<ZTile>& tiles, std::vector<std::array<int, 3>>& launches, int64_t& tsize) {
+    const Plan& S = hs->plan;
+    const Plan& D = hd->plan;
+    auto bad = [&](const std::string& why) { return fail(hs, DMRG_EINVAL, "local operator: " + why); };
+    for (int side = 0; side < 2; ++side) {
+        const HalfTable& a = side == 0 ? S.S : S.E;
+        const HalfTable& b = side == 0 ? D.S : D.E;
+        if (a.nup != b.nup || a.ndn != b.ndn || a.dim != b.dim) return bad("the handles have different halves");
+    }
+    tsize = 0;
+    for (int t = 0; t < nterm; ++t) {
+        const dmrg_term& tm = terms[t];
+        if (tm.opS < -1 || tm.opS >= (int)S.S.ops.size() || tm.opE < -1 || tm.opE >= (int)S.E.ops.size())
+            return bad("operator index out of range");
+        if (!std::isfinite(tm.coef)) return fail(hs, DMRG_ENONFINITE, "local operator: coefficient is not finite");
+        int dq[2] = {0, 0};
+        if (tm.opS >= 0)
+            for (int k = 0; k < 2; ++k) dq[k] += (tm.transS ? -1 : 1) * S.S.ops[tm.opS].dq[k];
+        if (tm.opE >= 0)
+            for (int k = 0; k < 2; ++k) dq[k] += (tm.transE ? -1 : 1) * S.E.ops[tm.opE].dq[k];
+        if (S.target[0] + dq[0] != D.target[0] || S.target[1] + dq[1] != D.target[1])
+            return bad("the term does not map the source sector to the destination sector");
+        std::vector<ZTile> right, left;
+        int64_t toff = 0;
+        for (const PsiBlock& B : S.blocks) {
+            Factor fa, fb;
+            if (!factor_of(S.S, hs->opS_base, tm.opS, tm.transS, B.p, fa)) continue;
+            if (!factor_of(S.E, hs->opE_base, tm.opE, tm.transE, B.q, fb)) continue;
+            const int ob = fa.dst < (int)D.block_of_S.size() ? D.block_of_S[fa.dst] : -1;
+            if (ob < 0 || D.blocks[ob].q != fb.dst) continue;      // no such block in the target
+            const PsiBlock& O = D.blocks[ob];
+            const double sign = (tm.fermionic && ((S.S.nup[B.p] + S.S.ndn[B.p]) & 1)) ? -1.0 : 1.0;
+            const int eo = S.E.dim[fb.dst];
+            ZTile lt{};
+            lt.alpha = tm.coef * sign;
+            lt.acc = 1;
+            lt.M = O.d;
+            lt.N = eo;
+            lt.K = B.d;
+            lt.amode = fa.mode;
+            lt.aoff = fa.off;
+            lt.lda = fa.ld;
+            lt.bmode = ZM_COL;
+            lt.ldb = B.d;
+            lt.coff = O.off;
+            lt.cim = D.n;
+            lt.ldc = O.d;
+            if (fb.mode != ZM_ID) {
+                ZTile rt{};
+                rt.alpha = 1.0;
+                rt.M = B.d;
+                rt.N = eo;
+                rt.K = B.e;
+                rt.amode = ZM_COL;
+                rt.aoff = B.off;
+                rt.aim = S.n;
+                rt.lda = B.d;
+                rt.bmode = fb.mode == ZM_RCOL ? ZM_RT : ZM_RCOL;   // B^T of the stored block
+                rt.boff = fb.off;
+                rt.ldb = fb.ld;
+                rt.coff = toff;
+                rt.ldc = B.d;
+                for (int m0 = 0; m0 < rt.M; m0 += kZTile)
+                    for (int n0 = 0; n0 < rt.N; n0 += kZTile) {
+                        rt.m0 = m0;
+                        rt.n0 = n0;
+                        right.push_back(rt);
+                    }
+                lt.boff = toff;
+                lt.bim = -1;                  // the intermediate's plane offset, set below
+                toff += (int64_t)B.d * eo;
+            } else {
+                lt.boff = B.off;
+                lt.bim = S.n;
+            }
+            for (int m0 = 0; m0 < lt.M; m0 += kZTile)
+                for (int n0 = 0; n0 < lt.N; n0 += kZTile) {
+                    lt.m0 = m0;
+                    lt.n0 = n0;
+                    left.push_back(lt);
+                }
+        }
+        for (ZTile& z : right) z.cim = toff;
+        for (ZTile& z : left)
+            if (z.bim < 0) z.bim = toff;
+        tsize = std::max(tsize, toff);
+        if (!right.empty()) {
+            launches.push_back({(int)tiles.size(), (int)right.size(), 0});
+            tiles.insert(tiles.end(), right.begin(), right.end());
+        }
+        if (!left.empty()) {
+            launches.push_back({(int)tiles.size(), (int)left.size(), tm.opE >= 0 ? 1 : 2});
+            tiles.insert(tiles.end(), left.begin(), left.end());
+        }
+    }
+    return DMRG_OK;
+}
+
+// y (dst layout) = sum of the terms applied to x (src layout); asynchronous.  launches[i][2]:
+// 0 right products, 1 left products of the intermediate, 2 left products of x.
+int run_local(dmrg_handle hs, dmrg_handle hd, int nterm, const dmrg_term* terms, const double* x,
+              double* y) {
+    int rc = ensure_local_ops(hs);
+    if (rc) return rc;
+    std::vector<ZTile> tiles;
+    std::vector<std::array<int, 3>> launches;
+    int64_t tsize = 0;
+    rc = plan_local(hs, hd, nterm, terms, tiles, launches, tsize);
+    if (rc) return rc;
+    hipStream_t s = hs->stream;
+    if ((int64_t)hs->dLocT.bytes < (int64_t)sizeof(double) * 2 * std::max<int64_t>(tsize, 1)) {
+        HIP_TRY(hs, hipStreamSynchronize(s));
+        HIP_TRY(hs, hs->dLocT.alloc(sizeof(double) * 2 * (size_t)std::max<int64_t>(tsize, 1)));
+    }
+    HIP_TRY(hs, upload(hs->dLocTiles, tiles, s));
+    HIP_TRY(hs, launch_zero(y, 2 * hd->plan.n, s));
+    for (const auto& L : launches) {
+        ZPtrs p{};
+        if (L[2] == 0) {            // right products: x, environment blocks -> intermediate
+            p.a[0] = x;
+            p.b[0] = hs->dOpE.as<double>();
+            p.c[0] = hs->dLocT.as<double>();
+        } else {                    // left products: system blocks, intermediate or x -> y
+            p.a[0] = hs->dOpS.as<double>();
+            p.b[0] = L[2] == 1 ? hs->dLocT.as<double>() : x;
+            p.c[0] = y;
+        }
+        HIP_TRY(hs, launch_zgemm(hs->dLocTiles.as<ZTile>() + L[0], L[1], p, 1, s));
+    }
     return DMRG_OK;
 }
 
@@ -1101,6 +1294,38 @@ int dmrg_wft_destroy(dmrg_wft w) {
     if (!w) return DMRG_EINVAL;
     if (w->h) (void)hipStreamSynchronize(w->h->stream);
     delete w;
+    return DMRG_OK;
+}
+
+int dmrg_apply_local(dmrg_handle src, dmrg_handle dst, int32_t nterm, const dmrg_term* terms,
+                     const double* x, double* y) {
+    if (!src || !dst) return DMRG_EINVAL;
+    if (nterm < 1 || !terms || !x || !y) return fail(src, DMRG_EINVAL, "local operator: NULL or empty argument");
+    if (x == y) return fail(src, DMRG_EINVAL, "local operator: y must not be x");
+    return run_local(src, dst, nterm, terms, x, y);
+}
+
+int dmrg_expect_local(dmrg_handle h, int32_t nterm, const dmrg_term* terms, const double* x,
+                      double* re, double* im) {
+    if (!h) return DMRG_EINVAL;
+    if (nterm < 1 || !terms || !x) return fail(h, DMRG_EINVAL, "local operator: NULL or empty argument");
+    hipStream_t s = h->stream;
+    if (!h->dLocZ.p) HIP_TRY(h, h->dLocZ.alloc(sizeof(double) * 2 * (size_t)h->plan.n));
+    if (!h->dLocPart.p) HIP_TRY(h, h->dLocPart.alloc(sizeof(double) * 2 * kDotBlocks));
+    int rc = run_local(h, h, nterm, terms, x, h->dLocZ.as<double>());
+    if (rc) return rc;
+    HIP_TRY(h, launch_zdot(x, h->dLocZ.as<double>(), h->plan.n, h->dLocPart.as<double>(), kDotBlocks, s));
+    std::vector<double> part(2 * kDotBlocks);
+    HIP_TRY(h, hipMemcpyAsync(part.data(), h->dLocPart.p, sizeof(double) * part.size(),
+                              hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipStreamSynchronize(s));
+    double ar = 0.0, ai = 0.0;
+    for (int b = 0; b < kDotBlocks; ++b) {
+        ar += part[2 * b];
+        ai += part[2 * b + 1];
+    }
+    if (re) *re = ar;
+    if (im) *im = ai;
     return DMRG_OK;
 }
 

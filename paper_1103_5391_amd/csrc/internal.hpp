@@ -159,14 +159,20 @@ constexpr int kDensMaxDim = 1024;   // largest system sector the Jacobi kernel a
 constexpr int kDensMaxVec = 16;     // most target vectors of one density matrix
 constexpr int kDensSweeps = 40;     // Jacobi sweeps at most (convergence ends it earlier)
 
-// One 32 x 32 tile of a complex product C = A B (FP64; both planes of every operand: real
-// parts at off, imaginary parts at off + im).  A modes: 0 column-major, A(i, k) at i + k lda;
-// 1 conjugate transpose of a column-major X, A(i, k) = conj(X(k, i)) at k + i lda.  B modes:
-// 0 column-major, B(k, j) at k + j ldb; 1 transpose of a column-major X, B(k, j) = X(j, k) at
-// j + k ldb.  C is column-major (ldc).  K = 0 writes a zero tile.
+// One 32 x 32 tile of a complex product C = alpha A B (+ C if acc) (FP64; complex operands
+// have real parts at off and imaginary parts at off + im).  A modes: 0 complex column-major,
+// A(i, k) at i + k lda; 1 conjugate transpose of a complex column-major X, A(i, k) =
+// conj(X(k, i)) at k + i lda; 2 real column-major; 3 real transpose, A(i, k) = X(k, i) at
+// k + i lda; 4 the identity (no memory).  B modes: 0 complex column-major, B(k, j) at
+// k + j ldb; 1 transpose of a complex column-major X, B(k, j) = X(j, k) at j + k ldb; 2 real
+// column-major; 3 real transpose.  C is complex column-major (ldc).  K = 0 gives a zero
+// product.
+enum ZMode { ZM_COL = 0, ZM_CT = 1, ZM_RCOL = 2, ZM_RT = 3, ZM_ID = 4 };
 struct ZTile {
     int32_t M, N, K, m0, n0;
     int32_t amode, bmode, lda, ldb, ldc;
+    int32_t acc, pad;
+    double alpha;
     int64_t aoff, aim, boff, bim, coff, cim;
 };
 constexpr int kZTile = 32;

@@ -23,16 +23,29 @@ namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 
-// Element k of a lane's four consecutive K values: both planes of one operand element, zero
-// outside the matrix.
+// Both planes of one operand element (zero outside the matrix; imaginary part zero for real
+// operands).
 __device__ __forceinline__ void load_a(const ZTile& t, const double* __restrict__ A, int i, int k,
                                        double& re, double& im) {
     re = 0.0;
     im = 0.0;
-    if (i < t.M && k < t.K) {
-        const int64_t at = t.amode == 0 ? t.aoff + (int64_t)k * t.lda + i : t.aoff + (int64_t)i * t.lda + k;
-        re = A[at];
-        im = t.amode == 0 ? A[at + t.aim] : -A[at + t.aim];
+    if (i >= t.M || k >= t.K) return;
+    switch (t.amode) {
+        case ZM_COL: {
+            const int64_t at = t.aoff + (int64_t)k * t.lda + i;
+            re = A[at];
+            im = A[at + t.aim];
+            break;
+        }
+        case ZM_CT: {
+            const int64_t at = t.aoff + (int64_t)i * t.lda + k;
+            re = A[at];
+            im = -A[at + t.aim];
+            break;
+        }
+        case ZM_RCOL: re = A[t.aoff + (int64_t)k * t.lda + i]; break;
+        case ZM_RT: re = A[t.aoff + (int64_t)i * t.lda + k]; break;
+        default: re = i == k ? 1.0 : 0.0; break;
     }
 }
 
@@ -40,10 +53,22 @@ __device__ __forceinline__ void load_b(const ZTile& t, const double* __restrict_
                                        double& re, double& im) {
     re = 0.0;
     im = 0.0;
-    if (j < t.N && k < t.K) {
-        const int64_t at = t.bmode == 0 ? t.boff + (int64_t)j * t.ldb + k : t.boff + (int64_t)k * t.ldb + j;
-        re = B[at];
-        im = B[at + t.bim];
+    if (j >= t.N || k >= t.K) return;
+    switch (t.bmode) {
+        case ZM_COL: {
+            const int64_t at = t.boff + (int64_t)j * t.ldb + k;
+            re = B[at];
+            im = B[at + t.bim];
+            break;
+        }
+        case ZM_CT: {            // transpose (no conjugate) of a complex column-major matrix
+            const int64_t at = t.boff + (int64_t)k * t.ldb + j;
+            re = B[at];
+            im = B[at + t.bim];
+            break;
+        }
+        case ZM_RCOL: re = B[t.boff + (int64_t)j * t.ldb + k]; break;
+        default: re = B[t.boff + (int64_t)k * t.ldb + j]; break;
     }
 }
 
@@ -107,8 +132,13 @@ __global__ __launch_bounds__(64) void k_zgemm(const ZTile* __restrict__ tiles, Z
                 const int i = t.m0 + 16 * mi + g + 4 * q;
                 if (i >= t.M) continue;
                 const int64_t at = t.coff + (int64_t)j * t.ldc + i;
-                C[at] = cre[mi][nj][q];
-                C[at + t.cim] = cim[mi][nj][q];
+                double vr = t.alpha * cre[mi][nj][q], vi = t.alpha * cim[mi][nj][q];
+                if (t.acc) {
+                    vr += C[at];
+                    vi += C[at + t.cim];
+                }
+                C[at] = vr;
+                C[at + t.cim] = vi;
             }
         }
 }
@@ -132,6 +162,56 @@ hipError_t launch_wft(const ZTile* tA, int nA, const ZPtrs& pA, const ZTile* tB,
     }
     if (nA > 0) hipLaunchKernelGGL(k_zgemm, dim3(nA, nvec), dim3(64), 0, s, tA, pA);
     if (nB > 0) hipLaunchKernelGGL(k_zgemm, dim3(nB, nvec), dim3(64), 0, s, tB, pB);
+    return hipGetLastError();
+}
+
+// One list of product tiles for nvec vectors (local operators, Sec. II.B: B|psi> and the
+// measured operators).
+hipError_t launch_zgemm(const ZTile* t, int n, const ZPtrs& p, int nvec, hipStream_t s) {
+    if (nvec < 1 || nvec > kWftMaxVec) return hipErrorInvalidValue;
+    if (n > 0) hipLaunchKernelGGL(k_zgemm, dim3(n, nvec), dim3(64), 0, s, t, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero(double* x, int64_t n, hipStream_t s) {
+    if (n > 0) {
+        const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, x, n);
+    }
+    return hipGetLastError();
+}
+
+// Partial sums of <x|z> = sum conj(x) z over n complex elements (planes at +n): block b writes
+// (Re, Im) of its grid-stride share to part[2 b], part[2 b + 1]; the caller adds the partials
+// in order.
+__global__ __launch_bounds__(256) void k_zdot(const double* __restrict__ x, const double* __restrict__ z,
+                                              int64_t n, double* __restrict__ part) {
+    __shared__ double sr[256], si[256];
+    double ar = 0.0, ai = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const double xr = x[i], xi = x[n + i], zr = z[i], zi = z[n + i];
+        ar += xr * zr + xi * zi;
+        ai += xr * zi - xi * zr;
+    }
+    sr[threadIdx.x] = ar;
+    si[threadIdx.x] = ai;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+            sr[threadIdx.x] += sr[threadIdx.x + s];
+            si[threadIdx.x] += si[threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = sr[0];
+        part[2 * blockIdx.x + 1] = si[0];
+    }
+}
+
+hipError_t launch_zdot(const double* x, const double* z, int64_t n, double* part, int nblocks,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(k_zdot, dim3(nblocks), dim3(256), 0, s, x, z, n, part);
     return hipGetLastError();
 }
 

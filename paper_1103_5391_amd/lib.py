@@ -29,7 +29,8 @@ SYMBOLS = [
     "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_set_graph", "dmrg_batch_tst_targets",
     "dmrg_batch_set_gemm", "dmrg_batch_autotune", "dmrg_profile_matvec",
     "dmrg_tst_chains", "dmrg_batch_tst_chains", "dmrg_ground_state", "dmrg_density_truncate",
-    "dmrg_wft_create", "dmrg_wft_apply", "dmrg_wft_destroy",
+    "dmrg_wft_create", "dmrg_wft_apply", "dmrg_wft_destroy", "dmrg_apply_local",
+    "dmrg_expect_local",
     "dmrg_strerror", "dmrg_last_error",
 ]
 
@@ -120,6 +121,8 @@ def load(path: str = LIB_PATH):
     lib.dmrg_wft_create.argtypes = [vp, P(dmrg_wft_desc), P(vp), P(vp), P(i64)]
     lib.dmrg_wft_apply.argtypes = [vp, vp, i32, P(vp), P(vp), P(dbl)]
     lib.dmrg_wft_destroy.argtypes = [vp]
+    lib.dmrg_apply_local.argtypes = [vp, vp, i32, P(dmrg_term), vp, vp]
+    lib.dmrg_expect_local.argtypes = [vp, i32, P(dmrg_term), vp, P(dbl), P(dbl)]
     lib.dmrg_strerror.argtypes = [i32]
     lib.dmrg_strerror.restype = C.c_char_p
     lib.dmrg_last_error.argtypes = [vp]
@@ -354,6 +357,25 @@ class Handle:
 
     density_truncate = dmrg_density_truncate
 
+    def dmrg_apply_local(self, dst: "Handle", terms, x, y):
+        """y (dst's layout) = sum of terms applied to x; a term is (coef, opS, transS, opE,
+        transE, fermionic) with op indices into this handle's half operators (-1: identity)."""
+        ct = _terms_to_c(terms)
+        _check(self.lib.dmrg_apply_local(self.h, dst.h, len(terms), ct, _tensor_ptr(x, 2 * self.n),
+                                         _tensor_ptr(y, 2 * dst.n)), self.h)
+
+    apply_local = dmrg_apply_local
+
+    def dmrg_expect_local(self, terms, x) -> complex:
+        """<x| sum of terms |x> (terms that keep the sector)."""
+        ct = _terms_to_c(terms)
+        re, im = C.c_double(), C.c_double()
+        _check(self.lib.dmrg_expect_local(self.h, len(terms), ct, _tensor_ptr(x, 2 * self.n),
+                                          C.byref(re), C.byref(im)), self.h)
+        return complex(re.value, im.value)
+
+    expect_local = dmrg_expect_local
+
     def dmrg_wft_create(self, mv, W):
         """Plans a move of the centre (wave-function transformation) described by mv (an
         inputs.WftMove: sector tables of the move); W: per R sector a device tensor of
@@ -475,6 +497,14 @@ class Batch:
             self.dmrg_batch_destroy()
         except Exception:
             pass
+
+
+def _terms_to_c(terms):
+    ct = (dmrg_term * max(1, len(terms)))()
+    for i, t in enumerate(terms):
+        ct[i].coef, ct[i].opS, ct[i].transS = float(t[0]), int(t[1]), int(t[2])
+        ct[i].opE, ct[i].transE, ct[i].fermionic = int(t[3]), int(t[4]), int(t[5])
+    return ct
 
 
 def _i32(rows) -> np.ndarray:

@@ -653,6 +653,204 @@ def test_wft_rejects_inconsistent_moves(env):
     h.destroy()
 
 
+def _local_setup(pb, site_kinds):
+    """pb with the requested site operators appended to its halves: returns (problem, {(site,
+    kind): (side, op index, BlockOp)})."""
+    extra = {"S": [], "E": []}
+    keys = []
+    for (site, kind) in site_kinds:
+        side = "S" if site in pb.Sblk.sites else "E"
+        blk = pb.Sblk if side == "S" else pb.Eblk
+        extra[side].append(I.site_ops(blk, site)[kind])
+        keys.append((site, kind, side, len(extra[side]) - 1))
+    pbx, iS, iE = I.with_ops(pb, extra["S"], extra["E"])
+    ops = {}
+    for (site, kind, side, k) in keys:
+        ops[(site, kind)] = (side, (iS if side == "S" else iE)[k], extra[side][k])
+    return pbx, extra, ops
+
+
+_ODD = ("cdag", "c_", "holon", "doublon")
+
+
+def _gpu_and_oracle_term(pbx, ops, site, kind, trans=0, coef=1.0):
+    side, idx, op = ops[(site, kind)]
+    sp = pbx.S.space if side == "S" else pbx.E.space
+    o = I._transpose(op, sp) if trans else op
+    if side == "S":
+        return (coef, idx, trans, -1, 0, 0), (coef, o, None, 0)
+    f = 1 if kind.startswith(_ODD) else 0
+    return (coef, -1, 0, idx, trans, f), (coef, None, o, f)
+
+
+@pytest.mark.parametrize("name", ["ladder2x4_U10", "chain8_exact", "chain12_m30"])
+def test_local_operators_parity(env, name):
+    """Single-site operators (also transposed), a holon-doublon pair across the halves and a
+    sum of terms, applied through the C ABI into the destination sector's layout, and the
+    expectations of n_p and n_p,up n_p,dn: against the oracle."""
+    from oracle import observables as Ob
+    torch, L = env
+    say("local", name)
+    pb = problem(name)
+    sites = list(range(pb.L)) if pb.Sblk.space.occ is not None else [pb.Sblk.sites[-1], pb.Eblk.sites[0]]
+    kinds = ["cdag_0", "cdag_1", "n", "nn", "holon_1", "doublon_0"]
+    pbx, extra, ops = _local_setup(pb, [(st, k) for st in sites for k in kinds])
+    h = L.dmrg_create(pbx)
+    n = h.n
+    x = I.random_psi(n, np.random.default_rng(I.SEED_BASE + 95))
+    xd = _dev(torch, x)
+    dq_of = {"cdag_0": (1, 0), "cdag_1": (0, 1), "n": (0, 0), "nn": (0, 0), "holon_1": (0, -1),
+             "doublon_0": (1, 0)}
+    handles = {}
+
+    def dst(dq):
+        tgt = (pb.target[0] + dq[0], pb.target[1] + dq[1])
+        if tgt not in handles:
+            pd = I.with_ops(pb, extra["S"], extra["E"], target=tgt)[0]
+            handles[tgt] = (pd, L.dmrg_create(pd))
+        return handles[tgt]
+
+    worst = 0.0
+
+    def check(gterms, oterms, dq):
+        nonlocal worst
+        pd, hd = dst(dq)
+        y = torch.full((2 * hd.n,), float("nan"), dtype=torch.float64, device="cuda")
+        h.apply_local(hd, gterms, xd, y)
+        ref = Ob.apply_terms(pbx, pd, oterms, x)
+        got = _host(y)
+        assert np.all(np.isfinite(got))
+        worst = max(worst, float(np.max(np.abs(got - ref))) / max(1.0, float(np.max(np.abs(ref)))))
+
+    for st in sites:
+        for k in kinds:
+            g, o = _gpu_and_oracle_term(pbx, ops, st, k)
+            check([g], [o], dq_of[k])
+        g, o = _gpu_and_oracle_term(pbx, ops, st, "cdag_0", trans=1)     # c_up as cdag_up^T
+        check([g], [o], (-1, 0))
+    # holon at the last system site, doublon at the first environment site (parity of S)
+    i, j = pb.Sblk.sites[-1], pb.Eblk.sites[0]
+    _, hi, hop = ops[(i, "holon_1")]
+    _, dj, dop = ops[(j, "doublon_0")]
+    check([(0.7, hi, 0, dj, 0, 1)], [(0.7, hop, dop, 1)], (1, -1))
+    # a sum of terms into one sector
+    g1, o1 = _gpu_and_oracle_term(pbx, ops, i, "n", coef=0.5)
+    g2, o2 = _gpu_and_oracle_term(pbx, ops, j, "nn", coef=-2.0)
+    check([g1, g2], [o1, o2], (0, 0))
+    say("  max rel err", worst)
+    assert worst <= 1e-12
+    for st in sites:
+        for k in ("n", "nn"):
+            g, o = _gpu_and_oracle_term(pbx, ops, st, k)
+            e_gpu = h.expect_local([g], xd)
+            e_ref = Ob.expect(pbx, [o], x)
+            assert abs(e_gpu - e_ref) <= 1e-12 * max(1.0, abs(e_ref)), (st, k, e_gpu, e_ref)
+    for (_, hd) in handles.values():
+        hd.destroy()
+    h.destroy()
+
+
+@pytest.mark.parametrize("U", [0.0, 10.0])
+def test_holon_doublon_workflow(env, U):
+    """Fig. 3 and Fig. 5 on the GPU: ground state of the 2x4 ladder (t_x = 1, t_y = 0.5, 4 up +
+    4 down) by restarted Lanczos, the holon-doublon operator (i = 2, j = 4) applied into its
+    three sectors, densities and double occupations at t = 0 against the paper's values, then
+    Krylov evolution to t = 0.5 against the exact evolution of the exact diagonalisation."""
+    import itertools
+    import json
+    import os
+    from scipy.sparse.linalg import expm_multiply
+    from oracle import ed
+    torch, L = env
+    say("holon-doublon workflow U =", U)
+    Lsites, i, j = 8, 2, 4
+    bonds = I.ladder_bonds(4, 1.0, 0.5)
+    pb = I.exact_problem(Lsites, U, (4, 4), bonds=bonds)
+    kinds = [(i, f"holon_{s}") for s in (0, 1)] + [(j, f"doublon_{s}") for s in (0, 1)] + \
+        [(p, k) for p in range(Lsites) for k in ("n", "nn")]
+    pbx, extra, ops = _local_setup(pb, kinds)
+    h0 = L.dmrg_create(pbx)
+    x0 = _dev(torch, I.random_psi(h0.n, np.random.default_rng(I.SEED_BASE + 96), complex_=False))
+    gd = torch.empty_like(x0)
+    e0, used, info = h0.ground_state(x0, gd, 40, 60, 1e-12)
+    assert info["err_est"] <= 1e-10
+    hs, phis = {}, {}
+    for tgt in [(3, 5), (4, 4), (5, 3)]:
+        pd = I.with_ops(pb, extra["S"], extra["E"], target=tgt)[0]
+        hs[tgt] = L.dmrg_create(pd)
+        terms = []
+        for s, s2 in itertools.product((0, 1), (0, 1)):
+            if (4 - (s == 0) + (s2 == 0), 4 - (s == 1) + (s2 == 1)) != tgt:
+                continue
+            _, hi, _ = ops[(i, f"holon_{s}")]
+            _, dj, _ = ops[(j, f"doublon_{s2}")]
+            terms.append((1.0, hi, 0, dj, 0, 1))
+        y = torch.empty(2 * hs[tgt].n, dtype=torch.float64, device="cuda")
+        h0.apply_local(hs[tgt], terms, gd, y)
+        phis[tgt] = y
+
+    def measure(vecs):
+        norm = sum(float(torch.dot(v, v)) for v in vecs.values())
+        dens, docc = np.zeros(Lsites), np.zeros(Lsites)
+        for tgt, v in vecs.items():
+            for p in range(Lsites):
+                for k, arr in (("n", dens), ("nn", docc)):
+                    side, idx, _ = ops[(p, k)]
+                    term = (1.0, idx, 0, -1, 0, 0) if side == "S" else (1.0, -1, 0, idx, 0, 0)
+                    arr[p] += hs[tgt].expect_local([term], v).real
+        return dens / norm, docc / norm
+
+    dens, docc = measure(phis)
+    golden = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_values.json")))
+    g, gdd = golden["holon_doublon_density_t0"], golden["double_occupation_t0"]
+    want = np.full(Lsites, g["other_site_value"])
+    want[i], want[j] = g["holon_site_value"], g["doublon_site_value"]
+    say("  t = 0 density", np.round(dens, 12), "N_d(j), N_d(i)", docc[j], docc[i])
+    assert np.allclose(dens, want, atol=1e-9)
+    assert abs(docc[j] - gdd["doublon_site_value"]) < 1e-9 and abs(docc[i] - gdd["holon_site_value"]) < 1e-9
+    # evolution: 5 Krylov steps of tau = 0.1 per sector, against expm on the ED sectors
+    tau, nsteps = 0.1, 5
+    evolved = {}
+    for tgt, v in phis.items():
+        yv = torch.empty_like(v)
+        hs[tgt].krylov_expm(v, yv, tau, 16, nsteps)
+        evolved[tgt] = yv
+    dens_t, docc_t = measure(evolved)
+    sec0, H0 = ed.hamiltonian(Lsites, bonds, U, 4, 4)
+    _, gs = ed.ground_state(H0)
+    ref_n, ref_d, norm = np.zeros(Lsites), np.zeros(Lsites), 0.0
+    parts = {}
+    for s, s2 in itertools.product((0, 1), (0, 1)):
+        v = gs * ed.number(sec0, j, 1 - s2)
+        d1 = [4, 4]
+        d1[s2] += 1
+        sec1 = ed.Sector(Lsites, *d1)
+        v = ed.create(sec0, sec1, 2 * j + s2) @ v
+        v = v * (1.0 - ed.number(sec1, i, 1 - s))
+        d2 = list(d1)
+        d2[s] -= 1
+        sec2 = ed.Sector(Lsites, *d2)
+        v = ed.annihilate(sec1, sec2, 2 * i + s) @ v
+        parts[tuple(d2)] = (sec2, parts[tuple(d2)][1] + v) if tuple(d2) in parts else (sec2, v)
+    for key, (sec, v) in parts.items():
+        _, Hs = ed.hamiltonian(Lsites, bonds, U, *key)
+        vt = expm_multiply(-1j * tau * nsteps * Hs, v.astype(complex))
+        w = np.abs(vt) ** 2
+        norm += float(np.sum(w))
+        for p in range(Lsites):
+            ref_n[p] += np.sum(w * (ed.number(sec, p, 0) + ed.number(sec, p, 1)))
+            ref_d[p] += np.sum(w * ed.number(sec, p, 0) * ed.number(sec, p, 1))
+    ref_n /= norm
+    ref_d /= norm
+    say("  t = 0.5 density", np.round(dens_t, 6), "max err", np.max(np.abs(dens_t - ref_n)))
+    assert np.max(np.abs(dens_t - ref_n)) < 1e-8
+    assert np.max(np.abs(docc_t - ref_d)) < 1e-8
+    assert np.max(np.abs(dens_t - dens)) > 1e-3          # it does move
+    for hd in hs.values():
+        hd.destroy()
+    h0.destroy()
+
+
 def _batch_setup(torch, L, pbs, seed):
     hs = [L.dmrg_create(pb) for pb in pbs]
     phis = [I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + seed + i)) for i, h in enumerate(hs)]
