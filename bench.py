@@ -269,6 +269,7 @@ def main():
     ap.add_argument("--no-density", action="store_true",
                     help="skip the density-matrix + truncation run (and the transformation)")
     ap.add_argument("--no-wft", action="store_true", help="skip the wave-function transformation")
+    ap.add_argument("--no-local", action="store_true", help="skip the local-operator run")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a buffer of MIB MiB once before the run: a plain copy kernel of "
                          "known traffic that hardware-counter runs use as the byte scale")
@@ -422,6 +423,44 @@ def main():
         wf.destroy()
         print(f"[bench] wave-function transformation: {wft}", file=sys.stderr, flush=True)
 
+    # local operators at the central sites: the doublon factor c+_up n_dn on the first
+    # environment site and the holon factor c_dn (1 - n_up) on the last system site applied to
+    # the step's last target (into the (N_up + 1, N_dn - 1) sector), and the densities of both
+    # central sites measured on the four targets
+    local = None
+    if not args.no_local:
+        s1, s2 = pb.Sblk.sites[-1], pb.Eblk.sites[0]
+        ops_s = I.site_ops(pb.Sblk, s1)
+        ops_e = I.site_ops(pb.Eblk, s2)
+        pbx, iS, iE = I.with_ops(pb, [ops_s["holon_1"], ops_s["n"]], [ops_e["doublon_0"], ops_e["n"]])
+        tgt = (pb.target[0] + 1, pb.target[1] - 1)
+        pdx = I.with_ops(pb, [ops_s["holon_1"], ops_s["n"]], [ops_e["doublon_0"], ops_e["n"]], target=tgt)[0]
+        hx, hd = L.dmrg_create(pbx, stream), L.dmrg_create(pdx, stream)
+        xl = td[6 * n:8 * n].contiguous()
+        yl = torch.empty(2 * hd.n, dtype=torch.float64, device="cuda")
+        hd_terms = [(1.0, iS[0], 0, iE[0], 0, 1)]
+        dens_terms = [(1.0, iS[1], 0, -1, 0, 0), (1.0, -1, 0, iE[1], 0, 0)]
+        hx.apply_local(hd, hd_terms, xl, yl)
+        hx.expect_local(dens_terms, xl)
+        torch.cuda.synchronize()
+        reps = 20
+        e0.record(stream)
+        for _ in range(reps):
+            hx.apply_local(hd, hd_terms, xl, yl)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms_apply = e0.elapsed_time(e1) / reps
+        t0 = time.perf_counter()
+        vals = [hx.expect_local(dens_terms, td[2 * n * k:2 * n * (k + 1)]).real for k in range(4)]
+        ms_expect = (time.perf_counter() - t0) * 1e3 / 4
+        local = {"apply_ms": round(ms_apply, 4), "expect_ms_host_clock": round(ms_expect, 4),
+                 "holon_doublon_norm": round(float(torch.linalg.vector_norm(yl)), 12),
+                 "central_density_per_target": [round(v, 10) for v in vals],
+                 "sites": [int(s1), int(s2)], "target_sector": list(tgt)}
+        hx.destroy()
+        hd.destroy()
+        print(f"[bench] local operators: {local}", file=sys.stderr, flush=True)
+
     # product-only rate and the dominant kernel (HIP events around each launch)
     yd = torch.empty_like(pd)
     prof = h.profile_matvec(pd, yd, reps=20)
@@ -519,6 +558,7 @@ def main():
         "ground_state": gs,
         "density_truncate": dens,
         "wave_function_transformation": wft,
+        "local_operators": local,
         "mixed_precision": mixed,
         "batched_64": batched,
         "drift_m2000": drift,
