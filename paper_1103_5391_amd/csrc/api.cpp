@@ -33,8 +33,8 @@ hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
 hipError_t launch_tridiag(const VecGroup&, const double*, int, hipStream_t);
 hipError_t launch_lowest(const VecGroup&, hipStream_t);
 hipError_t launch_density(const DBlock*, int, const DTile*, int, const double* const*, const double*,
-                          int, int64_t, void*, void*, double*, int, int, int*, double*, double*,
-                          int*, double*, hipStream_t);
+                          int, int64_t, void*, void*, double*, int*, double*, int, int, int*, double*,
+                          double*, int*, double*, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const ZPtrs&, int, int64_t,
                       hipStream_t);
@@ -284,7 +284,7 @@ struct dmrg_ctx {
     Workspace ws[kChains];
     Group self;         // tables of the handle's own Krylov runs
     // density matrix and truncation (built on first use): sectors, tiles, matrices, results
-    DevBuf dDBlk, dDTile, dDA, dDV, dDEv, dDKept, dDNk, dDSums, dDVecs, dDW;
+    DevBuf dDBlk, dDTile, dDA, dDV, dDZ, dDFail, dDEv, dDKept, dDNk, dDSums, dDVecs, dDW;
     int dens_ntiles = 0, dens_ntot = 0;
     int64_t dens_nmat = 0;
     std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
@@ -1195,6 +1195,8 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
         HIP_TRY(h, upload(h->dDTile, tiles, s));
         HIP_TRY(h, h->dDA.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDV.alloc(2 * sizeof(double) * (size_t)aoff));
+        HIP_TRY(h, h->dDZ.alloc(sizeof(double) * (size_t)aoff));
+        HIP_TRY(h, h->dDFail.alloc(sizeof(int) * (size_t)nb));
         HIP_TRY(h, h->dDEv.alloc(sizeof(double) * (size_t)eoff));
         HIP_TRY(h, h->dDKept.alloc(sizeof(int) * (size_t)eoff));
         HIP_TRY(h, h->dDNk.alloc(sizeof(int) * (size_t)nb));
@@ -1205,17 +1207,21 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
     // per-call pointers and weights (synchronous copies; the call waits for its results)
     HIP_TRY(h, hipMemcpyAsync(h->dDVecs.p, vecs, sizeof(void*) * nvec, hipMemcpyHostToDevice, s));
     HIP_TRY(h, hipMemcpyAsync(h->dDW.p, weights, sizeof(double) * nvec, hipMemcpyHostToDevice, s));
+    HIP_TRY(h, hipMemsetAsync(h->dDFail.p, 0, sizeof(int) * (size_t)nb, s));
     HIP_TRY(h, launch_density(h->dDBlk.as<DBlock>(), nb, h->dDTile.as<DTile>(), h->dens_ntiles,
                               h->dDVecs.as<const double*>(), h->dDW.as<double>(), nvec, P.n,
-                              h->dDA.p, h->dDV.p, h->dDEv.as<double>(), h->dens_ntot, keep,
-                              h->dDKept.as<int>(), evals, evecs, h->dDNk.as<int>(),
-                              h->dDSums.as<double>(), s));
-    std::vector<int> nk(nb);
+                              h->dDA.p, h->dDV.p, h->dDZ.as<double>(), h->dDFail.as<int>(),
+                              h->dDEv.as<double>(), h->dens_ntot, keep, h->dDKept.as<int>(), evals,
+                              evecs, h->dDNk.as<int>(), h->dDSums.as<double>(), s));
+    std::vector<int> nk(nb), nofit(nb);
     std::vector<double> sums(2 * (size_t)nb);
     HIP_TRY(h, hipMemcpyAsync(nk.data(), h->dDNk.p, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipMemcpyAsync(sums.data(), h->dDSums.p, sizeof(double) * 2 * nb,
                               hipMemcpyDeviceToHost, s));
+    HIP_TRY(h, hipMemcpyAsync(nofit.data(), h->dDFail.p, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
+    for (int b = 0; b < nb; ++b)
+        if (nofit[b]) return fail(h, DMRG_ENONFINITE, "density matrix: QL iteration did not converge");
     double all = 0.0, kept_sum = 0.0;
     for (int b = 0; b < nb; ++b) {
         kept[b] = nk[b];

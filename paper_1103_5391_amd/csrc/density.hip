@@ -8,22 +8,17 @@
 // with Psi_{l,p} the d_p x e_q block of target l.  Steps:
 //   k_density   rho_p in 16 x 16 tiles (one work group per tile; row panels of the blocks staged
 //               through LDS, K = e_q columns per target, every target in turn)
-//   k_jacobi    eigen-decomposition of every rho_p by cyclic two-sided Jacobi, one work group
-//               per sector: rounds of d/2 disjoint rotations in the round-robin (circle) order,
-//               each rotation the phase that makes rho_pq real times the real rotation that
-//               zeroes it.  A round is one pass: the 2 x 2 block of rho at rows of pair k' and
-//               columns of pair k is multiplied by U_k'^H on the left and U_k on the right, for
-//               k' <= k (the block and its mirror written; rho stays Hermitian), and the columns
-//               of the eigenvector matrix by U_k.  Rotations too small to matter for the
-//               stopping rule are skipped with their blocks; sweeps end when the off-diagonal
-//               norm is below d eps of the whole
+//   k_heig      eigen-decomposition of every rho_p, one work group per sector: Householder
+//               reduction to a real tridiagonal matrix, implicit QL with shifts (one thread
+//               lists the rotations of a sweep, every thread applies them to its rows of Z),
+//               back-transformation by the reflectors (one thread per eigenvector)
 //   k_rank      global rank of every eigenvalue (larger first; equal values by sector, then by
 //               index), kept if the rank is below m
 //   k_finish    per sector: eigenvalues in descending order with their eigenvectors, the number
 //               kept, and the sums of all and of the kept eigenvalues (fixed-order reductions)
 // The matrices live in global memory (L2-resident for the sector sizes of these workloads); the
-// waves of a Jacobi work group hand them to each other through it, each wave waiting for its own
-// stores to complete before the barrier that hands them over.
+// waves of a work group hand them to each other through it, each wave waiting for its own stores
+// to complete before the barrier that hands them over.
 #include <cstdint>
 
 #include "internal.hpp"
@@ -38,10 +33,6 @@ __device__ __forceinline__ dv2 cmul(dv2 a, dv2 b) {
     return (dv2){a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 __device__ __forceinline__ dv2 cconj(dv2 a) { return (dv2){a.x, -a.y}; }
-
-constexpr int kJacThreads = 1024;   // threads of a Jacobi work group
-constexpr int kJacBlkBatch = 2;     // rho blocks whose loads a thread issues together
-constexpr int kJacVecBatch = 2;     // eigenvector items whose loads a thread issues together
 
 // Sum over a work group of NT threads, the same value returned to every thread; fixed order.
 template <int NT>
@@ -63,22 +54,6 @@ __device__ double group_sum(double v, double* scratch) {
 __device__ __forceinline__ void handover_barrier() {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-}
-
-// Right-multiplication of the row pair (x0 x1) by U = [[c, s], [-s e, c e]].
-__device__ __forceinline__ void rot_right(dv2& x0, dv2& x1, double c, double sn, dv2 e) {
-    const dv2 y = cmul(e, x1);
-    const dv2 n0 = c * x0 - sn * y, n1 = sn * x0 + c * y;
-    x0 = n0;
-    x1 = n1;
-}
-
-// Left-multiplication of the column pair (x0; x1) by U^H (U as above).
-__device__ __forceinline__ void rot_left(dv2& x0, dv2& x1, double c, double sn, dv2 e) {
-    const dv2 y = cmul(cconj(e), x1);
-    const dv2 n0 = c * x0 - sn * y, n1 = sn * x0 + c * y;
-    x0 = n0;
-    x1 = n1;
 }
 
 }  // namespace
@@ -127,159 +102,250 @@ __global__ __launch_bounds__(256) void k_density(const DBlock* __restrict__ blks
     if (i < B.d && j < B.d) A[B.aoff + (int64_t)j * B.d + i] = (dv2){sr, si};
 }
 
-// Cyclic Jacobi on rho_p (one work group per sector): eigenvalues to ev[blk.eoff ..] (in the
-// order of the diagonal), eigenvectors as the columns of V (column-major d x d at blk.aoff).
-__global__ __launch_bounds__(kJacThreads) void k_jacobi(const DBlock* __restrict__ blks,
-                                                        dv2* __restrict__ A, dv2* __restrict__ V,
-                                                        double* __restrict__ ev, int max_sweeps) {
+// Sum over the work group (NT threads) of one double, returned to every thread: shuffles
+// inside each wavefront, then the wave sums in a fixed order.  red: NT / 64 doubles.
+template <int NT>
+__device__ __forceinline__ double wg_sum(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    __syncthreads();
+    return s;
+}
+
+constexpr int kEigThreads = 512;    // threads of an eigen-decomposition work group
+constexpr int kQlMaxSweeps = 64;    // QL sweeps per eigenvalue at most
+constexpr int kEigChunk = 16;       // loads a thread issues together in the rotation and
+                                    // reflector passes (their values do not depend on the stores)
+
+// Eigen-decomposition of rho_p, one work group per sector (LAPACK's path for Hermitian
+// matrices, in three phases):
+//   1. Householder reduction to a real tridiagonal matrix: step k takes the reflector
+//      H_k = I - tau_k v_k v_k^H that maps column k below the diagonal to beta_k e_1 (beta_k
+//      real) and updates the trailing matrix B <- H_k^H B H_k as B - v w^H - w v^H with
+//      w = tau B v - (tau / 2)(w0^H v) v, w0 = tau B v.  v_k (v_k[0] = 1) is kept below the
+//      subdiagonal of A and tau_k on its diagonal.
+//   2. Implicit QL with shifts on the tridiagonal matrix (diagonal and subdiagonal in LDS):
+//      one thread runs the scalar recurrence and lists the plane rotations of a sweep; every
+//      thread applies them to its own rows of the real matrix Z (identity at the start).
+//   3. Back-transformation Y = H_0 H_1 ... H_{d-2} Z, one thread per column of Y (row-major),
+//      the reflectors read from A.
+// Eigenvalues (in QL order) go to ev, eigenvectors to the columns of Y.  A sweep count above
+// the limit sets fail[blk].
+__global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__ blks,
+                                                      dv2* __restrict__ A, double* __restrict__ Zb,
+                                                      dv2* __restrict__ Yb, double* __restrict__ ev,
+                                                      int* __restrict__ fail) {
+    constexpr int NT = kEigThreads;
     const DBlock B = blks[blockIdx.x];
     const int d = B.d, tid = threadIdx.x;
     dv2* __restrict__ a = A + B.aoff;
-    dv2* __restrict__ v = V + B.aoff;
-    __shared__ double scratch[kJacThreads];
-    __shared__ int rp[kDensMaxDim / 2], rq[kDensMaxDim / 2];
-    __shared__ double rc[kDensMaxDim / 2], rs[kDensMaxDim / 2];
-    __shared__ dv2 re[kDensMaxDim / 2];
-    __shared__ int done;
-    for (int64_t idx = tid; idx < (int64_t)d * d; idx += kJacThreads) {
-        const int i = (int)(idx % d), j = (int)(idx / d);
-        v[idx] = (dv2){i == j ? 1.0 : 0.0, 0.0};
-    }
-    const int n2 = d + (d & 1), npair = n2 / 2;
-    const int ntri = npair * (npair + 1) / 2;        // blocks (k', k) with k' <= k
-    const int nvit = d * npair;                      // eigenvector items (row, pair)
-    handover_barrier();
-    for (int sweep = 0; sweep < max_sweeps && d > 1; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int64_t idx = tid; idx < (int64_t)d * d; idx += kJacThreads) {
-            const dv2 z = a[idx];
-            const double m2 = z.x * z.x + z.y * z.y;
-            tot += m2;
-            if (idx % d != idx / d) off += m2;
+    double* __restrict__ Z = Zb + B.aoff;
+    dv2* __restrict__ Y = Yb + B.aoff;
+    __shared__ double dg[kDensMaxDim], e[kDensMaxDim];
+    __shared__ dv2 vv[kDensMaxDim], ww[kDensMaxDim];
+    __shared__ dv2 pp[NT];
+    __shared__ double red[2 * NT / 64];
+    __shared__ double s_beta;
+    __shared__ dv2 s_tau, s_scale;
+    __shared__ int s_i0, s_cnt, s_done;
+    // ---------------------------------------------------------------- 1. tridiagonal
+    for (int k = 0; k + 1 < d; ++k) {
+        const int m = d - k - 1;
+        const int64_t ck = (int64_t)k * d;
+        double part = 0.0;
+        for (int i = tid; i < m; i += NT) {
+            const dv2 x = a[ck + k + 1 + i];
+            vv[i] = x;
+            if (i > 0) part += x.x * x.x + x.y * x.y;
         }
-        off = group_sum<kJacThreads>(off, scratch);
-        tot = group_sum<kJacThreads>(tot, scratch);
-        // converged: the off-diagonal norm at the level of the rounding of d terms
-        const double lim = fmax(1e-30, (d * 2.220446049250313e-16) * (d * 2.220446049250313e-16)) * tot;
-        if (tid == 0) done = off <= lim;
+        if (tid == 0) dg[k] = a[ck + k].x;
+        const double xn2 = wg_sum<NT>(part, red);
+        if (tid == 0) {
+            const dv2 al = vv[0];
+            if (xn2 == 0.0 && al.y == 0.0) {
+                s_beta = al.x;
+                s_tau = (dv2){0.0, 0.0};
+                s_scale = (dv2){0.0, 0.0};
+            } else {
+                const double beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
+                s_beta = beta;
+                s_tau = (dv2){(beta - al.x) / beta, -al.y / beta};
+                const dv2 den = (dv2){al.x - beta, al.y};              // 1 / (alpha - beta)
+                const double q = den.x * den.x + den.y * den.y;
+                s_scale = (dv2){den.x / q, -den.y / q};
+            }
+            e[k] = s_beta;
+            a[ck + k] = s_tau;                                          // tau_k on the diagonal
+        }
         __syncthreads();
-        if (done) break;
-        // an element whose square is below this share of the threshold is left for later sweeps
-        // (if all are, the sum of their squares is below the threshold and the next sweep stops)
-        const double skip = lim / ((double)d * d);
-        for (int r = 0; r < n2 - 1; ++r) {
-            // circle order: position 0 fixed, positions 1 .. n2-1 rotate by r; pair k joins the
-            // k-th and the (n2-1-k)-th position
-            for (int k = tid; k < npair; k += kJacThreads) {
-                const int pk = k == 0 ? 0 : 1 + (k - 1 + r) % (n2 - 1);
-                const int k2 = n2 - 1 - k;
-                const int qk = 1 + (k2 - 1 + r) % (n2 - 1);
-                int p = min(pk, qk), q = max(pk, qk);
-                double cs = 1.0, sn = 0.0;
-                dv2 e = (dv2){1.0, 0.0};
-                if (q < d) {
-                    const double app = a[(int64_t)p * d + p].x, aqq = a[(int64_t)q * d + q].x;
-                    const dv2 apq = a[(int64_t)q * d + p];           // row p, column q
-                    const double m2 = apq.x * apq.x + apq.y * apq.y;
-                    if (m2 > skip && m2 > 1e-300) {
-                        const double mag = sqrt(m2);
-                        const double tau = (aqq - app) / (2.0 * mag);
-                        const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                        cs = 1.0 / sqrt(1.0 + t * t);
-                        sn = t * cs;
-                        e = (dv2){apq.x / mag, -apq.y / mag};           // exp(-i phase(apq))
-                    }
-                } else {
-                    q = -1;                                             // paired with the padding
+        const dv2 tau = s_tau, sc = s_scale;
+        for (int i = tid; i < m; i += NT) {
+            const dv2 v = i == 0 ? (dv2){1.0, 0.0} : cmul(vv[i], sc);
+            vv[i] = v;
+            if (i > 0) a[ck + k + 1 + i] = v;                           // v_k below the subdiagonal
+        }
+        __syncthreads();
+        if (tau.x == 0.0 && tau.y == 0.0) continue;                     // H_k = I
+        // w0 = tau B v: rows i, column groups g (G groups of the columns; G = 1 when a thread
+        // takes whole rows)
+        const int G = m >= NT ? 1 : NT / m;
+        for (int it = tid; it < m * G; it += NT) {
+            const int i = it % m, g = it / m;
+            dv2 acc = (dv2){0.0, 0.0};
+            for (int j = g; j < m; j += G) acc += cmul(a[(int64_t)(k + 1 + j) * d + k + 1 + i], vv[j]);
+            if (G > 1) pp[it] = acc;
+            else ww[i] = acc;
+        }
+        __syncthreads();
+        double pr = 0.0, pi = 0.0;
+        for (int i = tid; i < m; i += NT) {
+            dv2 acc = (dv2){0.0, 0.0};
+            if (G > 1)
+                for (int g = 0; g < G; ++g) acc += pp[g * m + i];
+            else
+                acc = ww[i];
+            const dv2 w = cmul(tau, acc);
+            ww[i] = w;
+            const dv2 v = vv[i];                                        // conj(w) v
+            pr += w.x * v.x + w.y * v.y;
+            pi += w.x * v.y - w.y * v.x;
+        }
+        const double dr = wg_sum<NT>(pr, red), di = wg_sum<NT>(pi, red + NT / 64);
+        const dv2 al2 = cmul((dv2){-0.5 * tau.x, -0.5 * tau.y}, (dv2){dr, di});
+        for (int i = tid; i < m; i += NT) ww[i] += cmul(al2, vv[i]);
+        __syncthreads();
+        // B -= v w^H + w v^H
+        for (int64_t it = tid; it < (int64_t)m * m; it += NT) {
+            const int i = (int)(it % m), j = (int)(it / m);
+            const int64_t at = (int64_t)(k + 1 + j) * d + k + 1 + i;
+            a[at] -= cmul(vv[i], cconj(ww[j])) + cmul(ww[i], cconj(vv[j]));
+        }
+        handover_barrier();
+    }
+    if (tid == 0 && d > 0) {
+        dg[d - 1] = a[(int64_t)(d - 1) * d + d - 1].x;
+        e[d - 1] = 0.0;
+    }
+    for (int64_t it = tid; it < (int64_t)d * d; it += NT)
+        Z[it] = (it % d == it / d) ? 1.0 : 0.0;
+    handover_barrier();
+    // ---------------------------------------------------------------- 2. implicit QL
+    double* rc = reinterpret_cast<double*>(vv);         // rotation lists reuse the vectors
+    double* rs = reinterpret_cast<double*>(ww);
+    int l = 0, sweeps = 0;                              // scalar state (thread 0)
+    for (;;) {
+        if (tid == 0) {
+            s_cnt = 0;
+            s_done = 0;
+            for (;;) {
+                if (l >= d) {
+                    s_done = 1;
+                    break;
                 }
-                rp[k] = p;
-                rq[k] = q;
-                rc[k] = cs;
-                rs[k] = sn;
-                re[k] = e;
+                int m = l;
+                while (m < d - 1 && fabs(e[m]) > 2.220446049250313e-16 * (fabs(dg[m]) + fabs(dg[m + 1]))) ++m;
+                if (m == l) {
+                    ++l;
+                    sweeps = 0;
+                    continue;
+                }
+                if (++sweeps > kQlMaxSweeps) {
+                    fail[blockIdx.x] = 1;
+                    s_done = 1;
+                    break;
+                }
+                // shift from the leading 2 x 2 block of the unreduced part, then chase upward
+                double g = (dg[l + 1] - dg[l]) / (2.0 * e[l]);
+                double r = hypot(g, 1.0);
+                g = dg[m] - dg[l] + e[l] / (g + copysign(r, g));
+                double sn = 1.0, cs = 1.0, p = 0.0;
+                int cnt = 0;
+                bool early = false;
+                for (int i = m - 1; i >= l; --i) {
+                    const double f = sn * e[i], b = cs * e[i];
+                    r = hypot(f, g);
+                    e[i + 1] = r;
+                    if (r == 0.0) {
+                        dg[i + 1] -= p;
+                        e[m] = 0.0;
+                        early = true;
+                        break;
+                    }
+                    sn = f / r;
+                    cs = g / r;
+                    g = dg[i + 1] - p;
+                    r = (dg[i] - g) * sn + 2.0 * cs * b;
+                    p = sn * r;
+                    dg[i + 1] = g + p;
+                    g = cs * r - b;
+                    rc[cnt] = cs;
+                    rs[cnt] = sn;
+                    ++cnt;
+                }
+                if (!early) {
+                    dg[l] -= p;
+                    e[l] = g;
+                    e[m] = 0.0;
+                }
+                s_i0 = m - 1;
+                s_cnt = cnt;
+                break;
             }
-            __syncthreads();
-            // rho blocks: rows of pair k' (kp), columns of pair k; t = k (k + 1) / 2 + k'
-            for (int base = tid; base < ntri; base += kJacBlkBatch * kJacThreads) {
-                dv2 x[kJacBlkBatch][4];
-                int ad[kJacBlkBatch][4];                        // offsets in the sector (d <= 1024)
-                int kk[kJacBlkBatch], kq[kJacBlkBatch];
+        }
+        __syncthreads();
+        if (s_done) break;
+        const int i0 = s_i0, cnt = s_cnt;
+        // rotation t mixes columns i0 - t and i0 - t + 1; column i0 - t is read before any
+        // rotation of the sweep writes it, so a chunk of reads goes out at once
+        for (int row = tid; row < d && cnt > 0; row += NT) {
+            double carry = Z[(int64_t)(i0 + 1) * d + row];
+            for (int t0 = 0; t0 < cnt; t0 += kEigChunk) {
+                double zv[kEigChunk];
 #pragma unroll
-                for (int u = 0; u < kJacBlkBatch; ++u) {
-                    const int t = base + u * kJacThreads;
-                    kk[u] = -1;
+                for (int u = 0; u < kEigChunk; ++u)
+                    if (t0 + u < cnt) zv[u] = Z[(int64_t)(i0 - t0 - u) * d + row];
 #pragma unroll
-                    for (int m = 0; m < 4; ++m) ad[u][m] = -1;
-                    if (t >= ntri) continue;
-                    int k = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-                    while (k * (k + 1) / 2 > t) --k;
-                    while ((k + 1) * (k + 2) / 2 <= t) ++k;
-                    const int kp = t - k * (k + 1) / 2;
-                    if (rs[k] == 0.0 && rs[kp] == 0.0) continue;
-                    kk[u] = k;
-                    kq[u] = kp;
-                    const int r0 = rp[kp], r1 = rq[kp], c0 = rp[k], c1 = rq[k];
-                    ad[u][0] = c0 * d + r0;
-                    if (c1 >= 0) ad[u][1] = c1 * d + r0;
-                    if (r1 >= 0) ad[u][2] = c0 * d + r1;
-                    if (c1 >= 0 && r1 >= 0) ad[u][3] = c1 * d + r1;
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) x[u][m] = ad[u][m] >= 0 ? a[ad[u][m]] : (dv2){0.0, 0.0};
-                }
-#pragma unroll
-                for (int u = 0; u < kJacBlkBatch; ++u) {
-                    const int k = kk[u];
-                    if (k < 0) continue;
-                    const int kp = kq[u];
-                    if (rs[k] != 0.0) {                      // columns: block * U_k
-                        rot_right(x[u][0], x[u][1], rc[k], rs[k], re[k]);
-                        rot_right(x[u][2], x[u][3], rc[k], rs[k], re[k]);
-                    }
-                    if (rs[kp] != 0.0) {                     // rows: U_k'^H * block
-                        rot_left(x[u][0], x[u][2], rc[kp], rs[kp], re[kp]);
-                        rot_left(x[u][1], x[u][3], rc[kp], rs[kp], re[kp]);
-                    }
-#pragma unroll
-                    for (int m = 0; m < 4; ++m)
-                        if (ad[u][m] >= 0) a[ad[u][m]] = x[u][m];
-                    if (kp != k) {                           // mirror block: conjugate transpose
-                        const int r0 = rp[kp], r1 = rq[kp], c0 = rp[k], c1 = rq[k];
-                        a[r0 * d + c0] = cconj(x[u][0]);
-                        if (c1 >= 0) a[r0 * d + c1] = cconj(x[u][1]);
-                        if (r1 >= 0) a[r1 * d + c0] = cconj(x[u][2]);
-                        if (c1 >= 0 && r1 >= 0) a[r1 * d + c1] = cconj(x[u][3]);
+                for (int u = 0; u < kEigChunk; ++u) {
+                    const int t = t0 + u;
+                    if (t < cnt) {
+                        Z[(int64_t)(i0 - t + 1) * d + row] = rs[t] * zv[u] + rc[t] * carry;
+                        carry = rc[t] * zv[u] - rs[t] * carry;
                     }
                 }
             }
-            // eigenvectors: V <- V U, columns p, q of every pair; item = k d + i
-            for (int base = tid; base < nvit; base += kJacVecBatch * kJacThreads) {
-                dv2 x0[kJacVecBatch], x1[kJacVecBatch];
-                int ap[kJacVecBatch], aq[kJacVecBatch];
+            Z[(int64_t)(i0 - cnt + 1) * d + row] = carry;
+        }
+        __syncthreads();
+    }
+    handover_barrier();                                 // rows of Z to the column owners
+    for (int i = tid; i < d; i += NT) ev[B.eoff + i] = dg[i];
+    // ---------------------------------------------------------------- 3. back-transformation
+    for (int j = tid; j < d; j += NT) {
+        for (int i = 0; i < d; ++i) Y[(int64_t)i * d + j] = (dv2){Z[(int64_t)j * d + i], 0.0};
+        for (int k = d - 2; k >= 0; --k) {
+            const int64_t ck = (int64_t)k * d;
+            const dv2 tau = a[ck + k];
+            if (tau.x == 0.0 && tau.y == 0.0) continue;
+            dv2 dot = Y[(int64_t)(k + 1) * d + j];                      // v_k[0] = 1
+            for (int i = k + 2; i < d; ++i) dot += cmul(cconj(a[ck + i]), Y[(int64_t)i * d + j]);
+            const dv2 c = cmul(tau, dot);
+            Y[(int64_t)(k + 1) * d + j] -= c;
+            for (int i0 = k + 2; i0 < d; i0 += kEigChunk) {
+                dv2 yv[kEigChunk];
 #pragma unroll
-                for (int u = 0; u < kJacVecBatch; ++u) {
-                    const int t = base + u * kJacThreads;
-                    ap[u] = -1;
-                    if (t >= nvit) continue;
-                    const int i = t % d, k = t / d;
-                    if (rs[k] == 0.0) continue;
-                    ap[u] = rp[k] * d + i;
-                    aq[u] = rq[k] * d + i;
-                    x0[u] = v[ap[u]];
-                    x1[u] = v[aq[u]];
-                }
+                for (int u = 0; u < kEigChunk; ++u)
+                    if (i0 + u < d) yv[u] = Y[(int64_t)(i0 + u) * d + j];
 #pragma unroll
-                for (int u = 0; u < kJacVecBatch; ++u) {
-                    if (ap[u] < 0) continue;
-                    const int k = (base + u * kJacThreads) / d;
-                    rot_right(x0[u], x1[u], rc[k], rs[k], re[k]);
-                    v[ap[u]] = x0[u];
-                    v[aq[u]] = x1[u];
-                }
+                for (int u = 0; u < kEigChunk; ++u)
+                    if (i0 + u < d) Y[(int64_t)(i0 + u) * d + j] = yv[u] - cmul(a[ck + i0 + u], c);
             }
-            handover_barrier();
         }
     }
-    for (int i = tid; i < d; i += kJacThreads) ev[B.eoff + i] = a[(int64_t)i * d + i].x;
 }
 
 // Global rank of eigenvalue g among all ntot: larger first, equal values by sector then index
@@ -318,11 +384,11 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
         int r = 0;
         for (int h = 0; h < d; ++h) r += (e[h] > x) || (e[h] == x && h < i);
         evals[B.eoff + r] = x;
-        const dv2* src = V + B.aoff + (int64_t)i * d;
+        const dv2* src = V + B.aoff + i;                 // column i of a row-major matrix
         double* dre = evecs + 2 * B.aoff + (int64_t)r * d;
         double* dim = dre + (int64_t)d * d;
         for (int row = 0; row < d; ++row) {
-            const dv2 z = src[row];
+            const dv2 z = src[(int64_t)row * d];
             dre[row] = z.x;
             dim[row] = z.y;
         }
@@ -344,12 +410,13 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
 
 hipError_t launch_density(const DBlock* blks, int nblk, const DTile* tiles, int ntiles,
                           const double* const* vecs, const double* weights, int nv, int64_t n,
-                          void* A, void* V, double* ev, int ntot, int keep, int* kept,
-                          double* evals, double* evecs, int* nkept, double* sums, hipStream_t s) {
+                          void* A, void* V, double* Z, int* fail, double* ev, int ntot, int keep,
+                          int* kept, double* evals, double* evecs, int* nkept, double* sums,
+                          hipStream_t s) {
     hipLaunchKernelGGL(k_density, dim3(ntiles), dim3(256), 0, s, blks, tiles, vecs, weights, nv, n,
                        static_cast<dv2*>(A));
-    hipLaunchKernelGGL(k_jacobi, dim3(nblk), dim3(kJacThreads), 0, s, blks, static_cast<dv2*>(A),
-                       static_cast<dv2*>(V), ev, kDensSweeps);
+    hipLaunchKernelGGL(k_heig, dim3(nblk), dim3(kEigThreads), 0, s, blks, static_cast<dv2*>(A), Z,
+                       static_cast<dv2*>(V), ev, fail);
     hipLaunchKernelGGL(k_rank, dim3((ntot + 255) / 256), dim3(256), 0, s, ev, ntot, keep, kept);
     hipLaunchKernelGGL(k_finish, dim3(nblk), dim3(256), 0, s, blks, ev, kept,
                        static_cast<const dv2*>(V), evals, evecs, nkept, sums);

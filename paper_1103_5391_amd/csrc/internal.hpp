@@ -155,9 +155,8 @@ struct DBlock {
 struct DTile {            // 16 x 16 tile of one sector's density matrix
     int32_t blk, i0, j0, pad;
 };
-constexpr int kDensMaxDim = 1024;   // largest system sector the Jacobi kernel accepts
+constexpr int kDensMaxDim = 1024;   // largest system sector the eigen-decomposition accepts
 constexpr int kDensMaxVec = 16;     // most target vectors of one density matrix
-constexpr int kDensSweeps = 40;     // Jacobi sweeps at most (convergence ends it earlier)
 
 // One 32 x 32 tile of a complex product C = alpha A B (+ C if acc) (FP64; complex operands
 // have real parts at off and imaginary parts at off + im).  A modes: 0 complex column-major,
