@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     __shared__ double red[2 * NT / 64];
     __shared__ double s_beta;
     __shared__ dv2 s_tau, s_scale;
-    __shared__ int s_i0, s_cnt, s_done;
+    __shared__ int s_i0[2], s_cnt[2], s_done[2];
     // ---------------------------------------------------------------- 1. tridiagonal
     for (int k = 0; k + 1 < d; ++k) {
         const int m = d - k - 1;
@@ -235,114 +235,149 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
         Z[it] = (it % d == it / d) ? 1.0 : 0.0;
     handover_barrier();
     // ---------------------------------------------------------------- 2. implicit QL
-    double* rc = reinterpret_cast<double*>(vv);         // rotation lists reuse the vectors
-    double* rs = reinterpret_cast<double*>(ww);
+    // Wavefront 0 (its first lane) runs the sweep recurrence and lists the rotations of the next
+    // sweep while the other wavefronts apply the current one (two rotation lists in LDS).
+    auto rcl = [&](int buf) { return buf ? reinterpret_cast<double*>(ww) : reinterpret_cast<double*>(vv); };
+    auto rsl = [&](int buf) { return rcl(buf) + kDensMaxDim; };
     int l = 0, sweeps = 0;                              // scalar state (thread 0)
-    for (;;) {
-        if (tid == 0) {
-            s_cnt = 0;
-            s_done = 0;
-            for (;;) {
-                if (l >= d) {
-                    s_done = 1;
-                    break;
-                }
-                int m = l;
-                while (m < d - 1 && fabs(e[m]) > 2.220446049250313e-16 * (fabs(dg[m]) + fabs(dg[m + 1]))) ++m;
-                if (m == l) {
-                    ++l;
-                    sweeps = 0;
-                    continue;
-                }
-                if (++sweeps > kQlMaxSweeps) {
-                    fail[blockIdx.x] = 1;
-                    s_done = 1;
-                    break;
-                }
-                // shift from the leading 2 x 2 block of the unreduced part, then chase upward
-                double g = (dg[l + 1] - dg[l]) / (2.0 * e[l]);
-                double r = hypot(g, 1.0);
-                g = dg[m] - dg[l] + e[l] / (g + copysign(r, g));
-                double sn = 1.0, cs = 1.0, p = 0.0;
-                int cnt = 0;
-                bool early = false;
-                for (int i = m - 1; i >= l; --i) {
-                    const double f = sn * e[i], b = cs * e[i];
-                    r = hypot(f, g);
-                    e[i + 1] = r;
-                    if (r == 0.0) {
-                        dg[i + 1] -= p;
-                        e[m] = 0.0;
-                        early = true;
-                        break;
-                    }
-                    sn = f / r;
-                    cs = g / r;
-                    g = dg[i + 1] - p;
-                    r = (dg[i] - g) * sn + 2.0 * cs * b;
-                    p = sn * r;
-                    dg[i + 1] = g + p;
-                    g = cs * r - b;
-                    rc[cnt] = cs;
-                    rs[cnt] = sn;
-                    ++cnt;
-                }
-                if (!early) {
-                    dg[l] -= p;
-                    e[l] = g;
+    auto next_sweep = [&](int buf) {                    // thread 0: the next sweep into list buf
+        double* rc = rcl(buf);
+        double* rs = rsl(buf);
+        s_cnt[buf] = 0;
+        s_done[buf] = 0;
+        for (;;) {
+            if (l >= d) {
+                s_done[buf] = 1;
+                return;
+            }
+            int m = l;
+            while (m < d - 1 && fabs(e[m]) > 2.220446049250313e-16 * (fabs(dg[m]) + fabs(dg[m + 1]))) ++m;
+            if (m == l) {
+                ++l;
+                sweeps = 0;
+                continue;
+            }
+            if (++sweeps > kQlMaxSweeps) {
+                fail[blockIdx.x] = 1;
+                s_done[buf] = 1;
+                return;
+            }
+            // shift from the leading 2 x 2 block of the unreduced part, then chase upward
+            double g = (dg[l + 1] - dg[l]) / (2.0 * e[l]);
+            double r = hypot(g, 1.0);
+            g = dg[m] - dg[l] + e[l] / (g + copysign(r, g));
+            double sn = 1.0, cs = 1.0, p = 0.0;
+            int cnt = 0;
+            bool early = false;
+            for (int i = m - 1; i >= l; --i) {
+                const double f = sn * e[i], b = cs * e[i];
+                r = hypot(f, g);
+                e[i + 1] = r;
+                if (r == 0.0) {
+                    dg[i + 1] -= p;
                     e[m] = 0.0;
+                    early = true;
+                    break;
                 }
-                s_i0 = m - 1;
-                s_cnt = cnt;
-                break;
+                sn = f / r;
+                cs = g / r;
+                g = dg[i + 1] - p;
+                r = (dg[i] - g) * sn + 2.0 * cs * b;
+                p = sn * r;
+                dg[i + 1] = g + p;
+                g = cs * r - b;
+                rc[cnt] = cs;
+                rs[cnt] = sn;
+                ++cnt;
             }
+            if (!early) {
+                dg[l] -= p;
+                e[l] = g;
+                e[m] = 0.0;
+            }
+            s_i0[buf] = m - 1;
+            s_cnt[buf] = cnt;
+            return;
         }
-        __syncthreads();
-        if (s_done) break;
-        const int i0 = s_i0, cnt = s_cnt;
-        // rotation t mixes columns i0 - t and i0 - t + 1; column i0 - t is read before any
-        // rotation of the sweep writes it, so a chunk of reads goes out at once
-        for (int row = tid; row < d && cnt > 0; row += NT) {
-            double carry = Z[(int64_t)(i0 + 1) * d + row];
-            for (int t0 = 0; t0 < cnt; t0 += kEigChunk) {
-                double zv[kEigChunk];
+    };
+    if (tid == 0) next_sweep(0);
+    __syncthreads();
+    for (int it = 0;; ++it) {
+        const int cur = it & 1;
+        if (s_done[cur]) break;
+        if (tid == 0) {
+            next_sweep(cur ^ 1);
+        } else if (tid >= 64) {
+            const int i0 = s_i0[cur], cnt = s_cnt[cur];
+            const double* rc = rcl(cur);
+            const double* rs = rsl(cur);
+            // rotation t mixes columns i0 - t and i0 - t + 1; column i0 - t is read before any
+            // rotation of the sweep writes it, so a chunk of reads goes out at once
+            for (int row = tid - 64; row < d && cnt > 0; row += NT - 64) {
+                double carry = Z[(int64_t)(i0 + 1) * d + row];
+                for (int t0 = 0; t0 < cnt; t0 += kEigChunk) {
+                    double zv[kEigChunk];
 #pragma unroll
-                for (int u = 0; u < kEigChunk; ++u)
-                    if (t0 + u < cnt) zv[u] = Z[(int64_t)(i0 - t0 - u) * d + row];
+                    for (int u = 0; u < kEigChunk; ++u)
+                        if (t0 + u < cnt) zv[u] = Z[(int64_t)(i0 - t0 - u) * d + row];
 #pragma unroll
-                for (int u = 0; u < kEigChunk; ++u) {
-                    const int t = t0 + u;
-                    if (t < cnt) {
-                        Z[(int64_t)(i0 - t + 1) * d + row] = rs[t] * zv[u] + rc[t] * carry;
-                        carry = rc[t] * zv[u] - rs[t] * carry;
+                    for (int u = 0; u < kEigChunk; ++u) {
+                        const int t = t0 + u;
+                        if (t < cnt) {
+                            Z[(int64_t)(i0 - t + 1) * d + row] = rs[t] * zv[u] + rc[t] * carry;
+                            carry = rc[t] * zv[u] - rs[t] * carry;
+                        }
                     }
                 }
+                Z[(int64_t)(i0 - cnt + 1) * d + row] = carry;
             }
-            Z[(int64_t)(i0 - cnt + 1) * d + row] = carry;
         }
         __syncthreads();
     }
     handover_barrier();                                 // rows of Z to the column owners
     for (int i = tid; i < d; i += NT) ev[B.eoff + i] = dg[i];
     // ---------------------------------------------------------------- 3. back-transformation
-    for (int j = tid; j < d; j += NT) {
-        for (int i = 0; i < d; ++i) Y[(int64_t)i * d + j] = (dv2){Z[(int64_t)j * d + i], 0.0};
+    // G lanes per column of Y (a power of two, inside one wavefront): lane q of a group takes
+    // the rows i = q mod G; the group adds its partial inner products by shuffles
+    int G = 1;
+    while (G < 8 && 2 * G * d <= NT) G *= 2;
+    const int q = tid % G;
+    for (int j0 = tid / G; j0 < (d + NT / G - 1) / (NT / G) * (NT / G); j0 += NT / G) {
+        const int j = j0 < d ? j0 : d - 1;              // idle groups repeat the last column's
+        const bool own = j0 < d;                        // arithmetic without storing
+        for (int i = q; i < d; i += G)
+            if (own) Y[(int64_t)i * d + j] = (dv2){Z[(int64_t)j * d + i], 0.0};
         for (int k = d - 2; k >= 0; --k) {
             const int64_t ck = (int64_t)k * d;
             const dv2 tau = a[ck + k];
             if (tau.x == 0.0 && tau.y == 0.0) continue;
-            dv2 dot = Y[(int64_t)(k + 1) * d + j];                      // v_k[0] = 1
-            for (int i = k + 2; i < d; ++i) dot += cmul(cconj(a[ck + i]), Y[(int64_t)i * d + j]);
+            // rows k+1 .. d-1 of this lane: first row of the lane's share
+            int i1 = k + 1 + ((q - (k + 1) % G) % G + G) % G;
+            dv2 dot = (dv2){0.0, 0.0};
+            for (int i = i1; i < d; i += G) {
+                const dv2 v = i == k + 1 ? (dv2){1.0, 0.0} : a[ck + i];          // v_k[0] = 1
+                dot += cmul(cconj(v), Y[(int64_t)i * d + j]);
+            }
+            for (int o = 1; o < G; o <<= 1) {
+                dot.x += __shfl_xor(dot.x, o, 64);
+                dot.y += __shfl_xor(dot.y, o, 64);
+            }
             const dv2 c = cmul(tau, dot);
-            Y[(int64_t)(k + 1) * d + j] -= c;
-            for (int i0 = k + 2; i0 < d; i0 += kEigChunk) {
+            for (int i00 = i1; i00 < d; i00 += G * kEigChunk) {
                 dv2 yv[kEigChunk];
 #pragma unroll
-                for (int u = 0; u < kEigChunk; ++u)
-                    if (i0 + u < d) yv[u] = Y[(int64_t)(i0 + u) * d + j];
+                for (int u = 0; u < kEigChunk; ++u) {
+                    const int i = i00 + u * G;
+                    if (i < d) yv[u] = Y[(int64_t)i * d + j];
+                }
 #pragma unroll
-                for (int u = 0; u < kEigChunk; ++u)
-                    if (i0 + u < d) Y[(int64_t)(i0 + u) * d + j] = yv[u] - cmul(a[ck + i0 + u], c);
+                for (int u = 0; u < kEigChunk; ++u) {
+                    const int i = i00 + u * G;
+                    if (i < d && own) {
+                        const dv2 v = i == k + 1 ? (dv2){1.0, 0.0} : a[ck + i];
+                        Y[(int64_t)i * d + j] = yv[u] - cmul(v, c);
+                    }
+                }
             }
         }
     }
