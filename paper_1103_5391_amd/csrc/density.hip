@@ -269,26 +269,32 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
             double sn = 1.0, cs = 1.0, p = 0.0;
             int cnt = 0;
             bool early = false;
+            double ei = e[m - 1], di = dg[m - 1], di1 = dg[m];      // values of the next rotation
             for (int i = m - 1; i >= l; --i) {
-                const double f = sn * e[i], b = cs * e[i];
-                r = hypot(f, g);
+                const double en = i > l ? e[i - 1] : 0.0, dn = i > l ? dg[i - 1] : 0.0;
+                const double f = sn * ei, b = cs * ei;
+                r = sqrt(f * f + g * g);
                 e[i + 1] = r;
                 if (r == 0.0) {
-                    dg[i + 1] -= p;
+                    dg[i + 1] = di1 - p;
                     e[m] = 0.0;
                     early = true;
                     break;
                 }
-                sn = f / r;
-                cs = g / r;
-                g = dg[i + 1] - p;
-                r = (dg[i] - g) * sn + 2.0 * cs * b;
+                const double rinv = 1.0 / r;
+                sn = f * rinv;
+                cs = g * rinv;
+                g = di1 - p;
+                r = (di - g) * sn + 2.0 * cs * b;
                 p = sn * r;
                 dg[i + 1] = g + p;
                 g = cs * r - b;
                 rc[cnt] = cs;
                 rs[cnt] = sn;
                 ++cnt;
+                di1 = di;
+                ei = en;
+                di = dn;
             }
             if (!early) {
                 dg[l] -= p;
