@@ -33,8 +33,8 @@ hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
 hipError_t launch_tridiag(const VecGroup&, const double*, int, hipStream_t);
 hipError_t launch_lowest(const VecGroup&, hipStream_t);
 hipError_t launch_density(const DBlock*, int, const DTile*, int, const double* const*, const double*,
-                          int, int64_t, void*, void*, double*, int*, double*, int, int, int*, double*,
-                          double*, int*, double*, hipStream_t);
+                          int, int64_t, void*, void*, double*, double*, int*, double*, int, int, int*,
+                          double*, double*, int*, double*, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const ZPtrs&, int, int64_t,
                       hipStream_t);
@@ -284,7 +284,7 @@ struct dmrg_ctx {
     Workspace ws[kChains];
     Group self;         // tables of the handle's own Krylov runs
     // density matrix and truncation (built on first use): sectors, tiles, matrices, results
-    DevBuf dDBlk, dDTile, dDA, dDV, dDZ, dDFail, dDEv, dDKept, dDNk, dDSums, dDVecs, dDW;
+    DevBuf dDBlk, dDTile, dDA, dDV, dDZ, dDS, dDFail, dDEv, dDKept, dDNk, dDSums, dDVecs, dDW;
     int dens_ntiles = 0, dens_ntot = 0;
     int64_t dens_nmat = 0;
     std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
@@ -1196,6 +1196,7 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
         HIP_TRY(h, h->dDA.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDV.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDZ.alloc(sizeof(double) * (size_t)aoff));
+        HIP_TRY(h, h->dDS.alloc(5 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDFail.alloc(sizeof(int) * (size_t)nb));
         HIP_TRY(h, h->dDEv.alloc(sizeof(double) * (size_t)eoff));
         HIP_TRY(h, h->dDKept.alloc(sizeof(int) * (size_t)eoff));
@@ -1210,7 +1211,8 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
     HIP_TRY(h, hipMemsetAsync(h->dDFail.p, 0, sizeof(int) * (size_t)nb, s));
     HIP_TRY(h, launch_density(h->dDBlk.as<DBlock>(), nb, h->dDTile.as<DTile>(), h->dens_ntiles,
                               h->dDVecs.as<const double*>(), h->dDW.as<double>(), nvec, P.n,
-                              h->dDA.p, h->dDV.p, h->dDZ.as<double>(), h->dDFail.as<int>(),
+                              h->dDA.p, h->dDV.p, h->dDZ.as<double>(), h->dDS.as<double>(),
+                              h->dDFail.as<int>(),
                               h->dDEv.as<double>(), h->dens_ntot, keep, h->dDKept.as<int>(), evals,
                               evecs, h->dDNk.as<int>(), h->dDSums.as<double>(), s));
     std::vector<int> nk(nb), nofit(nb);

@@ -119,6 +119,8 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
 
 constexpr int kEigThreads = 512;    // threads of an eigen-decomposition work group
 constexpr int kQlMaxSweeps = 64;    // QL sweeps per eigenvalue at most
+constexpr int kClusterMax = 8;      // inverse iteration when no cluster of eigenvalues is larger
+constexpr double kClusterGap = 1e-3;  // eigenvalues closer than this times |T| form a cluster
 constexpr int kEigChunk = 16;       // loads a thread issues together in the rotation and
                                     // reflector passes (their values do not depend on the stores)
 
@@ -138,8 +140,8 @@ constexpr int kEigChunk = 16;       // loads a thread issues together in the rot
 // the limit sets fail[blk].
 __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__ blks,
                                                       dv2* __restrict__ A, double* __restrict__ Zb,
-                                                      dv2* __restrict__ Yb, double* __restrict__ ev,
-                                                      int* __restrict__ fail) {
+                                                      double* __restrict__ Sb, dv2* __restrict__ Yb,
+                                                      double* __restrict__ ev, int* __restrict__ fail) {
     constexpr int NT = kEigThreads;
     const DBlock B = blks[blockIdx.x];
     const int d = B.d, tid = threadIdx.x;
@@ -152,7 +154,8 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     __shared__ double red[2 * NT / 64];
     __shared__ double s_beta;
     __shared__ dv2 s_tau, s_scale;
-    __shared__ int s_i0[2], s_cnt[2], s_done[2];
+    __shared__ int s_i0[2], s_cnt[2], s_done[2], s_path;
+    __shared__ double s_lo, s_hi, s_tn;
     // ---------------------------------------------------------------- 1. tridiagonal
     for (int k = 0; k + 1 < d; ++k) {
         const int m = d - k - 1;
@@ -231,10 +234,156 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
         dg[d - 1] = a[(int64_t)(d - 1) * d + d - 1].x;
         e[d - 1] = 0.0;
     }
+    __syncthreads();
+    // ---------------------------------------------------------------- 2. eigenvalues
+    // Bisection on Sturm counts (the signs of the pivots of T - x I = L D L^T), one thread per
+    // eigenvalue, from the Gershgorin interval to rounding level.
+    double* e2 = reinterpret_cast<double*>(pp);         // squared subdiagonal (pp is free now)
+    double* lam = reinterpret_cast<double*>(ww);        // eigenvalues, ascending
+    for (int i = tid; i + 1 < d; i += NT) e2[i] = e[i] * e[i];
+    if (tid == 0) {
+        double lo = dg[0], hi = dg[0], tn = 0.0;
+        for (int i = 0; i < d; ++i) {
+            const double r = (i > 0 ? fabs(e[i - 1]) : 0.0) + (i + 1 < d ? fabs(e[i]) : 0.0);
+            lo = fmin(lo, dg[i] - r);
+            hi = fmax(hi, dg[i] + r);
+        }
+        tn = fmax(fabs(lo), fabs(hi));
+        s_lo = lo - 2.220446049250313e-16 * tn - 1e-300;
+        s_hi = hi + 2.220446049250313e-16 * tn + 1e-300;
+        s_tn = fmax(tn, 1e-300);
+    }
+    __syncthreads();
+    for (int j = tid; j < d; j += NT) {
+        double lo = s_lo, hi = s_hi;
+        for (int it = 0; it < 256; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            if (hi - lo <= 4.440892098500626e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300 || mid <= lo || mid >= hi) break;
+            double q = dg[0] - mid;
+            int cnt = q < 0.0;
+            for (int i = 1; i < d; ++i) {
+                if (fabs(q) < 1e-300) q = -1e-300;
+                q = (dg[i] - mid) - e2[i - 1] / q;
+                cnt += q < 0.0;
+            }
+            if (cnt > j) hi = mid;
+            else lo = mid;
+        }
+        lam[j] = 0.5 * (lo + hi);
+    }
+    __syncthreads();
+    if (tid == 0) {                                     // largest cluster decides the path
+        int run = 1, big = 1;
+        for (int j = 1; j < d; ++j) {
+            run = lam[j] - lam[j - 1] <= kClusterGap * s_tn ? run + 1 : 1;
+            big = max(big, run);
+        }
+        s_path = big <= kClusterMax ? 0 : 1;
+    }
+    __syncthreads();
+    int zr = d, zc = 1;                                 // Z(i, j) at i zr + j zc
+    if (s_path == 0) {
+        // ------------------------------------------------------------ 3a. inverse iteration
+        // The thread of the first eigenvalue of each cluster takes the cluster's eigenvectors in
+        // order: T - lam I = P L U (partial pivoting), three solves from a fixed start, each
+        // orthogonalised against the cluster's earlier vectors.  Z and the factors are
+        // row-major [i][j] (consecutive threads, consecutive addresses).
+        double* u0 = Sb + 5 * B.aoff;                   // 1 / pivot
+        double* u1 = u0 + (int64_t)d * d;
+        double* u2 = u1 + (int64_t)d * d;
+        double* lm = u2 + (int64_t)d * d;
+        double* pv = lm + (int64_t)d * d;               // 1 where rows i, i+1 were swapped
+        const double tiny = 2.220446049250313e-16 * s_tn;
+        for (int j0 = tid; j0 < d; j0 += NT) {
+            if (j0 > 0 && lam[j0] - lam[j0 - 1] <= kClusterGap * s_tn) continue;   // not first
+            for (int j = j0; j < d && (j == j0 || lam[j] - lam[j - 1] <= kClusterGap * s_tn); ++j) {
+                const double x = lam[j];
+                // factorisation, row by row: (dd, du) = current row's diagonal and superdiagonal
+                double dd = dg[0] - x, du = d > 1 ? e[0] : 0.0;
+                for (int i = 0; i + 1 < d; ++i) {
+                    const int64_t at = (int64_t)i * d + j;
+                    const double sub = e[i], nd = dg[i + 1] - x, nu = i + 2 < d ? e[i + 1] : 0.0;
+                    if (fabs(dd) >= fabs(sub)) {
+                        const double piv = fabs(dd) >= tiny ? dd : (dd < 0.0 ? -tiny : tiny);
+                        const double m = sub / piv;
+                        u0[at] = 1.0 / piv;
+                        u1[at] = du;
+                        u2[at] = 0.0;
+                        lm[at] = m;
+                        pv[at] = 0.0;
+                        dd = nd - m * du;
+                        du = nu;
+                    } else {
+                        const double m = dd / sub;
+                        u0[at] = 1.0 / sub;
+                        u1[at] = nd;
+                        u2[at] = nu;
+                        lm[at] = m;
+                        pv[at] = 1.0;
+                        dd = du - m * nd;
+                        du = -m * nu;
+                    }
+                }
+                {
+                    const int64_t at = (int64_t)(d - 1) * d + j;
+                    const double piv = fabs(dd) >= tiny ? dd : (dd < 0.0 ? -tiny : tiny);
+                    u0[at] = 1.0 / piv;
+                    u1[at] = 0.0;
+                    u2[at] = 0.0;
+                }
+                // start vector
+                for (int i = 0; i < d; ++i) Z[(int64_t)i * d + j] = cos(0.7 * i + j);
+                double scale = 1.0;
+                for (int rep = 0; rep < 3; ++rep) {
+                    // forward: P and L^-1 (the current entry carried in a register)
+                    double cur = scale * Z[j];
+                    for (int i = 0; i + 1 < d; ++i) {
+                        const int64_t at = (int64_t)i * d + j;
+                        double nxt = scale * Z[at + d];
+                        if (pv[at] != 0.0) {
+                            const double t = cur;
+                            cur = nxt;
+                            nxt = t;
+                        }
+                        Z[at] = cur;
+                        cur = nxt - lm[at] * cur;
+                    }
+                    Z[(int64_t)(d - 1) * d + j] = cur;
+                    // backward: U^-1
+                    double y1 = 0.0, y2 = 0.0, nrm = 0.0;
+                    for (int i = d - 1; i >= 0; --i) {
+                        const int64_t at = (int64_t)i * d + j;
+                        const double y = (Z[at] - u1[at] * y1 - u2[at] * y2) * u0[at];
+                        Z[at] = y;
+                        nrm += y * y;
+                        y2 = y1;
+                        y1 = y;
+                    }
+                    // against the cluster's earlier eigenvectors (modified Gram-Schmidt)
+                    for (int k = j0; k < j; ++k) {
+                        double dot = 0.0;
+                        for (int i = 0; i < d; ++i) dot += Z[(int64_t)i * d + k] * Z[(int64_t)i * d + j];
+                        nrm = 0.0;
+                        for (int i = 0; i < d; ++i) {
+                            const double y = Z[(int64_t)i * d + j] - dot * Z[(int64_t)i * d + k];
+                            Z[(int64_t)i * d + j] = y;
+                            nrm += y * y;
+                        }
+                    }
+                    scale = 1.0 / sqrt(fmax(nrm, 1e-300));
+                }
+                for (int i = 0; i < d; ++i) Z[(int64_t)i * d + j] *= scale;
+                ev[B.eoff + j] = x;
+            }
+        }
+        handover_barrier();
+    } else {
+    zr = 1;
+    zc = d;
     for (int64_t it = tid; it < (int64_t)d * d; it += NT)
         Z[it] = (it % d == it / d) ? 1.0 : 0.0;
     handover_barrier();
-    // ---------------------------------------------------------------- 2. implicit QL
+    // ---------------------------------------------------------------- 3b. implicit QL
     // Wavefront 0 (its first lane) runs the sweep recurrence and lists the rotations of the next
     // sweep while the other wavefronts apply the current one (two rotation lists in LDS).
     auto rcl = [&](int buf) { return buf ? reinterpret_cast<double*>(ww) : reinterpret_cast<double*>(vv); };
@@ -342,7 +491,8 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     }
     handover_barrier();                                 // rows of Z to the column owners
     for (int i = tid; i < d; i += NT) ev[B.eoff + i] = dg[i];
-    // ---------------------------------------------------------------- 3. back-transformation
+    }
+    // ---------------------------------------------------------------- 4. back-transformation
     // G lanes per column of Y (a power of two, inside one wavefront): lane q of a group takes
     // the rows i = q mod G; the group adds its partial inner products by shuffles
     int G = 1;
@@ -352,7 +502,7 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
         const int j = j0 < d ? j0 : d - 1;              // idle groups repeat the last column's
         const bool own = j0 < d;                        // arithmetic without storing
         for (int i = q; i < d; i += G)
-            if (own) Y[(int64_t)i * d + j] = (dv2){Z[(int64_t)j * d + i], 0.0};
+            if (own) Y[(int64_t)i * d + j] = (dv2){Z[(int64_t)i * zr + (int64_t)j * zc], 0.0};
         for (int k = d - 2; k >= 0; --k) {
             const int64_t ck = (int64_t)k * d;
             const dv2 tau = a[ck + k];
@@ -451,12 +601,12 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
 
 hipError_t launch_density(const DBlock* blks, int nblk, const DTile* tiles, int ntiles,
                           const double* const* vecs, const double* weights, int nv, int64_t n,
-                          void* A, void* V, double* Z, int* fail, double* ev, int ntot, int keep,
-                          int* kept, double* evals, double* evecs, int* nkept, double* sums,
-                          hipStream_t s) {
+                          void* A, void* V, double* Z, double* S, int* fail, double* ev, int ntot,
+                          int keep, int* kept, double* evals, double* evecs, int* nkept,
+                          double* sums, hipStream_t s) {
     hipLaunchKernelGGL(k_density, dim3(ntiles), dim3(256), 0, s, blks, tiles, vecs, weights, nv, n,
                        static_cast<dv2*>(A));
-    hipLaunchKernelGGL(k_heig, dim3(nblk), dim3(kEigThreads), 0, s, blks, static_cast<dv2*>(A), Z,
+    hipLaunchKernelGGL(k_heig, dim3(nblk), dim3(kEigThreads), 0, s, blks, static_cast<dv2*>(A), Z, S,
                        static_cast<dv2*>(V), ev, fail);
     hipLaunchKernelGGL(k_rank, dim3((ntot + 255) / 256), dim3(256), 0, s, ev, ntot, keep, kept);
     hipLaunchKernelGGL(k_finish, dim3(nblk), dim3(256), 0, s, blks, ev, kept,

@@ -475,27 +475,41 @@ def test_ground_state_converges_to_exact(env):
     h.destroy()
 
 
-@pytest.mark.parametrize("name", ["chain12_m30", "chain8_exact", "chain8_m17_odd", "ladder16_m1000"])
-def test_density_truncate_parity(env, name):
+def _decaying(pb, x, decades):
+    """x with the rows of every block scaled by 10^(-decades i / d): a density matrix whose
+    spectrum decays over `decades` decades (clusters of small eigenvalues)."""
+    blocks = M.unpack(pb, x)
+    out = {p: b * np.logspace(0, -decades, b.shape[0])[:, None] for p, b in blocks.items()}
+    y = M.pack(pb, out)
+    return y / np.linalg.norm(y)
+
+
+@pytest.mark.parametrize("name,decades", [("chain12_m30", 0), ("chain8_exact", 0), ("chain8_m17_odd", 0),
+                                          ("ladder16_m1000", 0), ("chain12_m30", 12),
+                                          ("ladder16_m1000", 14)])
+def test_density_truncate_parity(env, name, decades):
     """Density matrix of five weighted targets and its truncation against the oracle: every
     eigenvalue, the kept count of every sector and the truncation error; eigen-pairs (residual
     against the oracle's rho, orthonormality); the kept subspace of every sector (its
-    projector), which is unique where the kept and discarded eigenvalues are apart."""
+    projector), which is unique where the kept and discarded eigenvalues are apart.  Decaying
+    spectra (clusters of small eigenvalues) take the kernel's other tridiagonal solver."""
     from oracle import density as Dn
     torch, L = env
-    say("density", name)
+    say("density", name, "decades", decades)
     pb = problem(name)
     h = L.dmrg_create(pb)
     n = h.n
     rng = np.random.default_rng(I.SEED_BASE + 80)
     vecs = [I.random_psi(n, rng) for _ in range(5)]
+    if decades:
+        vecs = [_decaying(pb, v, decades) for v in vecs]
     w = K.tst_weights()
     rows = [int(r) for r in h.psi_layout()["rows"]]
     total = sum(rows)
     # a cut with a clear gap, near a quarter of the states
     ref_all = Dn.truncate(pb, vecs, w, keep=total)
     allv = np.sort(np.concatenate([ref_all.evals[p] for p in ref_all.sectors]))[::-1]
-    lo, hi = max(1, total // 8), max(2, total // 3)
+    lo, hi = (1 if decades else max(1, total // 8)), max(2, total // 3)
     gaps = (allv[lo - 1:hi - 1] - allv[lo:hi]) / allv[0]
     keep = lo + int(np.argmax(gaps))
     assert gaps.max() > 1e-6
