@@ -33,8 +33,8 @@ hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
 hipError_t launch_tridiag(const VecGroup&, const double*, int, hipStream_t);
 hipError_t launch_lowest(const VecGroup&, hipStream_t);
 hipError_t launch_density(const DBlock*, int, const DTile*, int, const double* const*, const double*,
-                          int, int64_t, void*, void*, double*, double*, int*, double*, int, int, int*,
-                          double*, double*, int*, double*, hipStream_t);
+                          int, int64_t, void*, void*, double*, double*, int*, int, double*, int, int,
+                          int*, double*, double*, int*, double*, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const ZPtrs&, int, int64_t,
                       hipStream_t);
@@ -285,7 +285,7 @@ struct dmrg_ctx {
     Group self;         // tables of the handle's own Krylov runs
     // density matrix and truncation (built on first use): sectors, tiles, matrices, results
     DevBuf dDBlk, dDTile, dDA, dDV, dDZ, dDS, dDFail, dDEv, dDKept, dDNk, dDSums, dDVecs, dDW;
-    int dens_ntiles = 0, dens_ntot = 0;
+    int dens_ntiles = 0, dens_ntot = 0, dens_maxd = 0;
     int64_t dens_nmat = 0;
     std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
     // local operators (built on first use): raw operator blocks of both halves, the product
@@ -1183,6 +1183,7 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
             const PsiBlock& pbk = P.blocks[b];
             if (pbk.d > kDensMaxDim) return fail(h, DMRG_EINVAL, "system sector larger than 1024");
             blks[b] = DBlock{pbk.d, pbk.e, pbk.off, aoff, eoff};
+            h->dens_maxd = std::max(h->dens_maxd, pbk.d);
             for (int i0 = 0; i0 < pbk.d; i0 += 16)
                 for (int j0 = 0; j0 < pbk.d; j0 += 16) tiles.push_back(DTile{b, i0, j0, 0});
             aoff += (int64_t)pbk.d * pbk.d;
@@ -1212,7 +1213,7 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
     HIP_TRY(h, launch_density(h->dDBlk.as<DBlock>(), nb, h->dDTile.as<DTile>(), h->dens_ntiles,
                               h->dDVecs.as<const double*>(), h->dDW.as<double>(), nvec, P.n,
                               h->dDA.p, h->dDV.p, h->dDZ.as<double>(), h->dDS.as<double>(),
-                              h->dDFail.as<int>(),
+                              h->dDFail.as<int>(), h->dens_maxd,
                               h->dDEv.as<double>(), h->dens_ntot, keep, h->dDKept.as<int>(), evals,
                               evecs, h->dDNk.as<int>(), h->dDSums.as<double>(), s));
     std::vector<int> nk(nb), nofit(nb);
@@ -1223,7 +1224,7 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
     HIP_TRY(h, hipMemcpyAsync(nofit.data(), h->dDFail.p, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
     for (int b = 0; b < nb; ++b)
-        if (nofit[b]) return fail(h, DMRG_ENONFINITE, "density matrix: QL iteration did not converge");
+        if (nofit[b] & 1) return fail(h, DMRG_ENONFINITE, "density matrix: QL iteration did not converge");
     double all = 0.0, kept_sum = 0.0;
     for (int b = 0; b < nb; ++b) {
         kept[b] = nk[b];

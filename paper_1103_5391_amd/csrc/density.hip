@@ -121,7 +121,9 @@ constexpr int kEigThreads = 512;    // threads of an eigen-decomposition work gr
 constexpr int kQlMaxSweeps = 64;    // QL sweeps per eigenvalue at most
 constexpr int kClusterMax = 8;      // inverse iteration when no cluster of eigenvalues is larger
 constexpr double kClusterGap = 1e-3;  // eigenvalues closer than this times |T| form a cluster
-constexpr int kEigChunk = 16;       // loads a thread issues together in the rotation and
+constexpr int kEigChunk = 16;
+constexpr int kBt = 8;              // reflectors per block of the back-transformation
+constexpr int kBtChunk = 2;         // rows a lane reads together in the back-transformation       // loads a thread issues together in the rotation and
                                     // reflector passes (their values do not depend on the stores)
 
 // Eigen-decomposition of rho_p, one work group per sector (LAPACK's path for Hermitian
@@ -492,50 +494,135 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     handover_barrier();                                 // rows of Z to the column owners
     for (int i = tid; i < d; i += NT) ev[B.eoff + i] = dg[i];
     }
-    // ---------------------------------------------------------------- 4. back-transformation
-    // G lanes per column of Y (a power of two, inside one wavefront): lane q of a group takes
-    // the rows i = q mod G; the group adds its partial inner products by shuffles
+    if (tid == 0 && zr == 1) atomicOr(&fail[blockIdx.x], 2);   // Z column-major (QL path)
+
+}
+
+// Back-transformation Y = H_0 H_1 ... H_{d-2} Z of one sector's eigenvectors (one work group
+// per sector and range of kBackCols columns of Y; Z row-major, or column-major when bit 1 of
+// flags[blk] is set), kBt reflectors at a time: the product H_k1 ... H_k2 of a block is
+// I - V T V^H (V the block's reflectors as columns, staged in LDS; T upper triangular from the
+// taus on the diagonal of A and the Gram matrix V^H V), applied as Y - V (T (V^H Y)): one pass
+// over the rows for V^H Y and one for the update.  G lanes per column (a power of two inside a
+// wavefront): lane q takes the rows i = q mod G, the group adds its partial inner products by
+// shuffles.
+constexpr int kBackThreads = 256;
+constexpr int kBackCols = 32;
+__global__ __launch_bounds__(kBackThreads) void k_heig_back(const DBlock* __restrict__ blks,
+                                                            const dv2* __restrict__ A,
+                                                            const double* __restrict__ Zb,
+                                                            dv2* __restrict__ Yb,
+                                                            const int* __restrict__ flags) {
+    constexpr int NT = kBackThreads, BT = kBt;
+    const DBlock B = blks[blockIdx.x];
+    const int d = B.d, tid = threadIdx.x;
+    const int jb = blockIdx.y * kBackCols;
+    if (jb >= d) return;
+    const int je = jb + kBackCols < d ? jb + kBackCols : d;
+    const dv2* __restrict__ a = A + B.aoff;
+    const double* __restrict__ Z = Zb + B.aoff;
+    dv2* __restrict__ Y = Yb + B.aoff;
+    const bool colmajor = (flags[blockIdx.x] & 2) != 0;
+    const int64_t zr = colmajor ? 1 : d, zc = colmajor ? d : 1;
+    __shared__ dv2 Vs[2 * kDensMaxDim];                 // the block's reflectors, Vs[c d + i]
+    __shared__ dv2 Tt[BT * BT], Gm[BT * BT];
+    const int bt = 2 * kDensMaxDim / d < BT ? 2 * kDensMaxDim / d : BT;
     int G = 1;
-    while (G < 8 && 2 * G * d <= NT) G *= 2;
-    const int q = tid % G;
-    for (int j0 = tid / G; j0 < (d + NT / G - 1) / (NT / G) * (NT / G); j0 += NT / G) {
-        const int j = j0 < d ? j0 : d - 1;              // idle groups repeat the last column's
-        const bool own = j0 < d;                        // arithmetic without storing
-        for (int i = q; i < d; i += G)
-            if (own) Y[(int64_t)i * d + j] = (dv2){Z[(int64_t)i * zr + (int64_t)j * zc], 0.0};
-        for (int k = d - 2; k >= 0; --k) {
-            const int64_t ck = (int64_t)k * d;
-            const dv2 tau = a[ck + k];
-            if (tau.x == 0.0 && tau.y == 0.0) continue;
-            // rows k+1 .. d-1 of this lane: first row of the lane's share
-            int i1 = k + 1 + ((q - (k + 1) % G) % G + G) % G;
-            dv2 dot = (dv2){0.0, 0.0};
-            for (int i = i1; i < d; i += G) {
-                const dv2 v = i == k + 1 ? (dv2){1.0, 0.0} : a[ck + i];          // v_k[0] = 1
-                dot += cmul(cconj(v), Y[(int64_t)i * d + j]);
-            }
-            for (int o = 1; o < G; o <<= 1) {
-                dot.x += __shfl_xor(dot.x, o, 64);
-                dot.y += __shfl_xor(dot.y, o, 64);
-            }
-            const dv2 c = cmul(tau, dot);
-            for (int i00 = i1; i00 < d; i00 += G * kEigChunk) {
-                dv2 yv[kEigChunk];
+    while (G < 8 && G * kBackCols * 2 <= NT) G *= 2;
+    const int q = tid % G, slots = NT / G;
+    const int wv = tid >> 6, ln = tid & 63;
+    for (int j = jb + tid / G; j < je; j += slots)
+        for (int i = q; i < d; i += G) Y[(int64_t)i * d + j] = (dv2){Z[i * zr + j * zc], 0.0};
+    for (int k2 = d - 2; k2 >= 0; k2 -= bt) {
+        const int k1 = k2 - bt + 1 > 0 ? k2 - bt + 1 : 0, nb = k2 - k1 + 1;
+        for (int t = tid; t < nb * d; t += NT) {
+            const int c = t / d, i = t % d, k = k1 + c;
+            Vs[t] = i <= k ? (dv2){0.0, 0.0} : (i == k + 1 ? (dv2){1.0, 0.0} : a[(int64_t)k * d + i]);
+        }
+        __syncthreads();
+        for (int t = wv; t < nb * nb; t += NT / 64) {   // one wavefront per Gram entry
+            const int c1 = t % nb, c2 = t / nb;
+            if (c1 >= c2) continue;
+            dv2 acc = (dv2){0.0, 0.0};
+            for (int i = k1 + c2 + 1 + ln; i < d; i += 64) acc += cmul(cconj(Vs[c1 * d + i]), Vs[c2 * d + i]);
 #pragma unroll
-                for (int u = 0; u < kEigChunk; ++u) {
-                    const int i = i00 + u * G;
-                    if (i < d) yv[u] = Y[(int64_t)i * d + j];
+            for (int o = 32; o > 0; o >>= 1) {
+                acc.x += __shfl_xor(acc.x, o, 64);
+                acc.y += __shfl_xor(acc.y, o, 64);
+            }
+            if (ln == 0) Gm[c1 + BT * c2] = acc;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            for (int c = 0; c < nb; ++c) {
+                const dv2 tau = a[(int64_t)(k1 + c) * d + k1 + c];
+                for (int r = 0; r < c; ++r) {
+                    dv2 sum = (dv2){0.0, 0.0};
+                    for (int u = r; u < c; ++u) sum += cmul(Tt[r + BT * u], Gm[u + BT * c]);
+                    Tt[r + BT * c] = cmul((dv2){-tau.x, -tau.y}, sum);
+                }
+                Tt[c + BT * c] = tau;
+            }
+        }
+        __syncthreads();
+        const int i1 = k1 + 1 + ((q - (k1 + 1) % G) % G + G) % G;
+        for (int j0 = jb + tid / G; j0 < jb + kBackCols; j0 += slots) {
+            const int j = j0 < je ? j0 : je - 1;        // idle groups repeat the last column's
+            const bool own = j0 < je;                   // arithmetic without storing
+            dv2 w[BT];
+#pragma unroll
+            for (int c = 0; c < BT; ++c) w[c] = (dv2){0.0, 0.0};
+            for (int i0 = i1; i0 < d; i0 += G * kBtChunk) {
+                dv2 yv[kBtChunk];
+#pragma unroll
+                for (int u = 0; u < kBtChunk; ++u) {
+                    const int i = i0 + u * G;
+                    yv[u] = i < d ? Y[(int64_t)i * d + j] : (dv2){0.0, 0.0};
                 }
 #pragma unroll
-                for (int u = 0; u < kEigChunk; ++u) {
-                    const int i = i00 + u * G;
-                    if (i < d && own) {
-                        const dv2 v = i == k + 1 ? (dv2){1.0, 0.0} : a[ck + i];
-                        Y[(int64_t)i * d + j] = yv[u] - cmul(v, c);
-                    }
+                for (int u = 0; u < kBtChunk; ++u) {
+                    const int i = i0 + u * G;
+                    if (i >= d) continue;
+#pragma unroll
+                    for (int c = 0; c < BT; ++c)
+                        if (c < nb) w[c] += cmul(cconj(Vs[c * d + i]), yv[u]);
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < BT; ++c)
+                for (int o = 1; o < G; o <<= 1) {
+                    w[c].x += __shfl_xor(w[c].x, o, 64);
+                    w[c].y += __shfl_xor(w[c].y, o, 64);
+                }
+            dv2 u[BT];
+#pragma unroll
+            for (int r = 0; r < BT; ++r) {
+                u[r] = (dv2){0.0, 0.0};
+#pragma unroll
+                for (int c = 0; c < BT; ++c)
+                    if (r <= c && c < nb) u[r] += cmul(Tt[r + BT * c], w[c]);
+            }
+            if (!own) continue;
+            for (int i0 = i1; i0 < d; i0 += G * kBtChunk) {
+                dv2 yv[kBtChunk];
+#pragma unroll
+                for (int uu = 0; uu < kBtChunk; ++uu) {
+                    const int i = i0 + uu * G;
+                    yv[uu] = i < d ? Y[(int64_t)i * d + j] : (dv2){0.0, 0.0};
+                }
+#pragma unroll
+                for (int uu = 0; uu < kBtChunk; ++uu) {
+                    const int i = i0 + uu * G;
+                    if (i >= d) continue;
+                    dv2 y = yv[uu];
+#pragma unroll
+                    for (int c = 0; c < BT; ++c)
+                        if (c < nb) y -= cmul(Vs[c * d + i], u[c]);
+                    Y[(int64_t)i * d + j] = y;
                 }
             }
         }
+        __syncthreads();
     }
 }
 
@@ -543,15 +630,22 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
 // (the order of the flat array); kept[g] = rank < keep.
 __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ev, int ntot, int keep,
                                               int* __restrict__ kept) {
+    constexpr int CH = 2048;                            // values staged in LDS at a time
+    __shared__ double sv[CH];
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= ntot) return;
-    const double x = ev[g];
+    const double x = g < ntot ? ev[g] : 0.0;
     int rank = 0;
-    for (int h = 0; h < ntot; ++h) {
-        const double y = ev[h];
-        rank += (y > x) || (y == x && h < g);
+    for (int h0 = 0; h0 < ntot; h0 += CH) {
+        const int nh = ntot - h0 < CH ? ntot - h0 : CH;
+        for (int t = threadIdx.x; t < nh; t += blockDim.x) sv[t] = ev[h0 + t];
+        __syncthreads();
+        for (int t = 0; t < nh; ++t) {
+            const double y = sv[t];
+            rank += (y > x) || (y == x && h0 + t < g);
+        }
+        __syncthreads();
     }
-    kept[g] = rank < keep;
+    if (g < ntot) kept[g] = rank < keep;
 }
 
 // Per sector: eigenvalues in descending order (equal values by index) with their eigenvectors
@@ -601,13 +695,15 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
 
 hipError_t launch_density(const DBlock* blks, int nblk, const DTile* tiles, int ntiles,
                           const double* const* vecs, const double* weights, int nv, int64_t n,
-                          void* A, void* V, double* Z, double* S, int* fail, double* ev, int ntot,
-                          int keep, int* kept, double* evals, double* evecs, int* nkept,
+                          void* A, void* V, double* Z, double* S, int* fail, int maxd, double* ev,
+                          int ntot, int keep, int* kept, double* evals, double* evecs, int* nkept,
                           double* sums, hipStream_t s) {
     hipLaunchKernelGGL(k_density, dim3(ntiles), dim3(256), 0, s, blks, tiles, vecs, weights, nv, n,
                        static_cast<dv2*>(A));
     hipLaunchKernelGGL(k_heig, dim3(nblk), dim3(kEigThreads), 0, s, blks, static_cast<dv2*>(A), Z, S,
                        static_cast<dv2*>(V), ev, fail);
+    hipLaunchKernelGGL(k_heig_back, dim3(nblk, (maxd + kBackCols - 1) / kBackCols), dim3(kBackThreads), 0,
+                       s, blks, static_cast<const dv2*>(A), Z, static_cast<dv2*>(V), fail);
     hipLaunchKernelGGL(k_rank, dim3((ntot + 255) / 256), dim3(256), 0, s, ev, ntot, keep, kept);
     hipLaunchKernelGGL(k_finish, dim3(nblk), dim3(256), 0, s, blks, ev, kept,
                        static_cast<const dv2*>(V), evals, evecs, nkept, sums);
