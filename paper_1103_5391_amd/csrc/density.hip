@@ -117,6 +117,39 @@ __device__ __forceinline__ double wg_sum(double v, double* red) {
     return s;
 }
 
+// As wg_sum, with one barrier: the caller keeps `red` untouched until a further barrier has
+// passed (so every thread has read the previous sum).
+template <int NT>
+__device__ __forceinline__ double wg_sum1(double v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
+    return s;
+}
+
+// The same for a complex value (red: 2 NT / 64 doubles).
+template <int NT>
+__device__ __forceinline__ dv2 wg_sum1c(dv2 v, double* red) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        v.x += __shfl_xor(v.x, o, 64);
+        v.y += __shfl_xor(v.y, o, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        red[2 * (threadIdx.x >> 6)] = v.x;
+        red[2 * (threadIdx.x >> 6) + 1] = v.y;
+    }
+    __syncthreads();
+    dv2 s = (dv2){0.0, 0.0};
+#pragma unroll
+    for (int w = 0; w < NT / 64; ++w) s += (dv2){red[2 * w], red[2 * w + 1]};
+    return s;
+}
+
 constexpr int kEigThreads = 512;    // threads of an eigen-decomposition work group
 constexpr int kQlMaxSweeps = 64;    // QL sweeps per eigenvalue at most
 constexpr int kClusterMax = 8;      // inverse iteration when no cluster of eigenvalues is larger
@@ -153,12 +186,14 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     __shared__ double dg[kDensMaxDim], e[kDensMaxDim];
     __shared__ dv2 vv[kDensMaxDim], ww[kDensMaxDim];
     __shared__ dv2 pp[NT];
-    __shared__ double red[2 * NT / 64];
-    __shared__ double s_beta;
-    __shared__ dv2 s_tau, s_scale;
+    __shared__ double red[3 * NT / 64];
     __shared__ int s_i0[2], s_cnt[2], s_done[2], s_path;
     __shared__ double s_lo, s_hi, s_tn;
     // ---------------------------------------------------------------- 1. tridiagonal
+    // Five barriers a step: the norm of the column (buffer red), the reflector, the product B v,
+    // the inner product w0^H v (buffer red2), and the hand-over of the updated trailing matrix.
+    // The two sums use separate buffers and each is reused only after further barriers.
+    double* red2 = red + NT / 64;
     for (int k = 0; k + 1 < d; ++k) {
         const int m = d - k - 1;
         const int64_t ck = (int64_t)k * d;
@@ -169,33 +204,29 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
             if (i > 0) part += x.x * x.x + x.y * x.y;
         }
         if (tid == 0) dg[k] = a[ck + k].x;
-        const double xn2 = wg_sum<NT>(part, red);
-        if (tid == 0) {
-            const dv2 al = vv[0];
-            if (xn2 == 0.0 && al.y == 0.0) {
-                s_beta = al.x;
-                s_tau = (dv2){0.0, 0.0};
-                s_scale = (dv2){0.0, 0.0};
-            } else {
-                const double beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
-                s_beta = beta;
-                s_tau = (dv2){(beta - al.x) / beta, -al.y / beta};
-                const dv2 den = (dv2){al.x - beta, al.y};              // 1 / (alpha - beta)
-                const double q = den.x * den.x + den.y * den.y;
-                s_scale = (dv2){den.x / q, -den.y / q};
-            }
-            e[k] = s_beta;
-            a[ck + k] = s_tau;                                          // tau_k on the diagonal
+        const double xn2 = wg_sum1<NT>(part, red);
+        // every thread forms the reflector (the same arithmetic on the same values)
+        const dv2 al = vv[0];
+        dv2 tau = (dv2){0.0, 0.0}, sc = (dv2){0.0, 0.0};
+        double beta = al.x;
+        if (!(xn2 == 0.0 && al.y == 0.0)) {
+            beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
+            tau = (dv2){(beta - al.x) / beta, -al.y / beta};
+            const dv2 den = (dv2){al.x - beta, al.y};                   // 1 / (alpha - beta)
+            const double q = den.x * den.x + den.y * den.y;
+            sc = (dv2){den.x / q, -den.y / q};
         }
-        __syncthreads();
-        const dv2 tau = s_tau, sc = s_scale;
-        for (int i = tid; i < m; i += NT) {
+        if (tid == 0) {
+            e[k] = beta;
+            a[ck + k] = tau;                                            // tau_k on the diagonal
+        }
+        for (int i = tid; i < m; i += NT) {                             // own entries of vv
             const dv2 v = i == 0 ? (dv2){1.0, 0.0} : cmul(vv[i], sc);
             vv[i] = v;
             if (i > 0) a[ck + k + 1 + i] = v;                           // v_k below the subdiagonal
         }
-        __syncthreads();
-        if (tau.x == 0.0 && tau.y == 0.0) continue;                     // H_k = I
+        __syncthreads();                                                // v complete; red read
+        if (tau.x == 0.0 && tau.y == 0.0) continue;                     // H_k = I (uniform)
         // w0 = tau B v: rows i, column groups g (G groups of the columns; G = 1 when a thread
         // takes whole rows)
         const int G = m >= NT ? 1 : NT / m;
@@ -220,15 +251,14 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
             pr += w.x * v.x + w.y * v.y;
             pi += w.x * v.y - w.y * v.x;
         }
-        const double dr = wg_sum<NT>(pr, red), di = wg_sum<NT>(pi, red + NT / 64);
-        const dv2 al2 = cmul((dv2){-0.5 * tau.x, -0.5 * tau.y}, (dv2){dr, di});
-        for (int i = tid; i < m; i += NT) ww[i] += cmul(al2, vv[i]);
-        __syncthreads();
-        // B -= v w^H + w v^H
+        const dv2 dsum = wg_sum1c<NT>((dv2){pr, pi}, red2);
+        const dv2 al2 = cmul((dv2){-0.5 * tau.x, -0.5 * tau.y}, dsum);
+        // B -= v w^H + w v^H with w = w0 + al2 v, formed on the fly
         for (int64_t it = tid; it < (int64_t)m * m; it += NT) {
             const int i = (int)(it % m), j = (int)(it / m);
             const int64_t at = (int64_t)(k + 1 + j) * d + k + 1 + i;
-            a[at] -= cmul(vv[i], cconj(ww[j])) + cmul(ww[i], cconj(vv[j]));
+            const dv2 wi = ww[i] + cmul(al2, vv[i]), wj = ww[j] + cmul(al2, vv[j]);
+            a[at] -= cmul(vv[i], cconj(wj)) + cmul(wi, cconj(vv[j]));
         }
         handover_barrier();
     }
@@ -256,22 +286,47 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
         s_tn = fmax(tn, 1e-300);
     }
     __syncthreads();
-    for (int j = tid; j < d; j += NT) {
-        double lo = s_lo, hi = s_hi;
-        for (int it = 0; it < 256; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            if (hi - lo <= 4.440892098500626e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300 || mid <= lo || mid >= hi) break;
-            double q = dg[0] - mid;
-            int cnt = q < 0.0;
-            for (int i = 1; i < d; ++i) {
-                if (fabs(q) < 1e-300) q = -1e-300;
-                q = (dg[i] - mid) - e2[i - 1] / q;
-                cnt += q < 0.0;
+    {
+        // GB lanes per eigenvalue (a power of two inside a wavefront) count at GB interior
+        // points of the interval and keep the piece that holds the eigenvalue
+        int GB = 1;
+        while (GB < 8 && 2 * GB * d <= NT) GB *= 2;
+        const int qb = tid % GB, jslots = NT / GB;
+        const int jend = (d + jslots - 1) / jslots * jslots;
+        for (int j0 = tid / GB; j0 < jend; j0 += jslots) {
+            const int j = j0 < d ? j0 : d - 1;
+            double lo = s_lo, hi = s_hi;
+            for (int it = 0; it < 256; ++it) {
+                if (hi - lo <= 4.440892098500626e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
+                const double step = (hi - lo) / (GB + 1);
+                const double x = lo + step * (qb + 1);
+                double q = dg[0] - x;
+                int cnt = q < 0.0;
+                for (int i = 1; i < d; ++i) {
+                    if (fabs(q) < 1e-300) q = -1e-300;
+                    q = (dg[i] - x) - e2[i - 1] / q;
+                    cnt += q < 0.0;
+                }
+                double nlo = lo, nhi = hi;
+                bool found = false;
+                for (int u = 0; u < GB; ++u) {
+                    const int cu = __shfl(cnt, (tid & 63) - qb + u, 64);
+                    const double xu = lo + step * (u + 1);
+                    if (!found) {
+                        if (cu > j) {
+                            nhi = xu;
+                            found = true;
+                        } else {
+                            nlo = xu;
+                        }
+                    }
+                }
+                if (!(nhi - nlo < hi - lo)) break;      // no progress at rounding level
+                lo = nlo;
+                hi = nhi;
             }
-            if (cnt > j) hi = mid;
-            else lo = mid;
+            if (qb == 0 && j0 < d) lam[j] = 0.5 * (lo + hi);
         }
-        lam[j] = 0.5 * (lo + hi);
     }
     __syncthreads();
     if (tid == 0) {                                     // largest cluster decides the path
