@@ -8,10 +8,14 @@
 // with Psi_{l,p} the d_p x e_q block of target l.  Steps:
 //   k_density   rho_p in 16 x 16 tiles (one work group per tile; row panels of the blocks staged
 //               through LDS, K = e_q columns per target, every target in turn)
-//   k_heig      eigen-decomposition of every rho_p, one work group per sector: Householder
-//               reduction to a real tridiagonal matrix, implicit QL with shifts (one thread
-//               lists the rotations of a sweep, every thread applies them to its rows of Z),
-//               back-transformation by the reflectors (one thread per eigenvector)
+//   k_heig      eigen-decomposition of every rho_p up to the back-transformation, one work
+//               group per sector: Householder reduction to a real tridiagonal matrix T,
+//               eigenvalues of T by multisection on Sturm counts, eigenvectors of T by inverse
+//               iteration (no cluster of close eigenvalues larger than 8) or else by implicit QL
+//               with shifts (one lane lists the rotations of the next sweep while the other
+//               wavefronts apply the current one to their rows)
+//   k_heig_back back-transformation by the reflectors in compact WY blocks, several work
+//               groups per sector
 //   k_rank      global rank of every eigenvalue (larger first; equal values by sector, then by
 //               index), kept if the rank is below m
 //   k_finish    per sector: eigenvalues in descending order with their eigenvectors, the number

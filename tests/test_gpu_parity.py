@@ -486,7 +486,7 @@ def _decaying(pb, x, decades):
 
 @pytest.mark.parametrize("name,decades", [("chain12_m30", 0), ("chain8_exact", 0), ("chain8_m17_odd", 0),
                                           ("ladder16_m1000", 0), ("chain12_m30", 12),
-                                          ("ladder16_m1000", 14)])
+                                          ("ladder16_m1000", 14), ("ladder32_m2000", 0)])
 def test_density_truncate_parity(env, name, decades):
     """Density matrix of five weighted targets and its truncation against the oracle: every
     eigenvalue, the kept count of every sector and the truncation error; eigen-pairs (residual
@@ -541,6 +541,11 @@ def test_density_truncate_parity(env, name, decades):
     say("  keep", keep, "trunc err", err, ref.trunc_err, "worst projector diff", worst)
     assert abs(err - ref.trunc_err) <= 1e-12
     assert worst <= 1e-8
+    # the two ends of the truncation: nothing kept (the error is the trace) and everything kept
+    k0, err0 = h.density_truncate(xds, w, 0, torch.empty_like(evd), torch.empty_like(vcd))
+    assert sum(int(k) for k in k0) == 0 and abs(err0 - ref.trace) <= 1e-12 * max(1.0, ref.trace)
+    kall, errall = h.density_truncate(xds, w, total + 5, torch.empty_like(evd), torch.empty_like(vcd))
+    assert [int(k) for k in kall] == rows and abs(errall) <= 1e-12 * max(1.0, ref.trace)
     # a second call gives the same bits (fixed-order arithmetic throughout)
     ev2 = torch.full_like(evd, float("nan"))
     vc2 = torch.full_like(vcd, float("nan"))
@@ -664,6 +669,15 @@ def test_wft_rejects_inconsistent_moves(env):
         h.wft_create(bad, Wd)
     w = h.wft_create(mv, Wd)
     w.destroy()
+    # density matrix: vector counts outside [1, 16] and a negative keep are rejected
+    x = _dev(torch, I.random_psi(h.n, np.random.default_rng(3)))
+    evd = torch.empty(sum(rows), dtype=torch.float64, device="cuda")
+    vcd = torch.empty(sum(2 * r * r for r in rows), dtype=torch.float64, device="cuda")
+    for vecs, wts, keep in (([x] * 17, [0.05] * 17, 10), ([x], [1.0], -1)):
+        with pytest.raises(L.DmrgError):
+            h.density_truncate(vecs, wts, keep, evd, vcd)
+    with pytest.raises(L.DmrgError):
+        h.density_truncate([x], [float("nan")], 10, evd, vcd)
     h.destroy()
 
 
