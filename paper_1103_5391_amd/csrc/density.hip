@@ -157,7 +157,7 @@ __device__ __forceinline__ dv2 wg_sum1c(dv2 v, double* red) {
 constexpr int kEigThreads = 512;    // threads of an eigen-decomposition work group
 constexpr int kQlMaxSweeps = 64;    // QL sweeps per eigenvalue at most
 constexpr int kClusterMax = 8;      // inverse iteration when no cluster of eigenvalues is larger
-constexpr double kClusterGap = 1e-3;  // eigenvalues closer than this times |T| form a cluster
+constexpr double kClusterGap = 1e-5;  // eigenvalues closer than this times |T| form a cluster
 constexpr int kEigChunk = 16;
 constexpr int kBt = 8;              // reflectors per block of the back-transformation
 constexpr int kBtChunk = 2;         // rows a lane reads together in the back-transformation       // loads a thread issues together in the rotation and
@@ -698,10 +698,15 @@ __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ev, int
         const int nh = ntot - h0 < CH ? ntot - h0 : CH;
         for (int t = threadIdx.x; t < nh; t += blockDim.x) sv[t] = ev[h0 + t];
         __syncthreads();
-        for (int t = 0; t < nh; ++t) {
-            const double y = sv[t];
-            rank += (y > x) || (y == x && h0 + t < g);
+        int t = 0;
+        for (; t + 8 <= nh; t += 8) {                   // eight LDS reads in flight
+            double y[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) y[u] = sv[t + u];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) rank += (y[u] > x) || (y[u] == x && h0 + t + u < g);
         }
+        for (; t < nh; ++t) rank += (sv[t] > x) || (sv[t] == x && h0 + t < g);
         __syncthreads();
     }
     if (g < ntot) kept[g] = rank < keep;
