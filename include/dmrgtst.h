@@ -297,6 +297,8 @@ int dmrg_wft_create(dmrg_handle h, const dmrg_wft_desc* desc, const double* cons
 int dmrg_wft_apply(dmrg_wft w, const double* U, int32_t nvec, const double* const* x,
                    double* const* y, double* flops);
 
+/* Releases a planned move (waits for the handle's stream).  Destroy every move of a handle
+ * before the handle.  DMRG_EINVAL for NULL. */
 int dmrg_wft_destroy(dmrg_wft w);
 
 /* Local operators on the superblock (Sec. II.B, Eq. (b): the operators B applied to the ground
