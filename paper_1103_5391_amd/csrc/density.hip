@@ -17,7 +17,7 @@
 //   k_heig_back back-transformation by the reflectors in compact WY blocks, several work
 //               groups per sector
 //   k_rank      global rank of every eigenvalue (larger first; equal values by sector, then by
-//               index), kept if the rank is below m
+//               index) in pieces over a two-dimensional grid; kept if the rank is below m
 //   k_finish    per sector: eigenvalues in descending order with their eigenvectors, the number
 //               kept, and the sums of all and of the kept eigenvalues (fixed-order reductions)
 // The matrices live in global memory (L2-resident for the sector sizes of these workloads); the
@@ -685,31 +685,34 @@ __global__ __launch_bounds__(kBackThreads) void k_heig_back(const DBlock* __rest
     }
 }
 
-// Global rank of eigenvalue g among all ntot: larger first, equal values by sector then index
-// (the order of the flat array); kept[g] = rank < keep.
-__global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ev, int ntot, int keep,
-                                              int* __restrict__ kept) {
-    constexpr int CH = 2048;                            // values staged in LDS at a time
-    __shared__ double sv[CH];
+// Global rank of eigenvalue g among all ntot (larger first, equal values by sector then index:
+// the order of the flat array), in pieces: work group (x, y) counts, for its 256 eigenvalues,
+// the values of chunk y (kRankChunk values through LDS) that rank before them, and adds the
+// count to rank[g] (integer atomics: the sum does not depend on their order).  rank starts at
+// zero.
+constexpr int kRankChunk = 256;
+__global__ __launch_bounds__(256) void k_zero_int(int* __restrict__ x, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ev, int ntot,
+                                              int* __restrict__ rank) {
+    __shared__ double sv[kRankChunk];
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const double x = g < ntot ? ev[g] : 0.0;
-    int rank = 0;
-    for (int h0 = 0; h0 < ntot; h0 += CH) {
-        const int nh = ntot - h0 < CH ? ntot - h0 : CH;
-        for (int t = threadIdx.x; t < nh; t += blockDim.x) sv[t] = ev[h0 + t];
-        __syncthreads();
-        int t = 0;
-        for (; t + 8 <= nh; t += 8) {                   // eight LDS reads in flight
-            double y[8];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) y[u] = sv[t + u];
-#pragma unroll
-            for (int u = 0; u < 8; ++u) rank += (y[u] > x) || (y[u] == x && h0 + t + u < g);
-        }
-        for (; t < nh; ++t) rank += (sv[t] > x) || (sv[t] == x && h0 + t < g);
-        __syncthreads();
+    const int h0 = blockIdx.y * kRankChunk;
+    const int nh = ntot - h0 < kRankChunk ? ntot - h0 : kRankChunk;
+    if (nh <= 0) return;
+    for (int t = threadIdx.x; t < nh; t += blockDim.x) sv[t] = ev[h0 + t];
+    __syncthreads();
+    if (g >= ntot) return;
+    const double x = ev[g];
+    int r = 0;
+    for (int t = 0; t < nh; ++t) {
+        const double y = sv[t];
+        r += (int)(y > x) | ((int)(y == x) & (int)(h0 + t < g));
     }
-    if (g < ntot) kept[g] = rank < keep;
+    if (r) atomicAdd(&rank[g], r);
 }
 
 // Per sector: eigenvalues in descending order (equal values by index) with their eigenvectors
@@ -717,7 +720,7 @@ __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ev, int
 // the number kept and the sums of all and of the kept eigenvalues.
 __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
                                                 const double* __restrict__ ev,
-                                                const int* __restrict__ kept,
+                                                const int* __restrict__ rank, int keep,
                                                 const dv2* __restrict__ V,
                                                 double* __restrict__ evals,
                                                 double* __restrict__ evecs,
@@ -742,7 +745,7 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
             dim[row] = z.y;
         }
         all += x;
-        if (kept[B.eoff + i]) {
+        if (rank[B.eoff + i] < keep) {
             ksum += x;
             kc += 1.0;
         }
@@ -768,8 +771,10 @@ hipError_t launch_density(const DBlock* blks, int nblk, const DTile* tiles, int 
                        static_cast<dv2*>(V), ev, fail);
     hipLaunchKernelGGL(k_heig_back, dim3(nblk, (maxd + kBackCols - 1) / kBackCols), dim3(kBackThreads), 0,
                        s, blks, static_cast<const dv2*>(A), Z, static_cast<dv2*>(V), fail);
-    hipLaunchKernelGGL(k_rank, dim3((ntot + 255) / 256), dim3(256), 0, s, ev, ntot, keep, kept);
-    hipLaunchKernelGGL(k_finish, dim3(nblk), dim3(256), 0, s, blks, ev, kept,
+    hipLaunchKernelGGL(k_zero_int, dim3((ntot + 255) / 256), dim3(256), 0, s, kept, ntot);
+    hipLaunchKernelGGL(k_rank, dim3((ntot + 255) / 256, (ntot + kRankChunk - 1) / kRankChunk), dim3(256), 0,
+                       s, ev, ntot, kept);
+    hipLaunchKernelGGL(k_finish, dim3(nblk), dim3(256), 0, s, blks, ev, kept, keep,
                        static_cast<const dv2*>(V), evals, evecs, nkept, sums);
     return hipGetLastError();
 }
