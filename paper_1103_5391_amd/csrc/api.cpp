@@ -38,7 +38,7 @@ hipError_t launch_density(const DBlock*, int, const DTile*, int, const double* c
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const ZPtrs&, int, int64_t,
                       hipStream_t);
-hipError_t launch_zgemm(const ZTile*, int, const ZPtrs&, int, hipStream_t);
+hipError_t launch_zgemm(const ZTile*, int, const ZPtrs&, int, int, int, hipStream_t);
 hipError_t launch_zero(double*, int64_t, hipStream_t);
 hipError_t launch_zdot(const double*, const double*, int64_t, double*, int, hipStream_t);
 constexpr int kDotBlocks = 256;     // partial sums of one inner product
@@ -809,7 +809,7 @@ bool factor_of(const HalfTable& T, const std::vector<int64_t>& base, int op, int
 // the right products T = X B^T (terms with an environment factor) then the left products
 // y += alpha A T; launches[i] = (first tile, count, which product).
 int plan_local(dmrg_handle hs, dmrg_handle hd, int nterm, const dmrg_term* terms,
-               std::vector<ZTile>& tiles, std::vector<std::array<int, 3>>& launches, int64_t& tsize) {
+               std::vector<ZTile>& tiles, std::vector<std::array<int, 5>>& launches, int64_t& tsize) {
     const Plan& S = hs->plan;
     const Plan& D = hd->plan;
     auto bad = [&](const std::string& why) { return fail(hs, DMRG_EINVAL, "local operator: " + why); };
@@ -896,25 +896,27 @@ int plan_local(dmrg_handle hs, dmrg_handle hd, int nterm, const dmrg_term* terms
             if (z.bim < 0) z.bim = toff;
         tsize = std::max(tsize, toff);
         if (!right.empty()) {
-            launches.push_back({(int)tiles.size(), (int)right.size(), 0});
+            launches.push_back({(int)tiles.size(), (int)right.size(), 0, right[0].amode, right[0].bmode});
             tiles.insert(tiles.end(), right.begin(), right.end());
         }
         if (!left.empty()) {
-            launches.push_back({(int)tiles.size(), (int)left.size(), tm.opE >= 0 ? 1 : 2});
+            launches.push_back({(int)tiles.size(), (int)left.size(), tm.opE >= 0 ? 1 : 2, left[0].amode,
+                                left[0].bmode});
             tiles.insert(tiles.end(), left.begin(), left.end());
         }
     }
     return DMRG_OK;
 }
 
-// y (dst layout) = sum of the terms applied to x (src layout); asynchronous.  launches[i][2]:
-// 0 right products, 1 left products of the intermediate, 2 left products of x.
+// y (dst layout) = sum of the terms applied to x (src layout); asynchronous.  launches[i] =
+// (first tile, tiles, kind, A mode, B mode), kind 0 right products, 1 left products of the
+// intermediate, 2 left products of x (the tiles of a launch share their operand modes).
 int run_local(dmrg_handle hs, dmrg_handle hd, int nterm, const dmrg_term* terms, const double* x,
               double* y) {
     int rc = ensure_local_ops(hs);
     if (rc) return rc;
     std::vector<ZTile> tiles;
-    std::vector<std::array<int, 3>> launches;
+    std::vector<std::array<int, 5>> launches;
     int64_t tsize = 0;
     rc = plan_local(hs, hd, nterm, terms, tiles, launches, tsize);
     if (rc) return rc;
@@ -936,7 +938,7 @@ int run_local(dmrg_handle hs, dmrg_handle hd, int nterm, const dmrg_term* terms,
             p.b[0] = L[2] == 1 ? hs->dLocT.as<double>() : x;
             p.c[0] = y;
         }
-        HIP_TRY(hs, launch_zgemm(hs->dLocTiles.as<ZTile>() + L[0], L[1], p, 1, s));
+        HIP_TRY(hs, launch_zgemm(hs->dLocTiles.as<ZTile>() + L[0], L[1], p, 1, L[3], L[4], s));
     }
     return DMRG_OK;
 }

@@ -24,51 +24,48 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 // Both planes of one operand element (zero outside the matrix; imaginary part zero for real
-// operands).
+// operands); the access mode is a template parameter.
+template <int AM>
 __device__ __forceinline__ void load_a(const ZTile& t, const double* __restrict__ A, int i, int k,
                                        double& re, double& im) {
     re = 0.0;
     im = 0.0;
     if (i >= t.M || k >= t.K) return;
-    switch (t.amode) {
-        case ZM_COL: {
-            const int64_t at = t.aoff + (int64_t)k * t.lda + i;
-            re = A[at];
-            im = A[at + t.aim];
-            break;
-        }
-        case ZM_CT: {
-            const int64_t at = t.aoff + (int64_t)i * t.lda + k;
-            re = A[at];
-            im = -A[at + t.aim];
-            break;
-        }
-        case ZM_RCOL: re = A[t.aoff + (int64_t)k * t.lda + i]; break;
-        case ZM_RT: re = A[t.aoff + (int64_t)i * t.lda + k]; break;
-        default: re = i == k ? 1.0 : 0.0; break;
+    if constexpr (AM == ZM_COL) {
+        const int64_t at = t.aoff + (int64_t)k * t.lda + i;
+        re = A[at];
+        im = A[at + t.aim];
+    } else if constexpr (AM == ZM_CT) {
+        const int64_t at = t.aoff + (int64_t)i * t.lda + k;
+        re = A[at];
+        im = -A[at + t.aim];
+    } else if constexpr (AM == ZM_RCOL) {
+        re = A[t.aoff + (int64_t)k * t.lda + i];
+    } else if constexpr (AM == ZM_RT) {
+        re = A[t.aoff + (int64_t)i * t.lda + k];
+    } else {
+        re = i == k ? 1.0 : 0.0;
     }
 }
 
+template <int BM>
 __device__ __forceinline__ void load_b(const ZTile& t, const double* __restrict__ B, int k, int j,
                                        double& re, double& im) {
     re = 0.0;
     im = 0.0;
     if (j >= t.N || k >= t.K) return;
-    switch (t.bmode) {
-        case ZM_COL: {
-            const int64_t at = t.boff + (int64_t)j * t.ldb + k;
-            re = B[at];
-            im = B[at + t.bim];
-            break;
-        }
-        case ZM_CT: {            // transpose (no conjugate) of a complex column-major matrix
-            const int64_t at = t.boff + (int64_t)k * t.ldb + j;
-            re = B[at];
-            im = B[at + t.bim];
-            break;
-        }
-        case ZM_RCOL: re = B[t.boff + (int64_t)j * t.ldb + k]; break;
-        default: re = B[t.boff + (int64_t)k * t.ldb + j]; break;
+    if constexpr (BM == ZM_COL) {
+        const int64_t at = t.boff + (int64_t)j * t.ldb + k;
+        re = B[at];
+        im = B[at + t.bim];
+    } else if constexpr (BM == ZM_CT) {      // transpose (no conjugate) of a complex matrix
+        const int64_t at = t.boff + (int64_t)k * t.ldb + j;
+        re = B[at];
+        im = B[at + t.bim];
+    } else if constexpr (BM == ZM_RCOL) {
+        re = B[t.boff + (int64_t)j * t.ldb + k];
+    } else {
+        re = B[t.boff + (int64_t)k * t.ldb + j];
     }
 }
 
@@ -83,7 +80,9 @@ __device__ __forceinline__ d4 mma4(const double (&a)[4], const double (&b)[4], d
 // One wavefront per output tile; vector v = blockIdx.y.  Lane (g, r) = (lane / 16, lane % 16)
 // supplies rows (columns) r of the 16-row (16-column) blocks and the K indices 4 g + u of a
 // chunk of 16 (the u-th MFMA of the chunk takes index 4 g + u from lane group g, the same for
-// A and B); result element (g + 4 v, r) of a 16 x 16 block is accumulator component v.
+// A and B); result element (g + 4 v, r) of a 16 x 16 block is accumulator component v.  The
+// operands of the next chunk are loaded while the MFMAs of the current one run.
+template <int AM, int BM>
 __global__ __launch_bounds__(64) void k_zgemm(const ZTile* __restrict__ tiles, ZPtrs ptr) {
     const ZTile t = tiles[blockIdx.x];
     const int v = blockIdx.y;
@@ -99,27 +98,44 @@ __global__ __launch_bounds__(64) void k_zgemm(const ZTile* __restrict__ tiles, Z
             cre[mi][nj] = (d4){0.0, 0.0, 0.0, 0.0};
             cim[mi][nj] = (d4){0.0, 0.0, 0.0, 0.0};
         }
-    for (int k0 = 0; k0 < t.K; k0 += 16) {
-        double ar[2][4], ai[2][4], an[2][4], br[2][4], bi[2][4];
+    double ar[2][2][4], ai[2][2][4], br[2][2][4], bi[2][2][4];   // [buffer][half][u]
+    auto load = [&](int buf, int k0) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int k = k0 + 4 * g + u;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
-                load_a(t, A, t.m0 + 16 * h + r, k, ar[h][u], ai[h][u]);
-                an[h][u] = -ai[h][u];
-                load_b(t, B, k, t.n0 + 16 * h + r, br[h][u], bi[h][u]);
+                load_a<AM>(t, A, t.m0 + 16 * h + r, k, ar[buf][h][u], ai[buf][h][u]);
+                load_b<BM>(t, B, k, t.n0 + 16 * h + r, br[buf][h][u], bi[buf][h][u]);
             }
         }
+    };
+    auto mma = [&](int buf) {
+        double an[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) an[h][u] = -ai[buf][h][u];
 #pragma unroll
         for (int mi = 0; mi < 2; ++mi)
 #pragma unroll
             for (int nj = 0; nj < 2; ++nj) {
-                cre[mi][nj] = mma4(ar[mi], br[nj], cre[mi][nj]);
-                cre[mi][nj] = mma4(an[mi], bi[nj], cre[mi][nj]);
-                cim[mi][nj] = mma4(ar[mi], bi[nj], cim[mi][nj]);
-                cim[mi][nj] = mma4(ai[mi], br[nj], cim[mi][nj]);
+                cre[mi][nj] = mma4(ar[buf][mi], br[buf][nj], cre[mi][nj]);
+                cre[mi][nj] = mma4(an[mi], bi[buf][nj], cre[mi][nj]);
+                cim[mi][nj] = mma4(ar[buf][mi], bi[buf][nj], cim[mi][nj]);
+                cim[mi][nj] = mma4(ai[buf][mi], br[buf][nj], cim[mi][nj]);
             }
+    };
+    if (t.K > 0) {
+        load(0, 0);
+        for (int k0 = 0;; k0 += 32) {
+            if (k0 + 16 < t.K) load(1, k0 + 16);
+            mma(0);
+            if (k0 + 16 >= t.K) break;
+            if (k0 + 32 < t.K) load(0, k0 + 32);
+            mma(1);
+            if (k0 + 32 >= t.K) break;
+        }
     }
 #pragma unroll
     for (int mi = 0; mi < 2; ++mi)
@@ -143,6 +159,27 @@ __global__ __launch_bounds__(64) void k_zgemm(const ZTile* __restrict__ tiles, Z
         }
 }
 
+// Launch of one tile list whose tiles share the operand modes (am, bm).
+hipError_t launch_zgemm_modes(const ZTile* t, int n, const ZPtrs& p, int nvec, int am, int bm,
+                              hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const dim3 grid(n, nvec);
+#define DMRG_ZGEMM_CASE(A_, B_)                                                            \
+    if (am == A_ && bm == B_) {                                                            \
+        hipLaunchKernelGGL((k_zgemm<A_, B_>), grid, dim3(64), 0, s, t, p);                 \
+        return hipGetLastError();                                                          \
+    }
+    DMRG_ZGEMM_CASE(ZM_CT, ZM_COL)        // wave-function transformation, stage A
+    DMRG_ZGEMM_CASE(ZM_COL, ZM_CT)        // wave-function transformation, stage B
+    DMRG_ZGEMM_CASE(ZM_COL, ZM_RT)        // local operators: right products
+    DMRG_ZGEMM_CASE(ZM_COL, ZM_RCOL)
+    DMRG_ZGEMM_CASE(ZM_RCOL, ZM_COL)      // local operators: left products
+    DMRG_ZGEMM_CASE(ZM_RT, ZM_COL)
+    DMRG_ZGEMM_CASE(ZM_ID, ZM_COL)
+#undef DMRG_ZGEMM_CASE
+    return hipErrorInvalidValue;
+}
+
 __global__ __launch_bounds__(256) void k_zero(double* __restrict__ x, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x)
@@ -160,17 +197,18 @@ hipError_t launch_wft(const ZTile* tA, int nA, const ZPtrs& pA, const ZTile* tB,
         const int blocks = (int)std::min<int64_t>((tot + 255) / 256, 4096);
         hipLaunchKernelGGL(k_zero, dim3(blocks), dim3(256), 0, s, pA.c[0], tot);
     }
-    if (nA > 0) hipLaunchKernelGGL(k_zgemm, dim3(nA, nvec), dim3(64), 0, s, tA, pA);
-    if (nB > 0) hipLaunchKernelGGL(k_zgemm, dim3(nB, nvec), dim3(64), 0, s, tB, pB);
+    hipError_t e = launch_zgemm_modes(tA, nA, pA, nvec, ZM_CT, ZM_COL, s);
+    if (e == hipSuccess) e = launch_zgemm_modes(tB, nB, pB, nvec, ZM_COL, ZM_CT, s);
+    if (e != hipSuccess) return e;
     return hipGetLastError();
 }
 
 // One list of product tiles for nvec vectors (local operators, Sec. II.B: B|psi> and the
 // measured operators).
-hipError_t launch_zgemm(const ZTile* t, int n, const ZPtrs& p, int nvec, hipStream_t s) {
+hipError_t launch_zgemm(const ZTile* t, int n, const ZPtrs& p, int nvec, int am, int bm,
+                        hipStream_t s) {
     if (nvec < 1 || nvec > kWftMaxVec) return hipErrorInvalidValue;
-    if (n > 0) hipLaunchKernelGGL(k_zgemm, dim3(n, nvec), dim3(64), 0, s, t, p);
-    return hipGetLastError();
+    return launch_zgemm_modes(t, n, p, nvec, am, bm, s);
 }
 
 hipError_t launch_zero(double* x, int64_t n, hipStream_t s) {
