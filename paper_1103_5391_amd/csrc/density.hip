@@ -188,29 +188,46 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     double* __restrict__ Z = Zb + B.aoff;
     dv2* __restrict__ Y = Yb + B.aoff;
     __shared__ double dg[kDensMaxDim], e[kDensMaxDim];
-    __shared__ dv2 vv[kDensMaxDim], ww[kDensMaxDim];
+    __shared__ dv2 vv[kDensMaxDim], ww[kDensMaxDim], vv1[kDensMaxDim], ww1[kDensMaxDim];
     __shared__ dv2 pp[NT];
     __shared__ double red[3 * NT / 64];
     __shared__ int s_i0[2], s_cnt[2], s_done[2], s_path;
     __shared__ double s_lo, s_hi, s_tn;
     // ---------------------------------------------------------------- 1. tridiagonal
-    // Five barriers a step: the norm of the column (buffer red), the reflector, the product B v,
-    // the inner product w0^H v (buffer red2), and the hand-over of the updated trailing matrix.
-    // The two sums use separate buffers and each is reused only after further barriers.
+    // The update of step k is applied lazily, inside step k + 1's pass over the trailing
+    // matrix, which also forms that step's product B v: one read and one write of the trailing
+    // matrix per step.  The pending update is kept as (v, w0, al2) with w = w0 + al2 v, in one
+    // of two vector sets (step k writes set k & 1 and reads set (k - 1) & 1).  Four barriers a
+    // step: the norm of the column, the reflector, the hand-over after the pass (with the
+    // product's partial sums), and the inner product w0^H v.  The two sums use separate buffers,
+    // each reused only after further barriers.
     double* red2 = red + NT / 64;
+    dv2 al2p = (dv2){0.0, 0.0};                         // al2 of the pending update
     for (int k = 0; k + 1 < d; ++k) {
         const int m = d - k - 1;
         const int64_t ck = (int64_t)k * d;
+        dv2* vc = (k & 1) ? vv1 : vv;                   // this step's v and w0
+        dv2* wc = (k & 1) ? ww1 : ww;
+        const dv2* vq = (k & 1) ? vv : vv1;             // pending (step k - 1), rows k .. d-1
+        const dv2* wq = (k & 1) ? ww : ww1;
+        const bool pend = k > 0;
+        // pending correction of element (r, c) of the trailing matrix, rows/columns >= k
+        auto corr = [&](int r, int c) -> dv2 {
+            const dv2 vr = vq[r - k], vcn = vq[c - k];
+            const dv2 wr = wq[r - k] + cmul(al2p, vr), wcn = wq[c - k] + cmul(al2p, vcn);
+            return cmul(vr, cconj(wcn)) + cmul(wr, cconj(vcn));
+        };
         double part = 0.0;
         for (int i = tid; i < m; i += NT) {
-            const dv2 x = a[ck + k + 1 + i];
-            vv[i] = x;
+            dv2 x = a[ck + k + 1 + i];
+            if (pend) x -= corr(k + 1 + i, k);
+            vc[i] = x;
             if (i > 0) part += x.x * x.x + x.y * x.y;
         }
-        if (tid == 0) dg[k] = a[ck + k].x;
+        if (tid == 0) dg[k] = a[ck + k].x - (pend ? corr(k, k).x : 0.0);
         const double xn2 = wg_sum1<NT>(part, red);
         // every thread forms the reflector (the same arithmetic on the same values)
-        const dv2 al = vv[0];
+        const dv2 al = vc[0];
         dv2 tau = (dv2){0.0, 0.0}, sc = (dv2){0.0, 0.0};
         double beta = al.x;
         if (!(xn2 == 0.0 && al.y == 0.0)) {
@@ -224,51 +241,61 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
             e[k] = beta;
             a[ck + k] = tau;                                            // tau_k on the diagonal
         }
-        for (int i = tid; i < m; i += NT) {                             // own entries of vv
-            const dv2 v = i == 0 ? (dv2){1.0, 0.0} : cmul(vv[i], sc);
-            vv[i] = v;
+        for (int i = tid; i < m; i += NT) {                             // own entries
+            const dv2 v = i == 0 ? (dv2){1.0, 0.0} : cmul(vc[i], sc);
+            vc[i] = v;
             if (i > 0) a[ck + k + 1 + i] = v;                           // v_k below the subdiagonal
         }
         __syncthreads();                                                // v complete; red read
-        if (tau.x == 0.0 && tau.y == 0.0) continue;                     // H_k = I (uniform)
-        // w0 = tau B v: rows i, column groups g (G groups of the columns; G = 1 when a thread
-        // takes whole rows)
+        // pass over B = A[k+1:, k+1:]: apply the pending update, store, and form w0 = tau B v
+        // (rows i, column groups g; G = 1 when a thread takes whole rows)
         const int G = m >= NT ? 1 : NT / m;
         for (int it = tid; it < m * G; it += NT) {
             const int i = it % m, g = it / m;
             dv2 acc = (dv2){0.0, 0.0};
-            for (int j = g; j < m; j += G) acc += cmul(a[(int64_t)(k + 1 + j) * d + k + 1 + i], vv[j]);
+            for (int j = g; j < m; j += G) {
+                const int64_t at = (int64_t)(k + 1 + j) * d + k + 1 + i;
+                dv2 b = a[at];
+                if (pend) {
+                    b -= corr(k + 1 + i, k + 1 + j);
+                    a[at] = b;
+                }
+                acc += cmul(b, vc[j]);
+            }
             if (G > 1) pp[it] = acc;
-            else ww[i] = acc;
+            else wc[i] = acc;
         }
-        __syncthreads();
+        handover_barrier();
         double pr = 0.0, pi = 0.0;
         for (int i = tid; i < m; i += NT) {
             dv2 acc = (dv2){0.0, 0.0};
             if (G > 1)
                 for (int g = 0; g < G; ++g) acc += pp[g * m + i];
             else
-                acc = ww[i];
+                acc = wc[i];
             const dv2 w = cmul(tau, acc);
-            ww[i] = w;
-            const dv2 v = vv[i];                                        // conj(w) v
+            wc[i] = w;
+            const dv2 v = vc[i];                                        // conj(w) v
             pr += w.x * v.x + w.y * v.y;
             pi += w.x * v.y - w.y * v.x;
         }
         const dv2 dsum = wg_sum1c<NT>((dv2){pr, pi}, red2);
-        const dv2 al2 = cmul((dv2){-0.5 * tau.x, -0.5 * tau.y}, dsum);
-        // B -= v w^H + w v^H with w = w0 + al2 v, formed on the fly
-        for (int64_t it = tid; it < (int64_t)m * m; it += NT) {
-            const int i = (int)(it % m), j = (int)(it / m);
-            const int64_t at = (int64_t)(k + 1 + j) * d + k + 1 + i;
-            const dv2 wi = ww[i] + cmul(al2, vv[i]), wj = ww[j] + cmul(al2, vv[j]);
-            a[at] -= cmul(vv[i], cconj(wj)) + cmul(wi, cconj(vv[j]));
-        }
-        handover_barrier();
+        al2p = cmul((dv2){-0.5 * tau.x, -0.5 * tau.y}, dsum);
     }
-    if (tid == 0 && d > 0) {
-        dg[d - 1] = a[(int64_t)(d - 1) * d + d - 1].x;
-        e[d - 1] = 0.0;
+    if (d > 0) {
+        // the last diagonal element, with the update of the last step
+        const int k = d - 1;
+        const dv2* vq = (k & 1) ? vv : vv1;
+        const dv2* wq = (k & 1) ? ww : ww1;
+        dv2 c0 = (dv2){0.0, 0.0};
+        if (k > 0) {
+            const dv2 vr = vq[0], wr = wq[0] + cmul(al2p, vr);
+            c0 = cmul(vr, cconj(wr)) + cmul(wr, cconj(vr));
+        }
+        if (tid == 0) {
+            dg[d - 1] = a[(int64_t)(d - 1) * d + d - 1].x - c0.x;
+            e[d - 1] = 0.0;
+        }
     }
     __syncthreads();
     // ---------------------------------------------------------------- 2. eigenvalues
