@@ -235,10 +235,12 @@ int dmrg_ground_state(dmrg_handle h, const double* x0, double* y, int32_t kdim,
  *           real parts then imaginary parts, columns in the order of evals;
  *   kept    host int32 per sector: how many of its leading eigenvectors are kept;
  *   trunc_err  host (may be NULL): the sum of the discarded eigenvalues.
- * The eigen-decomposition is Householder tridiagonalisation, implicit QL and back-transformation
- * per sector.  The call waits for the stream.  DMRG_EINVAL for NULL arguments, nvec outside
- * [1, 16], keep < 0 or a system sector larger than 1024 states; DMRG_ENONFINITE for a weight that
- * is not finite or a QL iteration that does not converge (64 sweeps per eigenvalue). */
+ * The eigen-decomposition per sector is Householder tridiagonalisation, bisection for the
+ * eigenvalues, inverse iteration for the eigenvectors (implicit QL when close eigenvalues form a
+ * cluster larger than 8) and back-transformation.  The call waits for the stream.  DMRG_EINVAL
+ * for NULL arguments, nvec outside [1, 16], keep < 0 or a system sector larger than 1024 states;
+ * DMRG_ENONFINITE for a weight that is not finite or a QL iteration that does not converge (64
+ * sweeps per eigenvalue). */
 int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double* weights,
                           int32_t nvec, int32_t keep, double* evals, double* evecs, int32_t* kept,
                           double* trunc_err);
