@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <array>
 #include <cmath>
 #include <cstring>
@@ -40,6 +41,8 @@ hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const 
                       hipStream_t);
 hipError_t launch_zgemm(const ZTile*, int, const ZPtrs&, int, int, int, hipStream_t);
 hipError_t launch_zero(double*, int64_t, hipStream_t);
+hipError_t launch_local_mono(const SJob*, int, int64_t, const int*, const double*, const int*,
+                             const double*, const double*, int64_t, double*, int64_t, hipStream_t);
 hipError_t launch_zdot(const double*, const double*, int64_t, double*, int, hipStream_t);
 constexpr int kDotBlocks = 256;     // partial sums of one inner product
 int vec_blocks(int64_t n);
@@ -290,8 +293,20 @@ struct dmrg_ctx {
     std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
     // local operators (built on first use): raw operator blocks of both halves, the product
     // intermediate, the tile list and the inner-product partials
-    DevBuf dOpS, dOpE, dLocT, dLocZ, dLocTiles, dLocPart;
+    DevBuf dOpS, dOpE, dLocT, dLocZ, dLocTiles, dLocPart, dLocJobs;
     std::vector<int64_t> opS_base, opE_base;
+    // monomial operator blocks (at most one nonzero per row and column): per half the maps
+    // (input index -> output index) and values, and per operator and source sector the offsets
+    // of the map of the block (fwd) and of its transpose (bwd), -1 if the block is not monomial
+    DevBuf dMonoMap[2], dMonoVal[2];
+    std::vector<std::vector<int>> mono_fwd[2], mono_bwd[2];
+    // the last planned call (terms and destination), whose device lists are reused when the
+    // next call repeats it
+    std::vector<dmrg_term> loc_terms;
+    uint64_t loc_dst = 0;               // serial of the destination handle (0: none)
+    uint64_t serial = 0;                // unique per handle in the process (never reused)
+    std::vector<std::array<int, 5>> loc_launches;
+    int64_t loc_tsize = 0;
 };
 
 // A planned move of the centre (wave-function transformation): tile lists of its two stages,
@@ -772,6 +787,45 @@ int ensure_local_ops(dmrg_handle h) {
             all.insert(all.end(), op.data.begin(), op.data.end());
         }
         HIP_TRY(h, upload(side == 0 ? h->dOpS : h->dOpE, all, h->stream));
+        // monomial blocks: maps of the block and of its transpose
+        std::vector<int> maps;
+        std::vector<double> vals;
+        h->mono_fwd[side].assign(T.ops.size(), std::vector<int>(T.nsec, -1));
+        h->mono_bwd[side].assign(T.ops.size(), std::vector<int>(T.nsec, -1));
+        for (size_t o = 0; o < T.ops.size(); ++o) {
+            const HalfTable::Op& op = T.ops[o];
+            for (int p = 0; p < T.nsec; ++p) {
+                if (op.boff[p] < 0) continue;
+                const int q = T.find(T.nup[p] + op.dq[0], T.ndn[p] + op.dq[1]);
+                const int rows = T.dim[q], cols = T.dim[p];
+                const double* X = op.data.data() + op.boff[p];
+                std::vector<int> fwd(cols, -1), bwd(rows, -1);
+                std::vector<double> fv(cols, 0.0), bv(rows, 0.0);
+                bool mono = true;
+                for (int c = 0; c < cols && mono; ++c)
+                    for (int r = 0; r < rows; ++r) {
+                        const double v = X[(int64_t)c * rows + r];
+                        if (v == 0.0) continue;
+                        if (fwd[c] >= 0 || bwd[r] >= 0) {
+                            mono = false;
+                            break;
+                        }
+                        fwd[c] = r;
+                        bwd[r] = c;
+                        fv[c] = v;
+                        bv[r] = v;
+                    }
+                if (!mono) continue;
+                h->mono_fwd[side][o][p] = (int)maps.size();
+                maps.insert(maps.end(), fwd.begin(), fwd.end());
+                vals.insert(vals.end(), fv.begin(), fv.end());
+                h->mono_bwd[side][o][p] = (int)maps.size();
+                maps.insert(maps.end(), bwd.begin(), bwd.end());
+                vals.insert(vals.end(), bv.begin(), bv.end());
+            }
+        }
+        HIP_TRY(h, upload(h->dMonoMap[side], maps, h->stream));
+        HIP_TRY(h, upload(h->dMonoVal[side], vals, h->stream));
     }
     return DMRG_OK;
 }
@@ -809,7 +863,8 @@ bool factor_of(const HalfTable& T, const std::vector<int64_t>& base, int op, int
 // the right products T = X B^T (terms with an environment factor) then the left products
 // y += alpha A T; launches[i] = (first tile, count, which product).
 int plan_local(dmrg_handle hs, dmrg_handle hd, int nterm, const dmrg_term* terms,
-               std::vector<ZTile>& tiles, std::vector<std::array<int, 5>>& launches, int64_t& tsize) {
+               std::vector<ZTile>& tiles, std::vector<SJob>& jobs,
+               std::vector<std::array<int, 5>>& launches, int64_t& tsize) {
     const Plan& S = hs->plan;
     const Plan& D = hd->plan;
     auto bad = [&](const std::string& why) { return fail(hs, DMRG_EINVAL, "local operator: " + why); };
@@ -831,6 +886,40 @@ int plan_local(dmrg_handle hs, dmrg_handle hd, int nterm, const dmrg_term* terms
             for (int k = 0; k < 2; ++k) dq[k] += (tm.transE ? -1 : 1) * S.E.ops[tm.opE].dq[k];
         if (S.target[0] + dq[0] != D.target[0] || S.target[1] + dq[1] != D.target[1])
             return bad("the term does not map the source sector to the destination sector");
+        // monomial factors: every block this term uses maps one element to one element
+        auto mono_of = [&](int side, int op, int trans, int p) -> int {
+            if (op < 0) return -2;                              // identity
+            const HalfTable& T = side == 0 ? S.S : S.E;
+            if (!trans) return hs->mono_fwd[side][op][p];
+            const int src = T.find(T.nup[p] - T.ops[op].dq[0], T.ndn[p] - T.ops[op].dq[1]);
+            return src < 0 ? -1 : hs->mono_bwd[side][op][src];
+        };
+        bool mono = true;
+        std::vector<SJob> tj;
+        for (const PsiBlock& B : S.blocks) {
+            Factor fa, fb;
+            if (!factor_of(S.S, hs->opS_base, tm.opS, tm.transS, B.p, fa)) continue;
+            if (!factor_of(S.E, hs->opE_base, tm.opE, tm.transE, B.q, fb)) continue;
+            const int ob = fa.dst < (int)D.block_of_S.size() ? D.block_of_S[fa.dst] : -1;
+            if (ob < 0 || D.blocks[ob].q != fb.dst) continue;
+            const int ma = mono_of(0, tm.opS, tm.transS, B.p), mb = mono_of(1, tm.opE, tm.transE, B.q);
+            if (ma == -1 || mb == -1) {
+                mono = false;
+                break;
+            }
+            const double sign = (tm.fermionic && ((S.S.nup[B.p] + S.S.ndn[B.p]) & 1)) ? -1.0 : 1.0;
+            tj.push_back(SJob{B.off, D.blocks[ob].off, B.d, B.e, D.blocks[ob].d, ma < 0 ? -1 : ma,
+                              mb < 0 ? -1 : mb, 0, tm.coef * sign});
+        }
+        if (mono) {
+            if (!tj.empty()) {
+                int64_t mx = 0;
+                for (const SJob& j : tj) mx = std::max<int64_t>(mx, (int64_t)j.d * j.e);
+                launches.push_back({(int)jobs.size(), (int)tj.size(), 3, (int)mx, 0});
+                jobs.insert(jobs.end(), tj.begin(), tj.end());
+            }
+            continue;
+        }
         std::vector<ZTile> right, left;
         int64_t toff = 0;
         for (const PsiBlock& B : S.blocks) {
@@ -910,24 +999,46 @@ int plan_local(dmrg_handle hs, dmrg_handle hd, int nterm, const dmrg_term* terms
 
 // y (dst layout) = sum of the terms applied to x (src layout); asynchronous.  launches[i] =
 // (first tile, tiles, kind, A mode, B mode), kind 0 right products, 1 left products of the
-// intermediate, 2 left products of x (the tiles of a launch share their operand modes).
+// intermediate, 2 left products of x (the tiles of a launch share their operand modes), 3 a
+// term with monomial factors (first job, jobs, kind, largest block's element count).
 int run_local(dmrg_handle hs, dmrg_handle hd, int nterm, const dmrg_term* terms, const double* x,
               double* y) {
     int rc = ensure_local_ops(hs);
     if (rc) return rc;
-    std::vector<ZTile> tiles;
-    std::vector<std::array<int, 5>> launches;
-    int64_t tsize = 0;
-    rc = plan_local(hs, hd, nterm, terms, tiles, launches, tsize);
-    if (rc) return rc;
     hipStream_t s = hs->stream;
-    if ((int64_t)hs->dLocT.bytes < (int64_t)sizeof(double) * 2 * std::max<int64_t>(tsize, 1)) {
-        HIP_TRY(hs, hipStreamSynchronize(s));
-        HIP_TRY(hs, hs->dLocT.alloc(sizeof(double) * 2 * (size_t)std::max<int64_t>(tsize, 1)));
+    auto same = [](const dmrg_term& a, const dmrg_term& b) {
+        return a.coef == b.coef && a.opS == b.opS && a.transS == b.transS && a.opE == b.opE &&
+               a.transE == b.transE && a.fermionic == b.fermionic;
+    };
+    bool repeat = hs->loc_dst == hd->serial && (int)hs->loc_terms.size() == nterm;
+    for (int t = 0; repeat && t < nterm; ++t) repeat = same(hs->loc_terms[t], terms[t]);
+    if (!repeat) {
+        std::vector<ZTile> tiles;
+        std::vector<SJob> jobs;
+        std::vector<std::array<int, 5>> launches;
+        int64_t tsize = 0;
+        hs->loc_dst = 0;
+        rc = plan_local(hs, hd, nterm, terms, tiles, jobs, launches, tsize);
+        if (rc) return rc;
+        if ((int64_t)hs->dLocT.bytes < (int64_t)sizeof(double) * 2 * std::max<int64_t>(tsize, 1)) {
+            HIP_TRY(hs, hipStreamSynchronize(s));
+            HIP_TRY(hs, hs->dLocT.alloc(sizeof(double) * 2 * (size_t)std::max<int64_t>(tsize, 1)));
+        }
+        HIP_TRY(hs, upload(hs->dLocTiles, tiles, s));
+        HIP_TRY(hs, upload(hs->dLocJobs, jobs, s));
+        hs->loc_terms.assign(terms, terms + nterm);
+        hs->loc_launches = launches;
+        hs->loc_tsize = tsize;
+        hs->loc_dst = hd->serial;
     }
-    HIP_TRY(hs, upload(hs->dLocTiles, tiles, s));
     HIP_TRY(hs, launch_zero(y, 2 * hd->plan.n, s));
-    for (const auto& L : launches) {
+    for (const auto& L : hs->loc_launches) {
+        if (L[2] == 3) {            // monomial factors: one element to one element
+            HIP_TRY(hs, launch_local_mono(hs->dLocJobs.as<SJob>() + L[0], L[1], L[3], hs->dMonoMap[0].as<int>(),
+                                          hs->dMonoVal[0].as<double>(), hs->dMonoMap[1].as<int>(),
+                                          hs->dMonoVal[1].as<double>(), x, hs->plan.n, y, hd->plan.n, s));
+            continue;
+        }
         ZPtrs p{};
         if (L[2] == 0) {            // right products: x, environment blocks -> intermediate
             p.a[0] = x;
@@ -958,6 +1069,8 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
     *out = nullptr;
     dmrg_ctx* h = new (std::nothrow) dmrg_ctx();
     if (!h) return DMRG_ENOMEM;
+    static std::atomic<uint64_t> next_serial{1};
+    h->serial = next_serial.fetch_add(1);
     try {
         g_create_error.clear();
         std::string err = build_plan(problem, h->plan);

@@ -182,6 +182,18 @@ struct ZPtrs {                      // per vector: the A, B and C buffers of one
     double* c[kWftMaxVec];
 };
 
+// One source block of a local term whose factors have at most one nonzero per row and per
+// column (site operators on exact blocks and at the central sites): every element of the block
+// goes to one element of the destination, scaled.  amap / bmap: offsets of the factors' maps
+// (input index -> output index, -1 for none, with the value) in the system / environment
+// tables, -1 for the identity.
+struct SJob {
+    int64_t src, dst;       // block offsets in x and y (complex elements)
+    int32_t d, e, dout;     // source rows and columns, destination rows
+    int32_t amap, bmap, pad;
+    double alpha;
+};
+
 // Device state of one Krylov run on one problem.
 struct KState {
     double alpha[kMaxKrylov];

@@ -211,6 +211,43 @@ hipError_t launch_zgemm(const ZTile* t, int n, const ZPtrs& p, int nvec, int am,
     return launch_zgemm_modes(t, n, p, nvec, am, bm, s);
 }
 
+// Local term with monomial factors, work group (b, c) taking elements c kMonoChunk ... of source
+// block b (blocks in the first grid dimension, chunks in the second): element (i, j) goes to
+// (amap(i), bmap(j)) times alpha and the two factor values; the maps are one-to-one, so no two
+// elements of a term meet.  Real and imaginary planes at +nx / +ny.
+constexpr int64_t kMonoChunk = 2048;    // elements of a source block per work group
+__global__ __launch_bounds__(256) void k_local_mono(const SJob* __restrict__ jobs,
+                                                    const int* __restrict__ mapS,
+                                                    const double* __restrict__ valS,
+                                                    const int* __restrict__ mapE,
+                                                    const double* __restrict__ valE,
+                                                    const double* __restrict__ x, int64_t nx,
+                                                    double* __restrict__ y, int64_t ny) {
+    const SJob J = jobs[blockIdx.x];
+    const int64_t cnt = (int64_t)J.d * J.e;
+    const int64_t t0 = (int64_t)blockIdx.y * kMonoChunk;
+    const int64_t t1 = t0 + kMonoChunk < cnt ? t0 + kMonoChunk : cnt;
+    for (int64_t t = t0 + threadIdx.x; t < t1; t += blockDim.x) {
+        const int i = (int)(t % J.d), j = (int)(t / J.d);
+        const int io = J.amap < 0 ? i : mapS[J.amap + i];
+        const int jo = J.bmap < 0 ? j : mapE[J.bmap + j];
+        if (io < 0 || jo < 0) continue;
+        const double sc = J.alpha * (J.amap < 0 ? 1.0 : valS[J.amap + i]) * (J.bmap < 0 ? 1.0 : valE[J.bmap + j]);
+        const int64_t src = J.src + t, dst = J.dst + (int64_t)jo * J.dout + io;
+        y[dst] += sc * x[src];
+        y[ny + dst] += sc * x[nx + src];
+    }
+}
+
+hipError_t launch_local_mono(const SJob* jobs, int njobs, int64_t maxcnt, const int* mapS,
+                             const double* valS, const int* mapE, const double* valE,
+                             const double* x, int64_t nx, double* y, int64_t ny, hipStream_t s) {
+    if (njobs > 0 && maxcnt > 0)
+        hipLaunchKernelGGL(k_local_mono, dim3(njobs, (int)((maxcnt + kMonoChunk - 1) / kMonoChunk)), dim3(256),
+                           0, s, jobs, mapS, valS, mapE, valE, x, nx, y, ny);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero(double* x, int64_t n, hipStream_t s) {
     if (n > 0) {
         const int blocks = (int)std::min<int64_t>((n + 255) / 256, 4096);

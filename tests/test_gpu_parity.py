@@ -765,7 +765,44 @@ def test_local_operators_parity(env, name):
     g1, o1 = _gpu_and_oracle_term(pbx, ops, i, "n", coef=0.5)
     g2, o2 = _gpu_and_oracle_term(pbx, ops, j, "nn", coef=-2.0)
     check([g1, g2], [o1, o2], (0, 0))
-    say("  max rel err", worst)
+    # a repeated call reuses its planned lists; a new destination handle plans again
+    g1, o1 = _gpu_and_oracle_term(pbx, ops, i, "doublon_0")
+    check([g1], [o1], (1, 0))
+    check([g1], [o1], (1, 0))
+    tgt = (pb.target[0] + 1, pb.target[1])
+    handles[tgt][1].destroy()
+    pd2 = I.with_ops(pb, extra["S"], extra["E"], target=tgt)[0]
+    handles[tgt] = (pd2, L.dmrg_create(pd2))
+    check([g1], [o1], (1, 0))
+    say("  max rel err (monomial factors)", worst)
+    assert worst <= 1e-12
+    # dense operators (every element of a block nonzero): the product path
+    rng = np.random.default_rng(I.SEED_BASE + 97)
+    dS = I.BlockOp((0, 0), {p: rng.standard_normal((int(dd), int(dd))) for p, dd in enumerate(pb.S.space.dim)})
+    dE = I.BlockOp((1, 0))
+    for q in range(pb.E.space.nsec):
+        q2 = pb.E.space.shift(q, (1, 0))
+        if q2 is not None:
+            dE.blocks[q] = rng.standard_normal((int(pb.E.space.dim[q2]), int(pb.E.space.dim[q])))
+    pbd, iS2, iE2 = I.with_ops(pb, [dS], [dE])
+    hdn = L.dmrg_create(pbd)
+    worst = 0.0
+    for (gterms, oterms, dq) in (([(0.3, iS2[0], 0, -1, 0, 0)], [(0.3, dS, None, 0)], (0, 0)),
+                                 ([(1.0, -1, 0, iE2[0], 0, 1)], [(1.0, None, dE, 1)], (1, 0)),
+                                 ([(-0.7, iS2[0], 1, iE2[0], 0, 1)],
+                                  [(-0.7, I._transpose(dS, pb.S.space), dE, 1)], (1, 0))):
+        tgt = (pb.target[0] + dq[0], pb.target[1] + dq[1])
+        pdd = I.with_ops(pb, [dS], [dE], target=tgt)[0]
+        hdd = L.dmrg_create(pdd)
+        y = torch.full((2 * hdd.n,), float("nan"), dtype=torch.float64, device="cuda")
+        hdn.apply_local(hdd, gterms, xd, y)
+        ref = Ob.apply_terms(pbd, pdd, oterms, x)
+        got = _host(y)
+        assert np.all(np.isfinite(got))
+        worst = max(worst, float(np.max(np.abs(got - ref))) / max(1.0, float(np.max(np.abs(ref)))))
+        hdd.destroy()
+    hdn.destroy()
+    say("  max rel err (dense factors)", worst)
     assert worst <= 1e-12
     for st in sites:
         for k in ("n", "nn"):
