@@ -452,7 +452,8 @@ int group_prepare(Group& g, int kdim) {
     if (np > 1) HIP_TRY(h0, upload(g.dBmapR, bmapr, h0->stream));
     HIP_TRY(h0, upload(g.dProbs, pp, h0->stream));
     g.vg = VecGroup{g.dVP.as<VecProb>(), np > 1 ? g.dBmap.as<int>() : nullptr,
-                    np > 1 ? g.dBmapR.as<int>() : nullptr, np, b0, b0r, 4};
+                    np > 1 ? g.dBmapR.as<int>() : nullptr, np, b0, b0r, 4,
+                    np == 1 ? vp[0] : VecProb{}};
     g.prec = prec;
     g.gens.resize(np);
     for (int i = 0; i < np; ++i) g.gens[i] = g.hs[i]->ws[g.rhs[i]].gen;

@@ -143,6 +143,7 @@ struct VecGroup {
     int nprob, nblk;      // problems, blocks of a pass (sum of nb)
     int nblkr;            // blocks of a reduction pass (sum of nbr)
     int combine_mult;     // blocks per pass block of the non-chained combination
+    VecProb one;          // host copy of the descriptor when nprob == 1
 };
 
 // Reduced density matrix and truncation: one system sector (psi block) of the step.

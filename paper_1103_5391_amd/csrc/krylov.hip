@@ -97,12 +97,38 @@ __device__ __forceinline__ Where locate(const VecProb* vp, const int* bmap, int 
     return w;
 }
 
+// The per-iteration passes are instantiated twice: ONE for a lone problem, whose descriptor
+// comes by value with the kernel arguments (`one`), so the first data loads wait for no global
+// load of a table entry; otherwise the table vp and the block map.  (A run-time choice between
+// the two would read the descriptor through a generic pointer.)
+template <bool ONE>
+__device__ __forceinline__ Where locate1(const VecProb* vp, const int* bmap, const VecProb& one) {
+    Where w;
+    if constexpr (ONE) {
+        w.prob = 0;
+        w.p = one;
+    } else {
+        w.prob = bmap[blockIdx.x];
+        w.p = vp[w.prob];
+    }
+    w.lb = (int)blockIdx.x - w.p.b0;
+    w.nbt = w.p.nb;
+    return w;
+}
+
 // The same for the reduction pass, which has its own block decomposition (nbr blocks per problem,
 // several elements per thread, so that the per-block sums of its many values are amortised).
-__device__ __forceinline__ Where locate_red(const VecProb* vp, const int* bmapr) {
+template <bool ONE>
+__device__ __forceinline__ Where locate_red(const VecProb* vp, const int* bmapr,
+                                            const VecProb& one) {
     Where w;
-    w.prob = bmapr ? bmapr[blockIdx.x] : 0;
-    w.p = vp[w.prob];
+    if constexpr (ONE) {
+        w.prob = 0;
+        w.p = one;
+    } else {
+        w.prob = bmapr[blockIdx.x];
+        w.p = vp[w.prob];
+    }
     w.lb = (int)blockIdx.x - w.p.b0r;
     w.nbt = w.p.nbr;
     return w;
@@ -307,12 +333,14 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_start(const VecProb* vp, in
 // the first launch also accumulates u1^H w_raw, ||u1||^2 and ||w_raw||^2.  Partial rows of
 // launch q: kDVals values (a_c, b_c per slot, then c, d, e), unused values zero.
 // ---------------------------------------------------------------------------------------
-template <int NC, bool FIRST>
+template <int NC, bool FIRST, bool ONE>
 __global__ __launch_bounds__(kVecThreads) void k_dreduce(const VecProb* vp, const int* bmap, int j,
-                                                         int c0, int q) {
+                                                         int c0, int q, VecProb one) {
     constexpr int NV = 4 * NC + (FIRST ? 4 : 0);
-    const Where W = locate_red(vp, bmap);
-    if (W.p.st->broken) return;
+    const Where W = locate_red<ONE>(vp, bmap, one);
+    // No breakdown test: the pass writes only its partial rows, which the totals kernel ignores
+    // after a breakdown (the slots stay allocated, so every load is in bounds); a test here
+    // would put the flag's load before the first data load.
     const double* __restrict__ V0 = W.p.V + (int64_t)c0 * W.p.vstride;
     const double* __restrict__ u1 = W.p.V + (int64_t)j * W.p.vstride;
     const double* __restrict__ w = W.p.w;
@@ -382,10 +410,11 @@ __global__ __launch_bounds__(kVecThreads) void k_dreduce(const VecProb* vp, cons
 // value v = 4 x + w of the nq * kDVals values over the nbr partial rows (fixed order: lane l
 // adds rows l, l + 64, ... in turn, then the wavefront sum) into the state; many blocks, so the
 // partial rows are read in parallel across the chip rather than through one compute unit.
-__global__ __launch_bounds__(kVecThreads) void k_dsum(const VecProb* vp) {
-    const VecProb P = vp[blockIdx.y];
+template <bool ONE>
+__global__ __launch_bounds__(kVecThreads) void k_dsum(const VecProb* vp, VecProb one) {
+    const VecProb P = ONE ? one : vp[blockIdx.y];
     KState* st = P.st;
-    if (((const int __attribute__((address_space(1)))*)&st->broken)[0]) return;
+    const int broken = ((const int __attribute__((address_space(1)))*)&st->broken)[0];
     const int lane = threadIdx.x & 63;
     const int v = blockIdx.x * (kVecThreads / 64) + (threadIdx.x >> 6);
     const gcptr row = (gcptr)(P.part + (int64_t)v * kVecMaxBlocks);
@@ -400,7 +429,7 @@ __global__ __launch_bounds__(kVecThreads) void k_dsum(const VecProb* vp) {
 #pragma unroll
     for (int k = 0; k < kVecMaxBlocks / 64; ++k) acc += x[k];
     acc = wave_sum(acc);
-    if (lane == 0) st->red[v] = acc;
+    if (lane == 0 && !broken) st->red[v] = acc;
 }
 
 // Lanczos iteration j: the small algebra of the iteration (see the top of this file), run by
@@ -413,14 +442,16 @@ __global__ __launch_bounds__(kVecThreads) void k_dsum(const VecProb* vp) {
 // writes here.  Result in LDS: co[0][c] = a_c scale_c, co[1][c] = t_c scale_c,
 // co[2][c] = h_c scale_c (c < j, zero up to j8), cj = {scale_j, t_j scale_j, h_j scale_j}.
 // Returns false (block-uniform) when the basis has broken down.
-__device__ bool iteration_coefficients(KState* st, int j, int kdim, int nc0, bool writer, int j8,
-                                       double (&co)[3][2 * kMaxKrylov], double (&cj)[5]) {
+__device__ __forceinline__ bool iteration_coefficients(KState* st, int j, int kdim, int nc0,
+                                                       bool writer, int j8,
+                                       int broken, double (&co)[3][2 * kMaxKrylov], double (&cj)[5]) {
     const int tid = threadIdx.x, lane = tid & 63;
     __shared__ double al[kMaxKrylov], be[kMaxKrylov + 1];
     __shared__ double A[2 * kMaxKrylov], Bv[2 * kMaxKrylov], T[2 * kMaxKrylov + 2], sc[kMaxKrylov];
     __shared__ double cde[4], sh[4];
     __shared__ int ok;
     const gcptr red = (gcptr)st->red;
+    const double cdev = red[4 * nc0 + (tid & 3)];   // issued with the loads below
     for (int c = tid; c < j; c += blockDim.x) {
         const double s = ((gcptr)st->scale)[c];
         al[c] = ((gcptr)st->alpha)[c];
@@ -432,8 +463,9 @@ __device__ bool iteration_coefficients(KState* st, int j, int kdim, int nc0, boo
         Bv[2 * c] = s * red[base + 2];
         Bv[2 * c + 1] = s * red[base + 3];
     }
-    if (tid < 4) cde[tid] = red[4 * nc0 + tid];
+    if (tid < 4) cde[tid] = cdev;
     __syncthreads();
+    if (broken) return false;   // an earlier iteration broke down: nothing is written
     if (tid < 64) {
         // wave 0: |a|^2, u^H w_raw = c - a^H b, and the breakdown scale max(1, |alpha_c|, beta_c)
         // over the iterations before j (lane c holds slot c; j <= kMaxKrylov = 64)
@@ -536,35 +568,56 @@ __device__ bool iteration_coefficients(KState* st, int j, int kdim, int nc0, boo
 // Lanczos iteration j: update pass.  slot j <- u = u1 - sum_c a_c v_c; with v_j = u scale_j and
 // w = (w_raw - sum_{c<j} t_c v_c - t_j v_j) scale_j: slot j+1 <- w - sum_{c<j} h_c v_c - h_j v_j
 // (skipped after the last iteration).
+template <bool ONE>
 __global__ __launch_bounds__(kVecThreads) void k_dupdate(const VecProb* vp, const int* bmap, int j,
-                                                         int kdim, int nc0) {
-    const Where W = locate(vp, bmap, 1);
+                                                         int kdim, int nc0, VecProb one) {
+    const Where W = locate1<ONE>(vp, bmap, one);
     KState* st = W.p.st;
-    if (((const int __attribute__((address_space(1)))*)&st->broken)[0]) return;
+    const int broken = ((const int __attribute__((address_space(1)))*)&st->broken)[0];
     constexpr int G = 8;                       // basis slots loaded per round trip
     const int j8 = (j + G - 1) / G * G;
     __shared__ double co[3][2 * kMaxKrylov];
     __shared__ double cj[5];
-    if (!iteration_coefficients(st, j, kdim, nc0, W.lb == 0, j8, co, cj)) return;
-    const bool last = j == kdim - 1;
-    const double sj = cj[0], tjr = cj[1], tji = cj[2], hjr = cj[3], hji = cj[4];
     double* __restrict__ uj = W.p.V + (int64_t)j * W.p.vstride;
     double* __restrict__ un = W.p.V + (int64_t)(j + 1) * W.p.vstride;
     const double* __restrict__ V = W.p.V;
     const double* __restrict__ w = W.p.w;
     const int64_t n = W.p.n, vstride = W.p.vstride;
     const int64_t stride = (int64_t)W.nbt * blockDim.x;
-    if ((n & 1) == 0) {
-        for (int64_t i = 2 * ((int64_t)W.lb * blockDim.x + threadIdx.x); i < n; i += 2 * stride) {
+    const bool even = (n & 1) == 0;
+    // even length: every element pair's loads of the first G basis slots are issued ahead of
+    // its arithmetic, for the first pair before the coefficients, so that their latency
+    // overlaps the small algebra; the slots are allocated whatever the state, and nothing is
+    // stored after a breakdown
+    const int64_t i0 = 2 * ((int64_t)W.lb * blockDim.x + threadIdx.x);
+    d2v vr[G], vi[G];
+    auto head = [&](int64_t i) {
+        if (j > 0) {
+#pragma unroll
+            for (int k = 0; k < G; ++k) {
+                const double* v = V + (int64_t)min(k, j - 1) * vstride;
+                vr[k] = ld2(v, i);
+                vi[k] = ld2(v, n + i);
+            }
+        }
+    };
+    if (even && i0 < n) head(i0);
+    if (!iteration_coefficients(st, j, kdim, nc0, W.lb == 0, j8, broken, co, cj)) return;
+    const bool last = j == kdim - 1;
+    const double sj = cj[0], tjr = cj[1], tji = cj[2], hjr = cj[3], hji = cj[4];
+    if (even) {
+        for (int64_t i = i0; i < n; i += 2 * stride) {
+            if (i != i0) head(i);
             const d2v u0r = ld2(uj, i), u0i = ld2(uj, n + i), w0r = ld2(w, i), w0i = ld2(w, n + i);
             d2v ar = 0.0, ai = 0.0, tr = 0.0, ti = 0.0, hr = 0.0, hi = 0.0;
             for (int c0 = 0; c0 < j; c0 += G) {
-                d2v vr[G], vi[G];
+                if (c0 > 0) {
 #pragma unroll
-                for (int k = 0; k < G; ++k) {
-                    const double* v = V + (int64_t)min(c0 + k, j - 1) * vstride;
-                    vr[k] = ld2(v, i);
-                    vi[k] = ld2(v, n + i);
+                    for (int k = 0; k < G; ++k) {
+                        const double* v = V + (int64_t)min(c0 + k, j - 1) * vstride;
+                        vr[k] = ld2(v, i);
+                        vi[k] = ld2(v, n + i);
+                    }
                 }
                 __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -959,15 +1012,20 @@ hipError_t launch_start(const VecGroup& g, const double* x1, const double* const
 
 namespace {
 
-typedef void (*RedFn)(const VecProb*, const int*, int, int, int);
+typedef void (*RedFn)(const VecProb*, const int*, int, int, int, VecProb);
 
-template <bool FIRST, int... I>
+template <bool FIRST, bool ONE, int... I>
 constexpr auto red_table(std::integer_sequence<int, I...>) {
-    return std::array<RedFn, sizeof...(I)>{&k_dreduce<I, FIRST>...};
+    return std::array<RedFn, sizeof...(I)>{&k_dreduce<I, FIRST, ONE>...};
 }
 
-const auto kRedFirst = red_table<true>(std::make_integer_sequence<int, kDSlots + 1>{});
-const auto kRedMore = red_table<false>(std::make_integer_sequence<int, kDSlots + 1>{});
+// [one problem][slots of the launch]
+const std::array<RedFn, kDSlots + 1> kRedFirst[2] = {
+    red_table<true, false>(std::make_integer_sequence<int, kDSlots + 1>{}),
+    red_table<true, true>(std::make_integer_sequence<int, kDSlots + 1>{})};
+const std::array<RedFn, kDSlots + 1> kRedMore[2] = {
+    red_table<false, false>(std::make_integer_sequence<int, kDSlots + 1>{}),
+    red_table<false, true>(std::make_integer_sequence<int, kDSlots + 1>{})};
 
 }  // namespace
 
@@ -976,13 +1034,23 @@ hipError_t launch_lanczos_iter(const VecGroup& g, int j, int kdim, hipStream_t s
     const dim3 grid(g.nblk), gridr(g.nblkr), blk(kVecThreads);
     const int nq = j > kDSlots ? (j + kDSlots - 1) / kDSlots : 1;
     const int nc0 = min(j, kDSlots);
-    hipLaunchKernelGGL(kRedFirst[nc0], gridr, blk, 0, s, g.vp, g.bmapr, j, 0, 0);
+    // one problem (no block map): its descriptor travels by value
+    const int one = g.nprob == 1 && g.bmap == nullptr && g.bmapr == nullptr;
+    const VecProb* vp = g.vp;
+    hipLaunchKernelGGL(kRedFirst[one][nc0], gridr, blk, 0, s, vp, g.bmapr, j, 0, 0, g.one);
     for (int q = 1; q < nq; ++q) {
         const int nc = min(kDSlots, j - q * kDSlots);
-        hipLaunchKernelGGL(kRedMore[nc], gridr, blk, 0, s, g.vp, g.bmapr, j, q * kDSlots, q);
+        hipLaunchKernelGGL(kRedMore[one][nc], gridr, blk, 0, s, vp, g.bmapr, j, q * kDSlots, q,
+                           g.one);
     }
-    hipLaunchKernelGGL(k_dsum, dim3(nq * kDVals / (kVecThreads / 64), g.nprob), blk, 0, s, g.vp);
-    hipLaunchKernelGGL(k_dupdate, grid, blk, 0, s, g.vp, g.bmap, j, kdim, nc0);
+    const dim3 grids(nq * kDVals / (kVecThreads / 64), g.nprob);
+    if (one) {
+        hipLaunchKernelGGL(k_dsum<true>, grids, blk, 0, s, vp, g.one);
+        hipLaunchKernelGGL(k_dupdate<true>, grid, blk, 0, s, vp, g.bmap, j, kdim, nc0, g.one);
+    } else {
+        hipLaunchKernelGGL(k_dsum<false>, grids, blk, 0, s, vp, g.one);
+        hipLaunchKernelGGL(k_dupdate<false>, grid, blk, 0, s, vp, g.bmap, j, kdim, nc0, g.one);
+    }
     return hipGetLastError();
 }
 
