@@ -158,9 +158,7 @@ constexpr int kEigThreads = 512;    // threads of an eigen-decomposition work gr
 constexpr int kQlMaxSweeps = 64;    // QL sweeps per eigenvalue at most
 constexpr int kClusterMax = 8;      // inverse iteration when no cluster of eigenvalues is larger
 constexpr double kClusterGap = 1e-5;  // eigenvalues closer than this times |T| form a cluster
-constexpr int kEigChunk = 16;
-constexpr int kBt = 8;              // reflectors per block of the back-transformation
-constexpr int kBtChunk = 2;         // rows a lane reads together in the back-transformation       // loads a thread issues together in the rotation and
+constexpr int kEigChunk = 16;       // loads a thread issues together in the rotation and
                                     // reflector passes (their values do not depend on the stores)
 
 // Eigen-decomposition of rho_p, one work group per sector (LAPACK's path for Hermitian
@@ -585,98 +583,112 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
 }
 
 // Back-transformation Y = H_0 H_1 ... H_{d-2} Z of one sector's eigenvectors (one work group
-// per sector and range of kBackCols columns of Y; Z row-major, or column-major when bit 1 of
-// flags[blk] is set), kBt reflectors at a time: the product H_k1 ... H_k2 of a block is
-// I - V T V^H (V the block's reflectors as columns, staged in LDS; T upper triangular from the
-// taus on the diagonal of A and the Gram matrix V^H V), applied as Y - V (T (V^H Y)): one pass
-// over the rows for V^H Y and one for the update.  G lanes per column (a power of two inside a
-// wavefront): lane q takes the rows i = q mod G, the group adds its partial inner products by
-// shuffles.
+// per sector and range of back_cols(d) columns of Y; Z row-major, or column-major when bit 1 of
+// flags[blk] is set), BT reflectors at a time (8, or fewer for sectors above 256 states, so
+// that a block's reflectors fit in LDS): the product H_k1 ... H_k2 of a block is I - V T V^H (V
+// the block's reflectors as columns, staged in LDS; T upper triangular from the taus on the
+// diagonal of A and the Gram matrix V^H V), applied as Y - V (T (V^H Y)): one pass over the
+// rows for V^H Y and one for the update.  The block nearest the top is padded with identity
+// factors (zero reflector, tau = 0) so that every block has BT of them.  The work group's
+// columns of Y stay in LDS from the load of Z to the final store.  kBackLanes lanes per column:
+// lane q takes the rows i = q mod kBackLanes, the group adds its partial inner products by
+// shuffles.  T is built by one wavefront, lane r holding row r in registers.
 constexpr int kBackThreads = 256;
-constexpr int kBackCols = 32;
-__global__ __launch_bounds__(kBackThreads) void k_heig_back(const DBlock* __restrict__ blks,
-                                                            const dv2* __restrict__ A,
-                                                            const double* __restrict__ Zb,
-                                                            dv2* __restrict__ Yb,
-                                                            const int* __restrict__ flags) {
-    constexpr int NT = kBackThreads, BT = kBt;
-    const DBlock B = blks[blockIdx.x];
-    const int d = B.d, tid = threadIdx.x;
-    const int jb = blockIdx.y * kBackCols;
-    if (jb >= d) return;
-    const int je = jb + kBackCols < d ? jb + kBackCols : d;
-    const dv2* __restrict__ a = A + B.aoff;
-    const double* __restrict__ Z = Zb + B.aoff;
-    dv2* __restrict__ Y = Yb + B.aoff;
-    const bool colmajor = (flags[blockIdx.x] & 2) != 0;
-    const int64_t zr = colmajor ? 1 : d, zc = colmajor ? d : 1;
-    __shared__ dv2 Vs[2 * kDensMaxDim];                 // the block's reflectors, Vs[c d + i]
-    __shared__ dv2 Tt[BT * BT], Gm[BT * BT];
-    const int bt = 2 * kDensMaxDim / d < BT ? 2 * kDensMaxDim / d : BT;
-    int G = 1;
-    while (G < 8 && G * kBackCols * 2 <= NT) G *= 2;
-    const int q = tid % G, slots = NT / G;
-    const int wv = tid >> 6, ln = tid & 63;
-    for (int j = jb + tid / G; j < je; j += slots)
-        for (int i = q; i < d; i += G) Y[(int64_t)i * d + j] = (dv2){Z[i * zr + j * zc], 0.0};
-    for (int k2 = d - 2; k2 >= 0; k2 -= bt) {
-        const int k1 = k2 - bt + 1 > 0 ? k2 - bt + 1 : 0, nb = k2 - k1 + 1;
-        for (int t = tid; t < nb * d; t += NT) {
-            const int c = t / d, i = t % d, k = k1 + c;
-            Vs[t] = i <= k ? (dv2){0.0, 0.0} : (i == k + 1 ? (dv2){1.0, 0.0} : a[(int64_t)k * d + i]);
-        }
-        __syncthreads();
-        for (int t = wv; t < nb * nb; t += NT / 64) {   // one wavefront per Gram entry
-            const int c1 = t % nb, c2 = t / nb;
-            if (c1 >= c2) continue;
-            dv2 acc = (dv2){0.0, 0.0};
-            for (int i = k1 + c2 + 1 + ln; i < d; i += 64) acc += cmul(cconj(Vs[c1 * d + i]), Vs[c2 * d + i]);
+constexpr int kBackLanes = 8;       // lanes per column of Y
+constexpr int kBackCols = kBackThreads / kBackLanes;   // most columns of Y per work group
+constexpr int kBackLds = 6144;      // complex elements of the work group's columns in LDS (96 KB)
+__host__ __device__ constexpr int back_cols(int d) {
+    return d * kBackCols <= kBackLds ? kBackCols : kBackLds / d;
+}
+static_assert(kBackLds / kDensMaxDim >= 1, "one column of the largest sector fits");
+
+template <int BT>
+__device__ __forceinline__ void back_blocks(int d, int nc, const dv2* __restrict__ a,
+                                            dv2* __restrict__ Vs, dv2* __restrict__ Ys,
+                                            dv2* __restrict__ Tt, dv2* __restrict__ Gm,
+                                            dv2* __restrict__ taus) {
+    constexpr int NT = kBackThreads, L = kBackLanes;
+    constexpr int NP = BT * (BT - 1) / 2, PW = (NP + NT / 64 - 1) / (NT / 64);   // Gram pairs
+    // the caller takes BT = 8, 4, 2 for d up to 2 kDensMaxDim / BT: BT d elements fit in Vs
+    const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
+    const int q = tid % L, jl = tid / L;
+    for (int k2 = d - 2; k2 >= 0; k2 -= BT) {
+        const int k1 = k2 - BT + 1;                     // reflectors k1 .. k2 (k < 0: identity)
 #pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                acc.x += __shfl_xor(acc.x, o, 64);
-                acc.y += __shfl_xor(acc.y, o, 64);
-            }
-            if (ln == 0) Gm[c1 + BT * c2] = acc;
+        for (int c = 0; c < BT; ++c) {
+            const int k = k1 + c;
+            for (int i = tid; i < d; i += NT)
+                Vs[c * d + i] = (k < 0 || i <= k) ? (dv2){0.0, 0.0}
+                                : (i == k + 1 ? (dv2){1.0, 0.0} : a[(int64_t)k * d + i]);
         }
+        if (tid < BT) taus[tid] = k1 + tid < 0 ? (dv2){0.0, 0.0}
+                                               : a[(int64_t)(k1 + tid) * d + k1 + tid];
         __syncthreads();
-        if (tid == 0) {
-            for (int c = 0; c < nb; ++c) {
-                const dv2 tau = a[(int64_t)(k1 + c) * d + k1 + c];
-                for (int r = 0; r < c; ++r) {
-                    dv2 sum = (dv2){0.0, 0.0};
-                    for (int u = r; u < c; ++u) sum += cmul(Tt[r + BT * u], Gm[u + BT * c]);
-                    Tt[r + BT * c] = cmul((dv2){-tau.x, -tau.y}, sum);
+        {
+            // Gram entries G[c1][c2] (c1 < c2), pair p = wv + 4 s of wavefront wv: lanes over rows
+            dv2 acc[PW];
+            int pc1[PW], pc2[PW];
+#pragma unroll
+            for (int sp = 0; sp < PW; ++sp) {
+                const int p = wv + (NT / 64) * sp;
+                int c2 = 1, base = 0;                   // pairs with c2 = m start at m (m - 1) / 2
+                while (c2 < BT && base + c2 <= p) base += c2++;
+                pc2[sp] = c2;
+                pc1[sp] = p - base;
+                acc[sp] = (dv2){0.0, 0.0};
+                if (p < NP) {
+                    const int i0 = k1 + c2 + 1 > 0 ? k1 + c2 + 1 : 0;
+                    for (int i = i0 + ln; i < d; i += 64)
+                        acc[sp] += cmul(cconj(Vs[pc1[sp] * d + i]), Vs[c2 * d + i]);
                 }
-                Tt[c + BT * c] = tau;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1)
+#pragma unroll
+                for (int sp = 0; sp < PW; ++sp) {
+                    acc[sp].x += __shfl_xor(acc[sp].x, o, 64);
+                    acc[sp].y += __shfl_xor(acc[sp].y, o, 64);
+                }
+#pragma unroll
+            for (int sp = 0; sp < PW; ++sp)
+                if (ln == 0 && wv + (NT / 64) * sp < NP) Gm[pc1[sp] + BT * pc2[sp]] = acc[sp];
+        }
+        __syncthreads();
+        if (tid < 64) {
+            // T[r][c] = -tau_c sum_{r <= u < c} T[r][u] G[u][c] (r < c), T[c][c] = tau_c
+            const int r = tid;
+            dv2 tr[BT];
+#pragma unroll
+            for (int c = 0; c < BT; ++c) {
+                dv2 sum = (dv2){0.0, 0.0};
+#pragma unroll
+                for (int u = 0; u < c; ++u)
+                    if (u >= r) sum += cmul(tr[u], Gm[u + BT * c]);
+                const dv2 tau = taus[c];
+                tr[c] = r < c ? cmul((dv2){-tau.x, -tau.y}, sum) : (r == c ? tau : (dv2){0.0, 0.0});
+            }
+            if (r < BT) {
+#pragma unroll
+                for (int c = 0; c < BT; ++c) Tt[r + BT * c] = tr[c];
             }
         }
         __syncthreads();
-        const int i1 = k1 + 1 + ((q - (k1 + 1) % G) % G + G) % G;
-        for (int j0 = jb + tid / G; j0 < jb + kBackCols; j0 += slots) {
-            const int j = j0 < je ? j0 : je - 1;        // idle groups repeat the last column's
-            const bool own = j0 < je;                   // arithmetic without storing
+        if (jl < nc) {                                  // uniform over the lane group
+            dv2* __restrict__ y = Ys + jl * d;
+            const int i0 = k1 + 1 > 0 ? k1 + 1 : 0;     // rows above are not touched
+            const int i1 = i0 + ((q - i0 % L) % L + L) % L;
             dv2 w[BT];
 #pragma unroll
             for (int c = 0; c < BT; ++c) w[c] = (dv2){0.0, 0.0};
-            for (int i0 = i1; i0 < d; i0 += G * kBtChunk) {
-                dv2 yv[kBtChunk];
+            for (int i = i1; i < d; i += L) {
+                const dv2 yv = y[i];
 #pragma unroll
-                for (int u = 0; u < kBtChunk; ++u) {
-                    const int i = i0 + u * G;
-                    yv[u] = i < d ? Y[(int64_t)i * d + j] : (dv2){0.0, 0.0};
-                }
-#pragma unroll
-                for (int u = 0; u < kBtChunk; ++u) {
-                    const int i = i0 + u * G;
-                    if (i >= d) continue;
-#pragma unroll
-                    for (int c = 0; c < BT; ++c)
-                        if (c < nb) w[c] += cmul(cconj(Vs[c * d + i]), yv[u]);
-                }
+                for (int c = 0; c < BT; ++c) w[c] += cmul(cconj(Vs[c * d + i]), yv);
             }
 #pragma unroll
-            for (int c = 0; c < BT; ++c)
-                for (int o = 1; o < G; o <<= 1) {
+            for (int o = 1; o < L; o <<= 1)
+#pragma unroll
+                for (int c = 0; c < BT; ++c) {
                     w[c].x += __shfl_xor(w[c].x, o, 64);
                     w[c].y += __shfl_xor(w[c].y, o, 64);
                 }
@@ -685,31 +697,49 @@ __global__ __launch_bounds__(kBackThreads) void k_heig_back(const DBlock* __rest
             for (int r = 0; r < BT; ++r) {
                 u[r] = (dv2){0.0, 0.0};
 #pragma unroll
-                for (int c = 0; c < BT; ++c)
-                    if (r <= c && c < nb) u[r] += cmul(Tt[r + BT * c], w[c]);
+                for (int c = r; c < BT; ++c) u[r] += cmul(Tt[r + BT * c], w[c]);
             }
-            if (!own) continue;
-            for (int i0 = i1; i0 < d; i0 += G * kBtChunk) {
-                dv2 yv[kBtChunk];
+            for (int i = i1; i < d; i += L) {
+                dv2 yv = y[i];
 #pragma unroll
-                for (int uu = 0; uu < kBtChunk; ++uu) {
-                    const int i = i0 + uu * G;
-                    yv[uu] = i < d ? Y[(int64_t)i * d + j] : (dv2){0.0, 0.0};
-                }
-#pragma unroll
-                for (int uu = 0; uu < kBtChunk; ++uu) {
-                    const int i = i0 + uu * G;
-                    if (i >= d) continue;
-                    dv2 y = yv[uu];
-#pragma unroll
-                    for (int c = 0; c < BT; ++c)
-                        if (c < nb) y -= cmul(Vs[c * d + i], u[c]);
-                    Y[(int64_t)i * d + j] = y;
-                }
+                for (int c = 0; c < BT; ++c) yv -= cmul(Vs[c * d + i], u[c]);
+                y[i] = yv;
             }
         }
         __syncthreads();
     }
+}
+
+__global__ __launch_bounds__(kBackThreads) void k_heig_back(const DBlock* __restrict__ blks,
+                                                            const dv2* __restrict__ A,
+                                                            const double* __restrict__ Zb,
+                                                            dv2* __restrict__ Yb,
+                                                            const int* __restrict__ flags) {
+    constexpr int NT = kBackThreads;
+    const DBlock B = blks[blockIdx.x];
+    const int d = B.d, tid = threadIdx.x;
+    const int cols = back_cols(d);
+    const int jb = blockIdx.y * cols;
+    if (jb >= d) return;
+    const int nc = jb + cols < d ? cols : d - jb;       // columns jb .. jb + nc - 1
+    const dv2* __restrict__ a = A + B.aoff;
+    const double* __restrict__ Z = Zb + B.aoff;
+    dv2* __restrict__ Y = Yb + B.aoff;
+    const bool colmajor = (flags[blockIdx.x] & 2) != 0;
+    const int64_t zr = colmajor ? 1 : d, zc = colmajor ? d : 1;
+    __shared__ dv2 Vs[2 * kDensMaxDim];                 // the block's reflectors, Vs[c d + i]
+    __shared__ dv2 Ys[kBackLds];                        // Ys[jl d + i] = Y[i][jb + jl]
+    __shared__ dv2 Tt[8 * 8], Gm[8 * 8], taus[8];
+    for (int jl = 0; jl < nc; ++jl)
+        for (int i = tid; i < d; i += NT) Ys[jl * d + i] = (dv2){Z[i * zr + (jb + jl) * zc], 0.0};
+    if (d <= 2 * kDensMaxDim / 8)
+        back_blocks<8>(d, nc, a, Vs, Ys, Tt, Gm, taus);
+    else if (d <= 2 * kDensMaxDim / 4)
+        back_blocks<4>(d, nc, a, Vs, Ys, Tt, Gm, taus);
+    else
+        back_blocks<2>(d, nc, a, Vs, Ys, Tt, Gm, taus);
+    for (int jl = 0; jl < nc; ++jl)
+        for (int i = tid; i < d; i += NT) Y[(int64_t)i * d + jb + jl] = Ys[jl * d + i];
 }
 
 // Global rank of eigenvalue g among all ntot (larger first, equal values by sector then index:
@@ -796,8 +826,10 @@ hipError_t launch_density(const DBlock* blks, int nblk, const DTile* tiles, int 
                        static_cast<dv2*>(A));
     hipLaunchKernelGGL(k_heig, dim3(nblk), dim3(kEigThreads), 0, s, blks, static_cast<dv2*>(A), Z, S,
                        static_cast<dv2*>(V), ev, fail);
-    hipLaunchKernelGGL(k_heig_back, dim3(nblk, (maxd + kBackCols - 1) / kBackCols), dim3(kBackThreads), 0,
-                       s, blks, static_cast<const dv2*>(A), Z, static_cast<dv2*>(V), fail);
+    // work groups per sector: ceil(d / back_cols(d)) grows with d, so maxd gives the most
+    const int bcy = (maxd + back_cols(maxd) - 1) / back_cols(maxd);
+    hipLaunchKernelGGL(k_heig_back, dim3(nblk, bcy), dim3(kBackThreads), 0, s, blks,
+                       static_cast<const dv2*>(A), Z, static_cast<dv2*>(V), fail);
     hipLaunchKernelGGL(k_zero_int, dim3((ntot + 255) / 256), dim3(256), 0, s, kept, ntot);
     hipLaunchKernelGGL(k_rank, dim3((ntot + 255) / 256, (ntot + kRankChunk - 1) / kRankChunk), dim3(256), 0,
                        s, ev, ntot, kept);

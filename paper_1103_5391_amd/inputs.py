@@ -425,9 +425,10 @@ def synthetic_block(l: int, m: int, sites, edge_sites, rng, width: float = 8.0,
 
 
 def synthetic_problem(L: int, m: int, U: float, lattice_bonds, seed: int, name="",
-                      target=None) -> Problem:
+                      target=None, width: float = 8.0) -> Problem:
     """Superblock at the lattice centre from two synthetic truncated blocks of m states,
-    each enlarged by one exact site: m_S = m_E = 4m."""
+    each enlarged by one exact site: m_S = m_E = 4m.  width: spread of the sector weights
+    (smaller concentrates the states in fewer, larger sectors)."""
     rng = np.random.default_rng(seed)
     l = (L - 2) // 2
     s1, s2 = l, l + 1
@@ -436,8 +437,8 @@ def synthetic_problem(L: int, m: int, U: float, lattice_bonds, seed: int, name="
     pairs = [(i, j) for (i, j, t) in lattice_bonds] + [(j, i) for (i, j, t) in lattice_bonds]
     Ledge = sorted({i for (i, j) in pairs if i in Lsites and j not in Lsites})
     Redge = sorted({i for (i, j) in pairs if i in Rsites and j not in Rsites})
-    left = synthetic_block(l, m, Lsites, Ledge, rng)
-    right = synthetic_block(L - l - 2, m, Rsites, Redge, rng)
+    left = synthetic_block(l, m, Lsites, Ledge, rng, width=width)
+    right = synthetic_block(L - l - 2, m, Rsites, Redge, rng, width=width)
     all_sites = set(range(L))
     S = _enlarge(left, s1, U, lattice_bonds, site_first=False, keep_sites=all_sites)
     E = _enlarge(right, s2, U, lattice_bonds, site_first=True, keep_sites=all_sites)

@@ -63,6 +63,9 @@ def problem(name):
             _PROBLEMS[name] = I.synthetic_problem(8, 17, 4.0, I.chain_bonds(8), 47, name=name)
         elif name == "chain20_m150":
             _PROBLEMS[name] = I.synthetic_problem(20, 150, 4.0, I.chain_bonds(20), 12, name=name)
+        elif name == "ladder2x8_m700_big":   # concentrated sectors: one of 624 states, four of 330
+            _PROBLEMS[name] = I.synthetic_problem(16, 700, 8.0, I.ladder_bonds(8), 90, name=name,
+                                                  width=0.7)
         elif name == "ladder2x4_U10":
             _PROBLEMS[name] = I.exact_problem(8, 10.0, (4, 4), bonds=I.ladder_bonds(4, 1.0, 0.5))
         elif name == "chain4_exact":
@@ -486,13 +489,16 @@ def _decaying(pb, x, decades):
 
 @pytest.mark.parametrize("name,decades", [("chain12_m30", 0), ("chain8_exact", 0), ("chain8_m17_odd", 0),
                                           ("ladder16_m1000", 0), ("chain12_m30", 12),
-                                          ("ladder16_m1000", 14), ("ladder32_m2000", 0)])
+                                          ("ladder16_m1000", 14), ("ladder32_m2000", 0),
+                                          ("ladder2x8_m700_big", 0)])
 def test_density_truncate_parity(env, name, decades):
     """Density matrix of five weighted targets and its truncation against the oracle: every
     eigenvalue, the kept count of every sector and the truncation error; eigen-pairs (residual
     against the oracle's rho, orthonormality); the kept subspace of every sector (its
     projector), which is unique where the kept and discarded eigenvalues are apart.  Decaying
-    spectra (clusters of small eigenvalues) take the kernel's other tridiagonal solver."""
+    spectra (clusters of small eigenvalues) take the kernel's other tridiagonal solver.  The
+    sectors of ladder32_m2000 (up to 300 states) and ladder2x8_m700_big (330 and 624) take the
+    back-transformation's blocks of four and two reflectors."""
     from oracle import density as Dn
     torch, L = env
     say("density", name, "decades", decades)
