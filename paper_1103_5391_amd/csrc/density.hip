@@ -158,6 +158,7 @@ constexpr int kEigThreads = 512;    // threads of an eigen-decomposition work gr
 constexpr int kQlMaxSweeps = 64;    // QL sweeps per eigenvalue at most
 constexpr int kClusterMax = 8;      // inverse iteration when no cluster of eigenvalues is larger
 constexpr double kClusterGap = 1e-5;  // eigenvalues closer than this times |T| form a cluster
+constexpr int kSturmPts = 1;        // Sturm sequences one lane evaluates together in bisection
 constexpr int kEigChunk = 16;       // loads a thread issues together in the rotation and
                                     // reflector passes (their values do not depend on the stores)
 
@@ -298,7 +299,10 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     __syncthreads();
     // ---------------------------------------------------------------- 2. eigenvalues
     // Bisection on Sturm counts (the signs of the pivots of T - x I = L D L^T), one thread per
-    // eigenvalue, from the Gershgorin interval to rounding level.
+    // eigenvalue, from the Gershgorin interval to an absolute width of 2 eps |T| (|T| the
+    // Gershgorin bound): the reduction to T already moves the eigenvalues by about eps |T|, so
+    // narrower intervals around small eigenvalues would add rounds and no accuracy (LAPACK's
+    // bisection takes the same absolute tolerance by default).
     double* e2 = reinterpret_cast<double*>(pp);         // squared subdiagonal (pp is free now)
     double* lam = reinterpret_cast<double*>(ww);        // eigenvalues, ascending
     for (int i = tid; i + 1 < d; i += NT) e2[i] = e[i] * e[i];
@@ -316,8 +320,11 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     }
     __syncthreads();
     {
-        // GB lanes per eigenvalue (a power of two inside a wavefront) count at GB interior
-        // points of the interval and keep the piece that holds the eigenvalue
+        // GB lanes per eigenvalue (a power of two inside a wavefront), kSturmPts points per lane
+        // (independent Sturm sequences interleaved in one pass over T): the lanes count at
+        // GB kSturmPts interior points of the interval and keep the piece that holds the
+        // eigenvalue
+        constexpr int P = kSturmPts;
         int GB = 1;
         while (GB < 8 && 2 * GB * d <= NT) GB *= 2;
         const int qb = tid % GB, jslots = NT / GB;
@@ -326,27 +333,43 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
             const int j = j0 < d ? j0 : d - 1;
             double lo = s_lo, hi = s_hi;
             for (int it = 0; it < 256; ++it) {
-                if (hi - lo <= 4.440892098500626e-16 * fmax(fabs(lo), fabs(hi)) + 1e-300) break;
-                const double step = (hi - lo) / (GB + 1);
-                const double x = lo + step * (qb + 1);
-                double q = dg[0] - x;
-                int cnt = q < 0.0;
+                if (hi - lo <= 4.440892098500626e-16 * s_tn) break;
+                const double step = (hi - lo) / (GB * P + 1);
+                double x[P], q[P];
+                int cnt[P];
+#pragma unroll
+                for (int u = 0; u < P; ++u) {
+                    x[u] = lo + step * (qb * P + u + 1);
+                    q[u] = dg[0] - x[u];
+                    cnt[u] = q[u] < 0.0;
+                }
                 for (int i = 1; i < d; ++i) {
-                    if (fabs(q) < 1e-300) q = -1e-300;
-                    q = (dg[i] - x) - e2[i - 1] / q;
-                    cnt += q < 0.0;
+                    const double di = dg[i], ei = e2[i - 1];
+#pragma unroll
+                    for (int u = 0; u < P; ++u) {
+                        if (fabs(q[u]) < 1e-300) q[u] = -1e-300;
+                        // 1 / q: the hardware reciprocal and one Newton step (a few ulp; the
+                        // counts then place each eigenvalue within a few eps |T|)
+                        const double r0 = __builtin_amdgcn_rcp(q[u]);
+                        const double r = fma(fma(-q[u], r0, 1.0), r0, r0);
+                        q[u] = (di - x[u]) - ei * r;
+                        cnt[u] += q[u] < 0.0;
+                    }
                 }
                 double nlo = lo, nhi = hi;
                 bool found = false;
-                for (int u = 0; u < GB; ++u) {
-                    const int cu = __shfl(cnt, (tid & 63) - qb + u, 64);
-                    const double xu = lo + step * (u + 1);
-                    if (!found) {
-                        if (cu > j) {
-                            nhi = xu;
-                            found = true;
-                        } else {
-                            nlo = xu;
+                for (int l = 0; l < GB; ++l) {
+#pragma unroll
+                    for (int u = 0; u < P; ++u) {
+                        const int cu = __shfl(cnt[u], (tid & 63) - qb + l, 64);
+                        const double xu = lo + step * (l * P + u + 1);
+                        if (!found) {
+                            if (cu > j) {
+                                nhi = xu;
+                                found = true;
+                            } else {
+                                nlo = xu;
+                            }
                         }
                     }
                 }
