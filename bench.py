@@ -38,7 +38,7 @@ MEASURED_TRAFFIC = {
     "workload": "ladder16_m1000",
     "source": "paper_1103_5391_amd/csrc/gemm.hip",
     "source_sha256": "b77e06c0d246e917d715002a31ca0250cf2d152dac785479a1a2835ae704666d",
-    "bytes": 83.27e6 + 5.13e6,
+    "bytes": 83.62e6 + 5.12e6,
     "profile": "profiles/stage2_fp64_ladder16_m1000_kernel_stats.txt",
 }
 
