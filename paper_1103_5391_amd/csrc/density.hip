@@ -159,6 +159,7 @@ constexpr int kQlMaxSweeps = 64;    // QL sweeps per eigenvalue at most
 constexpr int kClusterMax = 8;      // inverse iteration when no cluster of eigenvalues is larger
 constexpr double kClusterGap = 1e-5;  // eigenvalues closer than this times |T| form a cluster
 constexpr int kSturmPts = 1;        // Sturm sequences one lane evaluates together in bisection
+constexpr int kHhLdsDim = 66;       // largest trailing matrix the Householder phase keeps in LDS
 constexpr int kEigChunk = 16;       // loads a thread issues together in the rotation and
                                     // reflector passes (their values do not depend on the stores)
 
@@ -192,6 +193,7 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     __shared__ double red[3 * NT / 64];
     __shared__ int s_i0[2], s_cnt[2], s_done[2], s_path;
     __shared__ double s_lo, s_hi, s_tn;
+    __shared__ dv2 tm[kHhLdsDim * kHhLdsDim];          // trailing matrix once it fits
     // ---------------------------------------------------------------- 1. tridiagonal
     // The update of step k is applied lazily, inside step k + 1's pass over the trailing
     // matrix, which also forms that step's product B v: one read and one write of the trailing
@@ -200,9 +202,16 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     // step: the norm of the column, the reflector, the hand-over after the pass (with the
     // product's partial sums), and the inner product w0^H v.  The two sums use separate buffers,
     // each reused only after further barriers.
+    // The trailing matrix is read and written through an accessor M(r, c): in place in A while
+    // it is larger than kHhLdsDim, then in LDS (copied once, with the pending update not yet
+    // applied), so the last steps make no round trip to L2.  The reflectors and taus always go
+    // to A, where the back-transformation reads them.
     double* red2 = red + NT / 64;
     dv2 al2p = (dv2){0.0, 0.0};                         // al2 of the pending update
-    for (int k = 0; k + 1 < d; ++k) {
+    auto gmat = [&](int r, int c) -> dv2& { return a[(int64_t)c * d + r]; };
+    int k0 = 0, L0 = 0;                                 // LDS copy of A[k0:, k0:], stride L0
+    auto lmat = [&](int r, int c) -> dv2& { return tm[(c - k0) * L0 + (r - k0)]; };
+    auto step = [&](const int k, auto&& M) {
         const int m = d - k - 1;
         const int64_t ck = (int64_t)k * d;
         dv2* vc = (k & 1) ? vv1 : vv;                   // this step's v and w0
@@ -218,12 +227,12 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
         };
         double part = 0.0;
         for (int i = tid; i < m; i += NT) {
-            dv2 x = a[ck + k + 1 + i];
+            dv2 x = M(k + 1 + i, k);
             if (pend) x -= corr(k + 1 + i, k);
             vc[i] = x;
             if (i > 0) part += x.x * x.x + x.y * x.y;
         }
-        if (tid == 0) dg[k] = a[ck + k].x - (pend ? corr(k, k).x : 0.0);
+        if (tid == 0) dg[k] = M(k, k).x - (pend ? corr(k, k).x : 0.0);
         const double xn2 = wg_sum1<NT>(part, red);
         // every thread forms the reflector (the same arithmetic on the same values)
         const dv2 al = vc[0];
@@ -253,11 +262,11 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
             const int i = it % m, g = it / m;
             dv2 acc = (dv2){0.0, 0.0};
             for (int j = g; j < m; j += G) {
-                const int64_t at = (int64_t)(k + 1 + j) * d + k + 1 + i;
-                dv2 b = a[at];
+                dv2& bm = M(k + 1 + i, k + 1 + j);
+                dv2 b = bm;
                 if (pend) {
                     b -= corr(k + 1 + i, k + 1 + j);
-                    a[at] = b;
+                    bm = b;
                 }
                 acc += cmul(b, vc[j]);
             }
@@ -280,6 +289,21 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
         }
         const dv2 dsum = wg_sum1c<NT>((dv2){pr, pi}, red2);
         al2p = cmul((dv2){-0.5 * tau.x, -0.5 * tau.y}, dsum);
+    };
+    int k = 0;
+    for (; k + 1 < d && d - k > kHhLdsDim; ++k) step(k, gmat);
+    bool inlds = false;
+    if (k + 1 < d) {
+        // the previous step's stores are complete and visible (its hand-over and sum barriers)
+        k0 = k;
+        L0 = d - k;
+        for (int t = tid; t < L0 * L0; t += NT) {
+            const int c = t / L0, r = t - c * L0;
+            tm[t] = a[(int64_t)(k0 + c) * d + k0 + r];
+        }
+        __syncthreads();
+        inlds = true;
+        for (; k + 1 < d; ++k) step(k, lmat);
     }
     if (d > 0) {
         // the last diagonal element, with the update of the last step
@@ -292,7 +316,7 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
             c0 = cmul(vr, cconj(wr)) + cmul(wr, cconj(vr));
         }
         if (tid == 0) {
-            dg[d - 1] = a[(int64_t)(d - 1) * d + d - 1].x - c0.x;
+            dg[d - 1] = (inlds ? lmat(d - 1, d - 1) : gmat(d - 1, d - 1)).x - c0.x;
             e[d - 1] = 0.0;
         }
     }
