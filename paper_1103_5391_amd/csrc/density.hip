@@ -20,9 +20,11 @@
 //               index) in pieces over a two-dimensional grid; kept if the rank is below m
 //   k_finish    per sector: eigenvalues in descending order with their eigenvectors, the number
 //               kept, and the sums of all and of the kept eigenvalues (fixed-order reductions)
-// The matrices live in global memory (L2-resident for the sector sizes of these workloads); the
-// waves of a work group hand them to each other through it, each wave waiting for its own stores
-// to complete before the barrier that hands them over.
+// The matrices live in global memory (L2-resident for the sector sizes of these workloads),
+// except the trailing matrix of the Householder phase once it fits in LDS and the columns a
+// back-transformation work group owns; the waves of a work group hand global data to each other
+// through it, each wave waiting for its own stores to complete before the barrier that hands
+// them over.
 #include <cstdint>
 
 #include "internal.hpp"
@@ -160,23 +162,24 @@ constexpr int kClusterMax = 8;      // inverse iteration when no cluster of eige
 constexpr double kClusterGap = 1e-5;  // eigenvalues closer than this times |T| form a cluster
 constexpr int kSturmPts = 1;        // Sturm sequences one lane evaluates together in bisection
 constexpr int kHhLdsDim = 66;       // largest trailing matrix the Householder phase keeps in LDS
-constexpr int kEigChunk = 16;       // loads a thread issues together in the rotation and
-                                    // reflector passes (their values do not depend on the stores)
+constexpr int kEigChunk = 16;       // loads a thread issues together in the QL rotation pass
+                                    // (their values do not depend on the stores)
 
-// Eigen-decomposition of rho_p, one work group per sector (LAPACK's path for Hermitian
-// matrices, in three phases):
+// Eigen-decomposition of rho_p up to the back-transformation, one work group per sector
+// (LAPACK's path for Hermitian matrices):
 //   1. Householder reduction to a real tridiagonal matrix: step k takes the reflector
 //      H_k = I - tau_k v_k v_k^H that maps column k below the diagonal to beta_k e_1 (beta_k
 //      real) and updates the trailing matrix B <- H_k^H B H_k as B - v w^H - w v^H with
 //      w = tau B v - (tau / 2)(w0^H v) v, w0 = tau B v.  v_k (v_k[0] = 1) is kept below the
 //      subdiagonal of A and tau_k on its diagonal.
-//   2. Implicit QL with shifts on the tridiagonal matrix (diagonal and subdiagonal in LDS):
-//      one thread runs the scalar recurrence and lists the plane rotations of a sweep; every
-//      thread applies them to its own rows of the real matrix Z (identity at the start).
-//   3. Back-transformation Y = H_0 H_1 ... H_{d-2} Z, one thread per column of Y (row-major),
-//      the reflectors read from A.
-// Eigenvalues (in QL order) go to ev, eigenvectors to the columns of Y.  A sweep count above
-// the limit sets fail[blk].
+//   2. Eigenvalues of the tridiagonal matrix by multisection on Sturm counts.
+//   3. Eigenvectors of the tridiagonal matrix into the real matrix Z: inverse iteration when no
+//      cluster of close eigenvalues has more than kClusterMax members (3a), else implicit QL
+//      with shifts (3b: one lane runs the scalar recurrence and lists the plane rotations of a
+//      sweep while the other wavefronts apply the previous sweep to their rows of Z).
+// Eigenvalues go to ev, eigenvectors to Z (row-major, or column-major after QL: bit 1 of
+// fail[blk]); k_heig_back applies the reflectors.  A QL sweep count above the limit sets bit 0
+// of fail[blk].
 __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__ blks,
                                                       dv2* __restrict__ A, double* __restrict__ Zb,
                                                       double* __restrict__ Sb, dv2* __restrict__ Yb,
