@@ -28,6 +28,8 @@
 // Every kernel runs over a table of problems (one entry for a single superblock, many for a
 // batch): block b of a pass works on problem bmap[b] (problem 0 when there is no map), as block
 // b - b0 of that problem's nb blocks; the small kernels run one block (or a few) per problem.
+// The three kernels of a Lanczos iteration have a second instance for a lone problem, which
+// takes its descriptor by value instead of from the table.
 // Grid-wide sums are deterministic: every block writes its partial sums and a later kernel adds
 // them in a fixed order (the kernel boundary orders the two; no device-wide fences or atomics:
 // on this chip a device-scope release writes back the XCD's L2 and costs more than a launch).
