@@ -161,6 +161,7 @@ constexpr int kQlMaxSweeps = 64;    // QL sweeps per eigenvalue at most
 constexpr int kClusterMax = 8;      // inverse iteration when no cluster of eigenvalues is larger
 constexpr double kClusterGap = 1e-5;  // eigenvalues closer than this times |T| form a cluster
 constexpr int kSturmPts = 1;        // Sturm sequences one lane evaluates together in bisection
+constexpr int kSturmRun = 8;        // Sturm steps whose LDS reads are issued together
 constexpr int kHhLdsDim = 66;       // largest trailing matrix the Householder phase keeps in LDS
 constexpr int kEigChunk = 16;       // loads a thread issues together in the QL rotation pass
                                     // (their values do not depend on the stores)
@@ -370,19 +371,30 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
                     q[u] = dg[0] - x[u];
                     cnt[u] = q[u] < 0.0;
                 }
-                for (int i = 1; i < d; ++i) {
-                    const double di = dg[i], ei = e2[i - 1];
+                // 1 / q: the hardware reciprocal and one Newton step (a few ulp; the counts then
+                // place each eigenvalue within a few eps |T|)
+                auto sturm = [&](double di, double ei) {
 #pragma unroll
                     for (int u = 0; u < P; ++u) {
                         if (fabs(q[u]) < 1e-300) q[u] = -1e-300;
-                        // 1 / q: the hardware reciprocal and one Newton step (a few ulp; the
-                        // counts then place each eigenvalue within a few eps |T|)
                         const double r0 = __builtin_amdgcn_rcp(q[u]);
                         const double r = fma(fma(-q[u], r0, 1.0), r0, r0);
                         q[u] = (di - x[u]) - ei * r;
                         cnt[u] += q[u] < 0.0;
                     }
+                };
+                int i = 1;
+                for (; i + kSturmRun <= d; i += kSturmRun) {   // LDS reads of a run issued first
+                    double dr[kSturmRun], er[kSturmRun];
+#pragma unroll
+                    for (int t = 0; t < kSturmRun; ++t) {
+                        dr[t] = dg[i + t];
+                        er[t] = e2[i - 1 + t];
+                    }
+#pragma unroll
+                    for (int t = 0; t < kSturmRun; ++t) sturm(dr[t], er[t]);
                 }
+                for (; i < d; ++i) sturm(dg[i], e2[i - 1]);
                 double nlo = lo, nhi = hi;
                 bool found = false;
                 for (int l = 0; l < GB; ++l) {
