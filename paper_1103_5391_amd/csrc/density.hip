@@ -39,6 +39,11 @@ __device__ __forceinline__ dv2 cmul(dv2 a, dv2 b) {
     return (dv2){a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 __device__ __forceinline__ dv2 cconj(dv2 a) { return (dv2){a.x, -a.y}; }
+// 1 / x: the hardware reciprocal and one Newton step (within a few ulp)
+__device__ __forceinline__ double recip(double x) {
+    const double r0 = __builtin_amdgcn_rcp(x);
+    return fma(fma(-x, r0, 1.0), r0, r0);
+}
 
 // Sum over a work group of NT threads, the same value returned to every thread; fixed order.
 template <int NT>
@@ -162,6 +167,7 @@ constexpr int kClusterMax = 8;      // inverse iteration when no cluster of eige
 constexpr double kClusterGap = 1e-5;  // eigenvalues closer than this times |T| form a cluster
 constexpr int kSturmPts = 1;        // Sturm sequences one lane evaluates together in bisection
 constexpr int kSturmRun = 8;        // Sturm steps whose LDS reads are issued together
+constexpr int kInvRun = 8;          // rows an inverse-iteration solve loads before storing
 constexpr int kHhLdsDim = 66;       // largest trailing matrix the Householder phase keeps in LDS
 constexpr int kEigChunk = 16;       // loads a thread issues together in the QL rotation pass
                                     // (their values do not depend on the stores)
@@ -453,8 +459,9 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
                     const double sub = e[i], nd = dg[i + 1] - x, nu = i + 2 < d ? e[i + 1] : 0.0;
                     if (fabs(dd) >= fabs(sub)) {
                         const double piv = fabs(dd) >= tiny ? dd : (dd < 0.0 ? -tiny : tiny);
-                        const double m = sub / piv;
-                        u0[at] = 1.0 / piv;
+                        const double ip = recip(piv);
+                        const double m = sub * ip;
+                        u0[at] = ip;
                         u1[at] = du;
                         u2[at] = 0.0;
                         lm[at] = m;
@@ -462,8 +469,9 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
                         dd = nd - m * du;
                         du = nu;
                     } else {
-                        const double m = dd / sub;
-                        u0[at] = 1.0 / sub;
+                        const double is = recip(sub);
+                        const double m = dd * is;
+                        u0[at] = is;
                         u1[at] = nd;
                         u2[at] = nu;
                         lm[at] = m;
@@ -479,33 +487,71 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
                     u1[at] = 0.0;
                     u2[at] = 0.0;
                 }
-                // start vector
-                for (int i = 0; i < d; ++i) Z[(int64_t)i * d + j] = cos(0.7 * i + j);
+                // start vector cos(0.7 i + j), by the recurrence
+                // cos(a + (i + 1) b) = 2 cos(b) cos(a + i b) - cos(a + (i - 1) b) (any fixed,
+                // generic vector serves; this one costs no call per element)
+                {
+                    const double c2 = 2.0 * cos(0.7);
+                    double cm = cos(j - 0.7), c0 = cos((double)j);
+                    for (int i = 0; i < d; ++i) {
+                        Z[(int64_t)i * d + j] = c0;
+                        const double cn = c2 * c0 - cm;
+                        cm = c0;
+                        c0 = cn;
+                    }
+                }
                 double scale = 1.0;
                 for (int rep = 0; rep < 3; ++rep) {
-                    // forward: P and L^-1 (the current entry carried in a register)
+                    // forward: P and L^-1 (the current entry carried in a register); a run of
+                    // kInvRun rows is loaded before any of it is stored (row i is stored only
+                    // after row i + 1 is read, so no load depends on the stores)
                     double cur = scale * Z[j];
-                    for (int i = 0; i + 1 < d; ++i) {
-                        const int64_t at = (int64_t)i * d + j;
-                        double nxt = scale * Z[at + d];
-                        if (pv[at] != 0.0) {
-                            const double t = cur;
-                            cur = nxt;
-                            nxt = t;
+                    for (int i0 = 0; i0 + 1 < d; i0 += kInvRun) {
+                        double zn[kInvRun], pw[kInvRun], lw[kInvRun];
+#pragma unroll
+                        for (int t = 0; t < kInvRun; ++t) {
+                            const int i = min(i0 + t, d - 2);
+                            const int64_t at = (int64_t)i * d + j;
+                            zn[t] = Z[at + d];
+                            pw[t] = pv[at];
+                            lw[t] = lm[at];
                         }
-                        Z[at] = cur;
-                        cur = nxt - lm[at] * cur;
+#pragma unroll
+                        for (int t = 0; t < kInvRun; ++t) {
+                            if (i0 + t + 1 >= d) break;
+                            double nxt = scale * zn[t];
+                            if (pw[t] != 0.0) {
+                                const double tt = cur;
+                                cur = nxt;
+                                nxt = tt;
+                            }
+                            Z[(int64_t)(i0 + t) * d + j] = cur;
+                            cur = nxt - lw[t] * cur;
+                        }
                     }
                     Z[(int64_t)(d - 1) * d + j] = cur;
-                    // backward: U^-1
+                    // backward: U^-1, runs of kInvRun rows loaded first
                     double y1 = 0.0, y2 = 0.0, nrm = 0.0;
-                    for (int i = d - 1; i >= 0; --i) {
-                        const int64_t at = (int64_t)i * d + j;
-                        const double y = (Z[at] - u1[at] * y1 - u2[at] * y2) * u0[at];
-                        Z[at] = y;
-                        nrm += y * y;
-                        y2 = y1;
-                        y1 = y;
+                    for (int i0 = d - 1; i0 >= 0; i0 -= kInvRun) {
+                        double zv[kInvRun], a0[kInvRun], a1[kInvRun], a2[kInvRun];
+#pragma unroll
+                        for (int t = 0; t < kInvRun; ++t) {
+                            const int i = max(i0 - t, 0);
+                            const int64_t at = (int64_t)i * d + j;
+                            zv[t] = Z[at];
+                            a0[t] = u0[at];
+                            a1[t] = u1[at];
+                            a2[t] = u2[at];
+                        }
+#pragma unroll
+                        for (int t = 0; t < kInvRun; ++t) {
+                            if (i0 - t < 0) break;
+                            const double y = (zv[t] - a1[t] * y1 - a2[t] * y2) * a0[t];
+                            Z[(int64_t)(i0 - t) * d + j] = y;
+                            nrm += y * y;
+                            y2 = y1;
+                            y1 = y;
+                        }
                     }
                     // against the cluster's earlier eigenvectors (modified Gram-Schmidt)
                     for (int k = j0; k < j; ++k) {
