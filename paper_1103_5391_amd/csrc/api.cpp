@@ -386,22 +386,21 @@ int ensure_operators(dmrg_handle h, int prec) {
     return DMRG_OK;
 }
 
-ProbPtrs make_ptrs(dmrg_handle h, int prec, const double* x, double* y, const double* xscale,
-                   const int* skip, int r = 0) {
+ProbPtrs make_ptrs(dmrg_handle h, int prec, const double* x, double* y, const int* skip,
+                   int r = 0) {
     ProbPtrs pp;
     pp.x = x;
     pp.y = y;
     pp.T = h->ws[r].dT.p;
     pp.Lops = h->dA[prec].p;
     pp.Rops = h->dR[prec].p;
-    pp.xscale = xscale;
     pp.skip = skip;
     return pp;
 }
 
 // y = H_sb x for one caller vector.
 int matvec_one(dmrg_handle h, const double* x, double* y) {
-    const ProbPtrs pp = make_ptrs(h, h->precision, x, y, nullptr, nullptr);
+    const ProbPtrs pp = make_ptrs(h, h->precision, x, y, nullptr);
     HIP_TRY(h, run_stages(h->lists, h->precision, nullptr, pp, h->stream));
     return DMRG_OK;
 }
@@ -445,7 +444,7 @@ int group_prepare(Group& g, int kdim) {
         for (int j = 0; j < kMaxKrylov; ++j)
             // the products take slot j as it is (not yet normalised): no input scale
             pp[(size_t)j * np + i] = make_ptrs(h, prec, j < W.kcap ? V + (int64_t)j * 2 * n : nullptr,
-                                               W.dW.as<double>(), nullptr, &st->broken, r);
+                                               W.dW.as<double>(), &st->broken, r);
     }
     HIP_TRY(h0, upload(g.dVP, vp, h0->stream));
     if (np > 1) HIP_TRY(h0, upload(g.dBmap, bmap, h0->stream));
@@ -1583,7 +1582,7 @@ int dmrg_batch_tst_chains(dmrg_batch b, const double* const* phi, double tau, in
 int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps, double* out) {
     if (!h || !x || !y || !out || reps < 1) return DMRG_EINVAL;
     const int prec = h->precision;
-    const ProbPtrs pp = make_ptrs(h, prec, x, y, nullptr, nullptr);
+    const ProbPtrs pp = make_ptrs(h, prec, x, y, nullptr);
     const int v = h->lists.variant;
     // stage 1 and stage 2 are idempotent (stage 1 rewrites the intermediate from x, stage 2
     // rewrites y from x and the intermediate): each is timed over back-to-back launches
@@ -1616,7 +1615,7 @@ int dmrg_autotune(dmrg_handle h, int32_t reps, double* out) {
     const size_t bytes = sizeof(double) * 2 * (size_t)h->plan.n;
     HIP_TRY(h, hipMemsetAsync(h->ws[0].dV.p, 0, bytes, h->stream));
     const ProbPtrs pp = make_ptrs(h, h->precision, h->ws[0].dV.as<double>(), h->ws[0].dW.as<double>(),
-                                  nullptr, nullptr);
+                                  nullptr);
     HIP_TRY(h, autotune_lists(h->lists, h->precision, nullptr, pp, h->stream, reps, out));
     return DMRG_OK;
 }

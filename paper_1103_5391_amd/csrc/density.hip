@@ -203,6 +203,7 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     __shared__ double red[3 * NT / 64];
     __shared__ int s_i0[2], s_cnt[2], s_done[2], s_path;
     __shared__ double s_lo, s_hi, s_tn;
+    __shared__ dv2 s_alpha;                             // alpha of the current reflector
     __shared__ dv2 tm[kHhLdsDim * kHhLdsDim];          // trailing matrix once it fits
     // ---------------------------------------------------------------- 1. tridiagonal
     // The update of step k is applied lazily, inside step k + 1's pass over the trailing
@@ -241,11 +242,15 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
             if (pend) x -= corr(k + 1 + i, k);
             vc[i] = x;
             if (i > 0) part += x.x * x.x + x.y * x.y;
+            else s_alpha = x;
         }
         if (tid == 0) dg[k] = M(k, k).x - (pend ? corr(k, k).x : 0.0);
         const double xn2 = wg_sum1<NT>(part, red);
-        // every thread forms the reflector (the same arithmetic on the same values)
-        const dv2 al = vc[0];
+        // every thread forms the reflector (the same arithmetic on the same values).  alpha
+        // is read from its own slot: vc[0] is overwritten with 1 below, and a wave that reached
+        // this read after wave 0's store would otherwise form its reflector from alpha = 1.
+        // s_alpha is next written in the following step, after the barriers below.
+        const dv2 al = s_alpha;
         dv2 tau = (dv2){0.0, 0.0}, sc = (dv2){0.0, 0.0};
         double beta = al.x;
         if (!(xn2 == 0.0 && al.y == 0.0)) {

@@ -39,7 +39,6 @@ __device__ __forceinline__ void stage1_tile(const Tile& tl, const S1Block& B, co
     using frag_t = typename P::frag_t;
     const int lane = threadIdx.x;
     const int g = lane >> 4, r = lane & 15;
-    const double xs = P_.xscale ? *P_.xscale : 1.0;
     const double* __restrict__ X = P_.x;
     const int K = B.K;
     const int nch = (K + P::CK - 1) / P::CK;
@@ -79,17 +78,18 @@ __device__ __forceinline__ void stage1_tile(const Tile& tl, const S1Block& B, co
 #pragma unroll
             for (int nj = 0; nj < NJ; ++nj) acc[mi][nj] = P::mma(fa[mi], fb[nj], acc[mi][nj]);
     };
-    // two register buffers; the prefetch is unconditional (chunk index clamped) so that no
-    // load sits under a branch and the compiler waits only for the buffer being consumed
+    // two register buffers, the next chunk always in flight (as in the stage-2 loop)
     load(0, a[0], b[0]);
-    for (int c = 0;; c += 2) {
-        load(min(c + 1, nch - 1), a[1], b[1]);
+    int c = 0;
+    for (; c + 1 < nch; c += 2) {
+        load(c + 1, a[1], b[1]);
+        __builtin_amdgcn_sched_barrier(0);
         mma(a[0], b[0]);
-        if (c + 1 >= nch) break;
         load(min(c + 2, nch - 1), a[0], b[0]);
+        __builtin_amdgcn_sched_barrier(0);
         mma(a[1], b[1]);
-        if (c + 2 >= nch) break;
     }
+    if (c < nch) mma(a[0], b[0]);
     ws_t* __restrict__ T = static_cast<ws_t*>(P_.T);
     const View tv = B.T;
 #pragma unroll
@@ -104,7 +104,7 @@ __device__ __forceinline__ void stage1_tile(const Tile& tl, const S1Block& B, co
                 if (m < B.M) {
                     const int pl = m >= tv.split;
                     T[tv.off + pl * tv.poff + (int64_t)n * tv.ld + (m - pl * tv.split)] =
-                        (ws_t)(acc[mi][nj][v] * xs);
+                        (ws_t)acc[mi][nj][v];
                 }
             }
         }
@@ -145,16 +145,21 @@ __device__ __forceinline__ void kloop(typename P::acc_t (&acc)[MI][NJ], int c0, 
 #pragma unroll
             for (int nj = 0; nj < NJ; ++nj) acc[mi][nj] = P::mma(fa[mi], fb[nj], acc[mi][nj]);
     };
-    // unconditional (clamped) prefetch, as in stage 1
+    // Two register buffers, one exit test per pair of chunks: the chunk after the one being
+    // multiplied is always in flight (the last prefetch is clamped and unused).  The
+    // scheduling barriers keep each prefetch ahead of the products it overlaps; without them
+    // the compiler moved the loads down to their products and waited for them there.
     load(c0, a0, b0);
-    for (int c = c0;; c += 2 * step) {
-        load(min(c + step, last), a1, b1);
+    int c = c0;
+    for (; c + step <= last; c += 2 * step) {
+        load(c + step, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
         mma(a0, b0);
-        if (c + step > last) break;
         load(min(c + 2 * step, last), a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
         mma(a1, b1);
-        if (c + 2 * step > last) break;
     }
+    if (c <= last) mma(a0, b0);   // odd count: chunk c is in a0
 }
 
 // One 16 MI x 16 NJ output tile (MI = 2, or 1 for a half-height tile) per work group of NW
@@ -172,7 +177,6 @@ __device__ __forceinline__ void stage2_tile(const Tile& tl, const S2Block& B,
     const int lane = threadIdx.x & 63;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
     const int g = lane >> 4, r = lane & 15;
-    const double xs = P_.xscale ? *P_.xscale : 1.0;
     const int split = B.Y.split;   // columns per plane of the output and of every source
     const ws_t* __restrict__ Tws = static_cast<const ws_t*>(P_.T);
 
@@ -195,8 +199,7 @@ __device__ __forceinline__ void stage2_tile(const Tile& tl, const S2Block& B,
     for (int mi = 0; mi < MI; ++mi)
 #pragma unroll
         for (int nj = 0; nj < NJ; ++nj) zero<P>(acc[mi][nj]);
-    // pass 1: segment 0, the diagonal H_S term, reads the block itself from the input vector;
-    // its scale is applied before anything else adds in
+    // pass 1: segment 0, the diagonal H_S term, reads the block itself from the input vector
     const Segment s0 = segs[B.seg0];
     const int nch0 = (s0.K + P::CK - 1) / P::CK;
     {
@@ -217,12 +220,6 @@ __device__ __forceinline__ void stage2_tile(const Tile& tl, const S2Block& B,
             }
         };
         kloop<P, MI, NJ>(acc, wave, NW, nch0, load);
-#pragma unroll
-        for (int mi = 0; mi < MI; ++mi)
-#pragma unroll
-            for (int nj = 0; nj < NJ; ++nj)
-#pragma unroll
-                for (int v = 0; v < 4; ++v) acc[mi][nj][v] *= xs;
     }
     // pass 2: every workspace chunk of segments 1.. in one pipelined stream per wave (global
     // chunk c goes to wave c mod NW), its source view read from a per-chunk table in LDS (built

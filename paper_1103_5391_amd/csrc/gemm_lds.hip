@@ -105,7 +105,6 @@ __global__ __launch_bounds__(256, 3) void stage1_lds(const S1Block* __restrict__
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
     const int g = lane >> 4, r = lane & 15;
-    const double xs = P_.xscale ? *P_.xscale : 1.0;
     const int mval = min(4, (B.M - it.m0 + 15) / 16), nval = min(4, (B.N - it.n0 + 15) / 16);
     const int vm = clamp2(mval - 2 * wm), vn = clamp2(nval - 2 * wn);
     const int K = B.K, nch = (K + P::CK - 1) / P::CK;
@@ -157,7 +156,7 @@ __global__ __launch_bounds__(256, 3) void stage1_lds(const S1Block* __restrict__
                 if (m < B.M) {
                     const int pl = m >= tv.split;
                     T[tv.off + pl * tv.poff + (int64_t)n * tv.ld + (m - pl * tv.split)] =
-                        (ws_t)(acc[mi][nj][v] * xs);
+                        (ws_t)acc[mi][nj][v];
                 }
             }
         }
@@ -186,7 +185,6 @@ __global__ __launch_bounds__(256, 3) void stage2_lds(const S2Block* __restrict__
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int wm = wave >> 1, wn = wave & 1;
     const int g = lane >> 4, r = lane & 15;
-    const double xs = P_.xscale ? *P_.xscale : 1.0;
     const int split = B.Y.split;   // columns per plane of the output and of every source
     const ws_t* __restrict__ Tws = static_cast<const ws_t*>(P_.T);
     const int mval = min(4, (B.M - it.m0 + 15) / 16), nval = min(4, (B.N - it.n0 + 15) / 16);
@@ -238,8 +236,6 @@ __global__ __launch_bounds__(256, 3) void stage2_lds(const S2Block* __restrict__
     };
     auto store_x = [&](int d) {
         if (a_on) sm.A[d][wave][lane] = ra[d];
-#pragma unroll
-        for (int t = 0; t < P::KPL; ++t) xb[d][t] *= xs;
         sm.B[d][bp][bl] = P::from(xb[d]);
     };
     auto load_t = [&](int c, int d) {

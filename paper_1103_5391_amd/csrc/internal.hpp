@@ -118,7 +118,6 @@ struct ProbPtrs {
     void* T;                // workspace (FP64 or FP32 elements)
     const void* Lops;       // packed left factors (stage 2), precision dependent type
     const void* Rops;       // packed right factors (stage 1)
-    const double* xscale;   // scale applied to x on load (nullptr = 1)
     const int* skip;        // nonzero: skip all work of this problem (nullptr = never)
 };
 
