@@ -205,16 +205,28 @@ def batch_section(L, I, torch, steps, warmup, count=64):
 
 def drift_section(L, I, torch, name="ladder32_m2000", steps=50):
     """Config-5 drift: the ladder 2x32 at m = 2000 evolved by `steps` Krylov steps (kdim 20,
-    tau 0.05) in every arithmetic from the same normalised complex psi; per step the norm and
-    the energy Re <psi|H|psi> (FP64 products).  Reports the largest drift from step 0 and the
-    largest deviation from the FP64 run."""
+    tau 0.05) in every arithmetic from the holon-doublon-like start psi = (c+_{s1 up} P_S) (x)
+    c_{s2 dn} psi0 (psi0 a seeded normalised complex vector of the half-filled sector; psi,
+    normalised, lies in (N_up + 1, N_dn - 1) = (33, 31)), prepared by the library's local
+    operators; per step the norm and the energy Re <psi|H|psi> (FP64 products).  Reports the
+    largest drift from step 0 and the largest deviation from the FP64 run."""
     import numpy as np
     w = I.WORKLOADS[name]
-    pb = I.make_workload(name)
+    pb0 = I.make_workload(name)
+    s1, s2 = pb0.Sblk.sites[-1], pb0.Eblk.sites[0]
+    ops_s, ops_e = I.site_ops(pb0.Sblk, s1), I.site_ops(pb0.Eblk, s2)
+    psrc, iS, iE = I.with_ops(pb0, [ops_s["cdag_0"]], [ops_e["c_1"]])
+    tgt = (pb0.target[0] + 1, pb0.target[1] - 1)
+    pb = I.with_ops(pb0, [ops_s["cdag_0"]], [ops_e["c_1"]], target=tgt)[0]
+    hs = L.dmrg_create(psrc)
     he = L.dmrg_create(pb)                    # FP64 energies
     hp = L.dmrg_create(pb)
     n = hp.n
-    psi0 = torch.from_numpy(I.random_psi(n, np.random.default_rng(I.SEED_BASE + w["seed"] + 1000))).cuda()
+    x0 = torch.from_numpy(I.random_psi(hs.n, np.random.default_rng(I.SEED_BASE + w["seed"] + 1000))).cuda()
+    psi0 = torch.empty(2 * n, dtype=torch.float64, device="cuda")
+    hs.apply_local(hp, [(1.0, iS[0], 0, iE[0], 0, 1)], x0, psi0)
+    psi0 /= torch.linalg.vector_norm(psi0)
+    hs.destroy()
     hv = torch.empty_like(psi0)
 
     def energy(v):
@@ -251,7 +263,8 @@ def drift_section(L, I, torch, name="ladder32_m2000", steps=50):
     hp.destroy()
     he.destroy()
     return {"workload": name, "steps": steps, "kdim": w["kdim"], "tau": w["tau"], "energy0": e0,
-            "per_arithmetic": out}
+            "initial_state": "(c+_{s1 up} P_S) x c_{s2 dn} psi0, normalised",
+            "sector": list(tgt), "n_complex": n, "per_arithmetic": out}
 
 
 def main():

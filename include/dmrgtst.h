@@ -33,10 +33,15 @@
  *   a void* hipStream_t; NULL = the default stream).
  *
  * Errors
- *   Every function returns a dmrg_status (0 = success, negative = error).  No C++ exception
- *   crosses the boundary.  dmrg_last_error() returns a description of the last failure on a
- *   handle.  Lanczos breakdown is not an error: it is reported in dmrg_krylov_info and the
- *   result is then exact.
+ *   Every function returns a dmrg_status (0 = success, negative = error, positive = a result
+ *   that is returned but carries a warning).  No C++ exception crosses the boundary.
+ *   dmrg_last_error() returns a description of the last failure on a handle.  Lanczos breakdown
+ *   is not an error: it is reported in dmrg_krylov_info and the result is then exact.
+ *   Device memory: every buffer a handle allocates (operators, work lists, Krylov workspaces,
+ *   the buffers of the next rows) is charged to it; if the environment variable
+ *   DMRG_MAX_WORKSPACE holds a byte count when dmrg_create runs, an allocation that would take
+ *   the handle above it fails with DMRG_ENOMEM before any memory is requested.  Buffers of a
+ *   batch are charged to its first handle.
  *
  * Threads: a handle is used by one host thread at a time.
  */
@@ -58,7 +63,9 @@ enum dmrg_status {
     DMRG_ENOMEM = -2,     /* device or host allocation failed                             */
     DMRG_EHIP = -3,       /* a HIP runtime call failed                                    */
     DMRG_ENONFINITE = -4, /* non-finite value met where finite input is required          */
-    DMRG_ESTATE = -5      /* call not valid in the handle's current state                 */
+    DMRG_ESTATE = -5,     /* call not valid in the handle's current state                 */
+    DMRG_WNOTCONV = 1     /* iteration stopped before its tolerance; the last iterate is
+                             returned (dmrg_ground_state)                                  */
 };
 
 /* Arithmetic of the block products (the Lanczos recurrence, the reorthogonalisation, the
@@ -136,11 +143,20 @@ typedef struct {
     const dmrg_term* terms;
 } dmrg_problem;
 
-/* Krylov diagnostics (host struct).  k_eff: Lanczos vectors used in the last step (kdim
- * unless breakdown); k_eff_min over all steps; beta0 = ||x|| of the first step; beta_last =
- * last computed beta of the last step; err_est = beta_k |c_{k-1}(tau)| of the last step (an
- * upper estimate of the step's truncation error, 0 after breakdown); breakdown = 1 if any
- * step broke down (invariant subspace found, result exact). */
+/* Krylov diagnostics (host struct; Sec. II.A: the basis of n_l = kdim Lanczos vectors, which
+ * stops early at an invariant subspace).  Filled by the call:
+ *   k_eff      Lanczos vectors used in the last step (kdim unless breakdown);
+ *   k_eff_min  over all steps of the call;
+ *   beta0      ||x|| of the first step;  beta_last = last computed beta of the last step;
+ *   err_est    beta_k |c_{k-1}(tau)| of the last step (an upper estimate of the step's
+ *              truncation error, 0 after breakdown); dmrg_ground_state: the residual estimate;
+ *   breakdown  1 if any step broke down (invariant subspace found, result exact);
+ *   converged  dmrg_ground_state: 1 if the residual estimate met tol (else the call returns
+ *              DMRG_WNOTCONV); 1 for the other calls.
+ * Set by the caller (zero-initialise the struct if unused):
+ *   k_eff_steps  NULL, or a host array receiving the Lanczos vectors of every step: nsteps
+ *              entries for dmrg_krylov_expm, one per basis (at most max_restarts) for
+ *              dmrg_ground_state, one for the time-step-targeting calls. */
 typedef struct {
     int32_t k_eff;
     int32_t k_eff_min;
@@ -148,17 +164,42 @@ typedef struct {
     double beta_last;
     double err_est;
     int32_t breakdown;
+    int32_t converged;
+    int32_t* k_eff_steps;
 } dmrg_krylov_info;
 
 /* Builds the sector tables, the block work lists and the packed device copies of all
  * operators (Sec. IV: the Hamiltonian connections).  stream: hipStream_t or NULL.
  * Errors: DMRG_EINVAL for malformed input (unsorted or repeated sectors, non-positive
- * dims, out-of-range op indices, terms whose dq do not cancel, empty target sector),
- * DMRG_ENOMEM, DMRG_EHIP.  On error *out is set to NULL. */
+ * dims, out-of-range op indices, terms whose dq do not cancel, empty target sector) or a
+ * DMRG_MAX_WORKSPACE value that is not a decimal byte count, DMRG_ENOMEM (device memory
+ * exhausted, or the handle's buffers above DMRG_MAX_WORKSPACE), DMRG_EHIP.  On error *out is
+ * set to NULL and dmrg_last_error(NULL) describes the failure. */
 int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out);
 
 /* Releases all device memory of the handle (waits for its stream).  NULL is ignored. */
 void dmrg_destroy(dmrg_handle h);
+
+/* Host-only planning (no device memory, no HIP call): builds the plan dmrg_create would build
+ * for problem and packs its FP64 operators, and reports
+ *   n, nblk         complex length of a vector and number of psi blocks;
+ *   flops, flops_executed   as dmrg_flops and dmrg_flops_executed would;
+ *   create_bytes    device bytes dmrg_create allocates for the handle;
+ *   krylov_bytes    device bytes the handle's first dmrg_krylov_expm or dmrg_tst_targets call
+ *                   with kdim Lanczos vectors adds (basis slots, work vector, partial sums,
+ *                   state, iteration tables; a call that sets info->k_eff_steps adds 4 bytes
+ *                   per step, one with input checking on 8 bytes)
+ * (callers size DMRG_MAX_WORKSPACE or batches with it).  Errors as dmrg_create (DMRG_EINVAL,
+ * described by dmrg_last_error(NULL); kdim outside [1, 64] is DMRG_EINVAL too). */
+typedef struct {
+    int64_t n;
+    int32_t nblk;
+    double flops;
+    double flops_executed;
+    int64_t create_bytes;
+    int64_t krylov_bytes;
+} dmrg_plan_info;
+int dmrg_plan_stats(const dmrg_problem* problem, int32_t kdim, dmrg_plan_info* out);
 
 /* Vector layout: *n = complex length (a vector is 2n doubles); *nblk = number of blocks.
  * If the array pointers are non-NULL they receive, per block: off = offset inside a plane,
@@ -166,9 +207,18 @@ void dmrg_destroy(dmrg_handle h);
 int dmrg_psi_layout(dmrg_handle h, int64_t* n, int32_t* nblk, int64_t* off, int32_t* rows,
                     int32_t* cols, int32_t* secS, int32_t* secE);
 
-/* Algorithmic flops of one H_sb.psi for one complex vector: both real planes, two flops per
- * multiply-add, non-zero blocks only, the contraction order the library uses. */
+/* Algorithmic flops of one H_sb.psi for one complex vector (Sec. IV, the Hamiltonian
+ * connections): both real planes, two flops per multiply-add, terms with a non-zero operator
+ * block only, and for every connection term the cheaper of the two contraction orders
+ * (A X) B^T and A (X B^T); no padding.  Throughput figures divide this count by time. */
 int dmrg_flops(dmrg_handle h, double* flops);
+
+/* Flops the block products execute for one H_sb.psi, counted like dmrg_flops but in the order
+ * the kernels use (the right product X B^T first for every term: stage 1 forms the right
+ * products of each source block, stage 2 sums the left products into each output block).
+ * At least dmrg_flops; equal when the right-first order is the cheaper one for every term
+ * (for instance when both halves have the same sector dimensions). */
+int dmrg_flops_executed(dmrg_handle h, double* flops);
 
 /* Selects the block-product arithmetic; converted operator copies are built on first use and
  * cached.  A change of arithmetic waits for the handle's stream (the intermediate workspace is
@@ -191,6 +241,14 @@ int dmrg_autotune(dmrg_handle h, int32_t reps, double* out);
 /* Changes the stream all later work of the handle is ordered on. */
 int dmrg_set_stream(dmrg_handle h, void* stream);
 
+/* Input checking (off after dmrg_create).  When on, dmrg_matvec, dmrg_krylov_expm,
+ * dmrg_tst_targets, dmrg_tst_chains, dmrg_ground_state and dmrg_batch_tst_targets first count
+ * the NaN and infinite values of their input vectors on the device (one pass, then a wait for
+ * the stream) and return DMRG_ENONFINITE without computing if there is any.  Without checking,
+ * a Krylov call whose info is requested still returns DMRG_ENONFINITE when a step starts from a
+ * vector with a non-finite norm (that step is then run as a zero vector). */
+int dmrg_set_check_finite(dmrg_handle h, int32_t enable);
+
 /* y = H_sb x for nvec vectors stored back to back (2n doubles each), device pointers.
  * x and y must not overlap.  Asynchronous on the handle's stream. */
 int dmrg_matvec(dmrg_handle h, const double* x, double* y, int32_t nvec);
@@ -198,7 +256,9 @@ int dmrg_matvec(dmrg_handle h, const double* x, double* y, int32_t nvec);
 /* y = (exp(-i tau H_sb))^nsteps x: nsteps Krylov steps of size kdim (1 <= kdim <= 64), each
  * from a fresh Lanczos basis of the current vector (Sec. II.A, Eq. lanczosevolution2).
  * x, y: device vectors; y may equal x.  If info is non-NULL the call waits for the stream
- * and fills it; otherwise it is asynchronous. */
+ * and fills it (and info->k_eff_steps, if set, with nsteps entries); otherwise it is
+ * asynchronous.  DMRG_EINVAL for kdim outside [1, 64] or nsteps < 0; DMRG_ENONFINITE for a
+ * non-finite tau, or as described at dmrg_set_check_finite. */
 int dmrg_krylov_expm(dmrg_handle h, const double* x, double* y, double tau, int32_t kdim,
                      int32_t nsteps, dmrg_krylov_info* info);
 
@@ -217,8 +277,9 @@ int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim,
  * beta_kdim |z_{kdim-1}| = ||H y - E y|| is at most tol max(1, |E|).  y: the unit Ritz vector
  * (device, 2n doubles; may equal x0).  energy, restarts: NULL or host scalars receiving E and the
  * bases used; info as in dmrg_krylov_expm (err_est is the last residual estimate).  The call
- * waits for the stream after every basis (to test convergence).  DMRG_EINVAL for kdim outside
- * [1, 64], max_restarts < 1 or a negative tol. */
+ * waits for the stream after every basis (to test convergence).  Returns DMRG_WNOTCONV (with y,
+ * energy and info of the last basis, info->converged = 0) when max_restarts bases end above
+ * tol.  DMRG_EINVAL for kdim outside [1, 64], max_restarts < 1 or a negative tol. */
 int dmrg_ground_state(dmrg_handle h, const double* x0, double* y, int32_t kdim,
                       int32_t max_restarts, double tol, double* energy, int32_t* restarts,
                       dmrg_krylov_info* info);
@@ -374,8 +435,8 @@ int dmrg_batch_tst_chains(dmrg_batch b, const double* const* phi, double tau, in
 /* Measurement hook: one product y = H_sb x (one vector), then reps launches of the right-product
  * stage back to back and reps launches of the left-product stage back to back, with HIP events
  * on the handle's stream around each run; waits for them.  out[0], out[1]: average
- * milliseconds per launch of the two stages; out[2], out[3]: their algorithmic flops.  y holds
- * H_sb x afterwards. */
+ * milliseconds per launch of the two stages; out[2], out[3]: the flops each stage executes
+ * (their sum is dmrg_flops_executed).  y holds H_sb x afterwards. */
 int dmrg_profile_matvec(dmrg_handle h, const double* x, double* y, int32_t reps, double* out);
 
 /* Static description of a status code. */

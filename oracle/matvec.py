@@ -185,9 +185,10 @@ def superblock_matrix(pb, matvec=matvec_sector) -> np.ndarray:
 
 def flop_count(pb) -> int:
     """Algorithmic flops of one H_sb . psi for complex psi with real operators, cheaper
-    contraction order per connection term, blocks never densified or padded:
+    contraction order per connection term, blocks never densified or padded, terms whose
+    operator block is exactly zero not counted (they contribute nothing):
     F = 2 * sum_blocks [2 d_p^2 e_q + 2 d_p e_q^2
-                        + sum_terms 2 min(d' d e + d' e e', d e e' + d' d e')]."""
+                        + sum_nonzero_terms 2 min(d' d e + d' e e', d e e' + d' d e')]."""
     lay, n = layout(pb)
     qof = {p: q for (p, q, r, c, off) in lay}
     dS, dE = pb.S.space.dim, pb.E.space.dim
@@ -198,7 +199,9 @@ def flop_count(pb) -> int:
         for (p, q, r, c, off) in lay:
             A = _op_block(pb.S.space, pb.S.ops[a], p, ta)
             B = _op_block(pb.E.space, pb.E.ops[b], q, tb)
-            if A is None or B is None or A[0] not in qof:
+            if A is None or B is None or A[0] not in qof or qof[A[0]] != B[0]:
+                continue
+            if not (np.any(A[1]) and np.any(B[1])):
                 continue
             r2, c2 = int(dS[A[0]]), int(dE[B[0]])
             F += 2 * 2 * min(r2 * r * c + r2 * c * c2, r * c * c2 + r2 * r * c2)

@@ -31,8 +31,9 @@ hipError_t launch_stage2_lds(int, const S2Block*, const Segment*, const LItem2*,
 hipError_t launch_start(const VecGroup&, const double*, const double* const*, int, int,
                         hipStream_t);
 hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
-hipError_t launch_tridiag(const VecGroup&, const double*, int, hipStream_t);
-hipError_t launch_lowest(const VecGroup&, hipStream_t);
+hipError_t launch_tridiag(const VecGroup&, const double*, int, int*, int, hipStream_t);
+hipError_t launch_lowest(const VecGroup&, int*, int, hipStream_t);
+hipError_t launch_count_nonfinite(const double*, int64_t, int*, hipStream_t);
 hipError_t launch_density(const DBlock*, int, const DTile*, int, const double* const*, const double*,
                           int, int64_t, void*, void*, double*, double*, int*, int, double*, int, int,
                           int*, double*, double*, int*, double*, hipStream_t);
@@ -52,21 +53,46 @@ int red_blocks(int64_t n);
 // stages (the faster at the sizes measured so far).
 constexpr int DMRG_GEMM_DEFAULT = 0;
 
+// Device memory of one handle: a cap (DMRG_MAX_WORKSPACE bytes, read by dmrg_create; no cap
+// without it) and the bytes its buffers hold.  The entry points make their handle's budget the
+// current one for the calling thread; DevBuf allocations are charged to the current budget and
+// refused (hipErrorOutOfMemory, reported as DMRG_ENOMEM) beyond its cap, before hipMalloc.
+struct Budget {
+    size_t cap = SIZE_MAX;
+    size_t used = 0;
+};
+thread_local Budget* g_budget = nullptr;
+struct BudgetScope {
+    Budget* prev;
+    explicit BudgetScope(Budget* b) : prev(g_budget) { g_budget = b; }
+    ~BudgetScope() { g_budget = prev; }
+};
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;
+    Budget* owner = nullptr;      // budget the bytes are charged to
     ~DevBuf() { release(); }
     void release() {
         if (p) (void)hipFree(p);
+        if (owner) owner->used -= bytes;
         p = nullptr;
         bytes = 0;
+        owner = nullptr;
     }
     hipError_t alloc(size_t b) {
         release();
         if (b == 0) b = 8;
+        Budget* bg = g_budget;
+        if (bg && (b > bg->cap || bg->used > bg->cap - b)) return hipErrorOutOfMemory;
         hipError_t e = hipMalloc(&p, b);
-        if (e == hipSuccess) bytes = b;
-        else p = nullptr;
+        if (e == hipSuccess) {
+            bytes = b;
+            owner = bg;
+            if (bg) bg->used += b;
+        } else {
+            p = nullptr;
+        }
         return e;
     }
     template <typename T>
@@ -276,8 +302,13 @@ struct dmrg_batch_ctx {
 };
 
 struct dmrg_ctx {
+    Budget budget;      // first member: destroyed after every buffer charged to it
     Plan plan;
     hipStream_t stream = nullptr;
+    bool check_finite = false;          // check input vectors before a call (set_check_finite)
+    DevBuf dCount;                      // non-finite count of the check
+    DevBuf dKlog;                       // Lanczos vectors per step of one call
+    int klog_cap = 0;
     int precision = DMRG_FP64;
     std::string last_error;
     // device copies of the plan's work lists, packed operators per arithmetic (built on
@@ -332,6 +363,9 @@ int fail(dmrg_handle h, int code, const std::string& msg) {
 }
 
 int hip_fail(dmrg_handle h, hipError_t e, const char* where) {
+    if (e == hipErrorOutOfMemory)
+        return fail(h, DMRG_ENOMEM, std::string(where) + ": device memory exhausted (or above the "
+                                                         "handle's DMRG_MAX_WORKSPACE)");
     return fail(h, DMRG_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
@@ -346,6 +380,7 @@ int hip_fail(dmrg_handle h, hipError_t e, const char* where) {
 // is allocated by dmrg_create; the padding rows of every intermediate are read (times zero
 // factors) but never written, so intermediates start zeroed).
 int ensure_workspace(dmrg_handle h, int kdim, int r = 0) {
+    BudgetScope bs(&h->budget);
     Workspace& W = h->ws[r];
     if (W.kcap >= kdim + 1 && W.dW.p && W.dT.p) return DMRG_OK;
     const int64_t n2 = 2 * h->plan.n;
@@ -357,6 +392,7 @@ int ensure_workspace(dmrg_handle h, int kdim, int r = 0) {
         HIP_TRY(h, hipMemsetAsync(W.dT.p, 0, bytes, h->stream));
     }
     if (W.kcap < kdim + 1) {
+        W.kcap = 0;                     // the old basis is released first, even on failure
         HIP_TRY(h, W.dV.alloc(sizeof(double) * (size_t)n2 * (kdim + 1)));
         W.kcap = kdim + 1;
     }
@@ -374,7 +410,8 @@ int ensure_workspace(dmrg_handle h, int kdim, int r = 0) {
 
 // Packed operators of one arithmetic on the device (built and cached on first use).
 int ensure_operators(dmrg_handle h, int prec) {
-    if (h->dA[prec].p) return DMRG_OK;
+    if (h->dA[prec].p && h->dR[prec].p) return DMRG_OK;
+    BudgetScope bs(&h->budget);
     std::vector<uint8_t> A, R;
     try {
         pack_operators(h->plan, prec, A, R);
@@ -507,11 +544,9 @@ int group_io(Group& g, const std::vector<const void*>& io, hipStream_t s) {
     dmrg_ctx* h0 = g.hs[0];
     if (io == g.io_last) return DMRG_OK;
     const size_t bytes = io.size() * sizeof(void*);
-    if (!g.io_host) {
-        HIP_TRY(h0, hipHostMalloc((void**)&g.io_host, bytes, hipHostMallocDefault));
-        HIP_TRY(h0, hipEventCreateWithFlags(&g.io_ev, hipEventDisableTiming));
-        HIP_TRY(h0, g.dIO.alloc(bytes));
-    }
+    if (!g.io_host) HIP_TRY(h0, hipHostMalloc((void**)&g.io_host, bytes, hipHostMallocDefault));
+    if (!g.io_ev) HIP_TRY(h0, hipEventCreateWithFlags(&g.io_ev, hipEventDisableTiming));
+    if (!g.dIO.p) HIP_TRY(h0, g.dIO.alloc(bytes));
     HIP_TRY(h0, hipEventSynchronize(g.io_ev));   // the previous upload has left the staging
     std::memcpy(g.io_host, io.data(), bytes);
     HIP_TRY(h0, hipMemcpyAsync(g.dIO.p, g.io_host, bytes, hipMemcpyHostToDevice, s));
@@ -521,6 +556,7 @@ int group_io(Group& g, const std::vector<const void*>& io, hipStream_t s) {
 }
 
 void fill_info(const KState& st, dmrg_krylov_info* info) {
+    info->converged = 1;
     info->k_eff = st.keff;
     info->k_eff_min = st.keff_min > kMaxKrylov ? st.keff : st.keff_min;
     info->beta0 = st.beta0_first;
@@ -529,13 +565,50 @@ void fill_info(const KState& st, dmrg_krylov_info* info) {
     info->breakdown = st.any_break;
 }
 
-int read_info(dmrg_handle h, dmrg_krylov_info* info) {
+// nsteps: entries of the per-step record to copy into info->k_eff_steps (if requested).
+int read_info(dmrg_handle h, dmrg_krylov_info* info, int nsteps) {
     if (!info) return DMRG_OK;
     KState st;
     HIP_TRY(h, hipMemcpyAsync(&st, h->ws[0].dState.p, sizeof(KState), hipMemcpyDeviceToHost, h->stream));
+    if (info->k_eff_steps && nsteps > 0)
+        HIP_TRY(h, hipMemcpyAsync(info->k_eff_steps, h->dKlog.p, sizeof(int32_t) * (size_t)nsteps,
+                                  hipMemcpyDeviceToHost, h->stream));
     HIP_TRY(h, hipStreamSynchronize(h->stream));
     fill_info(st, info);
+    if (st.nonfinite)
+        return fail(h, DMRG_ENONFINITE, "a Krylov step started from a vector with a non-finite norm");
     if (st.exp_fail) return fail(h, DMRG_ENONFINITE, "Krylov exponential coefficients are not finite");
+    return DMRG_OK;
+}
+
+// Device record of the Lanczos vectors per step, sized for nsteps (only when the caller asked
+// for it through info->k_eff_steps); nullptr otherwise.
+int klog_for(dmrg_handle h, const dmrg_krylov_info* info, int nsteps, int** out) {
+    *out = nullptr;
+    if (!info || !info->k_eff_steps || nsteps <= 0) return DMRG_OK;
+    if (h->klog_cap < nsteps) {
+        HIP_TRY(h, hipStreamSynchronize(h->stream));
+        h->klog_cap = 0;
+        HIP_TRY(h, h->dKlog.alloc(sizeof(int32_t) * (size_t)nsteps));
+        h->klog_cap = nsteps;
+    }
+    *out = h->dKlog.as<int>();
+    return DMRG_OK;
+}
+
+// With checking on: DMRG_ENONFINITE if any of the count vectors (2n doubles each, device) holds
+// a NaN or an infinity (the call waits for the stream); otherwise nothing.
+int check_inputs(dmrg_handle h, const double* const* xs, int count) {
+    if (!h->check_finite) return DMRG_OK;
+    if (!h->dCount.p) HIP_TRY(h, h->dCount.alloc(sizeof(int)));
+    HIP_TRY(h, hipMemsetAsync(h->dCount.p, 0, sizeof(int), h->stream));
+    for (int i = 0; i < count; ++i)
+        HIP_TRY(h, launch_count_nonfinite(xs[i], 2 * h->plan.n, h->dCount.as<int>(), h->stream));
+    int bad = 0;
+    HIP_TRY(h, hipMemcpyAsync(&bad, h->dCount.p, sizeof(int), hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(h, hipStreamSynchronize(h->stream));
+    if (bad) return fail(h, DMRG_ENONFINITE, "input vector holds " + std::to_string(bad) +
+                                                 " non-finite values");
     return DMRG_OK;
 }
 
@@ -607,7 +680,7 @@ int run_chains(dmrg_batch_ctx& cs, int variant, bool graph, const double* const*
     HIP_TRY(h0, launch_start(g.vg, nullptr, xt, kdim, 1, s));
     rc = group_basis(g, kdim, s);
     if (rc) return rc;
-    HIP_TRY(h0, launch_tridiag(g.vg, &tau, 1, s));
+    HIP_TRY(h0, launch_tridiag(g.vg, &tau, 1, nullptr, 0, s));
     HIP_TRY(h0, launch_combine(g.vg, nullptr, yst, 1, 0, s));
     if (!infos) return DMRG_OK;
     std::vector<KState> st(np);
@@ -615,9 +688,15 @@ int run_chains(dmrg_batch_ctx& cs, int variant, bool graph, const double* const*
         HIP_TRY(h0, hipMemcpyAsync(&st[i], g.hs[i]->ws[g.rhs[i]].dState.p, sizeof(KState),
                                    hipMemcpyDeviceToHost, s));
     HIP_TRY(h0, hipStreamSynchronize(s));
-    for (int i = 0; i < np; ++i) fill_info(st[i], &infos[i]);
-    for (int i = 0; i < np; ++i)
+    for (int i = 0; i < np; ++i) {
+        fill_info(st[i], &infos[i]);
+        if (infos[i].k_eff_steps) infos[i].k_eff_steps[0] = st[i].keff;
+    }
+    for (int i = 0; i < np; ++i) {
+        if (st[i].nonfinite)
+            return fail(h0, DMRG_ENONFINITE, "a Krylov step started from a vector with a non-finite norm");
         if (st[i].exp_fail) return fail(h0, DMRG_ENONFINITE, "Krylov exponential coefficients are not finite");
+    }
     return DMRG_OK;
 }
 
@@ -1089,6 +1168,17 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
     h->stream = static_cast<hipStream_t>(stream);
     h->self.hs.assign(1, h);
     h->self.rhs.assign(1, 0);
+    if (const char* cap = std::getenv("DMRG_MAX_WORKSPACE")) {
+        char* end = nullptr;
+        const unsigned long long v = std::strtoull(cap, &end, 10);
+        if (end == cap || *end != '\0') {
+            g_create_error = "DMRG_MAX_WORKSPACE is not a byte count";
+            delete h;
+            return DMRG_EINVAL;
+        }
+        h->budget.cap = (size_t)v;
+    }
+    BudgetScope bs(&h->budget);
     const Plan& P = h->plan;
     hipError_t e = hipSuccess;
     h->self.lists = &h->lists;
@@ -1111,13 +1201,16 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
         e = hipMemsetAsync(h->ws[0].dT.p, 0, sizeof(double) * (size_t)P.T_size, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) {
+        g_create_error = e == hipErrorOutOfMemory
+                             ? "device memory exhausted (or above DMRG_MAX_WORKSPACE)"
+                             : std::string(hipGetErrorString(e));
         delete h;
         return e == hipErrorOutOfMemory ? DMRG_ENOMEM : DMRG_EHIP;
     }
-    if (ensure_operators(h, DMRG_FP64) != DMRG_OK) {
+    if (const int rc = ensure_operators(h, DMRG_FP64)) {
         g_create_error = h->last_error;
         delete h;
-        return DMRG_ENOMEM;
+        return rc;
     }
     *out = h;
     return DMRG_OK;
@@ -1151,8 +1244,70 @@ int dmrg_flops(dmrg_handle h, double* flops) {
     return DMRG_OK;
 }
 
+int dmrg_plan_stats(const dmrg_problem* problem, int32_t kdim, dmrg_plan_info* out) {
+    if (!problem || !out) return DMRG_EINVAL;
+    if (kdim < 1 || kdim > kMaxKrylov) {
+        g_create_error = "kdim outside [1, 64]";
+        return DMRG_EINVAL;
+    }
+    try {
+        g_create_error.clear();
+        Plan P;
+        const std::string err = build_plan(problem, P);
+        if (!err.empty()) {
+            g_create_error = err;
+            return DMRG_EINVAL;
+        }
+        std::vector<uint8_t> A, R;
+        pack_operators(P, DMRG_FP64, A, R);
+        // the allocations of dmrg_create, in its order (a buffer of zero bytes takes 8)
+        int64_t bytes = 0;
+        auto add = [&](size_t b) { bytes += (int64_t)(b ? b : 8); };
+        for (const Packing* pk : {&P.pk16, &P.pk32}) {
+            add(pk->s1.size() * sizeof(S1Block));
+            add(pk->s2.size() * sizeof(S2Block));
+            add(pk->segs.size() * sizeof(Segment));
+            add(pk->l2.size() * sizeof(LItem2));
+            add(pk->lred.size() * sizeof(LRed));
+        }
+        add(P.tiles1.size() * sizeof(Tile));
+        add(P.tiles1n.size() * sizeof(Tile));
+        add(P.tiles2.size() * sizeof(Tile));
+        add(P.tiles2n.size() * sizeof(Tile));
+        add(P.l1.size() * sizeof(LItem1));
+        add(sizeof(double) * (size_t)std::max(P.pk16.nslots, P.pk32.nslots) * kLTile * kLTile);
+        add(sizeof(double) * (size_t)P.T_size);
+        add(A.size());
+        add(R.size());
+        out->create_bytes = bytes;
+        // the first Krylov call of kdim vectors: basis, work vector, partial sums, state, and
+        // the handle's own group tables (descriptor, pointer table of every iteration)
+        const size_t n2 = 2 * (size_t)P.n;
+        out->krylov_bytes = (int64_t)(sizeof(double) * n2 * (size_t)(kdim + 1) + sizeof(double) * n2 +
+                                      sizeof(double) * (size_t)kDVals * kVecMaxBlocks * kDMaxQ +
+                                      sizeof(KState) + sizeof(VecProb) +
+                                      sizeof(ProbPtrs) * (size_t)kMaxKrylov);
+        out->n = P.n;
+        out->nblk = (int32_t)P.blocks.size();
+        out->flops = P.flops;
+        out->flops_executed = P.flops_exec;
+    } catch (const std::bad_alloc&) {
+        return DMRG_ENOMEM;
+    } catch (...) {
+        return DMRG_EINVAL;
+    }
+    return DMRG_OK;
+}
+
+int dmrg_flops_executed(dmrg_handle h, double* flops) {
+    if (!h || !flops) return DMRG_EINVAL;
+    *flops = h->plan.flops_exec;
+    return DMRG_OK;
+}
+
 int dmrg_set_precision(dmrg_handle h, int32_t precision) {
     if (!h) return DMRG_EINVAL;
+    BudgetScope bs(&h->budget);
     if (precision < DMRG_FP64 || precision > DMRG_BF16X6)
         return fail(h, DMRG_EINVAL, "unknown precision");
     const int rc = ensure_operators(h, precision);
@@ -1179,7 +1334,13 @@ int dmrg_set_stream(dmrg_handle h, void* stream) {
 int dmrg_matvec(dmrg_handle h, const double* x, double* y, int32_t nvec) {
     if (!h) return DMRG_EINVAL;
     if (nvec < 0 || (nvec > 0 && (!x || !y))) return fail(h, DMRG_EINVAL, "bad vectors");
+    BudgetScope bs(&h->budget);
     const int64_t vs = 2 * h->plan.n;
+    for (int v = 0; v < nvec; ++v) {
+        const double* xv = x + v * vs;
+        int rc = check_inputs(h, &xv, 1);
+        if (rc) return rc;
+    }
     for (int v = 0; v < nvec; ++v) {
         int rc = matvec_one(h, x + v * vs, y + v * vs);
         if (rc) return rc;
@@ -1194,12 +1355,21 @@ int dmrg_krylov_expm(dmrg_handle h, const double* x, double* y, double tau, int3
     if (nsteps < 0) return fail(h, DMRG_EINVAL, "negative nsteps");
     int rc = check_krylov_args(h, tau, kdim);
     if (rc) return rc;
+    BudgetScope bs(&h->budget);
+    rc = check_inputs(h, &x, 1);
+    if (rc) return rc;
     if (nsteps == 0) {
         HIP_TRY(h, hipMemcpyAsync(y, x, sizeof(double) * 2 * h->plan.n, hipMemcpyDeviceToDevice,
                                   h->stream));
-        if (info) *info = dmrg_krylov_info{0, 0, 0.0, 0.0, 0.0, 0};
+        if (info) {
+            int32_t* steps = info->k_eff_steps;
+            *info = dmrg_krylov_info{0, 0, 0.0, 0.0, 0.0, 0, 1, steps};
+        }
         return DMRG_OK;
     }
+    int* klog = nullptr;
+    rc = klog_for(h, info, nsteps, &klog);
+    if (rc) return rc;
     Group& g = h->self;
     rc = group_prepare(g, kdim);
     if (rc) return rc;
@@ -1207,12 +1377,12 @@ int dmrg_krylov_expm(dmrg_handle h, const double* x, double* y, double tau, int3
     for (int s = 0; s < nsteps; ++s) {
         rc = group_basis(g, kdim, h->stream);
         if (rc) return rc;
-        HIP_TRY(h, launch_tridiag(g.vg, &tau, 1, h->stream));
+        HIP_TRY(h, launch_tridiag(g.vg, &tau, 1, klog, s, h->stream));
         const bool last = s == nsteps - 1;
         double* out[1] = {y};
         HIP_TRY(h, launch_combine(g.vg, last ? out : nullptr, nullptr, 1, last ? 0 : 1, h->stream));
     }
-    return read_info(h, info);
+    return read_info(h, info, nsteps);
 }
 
 int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim, double* targets,
@@ -1220,6 +1390,12 @@ int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim,
     if (!h) return DMRG_EINVAL;
     if (!phi || !targets) return fail(h, DMRG_EINVAL, "NULL vector");
     int rc = check_krylov_args(h, tau, kdim);
+    if (rc) return rc;
+    BudgetScope bs(&h->budget);
+    rc = check_inputs(h, &phi, 1);
+    if (rc) return rc;
+    int* klog = nullptr;
+    rc = klog_for(h, info, 1, &klog);
     if (rc) return rc;
     Group& g = h->self;
     rc = group_prepare(g, kdim);
@@ -1229,11 +1405,11 @@ int dmrg_tst_targets(dmrg_handle h, const double* phi, double tau, int32_t kdim,
     rc = group_basis(g, kdim, h->stream);
     if (rc) return rc;
     const double times[4] = {0.0, tau / 3.0, 2.0 * tau / 3.0, tau};
-    HIP_TRY(h, launch_tridiag(g.vg, times, 4, h->stream));
+    HIP_TRY(h, launch_tridiag(g.vg, times, 4, klog, 0, h->stream));
     double* out[4] = {targets, targets + 2 * n, targets + 4 * n, targets + 6 * n};
     HIP_TRY(h, launch_combine(g.vg, out, nullptr, 4, 0, h->stream));
     tst_weights(weights);
-    return read_info(h, info);
+    return read_info(h, info, 1);
 }
 
 int dmrg_ground_state(dmrg_handle h, const double* x0, double* y, int32_t kdim,
@@ -1245,23 +1421,31 @@ int dmrg_ground_state(dmrg_handle h, const double* x0, double* y, int32_t kdim,
     if (!(tol >= 0.0)) return fail(h, DMRG_EINVAL, "tol must be a non-negative number");
     int rc = check_krylov_args(h, 0.0, kdim);
     if (rc) return rc;
+    BudgetScope bs(&h->budget);
+    rc = check_inputs(h, &x0, 1);
+    if (rc) return rc;
     Group& g = h->self;
     rc = group_prepare(g, kdim);
     if (rc) return rc;
     HIP_TRY(h, launch_start(g.vg, x0, nullptr, kdim, 1, h->stream));
     KState st;
     int used = 0;
+    bool converged = false;
     for (int r = 0; r < max_restarts; ++r) {
         rc = group_basis(g, kdim, h->stream);
         if (rc) return rc;
-        HIP_TRY(h, launch_lowest(g.vg, h->stream));
+        HIP_TRY(h, launch_lowest(g.vg, nullptr, 0, h->stream));
         ++used;
         HIP_TRY(h, hipMemcpyAsync(&st, h->ws[0].dState.p, sizeof(KState), hipMemcpyDeviceToHost,
                                   h->stream));
         HIP_TRY(h, hipStreamSynchronize(h->stream));
+        if (st.nonfinite) return fail(h, DMRG_ENONFINITE, "start vector with a non-finite norm");
         if (st.exp_fail) return fail(h, DMRG_ENONFINITE, "ground-state eigenpair is not finite");
-        const bool done = st.err_est <= tol * std::max(1.0, std::fabs(st.eig)) ||
-                          r == max_restarts - 1 || st.keff <= 0;
+        if (info && info->k_eff_steps) info->k_eff_steps[r] = st.keff;
+        // an invariant subspace (breakdown) makes the Ritz pair exact
+        converged = st.err_est <= tol * std::max(1.0, std::fabs(st.eig)) || st.keff <= 0 ||
+                    st.broken;
+        const bool done = converged || r == max_restarts - 1;
         double* out[1] = {y};
         // converged (or out of restarts): the Ritz vector into y; else into slot 0, restart
         HIP_TRY(h, launch_combine(g.vg, done ? out : nullptr, nullptr, 1, done ? 0 : 1, h->stream));
@@ -1272,6 +1456,11 @@ int dmrg_ground_state(dmrg_handle h, const double* x0, double* y, int32_t kdim,
     if (info) {
         HIP_TRY(h, hipStreamSynchronize(h->stream));
         fill_info(st, info);
+        info->converged = converged ? 1 : 0;
+    }
+    if (!converged) {
+        h->last_error = "ground state: residual estimate above tol after max_restarts bases";
+        return DMRG_WNOTCONV;
     }
     return DMRG_OK;
 }
@@ -1283,6 +1472,7 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
     if (!vecs || !weights || !evals || !evecs || !kept) return fail(h, DMRG_EINVAL, "NULL pointer");
     if (nvec < 1 || nvec > kDensMaxVec) return fail(h, DMRG_EINVAL, "nvec outside [1, 16]");
     if (keep < 0) return fail(h, DMRG_EINVAL, "negative keep");
+    BudgetScope bs(&h->budget);
     for (int l = 0; l < nvec; ++l) {
         if (!vecs[l]) return fail(h, DMRG_EINVAL, "NULL vector");
         if (!std::isfinite(weights[l])) return fail(h, DMRG_ENONFINITE, "weight is not finite");
@@ -1307,7 +1497,8 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
         h->dens_ntiles = (int)tiles.size();
         h->dens_ntot = (int)eoff;
         h->dens_nmat = aoff;
-        HIP_TRY(h, upload(h->dDBlk, blks, s));
+        // the sector table goes last: it opens this block's gate, so a failed allocation
+        // leaves every buffer to be allocated again by the next call
         HIP_TRY(h, upload(h->dDTile, tiles, s));
         HIP_TRY(h, h->dDA.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDV.alloc(2 * sizeof(double) * (size_t)aoff));
@@ -1320,6 +1511,7 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
         HIP_TRY(h, h->dDSums.alloc(2 * sizeof(double) * (size_t)nb));
         HIP_TRY(h, h->dDVecs.alloc(sizeof(void*) * kDensMaxVec));
         HIP_TRY(h, h->dDW.alloc(sizeof(double) * kDensMaxVec));
+        HIP_TRY(h, upload(h->dDBlk, blks, s));
     }
     // per-call pointers and weights (synchronous copies; the call waits for its results)
     HIP_TRY(h, hipMemcpyAsync(h->dDVecs.p, vecs, sizeof(void*) * nvec, hipMemcpyHostToDevice, s));
@@ -1360,6 +1552,7 @@ int dmrg_wft_create(dmrg_handle h, const dmrg_wft_desc* desc, const double* cons
     std::unique_ptr<dmrg_wft_ctx> w(new (std::nothrow) dmrg_wft_ctx());
     if (!w) return DMRG_ENOMEM;
     w->h = h;
+    BudgetScope bs(&h->budget);
     std::vector<ZTile> tA, tB;
     std::vector<int64_t> woff;
     int rc = plan_wft(h, *desc, tA, tB, woff, *w);
@@ -1389,11 +1582,13 @@ int dmrg_wft_apply(dmrg_wft w, const double* U, int32_t nvec, const double* cons
     dmrg_handle h = w->h;
     if (nvec < 1 || nvec > kWftMaxVec) return fail(h, DMRG_EINVAL, "wft: nvec outside [1, 16]");
     if (!U || !x || !y) return fail(h, DMRG_EINVAL, "wft: NULL pointer");
+    BudgetScope bs(&h->budget);
     for (int v = 0; v < nvec; ++v)
         if (!x[v] || !y[v]) return fail(h, DMRG_EINVAL, "wft: NULL vector");
     hipStream_t s = h->stream;
     if (w->phi_vecs < nvec) {
         HIP_TRY(h, hipStreamSynchronize(s));
+        w->phi_vecs = 0;
         HIP_TRY(h, w->dPhi.alloc(sizeof(double) * 2 * (size_t)std::max<int64_t>(w->nphi, 1) * nvec));
         w->phi_vecs = nvec;
     }
@@ -1426,6 +1621,7 @@ int dmrg_apply_local(dmrg_handle src, dmrg_handle dst, int32_t nterm, const dmrg
     if (!src || !dst) return DMRG_EINVAL;
     if (nterm < 1 || !terms || !x || !y) return fail(src, DMRG_EINVAL, "local operator: NULL or empty argument");
     if (x == y) return fail(src, DMRG_EINVAL, "local operator: y must not be x");
+    BudgetScope bs(&src->budget);
     return run_local(src, dst, nterm, terms, x, y);
 }
 
@@ -1433,6 +1629,7 @@ int dmrg_expect_local(dmrg_handle h, int32_t nterm, const dmrg_term* terms, cons
                       double* re, double* im) {
     if (!h) return DMRG_EINVAL;
     if (nterm < 1 || !terms || !x) return fail(h, DMRG_EINVAL, "local operator: NULL or empty argument");
+    BudgetScope bs(&h->budget);
     hipStream_t s = h->stream;
     if (!h->dLocZ.p) HIP_TRY(h, h->dLocZ.alloc(sizeof(double) * 2 * (size_t)h->plan.n));
     if (!h->dLocPart.p) HIP_TRY(h, h->dLocPart.alloc(sizeof(double) * 2 * kDotBlocks));
@@ -1459,11 +1656,22 @@ int dmrg_tst_chains(dmrg_handle h, const double* const* phi, double tau, int32_t
     if (!phi || !targets) return fail(h, DMRG_EINVAL, "NULL pointer array");
     int rc = check_krylov_args(h, tau, kdim);
     if (rc) return rc;
+    BudgetScope bs(&h->budget);
+    for (int k = 0; k < kChains; ++k)
+        if (!phi[k] || !targets[k]) return fail(h, DMRG_EINVAL, "NULL vector among the chains");
+    rc = check_inputs(h, phi, kChains);
+    if (rc) return rc;
     rc = chains_set(h->chains, std::vector<dmrg_ctx*>(1, h));
     if (rc) return rc;
     rc = run_chains(*h->chains, h->lists.variant, h->self.use_graph, phi, tau, kdim, targets, infos);
     if (rc) return rc;
     tst_weights(weights);
+    return DMRG_OK;
+}
+
+int dmrg_set_check_finite(dmrg_handle h, int32_t enable) {
+    if (!h) return DMRG_EINVAL;
+    h->check_finite = enable != 0;
     return DMRG_OK;
 }
 
@@ -1490,6 +1698,7 @@ int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out
     g.lists = &b->lists;
     g.use_graph = true;
     dmrg_ctx* h0 = g.hs[0];
+    BudgetScope bs(&h0->budget);
     try {
         std::vector<const Plan*> plans;
         for (dmrg_ctx* h : g.hs) plans.push_back(&h->plan);
@@ -1533,6 +1742,11 @@ int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, i
         if (!phi[i] || !targets[i]) return fail(h0, DMRG_EINVAL, "NULL vector in a batch");
     int rc = check_krylov_args(h0, tau, kdim);
     if (rc) return rc;
+    BudgetScope bs(&h0->budget);
+    for (int i = 0; i < np; ++i) {
+        rc = check_inputs(g.hs[i], &phi[i], 1);
+        if (rc) return rc == DMRG_ENONFINITE ? fail(h0, rc, g.hs[i]->last_error) : rc;
+    }
     rc = group_prepare(g, kdim);
     if (rc) return rc;
     hipStream_t s = h0->stream;
@@ -1550,7 +1764,7 @@ int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, i
     rc = group_basis(g, kdim, s);
     if (rc) return rc;
     const double times[4] = {0.0, tau / 3.0, 2.0 * tau / 3.0, tau};
-    HIP_TRY(h0, launch_tridiag(g.vg, times, 4, s));
+    HIP_TRY(h0, launch_tridiag(g.vg, times, 4, nullptr, 0, s));
     HIP_TRY(h0, launch_combine(g.vg, nullptr, yst, 4, 0, s));
     tst_weights(weights);
     if (!infos) return DMRG_OK;
@@ -1559,9 +1773,15 @@ int dmrg_batch_tst_targets(dmrg_batch b, const double* const* phi, double tau, i
         HIP_TRY(h0, hipMemcpyAsync(&st[i], g.hs[i]->ws[g.rhs[i]].dState.p, sizeof(KState),
                                    hipMemcpyDeviceToHost, s));
     HIP_TRY(h0, hipStreamSynchronize(s));
-    for (int i = 0; i < np; ++i) fill_info(st[i], &infos[i]);
-    for (int i = 0; i < np; ++i)
+    for (int i = 0; i < np; ++i) {
+        fill_info(st[i], &infos[i]);
+        if (infos[i].k_eff_steps) infos[i].k_eff_steps[0] = st[i].keff;
+    }
+    for (int i = 0; i < np; ++i) {
+        if (st[i].nonfinite)
+            return fail(h0, DMRG_ENONFINITE, "a Krylov step started from a vector with a non-finite norm");
         if (st[i].exp_fail) return fail(h0, DMRG_ENONFINITE, "Krylov exponential coefficients are not finite");
+    }
     return DMRG_OK;
 }
 
@@ -1571,6 +1791,7 @@ int dmrg_batch_tst_chains(dmrg_batch b, const double* const* phi, double tau, in
     dmrg_ctx* h0 = b->g.hs[0];
     int rc = check_krylov_args(h0, tau, kdim);
     if (rc) return rc;
+    BudgetScope bs(&h0->budget);
     rc = chains_set(b->chains, b->g.hs);
     if (rc) return rc;
     rc = run_chains(*b->chains, b->lists.variant, b->g.use_graph, phi, tau, kdim, targets, infos);
@@ -1609,6 +1830,7 @@ int dmrg_get_gemm(dmrg_handle h, int32_t* variant) {
 
 int dmrg_autotune(dmrg_handle h, int32_t reps, double* out) {
     if (!h || reps < 1) return DMRG_EINVAL;
+    BudgetScope bs(&h->budget);
     int rc = ensure_workspace(h, 1);
     if (rc) return rc;
     // timing inputs: basis slot 0 (zeroed) into the work vector
@@ -1632,6 +1854,7 @@ int dmrg_batch_autotune(dmrg_batch b, int32_t reps, double* out) {
     if (!b || reps < 1) return DMRG_EINVAL;
     Group& g = b->g;
     dmrg_ctx* h0 = g.hs[0];
+    BudgetScope bs(&h0->budget);
     int rc = group_prepare(g, 1);
     if (rc) return rc;
     for (dmrg_ctx* h : g.hs)
@@ -1645,6 +1868,7 @@ int dmrg_batch_autotune(dmrg_batch b, int32_t reps, double* out) {
 const char* dmrg_strerror(int status) {
     switch (status) {
         case DMRG_OK: return "success";
+        case DMRG_WNOTCONV: return "not converged (the last iterate is returned)";
         case DMRG_EINVAL: return "invalid argument";
         case DMRG_ENOMEM: return "out of memory";
         case DMRG_EHIP: return "HIP runtime error";

@@ -210,6 +210,10 @@ struct KState {
     int32_t any_break;                // over all steps of one call
     double beta0_first;               // ||x|| of the first step of one call
     double eig;                       // lowest eigenvalue of the Lanczos matrix (ground state)
+    int32_t nonfinite;                // a step started from a vector with a non-finite norm
+                                      // (any step of one call); the step is then run as a
+                                      // zero vector
+    int32_t pad;
 };
 
 }  // namespace dmrg

@@ -276,7 +276,11 @@ __device__ void final_sums(const double* part, int nb, double* totals_lds) {
 
 // Starts a Krylov step from ||x||^2: beta0, scale0, per-step flags.
 __device__ void begin_step(KState* st, double norm2, int kdim) {
-    const double b0 = sqrt(norm2);
+    double b0 = sqrt(norm2);
+    if (!isfinite(b0)) {          // NaN or infinity in the vector: flagged, run as zero
+        st->nonfinite = 1;
+        b0 = 0.0;
+    }
     st->beta[0] = b0;
     st->kdim = kdim;
     if (b0 > 0.0) {
@@ -319,6 +323,7 @@ __global__ __launch_bounds__(kVecThreads) void k_fin_start(const VecProb* vp, in
     __shared__ double tot[1];
     final_sums<1>(P.part, P.nb, tot);
     if (threadIdx.x == 0) {
+        if (first) st->nonfinite = 0;
         begin_step(st, tot[0], kdim);
         st->err_est = 0.0;
         st->exp_fail = 0;
@@ -707,10 +712,12 @@ __device__ __forceinline__ double wave_max(double v) {
 }  // namespace
 
 __global__ __launch_bounds__(64) void k_tridiag_expm(const VecProb* vp, double t0, double t1,
-                                                     double t2, double t3, int ntimes) {
+                                                     double t2, double t3, int ntimes,
+                                                     int* klog, int step) {
     KState* st = vp[blockIdx.x].st;
     const int r = threadIdx.x;
     const int k = st->keff;
+    if (klog && r == 0) klog[step] = k > 0 ? k : 0;     // Lanczos vectors of this step
     if (k <= 0) {
         for (int x = 0; x < ntimes; ++x) {
             st->coef[x][2 * r] = 0.0;
@@ -789,10 +796,11 @@ __global__ __launch_bounds__(64) void k_tridiag_expm(const VecProb* vp, double t
 // Output: coef[0] = z (real, unit norm; the combination gives the unit Ritz vector V z),
 // eig = lambda, err_est = beta_k |z_{k-1}| (the residual norm ||H V z - lambda V z||).
 // ---------------------------------------------------------------------------------------
-__global__ __launch_bounds__(64) void k_tridiag_lowest(const VecProb* vp) {
+__global__ __launch_bounds__(64) void k_tridiag_lowest(const VecProb* vp, int* klog, int step) {
     KState* st = vp[blockIdx.x].st;
     const int r = threadIdx.x;
     const int k = st->keff;
+    if (klog && r == 0) klog[step] = k > 0 ? k : 0;     // Lanczos vectors of this basis
     if (k <= 0) {
         st->coef[0][2 * r] = 0.0;
         st->coef[0][2 * r + 1] = 0.0;
@@ -1056,16 +1064,38 @@ hipError_t launch_lanczos_iter(const VecGroup& g, int j, int kdim, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_lowest(const VecGroup& g, hipStream_t s) {
-    hipLaunchKernelGGL(k_tridiag_lowest, dim3(g.nprob), dim3(64), 0, s, g.vp);
+// klog (one problem only, else nullptr): device array receiving the Lanczos vectors of the
+// basis at index step.
+hipError_t launch_lowest(const VecGroup& g, int* klog, int step, hipStream_t s) {
+    hipLaunchKernelGGL(k_tridiag_lowest, dim3(g.nprob), dim3(64), 0, s, g.vp, klog, step);
     return hipGetLastError();
 }
 
-hipError_t launch_tridiag(const VecGroup& g, const double* times, int ntimes, hipStream_t s) {
+hipError_t launch_tridiag(const VecGroup& g, const double* times, int ntimes, int* klog, int step,
+                          hipStream_t s) {
     double t[kMaxTimes] = {0, 0, 0, 0};
     for (int i = 0; i < ntimes; ++i) t[i] = times[i];
     hipLaunchKernelGGL(k_tridiag_expm, dim3(g.nprob), dim3(64), 0, s, g.vp, t[0], t[1], t[2], t[3],
-                       ntimes);
+                       ntimes, klog, step);
+    return hipGetLastError();
+}
+
+// Number of non-finite values among x[0 .. m) added to *count (which the caller zeroes):
+// integer atomics, one per thread that found any (their sum does not depend on the order).
+__global__ __launch_bounds__(kVecThreads) void k_count_nonfinite(const double* __restrict__ x,
+                                                                 int64_t m, int* count) {
+    int c = 0;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < m; i += stride)
+        c += !isfinite(x[i]);
+    if (c) atomicAdd(count, c);       // only where non-finite values were found
+}
+
+hipError_t launch_count_nonfinite(const double* x, int64_t m, int* count, hipStream_t s) {
+    int64_t nb = (m + kVecThreads - 1) / kVecThreads;
+    if (nb > 1024) nb = 1024;
+    if (nb < 1) nb = 1;
+    hipLaunchKernelGGL(k_count_nonfinite, dim3((unsigned)nb), dim3(kVecThreads), 0, s, x, m, count);
     return hipGetLastError();
 }
 

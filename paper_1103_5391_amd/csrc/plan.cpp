@@ -277,7 +277,16 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
         tile_list(P.tiles2, bi, B.d, 2 * B.e, kTile, kTile);
         tile_list(P.tiles2n, bi, B.d, 2 * B.e, kTile, kTile2NN);
     }
-    P.flops = P.flops1 + P.flops2;
+    P.flops_exec = P.flops1 + P.flops2;
+    // algorithmic count: the diagonal terms, and per connection term the cheaper of
+    // (A X) B^T and A (X B^T) (complex vector: two real planes, two flops per multiply-add)
+    P.flops = 0.0;
+    for (const auto& B : P.blocks) P.flops += 4.0 * ((double)B.d * B.d * B.e + (double)B.d * B.e * B.e);
+    for (const Edge& ed : P.edges) {
+        const double d = P.blocks[ed.src].d, e = P.blocks[ed.src].e;
+        const double d2 = P.blocks[ed.dst].d, e2 = P.blocks[ed.dst].e;
+        P.flops += 4.0 * std::min(d2 * d * e + d2 * e * e2, d * e * e2 + d2 * d * e2);
+    }
 
     // descriptors for both chunk depths
     for (Packing* pk : {&P.pk16, &P.pk32}) {

@@ -95,7 +95,10 @@ struct Plan {
     std::vector<LItem1> l1;                    // LDS-tiled stage-1 tiles (both packings)
     std::vector<double> w1, w2;                // per-block work estimates of the two stages
     Packing pk16, pk32;
-    double flops = 0.0;                        // algorithmic flops per complex matvec
+    double flops = 0.0;                        // algorithmic flops per complex matvec: the
+                                               // cheaper contraction order of every term
+    double flops_exec = 0.0;                   // flops the two stages execute (right product
+                                               // first for every term), padding excluded
     double flops1 = 0.0, flops2 = 0.0;         // of which stage 1 / stage 2
 };
 

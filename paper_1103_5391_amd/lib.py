@@ -13,17 +13,20 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdmrgtst.so")
+# DMRG_LIB selects another build of the same library (the sanitized host build in the tests)
+LIB_PATH = os.environ.get("DMRG_LIB") or os.path.join(HERE, "libdmrgtst.so")
 
 DMRG_FP64, DMRG_FP32, DMRG_BF16X3, DMRG_BF16X6 = 0, 1, 2, 3
 DMRG_GEMM_STAGE1_LDS, DMRG_GEMM_STAGE2_LDS = 1, 2
 DMRG_GEMM_STAGE1_NARROW, DMRG_GEMM_STAGE2_NARROW = 4, 8
 STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP",
-          -4: "DMRG_ENONFINITE", -5: "DMRG_ESTATE"}
+          -4: "DMRG_ENONFINITE", -5: "DMRG_ESTATE", 1: "DMRG_WNOTCONV"}
+DMRG_WNOTCONV = 1
 
 # exported symbols (kept in sync with include/dmrgtst.h; checked by the CPU tests)
 SYMBOLS = [
-    "dmrg_create", "dmrg_destroy", "dmrg_psi_layout", "dmrg_flops", "dmrg_set_precision",
+    "dmrg_create", "dmrg_destroy", "dmrg_psi_layout", "dmrg_flops", "dmrg_flops_executed",
+    "dmrg_set_precision", "dmrg_set_check_finite", "dmrg_plan_stats",
     "dmrg_set_stream", "dmrg_matvec", "dmrg_krylov_expm", "dmrg_tst_targets", "dmrg_set_graph",
     "dmrg_set_gemm", "dmrg_get_gemm", "dmrg_autotune",
     "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_set_graph", "dmrg_batch_tst_targets",
@@ -69,12 +72,33 @@ class dmrg_wft_desc(C.Structure):
                 ("e_new_dim", C.POINTER(C.c_int32))]
 
 
+class dmrg_plan_info(C.Structure):
+    _fields_ = [("n", C.c_int64), ("nblk", C.c_int32), ("flops", C.c_double),
+                ("flops_executed", C.c_double), ("create_bytes", C.c_int64),
+                ("krylov_bytes", C.c_int64)]
+
+
 class dmrg_krylov_info(C.Structure):
     _fields_ = [("k_eff", C.c_int32), ("k_eff_min", C.c_int32), ("beta0", C.c_double),
-                ("beta_last", C.c_double), ("err_est", C.c_double), ("breakdown", C.c_int32)]
+                ("beta_last", C.c_double), ("err_est", C.c_double), ("breakdown", C.c_int32),
+                ("converged", C.c_int32), ("k_eff_steps", C.POINTER(C.c_int32))]
 
-    def as_dict(self):
-        return {f: getattr(self, f) for f, _ in self._fields_}
+    def as_dict(self, nsteps: int = 0):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "k_eff_steps"}
+        if nsteps and self.k_eff_steps:
+            d["k_eff_steps"] = [int(self.k_eff_steps[i]) for i in range(nsteps)]
+        return d
+
+
+def _info(nsteps: int = 0):
+    """A zero-initialised info struct with a per-step array of nsteps entries (kept alive on
+    the struct)."""
+    inf = dmrg_krylov_info()
+    if nsteps > 0:
+        arr = (C.c_int32 * nsteps)()
+        inf._steps = arr
+        inf.k_eff_steps = C.cast(arr, C.POINTER(C.c_int32))
+    return inf
 
 
 _lib = None
@@ -95,6 +119,9 @@ def load(path: str = LIB_PATH):
     lib.dmrg_destroy.restype = None
     lib.dmrg_psi_layout.argtypes = [vp, P(i64), P(i32), P(i64), P(i32), P(i32), P(i32), P(i32)]
     lib.dmrg_flops.argtypes = [vp, P(dbl)]
+    lib.dmrg_flops_executed.argtypes = [vp, P(dbl)]
+    lib.dmrg_set_check_finite.argtypes = [vp, i32]
+    lib.dmrg_plan_stats.argtypes = [P(dmrg_problem), i32, P(dmrg_plan_info)]
     lib.dmrg_set_precision.argtypes = [vp, i32]
     lib.dmrg_set_stream.argtypes = [vp, vp]
     lib.dmrg_matvec.argtypes = [vp, vp, vp, i32]
@@ -141,7 +168,8 @@ class DmrgError(RuntimeError):
 
 
 def _check(rc: int, handle=None):
-    if rc != 0:
+    """Raises on an error status (negative); warnings (positive) are left to the caller."""
+    if rc < 0:
         lib = load()
         msg = lib.dmrg_last_error(handle).decode()
         raise DmrgError(rc, msg or lib.dmrg_strerror(rc).decode())
@@ -234,6 +262,18 @@ def dmrg_create(pb, stream=None, extra_terms=()):
     return Handle(h)
 
 
+def plan_stats(pb, kdim: int = 15, extra_terms=()) -> dict:
+    """Host-only planning of a problem (no GPU needed): n, block count, algorithmic and executed
+    flops, device bytes of dmrg_create and of a first Krylov call with kdim vectors."""
+    lib = load()
+    cpb, keep = problem_to_c(pb, extra_terms)
+    st = dmrg_plan_info()
+    rc = lib.dmrg_plan_stats(C.byref(cpb), int(kdim), C.byref(st))
+    if rc != 0:
+        raise DmrgError(rc, lib.dmrg_last_error(None).decode())
+    return {f: getattr(st, f) for f, _ in st._fields_}
+
+
 class Handle:
     def __init__(self, h: C.c_void_p):
         self.h = h
@@ -272,6 +312,18 @@ class Handle:
 
     flops = dmrg_flops
 
+    def dmrg_flops_executed(self) -> float:
+        f = C.c_double()
+        _check(self.lib.dmrg_flops_executed(self.h, C.byref(f)), self.h)
+        return f.value
+
+    flops_executed = dmrg_flops_executed
+
+    def dmrg_set_check_finite(self, enable: bool):
+        _check(self.lib.dmrg_set_check_finite(self.h, int(bool(enable))), self.h)
+
+    set_check_finite = dmrg_set_check_finite
+
     def dmrg_set_precision(self, prec: int):
         _check(self.lib.dmrg_set_precision(self.h, int(prec)), self.h)
 
@@ -290,12 +342,13 @@ class Handle:
     matvec = dmrg_matvec
 
     def dmrg_krylov_expm(self, x, y, tau: float, kdim: int, nsteps: int = 1, info: bool = True):
+        """y = exp(-i tau H)^nsteps x; returns the info dict (with k_eff_steps per step)."""
         n2 = 2 * self.n
-        inf = dmrg_krylov_info()
+        inf = _info(nsteps)
         _check(self.lib.dmrg_krylov_expm(self.h, _tensor_ptr(x, n2), _tensor_ptr(y, n2),
                                          float(tau), int(kdim), int(nsteps),
                                          C.byref(inf) if info else None), self.h)
-        return inf.as_dict() if info else None
+        return inf.as_dict(nsteps) if info else None
 
     krylov_expm = dmrg_krylov_expm
 
@@ -331,11 +384,12 @@ class Handle:
         n2 = 2 * self.n
         e = C.c_double()
         used = C.c_int32()
-        inf = dmrg_krylov_info()
-        _check(self.lib.dmrg_ground_state(self.h, _tensor_ptr(x0, n2), _tensor_ptr(y, n2), int(kdim),
-                                          int(max_restarts), float(tol), C.byref(e), C.byref(used),
-                                          C.byref(inf) if info else None), self.h)
-        return e.value, used.value, (inf.as_dict() if info else None)
+        inf = _info(max_restarts)
+        rc = self.lib.dmrg_ground_state(self.h, _tensor_ptr(x0, n2), _tensor_ptr(y, n2), int(kdim),
+                                        int(max_restarts), float(tol), C.byref(e), C.byref(used),
+                                        C.byref(inf) if info else None)
+        _check(rc, self.h)      # DMRG_WNOTCONV: returned, info["converged"] = 0
+        return e.value, used.value, (inf.as_dict(used.value) if info else None)
 
     ground_state = dmrg_ground_state
 

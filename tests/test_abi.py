@@ -66,3 +66,50 @@ def test_create_rejects_bad_problems(lib):
     pb2.S.space.qn = pb2.S.space.qn[::-1].copy()
     rc, msg, h = _create_status(pb2)
     assert rc == -1 and "increasing" in msg
+
+
+# workloads of the GPU product parity tests (kept in step with tests/test_gpu_parity.py)
+_FLOP_CASES = ["chain4_exact", "chain8_exact", "ladder2x4_U10", "chain12_m30", "ladder2x6_m40",
+               "chain8_m17_odd", "chain14_m25_off", "chain20_m150", "chain32_m400",
+               "ladder16_m800", "ladder16_m1000", "ladder32_m2000"]
+
+
+@pytest.mark.parametrize("name", _FLOP_CASES)
+def test_plan_flops_equal_oracle(lib, name):
+    """The library's algorithmic flop count (the numerator of every throughput figure) is
+    exactly the oracle's, which test_oracle_matvec pins by a brute-force tally; the executed
+    count is never below it, and the host-only plan agrees with the vector length."""
+    from oracle import matvec as M
+    from tests.test_gpu_parity import problem
+    pb = problem(name)
+    st = L.plan_stats(pb)
+    assert st["flops"] == float(M.flop_count(pb))
+    assert st["flops_executed"] >= st["flops"]
+    assert st["n"] == M.layout(pb)[1]
+    assert st["create_bytes"] > 0 and st["krylov_bytes"] > 16 * st["n"] * 16
+
+
+def test_plan_stats_rejects_bad_problems(lib):
+    pb = I.exact_problem(4, 4.0, (9, 9))
+    with pytest.raises(L.DmrgError) as e:
+        L.plan_stats(pb)
+    assert e.value.status == -1 and "empty" in str(e.value)
+    with pytest.raises(L.DmrgError) as e:
+        L.plan_stats(I.exact_problem(4, 4.0, (2, 2)), kdim=65)
+    assert e.value.status == -1
+
+
+def test_workspace_cap_refuses_handle_before_any_device_call(lib):
+    """DMRG_MAX_WORKSPACE smaller than the handle's first buffer: DMRG_ENOMEM after the plan is
+    built and before any memory is requested (so this runs without a GPU); a value that is not
+    a byte count: DMRG_EINVAL."""
+    pb = I.exact_problem(6, 4.0, (3, 3))
+    need = L.plan_stats(pb)["create_bytes"]
+    for cap, code, text in [("1", -2, "DMRG_MAX_WORKSPACE"), (str(need // 1000), -2, "DMRG_MAX_WORKSPACE"),
+                            ("12kB", -1, "byte count")]:
+        os.environ["DMRG_MAX_WORKSPACE"] = cap
+        try:
+            rc, msg, h = _create_status(pb)
+        finally:
+            del os.environ["DMRG_MAX_WORKSPACE"]
+        assert rc == code and text in msg and not h.value, (cap, rc, msg)

@@ -99,12 +99,95 @@ def test_linear_and_real():
     assert np.all(yr[n:] == 0) and np.all(yi[:n] == 0)
 
 
-def test_flop_count_chain8():
-    """Algorithmic flop count of the exact L=8 chain superblock (fixed by the block dims)."""
-    pb = I.exact_problem(8, 4.0, (4, 4))
+def _brute_flops(pb):
+    """Flops of one H_sb . psi found without the sector tables of the oracle: every product is
+    located by scanning the dense operators of the dense-halves definition for nonzero
+    sub-blocks at the sector offsets, performed by a matmul that tallies 2 m k n per real plane
+    from the shapes it multiplies (and whose products are summed and compared with the dense
+    definition), both contraction orders of each term performed and the cheaper counted."""
     lay, n = M.layout(pb)
-    # brute force: count multiply-adds of the naive per-block products in the cheaper order
-    F = 0
+    offS, offE = M._offsets(pb.S.space.dim), M._offsets(pb.E.space.dim)
+    tally = [0]
+
+    def cmm(a, b):
+        tally[0] += 2 * 2 * a.shape[0] * a.shape[1] * b.shape[1]   # complex = two real planes
+        return a @ b
+
+    X = M.unpack(pb, I.random_psi(n, np.random.default_rng(3)))
+    blocks = {(p, q): (p, q) for (p, q, r, c, off) in lay}
+    HS, HE = M.dense_half(pb.S.space, pb.S.H), M.dense_half(pb.E.space, pb.E.H)
+    PS = np.diag(M.dense_parity(pb.S.space))
+    Y = {p: np.zeros_like(X[p]) for p in X}
     for (p, q, r, c, off) in lay:
-        F += 2 * 2 * (r * r * c + r * c * c)
-    assert M.flop_count(pb) > F and n == 4900
+        Y[p] += cmm(HS[offS[p]:offS[p + 1], offS[p]:offS[p + 1]], X[p])
+        Y[p] += cmm(X[p], HE[offE[q]:offE[q + 1], offE[q]:offE[q + 1]].T)
+    F = tally[0]
+    dense_terms = []
+    for bd in pb.bonds:
+        for s in (0, 1):
+            Ca = M.dense_op(pb.S.space, pb.S.ops[bd.opS[s]])
+            Cb = M.dense_op(pb.E.space, pb.E.ops[bd.opE[s]])
+            dense_terms.append((-bd.t, Ca @ PS, Cb))           # coef * L X R
+            dense_terms.append((-bd.t, PS @ Ca.T, Cb.T))
+    for coef, Lm, Rm in dense_terms:
+        for (p, q, r, c, off) in lay:
+            for p2 in range(len(pb.S.space.dim)):
+                A = Lm[offS[p2]:offS[p2 + 1], offS[p]:offS[p + 1]]
+                if not np.any(A):
+                    continue
+                for q2 in range(len(pb.E.space.dim)):
+                    B = Rm[offE[q]:offE[q + 1], offE[q2]:offE[q2 + 1]]
+                    if not np.any(B) or (p2, q2) not in blocks:
+                        continue
+                    t0 = tally[0]
+                    y1 = cmm(cmm(A, X[p]), B)
+                    f_left = tally[0] - t0
+                    t0 = tally[0]
+                    y2 = cmm(A, cmm(X[p], B))
+                    f_right = tally[0] - t0
+                    assert np.allclose(y1, y2, atol=1e-12)
+                    F += min(f_left, f_right)
+                    Y[p2] += coef * y1
+    assert np.allclose(M.pack(pb, Y), M.matvec_dense(pb, M.pack(pb, X)), atol=1e-12)
+    return F
+
+
+@pytest.mark.parametrize("name", ["chain8_exact", "chain14_m25_off", "ladder2x6_m40",
+                                  "ladder2x4_exact"])
+def test_flop_count_brute_force(name):
+    """Algorithmic flop count: exact integer equality with the brute-force tally, on exact
+    blocks, an off-half-filling chain (where the two contraction orders differ by several
+    percent, so counting the dearer order or a wrong factor fails) and a ladder."""
+    pb = _flop_problem(name)
+    assert M.flop_count(pb) == _brute_flops(pb)
+
+
+def test_flop_count_orders_differ_off_half_filling():
+    """The off-half-filling chain is a case where the cheaper order matters: the count with the
+    dearer order is more than 1% larger."""
+    pb = _flop_problem("chain14_m25_off")
+    lay, n = M.layout(pb)
+    qof = {p: q for (p, q, r, c, off) in lay}
+    dS, dE = pb.S.space.dim, pb.E.space.dim
+    F_max = sum(4 * (r * r * c + r * c * c) for (p, q, r, c, off) in lay)
+    for (coef, a, ta, b, tb, ferm) in M.terms(pb):
+        for (p, q, r, c, off) in lay:
+            A = M._op_block(pb.S.space, pb.S.ops[a], p, ta)
+            B = M._op_block(pb.E.space, pb.E.ops[b], q, tb)
+            if A is None or B is None or A[0] not in qof or not (np.any(A[1]) and np.any(B[1])):
+                continue
+            r2, c2 = int(dS[A[0]]), int(dE[B[0]])
+            F_max += 4 * max(r2 * r * c + r2 * c * c2, r * c * c2 + r2 * r * c2)
+    assert F_max > 1.01 * M.flop_count(pb)
+
+
+def _flop_problem(name):
+    if name == "chain8_exact":
+        return I.exact_problem(8, 4.0, (4, 4))
+    if name == "ladder2x4_exact":
+        return I.exact_problem(8, 10.0, (4, 4), bonds=I.ladder_bonds(4, 1.0, 0.5))
+    if name == "chain14_m25_off":
+        return I.synthetic_problem(14, 25, 2.0, I.chain_bonds(14), 9, name=name, target=(6, 8))
+    if name == "ladder2x6_m40":
+        return I.synthetic_problem(12, 40, 8.0, I.ladder_bonds(6), 8, name=name)
+    raise KeyError(name)
