@@ -46,6 +46,8 @@ MEASURED_TRAFFIC = {
 def kernel_name(stage: int, variant: int) -> str:
     """Name of the FP64 kernel that runs a stage under a dmrg_gemm variant (as profilers show it,
     without the namespace)."""
+    if variant & 16:
+        return "stage1x" if stage == 1 else "stage2x"
     if stage == 1:
         if variant & 1:
             return "stage1_lds<PF64>"

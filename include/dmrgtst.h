@@ -93,7 +93,12 @@ enum dmrg_gemm {
     DMRG_GEMM_STAGE1_LDS = 1,
     DMRG_GEMM_STAGE2_LDS = 2,
     DMRG_GEMM_STAGE1_NARROW = 4,
-    DMRG_GEMM_STAGE2_NARROW = 8
+    DMRG_GEMM_STAGE2_NARROW = 8,
+    DMRG_GEMM_X = 16      /* LDS-staged family for both stages (alone, no other bit): work groups
+                             of four wavefronts share every operand chunk through LDS (stage 1:
+                             64 x 64 tiles; stage 2: 64 x 32 tiles, long K as two slices added
+                             into an output its stage 1 zeroes).  FP64 only: other arithmetics,
+                             and plans whose stage-2 tiles exceed 256 chunks, run register-tiled. */
 };
 
 /* A block operator of one half that changes (N_up, N_dn) by dq.  blocks: for every source
@@ -232,9 +237,11 @@ int dmrg_get_gemm(dmrg_handle h, int32_t* variant);
 
 /* Autotuner: times the kernel families of each stage on the handle's problem in its current
  * arithmetic (reps back-to-back launches each, on zeroed scratch vectors the handle owns) and
- * keeps the fastest of each.  out: NULL or 6 doubles receiving milliseconds per launch of
- * [stage 1 register-tiled, stage 1 LDS-tiled, stage 2 register-tiled, stage 2 LDS-tiled,
- *  stage 1 register-tiled narrow, stage 2 register-tiled narrow].
+ * keeps the fastest of each; in FP64 the LDS-staged family is timed as a pair of stages and
+ * kept if the pair beats the best of the others.  out: NULL or 8 doubles receiving
+ * milliseconds per launch of [stage 1 register-tiled, stage 1 LDS-tiled, stage 2
+ * register-tiled, stage 2 LDS-tiled, stage 1 register-tiled narrow, stage 2 register-tiled
+ * narrow, stage 1 LDS-staged, stage 2 LDS-staged] (-1 where not timed).
  * Waits for the handle's stream. */
 int dmrg_autotune(dmrg_handle h, int32_t reps, double* out);
 

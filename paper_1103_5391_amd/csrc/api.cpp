@@ -28,6 +28,10 @@ hipError_t launch_stage1_lds(int, const S1Block*, const LItem1*, int, const Prob
                              hipStream_t);
 hipError_t launch_stage2_lds(int, const S2Block*, const Segment*, const LItem2*, int, const LRed*,
                              int, const ProbPtrs*, ProbPtrs, double*, hipStream_t);
+hipError_t launch_stage1_x(const S1Block*, const LItem1*, int, const S2Block*, const XZero*, int,
+                           const ProbPtrs*, ProbPtrs, hipStream_t);
+hipError_t launch_stage2_x(const S2Block*, const XChunk*, const XItem2*, int, const ProbPtrs*,
+                           ProbPtrs, hipStream_t);
 hipError_t launch_start(const VecGroup&, const double*, const double* const*, int, int,
                         hipStream_t);
 hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
@@ -105,7 +109,9 @@ struct DevBuf {
 // their partial-tile workspace.
 struct Lists {
     DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT1n, dT2, dT2n, dL1, dL2[2], dLred[2], dPart;
+    DevBuf dXch, dX2, dXz;    // LDS-staged family: chunk tables, stage-2 items, zeroed regions
     int nt1 = 0, nt1n = 0, nt2 = 0, nt2n = 0, nl1 = 0, nl2[2] = {0, 0}, nred[2] = {0, 0};
+    int nx2 = 0, nxz = 0;
     int variant = 0;    // DMRG_GEMM_* bits: which kernel family runs each stage
 };
 
@@ -126,7 +132,9 @@ hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vec
                         const std::vector<Tile>& t1n, const std::vector<Tile>& t2,
                         const std::vector<Tile>& t2n, const std::vector<LItem1>& l1,
                         const std::vector<LItem2>* l2, const std::vector<LRed>* lred,
-                        const int* nslots, hipStream_t st) {
+                        const int* nslots, const std::vector<XChunk>& xch,
+                        const std::vector<XItem2>& x2, const std::vector<XZero>& xz,
+                        hipStream_t st) {
     hipError_t e = hipSuccess;
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
         e = upload(W.dS1[k], s1[k], st);
@@ -140,6 +148,11 @@ hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vec
     if (e == hipSuccess) e = upload(W.dT2, t2, st);
     if (e == hipSuccess) e = upload(W.dT2n, t2n, st);
     if (e == hipSuccess) e = upload(W.dL1, l1, st);
+    if (e == hipSuccess) e = upload(W.dXch, xch, st);
+    if (e == hipSuccess) e = upload(W.dX2, x2, st);
+    if (e == hipSuccess) e = upload(W.dXz, xz, st);
+    W.nx2 = (int)x2.size();
+    W.nxz = (int)xz.size();
     const int slots = std::max(nslots[0], nslots[1]);
     if (e == hipSuccess) e = W.dPart.alloc(sizeof(double) * (size_t)slots * kLTile * kLTile);
     W.nt1 = (int)t1.size();
@@ -159,6 +172,18 @@ hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vec
 hipError_t run_stage(const Lists& W, int stage, int variant, int prec, const ProbPtrs* probs,
                      ProbPtrs single, hipStream_t s) {
     const int pk = prec >= DMRG_BF16X3 ? 1 : 0;
+    // the LDS-staged family: FP64, and only where the plan offers it (else register-tiled)
+    if (variant & DMRG_GEMM_X) {
+        if (prec == DMRG_FP64 && W.nx2 > 0) {
+            if (stage == 1)
+                return launch_stage1_x(W.dS1[0].as<S1Block>(), W.dL1.as<LItem1>(), W.nl1,
+                                       W.dS2[0].as<S2Block>(), W.dXz.as<XZero>(), W.nxz, probs,
+                                       single, s);
+            return launch_stage2_x(W.dS2[0].as<S2Block>(), W.dXch.as<XChunk>(), W.dX2.as<XItem2>(),
+                                   W.nx2, probs, single, s);
+        }
+        variant = 0;
+    }
     if (stage == 1) {
         if (variant & DMRG_GEMM_STAGE1_LDS)
             return launch_stage1_lds(prec, W.dS1[pk].as<S1Block>(), W.dL1.as<LItem1>(), W.nl1,
@@ -227,16 +252,29 @@ hipError_t autotune_lists(Lists& W, int prec, const ProbPtrs* probs, ProbPtrs si
     for (int i = 0; i < kCand; ++i)
         if (t[i] < t[best[stage[i] - 1]]) best[stage[i] - 1] = i;
     W.variant = cand[best[0]] | cand[best[1]];
-    if (out)
+    // the LDS-staged family runs both stages (its stage 1 zeroes what its stage 2 adds into):
+    // timed as a pair, kept if the pair is faster
+    double tx[2] = {-1.0, -1.0};
+    if (prec == DMRG_FP64 && W.nx2 > 0) {
+        for (int st = 1; st <= 2 && e == hipSuccess; ++st)
+            e = time_stage(W, st, DMRG_GEMM_X, prec, probs, single, s, reps, &tx[st - 1]);
+        if (e != hipSuccess) return e;
+        if (tx[0] + tx[1] < t[best[0]] + t[best[1]]) W.variant = DMRG_GEMM_X;
+    }
+    if (out) {
         for (int i = 0; i < kCand; ++i) out[i] = t[i];
+        out[kCand] = tx[0];
+        out[kCand + 1] = tx[1];
+    }
     return hipSuccess;
 }
 
 // Whether a dmrg_gemm variant is valid: known bits, at most one family per stage.
 bool valid_variant(int32_t variant) {
     constexpr int32_t known = DMRG_GEMM_STAGE1_LDS | DMRG_GEMM_STAGE2_LDS |
-                              DMRG_GEMM_STAGE1_NARROW | DMRG_GEMM_STAGE2_NARROW;
+                              DMRG_GEMM_STAGE1_NARROW | DMRG_GEMM_STAGE2_NARROW | DMRG_GEMM_X;
     if (variant & ~known) return false;
+    if ((variant & DMRG_GEMM_X) && variant != DMRG_GEMM_X) return false;
     if ((variant & DMRG_GEMM_STAGE1_LDS) && (variant & DMRG_GEMM_STAGE1_NARROW)) return false;
     return !((variant & DMRG_GEMM_STAGE2_LDS) && (variant & DMRG_GEMM_STAGE2_NARROW));
 }
@@ -644,7 +682,7 @@ int chains_set(std::unique_ptr<dmrg_batch_ctx>& cs, const std::vector<dmrg_ctx*>
         merge_plans(plans, M);
         const hipError_t e = upload_lists(c->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles1n,
                                           M.tiles2, M.tiles2n, M.l1, M.l2, M.lred, M.nslots,
-                                          h0->stream);
+                                          M.xch, M.x2, M.xz, h0->stream);
         if (e != hipSuccess)
             return fail(h0, e == hipErrorOutOfMemory ? DMRG_ENOMEM : DMRG_EHIP, hipGetErrorString(e));
     } catch (const std::bad_alloc&) {
@@ -1191,8 +1229,7 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
         const std::vector<LRed> lr[2] = {P.pk16.lred, P.pk32.lred};
         const int ns[2] = {P.pk16.nslots, P.pk32.nslots};
         e = upload_lists(h->lists, s1, s2, sg, P.tiles1, P.tiles1n, P.tiles2, P.tiles2n, P.l1, l2,
-                         lr, ns,
-                         h->stream);
+                         lr, ns, P.pk16.xch, P.pk16.x2, P.pk16.xz, h->stream);
     }
     if (e == hipSuccess) e = h->ws[0].dT.alloc(sizeof(double) * (size_t)P.T_size);
     // the padding rows of the stage-1 workspace are read (times zero factors) but never
@@ -1275,6 +1312,9 @@ int dmrg_plan_stats(const dmrg_problem* problem, int32_t kdim, dmrg_plan_info* o
         add(P.tiles2.size() * sizeof(Tile));
         add(P.tiles2n.size() * sizeof(Tile));
         add(P.l1.size() * sizeof(LItem1));
+        add(P.pk16.xch.size() * sizeof(XChunk));
+        add(P.pk16.x2.size() * sizeof(XItem2));
+        add(P.pk16.xz.size() * sizeof(XZero));
         add(sizeof(double) * (size_t)std::max(P.pk16.nslots, P.pk32.nslots) * kLTile * kLTile);
         add(sizeof(double) * (size_t)P.T_size);
         add(A.size());
@@ -1706,8 +1746,8 @@ int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out
         merge_plans(plans, M);
         b->lists.variant = h0->lists.variant;
         const hipError_t e = upload_lists(b->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles1n, M.tiles2,
-                                          M.tiles2n, M.l1,
-                                          M.l2, M.lred, M.nslots, h0->stream);
+                                          M.tiles2n, M.l1, M.l2, M.lred, M.nslots, M.xch, M.x2,
+                                          M.xz, h0->stream);
         if (e != hipSuccess) {
             delete b;
             return fail(h0, e == hipErrorOutOfMemory ? DMRG_ENOMEM : DMRG_EHIP, hipGetErrorString(e));

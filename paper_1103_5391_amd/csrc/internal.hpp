@@ -111,6 +111,36 @@ struct LRed {
     int32_t blk, m0, n0, slot0, nslice, pad;
 };
 
+// Work of the LDS-staged (X) block-product family: work groups of four wavefronts whose
+// operands are staged through double-buffered LDS in MFMA lane order.  Stage 1 takes the 64 x 64
+// tiles of the LDS-tiled family (LItem1); stage 2 takes 64 x 32 output tiles, the long ones cut
+// into two K slices that add into a zeroed output (two additions onto zero give the same bits in
+// either order).
+constexpr int kXTile2N = 32;        // stage-2 tile columns
+constexpr int kXSplitChunks = 40;   // stage-2 tiles with more 16-deep K chunks run as two slices
+constexpr int kXMaxItemChunks = 256;   // most chunks of one stage-2 item (its table in LDS); a
+                                       // plan with longer items does not offer the family
+// Source of one 16-deep K chunk of a stage-2 block: element (k, column n of plane p) of the
+// chunk's segment at off + p poff + col ld + k, k counted from the block's first chunk (the
+// segment's own start subtracted); src 0: the input vector (rows < K0 valid), 1: the workspace.
+struct XChunk {
+    int64_t off;
+    int64_t poff;
+    int32_t ld;
+    int32_t src;
+};
+// One stage-2 work group: output tile (m0, n0) of block blk, K chunks [kc0, kc1); mode 0: the
+// whole K, y = T0 + product; 1: first slice, y += T0 + product (atomic); 2: second slice,
+// y += product (atomic).  ctab0: first entry of the block's chunk table.
+struct XItem2 {
+    int32_t blk, m0, n0, kc0, kc1, mode, ctab0, pad;
+};
+// A 64 x 32 output region of stage-2 block blk (at m0, n0) that split tiles add into: zeroed by
+// extra work groups of the stage-1 launch.
+struct XZero {
+    int32_t blk, m0, n0, pad;
+};
+
 // Per-problem pointers for one launch of a stage (single problem: tables of length 1).
 struct ProbPtrs {
     const double* x;        // input vector

@@ -169,6 +169,7 @@ void tile_list(std::vector<Tile>& out, int blk, int M, int N, int tm, int tn) {
 }  // namespace
 
 void lds_lists(Plan& P);
+void x_lists(Plan& P);
 
 std::string build_plan(const dmrg_problem* pb, Plan& P) {
     if (!pb) return "problem is NULL";
@@ -332,7 +333,7 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
             }
             s.nseg = (int)pk->segs.size() - s.seg0;
             s.nch = nch;
-            aoff += (int64_t)round_up(B.d, kTile) * nch * ck;
+            aoff += (int64_t)round_up(B.d, kLTile) * nch * ck;   // whole 64-row tiles
             pk->s2.push_back(s);
         }
         pk->R_elems = roff;
@@ -357,7 +358,57 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
     P.w1 = std::move(w1);
     P.w2 = std::move(w2);
     lds_lists(P);
+    x_lists(P);
     return "";
+}
+
+// Work of the LDS-staged family: the chunk table of every stage-2 block (its segments' source
+// views, 16-deep chunks), 64 x 32 output tiles, those with more than kXSplitChunks chunks cut
+// into two slices of about equal length, and the output regions of the cut tiles.
+void x_lists(Plan& P) {
+    Packing& pk = P.pk16;
+    pk.xch.clear();
+    pk.x2.clear();
+    pk.xz.clear();
+    const int nb = (int)P.blocks.size();
+    std::vector<double> w(nb, 0.0);
+    std::vector<int> ctab0(nb, 0);
+    for (int bi = 0; bi < nb; ++bi) {
+        const S2Block& s = pk.s2[bi];
+        ctab0[bi] = (int)pk.xch.size();
+        for (int si = 0; si < s.nseg; ++si) {
+            const Segment& sg = pk.segs[s.seg0 + si];
+            const int nc = (sg.K + pk.ck - 1) / pk.ck;
+            for (int c = 0; c < nc; ++c)
+                pk.xch.push_back(XChunk{sg.B.off - (int64_t)sg.ch0 * pk.ck, sg.B.poff, sg.B.ld, sg.src});
+        }
+    }
+    auto panels = [](int v) { return (v + kPanel - 1) / kPanel; };
+    for (int bi = 0; bi < nb; ++bi) {
+        const S2Block& s = pk.s2[bi];
+        const bool split = s.nch > kXSplitChunks;
+        const int half = s.nch / 2;
+        for (int m0 = 0; m0 < s.M; m0 += kLTile)
+            for (int n0 = 0; n0 < s.N; n0 += kXTile2N) {
+                const double area = (double)std::min(4, panels(s.M - m0)) *
+                                    std::min(2, panels(s.N - n0));
+                if (split) {
+                    pk.x2.push_back(XItem2{bi, m0, n0, 0, half, 1, ctab0[bi], 0});
+                    pk.x2.push_back(XItem2{bi, m0, n0, half, s.nch, 2, ctab0[bi], 0});
+                    pk.xz.push_back(XZero{bi, m0, n0, 0});
+                } else {
+                    pk.x2.push_back(XItem2{bi, m0, n0, 0, s.nch, 0, ctab0[bi], 0});
+                }
+                w[bi] += area * (s.nch + 2);
+            }
+    }
+    pk.x2 = xcd_order(pk.x2, w, 1);
+    for (const XItem2& t : pk.x2)
+        if (t.kc1 - t.kc0 > kXMaxItemChunks) {   // the family needs every item's table in LDS
+            pk.x2.clear();
+            pk.xz.clear();
+            break;
+        }
 }
 
 // Work lists of the LDS-tiled kernels: 64 x 64 tiles; stage-2 tiles whose K exceeds a slice
@@ -412,6 +463,7 @@ void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
     std::vector<double> w1, w2;
     std::vector<LItem1> l1;
     std::vector<LItem2> l2[2];
+    std::vector<XItem2> x2;
     int boff = 0;
     for (size_t i = 0; i < plans.size(); ++i) {
         const Plan& P = *plans[i];
@@ -444,6 +496,20 @@ void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
                 t.blk += boff;
                 l1.push_back(t);
             }
+        {
+            const int coff = (int)out.xch.size();
+            out.xch.insert(out.xch.end(), P.pk16.xch.begin(), P.pk16.xch.end());
+            for (XItem2 t : P.pk16.x2)
+                if (t.blk >= 0) {
+                    t.blk += boff;
+                    t.ctab0 += coff;
+                    x2.push_back(t);
+                }
+            for (XZero z : P.pk16.xz) {
+                z.blk += boff;
+                out.xz.push_back(z);
+            }
+        }
         for (int k = 0; k < 2; ++k) {
             const int soff = out.nslots[k];
             for (LItem2 t : pks[k]->l2)
@@ -474,6 +540,9 @@ void merge_plans(const std::vector<const Plan*>& plans, Merged& out) {
         for (const LItem2& t : l2[k]) wl[t.blk] += (double)(t.kc1 - t.kc0 + 1);
         out.l2[k] = xcd_order(l2[k], wl, 1);
     }
+    std::fill(wl.begin(), wl.end(), 0.0);
+    for (const XItem2& t : x2) wl[t.blk] += (double)(t.kc1 - t.kc0 + 2);
+    out.x2 = xcd_order(x2, wl, 1);
 }
 
 namespace {

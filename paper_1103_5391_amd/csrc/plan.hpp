@@ -77,6 +77,11 @@ struct Packing {
     std::vector<LItem2> l2;
     std::vector<LRed> lred;
     int nslots = 0;                            // partial tiles
+    // LDS-staged family (16-deep chunks only): per-block chunk tables, stage-2 items, and the
+    // output regions its split items add into
+    std::vector<XChunk> xch;
+    std::vector<XItem2> x2;
+    std::vector<XZero> xz;
 };
 
 struct Plan {
@@ -116,6 +121,9 @@ struct Merged {
     std::vector<LItem2> l2[2];
     std::vector<LRed> lred[2];
     int nslots[2] = {0, 0};
+    std::vector<XChunk> xch;                  // LDS-staged family (16-deep chunks)
+    std::vector<XItem2> x2;
+    std::vector<XZero> xz;
 };
 void merge_plans(const std::vector<const Plan*>& plans, Merged& out);
 
