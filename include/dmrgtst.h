@@ -260,6 +260,24 @@ int dmrg_set_check_finite(dmrg_handle h, int32_t enable);
  * x and y must not overlap.  Asynchronous on the handle's stream. */
 int dmrg_matvec(dmrg_handle h, const double* x, double* y, int32_t nvec);
 
+/* Bytes of device scratch per GPU held by the library for dmrg_matvec_noalloc. */
+#define DMRG_NOALLOC_SCRATCH_BYTES (64LL << 20)
+
+/* dmrg_matvec for callers that cannot allocate device memory during the call: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid allocation.  Same arguments,
+ * arithmetic and results (the same kernels and the same bits) as dmrg_matvec.  The call makes
+ * no device allocation and no free: the stage-1 intermediate, which dmrg_matvec keeps in the
+ * handle, lives here in a library-owned array of DMRG_NOALLOC_SCRATCH_BYTES on each GPU (held
+ * from the library's load on that GPU until the process ends; its address is resolved by
+ * dmrg_create).  Each call first clears the part it uses, with a kernel on the handle's stream.
+ *   Every call on one GPU, from any handle, shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams, other threads) race and give wrong results; order them on one
+ * stream.  The optional non-finite check (dmrg_set_check_finite) is not run.
+ * Errors: DMRG_EINVAL for a null handle, negative nvec, null vectors with nvec > 0, or a
+ * problem whose intermediate needs more than DMRG_NOALLOC_SCRATCH_BYTES (message via
+ * dmrg_last_error; nothing is launched); DMRG_EHIP. */
+int dmrg_matvec_noalloc(dmrg_handle h, const double* x, double* y, int32_t nvec);
+
 /* y = (exp(-i tau H_sb))^nsteps x: nsteps Krylov steps of size kdim (1 <= kdim <= 64), each
  * from a fresh Lanczos basis of the current vector (Sec. II.A, Eq. lanczosevolution2).
  * x, y: device vectors; y may equal x.  If info is non-NULL the call waits for the stream

@@ -46,6 +46,7 @@ hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const 
                       hipStream_t);
 hipError_t launch_zgemm(const ZTile*, int, const ZPtrs&, int, int, int, hipStream_t);
 hipError_t launch_zero(double*, int64_t, hipStream_t);
+hipError_t noalloc_scratch(double**);
 hipError_t launch_local_mono(const SJob*, int, int64_t, const int*, const double*, const int*,
                              const double*, const double*, int64_t, double*, int64_t, hipStream_t);
 hipError_t launch_zdot(const double*, const double*, int64_t, double*, int, hipStream_t);
@@ -1249,6 +1250,18 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
         delete h;
         return rc;
     }
+    {
+        // set-up of the allocation-free entry point: the scratch array's address on this
+        // device (once per device), resolved here so that later calls make no runtime query
+        double* scr = nullptr;
+        e = noalloc_scratch(&scr);
+        if (e != hipSuccess) {
+            g_create_error = std::string("device scratch of the allocation-free entry point: ") +
+                             hipGetErrorString(e);
+            delete h;
+            return DMRG_EHIP;
+        }
+    }
     *out = h;
     return DMRG_OK;
 }
@@ -1384,6 +1397,34 @@ int dmrg_matvec(dmrg_handle h, const double* x, double* y, int32_t nvec) {
     for (int v = 0; v < nvec; ++v) {
         int rc = matvec_one(h, x + v * vs, y + v * vs);
         if (rc) return rc;
+    }
+    return DMRG_OK;
+}
+
+int dmrg_matvec_noalloc(dmrg_handle h, const double* x, double* y, int32_t nvec) {
+    static_assert(kNoAllocScratchBytes == (size_t)DMRG_NOALLOC_SCRATCH_BYTES,
+                  "scratch size of the header and of the library differ");
+    if (!h) return DMRG_EINVAL;
+    if (nvec < 0 || (nvec > 0 && (!x || !y))) return fail(h, DMRG_EINVAL, "bad vectors");
+    if (nvec == 0) return DMRG_OK;
+    const int64_t tn = h->plan.T_size;
+    if ((size_t)tn * sizeof(double) > kNoAllocScratchBytes)
+        return fail(h, DMRG_EINVAL, "the stage-1 intermediate takes " +
+                                        std::to_string((size_t)tn * sizeof(double)) +
+                                        " bytes, above the " +
+                                        std::to_string(kNoAllocScratchBytes) +
+                                        " bytes of the allocation-free scratch");
+    double* T = nullptr;
+    HIP_TRY(h, noalloc_scratch(&T));
+    // the array holds whatever the last call on this GPU left: the intermediate's padding rows
+    // meet zero factors and must be finite, so the used region starts from zeros (a fill
+    // kernel, so that a captured call clears it on every replay)
+    HIP_TRY(h, launch_zero(T, tn, h->stream));
+    const int64_t vs = 2 * h->plan.n;
+    for (int v = 0; v < nvec; ++v) {
+        ProbPtrs pp = make_ptrs(h, h->precision, x + v * vs, y + v * vs, nullptr);
+        pp.T = T;
+        HIP_TRY(h, run_stages(h->lists, h->precision, nullptr, pp, h->stream));
     }
     return DMRG_OK;
 }

@@ -25,6 +25,9 @@ constexpr int kDMaxQ = (kMaxKrylov + kDSlots - 1) / kDSlots;   // reduction laun
 #endif
 constexpr int kRedElems = DMRG_RED_ELEMS;  // complex elements per thread of a reduction pass
 constexpr int kMaxTimes = 4;        // time points evaluated from one Krylov basis
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;   // device scratch per GPU of the
+                                    // allocation-free entry point (the public header's
+                                    // DMRG_NOALLOC_SCRATCH_BYTES)
 constexpr int kXcd = 8;             // MI355X: 8 XCDs of 32 CUs, each with its own L2; work
                                     // group i of a launch runs on XCD i mod 8
 

@@ -28,7 +28,7 @@ DMRG_WNOTCONV = 1
 SYMBOLS = [
     "dmrg_create", "dmrg_destroy", "dmrg_psi_layout", "dmrg_flops", "dmrg_flops_executed",
     "dmrg_set_precision", "dmrg_set_check_finite", "dmrg_plan_stats",
-    "dmrg_set_stream", "dmrg_matvec", "dmrg_krylov_expm", "dmrg_tst_targets", "dmrg_set_graph",
+    "dmrg_set_stream", "dmrg_matvec", "dmrg_matvec_noalloc", "dmrg_krylov_expm", "dmrg_tst_targets", "dmrg_set_graph",
     "dmrg_set_gemm", "dmrg_get_gemm", "dmrg_autotune",
     "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_set_graph", "dmrg_batch_tst_targets",
     "dmrg_batch_set_gemm", "dmrg_batch_autotune", "dmrg_profile_matvec",
@@ -126,6 +126,7 @@ def load(path: str = LIB_PATH):
     lib.dmrg_set_precision.argtypes = [vp, i32]
     lib.dmrg_set_stream.argtypes = [vp, vp]
     lib.dmrg_matvec.argtypes = [vp, vp, vp, i32]
+    lib.dmrg_matvec_noalloc.argtypes = [vp, vp, vp, i32]
     lib.dmrg_krylov_expm.argtypes = [vp, vp, vp, dbl, i32, i32, P(dmrg_krylov_info)]
     lib.dmrg_tst_targets.argtypes = [vp, vp, dbl, i32, vp, P(dbl), P(dmrg_krylov_info)]
     lib.dmrg_set_graph.argtypes = [vp, i32]
@@ -341,6 +342,15 @@ class Handle:
                                     int(nvec)), self.h)
 
     matvec = dmrg_matvec
+
+    def dmrg_matvec_noalloc(self, x, y, nvec: int = 1):
+        """As dmrg_matvec, with the intermediate in the library's per-GPU scratch (no device
+        allocation in the call; the problem's intermediate must fit the scratch)."""
+        n2 = 2 * self.n
+        _check(self.lib.dmrg_matvec_noalloc(self.h, _tensor_ptr(x, n2, nvec),
+                                            _tensor_ptr(y, n2, nvec), int(nvec)), self.h)
+
+    matvec_noalloc = dmrg_matvec_noalloc
 
     def dmrg_krylov_expm(self, x, y, tau: float, kdim: int, nsteps: int = 1, info: bool = True):
         """y = exp(-i tau H)^nsteps x; returns the info dict (with k_eff_steps per step)."""
