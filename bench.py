@@ -29,16 +29,15 @@ PEAK_FP32_TFLOPS = 157.3         # dense FP32 MFMA
 PEAK_BF16_TFLOPS = 2500.0        # dense BF16 MFMA (no sparsity)
 PEAK_HBM_GBS = 8000.0
 
-# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of this
-# bench on this workload, scaled by the readings of a plain 512 MiB copy (summary and commands
-# in profiles/).  Valid only for the kernel source they were taken on: reported as null once
-# the source differs.
+# HBM bytes per launch of the block-product kernels, from rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
+# this bench on this workload with the families fixed (--gemm 12), scaled by the readings of a
+# plain 512 MiB copy (summary and commands in profiles/).  Valid only for the kernel source they
+# were taken on: reported as null once the source differs.
 MEASURED_TRAFFIC = {
-    "kernel": "stage2<PF64, 1, 4>",
     "workload": "ladder16_m1000",
     "source": "paper_1103_5391_amd/csrc/gemm.hip",
-    "source_sha256": "b77e06c0d246e917d715002a31ca0250cf2d152dac785479a1a2835ae704666d",
-    "bytes": 83.62e6 + 5.12e6,
+    "source_sha256": "9cd19620cd124491004db22a3d04538ef1e390b35a4c60743f9748d8cf8d8a77",
+    "bytes": {"stage2<PF64, 1, 4>": 85.24e6 + 5.19e6, "stage1<PF64, 2>": 30.29e6 + 43.54e6},
     "profile": "profiles/stage2_fp64_ladder16_m1000_kernel_stats.txt",
 }
 
@@ -65,10 +64,9 @@ def measured_traffic(workload: str, kernel: str):
             sha = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if (sha != MEASURED_TRAFFIC["source_sha256"] or workload != MEASURED_TRAFFIC["workload"]
-            or kernel != MEASURED_TRAFFIC["kernel"]):
+    if sha != MEASURED_TRAFFIC["source_sha256"] or workload != MEASURED_TRAFFIC["workload"]:
         return None
-    return MEASURED_TRAFFIC["bytes"]
+    return MEASURED_TRAFFIC["bytes"].get(kernel)
 
 
 def _cpu_threads() -> int:
@@ -102,7 +100,7 @@ def cpu_baseline(pb, phi, kdim, tau, F, budget_s=12.0, dens=None):
             break
     per = float(np.median(times))
     out = {"value": kdim * F / per / 1e12, "unit": "TFLOP/s", "cores": _cpu_threads(),
-           "kind": "oracle", "steps_per_s": 1.0 / per,
+           "os_cpu_count": os.cpu_count(), "kind": "oracle", "steps_per_s": 1.0 / per,
            "sample": f"{len(times)} full time-step-targeting step(s) of the same workload "
                      f"(kdim={kdim}, oracle FP64 NumPy/SciPy), median of the step times, "
                      f"{el:.1f} s timed"}
@@ -205,6 +203,126 @@ def batch_section(L, I, torch, steps, warmup, count=64):
     return out
 
 
+def _oracle_steps(fn, budget_s):
+    """Median seconds of fn() over repeats for about budget_s seconds (at least one)."""
+    import numpy as np
+    times = []
+    t0 = time.perf_counter()
+    while True:
+        t1 = time.perf_counter()
+        fn()
+        times.append(time.perf_counter() - t1)
+        el = time.perf_counter() - t0
+        if el >= budget_s or el / len(times) * (len(times) + 1) > 2.5 * budget_s:
+            break
+    return float(np.median(times)), len(times), el
+
+
+def configs_section(L, I, torch, steps, warmup, cpu_budget, run_cpu):
+    """The smaller configurations, each on its own handle:
+      chain8_exact   Hubbard chain L = 8, U = 4, exact blocks: one product, then 10 Krylov steps
+                     (kdim 12, tau 0.1) in FP64; relative error against the oracle's 10 steps
+      chain32_m400   chain L = 32, m = 400: time-step-targeting steps (kdim 15) in FP64 and with
+                     FP32 block products
+      ladder16_m800  ladder 2x16, U = 8, m = 800: the same in FP64 and with BF16x3 products
+    and the FP64 oracle on the host for the first two (the same inputs)."""
+    import numpy as np
+    from oracle import krylov as K
+    from oracle import matvec as M
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        for _ in range(warmup):
+            fn()
+        torch.cuda.synchronize()
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out, cpu = {}, {}
+    # chain L = 8, exact blocks
+    name = "chain8_exact"
+    w = I.WORKLOADS[name]
+    pb = I.make_workload(name)
+    h = L.dmrg_create(pb, stream)
+    h.set_gemm(h.autotune(reps=5)["variant"])
+    F = h.flops()
+    x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + w["seed"]))
+    xd = torch.from_numpy(x).to("cuda")
+    yd = torch.empty_like(xd)
+    ms_mv = timed(lambda: h.matvec(xd, yd), 50)
+    ms_k = timed(lambda: h.krylov_expm(xd, yd, w["tau"], w["kdim"], w["nsteps"], info=False), 5)
+    apply_h = lambda v: M.matvec_sector(pb, v)
+    y_ref, _ = K.krylov_expm(apply_h, x, w["tau"], w["kdim"], w["nsteps"])
+    err = float(np.linalg.norm(yd.cpu().numpy() - y_ref) / np.linalg.norm(y_ref))
+    out[name] = {"n_complex": h.n, "flops_per_matvec": F, "matvec_ms": round(ms_mv, 5),
+                 "krylov_ms_per_step": round(ms_k / w["nsteps"], 5),
+                 "krylov_steps_per_s": round(1000.0 * w["nsteps"] / ms_k, 2),
+                 "kdim": w["kdim"], "tau": w["tau"], "nsteps": w["nsteps"],
+                 "rel_err_vs_oracle": err}
+    if run_cpu:
+        per, cnt, el = _oracle_steps(lambda: K.krylov_expm(apply_h, x, w["tau"], w["kdim"], 1),
+                                     cpu_budget / 4)
+        cpu[name] = {"ms_per_krylov_step": round(per * 1e3, 4), "steps_per_s": round(1.0 / per, 2),
+                     "tflops": w["kdim"] * F / per / 1e12,
+                     "gpu_speedup": round(per * 1e3 / (ms_k / w["nsteps"]), 2),
+                     "sample": f"{cnt} oracle Krylov steps (kdim {w['kdim']}), median, {el:.1f} s"}
+    h.destroy()
+    print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
+
+    # synthetic superblocks with a mixed arithmetic beside FP64
+    for name, prec, label in [("chain32_m400", L.DMRG_FP32, "fp32"),
+                              ("ladder16_m800", L.DMRG_BF16X3, "bf16x3")]:
+        w = I.WORKLOADS[name]
+        pb = I.make_workload(name)
+        h = L.dmrg_create(pb, stream)
+        F = h.flops()
+        x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + w["seed"] + 1000))
+        xd = torch.from_numpy(x).to("cuda")
+        td = torch.empty(8 * h.n, dtype=torch.float64, device="cuda")
+        yd = torch.empty_like(xd)
+        res = {"n_complex": h.n, "flops_per_matvec": F, "kdim": w["kdim"], "tau": w["tau"]}
+        ref = None
+        for pr, lab in [(L.DMRG_FP64, "fp64"), (prec, label)]:
+            h.set_precision(pr)
+            h.set_gemm(h.autotune(reps=5)["variant"])
+            ms = timed(lambda: h.tst_targets(xd, w["tau"], w["kdim"], td, info=False), steps)
+            pm = h.profile_matvec(xd, yd, reps=10)
+            ms_mv = pm["ms_stage1"] + pm["ms_stage2"]
+            r = {"ms_per_step": round(ms, 5), "krylov_steps_per_s": round(1000.0 / ms, 2),
+                 "matvec_ms": round(ms_mv, 5), "matvec_tflops": round(F / (ms_mv * 1e-3) / 1e12, 4),
+                 "step_tflops": round(w["kdim"] * F / (ms * 1e-3) / 1e12, 4)}
+            if ref is None:
+                ref = td.clone()
+            else:
+                n2 = 2 * h.n
+                r["tst_rel_err_vs_fp64"] = max(
+                    float(torch.linalg.vector_norm(td[n2 * i:n2 * (i + 1)] - ref[n2 * i:n2 * (i + 1)])
+                          / torch.linalg.vector_norm(ref[n2 * i:n2 * (i + 1)])) for i in range(4))
+                r["norm_drift"] = max(abs(float(torch.linalg.vector_norm(td[n2 * i:n2 * (i + 1)])) - 1.0)
+                                      for i in range(4))
+                r["speedup_vs_fp64"] = round(res["fp64"]["ms_per_step"] / ms, 3)
+            res[lab] = r
+        out[name] = res
+        if run_cpu and name == "chain32_m400":
+            apply_h = lambda v, pb=pb: M.matvec_sector(pb, v)
+            per, cnt, el = _oracle_steps(lambda: K.tst_targets(apply_h, x, w["tau"], w["kdim"]),
+                                         cpu_budget / 2)
+            cpu[name] = {"ms_per_step": round(per * 1e3, 3), "steps_per_s": round(1.0 / per, 3),
+                         "tflops": w["kdim"] * F / per / 1e12,
+                         "gpu_fp64_speedup": round(per * 1e3 / res["fp64"]["ms_per_step"], 2),
+                         "sample": f"{cnt} oracle time-step-targeting steps (kdim {w['kdim']}), "
+                                   f"median, {el:.1f} s"}
+        h.destroy()
+        print(f"[bench] {name}: {out[name]}", file=sys.stderr, flush=True)
+    return out, cpu
+
+
 def drift_section(L, I, torch, name="ladder32_m2000", steps=50):
     """Config-5 drift: the ladder 2x32 at m = 2000 evolved by `steps` Krylov steps (kdim 20,
     tau 0.05) in every arithmetic from the holon-doublon-like start psi = (c+_{s1 up} P_S) (x)
@@ -264,9 +382,10 @@ def drift_section(L, I, torch, name="ladder32_m2000", steps=50):
         print(f"[bench] drift {label}: {out[label]}", file=sys.stderr, flush=True)
     hp.destroy()
     he.destroy()
-    return {"workload": name, "steps": steps, "kdim": w["kdim"], "tau": w["tau"], "energy0": e0,
-            "initial_state": "(c+_{s1 up} P_S) x c_{s2 dn} psi0, normalised",
-            "sector": list(tgt), "n_complex": n, "per_arithmetic": out}
+    res = {"workload": name, "steps": steps, "kdim": w["kdim"], "tau": w["tau"], "energy0": e0,
+           "initial_state": "(c+_{s1 up} P_S) x c_{s2 dn} psi0, normalised",
+           "sector": list(tgt), "n_complex": n, "per_arithmetic": out}
+    return res, (pb, psi0.cpu().numpy(), out["fp64"]["ms_per_step_incl_energy"])
 
 
 def main():
@@ -285,10 +404,16 @@ def main():
                     help="skip the density-matrix + truncation run (and the transformation)")
     ap.add_argument("--no-wft", action="store_true", help="skip the wave-function transformation")
     ap.add_argument("--no-local", action="store_true", help="skip the local-operator run")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the smaller configurations (chain L = 8, chain m = 400, ladder m = 800)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="copy a buffer of MIB MiB once before the run: a plain copy kernel of "
                          "known traffic that hardware-counter runs use as the byte scale")
     ap.add_argument("--cpu-budget", type=float, default=12.0)
+    ap.add_argument("--gemm", type=int, default=-1, metavar="VARIANT",
+                    help="kernel families of the FP64 block products (dmrg_set_gemm bits) instead "
+                         "of the autotuner's choice, e.g. for hardware-counter runs that must "
+                         "see one family")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -315,8 +440,11 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     h = L.dmrg_create(pb, stream)
-    # the library's autotuner picks the kernel family of each block-product stage
+    # the library's autotuner picks the kernel family of each block-product stage (unless fixed)
     tune64 = h.autotune(reps=10)
+    if args.gemm >= 0:
+        h.set_gemm(args.gemm)
+        tune64["variant"] = args.gemm
     F = h.flops()
     n = h.n
     phi = I.random_psi(n, np.random.default_rng(I.SEED_BASE + w["seed"] + 1000))
@@ -540,10 +668,16 @@ def main():
         batched = batch_section(L, I, torch, max(3, args.steps // 5), 1)
         print(f"[bench] batched: {batched}", file=sys.stderr, flush=True)
 
-    drift = None
+    configs, cpu_configs = None, {}
+    if not args.no_configs:
+        print("[bench] smaller configurations", file=sys.stderr, flush=True)
+        configs, cpu_configs = configs_section(L, I, torch, max(5, args.steps // 3), args.warmup,
+                                               args.cpu_budget, not args.no_cpu_baseline)
+
+    drift, drift_host = None, None
     if not args.no_drift:
         print("[bench] drift (ladder 2x32, m = 2000, 50 steps)", file=sys.stderr, flush=True)
-        drift = drift_section(L, I, torch)
+        drift, drift_host = drift_section(L, I, torch)
 
     value = kdim * F / (ms_step * 1e-3) / 1e12
     out = {
@@ -576,6 +710,7 @@ def main():
         "local_operators": local,
         "mixed_precision": mixed,
         "batched_64": batched,
+        "configs": configs,
         "drift_m2000": drift,
         "roofline": {"bound": "mfma", "kernel": kernel_name(dom, int(tune64["variant"])),
                      "achieved": round(achieved, 4), "peak": PEAK_FP64_TFLOPS,
@@ -588,6 +723,20 @@ def main():
     if not args.no_cpu_baseline:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(pb, phi, kdim, tau, F, args.cpu_budget, dens_host)
+        if drift_host is not None:
+            # one oracle Krylov step of the m = 2000 ladder from the drift run's start vector
+            from oracle import krylov as K
+            from oracle import matvec as M
+            pb5, psi5, gpu_ms = drift_host
+            w5 = I.WORKLOADS["ladder32_m2000"]
+            t1 = time.perf_counter()
+            K.krylov_expm(lambda v: M.matvec_sector(pb5, v), psi5, w5["tau"], w5["kdim"], 1)
+            per = time.perf_counter() - t1
+            cpu_configs["ladder32_m2000"] = {
+                "ms_per_krylov_step": round(per * 1e3, 1), "steps_per_s": round(1.0 / per, 4),
+                "gpu_fp64_speedup_incl_energy": round(per * 1e3 / gpu_ms, 1),
+                "sample": f"1 oracle Krylov step (kdim {w5['kdim']}) from the drift run's start vector"}
+        out["cpu_baseline"]["configs"] = cpu_configs
     print(json.dumps(out), flush=True)
 
 
