@@ -94,11 +94,17 @@ enum dmrg_gemm {
     DMRG_GEMM_STAGE2_LDS = 2,
     DMRG_GEMM_STAGE1_NARROW = 4,
     DMRG_GEMM_STAGE2_NARROW = 8,
-    DMRG_GEMM_X = 16      /* LDS-staged family for both stages (alone, no other bit): work groups
+    DMRG_GEMM_X = 16,     /* LDS-staged family for both stages (alone, no other bit): work groups
                              of four wavefronts share every operand chunk through LDS (stage 1:
                              64 x 64 tiles; stage 2: 64 x 32 tiles, long K as two slices added
                              into an output its stage 1 zeroes).  FP64 only: other arithmetics,
                              and plans whose stage-2 tiles exceed 256 chunks, run register-tiled. */
+    DMRG_GEMM_K = 32      /* K-split family for both stages (alone, no other bit): the 4x4x4 FP64
+                             MFMA with its four blocks as four K slices, operands packed in lane
+                             order (the input vector packed by a first kernel of stage 1, the
+                             stage-1 intermediate written in stage 2's operand layout).  FP64
+                             only (other arithmetics run register-tiled); single handles only
+                             (merged batch lists run register-tiled). */
 };
 
 /* A block operator of one half that changes (N_up, N_dn) by dq.  blocks: for every source
@@ -237,11 +243,12 @@ int dmrg_get_gemm(dmrg_handle h, int32_t* variant);
 
 /* Autotuner: times the kernel families of each stage on the handle's problem in its current
  * arithmetic (reps back-to-back launches each, on zeroed scratch vectors the handle owns) and
- * keeps the fastest of each; in FP64 the LDS-staged family is timed as a pair of stages and
- * kept if the pair beats the best of the others.  out: NULL or 8 doubles receiving
+ * keeps the fastest of each; in FP64 the LDS-staged and the K-split families are timed as pairs
+ * of stages and kept if a pair beats the best of the others.  out: NULL or 10 doubles receiving
  * milliseconds per launch of [stage 1 register-tiled, stage 1 LDS-tiled, stage 2
  * register-tiled, stage 2 LDS-tiled, stage 1 register-tiled narrow, stage 2 register-tiled
- * narrow, stage 1 LDS-staged, stage 2 LDS-staged] (-1 where not timed).
+ * narrow, stage 1 LDS-staged, stage 2 LDS-staged, stage 1 K-split, stage 2 K-split] (-1 where
+ * not timed).
  * Waits for the handle's stream. */
 int dmrg_autotune(dmrg_handle h, int32_t reps, double* out);
 
@@ -274,7 +281,8 @@ int dmrg_matvec(dmrg_handle h, const double* x, double* y, int32_t nvec);
  * on one GPU (other streams, other threads) race and give wrong results; order them on one
  * stream.  The optional non-finite check (dmrg_set_check_finite) is not run.
  * Errors: DMRG_EINVAL for a null handle, negative nvec, null vectors with nvec > 0, or a
- * problem whose intermediate needs more than DMRG_NOALLOC_SCRATCH_BYTES (message via
+ * problem whose intermediate, in the layout of the handle's block-product family (the K-split
+ * family pads it more), needs more than DMRG_NOALLOC_SCRATCH_BYTES (message via
  * dmrg_last_error; nothing is launched); DMRG_EHIP. */
 int dmrg_matvec_noalloc(dmrg_handle h, const double* x, double* y, int32_t nvec);
 

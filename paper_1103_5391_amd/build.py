@@ -27,7 +27,7 @@ LIB_SAN = os.path.join(HERE, "_build", "libdmrgtst_san.so")
 OBJDIR = os.path.join(HERE, "_build")
 HOST_SOURCES = ["csrc/api.cpp", "csrc/plan.cpp"]
 DEVICE_SOURCES = ["csrc/gemm.hip", "csrc/gemm_lds.hip", "csrc/gemm_x.hip", "csrc/krylov.hip",
-                  "csrc/density.hip", "csrc/wft.hip", "csrc/noalloc.hip"]
+                  "csrc/density.hip", "csrc/wft.hip", "csrc/noalloc.hip", "csrc/gemm_k.hip"]
 SOURCES = HOST_SOURCES + DEVICE_SOURCES
 ARCH = os.environ.get("DMRG_OFFLOAD_ARCH", "gfx950")
 

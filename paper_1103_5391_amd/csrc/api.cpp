@@ -32,6 +32,10 @@ hipError_t launch_stage1_x(const S1Block*, const LItem1*, int, const S2Block*, c
                            const ProbPtrs*, ProbPtrs, hipStream_t);
 hipError_t launch_stage2_x(const S2Block*, const XChunk*, const XItem2*, int, const ProbPtrs*,
                            ProbPtrs, hipStream_t);
+hipError_t launch_stage1_k(const KXBlock*, const KPItem*, int, const KS1Block*, const KEdgeOut*,
+                           const KTile*, int, const ProbPtrs*, ProbPtrs, hipStream_t);
+hipError_t launch_stage2_k(const KS2Block*, const int64_t*, const KTile*, int, const ProbPtrs*,
+                           ProbPtrs, hipStream_t);
 hipError_t launch_start(const VecGroup&, const double*, const double* const*, int, int,
                         hipStream_t);
 hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
@@ -111,8 +115,10 @@ struct DevBuf {
 struct Lists {
     DevBuf dS1[2], dS2[2], dSeg[2], dT1, dT1n, dT2, dT2n, dL1, dL2[2], dLred[2], dPart;
     DevBuf dXch, dX2, dXz;    // LDS-staged family: chunk tables, stage-2 items, zeroed regions
+    DevBuf dKX, dKP, dKS1, dKE, dKT1, dKS2, dKC, dKT2;   // K-split family
     int nt1 = 0, nt1n = 0, nt2 = 0, nt2n = 0, nl1 = 0, nl2[2] = {0, 0}, nred[2] = {0, 0};
     int nx2 = 0, nxz = 0;
+    int nkp = 0, nkt1 = 0, nkt2 = 0;
     int variant = 0;    // DMRG_GEMM_* bits: which kernel family runs each stage
 };
 
@@ -135,7 +141,7 @@ hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vec
                         const std::vector<LItem2>* l2, const std::vector<LRed>* lred,
                         const int* nslots, const std::vector<XChunk>& xch,
                         const std::vector<XItem2>& x2, const std::vector<XZero>& xz,
-                        hipStream_t st) {
+                        const KLists& kf, hipStream_t st) {
     hipError_t e = hipSuccess;
     for (int k = 0; k < 2 && e == hipSuccess; ++k) {
         e = upload(W.dS1[k], s1[k], st);
@@ -154,6 +160,17 @@ hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vec
     if (e == hipSuccess) e = upload(W.dXz, xz, st);
     W.nx2 = (int)x2.size();
     W.nxz = (int)xz.size();
+    if (e == hipSuccess) e = upload(W.dKX, kf.xblk, st);
+    if (e == hipSuccess) e = upload(W.dKP, kf.pitems, st);
+    if (e == hipSuccess) e = upload(W.dKS1, kf.s1, st);
+    if (e == hipSuccess) e = upload(W.dKE, kf.eout, st);
+    if (e == hipSuccess) e = upload(W.dKT1, kf.t1, st);
+    if (e == hipSuccess) e = upload(W.dKS2, kf.s2, st);
+    if (e == hipSuccess) e = upload(W.dKC, kf.ctab, st);
+    if (e == hipSuccess) e = upload(W.dKT2, kf.t2, st);
+    W.nkp = (int)kf.pitems.size();
+    W.nkt1 = (int)kf.t1.size();
+    W.nkt2 = (int)kf.t2.size();
     const int slots = std::max(nslots[0], nslots[1]);
     if (e == hipSuccess) e = W.dPart.alloc(sizeof(double) * (size_t)slots * kLTile * kLTile);
     W.nt1 = (int)t1.size();
@@ -173,6 +190,18 @@ hipError_t upload_lists(Lists& W, const std::vector<S1Block>* s1, const std::vec
 hipError_t run_stage(const Lists& W, int stage, int variant, int prec, const ProbPtrs* probs,
                      ProbPtrs single, hipStream_t s) {
     const int pk = prec >= DMRG_BF16X3 ? 1 : 0;
+    // the K-split family: FP64, and only where the lists offer it (else register-tiled)
+    if (variant & DMRG_GEMM_K) {
+        if (prec == DMRG_FP64 && W.nkt2 > 0) {
+            if (stage == 1)
+                return launch_stage1_k(W.dKX.as<KXBlock>(), W.dKP.as<KPItem>(), W.nkp,
+                                       W.dKS1.as<KS1Block>(), W.dKE.as<KEdgeOut>(),
+                                       W.dKT1.as<KTile>(), W.nkt1, probs, single, s);
+            return launch_stage2_k(W.dKS2.as<KS2Block>(), W.dKC.as<int64_t>(), W.dKT2.as<KTile>(),
+                                   W.nkt2, probs, single, s);
+        }
+        variant = 0;
+    }
     // the LDS-staged family: FP64, and only where the plan offers it (else register-tiled)
     if (variant & DMRG_GEMM_X) {
         if (prec == DMRG_FP64 && W.nx2 > 0) {
@@ -262,10 +291,22 @@ hipError_t autotune_lists(Lists& W, int prec, const ProbPtrs* probs, ProbPtrs si
         if (e != hipSuccess) return e;
         if (tx[0] + tx[1] < t[best[0]] + t[best[1]]) W.variant = DMRG_GEMM_X;
     }
+    // the K-split family likewise (its stage 1 writes the operand layout its stage 2 reads)
+    double tk[2] = {-1.0, -1.0};
+    if (prec == DMRG_FP64 && W.nkt2 > 0) {
+        for (int st = 1; st <= 2 && e == hipSuccess; ++st)
+            e = time_stage(W, st, DMRG_GEMM_K, prec, probs, single, s, reps, &tk[st - 1]);
+        if (e != hipSuccess) return e;
+        double cur = t[best[0]] + t[best[1]];
+        if (W.variant == DMRG_GEMM_X) cur = tx[0] + tx[1];
+        if (tk[0] + tk[1] < cur) W.variant = DMRG_GEMM_K;
+    }
     if (out) {
         for (int i = 0; i < kCand; ++i) out[i] = t[i];
         out[kCand] = tx[0];
         out[kCand + 1] = tx[1];
+        out[kCand + 2] = tk[0];
+        out[kCand + 3] = tk[1];
     }
     return hipSuccess;
 }
@@ -273,9 +314,11 @@ hipError_t autotune_lists(Lists& W, int prec, const ProbPtrs* probs, ProbPtrs si
 // Whether a dmrg_gemm variant is valid: known bits, at most one family per stage.
 bool valid_variant(int32_t variant) {
     constexpr int32_t known = DMRG_GEMM_STAGE1_LDS | DMRG_GEMM_STAGE2_LDS |
-                              DMRG_GEMM_STAGE1_NARROW | DMRG_GEMM_STAGE2_NARROW | DMRG_GEMM_X;
+                              DMRG_GEMM_STAGE1_NARROW | DMRG_GEMM_STAGE2_NARROW | DMRG_GEMM_X |
+                              DMRG_GEMM_K;
     if (variant & ~known) return false;
     if ((variant & DMRG_GEMM_X) && variant != DMRG_GEMM_X) return false;
+    if ((variant & DMRG_GEMM_K) && variant != DMRG_GEMM_K) return false;
     if ((variant & DMRG_GEMM_STAGE1_LDS) && (variant & DMRG_GEMM_STAGE1_NARROW)) return false;
     return !((variant & DMRG_GEMM_STAGE2_LDS) && (variant & DMRG_GEMM_STAGE2_NARROW));
 }
@@ -683,7 +726,7 @@ int chains_set(std::unique_ptr<dmrg_batch_ctx>& cs, const std::vector<dmrg_ctx*>
         merge_plans(plans, M);
         const hipError_t e = upload_lists(c->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles1n,
                                           M.tiles2, M.tiles2n, M.l1, M.l2, M.lred, M.nslots,
-                                          M.xch, M.x2, M.xz, h0->stream);
+                                          M.xch, M.x2, M.xz, M.kf, h0->stream);
         if (e != hipSuccess)
             return fail(h0, e == hipErrorOutOfMemory ? DMRG_ENOMEM : DMRG_EHIP, hipGetErrorString(e));
     } catch (const std::bad_alloc&) {
@@ -1230,7 +1273,7 @@ int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
         const std::vector<LRed> lr[2] = {P.pk16.lred, P.pk32.lred};
         const int ns[2] = {P.pk16.nslots, P.pk32.nslots};
         e = upload_lists(h->lists, s1, s2, sg, P.tiles1, P.tiles1n, P.tiles2, P.tiles2n, P.l1, l2,
-                         lr, ns, P.pk16.xch, P.pk16.x2, P.pk16.xz, h->stream);
+                         lr, ns, P.pk16.xch, P.pk16.x2, P.pk16.xz, P.kf, h->stream);
     }
     if (e == hipSuccess) e = h->ws[0].dT.alloc(sizeof(double) * (size_t)P.T_size);
     // the padding rows of the stage-1 workspace are read (times zero factors) but never
@@ -1328,6 +1371,14 @@ int dmrg_plan_stats(const dmrg_problem* problem, int32_t kdim, dmrg_plan_info* o
         add(P.pk16.xch.size() * sizeof(XChunk));
         add(P.pk16.x2.size() * sizeof(XItem2));
         add(P.pk16.xz.size() * sizeof(XZero));
+        add(P.kf.xblk.size() * sizeof(KXBlock));
+        add(P.kf.pitems.size() * sizeof(KPItem));
+        add(P.kf.s1.size() * sizeof(KS1Block));
+        add(P.kf.eout.size() * sizeof(KEdgeOut));
+        add(P.kf.t1.size() * sizeof(KTile));
+        add(P.kf.s2.size() * sizeof(KS2Block));
+        add(P.kf.ctab.size() * sizeof(int64_t));
+        add(P.kf.t2.size() * sizeof(KTile));
         add(sizeof(double) * (size_t)std::max(P.pk16.nslots, P.pk32.nslots) * kLTile * kLTile);
         add(sizeof(double) * (size_t)P.T_size);
         add(A.size());
@@ -1407,7 +1458,11 @@ int dmrg_matvec_noalloc(dmrg_handle h, const double* x, double* y, int32_t nvec)
     if (!h) return DMRG_EINVAL;
     if (nvec < 0 || (nvec > 0 && (!x || !y))) return fail(h, DMRG_EINVAL, "bad vectors");
     if (nvec == 0) return DMRG_OK;
-    const int64_t tn = h->plan.T_size;
+    // the part of the intermediate the handle's block-product family uses (the K-split
+    // family pads it further)
+    const int64_t tn = (h->lists.variant & DMRG_GEMM_K) && h->lists.nkt2 > 0
+                           ? h->plan.kf.T_size
+                           : h->plan.T_base;
     if ((size_t)tn * sizeof(double) > kNoAllocScratchBytes)
         return fail(h, DMRG_EINVAL, "the stage-1 intermediate takes " +
                                         std::to_string((size_t)tn * sizeof(double)) +
@@ -1788,7 +1843,7 @@ int dmrg_batch_create(const dmrg_handle* handles, int32_t count, dmrg_batch* out
         b->lists.variant = h0->lists.variant;
         const hipError_t e = upload_lists(b->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles1n, M.tiles2,
                                           M.tiles2n, M.l1, M.l2, M.lred, M.nslots, M.xch, M.x2,
-                                          M.xz, h0->stream);
+                                          M.xz, M.kf, h0->stream);
         if (e != hipSuccess) {
             delete b;
             return fail(h0, e == hipErrorOutOfMemory ? DMRG_ENOMEM : DMRG_EHIP, hipGetErrorString(e));

@@ -145,6 +145,78 @@ struct XZero {
 };
 
 // Per-problem pointers for one launch of a stage (single problem: tables of length 1).
+// Work of the K-split family (FP64): v_mfma_f64_4x4x4_4b_f64 with its four blocks taken as four
+// slices of a 16-deep K chunk (partial sums added across the lanes once per tile), both operands
+// of every stage packed in the instruction's lane order and streamed with 16-byte loads.
+//   A operand (M x K): lane 16 k' + 4 b + x of the instruction for row group q holds
+//     A(4 q + x, 16 c + 4 b + k'); B operand (K x N) likewise with column groups.
+//   Piece (panel P of 32 rows or columns, chunk c): 512 doubles, [pair i][lane][2] with row
+//     (column) group 2 i + s in element s of the pair; at off + (P pstride + c cstride) 512.
+// Stage 1: T_b = X_b R_b as 32 x 32 tiles (or 16, 8, 4 rows / columns at block edges) of one
+// wavefront; X_b comes from a pack of the input vector (written first by k_prepack), R_b from
+// the packed right factors.  Its H_E columns go to T0 (d x 2e, column-major per block), the
+// columns of every edge into that edge's packed stage-2 operand.  Stage 2: Y_b' = T0 + Acat Bcat,
+// tiles of four wavefronts that deal the K chunks round-robin and add their partial tiles in
+// LDS in a fixed order; the B piece of each chunk comes from a per-block chunk table (the
+// block's own pack of the input vector for the H_S segment, then the edges' packs).
+constexpr int kKPanel = 32;         // rows (columns) per packed panel: 8 groups of 4
+constexpr int kKPiece = 512;        // doubles per (panel, chunk) piece
+struct KPack {
+    int64_t off;
+    int32_t pstride, cstride;       // piece (P, c) at off + (P pstride + c cstride) kKPiece
+};
+// The family's index spaces start every piece of a block on a panel: stage 1's rows are the two
+// planes of the block, each padded to dpad = d rounded up to 32 (plane p at rows p dpad..); its
+// columns are the H_E columns, then every edge's, each padded to a multiple of 32; stage 2's
+// columns are the two planes, each padded to epad = e rounded up to 32 (plane p at columns
+// p epad..).  Padding rows and columns of the packs hold zeros and are never stored to, and no
+// tile covers them (tiles cover groups of 4 up to the true extent): memory, not flops.
+// Packing of the input vector for one psi block: xa = X_b (2 dpad x e) for stage 1, xb = the
+// block as the H_S segment's B operand (d x 2 epad) for stage 2.
+struct KXBlock {
+    int32_t d, e, prob, dpad;
+    int32_t epad, pad0;
+    int64_t xoff;                   // block offset (complex elements) in the vector
+    int64_t xplane;                 // offset of the vector's imaginary plane
+    KPack xa, xb;                   // into the workspace
+};
+// One piece written by k_prepack: `which` 0: xa piece (P, c); 1: xb piece (P, c).
+struct KPItem {
+    int32_t blk, which, P, c;
+};
+// Stage-1 block: M = 2 dpad rows, K = e, N columns (segments padded to 32).
+struct KS1Block {
+    int32_t M, N, K, prob;
+    int32_t d, e, nch, nedge;
+    int32_t edge0, dpad, epad, pad0;
+    KPack A;                        // the block's xa (workspace)
+    KPack B;                        // packed right factors (operator buffer)
+    int64_t t0off;                  // T0 (workspace): element (i, p epad + j) at + (p epad + j) d + i
+};
+// Stage-1 columns [col, col + e2) of a block (col a multiple of 32): one edge, whose stage-2
+// operand (d_src x 2 e2pad, e2pad = e2 rounded up to 32) is packed at P (workspace,
+// chunk-major: pstride 1, cstride = column panels of 2 e2pad).
+struct KEdgeOut {
+    int32_t col, e2, e2pad, pad0;
+    KPack P;
+};
+// Stage-2 block: M = d' rows, N = 2 epad' columns, nch K chunks of the concatenated segments.
+struct KS2Block {
+    int32_t M, N, prob, nch;
+    int32_t ctab0, e, epad, pad0;
+    KPack A;                        // packed left factors (operator buffer)
+    int64_t t0off;                  // T0 (workspace), as in KS1Block
+    View Y;                         // into the output vector
+};
+// Tile of either stage: row groups g0 .. g0 + RQ - 1, column groups h0 .. h0 + CP - 1 (groups of
+// 4), shape = 4 log2(RQ) + log2(CP) for RQ, CP in {1, 2, 4, 8} (RQ, CP >= 2: g0, h0 even).
+// Stage 1 also names the tile's plane and column segment (-1: the H_E columns, else the edge
+// index within the block's edges).
+struct KTile {
+    int32_t blk, g0, h0, shape;
+    int32_t plane, seg, pad0, pad1;
+};
+
 struct ProbPtrs {
     const double* x;        // input vector
     double* y;              // output vector

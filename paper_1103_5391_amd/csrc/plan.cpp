@@ -166,10 +166,36 @@ void tile_list(std::vector<Tile>& out, int blk, int M, int N, int tm, int tn) {
         for (int n0 = 0; n0 < N; n0 += tn) out.push_back(Tile{blk, m0, n0, M - m0 <= tm / 2});
 }
 
+int cdiv(int a, int b) { return (a + b - 1) / b; }
+
+// K-split family: element offset of row (or column) i, K index k inside a packed operand.
+int64_t kpos(const KPack& pk, int i, int k) {
+    const int P = i / kKPanel, grp = (i % kKPanel) / 4, x = i % 4;
+    const int c = k / 16, b = (k % 16) / 4, kk = k % 4;
+    const int lane = 16 * kk + 4 * b + x;
+    return pk.off + ((int64_t)P * pk.pstride + (int64_t)c * pk.cstride) * kKPiece +
+           (int64_t)(grp / 2) * 128 + lane * 2 + (grp & 1);
+}
+
+// Pieces of n groups (of 4 rows or columns): whole runs of 8 groups, then the remainder as
+// pieces of 4, 2 and 1 groups (each starting at a multiple of its size).  (start, log2 size).
+std::vector<std::pair<int, int>> k_pieces(int ngroups) {
+    std::vector<std::pair<int, int>> out;
+    int g = 0;
+    for (; g + 8 <= ngroups; g += 8) out.push_back({g, 3});
+    for (int l = 2; l >= 0; --l)
+        if (g + (1 << l) <= ngroups) {
+            out.push_back({g, l});
+            g += 1 << l;
+        }
+    return out;
+}
+
 }  // namespace
 
 void lds_lists(Plan& P);
 void x_lists(Plan& P);
+void k_lists(Plan& P);
 
 std::string build_plan(const dmrg_problem* pb, Plan& P) {
     if (!pb) return "problem is NULL";
@@ -359,7 +385,141 @@ std::string build_plan(const dmrg_problem* pb, Plan& P) {
     P.w2 = std::move(w2);
     lds_lists(P);
     x_lists(P);
+    k_lists(P);
+    P.T_base = P.T_size;
+    P.T_size = std::max(P.T_size, P.kf.T_size);
     return "";
+}
+
+// Work of the K-split family (internal.hpp): workspace layout, input-vector pieces, block
+// descriptors, the stage-2 chunk tables, and tiles of up to 8 x 8 groups of 4 (the edges of each
+// plane and column segment covered by pieces of 4, 2 and 1 groups), in XCD order.
+void k_lists(Plan& P) {
+    KLists& K = P.kf;
+    K = KLists{};
+    const int nb = (int)P.blocks.size();
+    const int ne = (int)P.edges.size();
+    auto r32 = [](int v) { return round_up(v, kKPanel); };
+    int64_t w = 0;
+    std::vector<int64_t> t0(nb);
+    for (int bi = 0; bi < nb; ++bi) {
+        t0[bi] = w;
+        w += (int64_t)P.blocks[bi].d * 2 * r32(P.blocks[bi].e);
+    }
+    std::vector<KPack> tp(ne);
+    for (int ei = 0; ei < ne; ++ei) {
+        const int ds = P.blocks[P.edges[ei].src].d, e2 = P.blocks[P.edges[ei].dst].e;
+        const int np = 2 * r32(e2) / kKPanel;
+        tp[ei] = KPack{w, 1, np};
+        w += (int64_t)cdiv(ds, 16) * np * kKPiece;
+    }
+    for (int bi = 0; bi < nb; ++bi) {
+        const auto& B = P.blocks[bi];
+        const int dpad = r32(B.d), epad = r32(B.e);
+        const int npa = 2 * dpad / kKPanel, nca = cdiv(B.e, 16);
+        const int npb = 2 * epad / kKPanel, ncb = cdiv(B.d, 16);
+        KXBlock x;
+        x.d = B.d;
+        x.e = B.e;
+        x.prob = 0;
+        x.dpad = dpad;
+        x.epad = epad;
+        x.pad0 = 0;
+        x.xoff = B.off;
+        x.xplane = P.n;
+        x.xa = KPack{w, nca, 1};
+        w += (int64_t)npa * nca * kKPiece;
+        x.xb = KPack{w, 1, npb};
+        w += (int64_t)npb * ncb * kKPiece;
+        K.xblk.push_back(x);
+        for (int Pn = 0; Pn < npa; ++Pn)
+            for (int c = 0; c < nca; ++c) K.pitems.push_back(KPItem{bi, 0, Pn, c});
+        for (int Pn = 0; Pn < npb; ++Pn)
+            for (int c = 0; c < ncb; ++c) K.pitems.push_back(KPItem{bi, 1, Pn, c});
+    }
+    K.T_size = w;
+    // tiles of a rows x columns range given as (first group, groups) per side
+    auto tiles = [](std::vector<KTile>& out, double& wt, int bi, int rg0, int nr, int cg0, int nc,
+                    int plane, int seg, int depth) {
+        for (auto rp : k_pieces(nr))
+            for (auto cp : k_pieces(nc)) {
+                out.push_back(KTile{bi, rg0 + rp.first, cg0 + cp.first, 4 * rp.second + cp.second,
+                                    plane, seg, 0, 0});
+                wt += (double)(1 << rp.second) * (1 << cp.second) * depth;
+            }
+    };
+    std::vector<double> w1(nb, 0.0), w2(nb, 0.0);
+    int64_t r = P.pk16.R_elems;
+    for (int bi = 0; bi < nb; ++bi) {
+        const auto& B = P.blocks[bi];
+        const int dpad = r32(B.d), epad = r32(B.e);
+        KS1Block s;
+        s.edge0 = (int)K.eout.size();
+        int N = epad;
+        for (int ei : P.out_of[bi]) {
+            const int e2 = P.blocks[P.edges[ei].dst].e;
+            K.eout.push_back(KEdgeOut{N, e2, r32(e2), 0, tp[ei]});
+            N += r32(e2);
+        }
+        s.M = 2 * dpad;
+        s.N = N;
+        s.K = B.e;
+        s.prob = 0;
+        s.d = B.d;
+        s.e = B.e;
+        s.nch = cdiv(B.e, 16);
+        s.nedge = (int)P.out_of[bi].size();
+        s.dpad = dpad;
+        s.epad = epad;
+        s.pad0 = 0;
+        s.A = K.xblk[bi].xa;
+        s.B = KPack{r, s.nch, 1};
+        r += (int64_t)(N / kKPanel) * s.nch * kKPiece;
+        s.t0off = t0[bi];
+        K.s1.push_back(s);
+        for (int pl = 0; pl < 2; ++pl) {
+            const int rg0 = pl * dpad / 4, nr = cdiv(B.d, 4);
+            tiles(K.t1, w1[bi], bi, rg0, nr, 0, cdiv(B.e, 4), pl, -1, s.nch + 2);
+            for (int k = 0; k < s.nedge; ++k) {
+                const KEdgeOut& eo = K.eout[s.edge0 + k];
+                tiles(K.t1, w1[bi], bi, rg0, nr, eo.col / 4, cdiv(eo.e2, 4), pl, k, s.nch + 2);
+            }
+        }
+    }
+    K.R_elems = r - P.pk16.R_elems;
+    int64_t a = P.pk16.A_elems;
+    for (int bi = 0; bi < nb; ++bi) {
+        const auto& B = P.blocks[bi];
+        const int epad = r32(B.e);
+        KS2Block s;
+        s.M = B.d;
+        s.N = 2 * epad;
+        s.prob = 0;
+        s.ctab0 = (int)K.ctab.size();
+        s.e = B.e;
+        s.epad = epad;
+        s.pad0 = 0;
+        const int npb = 2 * epad / kKPanel;
+        for (int c = 0; c < cdiv(B.d, 16); ++c)
+            K.ctab.push_back(K.xblk[bi].xb.off + (int64_t)c * npb * kKPiece);
+        for (int ei : P.into[bi]) {
+            const int ds = P.blocks[P.edges[ei].src].d;
+            for (int c = 0; c < cdiv(ds, 16); ++c)
+                K.ctab.push_back(tp[ei].off + (int64_t)c * tp[ei].cstride * kKPiece);
+        }
+        s.nch = (int)K.ctab.size() - s.ctab0;
+        s.A = KPack{a, s.nch, 1};
+        a += (int64_t)cdiv(B.d, kKPanel) * s.nch * kKPiece;
+        s.t0off = t0[bi];
+        s.Y = View{B.off, P.n, B.d, B.e};
+        K.s2.push_back(s);
+        for (int pl = 0; pl < 2; ++pl)
+            tiles(K.t2, w2[bi], bi, 0, cdiv(B.d, 4), pl * epad / 4, cdiv(B.e, 4), pl, -1,
+                  s.nch / 4 + 3);
+    }
+    K.A_elems = a - P.pk16.A_elems;
+    K.t1 = xcd_order(K.t1, w1, 1);
+    K.t2 = xcd_order(K.t2, w2, 1);
 }
 
 // Work of the LDS-staged family: the chunk table of every stage-2 block (its segments' source
@@ -594,8 +754,9 @@ void pack_operators(const Plan& P, int kind, std::vector<uint8_t>& A, std::vecto
     const Packing& pk = split ? P.pk32 : P.pk16;
     const size_t esz = (kind == DMRG_FP64) ? 8 : (kind == DMRG_FP32 ? 4 : 2);
     const int per = kind == DMRG_BF16X3 ? 2 : (kind == DMRG_BF16X6 ? 3 : 1);
-    A.assign((size_t)pk.A_elems * per * esz, 0);
-    R.assign((size_t)pk.R_elems * per * esz, 0);
+    const bool kfam = kind == DMRG_FP64;   // the K-split family's packs follow (FP64 only)
+    A.assign((size_t)(pk.A_elems + (kfam ? P.kf.A_elems : 0)) * per * esz, 0);
+    R.assign((size_t)(pk.R_elems + (kfam ? P.kf.R_elems : 0)) * per * esz, 0);
     const Writer wa{kind, pk.ck, per, A.data()}, wr{kind, pk.ck, per, R.data()};
     const int nb = (int)P.blocks.size();
     for (int bi = 0; bi < nb; ++bi) {
@@ -626,6 +787,36 @@ void pack_operators(const Plan& P, int kind, std::vector<uint8_t>& A, std::vecto
             for (int k = 0; k < Bs.d; ++k)
                 for (int i = 0; i < B.d; ++i) wa.put(s2.Aoff, i, kbase + k, s2.nch, c * ed.a.at(i, k));
             ++si;
+        }
+    }
+    if (!kfam) return;
+    double* KA = reinterpret_cast<double*>(A.data());
+    double* KR = reinterpret_cast<double*>(R.data());
+    for (int bi = 0; bi < nb; ++bi) {
+        const auto& B = P.blocks[bi];
+        const KS1Block& s1 = P.kf.s1[bi];
+        const double* HE = P.E.H.data() + P.E.hoff[B.q];
+        for (int j = 0; j < B.e; ++j)
+            for (int k = 0; k < B.e; ++k) KR[kpos(s1.B, j, k)] = HE[(int64_t)k * B.e + j];
+        for (int k2 = 0; k2 < s1.nedge; ++k2) {
+            const Edge& ed = P.edges[P.out_of[bi][k2]];
+            const KEdgeOut& eo = P.kf.eout[s1.edge0 + k2];
+            for (int j = 0; j < eo.e2; ++j)
+                for (int k = 0; k < B.e; ++k) KR[kpos(s1.B, eo.col + j, k)] = ed.b.at(j, k);
+        }
+        const KS2Block& s2 = P.kf.s2[bi];
+        const double* HS = P.S.H.data() + P.S.hoff[B.p];
+        for (int k = 0; k < B.d; ++k)
+            for (int i = 0; i < B.d; ++i) KA[kpos(s2.A, i, k)] = HS[(int64_t)k * B.d + i];
+        int kbase = cdiv(B.d, 16) * 16;
+        for (int ei : P.into[bi]) {
+            const Edge& ed = P.edges[ei];
+            const auto& Bs = P.blocks[ed.src];
+            const auto& t = P.terms[ed.term];
+            const double c = t.coef * (t.fermionic ? P.S.parity(Bs.p) : 1);
+            for (int k = 0; k < Bs.d; ++k)
+                for (int i = 0; i < B.d; ++i) KA[kpos(s2.A, i, kbase + k)] = c * ed.a.at(i, k);
+            kbase += cdiv(Bs.d, 16) * 16;
         }
     }
 }

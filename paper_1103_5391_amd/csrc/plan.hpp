@@ -84,6 +84,24 @@ struct Packing {
     std::vector<XZero> xz;
 };
 
+// Work of the K-split family (FP64): packs, descriptors and tiles.  Its packed factors follow the
+// FP64 buffers of the other families (offsets count from the start of those buffers); its
+// workspace layout (T0 per block, the edges' packed stage-2 operands, the packs of the input
+// vector) starts at the workspace's first element.
+struct KLists {
+    std::vector<KXBlock> xblk;
+    std::vector<KPItem> pitems;
+    std::vector<KS1Block> s1;
+    std::vector<KEdgeOut> eout;
+    std::vector<KTile> t1;
+    std::vector<KS2Block> s2;
+    std::vector<int64_t> ctab;                 // per stage-2 chunk: workspace offset of its B
+                                               // piece of column panel 0
+    std::vector<KTile> t2;
+    int64_t A_elems = 0, R_elems = 0;          // packed factor values after the FP64 packs
+    int64_t T_size = 0;                        // workspace elements
+};
+
 struct Plan {
     HalfTable S, E;
     int target[2] = {0, 0};
@@ -95,11 +113,14 @@ struct Plan {
     std::vector<std::vector<int>> out_of, into;
     std::vector<int> N1;                       // stage-1 columns per source block
     std::vector<View> Tview;                   // stage-1 workspace view per block
-    int64_t T_size = 0;                        // workspace elements
+    int64_t T_size = 0;                        // workspace elements (every family)
+    int64_t T_base = 0;                        // of them, what the families other than the
+                                               // K-split one use
     std::vector<Tile> tiles1, tiles1n, tiles2, tiles2n;   // register-tiled lists (wide, narrow)
     std::vector<LItem1> l1;                    // LDS-tiled stage-1 tiles (both packings)
     std::vector<double> w1, w2;                // per-block work estimates of the two stages
     Packing pk16, pk32;
+    KLists kf;
     double flops = 0.0;                        // algorithmic flops per complex matvec: the
                                                // cheaper contraction order of every term
     double flops_exec = 0.0;                   // flops the two stages execute (right product
@@ -124,6 +145,7 @@ struct Merged {
     std::vector<XChunk> xch;                  // LDS-staged family (16-deep chunks)
     std::vector<XItem2> x2;
     std::vector<XZero> xz;
+    KLists kf;                                // K-split family
 };
 void merge_plans(const std::vector<const Plan*>& plans, Merged& out);
 

@@ -20,6 +20,7 @@ DMRG_FP64, DMRG_FP32, DMRG_BF16X3, DMRG_BF16X6 = 0, 1, 2, 3
 DMRG_GEMM_STAGE1_LDS, DMRG_GEMM_STAGE2_LDS = 1, 2
 DMRG_GEMM_STAGE1_NARROW, DMRG_GEMM_STAGE2_NARROW = 4, 8
 DMRG_GEMM_X = 16
+DMRG_GEMM_K = 32
 STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP",
           -4: "DMRG_ENONFINITE", -5: "DMRG_ESTATE", 1: "DMRG_WNOTCONV"}
 DMRG_WNOTCONV = 1
@@ -469,11 +470,12 @@ class Handle:
     def dmrg_autotune(self, reps: int = 10):
         """Times the kernel families of each stage, keeps the fastest; returns the timings (ms)
         and the chosen variant bits."""
-        out = np.zeros(8)
+        out = np.zeros(10)
         _check(self.lib.dmrg_autotune(self.h, int(reps), _dptr(out, C.c_double)), self.h)
         return dict(stage1_register=out[0], stage1_lds=out[1], stage2_register=out[2],
                     stage2_lds=out[3], stage1_narrow=out[4], stage2_narrow=out[5],
-                    stage1_x=out[6], stage2_x=out[7], variant=self.get_gemm())
+                    stage1_x=out[6], stage2_x=out[7], stage1_k=out[8], stage2_k=out[9],
+                    variant=self.get_gemm())
 
     autotune = dmrg_autotune
 
@@ -512,12 +514,12 @@ class Batch:
     set_gemm = dmrg_batch_set_gemm
 
     def dmrg_batch_autotune(self, reps: int = 5):
-        out = np.zeros(8)
+        out = np.zeros(10)
         _check(self.lib.dmrg_batch_autotune(self.b, int(reps), _dptr(out, C.c_double)),
                self.handles[0].h)
         return dict(stage1_register=out[0], stage1_lds=out[1], stage2_register=out[2],
                     stage2_lds=out[3], stage1_narrow=out[4], stage2_narrow=out[5],
-                    stage1_x=out[6], stage2_x=out[7])
+                    stage1_x=out[6], stage2_x=out[7], stage1_k=out[8], stage2_k=out[9])
 
     autotune = dmrg_batch_autotune
 

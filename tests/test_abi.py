@@ -100,12 +100,13 @@ def test_plan_stats_rejects_bad_problems(lib):
 
 
 def test_workspace_cap_refuses_handle_before_any_device_call(lib):
-    """DMRG_MAX_WORKSPACE smaller than the handle's first buffer: DMRG_ENOMEM after the plan is
-    built and before any memory is requested (so this runs without a GPU); a value that is not
-    a byte count: DMRG_EINVAL."""
+    """DMRG_MAX_WORKSPACE smaller than the handle's first buffer (one stage-1 block descriptor,
+    more than 64 bytes): DMRG_ENOMEM after the plan is built and before any memory is requested
+    (so this runs without a GPU); a value that is not a byte count: DMRG_EINVAL."""
     pb = I.exact_problem(6, 4.0, (3, 3))
     need = L.plan_stats(pb)["create_bytes"]
-    for cap, code, text in [("1", -2, "DMRG_MAX_WORKSPACE"), (str(need // 1000), -2, "DMRG_MAX_WORKSPACE"),
+    assert need > 64
+    for cap, code, text in [("1", -2, "DMRG_MAX_WORKSPACE"), ("64", -2, "DMRG_MAX_WORKSPACE"),
                             ("12kB", -1, "byte count")]:
         os.environ["DMRG_MAX_WORKSPACE"] = cap
         try:

@@ -100,10 +100,10 @@ def test_layout_matches_oracle(env):
         h.destroy()
 
 
-GEMM_VARIANTS = pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 6, 8, 9, 12, 16],
+GEMM_VARIANTS = pytest.mark.parametrize("variant", [0, 1, 2, 3, 4, 6, 8, 9, 12, 16, 32],
                                         ids=["reg-reg", "lds-reg", "reg-lds", "lds-lds",
                                              "narrow-reg", "narrow-lds", "reg-narrow",
-                                             "lds-narrow", "narrow-narrow", "x"])
+                                             "lds-narrow", "narrow-narrow", "x", "k"])
 
 
 @GEMM_VARIANTS
@@ -184,7 +184,7 @@ KRYLOV_CASES = [
 ]
 
 
-@pytest.mark.parametrize("variant", [0, 16], ids=["register", "x"])
+@pytest.mark.parametrize("variant", [0, 16, 32], ids=["register", "x", "k"])
 @pytest.mark.parametrize("name,kdim,tau,nsteps", KRYLOV_CASES)
 def test_krylov_parity(env, name, kdim, tau, nsteps, variant):
     torch, L = env
@@ -1087,16 +1087,19 @@ def test_autotune_and_variants_agree(env, prec):
     s2 = min([(t["stage2_register"], 0), (t["stage2_lds"], L.DMRG_GEMM_STAGE2_LDS),
               (t["stage2_narrow"], L.DMRG_GEMM_STAGE2_NARROW)], key=lambda p: p[0])[1]
     want = s1 | s2
-    if prec == 0 and t["stage1_x"] > 0 and t["stage1_x"] + t["stage2_x"] < (
-            min(t["stage1_register"], t["stage1_lds"], t["stage1_narrow"]) +
-            min(t["stage2_register"], t["stage2_lds"], t["stage2_narrow"])):
+    best = (min(t["stage1_register"], t["stage1_lds"], t["stage1_narrow"]) +
+            min(t["stage2_register"], t["stage2_lds"], t["stage2_narrow"]))
+    if prec == 0 and t["stage1_x"] > 0 and t["stage1_x"] + t["stage2_x"] < best:
         want = L.DMRG_GEMM_X
+        best = t["stage1_x"] + t["stage2_x"]
+    if prec == 0 and t["stage1_k"] > 0 and t["stage1_k"] + t["stage2_k"] < best:
+        want = L.DMRG_GEMM_K
     assert t["variant"] == want
     x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 91))
     xd = _dev(torch, x)
     yref = M.matvec_sector(pb, x)
     tol = MV_TOL if prec == 0 else MIXED_TOL[prec]
-    for v in (0, 1, 2, 3, 4, 6, 8, 9, 12, 16):
+    for v in (0, 1, 2, 3, 4, 6, 8, 9, 12, 16, 32):
         h.set_gemm(v)
         yd = torch.empty_like(xd)
         h.matvec(xd, yd)
@@ -1104,8 +1107,9 @@ def test_autotune_and_variants_agree(env, prec):
         say("  variant", v, err)
         assert err <= tol
     for bad in (L.DMRG_GEMM_STAGE1_LDS | L.DMRG_GEMM_STAGE1_NARROW,
-                L.DMRG_GEMM_STAGE2_LDS | L.DMRG_GEMM_STAGE2_NARROW, 32,
-                L.DMRG_GEMM_X | L.DMRG_GEMM_STAGE1_NARROW):
+                L.DMRG_GEMM_STAGE2_LDS | L.DMRG_GEMM_STAGE2_NARROW, 64,
+                L.DMRG_GEMM_X | L.DMRG_GEMM_STAGE1_NARROW, L.DMRG_GEMM_K | L.DMRG_GEMM_X,
+                L.DMRG_GEMM_K | L.DMRG_GEMM_STAGE2_NARROW):
         with pytest.raises(L.DmrgError):
             h.set_gemm(bad)
     h.destroy()
