@@ -42,8 +42,8 @@ hipError_t launch_lanczos_iter(const VecGroup&, int, int, hipStream_t);
 hipError_t launch_tridiag(const VecGroup&, const double*, int, int*, int, hipStream_t);
 hipError_t launch_lowest(const VecGroup&, int*, int, hipStream_t);
 hipError_t launch_count_nonfinite(const double*, int64_t, int*, hipStream_t);
-hipError_t launch_density(const DBlock*, int, const DTile*, int, const double* const*, const double*,
-                          int, int64_t, void*, void*, double*, double*, int*, int, double*, int, int,
+hipError_t launch_density(const DBlock*, int, const int*, int, const DTile*, int, const DensIn&, int,
+                          int64_t, void*, void*, double*, double*, int*, int, double*, int, int,
                           int*, double*, double*, int*, double*, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const ZPtrs&, int, int64_t,
@@ -102,6 +102,29 @@ struct DevBuf {
         } else {
             p = nullptr;
         }
+        return e;
+    }
+    template <typename T>
+    T* as() const { return static_cast<T*>(p); }
+};
+
+// Pinned host memory (hipHostMalloc), for results the host reads after a call.
+struct HostBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+    ~HostBuf() { release(); }
+    void release() {
+        if (p) (void)hipHostFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t b) {
+        release();
+        hipError_t e = hipHostMalloc(&p, b == 0 ? 8 : b, hipHostMallocDefault);
+        if (e == hipSuccess)
+            bytes = b;
+        else
+            p = nullptr;
         return e;
     }
     template <typename T>
@@ -400,8 +423,11 @@ struct dmrg_ctx {
     Workspace ws[kChains];
     Group self;         // tables of the handle's own Krylov runs
     // density matrix and truncation (built on first use): sectors, tiles, matrices, results
-    DevBuf dDBlk, dDTile, dDA, dDV, dDZ, dDS, dDFail, dDEv, dDKept, dDNk, dDSums, dDVecs, dDW;
-    int dens_ntiles = 0, dens_ntot = 0, dens_maxd = 0;
+    // the call's results in one device area (per sector: the two sums, the number kept, the
+    // eigen-decomposition flags), copied at once into pinned host memory
+    DevBuf dDBlk, dDSel, dDTile, dDA, dDV, dDZ, dDS, dDEv, dDKept, dDRes;
+    HostBuf hDRes;
+    int dens_ntiles = 0, dens_ntot = 0, dens_maxd = 0, dens_nreg = 0;
     int64_t dens_nmat = 0;
     std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
     // local operators (built on first use): raw operator blocks of both halves, the product
@@ -1616,58 +1642,65 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
     const Plan& P = h->plan;
     const int nb = (int)P.blocks.size();
     hipStream_t s = h->stream;
+    // result area: sums (2 nb doubles), numbers kept (nb ints), flags (nb ints)
+    const size_t res_bytes = sizeof(double) * 2 * (size_t)nb + 2 * sizeof(int) * (size_t)nb;
     if (!h->dDBlk.p) {
         std::vector<DBlock> blks(nb);
         std::vector<DTile> tiles;
+        std::vector<int> sel;
         int64_t aoff = 0, eoff = 0;
         for (int b = 0; b < nb; ++b) {
             const PsiBlock& pbk = P.blocks[b];
             if (pbk.d > kDensMaxDim) return fail(h, DMRG_EINVAL, "system sector larger than 1024");
             blks[b] = DBlock{pbk.d, pbk.e, pbk.off, aoff, eoff};
             h->dens_maxd = std::max(h->dens_maxd, pbk.d);
+            if (pbk.d <= kDensRegMaxDim) sel.push_back(b);
             for (int i0 = 0; i0 < pbk.d; i0 += 16)
                 for (int j0 = 0; j0 < pbk.d; j0 += 16) tiles.push_back(DTile{b, i0, j0, 0});
             aoff += (int64_t)pbk.d * pbk.d;
             eoff += pbk.d;
         }
+        h->dens_nreg = (int)sel.size();
+        for (int b = 0; b < nb; ++b)
+            if (P.blocks[b].d > kDensRegMaxDim) sel.push_back(b);
         h->dens_ntiles = (int)tiles.size();
         h->dens_ntot = (int)eoff;
         h->dens_nmat = aoff;
         // the sector table goes last: it opens this block's gate, so a failed allocation
         // leaves every buffer to be allocated again by the next call
         HIP_TRY(h, upload(h->dDTile, tiles, s));
+        HIP_TRY(h, upload(h->dDSel, sel, s));
         HIP_TRY(h, h->dDA.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDV.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDZ.alloc(sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDS.alloc(5 * sizeof(double) * (size_t)aoff));
-        HIP_TRY(h, h->dDFail.alloc(sizeof(int) * (size_t)nb));
         HIP_TRY(h, h->dDEv.alloc(sizeof(double) * (size_t)eoff));
         HIP_TRY(h, h->dDKept.alloc(sizeof(int) * (size_t)eoff));
-        HIP_TRY(h, h->dDNk.alloc(sizeof(int) * (size_t)nb));
-        HIP_TRY(h, h->dDSums.alloc(2 * sizeof(double) * (size_t)nb));
-        HIP_TRY(h, h->dDVecs.alloc(sizeof(void*) * kDensMaxVec));
-        HIP_TRY(h, h->dDW.alloc(sizeof(double) * kDensMaxVec));
+        HIP_TRY(h, h->dDRes.alloc(res_bytes));
+        HIP_TRY(h, h->hDRes.alloc(res_bytes));
         HIP_TRY(h, upload(h->dDBlk, blks, s));
     }
-    // per-call pointers and weights (synchronous copies; the call waits for its results)
-    HIP_TRY(h, hipMemcpyAsync(h->dDVecs.p, vecs, sizeof(void*) * nvec, hipMemcpyHostToDevice, s));
-    HIP_TRY(h, hipMemcpyAsync(h->dDW.p, weights, sizeof(double) * nvec, hipMemcpyHostToDevice, s));
-    HIP_TRY(h, hipMemsetAsync(h->dDFail.p, 0, sizeof(int) * (size_t)nb, s));
-    HIP_TRY(h, launch_density(h->dDBlk.as<DBlock>(), nb, h->dDTile.as<DTile>(), h->dens_ntiles,
-                              h->dDVecs.as<const double*>(), h->dDW.as<double>(), nvec, P.n,
-                              h->dDA.p, h->dDV.p, h->dDZ.as<double>(), h->dDS.as<double>(),
-                              h->dDFail.as<int>(), h->dens_maxd,
-                              h->dDEv.as<double>(), h->dens_ntot, keep, h->dDKept.as<int>(), evals,
-                              evecs, h->dDNk.as<int>(), h->dDSums.as<double>(), s));
-    std::vector<int> nk(nb), nofit(nb);
-    std::vector<double> sums(2 * (size_t)nb);
-    HIP_TRY(h, hipMemcpyAsync(nk.data(), h->dDNk.p, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
-    HIP_TRY(h, hipMemcpyAsync(sums.data(), h->dDSums.p, sizeof(double) * 2 * nb,
-                              hipMemcpyDeviceToHost, s));
-    HIP_TRY(h, hipMemcpyAsync(nofit.data(), h->dDFail.p, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+    // per-call pointers and weights go by value in the launch
+    DensIn in{};
+    for (int l = 0; l < nvec; ++l) {
+        in.v[l] = vecs[l];
+        in.w[l] = weights[l];
+    }
+    double* d_sums = h->dDRes.as<double>();
+    int* d_nk = reinterpret_cast<int*>(d_sums + 2 * (size_t)nb);
+    int* d_flags = d_nk + nb;
+    HIP_TRY(h, launch_density(h->dDBlk.as<DBlock>(), nb, h->dDSel.as<int>(), h->dens_nreg,
+                              h->dDTile.as<DTile>(), h->dens_ntiles, in, nvec, P.n, h->dDA.p,
+                              h->dDV.p, h->dDZ.as<double>(), h->dDS.as<double>(), d_flags,
+                              h->dens_maxd, h->dDEv.as<double>(), h->dens_ntot, keep,
+                              h->dDKept.as<int>(), evals, evecs, d_nk, d_sums, s));
+    HIP_TRY(h, hipMemcpyAsync(h->hDRes.p, h->dDRes.p, res_bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));
+    const double* sums = h->hDRes.as<double>();
+    const int* nk = reinterpret_cast<const int*>(sums + 2 * (size_t)nb);
+    const int* flags = nk + nb;
     for (int b = 0; b < nb; ++b)
-        if (nofit[b] & 1) return fail(h, DMRG_ENONFINITE, "density matrix: QL iteration did not converge");
+        if (flags[b] & 1) return fail(h, DMRG_ENONFINITE, "density matrix: QL iteration did not converge");
     double all = 0.0, kept_sum = 0.0;
     for (int b = 0; b < nb; ++b) {
         kept[b] = nk[b];

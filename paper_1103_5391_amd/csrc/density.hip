@@ -9,7 +9,8 @@
 //   k_density   rho_p in 16 x 16 tiles (one work group per tile; row panels of the blocks staged
 //               through LDS, K = e_q columns per target, every target in turn)
 //   k_heig      eigen-decomposition of every rho_p up to the back-transformation, one work
-//               group per sector: Householder reduction to a real tridiagonal matrix T,
+//               group per sector (k_heig_r for sectors of up to 160 states, with the matrix
+//               in registers during the reduction): Householder reduction to a real tridiagonal matrix T,
 //               eigenvalues of T by multisection on Sturm counts, eigenvectors of T by inverse
 //               iteration (no cluster of close eigenvalues larger than 8) or else by implicit QL
 //               with shifts (one lane lists the rotations of the next sweep while the other
@@ -45,6 +46,14 @@ __device__ __forceinline__ double recip(double x) {
     return fma(fma(-x, r0, 1.0), r0, r0);
 }
 
+// 1 / sqrt(x), x > 0: the hardware reciprocal square root and two Newton steps
+__device__ __forceinline__ double rsqrt_nr(double x) {
+    double y = __builtin_amdgcn_rsq(x);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    y = fma(0.5 * y, fma(-x * y, y, 1.0), y);
+    return y;
+}
+
 // Sum over a work group of NT threads, the same value returned to every thread; fixed order.
 template <int NT>
 __device__ double group_sum(double v, double* scratch) {
@@ -72,11 +81,13 @@ __device__ __forceinline__ void handover_barrier() {
 // rho tiles: element (i, j) = sum_l w_l sum_c Psi_l[i, c] conj(Psi_l[j, c]), written to A
 // (complex, column-major d x d at blk.aoff).  Thread (ti, tj) of the 16 x 16 work group owns
 // element (i0 + ti, j0 + tj).
+// Work group 0 also clears the per-sector flags of the eigen-decomposition.
 __global__ __launch_bounds__(256) void k_density(const DBlock* __restrict__ blks,
-                                                 const DTile* __restrict__ tiles,
-                                                 const double* const* __restrict__ vecs,
-                                                 const double* __restrict__ weights, int nv,
-                                                 int64_t n, dv2* __restrict__ A) {
+                                                 const DTile* __restrict__ tiles, const DensIn in,
+                                                 int nv, int64_t n, dv2* __restrict__ A,
+                                                 int* __restrict__ fail, int nblk) {
+    if (blockIdx.x == 0)
+        for (int t = threadIdx.x; t < nblk; t += blockDim.x) fail[t] = 0;
     const DTile tl = tiles[blockIdx.x];
     const DBlock B = blks[tl.blk];
     const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
@@ -84,8 +95,8 @@ __global__ __launch_bounds__(256) void k_density(const DBlock* __restrict__ blks
     const int i = tl.i0 + ti, j = tl.j0 + tj;
     double sr = 0.0, si = 0.0;
     for (int l = 0; l < nv; ++l) {
-        const double* x = vecs[l];
-        const double w = weights[l];
+        const double* x = in.v[l];
+        const double w = in.w[l];
         double lr = 0.0, li = 0.0;
         for (int c0 = 0; c0 < B.e; c0 += 16) {
             // thread (ti, tj) stages element (row ti, column tj) of both panels
@@ -168,9 +179,270 @@ constexpr double kClusterGap = 1e-5;  // eigenvalues closer than this times |T| 
 constexpr int kSturmPts = 1;        // Sturm sequences one lane evaluates together in bisection
 constexpr int kSturmRun = 8;        // Sturm steps whose LDS reads are issued together
 constexpr int kInvRun = 8;          // rows an inverse-iteration solve loads before storing
+constexpr int kInvSolves = 2;       // inverse-iteration solves per eigenvector
 constexpr int kHhLdsDim = 66;       // largest trailing matrix the Householder phase keeps in LDS
 constexpr int kEigChunk = 16;       // loads a thread issues together in the QL rotation pass
                                     // (their values do not depend on the stores)
+
+constexpr int kEigThreadsR = 1024;  // threads of the register-resident eigen-decomposition
+constexpr int kRegBlocks = 5;        // 32-row blocks of the matrix it holds in registers
+constexpr int kRegMaxDim = 32 * kRegBlocks;   // largest sector it takes
+static_assert(kRegMaxDim == kDensRegMaxDim, "register-resident limit of the planner");
+
+// A DPP move of a double (both halves), rows ROWS only; disabled and out-of-row lanes read 0.
+template <int CTRL, int ROWS = 0xF>
+__device__ __forceinline__ double dpp_mov(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+
+// A DPP shift of a double within rows of 16 lanes; lanes without a source read 0.
+template <int CTRL>
+__device__ __forceinline__ double dpp_shr(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+
+// Sum over each 32-lane half of the wavefront into its last lane (31 and 63), for N values
+// level by level: shifts by 1, 2, 4 and 8 lanes within each row of 16 (lane 15 of a row then
+// holds the row's sum), then lane 15 of rows 0 and 2 added into rows 1 and 3.  Other lanes hold
+// partial sums.
+template <int N>
+__device__ __forceinline__ void half_sums(double (&v)[N]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x111>(v[q]);          // row_shr:1
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x112>(v[q]);          // row_shr:2
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x114>(v[q]);          // row_shr:4
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_shr<0x118>(v[q]);          // row_shr:8
+#pragma unroll
+    for (int q = 0; q < N; ++q) v[q] += dpp_mov<0x142, 0xA>(v[q]);     // row_bcast:15, rows 1, 3
+}
+__device__ __forceinline__ double half_sum(double v) {
+    double a[1] = {v};
+    half_sums<1>(a);
+    return a[0];
+}
+
+// Sum over the 64 lanes of a wavefront, the same value in every lane; waves that sum the same
+// values lane for lane get the same bits (the same additions in the same order).
+__device__ __forceinline__ double wave_sum(double v) {
+    v = half_sum(v);
+    const double lo = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 31),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 31));
+    const double hi = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), 63),
+                                       __builtin_amdgcn_readlane(__double2loint(v), 63));
+    return lo + hi;
+}
+
+// acc + a b and acc - a conj(b) as four fused multiply-adds each
+__device__ __forceinline__ dv2 cmac(dv2 acc, dv2 a, dv2 b) {
+    acc.x = fma(a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(a.y, b.x, acc.y);
+    return acc;
+}
+__device__ __forceinline__ dv2 cmsc(dv2 acc, dv2 a, dv2 b) {
+    acc.x = fma(-a.x, b.x, acc.x);
+    acc.x = fma(-a.y, b.y, acc.x);
+    acc.y = fma(a.x, b.y, acc.y);
+    acc.y = fma(-a.y, b.x, acc.y);
+    return acc;
+}
+
+// Householder reduction to a real tridiagonal matrix (the arithmetic of step 1 of the general
+// kernel below: the same reflectors, tau_k on the diagonal of A, v_k below the subdiagonal),
+// with the lower triangle of the matrix in the registers of a work group of 1024 threads, a 32 x
+// 32 grid: thread (r, c) = (tid mod 32, tid div 32) holds element (32 I + r, 32 J + c) for
+// J <= I < S in slot I (I + 1) / 2 + J; entries above the diagonal and beyond d are zeros and
+// stay zeros.  The update of step k is applied at once.  Step k:
+//   1. the thread of column k that holds row i >= 32 (k div 32) stores x_i (0 for i <= k) into
+//      xs (LDS; two buffers by the parity of k) and the diagonal entry into dg;
+//   2. the waves of the vector threads (t < 32 S) form the same reflector from xs (the same
+//      sums in the same order), and thread t stores v_t (0 outside k < t < d) into vs;
+//   3. the product B v over the trailing matrix: from its slots a thread forms row sums
+//      (B_ij v_j, j <= i) and column sums (conj(B_ij) v_i into entry j, i > j); each half-wave
+//      stores its row of row sums (rp), and the column sums over its 32 lanes, added by DPP
+//      moves, are complete (cs);
+//   4. thread t adds the half-waves' rows and the column sum of entry t: w0_t = tau p_t (ps);
+//   5. those waves form the same w0^H v, and thread t stores w_t = w0_t - (tau / 2)(w0^H v) v_t;
+//   6. each thread applies B <- B - v w^H - w v^H to its slots.
+// Entries at or above k enter only through v and w, which vanish there, so the stale rows and
+// columns of earlier steps are never masked.  Barriers end steps 1 to 5.
+template <int S>
+__device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double* __restrict__ dg,
+                                        double* __restrict__ e, dv2* __restrict__ xs0,
+                                        dv2* __restrict__ xs1, dv2* __restrict__ vs,
+                                        dv2* __restrict__ ws, dv2* __restrict__ ps,
+                                        dv2* __restrict__ cs, dv2* __restrict__ rp) {
+    constexpr int NW = kEigThreadsR / 64, MD = 32 * S;
+    const int tid = threadIdx.x, r = tid & 31, c = tid >> 5, wv = tid >> 6, ln = tid & 63;
+    const bool vw = wv < (MD + 63) / 64;                // a wave of the vector threads t < MD
+    const dv2 z = (dv2){0.0, 0.0};
+    dv2 m[S * (S + 1) / 2];
+#pragma unroll
+    for (int I = 0; I < S; ++I)
+#pragma unroll
+        for (int J = 0; J <= I; ++J) {
+            const int i = 32 * I + r, j = 32 * J + c;
+            dv2 x = z;
+            if (i < d && (I > J || r >= c)) x = a[(int64_t)j * d + i];
+            m[I * (I + 1) / 2 + J] = x;
+        }
+    for (int k = 0; k + 1 < d; ++k) {
+        dv2* __restrict__ xs = (k & 1) ? xs1 : xs0;
+        const int kb = k >> 5;                          // block of column k
+        const int lo = (k + 1) >> 5;                    // blocks below lo hold no entry > k
+        // 1.
+        if (c == (k & 31)) {
+#pragma unroll
+            for (int I = 0; I < S; ++I)
+#pragma unroll
+                for (int J = 0; J <= I; ++J)
+                    if (J == kb && I >= kb) {
+                        const int i = 32 * I + r;
+                        const dv2 x = m[I * (I + 1) / 2 + J];
+                        xs[i] = i > k ? x : z;
+                        if (i == k) dg[k] = x.x;
+                    }
+        }
+        __syncthreads();
+        // 2. (the waves of vector threads only)
+        dv2 tau = z;
+        if (vw) {
+            double part = 0.0;
+            for (int i = k + 2 + ln; i < d; i += 64) {
+                const dv2 x = xs[i];
+                part = fma(x.x, x.x, part);
+                part = fma(x.y, x.y, part);
+            }
+            const double xn2 = wave_sum(part);
+            const dv2 al = xs[k + 1];
+            dv2 sc = z;
+            double beta = al.x;
+            if (!(xn2 == 0.0 && al.y == 0.0)) {
+                beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
+                tau = (dv2){(beta - al.x) / beta, -al.y / beta};
+                const dv2 den = (dv2){al.x - beta, al.y};               // 1 / (alpha - beta)
+                const double q = den.x * den.x + den.y * den.y;
+                sc = (dv2){den.x / q, -den.y / q};
+            }
+            if (tid == 0) {
+                e[k] = beta;
+                a[(int64_t)k * d + k] = tau;
+            }
+            if (tid < MD && tid >= 32 * lo) {
+                dv2 v = z;
+                if (tid == k + 1) v = (dv2){1.0, 0.0};
+                else if (tid > k + 1 && tid < d) v = cmul(xs[tid], sc);
+                vs[tid] = v;
+                if (tid > k + 1 && tid < d) a[(int64_t)k * d + tid] = v;   // v_k below the subdiagonal
+            }
+        }
+        __syncthreads();
+        // 3.
+        {
+            dv2 pr[S];
+#pragma unroll
+            for (int I = 0; I < S; ++I) pr[I] = z;
+#pragma unroll
+            for (int J = 0; J < S; ++J) {
+                if (J < lo) continue;
+                const dv2 vc = vs[32 * J + c];
+#pragma unroll
+                for (int I = J; I < S; ++I) pr[I] = cmac(pr[I], m[I * (I + 1) / 2 + J], vc);
+            }
+#pragma unroll
+            for (int I = 0; I < S; ++I)
+                if (I >= lo) rp[(2 * wv + (ln >> 5)) * MD + 32 * I + r] = pr[I];
+        }
+        {
+            dv2 vr[S];
+            double pc[2 * S];
+#pragma unroll
+            for (int I = 0; I < S; ++I) vr[I] = I >= lo ? vs[32 * I + r] : z;
+#pragma unroll
+            for (int J = 0; J < S; ++J) {
+                dv2 q = z;
+                if (J >= lo) {
+#pragma unroll
+                    for (int I = J; I < S; ++I) {
+                        // conj(B_ij) v_i; the diagonal entry counts once, in the row sums
+                        const dv2 b = m[I * (I + 1) / 2 + J];
+                        q = cmac(q, (I > J || r != c) ? cconj(b) : z, vr[I]);
+                    }
+                }
+                pc[2 * J] = q.x;
+                pc[2 * J + 1] = q.y;
+            }
+            half_sums<2 * S>(pc);
+#pragma unroll
+            for (int J = 0; J < S; ++J)
+                if (J >= lo && r == 31) cs[32 * J + c] = (dv2){pc[2 * J], pc[2 * J + 1]};
+        }
+        __syncthreads();
+        // 4.
+        if (tid < MD && tid >= 32 * lo) {
+            dv2 p = cs[tid];
+#pragma unroll
+            for (int w = 0; w < 2 * NW; ++w) p += rp[w * MD + tid];
+            ps[tid] = (tid > k && tid < d) ? cmul(tau, p) : z;
+        }
+        __syncthreads();
+        // 5.
+        if (vw) {
+            double sr = 0.0, si = 0.0;                  // w0^H v
+            for (int i = k + 1 + ln; i < d; i += 64) {
+                const dv2 w = ps[i], v = vs[i];
+                sr = fma(w.x, v.x, sr);
+                sr = fma(w.y, v.y, sr);
+                si = fma(w.x, v.y, si);
+                si = fma(-w.y, v.x, si);
+            }
+            sr = wave_sum(sr);
+            si = wave_sum(si);
+            const dv2 al2 = cmul((dv2){-0.5 * tau.x, -0.5 * tau.y}, (dv2){sr, si});
+            if (tid < MD && tid >= 32 * lo) ws[tid] = cmac(ps[tid], al2, vs[tid]);
+        }
+        __syncthreads();
+        // 6.
+        {
+            dv2 vr[S], wr[S];
+#pragma unroll
+            for (int I = 0; I < S; ++I) {
+                vr[I] = I >= lo ? vs[32 * I + r] : z;
+                wr[I] = I >= lo ? ws[32 * I + r] : z;
+            }
+#pragma unroll
+            for (int J = 0; J < S; ++J) {
+                if (J < lo) continue;
+                const dv2 vc = vs[32 * J + c], wc = ws[32 * J + c];
+#pragma unroll
+                for (int I = J; I < S; ++I) {
+                    if (I > J || r >= c) {
+                        dv2& b = m[I * (I + 1) / 2 + J];
+                        b = cmsc(b, vr[I], wc);
+                        b = cmsc(b, wr[I], vc);
+                    }
+                }
+            }
+        }
+    }
+    if (d > 0) {
+        const int k = d - 1, kb = k >> 5;
+        if (r == (k & 31) && c == (k & 31)) {
+#pragma unroll
+            for (int I = 0; I < S; ++I)
+                if (I == kb) dg[k] = m[I * (I + 1) / 2 + I].x;
+        }
+        if (tid == 0) e[k] = 0.0;
+    }
+}
 
 // Eigen-decomposition of rho_p up to the back-transformation, one work group per sector
 // (LAPACK's path for Hermitian matrices):
@@ -187,25 +459,30 @@ constexpr int kEigChunk = 16;       // loads a thread issues together in the QL 
 // Eigenvalues go to ev, eigenvectors to Z (row-major, or column-major after QL: bit 1 of
 // fail[blk]); k_heig_back applies the reflectors.  A QL sweep count above the limit sets bit 0
 // of fail[blk].
-__global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__ blks,
-                                                      dv2* __restrict__ A, double* __restrict__ Zb,
-                                                      double* __restrict__ Sb, dv2* __restrict__ Yb,
-                                                      double* __restrict__ ev, int* __restrict__ fail) {
-    constexpr int NT = kEigThreads;
-    const DBlock B = blks[blockIdx.x];
+// NT threads, sectors of at most MAXD states; REG: step 1 by hh_regs (NT = kEigThreadsR).
+// Bisection takes GB lanes per eigenvalue, the largest power of two up to 8 with 2 GB d <= SBT.
+template <int NT, int MAXD, bool REG, int SBT = NT>
+__device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restrict__ A,
+                                     double* __restrict__ Zb, double* __restrict__ Sb,
+                                     double* __restrict__ ev, int* __restrict__ fail) {
     const int d = B.d, tid = threadIdx.x;
     dv2* __restrict__ a = A + B.aoff;
     double* __restrict__ Z = Zb + B.aoff;
-    dv2* __restrict__ Y = Yb + B.aoff;
-    __shared__ double dg[kDensMaxDim], e[kDensMaxDim];
-    __shared__ dv2 vv[kDensMaxDim], ww[kDensMaxDim], vv1[kDensMaxDim], ww1[kDensMaxDim];
+    __shared__ double dg[MAXD], e[MAXD];
+    __shared__ dv2 vv[MAXD], ww[MAXD], vv1[MAXD], ww1[MAXD];
     __shared__ dv2 pp[NT];
     __shared__ double red[3 * NT / 64];
     __shared__ int s_i0[2], s_cnt[2], s_done[2], s_path;
     __shared__ double s_lo, s_hi, s_tn;
+    // ---------------------------------------------------------------- 1. tridiagonal
+    if constexpr (REG) {
+        static_assert(NT == kEigThreadsR && MAXD % 32 == 0, "32 x 32 thread grid");
+        __shared__ dv2 rp[2 * (NT / 64) * MAXD];        // row sums of the half-waves
+        __shared__ dv2 vs[MAXD], ws[MAXD];
+        hh_regs<MAXD / 32>(d, a, dg, e, vv, vv1, vs, ws, ww, ww1, rp);
+    } else {
     __shared__ dv2 s_alpha;                             // alpha of the current reflector
     __shared__ dv2 tm[kHhLdsDim * kHhLdsDim];          // trailing matrix once it fits
-    // ---------------------------------------------------------------- 1. tridiagonal
     // The update of step k is applied lazily, inside step k + 1's pass over the trailing
     // matrix, which also forms that step's product B v: one read and one write of the trailing
     // matrix per step.  The pending update is kept as (v, w0, al2) with w = w0 + al2 v, in one
@@ -335,6 +612,7 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
             e[d - 1] = 0.0;
         }
     }
+    }
     __syncthreads();
     // ---------------------------------------------------------------- 2. eigenvalues
     // Bisection on Sturm counts (the signs of the pivots of T - x I = L D L^T), one thread per
@@ -363,12 +641,15 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
         // (independent Sturm sequences interleaved in one pass over T): the lanes count at
         // GB kSturmPts interior points of the interval and keep the piece that holds the
         // eigenvalue
+        // Only the whole wavefronts that hold eigenvalues take part (nact threads; lanes past
+        // the last eigenvalue repeat it, so that every lane of a wave runs the same rounds).
         constexpr int P = kSturmPts;
         int GB = 1;
-        while (GB < 8 && 2 * GB * d <= NT) GB *= 2;
-        const int qb = tid % GB, jslots = NT / GB;
+        while (GB < 8 && 2 * GB * d <= SBT) GB *= 2;
+        const int nact = GB * d >= NT ? NT : (GB * d + 63) / 64 * 64;
+        const int qb = tid % GB, jslots = nact / GB;
         const int jend = (d + jslots - 1) / jslots * jslots;
-        for (int j0 = tid / GB; j0 < jend; j0 += jslots) {
+        for (int j0 = tid / GB; tid < nact && j0 < jend; j0 += jslots) {
             const int j = j0 < d ? j0 : d - 1;
             double lo = s_lo, hi = s_hi;
             for (int it = 0; it < 256; ++it) {
@@ -444,7 +725,7 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     if (s_path == 0) {
         // ------------------------------------------------------------ 3a. inverse iteration
         // The thread of the first eigenvalue of each cluster takes the cluster's eigenvectors in
-        // order: T - lam I = P L U (partial pivoting), three solves from a fixed start, each
+        // order: T - lam I = P L U (partial pivoting), kInvSolves solves from a fixed start, each
         // orthogonalised against the cluster's earlier vectors.  Z and the factors are
         // row-major [i][j] (consecutive threads, consecutive addresses).
         double* u0 = Sb + 5 * B.aoff;                   // 1 / pivot
@@ -506,7 +787,7 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
                     }
                 }
                 double scale = 1.0;
-                for (int rep = 0; rep < 3; ++rep) {
+                for (int rep = 0; rep < kInvSolves; ++rep) {
                     // forward: P and L^-1 (the current entry carried in a register); a run of
                     // kInvRun rows is loaded before any of it is stored (row i is stored only
                     // after row i + 1 is read, so no load depends on the stores)
@@ -586,7 +867,7 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     // Wavefront 0 (its first lane) runs the sweep recurrence and lists the rotations of the next
     // sweep while the other wavefronts apply the current one (two rotation lists in LDS).
     auto rcl = [&](int buf) { return buf ? reinterpret_cast<double*>(ww) : reinterpret_cast<double*>(vv); };
-    auto rsl = [&](int buf) { return rcl(buf) + kDensMaxDim; };
+    auto rsl = [&](int buf) { return rcl(buf) + MAXD; };
     int l = 0, sweeps = 0;                              // scalar state (thread 0)
     auto next_sweep = [&](int buf) {                    // thread 0: the next sweep into list buf
         double* rc = rcl(buf);
@@ -606,7 +887,7 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
                 continue;
             }
             if (++sweeps > kQlMaxSweeps) {
-                fail[blockIdx.x] = 1;
+                fail[blk] = 1;
                 s_done[buf] = 1;
                 return;
             }
@@ -621,15 +902,20 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
             for (int i = m - 1; i >= l; --i) {
                 const double en = i > l ? e[i - 1] : 0.0, dn = i > l ? dg[i - 1] : 0.0;
                 const double f = sn * ei, b = cs * ei;
-                r = sqrt(f * f + g * g);
-                e[i + 1] = r;
-                if (r == 0.0) {
+                // r = sqrt(f^2 + g^2) and 1 / r from the hardware reciprocal square root with
+                // two Newton steps (a few ulp; the IEEE square root and division take a much
+                // longer dependent chain, and this recurrence runs on one lane)
+                const double s2 = fma(f, f, g * g);
+                if (s2 == 0.0) {
+                    e[i + 1] = 0.0;
                     dg[i + 1] = di1 - p;
                     e[m] = 0.0;
                     early = true;
                     break;
                 }
-                const double rinv = 1.0 / r;
+                const double rinv = rsqrt_nr(s2);
+                r = s2 * rinv;
+                e[i + 1] = r;
                 sn = f * rinv;
                 cs = g * rinv;
                 g = di1 - p;
@@ -691,8 +977,29 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
     handover_barrier();                                 // rows of Z to the column owners
     for (int i = tid; i < d; i += NT) ev[B.eoff + i] = dg[i];
     }
-    if (tid == 0 && zr == 1) atomicOr(&fail[blockIdx.x], 2);   // Z column-major (QL path)
+    if (tid == 0 && zr == 1) atomicOr(&fail[blk], 2);   // Z column-major (QL path)
+}
 
+// sel: the sectors of the launch, one per work group
+__global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__ blks,
+                                                      const int* __restrict__ sel,
+                                                      dv2* __restrict__ A, double* __restrict__ Zb,
+                                                      double* __restrict__ Sb,
+                                                      double* __restrict__ ev, int* __restrict__ fail) {
+    const int b = sel[blockIdx.x];
+    heig<kEigThreads, kDensMaxDim, false>(blks[b], b, A, Zb, Sb, ev, fail);
+}
+
+// The same for sectors of at most kRegMaxDim states, with the matrix in registers in step 1.
+__global__ __launch_bounds__(kEigThreadsR) void k_heig_r(const DBlock* __restrict__ blks,
+                                                         const int* __restrict__ sel,
+                                                         dv2* __restrict__ A,
+                                                         double* __restrict__ Zb,
+                                                         double* __restrict__ Sb,
+                                                         double* __restrict__ ev,
+                                                         int* __restrict__ fail) {
+    const int b = sel[blockIdx.x];
+    heig<kEigThreadsR, kRegMaxDim, true>(blks[b], b, A, Zb, Sb, ev, fail);
 }
 
 // Back-transformation Y = H_0 H_1 ... H_{d-2} Z of one sector's eigenvectors (one work group
@@ -705,7 +1012,8 @@ __global__ __launch_bounds__(kEigThreads) void k_heig(const DBlock* __restrict__
 // factors (zero reflector, tau = 0) so that every block has BT of them.  The work group's
 // columns of Y stay in LDS from the load of Z to the final store.  kBackLanes lanes per column:
 // lane q takes the rows i = q mod kBackLanes, the group adds its partial inner products by
-// shuffles.  T is built by one wavefront, lane r holding row r in registers.
+// shuffles.  T is built by one wavefront, lane r holding row r in registers.  Y is stored
+// column-major (column j at j d), so that the stores and k_finish's copies are contiguous.
 constexpr int kBackThreads = 256;
 constexpr int kBackLanes = 8;       // lanes per column of Y
 constexpr int kBackCols = kBackThreads / kBackLanes;   // most columns of Y per work group
@@ -852,7 +1160,7 @@ __global__ __launch_bounds__(kBackThreads) void k_heig_back(const DBlock* __rest
     else
         back_blocks<2>(d, nc, a, Vs, Ys, Tt, Gm, taus);
     for (int jl = 0; jl < nc; ++jl)
-        for (int i = tid; i < d; i += NT) Y[(int64_t)i * d + jb + jl] = Ys[jl * d + i];
+        for (int i = tid; i < d; i += NT) Y[(int64_t)(jb + jl) * d + i] = Ys[jl * d + i];
 }
 
 // Global rank of eigenvalue g among all ntot (larger first, equal values by sector then index:
@@ -899,6 +1207,7 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
     const DBlock B = blks[blockIdx.x];
     const int d = B.d, tid = threadIdx.x;
     __shared__ double scratch[kVecThreads];
+    __shared__ int src_of[kDensMaxDim];                 // output position r <- eigenvector i
     const double* e = ev + B.eoff;
     double all = 0.0, ksum = 0.0, kc = 0.0;
     for (int i = tid; i < d; i += blockDim.x) {
@@ -906,18 +1215,23 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
         int r = 0;
         for (int h = 0; h < d; ++h) r += (e[h] > x) || (e[h] == x && h < i);
         evals[B.eoff + r] = x;
-        const dv2* src = V + B.aoff + i;                 // column i of a row-major matrix
-        double* dre = evecs + 2 * B.aoff + (int64_t)r * d;
-        double* dim = dre + (int64_t)d * d;
-        for (int row = 0; row < d; ++row) {
-            const dv2 z = src[(int64_t)row * d];
-            dre[row] = z.x;
-            dim[row] = z.y;
-        }
+        src_of[r] = i;
         all += x;
         if (rank[B.eoff + i] < keep) {
             ksum += x;
             kc += 1.0;
+        }
+    }
+    __syncthreads();
+    // V column-major (column i at V + aoff + i d): each output column is a contiguous copy
+    for (int r = 0; r < d; ++r) {
+        const dv2* src = V + B.aoff + (int64_t)src_of[r] * d;
+        double* dre = evecs + 2 * B.aoff + (int64_t)r * d;
+        double* dim = dre + (int64_t)d * d;
+        for (int row = tid; row < d; row += blockDim.x) {
+            const dv2 z = src[row];
+            dre[row] = z.x;
+            dim[row] = z.y;
         }
     }
     all = group_sum<kVecThreads>(all, scratch);
@@ -930,15 +1244,20 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
     }
 }
 
-hipError_t launch_density(const DBlock* blks, int nblk, const DTile* tiles, int ntiles,
-                          const double* const* vecs, const double* weights, int nv, int64_t n,
+hipError_t launch_density(const DBlock* blks, int nblk, const int* sel, int nreg,
+                          const DTile* tiles, int ntiles, const DensIn& in, int nv, int64_t n,
                           void* A, void* V, double* Z, double* S, int* fail, int maxd, double* ev,
                           int ntot, int keep, int* kept, double* evals, double* evecs, int* nkept,
                           double* sums, hipStream_t s) {
-    hipLaunchKernelGGL(k_density, dim3(ntiles), dim3(256), 0, s, blks, tiles, vecs, weights, nv, n,
-                       static_cast<dv2*>(A));
-    hipLaunchKernelGGL(k_heig, dim3(nblk), dim3(kEigThreads), 0, s, blks, static_cast<dv2*>(A), Z, S,
-                       static_cast<dv2*>(V), ev, fail);
+    hipLaunchKernelGGL(k_density, dim3(ntiles), dim3(256), 0, s, blks, tiles, in, nv, n,
+                       static_cast<dv2*>(A), fail, nblk);
+    // sel: first the nreg sectors of the register-resident kernel, then the others
+    if (nreg > 0)
+        hipLaunchKernelGGL(k_heig_r, dim3(nreg), dim3(kEigThreadsR), 0, s, blks, sel,
+                           static_cast<dv2*>(A), Z, S, ev, fail);
+    if (nblk > nreg)
+        hipLaunchKernelGGL(k_heig, dim3(nblk - nreg), dim3(kEigThreads), 0, s, blks, sel + nreg,
+                           static_cast<dv2*>(A), Z, S, ev, fail);
     // work groups per sector: ceil(d / back_cols(d)) grows with d, so maxd gives the most
     const int bcy = (maxd + back_cols(maxd) - 1) / back_cols(maxd);
     hipLaunchKernelGGL(k_heig_back, dim3(nblk, bcy), dim3(kBackThreads), 0, s, blks,

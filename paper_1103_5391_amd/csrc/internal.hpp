@@ -262,6 +262,11 @@ struct DTile {            // 16 x 16 tile of one sector's density matrix
 };
 constexpr int kDensMaxDim = 1024;   // largest system sector the eigen-decomposition accepts
 constexpr int kDensMaxVec = 16;     // most target vectors of one density matrix
+struct DensIn {            // target vectors (device, 2n doubles each) and their weights
+    const double* v[kDensMaxVec];
+    double w[kDensMaxVec];
+};
+constexpr int kDensRegMaxDim = 160;   // sectors up to this size take the register-resident kernel
 
 // One 32 x 32 tile of a complex product C = alpha A B (+ C if acc) (FP64; complex operands
 // have real parts at off and imaginary parts at off + im).  A modes: 0 complex column-major,
