@@ -43,8 +43,8 @@ hipError_t launch_tridiag(const VecGroup&, const double*, int, int*, int, hipStr
 hipError_t launch_lowest(const VecGroup&, int*, int, hipStream_t);
 hipError_t launch_count_nonfinite(const double*, int64_t, int*, hipStream_t);
 hipError_t launch_density(const DBlock*, int, const int*, int, const DTile*, int, const DensIn&, int,
-                          int64_t, void*, void*, double*, double*, int*, int, double*, int, int,
-                          int*, double*, double*, int*, double*, hipStream_t);
+                          int64_t, void*, void*, double*, double*, void*, int, int*, int, double*,
+                          int, int, int*, double*, double*, int*, double*, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const ZPtrs&, int, int64_t,
                       hipStream_t);
@@ -425,9 +425,9 @@ struct dmrg_ctx {
     // density matrix and truncation (built on first use): sectors, tiles, matrices, results
     // the call's results in one device area (per sector: the two sums, the number kept, the
     // eigen-decomposition flags), copied at once into pinned host memory
-    DevBuf dDBlk, dDSel, dDTile, dDA, dDV, dDZ, dDS, dDEv, dDKept, dDRes;
+    DevBuf dDBlk, dDSel, dDTile, dDA, dDV, dDZ, dDS, dDT, dDEv, dDKept, dDRes;
     HostBuf hDRes;
-    int dens_ntiles = 0, dens_ntot = 0, dens_maxd = 0, dens_nreg = 0;
+    int dens_ntiles = 0, dens_ntot = 0, dens_maxd = 0, dens_nreg = 0, dens_nbt = 0;
     int64_t dens_nmat = 0;
     std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
     // local operators (built on first use): raw operator blocks of both halves, the product
@@ -1648,15 +1648,17 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
         std::vector<DBlock> blks(nb);
         std::vector<DTile> tiles;
         std::vector<int> sel;
-        int64_t aoff = 0, eoff = 0;
+        int64_t aoff = 0, eoff = 0, toff = 0;
         for (int b = 0; b < nb; ++b) {
             const PsiBlock& pbk = P.blocks[b];
             if (pbk.d > kDensMaxDim) return fail(h, DMRG_EINVAL, "system sector larger than 1024");
-            blks[b] = DBlock{pbk.d, pbk.e, pbk.off, aoff, eoff};
+            blks[b] = DBlock{pbk.d, pbk.e, pbk.off, aoff, eoff, toff};
+            toff += (int64_t)back_nblocks(pbk.d) * back_bt(pbk.d) * back_bt(pbk.d);
+            h->dens_nbt = std::max(h->dens_nbt, back_nblocks(pbk.d));
             h->dens_maxd = std::max(h->dens_maxd, pbk.d);
             if (pbk.d <= kDensRegMaxDim) sel.push_back(b);
-            for (int i0 = 0; i0 < pbk.d; i0 += 16)
-                for (int j0 = 0; j0 < pbk.d; j0 += 16) tiles.push_back(DTile{b, i0, j0, 0});
+            for (int i0 = 0; i0 < pbk.d; i0 += 16)       // tiles on and below the diagonal
+                for (int j0 = 0; j0 <= i0; j0 += 16) tiles.push_back(DTile{b, i0, j0, 0});
             aoff += (int64_t)pbk.d * pbk.d;
             eoff += pbk.d;
         }
@@ -1674,6 +1676,7 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
         HIP_TRY(h, h->dDV.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDZ.alloc(sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDS.alloc(5 * sizeof(double) * (size_t)aoff));
+        HIP_TRY(h, h->dDT.alloc(2 * sizeof(double) * (size_t)toff));
         HIP_TRY(h, h->dDEv.alloc(sizeof(double) * (size_t)eoff));
         HIP_TRY(h, h->dDKept.alloc(sizeof(int) * (size_t)eoff));
         HIP_TRY(h, h->dDRes.alloc(res_bytes));
@@ -1691,7 +1694,8 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
     int* d_flags = d_nk + nb;
     HIP_TRY(h, launch_density(h->dDBlk.as<DBlock>(), nb, h->dDSel.as<int>(), h->dens_nreg,
                               h->dDTile.as<DTile>(), h->dens_ntiles, in, nvec, P.n, h->dDA.p,
-                              h->dDV.p, h->dDZ.as<double>(), h->dDS.as<double>(), d_flags,
+                              h->dDV.p, h->dDZ.as<double>(), h->dDS.as<double>(), h->dDT.p,
+                              h->dens_nbt, d_flags,
                               h->dens_maxd, h->dDEv.as<double>(), h->dens_ntot, keep,
                               h->dDKept.as<int>(), evals, evecs, d_nk, d_sums, s));
     HIP_TRY(h, hipMemcpyAsync(h->hDRes.p, h->dDRes.p, res_bytes, hipMemcpyDeviceToHost, s));

@@ -6,8 +6,8 @@
 // targets lie in one (N_up, N_dn) sector, so rho is block diagonal over the system sectors p:
 //   rho_p = sum_l w_l Psi_{l,p} Psi_{l,p}^H       (d_p x d_p, complex Hermitian)
 // with Psi_{l,p} the d_p x e_q block of target l.  Steps:
-//   k_density   rho_p in 16 x 16 tiles (one work group per tile; row panels of the blocks staged
-//               through LDS, K = e_q columns per target, every target in turn)
+//   k_density   rho_p in 16 x 16 tiles on or below the diagonal (one wavefront per tile on the
+//               FP64 matrix cores, K = e_q columns per target, every target in turn)
 //   k_heig      eigen-decomposition of every rho_p up to the back-transformation, one work
 //               group per sector (k_heig_r for sectors of up to 160 states, with the matrix
 //               in registers during the reduction): Householder reduction to a real tridiagonal matrix T,
@@ -78,50 +78,77 @@ __device__ __forceinline__ void handover_barrier() {
 
 }  // namespace
 
-// rho tiles: element (i, j) = sum_l w_l sum_c Psi_l[i, c] conj(Psi_l[j, c]), written to A
-// (complex, column-major d x d at blk.aoff).  Thread (ti, tj) of the 16 x 16 work group owns
-// element (i0 + ti, j0 + tj).
-// Work group 0 also clears the per-sector flags of the eigen-decomposition.
-__global__ __launch_bounds__(256) void k_density(const DBlock* __restrict__ blks,
-                                                 const DTile* __restrict__ tiles, const DensIn in,
-                                                 int nv, int64_t n, dv2* __restrict__ A,
-                                                 int* __restrict__ fail, int nblk) {
+// rho tiles on the FP64 matrix cores: element (i, j) = sum_l w_l sum_c Psi_l[i, c]
+// conj(Psi_l[j, c]), as real products of the row panels P_i, P_j (16 rows, c along K) of every
+// target in turn,
+//   Re rho = sum_l w_l (Re P_i Re P_j^T + Im P_i Im P_j^T),
+//   Im rho = sum_l w_l (Im P_i Re P_j^T - Re P_i Im P_j^T),
+// one wavefront per tile (i0, j0) with j0 <= i0: v_mfma_f64_16x16x4f64 with lane (g, r) =
+// (lane div 16, lane mod 16) supplying row r of each panel at column c0 + g, the weight folded
+// into P_i, and the result in lane (g, r) at row g + 4 v, column r.  A tile below the diagonal
+// is also written, conjugated, at (j, i) (rho is Hermitian).  Written to A (complex,
+// column-major d x d at blk.aoff).  Work group 0 also clears the per-sector flags of the
+// eigen-decomposition.
+__global__ __launch_bounds__(64) void k_density(const DBlock* __restrict__ blks,
+                                                const DTile* __restrict__ tiles, const DensIn in,
+                                                int nv, int64_t n, dv2* __restrict__ A,
+                                                int* __restrict__ fail, int nblk) {
+    typedef double d4 __attribute__((ext_vector_type(4)));
     if (blockIdx.x == 0)
         for (int t = threadIdx.x; t < nblk; t += blockDim.x) fail[t] = 0;
     const DTile tl = tiles[blockIdx.x];
     const DBlock B = blks[tl.blk];
-    const int ti = threadIdx.x & 15, tj = threadIdx.x >> 4;
-    __shared__ double pr[2][16][17], pi[2][16][17];   // [row panel i / j][row][column]
-    const int i = tl.i0 + ti, j = tl.j0 + tj;
-    double sr = 0.0, si = 0.0;
+    const int ln = threadIdx.x, g = ln >> 4, r = ln & 15;
+    const int d = B.d, e = B.e;
+    const int ia = tl.i0 + r, jb = tl.j0 + r;
+    const bool oka = ia < d, okb = jb < d;
+    const int64_t ra = B.off + (oka ? ia : 0), rb = B.off + (okb ? jb : 0);
+    d4 cre[2] = {(d4){0.0, 0.0, 0.0, 0.0}, (d4){0.0, 0.0, 0.0, 0.0}};
+    d4 cim[2] = {(d4){0.0, 0.0, 0.0, 0.0}, (d4){0.0, 0.0, 0.0, 0.0}};
+    // one K chunk of 4 columns (c = c0 + g) into accumulator pair q
+    auto chunk = [&](double are, double aim, double bre, double bim, int q) {
+        cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(are, bre, cre[q], 0, 0, 0);
+        cre[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bim, cre[q], 0, 0, 0);
+        cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(aim, bre, cim[q], 0, 0, 0);
+        cim[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(-are, bim, cim[q], 0, 0, 0);
+    };
     for (int l = 0; l < nv; ++l) {
-        const double* x = in.v[l];
-        const double w = in.w[l];
-        double lr = 0.0, li = 0.0;
-        for (int c0 = 0; c0 < B.e; c0 += 16) {
-            // thread (ti, tj) stages element (row ti, column tj) of both panels
-            const int c = c0 + tj;
-            const int ri = tl.i0 + ti, rj = tl.j0 + ti;
-            const bool okc = c < B.e;
-            const int64_t bi = B.off + (int64_t)c * B.d + ri, bj = B.off + (int64_t)c * B.d + rj;
-            pr[0][ti][tj] = (okc && ri < B.d) ? x[bi] : 0.0;
-            pi[0][ti][tj] = (okc && ri < B.d) ? x[n + bi] : 0.0;
-            pr[1][ti][tj] = (okc && rj < B.d) ? x[bj] : 0.0;
-            pi[1][ti][tj] = (okc && rj < B.d) ? x[n + bj] : 0.0;
-            __syncthreads();
+        const double* __restrict__ x = in.v[l];
+        const double wa = oka ? in.w[l] : 0.0;          // rows beyond d: zero
+        const double mb = okb ? 1.0 : 0.0;
+        int c0 = 0;
+        for (; c0 + 16 <= e; c0 += 16) {                // four whole chunks, loads first
+            double v[4][4];
 #pragma unroll
-            for (int k = 0; k < 16; ++k) {
-                const double ar = pr[0][ti][k], ai = pi[0][ti][k];
-                const double br = pr[1][tj][k], bi2 = pi[1][tj][k];
-                lr += ar * br + ai * bi2;        // a conj(b)
-                li += ai * br - ar * bi2;
+            for (int u = 0; u < 4; ++u) {
+                const int64_t cc = (int64_t)(c0 + 4 * u + g) * d;
+                v[u][0] = x[ra + cc];
+                v[u][1] = x[n + ra + cc];
+                v[u][2] = x[rb + cc];
+                v[u][3] = x[n + rb + cc];
             }
-            __syncthreads();
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                chunk(wa * v[u][0], wa * v[u][1], mb * v[u][2], mb * v[u][3], u & 1);
         }
-        sr += w * lr;
-        si += w * li;
+        for (; c0 < e; c0 += 4) {                       // the rest, columns beyond e zero
+            const int c = c0 + g;
+            const bool okc = c < e;
+            const int64_t cc = (int64_t)(okc ? c : 0) * d;
+            const double sa = okc ? wa : 0.0, sb = okc ? mb : 0.0;
+            chunk(sa * x[ra + cc], sa * x[n + ra + cc], sb * x[rb + cc], sb * x[n + rb + cc], 0);
+        }
     }
-    if (i < B.d && j < B.d) A[B.aoff + (int64_t)j * B.d + i] = (dv2){sr, si};
+    const d4 sre = cre[0] + cre[1], sim = cim[0] + cim[1];
+    dv2* __restrict__ a = A + B.aoff;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        const int i = tl.i0 + g + 4 * v, j = tl.j0 + r;
+        if (i < d && j < d) {
+            a[(int64_t)j * d + i] = (dv2){sre[v], sim[v]};
+            if (tl.i0 != tl.j0) a[(int64_t)i * d + j] = (dv2){sre[v], -sim[v]};
+        }
+    }
 }
 
 // Sum over the work group (NT threads) of one double, returned to every thread: shuffles
@@ -181,6 +208,7 @@ constexpr int kSturmRun = 8;        // Sturm steps whose LDS reads are issued to
 constexpr int kInvRun = 8;          // rows an inverse-iteration solve loads before storing
 constexpr int kInvSolves = 2;       // inverse-iteration solves per eigenvector
 constexpr int kHhLdsDim = 66;       // largest trailing matrix the Householder phase keeps in LDS
+constexpr int kQlRun = 8;           // QL rotations whose LDS reads are issued together
 constexpr int kEigChunk = 16;       // loads a thread issues together in the QL rotation pass
                                     // (their values do not depend on the stores)
 
@@ -724,138 +752,182 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
     int zr = d, zc = 1;                                 // Z(i, j) at i zr + j zc
     if (s_path == 0) {
         // ------------------------------------------------------------ 3a. inverse iteration
-        // The thread of the first eigenvalue of each cluster takes the cluster's eigenvectors in
-        // order: T - lam I = P L U (partial pivoting), kInvSolves solves from a fixed start, each
-        // orthogonalised against the cluster's earlier vectors.  Z and the factors are
-        // row-major [i][j] (consecutive threads, consecutive addresses).
+        // Every eigenvalue has its own thread: T - lam I = P L U (partial pivoting, pivots
+        // floored at eps |T|), the factorisation fused with the forward substitution of the
+        // fixed start vector, and the first solve; an eigenvalue apart from both neighbours
+        // takes its remaining solves (kInvSolves in all, the vector rescaled between them) on
+        // the same thread and leaves 1 / |z| in sc.  Then the thread of the first eigenvalue of
+        // each cluster of close eigenvalues takes the cluster's members in order: each vector is
+        // orthogonalised against the cluster's earlier vectors (modified Gram-Schmidt) after
+        // every solve, normalised, and its sc set to 1.  A last pass over all elements scales the
+        // columns.  Z and the factors are row-major [i][j] (consecutive threads, consecutive
+        // addresses).
         double* u0 = Sb + 5 * B.aoff;                   // 1 / pivot
         double* u1 = u0 + (int64_t)d * d;
         double* u2 = u1 + (int64_t)d * d;
         double* lm = u2 + (int64_t)d * d;
         double* pv = lm + (int64_t)d * d;               // 1 where rows i, i+1 were swapped
+        double* sc = reinterpret_cast<double*>(vv1);    // per eigenvector: 1 / |z|
         const double tiny = 2.220446049250313e-16 * s_tn;
-        for (int j0 = tid; j0 < d; j0 += NT) {
-            if (j0 > 0 && lam[j0] - lam[j0 - 1] <= kClusterGap * s_tn) continue;   // not first
-            for (int j = j0; j < d && (j == j0 || lam[j] - lam[j - 1] <= kClusterGap * s_tn); ++j) {
-                const double x = lam[j];
-                // factorisation, row by row: (dd, du) = current row's diagonal and superdiagonal
-                double dd = dg[0] - x, du = d > 1 ? e[0] : 0.0;
-                for (int i = 0; i + 1 < d; ++i) {
+        auto first_of_cluster = [&](int j) { return j == 0 || lam[j] - lam[j - 1] > kClusterGap * s_tn; };
+        // one solve of eigenvector j from Z (times scale): P, L^-1 then U^-1; returns |z|^2
+        auto backward = [&](int j) {
+            // backward: U^-1, runs of kInvRun rows loaded first
+            double y1 = 0.0, y2 = 0.0, nrm = 0.0;
+            for (int i0 = d - 1; i0 >= 0; i0 -= kInvRun) {
+                double zv[kInvRun], a0[kInvRun], a1[kInvRun], a2[kInvRun];
+#pragma unroll
+                for (int t = 0; t < kInvRun; ++t) {
+                    const int i = max(i0 - t, 0);
                     const int64_t at = (int64_t)i * d + j;
-                    const double sub = e[i], nd = dg[i + 1] - x, nu = i + 2 < d ? e[i + 1] : 0.0;
-                    if (fabs(dd) >= fabs(sub)) {
-                        const double piv = fabs(dd) >= tiny ? dd : (dd < 0.0 ? -tiny : tiny);
-                        const double ip = recip(piv);
-                        const double m = sub * ip;
-                        u0[at] = ip;
-                        u1[at] = du;
-                        u2[at] = 0.0;
-                        lm[at] = m;
-                        pv[at] = 0.0;
-                        dd = nd - m * du;
-                        du = nu;
-                    } else {
-                        const double is = recip(sub);
-                        const double m = dd * is;
-                        u0[at] = is;
-                        u1[at] = nd;
-                        u2[at] = nu;
-                        lm[at] = m;
-                        pv[at] = 1.0;
-                        dd = du - m * nd;
-                        du = -m * nu;
-                    }
+                    zv[t] = Z[at];
+                    a0[t] = u0[at];
+                    a1[t] = u1[at];
+                    a2[t] = u2[at];
                 }
-                {
-                    const int64_t at = (int64_t)(d - 1) * d + j;
+#pragma unroll
+                for (int t = 0; t < kInvRun; ++t) {
+                    if (i0 - t < 0) break;
+                    const double y = (zv[t] - a1[t] * y1 - a2[t] * y2) * a0[t];
+                    Z[(int64_t)(i0 - t) * d + j] = y;
+                    nrm += y * y;
+                    y2 = y1;
+                    y1 = y;
+                }
+            }
+            return nrm;
+        };
+        auto solve = [&](int j, double scale) {
+            // forward: P and L^-1 (the current entry carried in a register); a run of
+            // kInvRun rows is loaded before any of it is stored (row i is stored only
+            // after row i + 1 is read, so no load depends on the stores)
+            double cur = scale * Z[j];
+            for (int i0 = 0; i0 + 1 < d; i0 += kInvRun) {
+                double zn[kInvRun], pw[kInvRun], lw[kInvRun];
+#pragma unroll
+                for (int t = 0; t < kInvRun; ++t) {
+                    const int i = min(i0 + t, d - 2);
+                    const int64_t at = (int64_t)i * d + j;
+                    zn[t] = Z[at + d];
+                    pw[t] = pv[at];
+                    lw[t] = lm[at];
+                }
+#pragma unroll
+                for (int t = 0; t < kInvRun; ++t) {
+                    if (i0 + t + 1 >= d) break;
+                    double nxt = scale * zn[t];
+                    if (pw[t] != 0.0) {
+                        const double tt = cur;
+                        cur = nxt;
+                        nxt = tt;
+                    }
+                    Z[(int64_t)(i0 + t) * d + j] = cur;
+                    cur = nxt - lw[t] * cur;
+                }
+            }
+            Z[(int64_t)(d - 1) * d + j] = cur;
+            return backward(j);
+        };
+        for (int j = tid; j < d; j += NT) {
+            const double x = lam[j];
+            // start vector cos(0.7 i + j), by the recurrence
+            // cos(a + (i + 1) b) = 2 cos(b) cos(a + i b) - cos(a + (i - 1) b) (any fixed,
+            // generic vector serves; this one costs no call per element)
+            const double c2 = 2.0 * cos(0.7);
+            double cm = cos(j - 0.7), c0 = cos((double)j);
+            auto next_start = [&]() {
+                const double v = c0, cn = c2 * c0 - cm;
+                cm = c0;
+                c0 = cn;
+                return v;
+            };
+            // factorisation, row by row ((dd, du) = the current row's diagonal and
+            // superdiagonal), with the forward substitution P, L^-1 of the start vector (the
+            // current entry carried in a register)
+            double dd = dg[0] - x, du = d > 1 ? e[0] : 0.0;
+            double cur = next_start();
+            for (int i = 0; i + 1 < d; ++i) {
+                const int64_t at = (int64_t)i * d + j;
+                const double sub = e[i], nd = dg[i + 1] - x, nu = i + 2 < d ? e[i + 1] : 0.0;
+                double nxt = next_start();
+                double m;
+                if (fabs(dd) >= fabs(sub)) {
                     const double piv = fabs(dd) >= tiny ? dd : (dd < 0.0 ? -tiny : tiny);
-                    u0[at] = 1.0 / piv;
-                    u1[at] = 0.0;
+                    const double ip = recip(piv);
+                    m = sub * ip;
+                    u0[at] = ip;
+                    u1[at] = du;
                     u2[at] = 0.0;
+                    lm[at] = m;
+                    pv[at] = 0.0;
+                    dd = nd - m * du;
+                    du = nu;
+                } else {
+                    const double is = recip(sub);
+                    m = dd * is;
+                    u0[at] = is;
+                    u1[at] = nd;
+                    u2[at] = nu;
+                    lm[at] = m;
+                    pv[at] = 1.0;
+                    dd = du - m * nd;
+                    du = -m * nu;
+                    const double tt = cur;
+                    cur = nxt;
+                    nxt = tt;
                 }
-                // start vector cos(0.7 i + j), by the recurrence
-                // cos(a + (i + 1) b) = 2 cos(b) cos(a + i b) - cos(a + (i - 1) b) (any fixed,
-                // generic vector serves; this one costs no call per element)
-                {
-                    const double c2 = 2.0 * cos(0.7);
-                    double cm = cos(j - 0.7), c0 = cos((double)j);
-                    for (int i = 0; i < d; ++i) {
-                        Z[(int64_t)i * d + j] = c0;
-                        const double cn = c2 * c0 - cm;
-                        cm = c0;
-                        c0 = cn;
-                    }
+                Z[at] = cur;
+                cur = nxt - m * cur;
+            }
+            {
+                const int64_t at = (int64_t)(d - 1) * d + j;
+                const double piv = fabs(dd) >= tiny ? dd : (dd < 0.0 ? -tiny : tiny);
+                u0[at] = 1.0 / piv;
+                u1[at] = 0.0;
+                u2[at] = 0.0;
+                Z[at] = cur;
+            }
+            // the first solve: backward substitution U^-1
+            sc[j] = 1.0 / sqrt(fmax(backward(j), 1e-300));
+            // an eigenvalue apart from both neighbours: the remaining solves now
+            if (first_of_cluster(j) && (j + 1 >= d || first_of_cluster(j + 1)))
+                for (int rep = 1; rep < kInvSolves; ++rep) sc[j] = 1.0 / sqrt(fmax(solve(j, sc[j]), 1e-300));
+            ev[B.eoff + j] = x;
+        }
+        handover_barrier();
+        // clusters: the thread of the first member takes the members in order, each
+        // orthogonalised against the cluster's earlier vectors (modified Gram-Schmidt) after
+        // every solve, as the first solve was
+        auto mgs = [&](int j0, int j) {                 // returns |z_j|^2 after the projection
+            double nrm = 0.0;
+            for (int k = j0; k < j; ++k) {
+                double dot = 0.0;
+                for (int i = 0; i < d; ++i) dot += Z[(int64_t)i * d + k] * Z[(int64_t)i * d + j];
+                nrm = 0.0;
+                for (int i = 0; i < d; ++i) {
+                    const double y = Z[(int64_t)i * d + j] - dot * Z[(int64_t)i * d + k];
+                    Z[(int64_t)i * d + j] = y;
+                    nrm += y * y;
                 }
-                double scale = 1.0;
-                for (int rep = 0; rep < kInvSolves; ++rep) {
-                    // forward: P and L^-1 (the current entry carried in a register); a run of
-                    // kInvRun rows is loaded before any of it is stored (row i is stored only
-                    // after row i + 1 is read, so no load depends on the stores)
-                    double cur = scale * Z[j];
-                    for (int i0 = 0; i0 + 1 < d; i0 += kInvRun) {
-                        double zn[kInvRun], pw[kInvRun], lw[kInvRun];
-#pragma unroll
-                        for (int t = 0; t < kInvRun; ++t) {
-                            const int i = min(i0 + t, d - 2);
-                            const int64_t at = (int64_t)i * d + j;
-                            zn[t] = Z[at + d];
-                            pw[t] = pv[at];
-                            lw[t] = lm[at];
-                        }
-#pragma unroll
-                        for (int t = 0; t < kInvRun; ++t) {
-                            if (i0 + t + 1 >= d) break;
-                            double nxt = scale * zn[t];
-                            if (pw[t] != 0.0) {
-                                const double tt = cur;
-                                cur = nxt;
-                                nxt = tt;
-                            }
-                            Z[(int64_t)(i0 + t) * d + j] = cur;
-                            cur = nxt - lw[t] * cur;
-                        }
-                    }
-                    Z[(int64_t)(d - 1) * d + j] = cur;
-                    // backward: U^-1, runs of kInvRun rows loaded first
-                    double y1 = 0.0, y2 = 0.0, nrm = 0.0;
-                    for (int i0 = d - 1; i0 >= 0; i0 -= kInvRun) {
-                        double zv[kInvRun], a0[kInvRun], a1[kInvRun], a2[kInvRun];
-#pragma unroll
-                        for (int t = 0; t < kInvRun; ++t) {
-                            const int i = max(i0 - t, 0);
-                            const int64_t at = (int64_t)i * d + j;
-                            zv[t] = Z[at];
-                            a0[t] = u0[at];
-                            a1[t] = u1[at];
-                            a2[t] = u2[at];
-                        }
-#pragma unroll
-                        for (int t = 0; t < kInvRun; ++t) {
-                            if (i0 - t < 0) break;
-                            const double y = (zv[t] - a1[t] * y1 - a2[t] * y2) * a0[t];
-                            Z[(int64_t)(i0 - t) * d + j] = y;
-                            nrm += y * y;
-                            y2 = y1;
-                            y1 = y;
-                        }
-                    }
-                    // against the cluster's earlier eigenvectors (modified Gram-Schmidt)
-                    for (int k = j0; k < j; ++k) {
-                        double dot = 0.0;
-                        for (int i = 0; i < d; ++i) dot += Z[(int64_t)i * d + k] * Z[(int64_t)i * d + j];
-                        nrm = 0.0;
-                        for (int i = 0; i < d; ++i) {
-                            const double y = Z[(int64_t)i * d + j] - dot * Z[(int64_t)i * d + k];
-                            Z[(int64_t)i * d + j] = y;
-                            nrm += y * y;
-                        }
-                    }
-                    scale = 1.0 / sqrt(fmax(nrm, 1e-300));
+            }
+            return nrm;
+        };
+        for (int j0 = tid; j0 < d; j0 += NT) {
+            if (!first_of_cluster(j0) || j0 + 1 >= d || first_of_cluster(j0 + 1)) continue;
+            for (int j = j0; j < d && (j == j0 || !first_of_cluster(j)); ++j) {
+                double s = sc[j];
+                if (j > j0) s = 1.0 / sqrt(fmax(mgs(j0, j), 1e-300));
+                for (int rep = 1; rep < kInvSolves; ++rep) {
+                    double nrm = solve(j, s);
+                    if (j > j0) nrm = mgs(j0, j);
+                    s = 1.0 / sqrt(fmax(nrm, 1e-300));
                 }
-                for (int i = 0; i < d; ++i) Z[(int64_t)i * d + j] *= scale;
-                ev[B.eoff + j] = x;
+                for (int i = 0; i < d; ++i) Z[(int64_t)i * d + j] *= s;
+                sc[j] = 1.0;
             }
         }
+        handover_barrier();
+        for (int t = tid; t < d * d; t += NT) Z[t] *= sc[t % d];
         handover_barrier();
     } else {
     zr = 1;
@@ -864,33 +936,51 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
         Z[it] = (it % d == it / d) ? 1.0 : 0.0;
     handover_barrier();
     // ---------------------------------------------------------------- 3b. implicit QL
-    // Wavefront 0 (its first lane) runs the sweep recurrence and lists the rotations of the next
+    // Wavefront 0 runs the sweep recurrence (its first lane) and lists the rotations of the next
     // sweep while the other wavefronts apply the current one (two rotation lists in LDS).
     auto rcl = [&](int buf) { return buf ? reinterpret_cast<double*>(ww) : reinterpret_cast<double*>(vv); };
     auto rsl = [&](int buf) { return rcl(buf) + MAXD; };
-    int l = 0, sweeps = 0;                              // scalar state (thread 0)
-    auto next_sweep = [&](int buf) {                    // thread 0: the next sweep into list buf
+    int l = 0, sweeps = 0;                              // scalar state (the same in every lane of wave 0)
+    // wave 0: the next sweep into list buf.  All its lanes look for the end m of the unreduced
+    // block together (a ballot over 64 entries at a time); lane 0 runs the recurrence and makes
+    // every store.  The fence orders lane 0's stores of e and dg before the other lanes' next
+    // search.
+    const int lane = tid & 63;
+    auto next_sweep = [&](int buf) {
         double* rc = rcl(buf);
         double* rs = rsl(buf);
-        s_cnt[buf] = 0;
-        s_done[buf] = 0;
+        if (lane == 0) {
+            s_cnt[buf] = 0;
+            s_done[buf] = 0;
+        }
         for (;;) {
             if (l >= d) {
-                s_done[buf] = 1;
+                if (lane == 0) s_done[buf] = 1;
                 return;
             }
-            int m = l;
-            while (m < d - 1 && fabs(e[m]) > 2.220446049250313e-16 * (fabs(dg[m]) + fabs(dg[m + 1]))) ++m;
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+            // m: the first index >= l that is the last row or has a negligible e[m]
+            int m = -1;
+            for (int base = l; m < 0; base += 64) {
+                const int i = base + lane;
+                const bool stop = i >= d - 1 ||
+                    !(fabs(e[i]) > 2.220446049250313e-16 * (fabs(dg[i]) + fabs(dg[i + 1])));
+                const unsigned long long hit = __ballot(stop);
+                if (hit) m = base + __builtin_ctzll(hit);
+            }
             if (m == l) {
                 ++l;
                 sweeps = 0;
                 continue;
             }
             if (++sweeps > kQlMaxSweeps) {
-                fail[blk] = 1;
-                s_done[buf] = 1;
+                if (lane == 0) {
+                    fail[blk] = 1;
+                    s_done[buf] = 1;
+                }
                 return;
             }
+            if (lane != 0) return;
             // shift from the leading 2 x 2 block of the unreduced part, then chase upward
             double g = (dg[l + 1] - dg[l]) / (2.0 * e[l]);
             double r = hypot(g, 1.0);
@@ -899,36 +989,49 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
             int cnt = 0;
             bool early = false;
             double ei = e[m - 1], di = dg[m - 1], di1 = dg[m];      // values of the next rotation
-            for (int i = m - 1; i >= l; --i) {
-                const double en = i > l ? e[i - 1] : 0.0, dn = i > l ? dg[i - 1] : 0.0;
-                const double f = sn * ei, b = cs * ei;
-                // r = sqrt(f^2 + g^2) and 1 / r from the hardware reciprocal square root with
-                // two Newton steps (a few ulp; the IEEE square root and division take a much
-                // longer dependent chain, and this recurrence runs on one lane)
-                const double s2 = fma(f, f, g * g);
-                if (s2 == 0.0) {
-                    e[i + 1] = 0.0;
-                    dg[i + 1] = di1 - p;
-                    e[m] = 0.0;
-                    early = true;
-                    break;
+            // rotation i reads e[i - 1] and dg[i - 1] and writes entries i + 1 and above, so
+            // the values of kQlRun rotations are loaded before any of them runs
+            for (int i0 = m - 1; i0 >= l && !early; i0 -= kQlRun) {
+                double en[kQlRun], dn[kQlRun];
+#pragma unroll
+                for (int t = 0; t < kQlRun; ++t) {
+                    const int i = i0 - t;
+                    en[t] = i > l ? e[i - 1] : 0.0;
+                    dn[t] = i > l ? dg[i - 1] : 0.0;
                 }
-                const double rinv = rsqrt_nr(s2);
-                r = s2 * rinv;
-                e[i + 1] = r;
-                sn = f * rinv;
-                cs = g * rinv;
-                g = di1 - p;
-                r = (di - g) * sn + 2.0 * cs * b;
-                p = sn * r;
-                dg[i + 1] = g + p;
-                g = cs * r - b;
-                rc[cnt] = cs;
-                rs[cnt] = sn;
-                ++cnt;
-                di1 = di;
-                ei = en;
-                di = dn;
+#pragma unroll
+                for (int t = 0; t < kQlRun; ++t) {
+                    const int i = i0 - t;
+                    if (i < l) break;
+                    const double f = sn * ei, b = cs * ei;
+                    // r = sqrt(f^2 + g^2) and 1 / r from the hardware reciprocal square root
+                    // with two Newton steps (a few ulp; the IEEE square root and division take
+                    // a much longer dependent chain, and this recurrence runs on one lane)
+                    const double s2 = fma(f, f, g * g);
+                    if (s2 == 0.0) {
+                        e[i + 1] = 0.0;
+                        dg[i + 1] = di1 - p;
+                        e[m] = 0.0;
+                        early = true;
+                        break;
+                    }
+                    const double rinv = rsqrt_nr(s2);
+                    r = s2 * rinv;
+                    e[i + 1] = r;
+                    sn = f * rinv;
+                    cs = g * rinv;
+                    g = di1 - p;
+                    r = (di - g) * sn + 2.0 * cs * b;
+                    p = sn * r;
+                    dg[i + 1] = g + p;
+                    g = cs * r - b;
+                    rc[cnt] = cs;
+                    rs[cnt] = sn;
+                    ++cnt;
+                    di1 = di;
+                    ei = en[t];
+                    di = dn[t];
+                }
             }
             if (!early) {
                 dg[l] -= p;
@@ -940,12 +1043,12 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
             return;
         }
     };
-    if (tid == 0) next_sweep(0);
+    if (tid < 64) next_sweep(0);
     __syncthreads();
     for (int it = 0;; ++it) {
         const int cur = it & 1;
         if (s_done[cur]) break;
-        if (tid == 0) {
+        if (tid < 64) {
             next_sweep(cur ^ 1);
         } else if (tid >= 64) {
             const int i0 = s_i0[cur], cnt = s_cnt[cur];
@@ -1002,98 +1105,133 @@ __global__ __launch_bounds__(kEigThreadsR) void k_heig_r(const DBlock* __restric
     heig<kEigThreadsR, kRegMaxDim, true>(blks[b], b, A, Zb, Sb, ev, fail);
 }
 
-// Back-transformation Y = H_0 H_1 ... H_{d-2} Z of one sector's eigenvectors (one work group
-// per sector and range of back_cols(d) columns of Y; Z row-major, or column-major when bit 1 of
-// flags[blk] is set), BT reflectors at a time (8, or fewer for sectors above 256 states, so
-// that a block's reflectors fit in LDS): the product H_k1 ... H_k2 of a block is I - V T V^H (V
-// the block's reflectors as columns, staged in LDS; T upper triangular from the taus on the
-// diagonal of A and the Gram matrix V^H V), applied as Y - V (T (V^H Y)): one pass over the
-// rows for V^H Y and one for the update.  The block nearest the top is padded with identity
-// factors (zero reflector, tau = 0) so that every block has BT of them.  The work group's
-// columns of Y stay in LDS from the load of Z to the final store.  kBackLanes lanes per column:
-// lane q takes the rows i = q mod kBackLanes, the group adds its partial inner products by
-// shuffles.  T is built by one wavefront, lane r holding row r in registers.  Y is stored
-// column-major (column j at j d), so that the stores and k_finish's copies are contiguous.
+// Back-transformation Y = H_0 H_1 ... H_{d-2} Z of one sector's eigenvectors, BT reflectors
+// at a time (back_bt(d): 8, or fewer above 256 states so that a block's reflectors fit in LDS),
+// the block nearest the top padded with identity factors (zero reflector, tau = 0) so that
+// every block has BT of them.  The product H_k1 ... H_k2 of a block is I - V T V^H (V the
+// block's reflectors as columns, T upper triangular from the taus on the diagonal of A and the
+// Gram matrix V^H V, T[r][c] = -tau_c sum_{r <= u < c} T[r][u] G[u][c], T[c][c] = tau_c).
+//   k_back_t     the T of every block, in parallel (one work group per sector and block), into
+//                Tb at blk.toff (block bi, from the bottom: bi BT^2 elements on, T[r][c] at
+//                r + BT c);
+//   k_heig_back  Y - V (T (V^H Y)) block after block, one work group per sector and range of
+//                back_cols(d) columns of Y, which stay in LDS from the load of Z (row-major, or
+//                column-major when bit 1 of flags[blk] is set) to the store of Y (column-major).
+//                The next block's reflectors and T are loaded into registers while the current
+//                one is applied, and written to the other half of double LDS buffers, so a block
+//                costs one barrier and no exposed global load.  kBackLanes lanes per column:
+//                lane q takes the rows i = q mod kBackLanes, and the lane group adds its partial
+//                inner products by shuffles.
 constexpr int kBackThreads = 256;
-constexpr int kBackLanes = 8;       // lanes per column of Y
+constexpr int kBackLanes = 16;      // lanes per column of Y
 constexpr int kBackCols = kBackThreads / kBackLanes;   // most columns of Y per work group
-constexpr int kBackLds = 6144;      // complex elements of the work group's columns in LDS (96 KB)
+constexpr int kBackLds = 4096;      // complex elements of the work group's columns in LDS (64 KB)
 __host__ __device__ constexpr int back_cols(int d) {
     return d * kBackCols <= kBackLds ? kBackCols : kBackLds / d;
 }
 static_assert(kBackLds / kDensMaxDim >= 1, "one column of the largest sector fits");
+static_assert(kBackVs / 2 >= kDensMaxDim, "two reflectors of the largest sector fit");
+
+// Reflector c of block bi (k = k1 + c), element i: 0 above the diagonal and for the padding,
+// 1 on the subdiagonal, v below it (kept in A below the subdiagonal).
+__device__ __forceinline__ dv2 back_v(const dv2* __restrict__ a, int d, int k, int i) {
+    if (k < 0 || i <= k) return (dv2){0.0, 0.0};
+    return i == k + 1 ? (dv2){1.0, 0.0} : a[(int64_t)k * d + i];
+}
+
+constexpr int kBackTThreads = 256;  // threads of k_back_t (8 per Gram entry, 28 entries)
+template <int BT>
+__device__ __forceinline__ void back_t(int d, int bi, const dv2* __restrict__ a,
+                                       dv2* __restrict__ tg) {
+    constexpr int NP = BT * (BT - 1) / 2, GL = 8;      // Gram pairs, lanes per pair
+    __shared__ dv2 Vl[kBackVs], Gm[BT * BT], taus[BT];
+    const int ln = threadIdx.x;
+    const int k2 = d - 2 - bi * BT, k1 = k2 - BT + 1;
+    for (int c = 0; c < BT; ++c)
+        for (int i = ln; i < d; i += kBackTThreads) Vl[c * d + i] = back_v(a, d, k1 + c, i);
+    if (ln < BT) taus[ln] = k1 + ln < 0 ? (dv2){0.0, 0.0} : a[(int64_t)(k1 + ln) * d + k1 + ln];
+    __syncthreads();
+    {
+        // Gram entry (c1, c2), c1 < c2, by GL lanes (rows i = q mod GL), added by shuffles
+        const int p = ln / GL, q = ln % GL;
+        dv2 acc = (dv2){0.0, 0.0};
+        int c1 = 0, c2 = 1;
+        if (p < NP) {
+            int base = 0;                               // pairs with c2 = m start at m (m - 1) / 2
+            while (base + c2 <= p) base += c2++;
+            c1 = p - base;
+            const int i0 = k1 + c2 + 1 > 0 ? k1 + c2 + 1 : 0;
+            for (int i = i0 + q; i < d; i += GL) acc = cmac(acc, cconj(Vl[c1 * d + i]), Vl[c2 * d + i]);
+        }
+#pragma unroll
+        for (int o = 1; o < GL; o <<= 1) {
+            acc.x += __shfl_xor(acc.x, o, 64);
+            acc.y += __shfl_xor(acc.y, o, 64);
+        }
+        if (p < NP && q == 0) Gm[c1 + BT * c2] = acc;
+    }
+    __syncthreads();
+    if (ln < BT) {
+        const int r = ln;
+        dv2 tr[BT];
+#pragma unroll
+        for (int c = 0; c < BT; ++c) {
+            dv2 sum = (dv2){0.0, 0.0};
+#pragma unroll
+            for (int u = 0; u < c; ++u)
+                if (u >= r) sum += cmul(tr[u], Gm[u + BT * c]);
+            const dv2 tau = taus[c];
+            tr[c] = r < c ? cmul((dv2){-tau.x, -tau.y}, sum) : (r == c ? tau : (dv2){0.0, 0.0});
+        }
+#pragma unroll
+        for (int c = 0; c < BT; ++c) tg[(int64_t)bi * BT * BT + r + BT * c] = tr[c];
+    }
+}
+
+__global__ __launch_bounds__(kBackTThreads) void k_back_t(const DBlock* __restrict__ blks,
+                                               const dv2* __restrict__ A, dv2* __restrict__ Tb) {
+    const DBlock B = blks[blockIdx.x];
+    const int d = B.d, bi = blockIdx.y;
+    if (bi >= back_nblocks(d)) return;
+    const dv2* __restrict__ a = A + B.aoff;
+    dv2* __restrict__ tg = Tb + B.toff;
+    if (back_bt(d) == 8)
+        back_t<8>(d, bi, a, tg);
+    else if (back_bt(d) == 4)
+        back_t<4>(d, bi, a, tg);
+    else
+        back_t<2>(d, bi, a, tg);
+}
 
 template <int BT>
 __device__ __forceinline__ void back_blocks(int d, int nc, const dv2* __restrict__ a,
-                                            dv2* __restrict__ Vs, dv2* __restrict__ Ys,
-                                            dv2* __restrict__ Tt, dv2* __restrict__ Gm,
-                                            dv2* __restrict__ taus) {
+                                            const dv2* __restrict__ tg, dv2* __restrict__ Vs,
+                                            dv2* __restrict__ Ys, dv2* __restrict__ Tt) {
     constexpr int NT = kBackThreads, L = kBackLanes;
-    constexpr int NP = BT * (BT - 1) / 2, PW = (NP + NT / 64 - 1) / (NT / 64);   // Gram pairs
-    // the caller takes BT = 8, 4, 2 for d up to 2 kDensMaxDim / BT: BT d elements fit in Vs
-    const int tid = threadIdx.x, wv = tid >> 6, ln = tid & 63;
-    const int q = tid % L, jl = tid / L;
-    for (int k2 = d - 2; k2 >= 0; k2 -= BT) {
-        const int k1 = k2 - BT + 1;                     // reflectors k1 .. k2 (k < 0: identity)
+    constexpr int PV = kBackVs / NT;                    // reflector elements a thread stages
+    const int tid = threadIdx.x, q = tid % L, jl = tid / L;
+    const int nb = back_nblocks(d);
+    dv2 pv[PV], pt = (dv2){0.0, 0.0};
+    auto fetch = [&](int bi) {                          // block bi into registers
+        const int k1 = d - 2 - bi * BT - BT + 1;
 #pragma unroll
-        for (int c = 0; c < BT; ++c) {
-            const int k = k1 + c;
-            for (int i = tid; i < d; i += NT)
-                Vs[c * d + i] = (k < 0 || i <= k) ? (dv2){0.0, 0.0}
-                                : (i == k + 1 ? (dv2){1.0, 0.0} : a[(int64_t)k * d + i]);
+        for (int u = 0; u < PV; ++u) {
+            const int t = tid + u * NT, c = t / d, i = t - c * d;
+            pv[u] = t < BT * d ? back_v(a, d, k1 + c, i) : (dv2){0.0, 0.0};
         }
-        if (tid < BT) taus[tid] = k1 + tid < 0 ? (dv2){0.0, 0.0}
-                                               : a[(int64_t)(k1 + tid) * d + k1 + tid];
-        __syncthreads();
-        {
-            // Gram entries G[c1][c2] (c1 < c2), pair p = wv + 4 s of wavefront wv: lanes over rows
-            dv2 acc[PW];
-            int pc1[PW], pc2[PW];
+        if (tid < BT * BT) pt = tg[(int64_t)bi * BT * BT + tid];
+    };
+    if (nb > 0) fetch(0);
+    for (int bi = 0; bi < nb; ++bi) {
+        dv2* __restrict__ V = Vs + (bi & 1) * kBackVs;
+        dv2* __restrict__ T = Tt + (bi & 1) * BT * BT;
 #pragma unroll
-            for (int sp = 0; sp < PW; ++sp) {
-                const int p = wv + (NT / 64) * sp;
-                int c2 = 1, base = 0;                   // pairs with c2 = m start at m (m - 1) / 2
-                while (c2 < BT && base + c2 <= p) base += c2++;
-                pc2[sp] = c2;
-                pc1[sp] = p - base;
-                acc[sp] = (dv2){0.0, 0.0};
-                if (p < NP) {
-                    const int i0 = k1 + c2 + 1 > 0 ? k1 + c2 + 1 : 0;
-                    for (int i = i0 + ln; i < d; i += 64)
-                        acc[sp] += cmul(cconj(Vs[pc1[sp] * d + i]), Vs[c2 * d + i]);
-                }
-            }
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1)
-#pragma unroll
-                for (int sp = 0; sp < PW; ++sp) {
-                    acc[sp].x += __shfl_xor(acc[sp].x, o, 64);
-                    acc[sp].y += __shfl_xor(acc[sp].y, o, 64);
-                }
-#pragma unroll
-            for (int sp = 0; sp < PW; ++sp)
-                if (ln == 0 && wv + (NT / 64) * sp < NP) Gm[pc1[sp] + BT * pc2[sp]] = acc[sp];
-        }
-        __syncthreads();
-        if (tid < 64) {
-            // T[r][c] = -tau_c sum_{r <= u < c} T[r][u] G[u][c] (r < c), T[c][c] = tau_c
-            const int r = tid;
-            dv2 tr[BT];
-#pragma unroll
-            for (int c = 0; c < BT; ++c) {
-                dv2 sum = (dv2){0.0, 0.0};
-#pragma unroll
-                for (int u = 0; u < c; ++u)
-                    if (u >= r) sum += cmul(tr[u], Gm[u + BT * c]);
-                const dv2 tau = taus[c];
-                tr[c] = r < c ? cmul((dv2){-tau.x, -tau.y}, sum) : (r == c ? tau : (dv2){0.0, 0.0});
-            }
-            if (r < BT) {
-#pragma unroll
-                for (int c = 0; c < BT; ++c) Tt[r + BT * c] = tr[c];
-            }
-        }
-        __syncthreads();
+        for (int u = 0; u < PV; ++u)
+            if (tid + u * NT < BT * d) V[tid + u * NT] = pv[u];
+        if (tid < BT * BT) T[tid] = pt;
+        __syncthreads();            // this block's buffers complete; the other buffers free
+        if (bi + 1 < nb) fetch(bi + 1);
+        const int k1 = d - 2 - bi * BT - BT + 1;
         if (jl < nc) {                                  // uniform over the lane group
             dv2* __restrict__ y = Ys + jl * d;
             const int i0 = k1 + 1 > 0 ? k1 + 1 : 0;     // rows above are not touched
@@ -1104,7 +1242,7 @@ __device__ __forceinline__ void back_blocks(int d, int nc, const dv2* __restrict
             for (int i = i1; i < d; i += L) {
                 const dv2 yv = y[i];
 #pragma unroll
-                for (int c = 0; c < BT; ++c) w[c] += cmul(cconj(Vs[c * d + i]), yv);
+                for (int c = 0; c < BT; ++c) w[c] = cmac(w[c], cconj(V[c * d + i]), yv);
             }
 #pragma unroll
             for (int o = 1; o < L; o <<= 1)
@@ -1118,21 +1256,21 @@ __device__ __forceinline__ void back_blocks(int d, int nc, const dv2* __restrict
             for (int r = 0; r < BT; ++r) {
                 u[r] = (dv2){0.0, 0.0};
 #pragma unroll
-                for (int c = r; c < BT; ++c) u[r] += cmul(Tt[r + BT * c], w[c]);
+                for (int c = r; c < BT; ++c) u[r] = cmac(u[r], T[r + BT * c], w[c]);
             }
             for (int i = i1; i < d; i += L) {
                 dv2 yv = y[i];
 #pragma unroll
-                for (int c = 0; c < BT; ++c) yv -= cmul(Vs[c * d + i], u[c]);
+                for (int c = 0; c < BT; ++c) yv = cmsc(yv, V[c * d + i], (dv2){u[c].x, -u[c].y});
                 y[i] = yv;
             }
         }
-        __syncthreads();
     }
 }
 
 __global__ __launch_bounds__(kBackThreads) void k_heig_back(const DBlock* __restrict__ blks,
                                                             const dv2* __restrict__ A,
+                                                            const dv2* __restrict__ Tb,
                                                             const double* __restrict__ Zb,
                                                             dv2* __restrict__ Yb,
                                                             const int* __restrict__ flags) {
@@ -1144,21 +1282,23 @@ __global__ __launch_bounds__(kBackThreads) void k_heig_back(const DBlock* __rest
     if (jb >= d) return;
     const int nc = jb + cols < d ? cols : d - jb;       // columns jb .. jb + nc - 1
     const dv2* __restrict__ a = A + B.aoff;
+    const dv2* __restrict__ tg = Tb + B.toff;
     const double* __restrict__ Z = Zb + B.aoff;
     dv2* __restrict__ Y = Yb + B.aoff;
     const bool colmajor = (flags[blockIdx.x] & 2) != 0;
     const int64_t zr = colmajor ? 1 : d, zc = colmajor ? d : 1;
-    __shared__ dv2 Vs[2 * kDensMaxDim];                 // the block's reflectors, Vs[c d + i]
+    __shared__ dv2 Vs[2 * kBackVs];                     // two blocks of reflectors, V[c d + i]
     __shared__ dv2 Ys[kBackLds];                        // Ys[jl d + i] = Y[i][jb + jl]
-    __shared__ dv2 Tt[8 * 8], Gm[8 * 8], taus[8];
+    __shared__ dv2 Tt[2 * 8 * 8];
     for (int jl = 0; jl < nc; ++jl)
         for (int i = tid; i < d; i += NT) Ys[jl * d + i] = (dv2){Z[i * zr + (jb + jl) * zc], 0.0};
-    if (d <= 2 * kDensMaxDim / 8)
-        back_blocks<8>(d, nc, a, Vs, Ys, Tt, Gm, taus);
-    else if (d <= 2 * kDensMaxDim / 4)
-        back_blocks<4>(d, nc, a, Vs, Ys, Tt, Gm, taus);
+    if (back_bt(d) == 8)
+        back_blocks<8>(d, nc, a, tg, Vs, Ys, Tt);
+    else if (back_bt(d) == 4)
+        back_blocks<4>(d, nc, a, tg, Vs, Ys, Tt);
     else
-        back_blocks<2>(d, nc, a, Vs, Ys, Tt, Gm, taus);
+        back_blocks<2>(d, nc, a, tg, Vs, Ys, Tt);
+    __syncthreads();
     for (int jl = 0; jl < nc; ++jl)
         for (int i = tid; i < d; i += NT) Y[(int64_t)(jb + jl) * d + i] = Ys[jl * d + i];
 }
@@ -1193,6 +1333,7 @@ __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ev, int
     if (r) atomicAdd(&rank[g], r);
 }
 
+constexpr int kFinishSplit = 8;     // work groups per sector of k_finish (the copy is shared)
 // Per sector: eigenvalues in descending order (equal values by index) with their eigenvectors
 // (two planes, column-major d x d at 2 blk.aoff in doubles: real parts, then imaginary parts),
 // the number kept and the sums of all and of the kept eigenvalues.
@@ -1207,14 +1348,17 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
     const DBlock B = blks[blockIdx.x];
     const int d = B.d, tid = threadIdx.x;
     __shared__ double scratch[kVecThreads];
+    __shared__ double se[kDensMaxDim];                  // the sector's eigenvalues
     __shared__ int src_of[kDensMaxDim];                 // output position r <- eigenvector i
-    const double* e = ev + B.eoff;
+    for (int i = tid; i < d; i += blockDim.x) se[i] = ev[B.eoff + i];
+    __syncthreads();
     double all = 0.0, ksum = 0.0, kc = 0.0;
+    const int ys = blockIdx.y, ny = gridDim.y;          // this work group's share of the copy
     for (int i = tid; i < d; i += blockDim.x) {
-        const double x = e[i];
+        const double x = se[i];
         int r = 0;
-        for (int h = 0; h < d; ++h) r += (e[h] > x) || (e[h] == x && h < i);
-        evals[B.eoff + r] = x;
+        for (int h = 0; h < d; ++h) r += (se[h] > x) || (se[h] == x && h < i);
+        if (ys == 0) evals[B.eoff + r] = x;
         src_of[r] = i;
         all += x;
         if (rank[B.eoff + i] < keep) {
@@ -1223,17 +1367,23 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
         }
     }
     __syncthreads();
-    // V column-major (column i at V + aoff + i d): each output column is a contiguous copy
-    for (int r = 0; r < d; ++r) {
-        const dv2* src = V + B.aoff + (int64_t)src_of[r] * d;
-        double* dre = evecs + 2 * B.aoff + (int64_t)r * d;
-        double* dim = dre + (int64_t)d * d;
-        for (int row = tid; row < d; row += blockDim.x) {
-            const dv2 z = src[row];
-            dre[row] = z.x;
-            dim[row] = z.y;
+    // V column-major (column i at V + aoff + i d): output column r (r = ys mod ny) is column
+    // src_of[r] of V, copied along consecutive addresses
+    {
+        const dv2* __restrict__ src = V + B.aoff;
+        double* __restrict__ dre = evecs + 2 * B.aoff;
+        double* __restrict__ dim = dre + (int64_t)d * d;
+        const int ncol = d > ys ? (d - ys + ny - 1) / ny : 0;
+        const int nel = ncol * d;
+#pragma unroll 4
+        for (int o = tid; o < nel; o += blockDim.x) {
+            const int rr = o / d, row = o - rr * d, r = ys + ny * rr;
+            const dv2 z = src[(int64_t)src_of[r] * d + row];
+            dre[(int64_t)r * d + row] = z.x;
+            dim[(int64_t)r * d + row] = z.y;
         }
     }
+    if (ys != 0) return;
     all = group_sum<kVecThreads>(all, scratch);
     ksum = group_sum<kVecThreads>(ksum, scratch);
     kc = group_sum<kVecThreads>(kc, scratch);
@@ -1246,10 +1396,11 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
 
 hipError_t launch_density(const DBlock* blks, int nblk, const int* sel, int nreg,
                           const DTile* tiles, int ntiles, const DensIn& in, int nv, int64_t n,
-                          void* A, void* V, double* Z, double* S, int* fail, int maxd, double* ev,
+                          void* A, void* V, double* Z, double* S, void* Tb, int nbt, int* fail,
+                          int maxd, double* ev,
                           int ntot, int keep, int* kept, double* evals, double* evecs, int* nkept,
                           double* sums, hipStream_t s) {
-    hipLaunchKernelGGL(k_density, dim3(ntiles), dim3(256), 0, s, blks, tiles, in, nv, n,
+    hipLaunchKernelGGL(k_density, dim3(ntiles), dim3(64), 0, s, blks, tiles, in, nv, n,
                        static_cast<dv2*>(A), fail, nblk);
     // sel: first the nreg sectors of the register-resident kernel, then the others
     if (nreg > 0)
@@ -1258,14 +1409,18 @@ hipError_t launch_density(const DBlock* blks, int nblk, const int* sel, int nreg
     if (nblk > nreg)
         hipLaunchKernelGGL(k_heig, dim3(nblk - nreg), dim3(kEigThreads), 0, s, blks, sel + nreg,
                            static_cast<dv2*>(A), Z, S, ev, fail);
+    if (nbt > 0)
+        hipLaunchKernelGGL(k_back_t, dim3(nblk, nbt), dim3(kBackTThreads), 0, s, blks,
+                           static_cast<const dv2*>(A), static_cast<dv2*>(Tb));
     // work groups per sector: ceil(d / back_cols(d)) grows with d, so maxd gives the most
     const int bcy = (maxd + back_cols(maxd) - 1) / back_cols(maxd);
     hipLaunchKernelGGL(k_heig_back, dim3(nblk, bcy), dim3(kBackThreads), 0, s, blks,
-                       static_cast<const dv2*>(A), Z, static_cast<dv2*>(V), fail);
+                       static_cast<const dv2*>(A), static_cast<const dv2*>(Tb), Z,
+                       static_cast<dv2*>(V), fail);
     hipLaunchKernelGGL(k_zero_int, dim3((ntot + 255) / 256), dim3(256), 0, s, kept, ntot);
     hipLaunchKernelGGL(k_rank, dim3((ntot + 255) / 256, (ntot + kRankChunk - 1) / kRankChunk), dim3(256), 0,
                        s, ev, ntot, kept);
-    hipLaunchKernelGGL(k_finish, dim3(nblk), dim3(256), 0, s, blks, ev, kept, keep,
+    hipLaunchKernelGGL(k_finish, dim3(nblk, kFinishSplit), dim3(256), 0, s, blks, ev, kept, keep,
                        static_cast<const dv2*>(V), evals, evecs, nkept, sums);
     return hipGetLastError();
 }

@@ -256,7 +256,17 @@ struct DBlock {
     int64_t off;          // psi block offset in a vector (complex elements)
     int64_t aoff;         // its d x d complex matrices in the workspace (complex elements)
     int64_t eoff;         // its eigenvalues (sum of d over earlier sectors)
+    int64_t toff;         // its back-transformation blocks T (complex elements)
 };
+// Back-transformation of a sector of d states: blocks of back_bt(d) reflectors (a block's
+// reflectors fit in kBackVs complex elements), back_nblocks(d) of them.
+constexpr int kBackVs = 2048;
+__host__ __device__ constexpr int back_bt(int d) {
+    return d <= kBackVs / 8 ? 8 : (d <= kBackVs / 4 ? 4 : 2);
+}
+__host__ __device__ constexpr int back_nblocks(int d) {
+    return d >= 2 ? (d - 1 + back_bt(d) - 1) / back_bt(d) : 0;
+}
 struct DTile {            // 16 x 16 tile of one sector's density matrix
     int32_t blk, i0, j0, pad;
 };
