@@ -46,6 +46,13 @@ __device__ __forceinline__ double recip(double x) {
     return fma(fma(-x, r0, 1.0), r0, r0);
 }
 
+// 1 / x with two Newton steps (to about an ulp; the reflector's scalars)
+__device__ __forceinline__ double recip2(double x) {
+    const double r0 = __builtin_amdgcn_rcp(x);
+    const double r1 = fma(fma(-x, r0, 1.0), r0, r0);
+    return fma(fma(-x, r1, 1.0), r1, r1);
+}
+
 // 1 / sqrt(x), x > 0: the hardware reciprocal square root and two Newton steps
 __device__ __forceinline__ double rsqrt_nr(double x) {
     double y = __builtin_amdgcn_rsq(x);
@@ -355,10 +362,11 @@ __device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double
             double beta = al.x;
             if (!(xn2 == 0.0 && al.y == 0.0)) {
                 beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
-                tau = (dv2){(beta - al.x) / beta, -al.y / beta};
+                const double rb = recip2(beta);
+                tau = (dv2){(beta - al.x) * rb, -al.y * rb};
                 const dv2 den = (dv2){al.x - beta, al.y};               // 1 / (alpha - beta)
-                const double q = den.x * den.x + den.y * den.y;
-                sc = (dv2){den.x / q, -den.y / q};
+                const double rq = recip2(den.x * den.x + den.y * den.y);
+                sc = (dv2){den.x * rq, -den.y * rq};
             }
             if (tid == 0) {
                 e[k] = beta;
@@ -693,10 +701,13 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
                 }
                 // 1 / q: the hardware reciprocal and one Newton step (a few ulp; the counts then
                 // place each eigenvalue within a few eps |T|)
-                auto sturm = [&](double di, double ei) {
+                // a pivot q with |q| < 1e-300 is taken as -1e-300 (guarded); the unguarded step
+                // meets such a pivot as a NaN (1 / 0 or an overflow), after which its count is
+                // discarded and the run taken again with the guard
+                auto sturm = [&](double di, double ei, bool guard) {
 #pragma unroll
                     for (int u = 0; u < P; ++u) {
-                        if (fabs(q[u]) < 1e-300) q[u] = -1e-300;
+                        if (guard && fabs(q[u]) < 1e-300) q[u] = -1e-300;
                         const double r0 = __builtin_amdgcn_rcp(q[u]);
                         const double r = fma(fma(-q[u], r0, 1.0), r0, r0);
                         q[u] = (di - x[u]) - ei * r;
@@ -711,10 +722,29 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
                         dr[t] = dg[i + t];
                         er[t] = e2[i - 1 + t];
                     }
+                    double q0[P];
+                    int c0[P];
 #pragma unroll
-                    for (int t = 0; t < kSturmRun; ++t) sturm(dr[t], er[t]);
+                    for (int u = 0; u < P; ++u) {
+                        q0[u] = q[u];
+                        c0[u] = cnt[u];
+                    }
+#pragma unroll
+                    for (int t = 0; t < kSturmRun; ++t) sturm(dr[t], er[t], false);
+                    bool bad = false;
+#pragma unroll
+                    for (int u = 0; u < P; ++u) bad |= __builtin_isnan(q[u]);
+                    if (bad) {
+#pragma unroll
+                        for (int u = 0; u < P; ++u) {
+                            q[u] = q0[u];
+                            cnt[u] = c0[u];
+                        }
+#pragma unroll
+                        for (int t = 0; t < kSturmRun; ++t) sturm(dr[t], er[t], true);
+                    }
                 }
-                for (; i < d; ++i) sturm(dg[i], e2[i - 1]);
+                for (; i < d; ++i) sturm(dg[i], e2[i - 1], true);
                 double nlo = lo, nhi = hi;
                 bool found = false;
                 for (int l = 0; l < GB; ++l) {
