@@ -66,6 +66,13 @@ def problem(name):
         elif name == "ladder2x8_m700_big":   # concentrated sectors: one of 624 states, four of 330
             _PROBLEMS[name] = I.synthetic_problem(16, 700, 8.0, I.ladder_bonds(8), 90, name=name,
                                                   width=0.7)
+        elif name == "ladder2x8_m340_edge":  # sectors of 160 and 161 states (the two eigensolver
+            # kernels' boundary) and up to 304 (back-transformation blocks of four)
+            _PROBLEMS[name] = I.synthetic_problem(16, 340, 8.0, I.ladder_bonds(8), 90, name=name,
+                                                  width=0.7)
+        elif name == "ladder2x8_m620_257":   # a sector of 257 states: the first with blocks of four
+            _PROBLEMS[name] = I.synthetic_problem(16, 620, 8.0, I.ladder_bonds(8), 90, name=name,
+                                                  width=1.2)
         elif name == "ladder2x4_U10":
             _PROBLEMS[name] = I.exact_problem(8, 10.0, (4, 4), bonds=I.ladder_bonds(4, 1.0, 0.5))
         elif name == "chain4_exact":
@@ -492,7 +499,8 @@ def _decaying(pb, x, decades):
 @pytest.mark.parametrize("name,decades", [("chain12_m30", 0), ("chain8_exact", 0), ("chain8_m17_odd", 0),
                                           ("ladder16_m1000", 0), ("chain12_m30", 12),
                                           ("ladder16_m1000", 14), ("ladder32_m2000", 0),
-                                          ("ladder2x8_m700_big", 0)])
+                                          ("ladder2x8_m700_big", 0), ("ladder2x8_m340_edge", 0),
+                                          ("ladder2x8_m340_edge", 12), ("ladder2x8_m620_257", 0)])
 def test_density_truncate_parity(env, name, decades):
     """Density matrix of five weighted targets and its truncation against the oracle: every
     eigenvalue, the kept count of every sector and the truncation error; eigen-pairs (residual
@@ -500,7 +508,9 @@ def test_density_truncate_parity(env, name, decades):
     projector), which is unique where the kept and discarded eigenvalues are apart.  Decaying
     spectra (clusters of small eigenvalues) take the kernel's other tridiagonal solver.  The
     sectors of ladder32_m2000 (up to 300 states) and ladder2x8_m700_big (330 and 624) take the
-    back-transformation's blocks of four and two reflectors."""
+    back-transformation's blocks of four and two reflectors; ladder2x8_m340_edge has sectors of
+    160 and 161 states, the last of the register-resident eigensolver and the first of the
+    general one, and ladder2x8_m620_257 one of 257 states, the first with blocks of four."""
     from oracle import density as Dn
     torch, L = env
     say("density", name, "decades", decades)
