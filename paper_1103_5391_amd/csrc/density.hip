@@ -214,6 +214,7 @@ constexpr int kSturmPts = 1;        // Sturm sequences one lane evaluates togeth
 constexpr int kSturmRun = 8;        // Sturm steps whose LDS reads are issued together
 constexpr int kInvRun = 8;          // rows an inverse-iteration solve loads before storing
 constexpr int kInvSolves = 2;       // inverse-iteration solves per eigenvector
+constexpr int kWaveCluster = 4;     // clusters of at least this many members go to a wavefront
 constexpr int kHhLdsDim = 66;       // largest trailing matrix the Householder phase keeps in LDS
 constexpr int kQlRun = 8;           // QL rotations whose LDS reads are issued together
 constexpr int kEigChunk = 16;       // loads a thread issues together in the QL rotation pass
@@ -508,7 +509,7 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
     __shared__ dv2 vv[MAXD], ww[MAXD], vv1[MAXD], ww1[MAXD];
     __shared__ dv2 pp[NT];
     __shared__ double red[3 * NT / 64];
-    __shared__ int s_i0[2], s_cnt[2], s_done[2], s_path;
+    __shared__ int s_i0[2], s_cnt[2], s_done[2], s_path, s_nlarge;
     __shared__ double s_lo, s_hi, s_tn;
     // ---------------------------------------------------------------- 1. tridiagonal
     if constexpr (REG) {
@@ -786,10 +787,11 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
         // floored at eps |T|), the factorisation fused with the forward substitution of the
         // fixed start vector, and the first solve; an eigenvalue apart from both neighbours
         // takes its remaining solves (kInvSolves in all, the vector rescaled between them) on
-        // the same thread and leaves 1 / |z| in sc.  Then the thread of the first eigenvalue of
-        // each cluster of close eigenvalues takes the cluster's members in order: each vector is
-        // orthogonalised against the cluster's earlier vectors (modified Gram-Schmidt) after
-        // every solve, normalised, and its sc set to 1.  A last pass over all elements scales the
+        // the same thread and leaves 1 / |z| in sc.  Then each cluster of close eigenvalues
+        // takes its members in order (the thread of its first eigenvalue, or a wavefront for a
+        // cluster of kWaveCluster or more): each vector is orthogonalised against the cluster's
+        // earlier vectors (modified Gram-Schmidt) after every solve, normalised, and its sc set
+        // to 1.  A last pass over all elements scales the
         // columns.  Z and the factors are row-major [i][j] (consecutive threads, consecutive
         // addresses).
         double* u0 = Sb + 5 * B.aoff;                   // 1 / pivot
@@ -800,6 +802,15 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
         double* sc = reinterpret_cast<double*>(vv1);    // per eigenvector: 1 / |z|
         const double tiny = 2.220446049250313e-16 * s_tn;
         auto first_of_cluster = [&](int j) { return j == 0 || lam[j] - lam[j - 1] > kClusterGap * s_tn; };
+        // a cluster of at least kWaveCluster members: its fourth member is close too
+        static_assert(kWaveCluster == 4, "large() tests three following members");
+        auto large = [&](int j0) {
+            return j0 + kWaveCluster - 1 < d && !first_of_cluster(j0 + 1) &&
+                   !first_of_cluster(j0 + 2) && !first_of_cluster(j0 + 3);
+        };
+        int* const largel = reinterpret_cast<int*>(pp);   // first members of large clusters
+        if (tid == 0) s_nlarge = 0;
+        __syncthreads();
         // one solve of eigenvector j from Z (times scale): P, L^-1 then U^-1; returns |z|^2
         auto backward = [&](int j) {
             // backward: U^-1, runs of kInvRun rows loaded first
@@ -919,6 +930,7 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
             }
             // the first solve: backward substitution U^-1
             sc[j] = 1.0 / sqrt(fmax(backward(j), 1e-300));
+            if (first_of_cluster(j) && large(j)) largel[atomicAdd(&s_nlarge, 1)] = j;
             // an eigenvalue apart from both neighbours: the remaining solves now
             if (first_of_cluster(j) && (j + 1 >= d || first_of_cluster(j + 1)))
                 for (int rep = 1; rep < kInvSolves; ++rep) sc[j] = 1.0 / sqrt(fmax(solve(j, sc[j]), 1e-300));
@@ -944,6 +956,7 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
         };
         for (int j0 = tid; j0 < d; j0 += NT) {
             if (!first_of_cluster(j0) || j0 + 1 >= d || first_of_cluster(j0 + 1)) continue;
+            if (large(j0)) continue;
             for (int j = j0; j < d && (j == j0 || !first_of_cluster(j)); ++j) {
                 double s = sc[j];
                 if (j > j0) s = 1.0 / sqrt(fmax(mgs(j0, j), 1e-300));
@@ -954,6 +967,50 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
                 }
                 for (int i = 0; i < d; ++i) Z[(int64_t)i * d + j] *= s;
                 sc[j] = 1.0;
+            }
+        }
+        // large clusters (the Gram-Schmidt steps grow as the square of the size, listed in
+        // phase 1): one wavefront each, dealt from the last wavefront down.  Lane 0 runs the solves; the lanes share the
+        // Gram-Schmidt steps (rows i = lane mod 64, sums by wave_sum, the same in every lane);
+        // the fences order the lanes' global stores of Z before the other lanes' loads.
+        {
+            const int wv = tid >> 6, lane = tid & 63;
+            auto mgsw = [&](int j0, int j) {            // |z_j|^2 after the projection
+                double nrm = 0.0;
+                for (int k = j0; k < j; ++k) {
+                    double part = 0.0;
+                    for (int i = lane; i < d; i += 64)
+                        part += Z[(int64_t)i * d + k] * Z[(int64_t)i * d + j];
+                    const double dot = wave_sum(part);
+                    double pn = 0.0;
+                    for (int i = lane; i < d; i += 64) {
+                        const double y = Z[(int64_t)i * d + j] - dot * Z[(int64_t)i * d + k];
+                        Z[(int64_t)i * d + j] = y;
+                        pn += y * y;
+                    }
+                    nrm = wave_sum(pn);
+                }
+                return nrm;
+            };
+            // the list's order depends on the atomics, but every cluster takes the same
+            // arithmetic on whichever wavefront runs it
+            for (int q = NT / 64 - 1 - wv; q < s_nlarge; q += NT / 64) {
+                const int j0 = largel[q];
+                for (int j = j0; j < d && (j == j0 || !first_of_cluster(j)); ++j) {
+                    double s = sc[j];
+                    if (j > j0) s = 1.0 / sqrt(fmax(mgsw(j0, j), 1e-300));
+                    for (int rep = 1; rep < kInvSolves; ++rep) {
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                        double nrm = 0.0;
+                        if (lane == 0) nrm = solve(j, s);
+                        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+                        nrm = __shfl(nrm, 0, 64);
+                        if (j > j0) nrm = mgsw(j0, j);
+                        s = 1.0 / sqrt(fmax(nrm, 1e-300));
+                    }
+                    for (int i = lane; i < d; i += 64) Z[(int64_t)i * d + j] *= s;
+                    if (lane == 0) sc[j] = 1.0;
+                }
             }
         }
         handover_barrier();
