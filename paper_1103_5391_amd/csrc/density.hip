@@ -15,17 +15,18 @@
 //               iteration (no cluster of close eigenvalues larger than 8) or else by implicit QL
 //               with shifts (one lane lists the rotations of the next sweep while the other
 //               wavefronts apply the current one to their rows)
-//   k_heig_back back-transformation by the reflectors in compact WY blocks, several work
-//               groups per sector
+//   k_back_t    the compact-WY factor T of every block of reflectors, all in parallel
+//   k_heig_back back-transformation by the reflectors in those blocks, several work groups per
+//               sector
 //   k_rank      global rank of every eigenvalue (larger first; equal values by sector, then by
 //               index) in pieces over a two-dimensional grid; kept if the rank is below m
 //   k_finish    per sector: eigenvalues in descending order with their eigenvectors, the number
 //               kept, and the sums of all and of the kept eigenvalues (fixed-order reductions)
 // The matrices live in global memory (L2-resident for the sector sizes of these workloads),
-// except the trailing matrix of the Householder phase once it fits in LDS and the columns a
-// back-transformation work group owns; the waves of a work group hand global data to each other
-// through it, each wave waiting for its own stores to complete before the barrier that hands
-// them over.
+// except the matrix of the register-resident Householder reduction, the trailing matrix of the
+// general one once it fits in LDS, and the columns a back-transformation work group owns; the
+// waves of a work group hand global data to each other through it, each wave waiting for its
+// own stores to complete before the barrier that hands them over.
 #include <cstdint>
 
 #include "internal.hpp"
