@@ -64,6 +64,7 @@ enum dmrg_status {
     DMRG_EHIP = -3,       /* a HIP runtime call failed                                    */
     DMRG_ENONFINITE = -4, /* non-finite value met where finite input is required          */
     DMRG_ESTATE = -5,     /* call not valid in the handle's current state                 */
+    DMRG_EIO = -6,        /* the tuning cache file cannot be read, parsed or written      */
     DMRG_WNOTCONV = 1     /* iteration stopped before its tolerance; the last iterate is
                              returned (dmrg_ground_state)                                  */
 };
@@ -251,6 +252,42 @@ int dmrg_get_gemm(dmrg_handle h, int32_t* variant);
  * not timed).
  * Waits for the handle's stream. */
 int dmrg_autotune(dmrg_handle h, int32_t reps, double* out);
+
+/* Persisted autotuner (host-side cache; the tuner itself is dmrg_autotune).  The choice of the
+ * autotuner depends on the architecture, the arithmetic and the sizes of the block products,
+ * so a JSON file at path (UTF-8, created when missing) remembers it per key, the key being the
+ * architecture name of the current device (gcnArchName up to its first ':'), the handle's
+ * arithmetic, the problem count, the connection-term count and the histogram of the
+ * superblock blocks' system and environment sector dimensions in buckets of 16 (see
+ * dmrg_tune_key).  On a hit whose variant the handle can run, the variant is applied with no
+ * device work; otherwise dmrg_autotune(h, reps, ...) runs and its choice and timings are stored
+ * under the key (an entry of the same key is replaced).  out: NULL or 10 doubles receiving the
+ * timings as in dmrg_autotune (those stored with the entry on a hit); hit: NULL or receives 1
+ * on a hit, else 0.  The file is replaced by renaming a complete temporary file
+ * (path.tmp.<pid>), so concurrent readers see the old or the new file; concurrent writers may
+ * drop each other's new entries, which are timed again on their next miss.  Returns DMRG_EIO
+ * (with the reason in dmrg_last_error) when the file exists but cannot be read or is not a
+ * cache of this format (it is then left untouched), or when it cannot be written (the tuned
+ * variant is applied all the same); DMRG_EINVAL for a NULL path or reps < 1. */
+int dmrg_autotune_cached(dmrg_handle h, const char* path, int32_t reps, double* out,
+                         int32_t* hit);
+
+/* Key of a problem in the tuning cache (host only: no device is needed or used): arch is the
+ * architecture name to key on (e.g. "gfx950"), precision a dmrg_precision.  Writes the key and a
+ * terminating NUL to buf when cap exceeds its length; *len (not NULL) receives the length
+ * without the NUL.  buf may be NULL to query the length.  DMRG_EINVAL for an invalid problem
+ * (reason in dmrg_last_error(NULL)) or when buf is too short (nothing written). */
+int dmrg_tune_key(const dmrg_problem* problem, int32_t precision, const char* arch, char* buf,
+                  int64_t cap, int64_t* len);
+
+/* Direct access to a tuning cache file (host only).  lookup: *found (not NULL) receives 1 and
+ * *variant (not NULL) the stored bits when key is present (ms: NULL or 10 doubles receiving the
+ * stored timings), else *found = 0.  store: adds or replaces the entry of key (ms: NULL, stored
+ * as -1, or 10 doubles).  DMRG_EIO as for dmrg_autotune_cached, with the reason in
+ * dmrg_last_error(NULL); DMRG_EINVAL for NULL arguments or unknown variant bits. */
+int dmrg_tune_cache_lookup(const char* path, const char* key, int32_t* variant, double* ms,
+                           int32_t* found);
+int dmrg_tune_cache_store(const char* path, const char* key, int32_t variant, const double* ms);
 
 /* Changes the stream all later work of the handle is ordered on. */
 int dmrg_set_stream(dmrg_handle h, void* stream);
@@ -450,6 +487,10 @@ int dmrg_batch_set_graph(dmrg_batch b, int32_t enable);
  * their autotuner (as dmrg_autotune, on the merged work lists of all handles). */
 int dmrg_batch_set_gemm(dmrg_batch b, int32_t variant);
 int dmrg_batch_autotune(dmrg_batch b, int32_t reps, double* out);
+/* As dmrg_autotune_cached, for the batch's merged launches: the key counts the problems, terms
+ * and blocks of all member handles in the arithmetic of the batch's tables. */
+int dmrg_batch_autotune_cached(dmrg_batch b, const char* path, int32_t reps, double* out,
+                               int32_t* hit);
 
 /* phi[i], targets[i]: device pointers for superblock i (host arrays of count pointers; the
  * targets of superblock i are 4 x 2 n_i doubles).  Results equal those of dmrg_tst_targets on

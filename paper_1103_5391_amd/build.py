@@ -25,7 +25,7 @@ ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdmrgtst.so")
 LIB_SAN = os.path.join(HERE, "_build", "libdmrgtst_san.so")
 OBJDIR = os.path.join(HERE, "_build")
-HOST_SOURCES = ["csrc/api.cpp", "csrc/plan.cpp"]
+HOST_SOURCES = ["csrc/api.cpp", "csrc/plan.cpp", "csrc/tune_cache.cpp"]
 DEVICE_SOURCES = ["csrc/gemm.hip", "csrc/gemm_lds.hip", "csrc/gemm_x.hip", "csrc/krylov.hip",
                   "csrc/density.hip", "csrc/wft.hip", "csrc/noalloc.hip", "csrc/gemm_k.hip"]
 SOURCES = HOST_SOURCES + DEVICE_SOURCES

@@ -17,6 +17,7 @@
 #include "../../include/dmrgtst.h"
 #include "internal.hpp"
 #include "plan.hpp"
+#include "tune_cache.hpp"
 
 namespace dmrg {
 
@@ -1249,6 +1250,58 @@ int check_krylov_args(dmrg_handle h, double tau, int kdim) {
 
 }  // namespace
 
+namespace {
+
+// Whether the lists hold the work of every kernel family the variant names in arithmetic prec
+// (a cache entry from another problem of the same key may name a family this one lacks).
+bool runnable_variant(const Lists& W, int prec, int32_t v) {
+    if (!valid_variant(v)) return false;
+    if (v == DMRG_GEMM_X) return prec == DMRG_FP64 && W.nx2 > 0;
+    if (v == DMRG_GEMM_K) return prec == DMRG_FP64 && W.nkt2 > 0;
+    return true;
+}
+
+// Architecture name of the current device (gcnArchName up to its first ':').
+hipError_t device_arch(std::string& arch) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, dev);
+    if (e != hipSuccess) return e;
+    arch.assign(prop.gcnArchName, strnlen(prop.gcnArchName, sizeof prop.gcnArchName));
+    const size_t colon = arch.find(':');
+    if (colon != std::string::npos) arch.resize(colon);
+    return hipSuccess;
+}
+
+// Shared body of the cached autotuners: look key up, apply a runnable hit, else tune (tune()
+// returns a status and fills the timings) and store.
+template <class Tune>
+int autotune_cached(dmrg_ctx* h, Lists& W, int prec, const std::string& key, const char* path,
+                    double* out, int32_t* hit, Tune tune) {
+    TuneEntry e;
+    bool found = false;
+    std::string err = tune_cache_find(path, key, e, found);
+    if (!err.empty()) return fail(h, DMRG_EIO, err);
+    if (found && runnable_variant(W, prec, e.variant)) {
+        W.variant = e.variant;
+        if (out) std::copy(e.ms, e.ms + kTuneTimes, out);
+        if (hit) *hit = 1;
+        return DMRG_OK;
+    }
+    const int rc = tune(e.ms);
+    if (rc) return rc;
+    e.key = key;
+    e.variant = W.variant;
+    if (out) std::copy(e.ms, e.ms + kTuneTimes, out);
+    if (hit) *hit = 0;
+    err = tune_cache_put(path, e);
+    return err.empty() ? DMRG_OK : fail(h, DMRG_EIO, err);
+}
+
+}  // namespace
+
 extern "C" {
 
 int dmrg_create(const dmrg_problem* problem, void* stream, dmrg_handle* out) {
@@ -2038,6 +2091,120 @@ int dmrg_batch_autotune(dmrg_batch b, int32_t reps, double* out) {
     return DMRG_OK;
 }
 
+int dmrg_autotune_cached(dmrg_handle h, const char* path, int32_t reps, double* out,
+                         int32_t* hit) {
+    if (!h || !path || reps < 1) return DMRG_EINVAL;
+    try {
+        std::string arch;
+        HIP_TRY(h, device_arch(arch));
+        const std::string key = tune_key({&h->plan}, h->precision, arch);
+        return autotune_cached(h, h->lists, h->precision, key, path, out, hit,
+                               [&](double* t) { return dmrg_autotune(h, reps, t); });
+    } catch (const std::bad_alloc&) {
+        return fail(h, DMRG_ENOMEM, "host allocation failed");
+    }
+}
+
+int dmrg_batch_autotune_cached(dmrg_batch b, const char* path, int32_t reps, double* out,
+                               int32_t* hit) {
+    if (!b || !path || reps < 1) return DMRG_EINVAL;
+    dmrg_ctx* h0 = b->g.hs[0];
+    try {
+        const int prec = h0->precision;
+        std::vector<const Plan*> plans;
+        for (dmrg_ctx* h : b->g.hs) {
+            if (h->precision != prec)
+                return fail(h0, DMRG_EINVAL, "batch members use different precisions");
+            plans.push_back(&h->plan);
+        }
+        std::string arch;
+        HIP_TRY(h0, device_arch(arch));
+        const std::string key = tune_key(plans, prec, arch);
+        return autotune_cached(h0, b->lists, prec, key, path, out, hit,
+                               [&](double* t) { return dmrg_batch_autotune(b, reps, t); });
+    } catch (const std::bad_alloc&) {
+        return fail(h0, DMRG_ENOMEM, "host allocation failed");
+    }
+}
+
+int dmrg_tune_key(const dmrg_problem* problem, int32_t precision, const char* arch, char* buf,
+                  int64_t cap, int64_t* len) {
+    if (!problem || !arch || !len || (buf && cap < 0)) return DMRG_EINVAL;
+    if (precision < DMRG_FP64 || precision > DMRG_BF16X6) {
+        g_create_error = "unknown precision";
+        return DMRG_EINVAL;
+    }
+    try {
+        g_create_error.clear();
+        Plan P;
+        const std::string err = build_plan(problem, P);
+        if (!err.empty()) {
+            g_create_error = err;
+            return DMRG_EINVAL;
+        }
+        const std::string key = tune_key({&P}, precision, arch);
+        *len = (int64_t)key.size();
+        if (!buf) return DMRG_OK;
+        if (cap <= (int64_t)key.size()) {
+            g_create_error = "key buffer too short";
+            return DMRG_EINVAL;
+        }
+        std::memcpy(buf, key.c_str(), key.size() + 1);
+        return DMRG_OK;
+    } catch (const std::bad_alloc&) {
+        g_create_error = "host allocation failed";
+        return DMRG_ENOMEM;
+    }
+}
+
+int dmrg_tune_cache_lookup(const char* path, const char* key, int32_t* variant, double* ms,
+                           int32_t* found) {
+    if (!path || !key || !variant || !found) return DMRG_EINVAL;
+    try {
+        g_create_error.clear();
+        TuneEntry e;
+        bool f = false;
+        const std::string err = tune_cache_find(path, key, e, f);
+        if (!err.empty()) {
+            g_create_error = err;
+            return DMRG_EIO;
+        }
+        *found = f ? 1 : 0;
+        if (f) {
+            *variant = e.variant;
+            if (ms) std::copy(e.ms, e.ms + kTuneTimes, ms);
+        }
+        return DMRG_OK;
+    } catch (const std::bad_alloc&) {
+        g_create_error = "host allocation failed";
+        return DMRG_ENOMEM;
+    }
+}
+
+int dmrg_tune_cache_store(const char* path, const char* key, int32_t variant, const double* ms) {
+    if (!path || !key) return DMRG_EINVAL;
+    if (!valid_variant(variant)) {
+        g_create_error = "unknown kernel variant bits";
+        return DMRG_EINVAL;
+    }
+    try {
+        g_create_error.clear();
+        TuneEntry e;
+        e.key = key;
+        e.variant = variant;
+        for (int i = 0; i < kTuneTimes; ++i) e.ms[i] = ms ? ms[i] : -1.0;
+        const std::string err = tune_cache_put(path, e);
+        if (!err.empty()) {
+            g_create_error = err;
+            return DMRG_EIO;
+        }
+        return DMRG_OK;
+    } catch (const std::bad_alloc&) {
+        g_create_error = "host allocation failed";
+        return DMRG_ENOMEM;
+    }
+}
+
 const char* dmrg_strerror(int status) {
     switch (status) {
         case DMRG_OK: return "success";
@@ -2047,6 +2214,7 @@ const char* dmrg_strerror(int status) {
         case DMRG_EHIP: return "HIP runtime error";
         case DMRG_ENONFINITE: return "non-finite value";
         case DMRG_ESTATE: return "invalid state";
+        case DMRG_EIO: return "tuning cache file error";
         default: return "unknown status";
     }
 }

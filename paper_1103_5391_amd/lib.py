@@ -22,15 +22,18 @@ DMRG_GEMM_STAGE1_NARROW, DMRG_GEMM_STAGE2_NARROW = 4, 8
 DMRG_GEMM_X = 16
 DMRG_GEMM_K = 32
 STATUS = {0: "DMRG_OK", -1: "DMRG_EINVAL", -2: "DMRG_ENOMEM", -3: "DMRG_EHIP",
-          -4: "DMRG_ENONFINITE", -5: "DMRG_ESTATE", 1: "DMRG_WNOTCONV"}
+          -4: "DMRG_ENONFINITE", -5: "DMRG_ESTATE", -6: "DMRG_EIO", 1: "DMRG_WNOTCONV"}
 DMRG_WNOTCONV = 1
+STATUS_CODE = {v: k for k, v in STATUS.items()}
 
 # exported symbols (kept in sync with include/dmrgtst.h; checked by the CPU tests)
 SYMBOLS = [
     "dmrg_create", "dmrg_destroy", "dmrg_psi_layout", "dmrg_flops", "dmrg_flops_executed",
     "dmrg_set_precision", "dmrg_set_check_finite", "dmrg_plan_stats",
     "dmrg_set_stream", "dmrg_matvec", "dmrg_matvec_noalloc", "dmrg_krylov_expm", "dmrg_tst_targets", "dmrg_set_graph",
-    "dmrg_set_gemm", "dmrg_get_gemm", "dmrg_autotune",
+    "dmrg_set_gemm", "dmrg_get_gemm", "dmrg_autotune", "dmrg_autotune_cached",
+    "dmrg_batch_autotune_cached", "dmrg_tune_key", "dmrg_tune_cache_lookup",
+    "dmrg_tune_cache_store",
     "dmrg_batch_create", "dmrg_batch_destroy", "dmrg_batch_set_graph", "dmrg_batch_tst_targets",
     "dmrg_batch_set_gemm", "dmrg_batch_autotune", "dmrg_profile_matvec",
     "dmrg_tst_chains", "dmrg_batch_tst_chains", "dmrg_ground_state", "dmrg_density_truncate",
@@ -136,6 +139,11 @@ def load(path: str = LIB_PATH):
     lib.dmrg_autotune.argtypes = [vp, i32, P(dbl)]
     lib.dmrg_batch_set_gemm.argtypes = [vp, i32]
     lib.dmrg_batch_autotune.argtypes = [vp, i32, P(dbl)]
+    lib.dmrg_autotune_cached.argtypes = [vp, C.c_char_p, i32, P(dbl), P(i32)]
+    lib.dmrg_batch_autotune_cached.argtypes = [vp, C.c_char_p, i32, P(dbl), P(i32)]
+    lib.dmrg_tune_key.argtypes = [P(dmrg_problem), i32, C.c_char_p, C.c_char_p, i64, P(i64)]
+    lib.dmrg_tune_cache_lookup.argtypes = [C.c_char_p, C.c_char_p, P(i32), P(dbl), P(i32)]
+    lib.dmrg_tune_cache_store.argtypes = [C.c_char_p, C.c_char_p, i32, P(dbl)]
     lib.dmrg_batch_create.argtypes = [P(vp), i32, P(vp)]
     lib.dmrg_batch_set_graph.argtypes = [vp, i32]
     lib.dmrg_batch_destroy.argtypes = [vp]
@@ -275,6 +283,62 @@ def plan_stats(pb, kdim: int = 15, extra_terms=()) -> dict:
     if rc != 0:
         raise DmrgError(rc, lib.dmrg_last_error(None).decode())
     return {f: getattr(st, f) for f, _ in st._fields_}
+
+
+_TUNE_FIELDS = ("stage1_register", "stage1_lds", "stage2_register", "stage2_lds",
+                "stage1_narrow", "stage2_narrow", "stage1_x", "stage2_x", "stage1_k", "stage2_k")
+
+
+def _tune_dict(out, variant, hit=None):
+    d = {f: float(v) for f, v in zip(_TUNE_FIELDS, out)}
+    d["variant"] = int(variant)
+    if hit is not None:
+        d["cached"] = bool(hit)
+    return d
+
+
+def _path_bytes(path) -> bytes:
+    return os.fsencode(os.fspath(path))
+
+
+def tune_key(pb, precision: int = DMRG_FP64, arch: str = "gfx950", extra_terms=()) -> str:
+    """Host-only key of a problem in the autotuner's cache (no GPU needed)."""
+    lib = load()
+    cpb, keep = problem_to_c(pb, extra_terms)
+    n = C.c_int64()
+    a = arch.encode()
+    rc = lib.dmrg_tune_key(C.byref(cpb), int(precision), a, None, 0, C.byref(n))
+    if rc != 0:
+        raise DmrgError(rc, lib.dmrg_last_error(None).decode())
+    buf = C.create_string_buffer(n.value + 1)
+    rc = lib.dmrg_tune_key(C.byref(cpb), int(precision), a, buf, n.value + 1, C.byref(n))
+    if rc != 0:
+        raise DmrgError(rc, lib.dmrg_last_error(None).decode())
+    return buf.value.decode()
+
+
+def tune_cache_lookup(path, key: str):
+    """Entry of key in the cache file at path as a dict (variant, timings), or None."""
+    lib = load()
+    v, found = C.c_int32(), C.c_int32()
+    ms = np.zeros(10)
+    rc = lib.dmrg_tune_cache_lookup(_path_bytes(path), key.encode(), C.byref(v),
+                                    _dptr(ms, C.c_double), C.byref(found))
+    if rc != 0:
+        raise DmrgError(rc, lib.dmrg_last_error(None).decode())
+    return _tune_dict(ms, v.value) if found.value else None
+
+
+def tune_cache_store(path, key: str, variant: int, ms=None):
+    """Adds or replaces the entry of key in the cache file at path."""
+    lib = load()
+    arr = None if ms is None else np.ascontiguousarray(ms, dtype=np.float64)
+    if arr is not None and arr.size != 10:
+        raise ValueError("ms must hold 10 timings")
+    rc = lib.dmrg_tune_cache_store(_path_bytes(path), key.encode(), int(variant),
+                                   None if arr is None else _dptr(arr, C.c_double))
+    if rc != 0:
+        raise DmrgError(rc, lib.dmrg_last_error(None).decode())
 
 
 class Handle:
@@ -467,15 +531,19 @@ class Handle:
 
     get_gemm = dmrg_get_gemm
 
-    def dmrg_autotune(self, reps: int = 10):
+    def dmrg_autotune(self, reps: int = 10, cache=None):
         """Times the kernel families of each stage, keeps the fastest; returns the timings (ms)
-        and the chosen variant bits."""
+        and the chosen variant bits.  cache: None, or the path of a JSON tuning cache that is
+        consulted first (a hit applies the stored choice without timing; "cached" in the result
+        tells which) and updated after a miss."""
         out = np.zeros(10)
-        _check(self.lib.dmrg_autotune(self.h, int(reps), _dptr(out, C.c_double)), self.h)
-        return dict(stage1_register=out[0], stage1_lds=out[1], stage2_register=out[2],
-                    stage2_lds=out[3], stage1_narrow=out[4], stage2_narrow=out[5],
-                    stage1_x=out[6], stage2_x=out[7], stage1_k=out[8], stage2_k=out[9],
-                    variant=self.get_gemm())
+        if cache is None:
+            _check(self.lib.dmrg_autotune(self.h, int(reps), _dptr(out, C.c_double)), self.h)
+            return _tune_dict(out, self.get_gemm())
+        hit = C.c_int32()
+        _check(self.lib.dmrg_autotune_cached(self.h, _path_bytes(cache), int(reps),
+                                             _dptr(out, C.c_double), C.byref(hit)), self.h)
+        return _tune_dict(out, self.get_gemm(), hit.value)
 
     autotune = dmrg_autotune
 
@@ -513,13 +581,20 @@ class Batch:
 
     set_gemm = dmrg_batch_set_gemm
 
-    def dmrg_batch_autotune(self, reps: int = 5):
+    def dmrg_batch_autotune(self, reps: int = 5, cache=None):
+        """As Handle.autotune, for the merged launches of the batch."""
         out = np.zeros(10)
-        _check(self.lib.dmrg_batch_autotune(self.b, int(reps), _dptr(out, C.c_double)),
+        if cache is None:
+            _check(self.lib.dmrg_batch_autotune(self.b, int(reps), _dptr(out, C.c_double)),
+                   self.handles[0].h)
+            return {f: float(v) for f, v in zip(_TUNE_FIELDS, out)}
+        hit = C.c_int32()
+        _check(self.lib.dmrg_batch_autotune_cached(self.b, _path_bytes(cache), int(reps),
+                                                   _dptr(out, C.c_double), C.byref(hit)),
                self.handles[0].h)
-        return dict(stage1_register=out[0], stage1_lds=out[1], stage2_register=out[2],
-                    stage2_lds=out[3], stage1_narrow=out[4], stage2_narrow=out[5],
-                    stage1_x=out[6], stage2_x=out[7], stage1_k=out[8], stage2_k=out[9])
+        d = {f: float(v) for f, v in zip(_TUNE_FIELDS, out)}
+        d["cached"] = bool(hit.value)
+        return d
 
     autotune = dmrg_batch_autotune
 

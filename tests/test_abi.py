@@ -114,3 +114,146 @@ def test_workspace_cap_refuses_handle_before_any_device_call(lib):
         finally:
             del os.environ["DMRG_MAX_WORKSPACE"]
         assert rc == code and text in msg and not h.value, (cap, rc, msg)
+
+
+# ---- persisted autotuner cache (host only) ----
+
+def _bucket(d):
+    return (int(d) + 15) // 16 * 16
+
+
+def _expected_key(pb, prec, arch, nterms):
+    """The key written out from its definition: superblock blocks are the pairs of a system
+    sector and the environment sector that completes the target quantum numbers."""
+    from collections import Counter
+    idx_e = {tuple(int(x) for x in q): i for i, q in enumerate(pb.E.space.qn)}
+    hs, he = Counter(), Counter()
+    for p, q in enumerate(pb.S.space.qn):
+        r = (int(pb.target[0]) - int(q[0]), int(pb.target[1]) - int(q[1]))
+        if r in idx_e:
+            hs[_bucket(pb.S.space.dim[p])] += 1
+            he[_bucket(pb.E.space.dim[idx_e[r]])] += 1
+    side = lambda h: ",".join(f"{k}:{h[k]}" for k in sorted(h))
+    return f"{arch}/{prec}/problems=1/terms={nterms}/S={side(hs)}/E={side(he)}"
+
+
+def test_tune_key_is_the_sector_histogram(lib):
+    """Four terms per hopping bond (two spins, each with its Hermitian conjugate) plus the generic
+    terms; every superblock block counted once per side, dimensions in buckets of 16."""
+    from tests.test_gpu_parity import problem
+    for name, prec, pname in [("chain12_m30", L.DMRG_FP64, "fp64"),
+                              ("ladder2x6_m40", L.DMRG_FP32, "fp32"),
+                              ("chain8_m17_odd", L.DMRG_BF16X3, "bf16x3")]:
+        pb = problem(name)
+        key = L.tune_key(pb, prec, "gfx950")
+        assert key == _expected_key(pb, pname, "gfx950", 4 * len(pb.bonds)), name
+    pb = I.exact_problem(4, 4.0, (2, 2))
+    extra = [(0.5, 0, 0, 0, 1, 1)]
+    assert L.tune_key(pb, L.DMRG_FP64, "gfx942", extra) == \
+        _expected_key(pb, "fp64", "gfx942", 4 * len(pb.bonds) + 1)
+
+
+def test_tune_key_separates_arithmetic_and_architecture(lib):
+    from tests.test_gpu_parity import problem
+    pb = problem("chain12_m30")
+    keys = {L.tune_key(pb, p, a) for p in (L.DMRG_FP64, L.DMRG_FP32, L.DMRG_BF16X3, L.DMRG_BF16X6)
+            for a in ("gfx950", "gfx942")}
+    assert len(keys) == 8
+    assert L.tune_key(pb) == L.tune_key(problem("chain12_m30"))
+    assert L.tune_key(pb) != L.tune_key(problem("ladder2x6_m40"))
+
+
+def test_tune_key_rejects_bad_input(lib):
+    with pytest.raises(L.DmrgError) as e:
+        L.tune_key(I.exact_problem(4, 4.0, (9, 9)))
+    assert e.value.status == -1 and "empty" in str(e.value)
+    with pytest.raises(L.DmrgError):
+        L.tune_key(I.exact_problem(4, 4.0, (2, 2)), precision=7)
+    # a buffer one byte short of the terminating NUL is refused and left untouched
+    cpb, keep = L.problem_to_c(I.exact_problem(4, 4.0, (2, 2)))
+    n = C.c_int64()
+    assert lib.dmrg_tune_key(C.byref(cpb), 0, b"gfx950", None, 0, C.byref(n)) == 0
+    buf = C.create_string_buffer(b"x" * n.value, n.value)
+    assert lib.dmrg_tune_key(C.byref(cpb), 0, b"gfx950", buf, n.value, C.byref(n)) == -1
+    assert buf.raw == b"x" * n.value
+
+
+def test_tune_cache_round_trip(lib, tmp_path):
+    import json
+    path = tmp_path / "tune.json"
+    assert L.tune_cache_lookup(path, "a") is None
+    assert not path.exists()                      # a lookup never creates the file
+    ms = np.arange(10) * 0.125 - 1.0
+    L.tune_cache_store(path, "a", L.DMRG_GEMM_K, ms)
+    L.tune_cache_store(path, "b", L.DMRG_GEMM_STAGE1_LDS | L.DMRG_GEMM_STAGE2_NARROW)
+    odd = 'q"uote\\back/slash\tτé\U0001F600'
+    L.tune_cache_store(path, odd, 0, [1e-300, 3.5, 1.0 / 3.0, -1, 0, 2e300, 7, 8, 9, 10])
+    a, b, o = (L.tune_cache_lookup(path, k) for k in ("a", "b", odd))
+    assert a["variant"] == L.DMRG_GEMM_K and [a[f] for f in L._TUNE_FIELDS] == list(ms)
+    assert b["variant"] == 9 and all(b[f] == -1.0 for f in L._TUNE_FIELDS)
+    assert o["variant"] == 0 and o["stage2_register"] == 1.0 / 3.0 and o["stage1_register"] == 1e-300
+    assert o["stage2_narrow"] == 2e300
+    doc = json.loads(path.read_text(encoding="utf-8"))
+    assert doc["format"] == "dmrgtst-autotune" and doc["version"] == 1
+    assert [e["key"] for e in doc["entries"]] == ["a", "b", odd]
+    # replacing keeps one entry per key (moved to the end)
+    L.tune_cache_store(path, "a", 0)
+    doc = json.loads(path.read_text(encoding="utf-8"))
+    assert [e["key"] for e in doc["entries"]] == ["b", odd, "a"]
+    assert L.tune_cache_lookup(path, "a")["variant"] == 0
+    assert not list(tmp_path.glob("*.tmp.*"))     # the temporary file was renamed away
+
+
+def test_tune_cache_reads_hand_written_json(lib, tmp_path):
+    path = tmp_path / "hand.json"
+    path.write_text('{ "entries" :[ {"ms":[0.5E+1,-0,1e-3,2,3,4,5,6,7,8.25], "variant" : 3 ,'
+                    '"note": [null, true, false, {"x": {}}], "key":"k\\u00e9\\ud83d\\ude00"}],'
+                    '"version":1, "format":"dmrgtst-autotune" }\r\n', encoding="utf-8")
+    e = L.tune_cache_lookup(path, "ké\U0001F600")
+    assert e["variant"] == 3 and e["stage1_register"] == 5.0 and e["stage2_k"] == 8.25
+    assert e["stage2_register"] == 1e-3
+
+
+@pytest.mark.parametrize("text,why", [
+    ("", "unexpected end"), ("{", "member name"), ('{"format": "dmrgtst-autotune"', "end"),
+    ('{"format": "dmrgtst-autotune", "version": 1, "entries": []} x', "after"),
+    ('{"format": "other", "version": 1, "entries": []}', "version-1"),
+    ('{"format": "dmrgtst-autotune", "version": 2, "entries": []}', "version-1"),
+    ('{"format": "dmrgtst-autotune", "version": 1}', "entries"),
+    ('{"format": "dmrgtst-autotune", "version": 1, "entries": [{"key": "a"}]}', "variant"),
+    ('{"format": "dmrgtst-autotune", "version": 1, "entries": [{"key": "a", "variant": 1.5}]}',
+     "variant"),
+    ('{"format": "dmrgtst-autotune", "version": 1, "entries": [{"key": "a", "variant": 1,'
+     ' "ms": [1]}]}', "10 numbers"),
+    ('{"format": "dmrgtst-autotune", "version": 1, "entries": [01]}', "after|expected"),
+    ('{"format": "dmrgtst-autotune\\x"}', "escape"), ('{"a": "\\ud800"}', "surrogate"),
+    ('{"a": 1e999}', "range"), ('{"a": tru}', "literal"), ('{"a": "\x01"}', "control"),
+    ("[" * 100 + "]" * 100, "deep"),
+])
+def test_tune_cache_rejects_malformed_files_untouched(lib, tmp_path, text, why):
+    path = tmp_path / "bad.json"
+    path.write_text(text, encoding="utf-8")
+    for call in (lambda: L.tune_cache_lookup(path, "a"), lambda: L.tune_cache_store(path, "a", 0)):
+        with pytest.raises(L.DmrgError) as e:
+            call()
+        assert e.value.status == L.STATUS_CODE["DMRG_EIO"]
+        assert re.search(why, str(e.value)), str(e.value)
+    assert path.read_text(encoding="utf-8") == text
+
+
+def test_tune_cache_write_errors(lib, tmp_path):
+    with pytest.raises(L.DmrgError) as e:
+        L.tune_cache_store(tmp_path / "no" / "such" / "dir.json", "a", 0)
+    assert e.value.status == L.STATUS_CODE["DMRG_EIO"] and "cannot write" in str(e.value)
+    with pytest.raises(L.DmrgError) as e:     # a directory cannot be opened as a cache
+        L.tune_cache_lookup(tmp_path, "a")
+    assert e.value.status == L.STATUS_CODE["DMRG_EIO"]
+    with pytest.raises(L.DmrgError) as e:
+        L.tune_cache_store(tmp_path / "t.json", "a", 1 << 10)
+    assert e.value.status == -1 and not (tmp_path / "t.json").exists()
+    with pytest.raises(ValueError):
+        L.tune_cache_store(tmp_path / "t.json", "a", 0, [1.0])
+    assert lib.dmrg_tune_cache_lookup(None, b"a", None, None, None) == -1
+    assert lib.dmrg_tune_cache_store(None, b"a", 0, None) == -1
+    assert lib.dmrg_autotune_cached(None, b"x", 1, None, None) == -1
+    assert lib.dmrg_batch_autotune_cached(None, b"x", 1, None, None) == -1
