@@ -259,6 +259,32 @@ __device__ __forceinline__ void half_sums(double (&v)[N]) {
 #pragma unroll
     for (int q = 0; q < N; ++q) v[q] += dpp_mov<0x142, 0xA>(v[q]);     // row_bcast:15, rows 1, 3
 }
+// half_sums of the entries from L on (the leading L entries are left as they are).
+template <int L, int N>
+__device__ __forceinline__ void half_sums_from(double (&v)[N]) {
+#pragma unroll
+    for (int q = L; q < N; ++q) v[q] += dpp_shr<0x111>(v[q]);
+#pragma unroll
+    for (int q = L; q < N; ++q) v[q] += dpp_shr<0x112>(v[q]);
+#pragma unroll
+    for (int q = L; q < N; ++q) v[q] += dpp_shr<0x114>(v[q]);
+#pragma unroll
+    for (int q = L; q < N; ++q) v[q] += dpp_shr<0x118>(v[q]);
+#pragma unroll
+    for (int q = L; q < N; ++q) v[q] += dpp_mov<0x142, 0xA>(v[q]);
+}
+// half_sums of the complex pairs from block lo on (lo < S, the same in every lane): the pairs
+// of blocks before lo are not summed.
+template <int S, int B = 0>
+__device__ __forceinline__ void half_sums_active(const int lo, double (&v)[2 * S]) {
+    if constexpr (B + 1 < S) {
+        if (lo > B) {
+            half_sums_active<S, B + 1>(lo, v);
+            return;
+        }
+    }
+    half_sums_from<2 * B>(v);
+}
 __device__ __forceinline__ double half_sum(double v) {
     double a[1] = {v};
     half_sums<1>(a);
@@ -310,7 +336,9 @@ __device__ __forceinline__ dv2 cmsc(dv2 acc, dv2 a, dv2 b) {
 //   5. those waves form the same w0^H v, and thread t stores w_t = w0_t - (tau / 2)(w0^H v) v_t;
 //   6. each thread applies B <- B - v w^H - w v^H to its slots.
 // Entries at or above k enter only through v and w, which vanish there, so the stale rows and
-// columns of earlier steps are never masked.  Barriers end steps 1 to 5.
+// columns of earlier steps are never masked.  Barriers end steps 1 to 5.  Blocks of rows and
+// columns wholly above k (those before (k + 1) div 32) are skipped, the column sums' DPP
+// additions included.
 template <int S>
 __device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double* __restrict__ dg,
                                         double* __restrict__ e, dv2* __restrict__ xs0,
@@ -418,7 +446,7 @@ __device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double
                 pc[2 * J] = q.x;
                 pc[2 * J + 1] = q.y;
             }
-            half_sums<2 * S>(pc);
+            half_sums_active<S>(lo, pc);                // blocks before lo hold zeros
 #pragma unroll
             for (int J = 0; J < S; ++J)
                 if (J >= lo && r == 31) cs[32 * J + c] = (dv2){pc[2 * J], pc[2 * J + 1]};
