@@ -309,3 +309,30 @@ def test_ground_state_not_converged_status(env):
     energy, used2, d = h.ground_state(xd, yd, 30, 40, 1e-9)
     assert d["converged"] == 1 and used2 < 40
     h.destroy()
+
+
+def test_ground_state_headline_converges(env):
+    """The ladder 2 x 16 at m = 1000 from a random start: restarted Lanczos with kdim 64 reaches
+    the relative residual 1e-6 within 20 bases.  The residual ||H y - E y|| and the Rayleigh
+    quotient y^H H y are formed with the oracle's product on the host, so neither rests on the
+    HIP path."""
+    torch, L = env
+    say("ground state at the headline, kdim 64")
+    pb = _problem("ladder16_m1000")
+    h = L.dmrg_create(pb)
+    x = I.random_psi(h.n, np.random.default_rng(I.SEED_BASE + 5))
+    xd = _dev(torch, x)
+    yd = torch.empty_like(xd)
+    e, used, info = h.ground_state(xd, yd, 64, 20, 1e-6)
+    y = _host(yd)
+    hy = M.matvec_sector(pb, y)
+    yc = y[:h.n] + 1j * y[h.n:]
+    hyc = hy[:h.n] + 1j * hy[h.n:]
+    rq = float(np.vdot(yc, hyc).real)
+    resid = float(np.linalg.norm(hyc - e * yc))
+    say("  E", e, "bases", used, "estimate", info["err_est"], "residual", resid, "y^H H y", rq)
+    assert info["converged"] == 1 and used <= 20
+    assert abs(np.linalg.norm(yc) - 1.0) < 1e-12
+    assert resid <= 1e-6 * abs(e)
+    assert abs(rq - e) <= 1e-10 * abs(e)
+    h.destroy()
