@@ -44,8 +44,9 @@ hipError_t launch_tridiag(const VecGroup&, const double*, int, int*, int, hipStr
 hipError_t launch_lowest(const VecGroup&, int*, int, hipStream_t);
 hipError_t launch_count_nonfinite(const double*, int64_t, int*, hipStream_t);
 hipError_t launch_density(const DBlock*, int, const int*, int, const DTile*, int, const DensIn&, int,
-                          int64_t, void*, void*, double*, double*, void*, int, int*, int, double*,
-                          int, int, int*, double*, double*, int*, double*, hipStream_t);
+                          int64_t, void*, void*, double*, double*, void*, int, int*,
+                          const DBackItem*, int, double*, int, int, int*, double*, double*, int*,
+                          double*, hipStream_t);
 hipError_t launch_combine(const VecGroup&, double* const*, double* const*, int, int, hipStream_t);
 hipError_t launch_wft(const ZTile*, int, const ZPtrs&, const ZTile*, int, const ZPtrs&, int, int64_t,
                       hipStream_t);
@@ -426,9 +427,9 @@ struct dmrg_ctx {
     // density matrix and truncation (built on first use): sectors, tiles, matrices, results
     // the call's results in one device area (per sector: the two sums, the number kept, the
     // eigen-decomposition flags), copied at once into pinned host memory
-    DevBuf dDBlk, dDSel, dDTile, dDA, dDV, dDZ, dDS, dDT, dDEv, dDKept, dDRes;
+    DevBuf dDBlk, dDSel, dDTile, dDBack, dDA, dDV, dDZ, dDS, dDT, dDEv, dDKept, dDRes;
     HostBuf hDRes;
-    int dens_ntiles = 0, dens_ntot = 0, dens_maxd = 0, dens_nreg = 0, dens_nbt = 0;
+    int dens_ntiles = 0, dens_ntot = 0, dens_nreg = 0, dens_nbt = 0, dens_nback = 0;
     int64_t dens_nmat = 0;
     std::unique_ptr<dmrg_batch_ctx> chains;   // the handle's four chains of the 4-RHS mode
     // local operators (built on first use): raw operator blocks of both halves, the product
@@ -1708,7 +1709,6 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
             blks[b] = DBlock{pbk.d, pbk.e, pbk.off, aoff, eoff, toff};
             toff += (int64_t)back_nblocks(pbk.d) * back_bt(pbk.d) * back_bt(pbk.d);
             h->dens_nbt = std::max(h->dens_nbt, back_nblocks(pbk.d));
-            h->dens_maxd = std::max(h->dens_maxd, pbk.d);
             if (pbk.d <= kDensRegMaxDim) sel.push_back(b);
             for (int i0 = 0; i0 < pbk.d; i0 += 16)       // tiles on and below the diagonal
                 for (int j0 = 0; j0 <= i0; j0 += 16) tiles.push_back(DTile{b, i0, j0, 0});
@@ -1718,6 +1718,16 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
         h->dens_nreg = (int)sel.size();
         for (int b = 0; b < nb; ++b)
             if (P.blocks[b].d > kDensRegMaxDim) sel.push_back(b);
+        // back-transformation work groups: every sector's column ranges, larger sectors first
+        std::vector<int> order(nb);
+        for (int b = 0; b < nb; ++b) order[b] = b;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int x, int y) { return P.blocks[x].d > P.blocks[y].d; });
+        std::vector<DBackItem> back;
+        for (int b : order)
+            for (int jb = 0; jb < P.blocks[b].d; jb += back_cols(P.blocks[b].d))
+                back.push_back(DBackItem{b, jb});
+        h->dens_nback = (int)back.size();
         h->dens_ntiles = (int)tiles.size();
         h->dens_ntot = (int)eoff;
         h->dens_nmat = aoff;
@@ -1725,6 +1735,7 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
         // leaves every buffer to be allocated again by the next call
         HIP_TRY(h, upload(h->dDTile, tiles, s));
         HIP_TRY(h, upload(h->dDSel, sel, s));
+        HIP_TRY(h, upload(h->dDBack, back, s));
         HIP_TRY(h, h->dDA.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDV.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDZ.alloc(sizeof(double) * (size_t)aoff));
@@ -1748,8 +1759,8 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
     HIP_TRY(h, launch_density(h->dDBlk.as<DBlock>(), nb, h->dDSel.as<int>(), h->dens_nreg,
                               h->dDTile.as<DTile>(), h->dens_ntiles, in, nvec, P.n, h->dDA.p,
                               h->dDV.p, h->dDZ.as<double>(), h->dDS.as<double>(), h->dDT.p,
-                              h->dens_nbt, d_flags,
-                              h->dens_maxd, h->dDEv.as<double>(), h->dens_ntot, keep,
+                              h->dens_nbt, d_flags, h->dDBack.as<DBackItem>(), h->dens_nback,
+                              h->dDEv.as<double>(), h->dens_ntot, keep,
                               h->dDKept.as<int>(), evals, evecs, d_nk, d_sums, s));
     HIP_TRY(h, hipMemcpyAsync(h->hDRes.p, h->dDRes.p, res_bytes, hipMemcpyDeviceToHost, s));
     HIP_TRY(h, hipStreamSynchronize(s));

@@ -242,6 +242,29 @@ __device__ __forceinline__ double dpp_shr(double v) {
     return __hiloint2double(hi, lo);
 }
 
+// Sums over the 16 lanes of each DPP row, for N complex values, into every lane of the row:
+// rotations by 8, 4, 2 and 1 lanes, each added.  After the rotation by r the values repeat with
+// period r, so the two addends of every lane's next sum are those of its partner's, swapped, and
+// all lanes of a row end with the same bits.
+template <int N>
+__device__ __forceinline__ void row_allsums(dv2 (&v)[N]) {
+#pragma unroll
+    for (int q = 0; q < N; ++q) { v[q].x += dpp_shr<0x128>(v[q].x); v[q].y += dpp_shr<0x128>(v[q].y); }
+#pragma unroll
+    for (int q = 0; q < N; ++q) { v[q].x += dpp_shr<0x124>(v[q].x); v[q].y += dpp_shr<0x124>(v[q].y); }
+#pragma unroll
+    for (int q = 0; q < N; ++q) { v[q].x += dpp_shr<0x122>(v[q].x); v[q].y += dpp_shr<0x122>(v[q].y); }
+#pragma unroll
+    for (int q = 0; q < N; ++q) { v[q].x += dpp_shr<0x121>(v[q].x); v[q].y += dpp_shr<0x121>(v[q].y); }
+}
+
+// The value of the lane 16 apart within each group of 32 lanes (ds_swizzle in bit mode: and
+// mask 0x1F, or mask 0, xor mask 0x10).
+__device__ __forceinline__ double swz16(double v) {
+    const int lo = __builtin_amdgcn_ds_swizzle(__double2loint(v), 0x401F);
+    const int hi = __builtin_amdgcn_ds_swizzle(__double2hiint(v), 0x401F);
+    return __hiloint2double(hi, lo);
+}
 // Sum over each 32-lane half of the wavefront into its last lane (31 and 63), for N values
 // level by level: shifts by 1, 2, 4 and 8 lanes within each row of 16 (lane 15 of a row then
 // holds the row's sum), then lane 15 of rows 0 and 2 added into rows 1 and 3.  Other lanes hold
@@ -1230,21 +1253,17 @@ __global__ __launch_bounds__(kEigThreadsR) void k_heig_r(const DBlock* __restric
 //   k_back_t     the T of every block, in parallel (one work group per sector and block), into
 //                Tb at blk.toff (block bi, from the bottom: bi BT^2 elements on, T[r][c] at
 //                r + BT c);
-//   k_heig_back  Y - V (T (V^H Y)) block after block, one work group per sector and range of
-//                back_cols(d) columns of Y, which stay in LDS from the load of Z (row-major, or
+//   k_heig_back  Y - V (T (V^H Y)) block after block, one work group per item of a host list
+//                (a sector and its range of back_cols(d) columns of Y; larger sectors first, so
+//                the longest work groups start first), the columns staying in LDS from the load
+//                of Z (row-major, or
 //                column-major when bit 1 of flags[blk] is set) to the store of Y (column-major).
 //                The next block's reflectors and T are loaded into registers while the current
 //                one is applied, and written to the other half of double LDS buffers, so a block
-//                costs one barrier and no exposed global load.  kBackLanes lanes per column:
-//                lane q takes the rows i = q mod kBackLanes, and the lane group adds its partial
-//                inner products by shuffles.
-constexpr int kBackThreads = 256;
-constexpr int kBackLanes = 16;      // lanes per column of Y
-constexpr int kBackCols = kBackThreads / kBackLanes;   // most columns of Y per work group
-constexpr int kBackLds = 4096;      // complex elements of the work group's columns in LDS (64 KB)
-__host__ __device__ constexpr int back_cols(int d) {
-    return d * kBackCols <= kBackLds ? kBackCols : kBackLds / d;
-}
+//                costs one barrier and no exposed global load.  kBackLanes (32) lanes per
+//                column: lane q takes the rows i = q mod kBackLanes, and the lane group adds its
+//                partial inner products by DPP rotations within each of its two rows of 16, then
+//                a swizzle across them (the same bits in every lane).
 static_assert(kBackLds / kDensMaxDim >= 1, "one column of the largest sector fits");
 static_assert(kBackVs / 2 >= kDensMaxDim, "two reflectors of the largest sector fit");
 
@@ -1355,18 +1374,21 @@ __device__ __forceinline__ void back_blocks(int d, int nc, const dv2* __restrict
             dv2 w[BT];
 #pragma unroll
             for (int c = 0; c < BT; ++c) w[c] = (dv2){0.0, 0.0};
+#pragma unroll 2
             for (int i = i1; i < d; i += L) {
                 const dv2 yv = y[i];
 #pragma unroll
                 for (int c = 0; c < BT; ++c) w[c] = cmac(w[c], cconj(V[c * d + i]), yv);
             }
-#pragma unroll
-            for (int o = 1; o < L; o <<= 1)
+            static_assert(L == 16 || L == 32, "a lane group is one or two DPP rows");
+            row_allsums(w);
+            if constexpr (L == 32) {
 #pragma unroll
                 for (int c = 0; c < BT; ++c) {
-                    w[c].x += __shfl_xor(w[c].x, o, 64);
-                    w[c].y += __shfl_xor(w[c].y, o, 64);
+                    w[c].x += swz16(w[c].x);
+                    w[c].y += swz16(w[c].y);
                 }
+            }
             dv2 u[BT];
 #pragma unroll
             for (int r = 0; r < BT; ++r) {
@@ -1374,6 +1396,7 @@ __device__ __forceinline__ void back_blocks(int d, int nc, const dv2* __restrict
 #pragma unroll
                 for (int c = r; c < BT; ++c) u[r] = cmac(u[r], T[r + BT * c], w[c]);
             }
+#pragma unroll 2
             for (int i = i1; i < d; i += L) {
                 dv2 yv = y[i];
 #pragma unroll
@@ -1385,23 +1408,24 @@ __device__ __forceinline__ void back_blocks(int d, int nc, const dv2* __restrict
 }
 
 __global__ __launch_bounds__(kBackThreads) void k_heig_back(const DBlock* __restrict__ blks,
+                                                            const DBackItem* __restrict__ items,
                                                             const dv2* __restrict__ A,
                                                             const dv2* __restrict__ Tb,
                                                             const double* __restrict__ Zb,
                                                             dv2* __restrict__ Yb,
                                                             const int* __restrict__ flags) {
     constexpr int NT = kBackThreads;
-    const DBlock B = blks[blockIdx.x];
+    const DBackItem it = items[blockIdx.x];
+    const DBlock B = blks[it.blk];
     const int d = B.d, tid = threadIdx.x;
     const int cols = back_cols(d);
-    const int jb = blockIdx.y * cols;
-    if (jb >= d) return;
+    const int jb = it.jb;
     const int nc = jb + cols < d ? cols : d - jb;       // columns jb .. jb + nc - 1
     const dv2* __restrict__ a = A + B.aoff;
     const dv2* __restrict__ tg = Tb + B.toff;
     const double* __restrict__ Z = Zb + B.aoff;
     dv2* __restrict__ Y = Yb + B.aoff;
-    const bool colmajor = (flags[blockIdx.x] & 2) != 0;
+    const bool colmajor = (flags[it.blk] & 2) != 0;
     const int64_t zr = colmajor ? 1 : d, zc = colmajor ? d : 1;
     __shared__ dv2 Vs[2 * kBackVs];                     // two blocks of reflectors, V[c d + i]
     __shared__ dv2 Ys[kBackLds];                        // Ys[jl d + i] = Y[i][jb + jl]
@@ -1513,7 +1537,7 @@ __global__ __launch_bounds__(256) void k_finish(const DBlock* __restrict__ blks,
 hipError_t launch_density(const DBlock* blks, int nblk, const int* sel, int nreg,
                           const DTile* tiles, int ntiles, const DensIn& in, int nv, int64_t n,
                           void* A, void* V, double* Z, double* S, void* Tb, int nbt, int* fail,
-                          int maxd, double* ev,
+                          const DBackItem* back, int nback, double* ev,
                           int ntot, int keep, int* kept, double* evals, double* evecs, int* nkept,
                           double* sums, hipStream_t s) {
     hipLaunchKernelGGL(k_density, dim3(ntiles), dim3(64), 0, s, blks, tiles, in, nv, n,
@@ -1528,9 +1552,7 @@ hipError_t launch_density(const DBlock* blks, int nblk, const int* sel, int nreg
     if (nbt > 0)
         hipLaunchKernelGGL(k_back_t, dim3(nblk, nbt), dim3(kBackTThreads), 0, s, blks,
                            static_cast<const dv2*>(A), static_cast<dv2*>(Tb));
-    // work groups per sector: ceil(d / back_cols(d)) grows with d, so maxd gives the most
-    const int bcy = (maxd + back_cols(maxd) - 1) / back_cols(maxd);
-    hipLaunchKernelGGL(k_heig_back, dim3(nblk, bcy), dim3(kBackThreads), 0, s, blks,
+    hipLaunchKernelGGL(k_heig_back, dim3(nback), dim3(kBackThreads), 0, s, blks, back,
                        static_cast<const dv2*>(A), static_cast<const dv2*>(Tb), Z,
                        static_cast<dv2*>(V), fail);
     hipLaunchKernelGGL(k_zero_int, dim3((ntot + 255) / 256), dim3(256), 0, s, kept, ntot);

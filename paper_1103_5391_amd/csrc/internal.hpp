@@ -267,6 +267,19 @@ __host__ __device__ constexpr int back_bt(int d) {
 __host__ __device__ constexpr int back_nblocks(int d) {
     return d >= 2 ? (d - 1 + back_bt(d) - 1) / back_bt(d) : 0;
 }
+// The back-transformation's work groups: kBackThreads threads, kBackLanes lanes per column of
+// the eigenvector block, so back_cols(d) columns per work group (fewer when they would not fit
+// the kBackLds complex elements of LDS).
+constexpr int kBackThreads = 256;
+constexpr int kBackLanes = 32;
+constexpr int kBackCols = kBackThreads / kBackLanes;
+constexpr int kBackLds = 4096;
+__host__ __device__ constexpr int back_cols(int d) {
+    return d * kBackCols <= kBackLds ? kBackCols : kBackLds / d;
+}
+struct DBackItem {        // one work group of the back-transformation: sector, first column
+    int32_t blk, jb;
+};
 struct DTile {            // 16 x 16 tile of one sector's density matrix
     int32_t blk, i0, j0, pad;
 };
