@@ -325,6 +325,12 @@ __device__ __forceinline__ double wave_sum(double v) {
     return lo + hi;
 }
 
+// The value of one lane (uniform lane index) in every lane.
+__device__ __forceinline__ double readlane_d(double v, int lane) {
+    return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(v), lane),
+                            __builtin_amdgcn_readlane(__double2loint(v), lane));
+}
+
 // acc + a b and acc - a conj(b) as four fused multiply-adds each
 __device__ __forceinline__ dv2 cmac(dv2 acc, dv2 a, dv2 b) {
     acc.x = fma(a.x, b.x, acc.x);
@@ -347,30 +353,33 @@ __device__ __forceinline__ dv2 cmsc(dv2 acc, dv2 a, dv2 b) {
 // 32 grid: thread (r, c) = (tid mod 32, tid div 32) holds element (32 I + r, 32 J + c) for
 // J <= I < S in slot I (I + 1) / 2 + J; entries above the diagonal and beyond d are zeros and
 // stay zeros.  The update of step k is applied at once.  Step k:
-//   1. the thread of column k that holds row i >= 32 (k div 32) stores x_i (0 for i <= k) into
-//      xs (LDS; two buffers by the parity of k) and the diagonal entry into dg;
-//   2. the waves of the vector threads (t < 32 S) form the same reflector from xs (the same
-//      sums in the same order), and thread t stores v_t (0 outside k < t < d) into vs;
-//   3. the product B v over the trailing matrix: from its slots a thread forms row sums
+//   1. the half-wave that holds column k (c = k mod 32; all its rows, in its lanes' slots of
+//      block column k div 32) forms the reflector: the squared norm of x below row k + 1 by
+//      DPP moves over its 32 lanes, alpha = x_{k+1} from the lane that holds it, then beta,
+//      tau and the scale of v in every lane alike; lane r stores v_i for its rows i (0 outside
+//      k < i < d) into vs (LDS; two buffers by the parity of k, since this half-wave starts
+//      step k + 1 right after its own update of step k, while others may still read v_k), the
+//      diagonal entry into dg, and tau into s_tau;
+//   2. the product B v over the trailing matrix: from its slots a thread forms row sums
 //      (B_ij v_j, j <= i) and column sums (conj(B_ij) v_i into entry j, i > j); each half-wave
 //      stores its row of row sums (rp), and the column sums over its 32 lanes, added by DPP
 //      moves, are complete (cs);
-//   4. thread t adds the half-waves' rows and the column sum of entry t: w0_t = tau p_t (ps);
-//   5. those waves form the same w0^H v, and thread t stores w_t = w0_t - (tau / 2)(w0^H v) v_t;
-//   6. each thread applies B <- B - v w^H - w v^H to its slots.
+//   3. thread t adds the half-waves' rows and the column sum of entry t: w0_t = tau p_t (ps);
+//   4. the waves of the vector threads (t < 32 S) form the same w0^H v (the same sums in the
+//      same order), and thread t stores w_t = w0_t - (tau / 2)(w0^H v) v_t;
+//   5. each thread applies B <- B - v w^H - w v^H to its slots.
 // Entries at or above k enter only through v and w, which vanish there, so the stale rows and
-// columns of earlier steps are never masked.  Barriers end steps 1 to 5.  Blocks of rows and
+// columns of earlier steps are never masked.  Barriers end phases 1 to 4.  Blocks of rows and
 // columns wholly above k (those before (k + 1) div 32) are skipped, the column sums' DPP
 // additions included.
 template <int S>
 __device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double* __restrict__ dg,
-                                        double* __restrict__ e, dv2* __restrict__ xs0,
-                                        dv2* __restrict__ xs1, dv2* __restrict__ vs,
-                                        dv2* __restrict__ ws, dv2* __restrict__ ps,
-                                        dv2* __restrict__ cs, dv2* __restrict__ rp) {
+                                        double* __restrict__ e, dv2* __restrict__ vs0,
+                                        dv2* __restrict__ vs1, dv2* __restrict__ ws,
+                                        dv2* __restrict__ ps, dv2* __restrict__ cs,
+                                        dv2* __restrict__ rp, dv2* __restrict__ s_tau) {
     constexpr int NW = kEigThreadsR / 64, MD = 32 * S;
     const int tid = threadIdx.x, r = tid & 31, c = tid >> 5, wv = tid >> 6, ln = tid & 63;
-    const bool vw = wv < (MD + 63) / 64;                // a wave of the vector threads t < MD
     const dv2 z = (dv2){0.0, 0.0};
     dv2 m[S * (S + 1) / 2];
 #pragma unroll
@@ -383,35 +392,37 @@ __device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double
             m[I * (I + 1) / 2 + J] = x;
         }
     for (int k = 0; k + 1 < d; ++k) {
-        dv2* __restrict__ xs = (k & 1) ? xs1 : xs0;
+        dv2* __restrict__ vs = (k & 1) ? vs1 : vs0;     // v of step k (two buffers by parity)
         const int kb = k >> 5;                          // block of column k
         const int lo = (k + 1) >> 5;                    // blocks below lo hold no entry > k
-        // 1.
+        const int i1 = k + 1, I1 = i1 >> 5;
+        // 1. the half-wave holding column k (c = k mod 32) forms the reflector from its slots
         if (c == (k & 31)) {
+            const int h = 32 * (c & 1);                 // its first lane in the wavefront
+            dv2 xr[S];                                  // column k, rows 32 I + r
 #pragma unroll
-            for (int I = 0; I < S; ++I)
+            for (int I = 0; I < S; ++I) {
+                xr[I] = z;
 #pragma unroll
                 for (int J = 0; J <= I; ++J)
-                    if (J == kb && I >= kb) {
-                        const int i = 32 * I + r;
-                        const dv2 x = m[I * (I + 1) / 2 + J];
-                        xs[i] = i > k ? x : z;
-                        if (i == k) dg[k] = x.x;
-                    }
-        }
-        __syncthreads();
-        // 2. (the waves of vector threads only)
-        dv2 tau = z;
-        if (vw) {
-            double part = 0.0;
-            for (int i = k + 2 + ln; i < d; i += 64) {
-                const dv2 x = xs[i];
-                part = fma(x.x, x.x, part);
-                part = fma(x.y, x.y, part);
+                    if (J == kb && I >= kb) xr[I] = m[I * (I + 1) / 2 + J];
             }
-            const double xn2 = wave_sum(part);
-            const dv2 al = xs[k + 1];
-            dv2 sc = z;
+            double part = 0.0;
+            dv2 x1 = z;
+#pragma unroll
+            for (int I = 0; I < S; ++I) {
+                const int i = 32 * I + r;
+                if (i > i1) {                           // rows beyond d hold zeros
+                    part = fma(xr[I].x, xr[I].x, part);
+                    part = fma(xr[I].y, xr[I].y, part);
+                }
+                if (I == I1) x1 = xr[I];
+                if (i == k) dg[k] = xr[I].x;
+            }
+            // |x below k + 1|^2 over the half-wave (into its lane 31), and alpha = x_{k+1}
+            const double xn2 = readlane_d(half_sum(part), h + 31);
+            const dv2 al = (dv2){readlane_d(x1.x, h + (i1 & 31)), readlane_d(x1.y, h + (i1 & 31))};
+            dv2 sc = z, tau = z;
             double beta = al.x;
             if (!(xn2 == 0.0 && al.y == 0.0)) {
                 beta = -copysign(sqrt(al.x * al.x + al.y * al.y + xn2), al.x);
@@ -421,20 +432,24 @@ __device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double
                 const double rq = recip2(den.x * den.x + den.y * den.y);
                 sc = (dv2){den.x * rq, -den.y * rq};
             }
-            if (tid == 0) {
+            if (r == 0) {
                 e[k] = beta;
                 a[(int64_t)k * d + k] = tau;
+                *s_tau = tau;
             }
-            if (tid < MD && tid >= 32 * lo) {
+#pragma unroll
+            for (int I = 0; I < S; ++I) {
+                if (I < lo) continue;
+                const int i = 32 * I + r;
                 dv2 v = z;
-                if (tid == k + 1) v = (dv2){1.0, 0.0};
-                else if (tid > k + 1 && tid < d) v = cmul(xs[tid], sc);
-                vs[tid] = v;
-                if (tid > k + 1 && tid < d) a[(int64_t)k * d + tid] = v;   // v_k below the subdiagonal
+                if (i == i1) v = (dv2){1.0, 0.0};
+                else if (i > i1 && i < d) v = cmul(xr[I], sc);
+                vs[i] = v;
+                if (i > i1 && i < d) a[(int64_t)k * d + i] = v;   // v_k below the subdiagonal
             }
         }
         __syncthreads();
-        // 3.
+        // 2.
         {
             dv2 pr[S];
 #pragma unroll
@@ -475,7 +490,8 @@ __device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double
                 if (J >= lo && r == 31) cs[32 * J + c] = (dv2){pc[2 * J], pc[2 * J + 1]};
         }
         __syncthreads();
-        // 4.
+        const dv2 tau = *s_tau;
+        // 3.
         if (tid < MD && tid >= 32 * lo) {
             dv2 p = cs[tid];
 #pragma unroll
@@ -483,8 +499,8 @@ __device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double
             ps[tid] = (tid > k && tid < d) ? cmul(tau, p) : z;
         }
         __syncthreads();
-        // 5.
-        if (vw) {
+        // 4.
+        if (wv < (MD + 63) / 64) {                      // the waves of the vector threads t < MD
             double sr = 0.0, si = 0.0;                  // w0^H v
             for (int i = k + 1 + ln; i < d; i += 64) {
                 const dv2 w = ps[i], v = vs[i];
@@ -499,7 +515,7 @@ __device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double
             if (tid < MD && tid >= 32 * lo) ws[tid] = cmac(ps[tid], al2, vs[tid]);
         }
         __syncthreads();
-        // 6.
+        // 5.
         {
             dv2 vr[S], wr[S];
 #pragma unroll
@@ -567,8 +583,8 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
     if constexpr (REG) {
         static_assert(NT == kEigThreadsR && MAXD % 32 == 0, "32 x 32 thread grid");
         __shared__ dv2 rp[2 * (NT / 64) * MAXD];        // row sums of the half-waves
-        __shared__ dv2 vs[MAXD], ws[MAXD];
-        hh_regs<MAXD / 32>(d, a, dg, e, vv, vv1, vs, ws, ww, ww1, rp);
+        __shared__ dv2 ws[MAXD], s_tau;
+        hh_regs<MAXD / 32>(d, a, dg, e, vv, vv1, ws, ww, ww1, rp, &s_tau);
     } else {
     __shared__ dv2 s_alpha;                             // alpha of the current reflector
     __shared__ dv2 tm[kHhLdsDim * kHhLdsDim];          // trailing matrix once it fits
@@ -1287,7 +1303,7 @@ __device__ __forceinline__ void back_t(int d, int bi, const dv2* __restrict__ a,
     if (ln < BT) taus[ln] = k1 + ln < 0 ? (dv2){0.0, 0.0} : a[(int64_t)(k1 + ln) * d + k1 + ln];
     __syncthreads();
     {
-        // Gram entry (c1, c2), c1 < c2, by GL lanes (rows i = q mod GL), added by shuffles
+        // Gram entry (c1, c2), c1 < c2, by GL lanes (rows i = q mod GL), added by DPP moves
         const int p = ln / GL, q = ln % GL;
         dv2 acc = (dv2){0.0, 0.0};
         int c1 = 0, c2 = 1;
@@ -1298,11 +1314,15 @@ __device__ __forceinline__ void back_t(int d, int bi, const dv2* __restrict__ a,
             const int i0 = k1 + c2 + 1 > 0 ? k1 + c2 + 1 : 0;
             for (int i = i0 + q; i < d; i += GL) acc = cmac(acc, cconj(Vl[c1 * d + i]), Vl[c2 * d + i]);
         }
-#pragma unroll
-        for (int o = 1; o < GL; o <<= 1) {
-            acc.x += __shfl_xor(acc.x, o, 64);
-            acc.y += __shfl_xor(acc.y, o, 64);
-        }
+        // the 8 lanes of a pair are half a DPP row: lane ^ 1 and lane ^ 2 (quad permutations),
+        // then lane 7 - i within the 8 (half-row mirror) give every lane the pair's sum
+        static_assert(GL == 8, "a pair's lanes are half a DPP row");
+        acc.x += dpp_shr<0xB1>(acc.x);
+        acc.y += dpp_shr<0xB1>(acc.y);
+        acc.x += dpp_shr<0x4E>(acc.x);
+        acc.y += dpp_shr<0x4E>(acc.y);
+        acc.x += dpp_shr<0x141>(acc.x);
+        acc.y += dpp_shr<0x141>(acc.y);
         if (p < NP && q == 0) Gm[c1 + BT * c2] = acc;
     }
     __syncthreads();
