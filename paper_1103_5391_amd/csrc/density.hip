@@ -96,14 +96,18 @@ __device__ __forceinline__ void handover_barrier() {
 // into P_i, and the result in lane (g, r) at row g + 4 v, column r.  A tile below the diagonal
 // is also written, conjugated, at (j, i) (rho is Hermitian).  Written to A (complex,
 // column-major d x d at blk.aoff).  Work group 0 also clears the per-sector flags of the
-// eigen-decomposition.
+// eigen-decomposition, and all work groups clear the rank counters of k_rank.
 __global__ __launch_bounds__(64) void k_density(const DBlock* __restrict__ blks,
                                                 const DTile* __restrict__ tiles, const DensIn in,
                                                 int nv, int64_t n, dv2* __restrict__ A,
-                                                int* __restrict__ fail, int nblk) {
+                                                int* __restrict__ fail, int nblk,
+                                                int* __restrict__ kept, int ntot) {
     typedef double d4 __attribute__((ext_vector_type(4)));
+    // the per-sector flags and the rank counters of this call start at zero
     if (blockIdx.x == 0)
         for (int t = threadIdx.x; t < nblk; t += blockDim.x) fail[t] = 0;
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < ntot; t += gridDim.x * blockDim.x)
+        kept[t] = 0;
     const DTile tl = tiles[blockIdx.x];
     const DBlock B = blks[tl.blk];
     const int ln = threadIdx.x, g = ln >> 4, r = ln & 15;
@@ -1467,13 +1471,8 @@ __global__ __launch_bounds__(kBackThreads) void k_heig_back(const DBlock* __rest
 // the order of the flat array), in pieces: work group (x, y) counts, for its 256 eigenvalues,
 // the values of chunk y (kRankChunk values through LDS) that rank before them, and adds the
 // count to rank[g] (integer atomics: the sum does not depend on their order).  rank starts at
-// zero.
+// zero (cleared by k_density).
 constexpr int kRankChunk = 256;
-__global__ __launch_bounds__(256) void k_zero_int(int* __restrict__ x, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) x[i] = 0;
-}
-
 __global__ __launch_bounds__(256) void k_rank(const double* __restrict__ ev, int ntot,
                                               int* __restrict__ rank) {
     __shared__ double sv[kRankChunk];
@@ -1561,7 +1560,7 @@ hipError_t launch_density(const DBlock* blks, int nblk, const int* sel, int nreg
                           int ntot, int keep, int* kept, double* evals, double* evecs, int* nkept,
                           double* sums, hipStream_t s) {
     hipLaunchKernelGGL(k_density, dim3(ntiles), dim3(64), 0, s, blks, tiles, in, nv, n,
-                       static_cast<dv2*>(A), fail, nblk);
+                       static_cast<dv2*>(A), fail, nblk, kept, ntot);
     // sel: first the nreg sectors of the register-resident kernel, then the others
     if (nreg > 0)
         hipLaunchKernelGGL(k_heig_r, dim3(nreg), dim3(kEigThreadsR), 0, s, blks, sel,
@@ -1575,7 +1574,6 @@ hipError_t launch_density(const DBlock* blks, int nblk, const int* sel, int nreg
     hipLaunchKernelGGL(k_heig_back, dim3(nback), dim3(kBackThreads), 0, s, blks, back,
                        static_cast<const dv2*>(A), static_cast<const dv2*>(Tb), Z,
                        static_cast<dv2*>(V), fail);
-    hipLaunchKernelGGL(k_zero_int, dim3((ntot + 255) / 256), dim3(256), 0, s, kept, ntot);
     hipLaunchKernelGGL(k_rank, dim3((ntot + 255) / 256, (ntot + kRankChunk - 1) / kRankChunk), dim3(256), 0,
                        s, ev, ntot, kept);
     hipLaunchKernelGGL(k_finish, dim3(nblk, kFinishSplit), dim3(256), 0, s, blks, ev, kept, keep,
