@@ -458,7 +458,10 @@ int dmrg_expect_local(dmrg_handle h, int32_t nterm, const dmrg_term* terms, cons
  * chains, each advanced by exp(-i tau H) with a Krylov basis of its own (kdim vectors, Sec. II.A)
  * instead of one basis evaluated at four times (the variant of the seeding of the next
  * interval, Sec. II.C; it agrees with dmrg_tst_targets only to Krylov error).  The four chains
- * share every block-product and vector-pass launch.  phi, targets: host arrays of 4 device
+ * share every block-product and vector-pass launch; in FP64 with narrow tiles in both stages
+ * (DMRG_GEMM_STAGE1_NARROW | DMRG_GEMM_STAGE2_NARROW) one stage-2 work group computes a tile
+ * for all four chains, loading the packed left factors once.  Each target has the same bits as
+ * one dmrg_krylov_expm step of its phi with the same kdim.  phi, targets: host arrays of 4 device
  * pointers (2n doubles each); targets[k] = exp(-i tau H) phi[k], and targets[k] may equal
  * phi[k].  weights as in dmrg_tst_targets.  infos: NULL or a host array of 4 structs (then the
  * call waits for the stream).  The first call allocates three more workspaces of the handle's

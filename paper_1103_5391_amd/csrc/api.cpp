@@ -25,6 +25,8 @@ hipError_t launch_stage1(int, int, const S1Block*, const Tile*, int, const ProbP
                          hipStream_t);
 hipError_t launch_stage2(int, int, const S2Block*, const Segment*, const Tile*, int,
                          const ProbPtrs*, ProbPtrs, hipStream_t);
+hipError_t launch_stage2_mr(const S2Block*, const Segment*, const Tile*, int, const ProbPtrs*,
+                            hipStream_t);
 hipError_t launch_stage1_lds(int, const S1Block*, const LItem1*, int, const ProbPtrs*, ProbPtrs,
                              hipStream_t);
 hipError_t launch_stage2_lds(int, const S2Block*, const Segment*, const LItem2*, int, const LRed*,
@@ -145,6 +147,9 @@ struct Lists {
     int nx2 = 0, nxz = 0;
     int nkp = 0, nkt1 = 0, nkt2 = 0;
     int variant = 0;    // DMRG_GEMM_* bits: which kernel family runs each stage
+    // 4-RHS mode only: the owners' lists (each plan once), whose stage 2 runs all chains of a
+    // tile in one work group (FP64, narrow tiles of both stages); nullptr elsewhere
+    const Lists* mr = nullptr;
 };
 
 // Device copy of a host vector (synchronous on s).
@@ -265,6 +270,12 @@ hipError_t run_stages(const Lists& W, int prec, const ProbPtrs* probs, ProbPtrs 
                       hipStream_t s) {
     const hipError_t e = run_stage(W, 1, W.variant, prec, probs, single, s);
     if (e != hipSuccess) return e;
+    if (W.mr && probs && prec == DMRG_FP64 &&
+        W.variant == (DMRG_GEMM_STAGE1_NARROW | DMRG_GEMM_STAGE2_NARROW)) {
+        const Lists& M = *W.mr;
+        return launch_stage2_mr(M.dS2[0].as<S2Block>(), M.dSeg[0].as<Segment>(),
+                                M.dT2n.as<Tile>(), M.nt2n, probs, s);
+    }
     return run_stage(W, 2, W.variant, prec, probs, single, s);
 }
 
@@ -404,6 +415,7 @@ struct Workspace {
 
 struct dmrg_batch_ctx {
     Lists lists;        // merged work lists of all members
+    Lists mrl;          // 4-RHS mode: the owners' lists, each plan once (lists.mr)
     Group g;
     std::unique_ptr<dmrg_batch_ctx> chains;   // the 4-RHS mode: every member's four chains
 };
@@ -752,9 +764,21 @@ int chains_set(std::unique_ptr<dmrg_batch_ctx>& cs, const std::vector<dmrg_ctx*>
             }
         Merged M;
         merge_plans(plans, M);
-        const hipError_t e = upload_lists(c->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles1n,
-                                          M.tiles2, M.tiles2n, M.l1, M.l2, M.lred, M.nslots,
-                                          M.xch, M.x2, M.xz, M.kf, h0->stream);
+        hipError_t e = upload_lists(c->lists, M.s1, M.s2, M.segs, M.tiles1, M.tiles1n,
+                                    M.tiles2, M.tiles2n, M.l1, M.l2, M.lred, M.nslots,
+                                    M.xch, M.x2, M.xz, M.kf, h0->stream);
+        if (e == hipSuccess) {
+            // the owners' lists for the shared-operator stage 2 (problem i = owner i)
+            static_assert(kChains == kMultiRhs, "chain c of owner i is problem kChains i + c");
+            std::vector<const Plan*> own;
+            for (dmrg_ctx* h : owners) own.push_back(&h->plan);
+            Merged O;
+            merge_plans(own, O);
+            e = upload_lists(c->mrl, O.s1, O.s2, O.segs, O.tiles1, O.tiles1n, O.tiles2,
+                             O.tiles2n, O.l1, O.l2, O.lred, O.nslots, O.xch, O.x2, O.xz, O.kf,
+                             h0->stream);
+            c->lists.mr = &c->mrl;
+        }
         if (e != hipSuccess)
             return fail(h0, e == hipErrorOutOfMemory ? DMRG_ENOMEM : DMRG_EHIP, hipGetErrorString(e));
     } catch (const std::bad_alloc&) {

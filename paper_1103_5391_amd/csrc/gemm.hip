@@ -327,6 +327,228 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
 }
 
 // ---------------------------------------------------------------------------------------
+// stage 2 for several right-hand sides that share the operators (the chains of the 4-RHS
+// mode): the tile list of the owners' plans, chain c of problem p at probs[NR p + c].  Each
+// chunk's left-factor fragments are loaded once for all NR chains.  Every chain's products run
+// in the order of the single-vector kernel above, so its results have the same bits.  A chain
+// whose skip flag is set is computed (its buffers are allocated) but not stored.  (Stage 1
+// stays per chain: four chains' accumulators and fragments there exceed the registers.)
+// ---------------------------------------------------------------------------------------
+// The chains' problem pointers of a tile and which of them are live.
+template <int NR>
+__device__ __forceinline__ bool chain_ptrs(const ProbPtrs* __restrict__ probs, int prob,
+                                           ProbPtrs (&PP)[NR], bool (&act)[NR]) {
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        PP[q] = probs[NR * prob + q];
+        act[q] = !(PP[q].skip && *PP[q].skip);
+        any |= act[q];
+    }
+    return any;
+}
+
+// kloop for NR chains sharing the A fragments.
+template <class P, int MI, int NJ, int NR, class Load>
+__device__ __forceinline__ void kloop_mr(typename P::acc_t (&acc)[NR][MI][NJ], int c0, int step,
+                                         int nch, Load load) {
+    using frag_t = typename P::frag_t;
+    if (c0 >= nch) return;
+    const int last = c0 + (nch - 1 - c0) / step * step;
+    frag_t a0[MI], b0[NR][NJ], a1[MI], b1[NR][NJ];
+    auto mma = [&](const frag_t (&fa)[MI], const frag_t (&fb)[NR][NJ]) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+#pragma unroll
+            for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+                for (int nj = 0; nj < NJ; ++nj) acc[q][mi][nj] = P::mma(fa[mi], fb[q][nj], acc[q][mi][nj]);
+    };
+    load(c0, a0, b0);
+    int c = c0;
+    for (; c + step <= last; c += 2 * step) {
+        load(c + step, a1, b1);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a0, b0);
+        load(min(c + 2 * step, last), a0, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(a1, b1);
+    }
+    if (c <= last) mma(a0, b0);
+}
+
+template <class P, int MI, int NJ, int NW, int NR>
+__device__ __forceinline__ void stage2_tile_mr(const Tile& tl, const S2Block& B,
+                                               const Segment* __restrict__ segs,
+                                               const ProbPtrs (&PP)[NR], const bool (&act)[NR],
+                                               int64_t (&ctab)[kChunkTab][3],
+                                               double (&red)[NW][16 * NJ][kTile + 1]) {
+    using op_t = typename P::op_t;
+    using ws_t = typename P::ws_t;
+    using acc_t = typename P::acc_t;
+    using frag_t = typename P::frag_t;
+    constexpr int TN = 16 * NJ;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);   // wave-uniform
+    const int g = lane >> 4, r = lane & 15;
+    const int split = B.Y.split;
+    const op_t* pa[MI];
+#pragma unroll
+    for (int i = 0; i < MI; ++i) {
+        const int pnl = tl.m0 / kPanel + i;
+        pa[i] = static_cast<const op_t*>(PP[0].Lops) + B.Aoff * P::PER +
+                (((int64_t)pnl * B.nch) * 4 + g) * (kPanel * lane_elems<P>()) + r * lane_elems<P>();
+    }
+    int pl[NJ], col[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int n = min(tl.n0 + 16 * j + r, B.N - 1);
+        pl[j] = n >= split;
+        col[j] = n - pl[j] * split;
+    }
+    acc_t acc[NR][MI][NJ];
+#pragma unroll
+    for (int q = 0; q < NR; ++q)
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < NJ; ++nj) zero<P>(acc[q][mi][nj]);
+    // pass 1: segment 0 (H_S) from each chain's input vector
+    const Segment s0 = segs[B.seg0];
+    const int nch0 = (s0.K + P::CK - 1) / P::CK;
+    {
+        int64_t bcol[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j)
+            bcol[j] = s0.B.off + pl[j] * s0.B.poff + (int64_t)col[j] * s0.B.ld;
+        auto load = [&](int c, frag_t (&fa)[MI], frag_t (&fb)[NR][NJ]) {
+            const int64_t ga = (int64_t)c * chunk_elems<P>();
+#pragma unroll
+            for (int i = 0; i < MI; ++i) fa[i] = P::load_op(pa[i] + ga);
+            const int kb = c * P::CK + P::KPL * g;
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    double v[P::KPL];
+                    load_clamped<P>(PP[q].x, bcol[j], kb, s0.K, 1, v);
+                    fb[q][j] = P::from(v);
+                }
+        };
+        kloop_mr<P, MI, NJ, NR>(acc, wave, NW, nch0, load);
+    }
+    // pass 2: the workspace chunks of segments 1.. from each chain's stage-1 intermediate
+    const int nT = B.nch - nch0;
+    if (nT > 0 && nT <= kChunkTab) {
+        for (int t = threadIdx.x; t < nT; t += blockDim.x) {
+            const int c = nch0 + t;
+            int si = 1;
+            Segment sg = segs[B.seg0 + 1];
+            while (c >= sg.ch0 + (sg.K + P::CK - 1) / P::CK) sg = segs[B.seg0 + ++si];
+            ctab[t][0] = sg.B.off - (int64_t)sg.ch0 * P::CK;
+            ctab[t][1] = sg.B.poff;
+            ctab[t][2] = sg.B.ld;
+        }
+        __syncthreads();
+        auto load = [&](int c, frag_t (&fa)[MI], frag_t (&fb)[NR][NJ]) {
+            const int64_t ga = (int64_t)c * chunk_elems<P>();
+#pragma unroll
+            for (int i = 0; i < MI; ++i) fa[i] = P::load_op(pa[i] + ga);
+            const int64_t* e = ctab[c - nch0];
+            const int64_t kb = (int64_t)c * P::CK + P::KPL * g;
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) {
+                    double v[P::KPL];
+                    load_run<P>(static_cast<const ws_t*>(PP[q].T),
+                                e[0] + pl[j] * e[1] + (int64_t)col[j] * e[2] + kb, v);
+                    fb[q][j] = P::from(v);
+                }
+        };
+        const int cw = nch0 + ((wave - nch0) % NW + NW) % NW;
+        kloop_mr<P, MI, NJ, NR>(acc, cw, NW, B.nch, load);
+    } else {
+        for (int s = 1; s < B.nseg; ++s) {
+            const Segment sg = segs[B.seg0 + s];
+            int64_t bcol[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+                bcol[j] = sg.B.off + pl[j] * sg.B.poff + (int64_t)col[j] * sg.B.ld;
+            const int nch = (sg.K + P::CK - 1) / P::CK;
+            const int c0 = ((wave - sg.ch0) % NW + NW) % NW;
+            auto load = [&](int c, frag_t (&fa)[MI], frag_t (&fb)[NR][NJ]) {
+                const int64_t ga = (int64_t)(sg.ch0 + c) * chunk_elems<P>();
+#pragma unroll
+                for (int i = 0; i < MI; ++i) fa[i] = P::load_op(pa[i] + ga);
+                const int kb = c * P::CK + P::KPL * g;
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+#pragma unroll
+                    for (int j = 0; j < NJ; ++j) {
+                        double v[P::KPL];
+                        load_run<P>(static_cast<const ws_t*>(PP[q].T), bcol[j] + kb, v);
+                        fb[q][j] = P::from(v);
+                    }
+            };
+            kloop_mr<P, MI, NJ, NR>(acc, c0, NW, nch, load);
+        }
+    }
+    // the waves' partial tiles summed in LDS in a fixed order, one chain after another
+    const View t0 = B.T0, yv = B.Y;
+    const int m = threadIdx.x & 31;
+    constexpr int kCols = 2 * NW;
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        if (!act[q]) continue;                          // the same in every thread
+#pragma unroll
+        for (int mi = 0; mi < MI; ++mi)
+#pragma unroll
+            for (int nj = 0; nj < NJ; ++nj)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    red[wave][16 * nj + r][16 * mi + P::row(g, v)] = (double)acc[q][mi][nj][v];
+        __syncthreads();
+        const ws_t* __restrict__ Tws = static_cast<const ws_t*>(PP[q].T);
+        double* __restrict__ Y = PP[q].y;
+#pragma unroll
+        for (int qq = 0; qq < TN / kCols; ++qq) {
+            const int n = (threadIdx.x >> 5) + kCols * qq;
+            const int gm = tl.m0 + m, gn = tl.n0 + n;
+            if (gm < B.M && gn < B.N) {
+                double v = red[0][n][m];
+#pragma unroll
+                for (int w = 1; w < NW; ++w) v += red[w][n][m];
+                const int p = gn >= split;
+                const int c = gn - p * split;
+                const double init = (double)Tws[t0.off + p * t0.poff + (int64_t)c * t0.ld + gm];
+                Y[yv.off + p * yv.poff + (int64_t)c * yv.ld + gm] = init + v;
+            }
+        }
+        __syncthreads();                                // red is written again for the next chain
+    }
+}
+
+template <class P, int NJ, int NW, int NR>
+__global__ __launch_bounds__(64 * NW, 2) void stage2_mr(const S2Block* __restrict__ blks,
+                                                        const Segment* __restrict__ segs,
+                                                        const Tile* __restrict__ tiles,
+                                                        const ProbPtrs* __restrict__ probs) {
+    const Tile tl = tiles[blockIdx.x];
+    if (tl.blk < 0) return;   // padding of the XCD-ordered list
+    const S2Block B = blks[tl.blk];
+    ProbPtrs PP[NR];
+    bool act[NR];
+    if (!chain_ptrs<NR>(probs, B.prob, PP, act)) return;
+    __shared__ int64_t ctab[kChunkTab][3];
+    __shared__ double red[NW][16 * NJ][kTile + 1];
+    if (tl.half)
+        stage2_tile_mr<P, 1, NJ, NW, NR>(tl, B, segs, PP, act, ctab, red);
+    else
+        stage2_tile_mr<P, 2, NJ, NW, NR>(tl, B, segs, PP, act, ctab, red);
+}
+
+// ---------------------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------------------
 namespace {
@@ -358,6 +580,16 @@ hipError_t launch2(int narrow, const S2Block* blks, const Segment* segs, const T
 }
 
 }  // namespace
+
+// Stage 2 of the chains of the 4-RHS mode in one launch (FP64, narrow tiles): the owners' tile
+// list, chain c of problem p at probs[kMultiRhs p + c].
+hipError_t launch_stage2_mr(const S2Block* blks, const Segment* segs, const Tile* tiles,
+                            int ntiles, const ProbPtrs* probs, hipStream_t st) {
+    if (ntiles == 0) return hipSuccess;
+    hipLaunchKernelGGL((stage2_mr<PF64, kTile2NN / 16, kWaves, kMultiRhs>), dim3(ntiles),
+                       dim3(64 * kWaves), 0, st, blks, segs, tiles, probs);
+    return hipGetLastError();
+}
 
 // prec: 0 FP64, 1 FP32, 2 BF16x3, 3 BF16x6 (the operator buffers and workspace must match);
 // narrow: the tiles are kTile x kTile1NN (else kTile x kTile1N)

@@ -14,6 +14,7 @@ constexpr int kTile2NN = 16;        // narrow stage-2 tiles are kTile x kTile2NN
 constexpr int kChunk = 16;          // K depth of one FP64/FP32 chunk (4 MFMA K-steps of 4)
 constexpr int kChunkMax = 32;       // K depth of one BF16 chunk (one 16x16x32 MFMA)
 constexpr int kWaves = 4;           // waves per work group (split-K among them)
+constexpr int kMultiRhs = 4;        // right-hand sides of the shared-operator stage kernels
 constexpr int kVecThreads = 256;    // threads per block of the vector kernels
 constexpr int kVecMaxBlocks = 1024; // blocks per problem of a vector pass (rows of partial sums)
 constexpr int kDSlots = 15;         // basis slots per Lanczos reduction launch (4 values each,

@@ -409,6 +409,57 @@ def test_tst_chains_parity(env, name, kdim, tau):
     h.destroy()
 
 
+@pytest.mark.parametrize("name", ["chain12_m30", "chain8_m17_odd", "chain14_m25_off",
+                                  "ladder16_m1000"])
+def test_tst_chains_shared_operator_stage2_bitwise(env, name):
+    """With narrow tiles in both stages (FP64), stage 2 of the 4-RHS mode runs all four chains
+    of a tile in one work group, loading the left factors once: each chain equals, bit for bit,
+    one step of its own vector through the single-vector path, in graph mode too."""
+    torch, L = env
+    say("shared-operator chains", name)
+    h = L.dmrg_create(problem(name))
+    h.set_gemm(L.DMRG_GEMM_STAGE1_NARROW | L.DMRG_GEMM_STAGE2_NARROW)
+    n = h.n
+    tau, kdim = 0.05, 15
+    xds = [_dev(torch, I.random_psi(n, np.random.default_rng(I.SEED_BASE + 700 + k)))
+           for k in range(4)]
+    for graph in (False, True):
+        h.set_graph(graph)
+        yds = [torch.full_like(xds[0], float("nan")) for _ in range(4)]
+        h.tst_chains(xds, tau, kdim, yds)
+        for k in range(4):
+            one = torch.empty_like(xds[k])
+            h.krylov_expm(xds[k], one, tau, kdim, 1, info=False)
+            torch.cuda.synchronize()
+            assert torch.equal(one, yds[k]), (graph, k)
+    h.destroy()
+
+
+def test_tst_chains_shared_operator_stage2_with_breakdown(env):
+    """One chain starts from an eigenvector and breaks down after one vector while the other
+    three go on: the shared-operator stage 2 leaves the broken chain's buffers alone, and every
+    chain still equals its single-vector step bit for bit."""
+    torch, L = env
+    say("shared-operator chains with a breakdown")
+    pb = problem("chain6_exact")
+    h = L.dmrg_create(pb)
+    h.set_gemm(L.DMRG_GEMM_STAGE1_NARROW | L.DMRG_GEMM_STAGE2_NARROW)
+    n = h.n
+    wv, vv = np.linalg.eigh(M.superblock_matrix(pb))
+    xs = [np.concatenate([vv[:, 5], np.zeros(n)])] + \
+         [I.random_psi(n, np.random.default_rng(I.SEED_BASE + 710 + k)) for k in range(3)]
+    xds = [_dev(torch, x) for x in xs]
+    yds = [torch.full_like(xds[0], float("nan")) for _ in range(4)]
+    _, infos = h.tst_chains(xds, 0.3, 12, yds)
+    assert infos[0]["k_eff"] == 1 and all(i["k_eff"] > 1 for i in infos[1:])
+    for k in range(4):
+        one = torch.empty_like(xds[k])
+        h.krylov_expm(xds[k], one, 0.3, 12, 1, info=False)
+        torch.cuda.synchronize()
+        assert torch.equal(one, yds[k]), k
+    h.destroy()
+
+
 def test_batch_tst_chains_matches_per_handle(env):
     """4-RHS mode of a batch (odd and even lengths, 12 chains in common launches): bit for bit
     the per-handle chains, and the oracle to 1e-10."""
@@ -434,6 +485,19 @@ def test_batch_tst_chains_matches_per_handle(env):
             assert torch.equal(own[k], yds[4 * i + k])
             assert inf1[k] == infos[4 * i + k]
             assert rel(_host(yds[4 * i + k]), ys[k]) <= KR_TOL
+    # narrow tiles in both stages: the shared-operator stage 2 over the three owners
+    narrow = L.DMRG_GEMM_STAGE1_NARROW | L.DMRG_GEMM_STAGE2_NARROW
+    b.set_gemm(narrow)
+    zds = [torch.full_like(y, float("nan")) for y in yds]
+    b.batch_tst_chains(xds, tau, kdim, zds)
+    for i, h in enumerate(hs):
+        h.set_gemm(narrow)
+        for k in range(4):
+            one = torch.empty_like(xds[4 * i + k])
+            h.krylov_expm(xds[4 * i + k], one, tau, kdim, 1, info=False)
+            torch.cuda.synchronize()
+            assert torch.equal(one, zds[4 * i + k]), (i, k)
+            assert rel(_host(zds[4 * i + k]), _host(yds[4 * i + k])) <= 1e-13
     b.destroy()
     for h in hs:
         h.destroy()
