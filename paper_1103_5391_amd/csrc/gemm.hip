@@ -334,14 +334,14 @@ __global__ __launch_bounds__(64 * NW, 3) void stage2(const S2Block* __restrict__
 // whose skip flag is set is computed (its buffers are allocated) but not stored.  (Stage 1
 // stays per chain: four chains' accumulators and fragments there exceed the registers.)
 // ---------------------------------------------------------------------------------------
-// The chains' problem pointers of a tile and which of them are live.
+// The problem pointers of chains c0 .. c0 + NR - 1 of a tile and which of them are live.
 template <int NR>
-__device__ __forceinline__ bool chain_ptrs(const ProbPtrs* __restrict__ probs, int prob,
+__device__ __forceinline__ bool chain_ptrs(const ProbPtrs* __restrict__ probs, int prob, int c0,
                                            ProbPtrs (&PP)[NR], bool (&act)[NR]) {
     bool any = false;
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
-        PP[q] = probs[NR * prob + q];
+        PP[q] = probs[kMultiRhs * prob + c0 + q];
         act[q] = !(PP[q].skip && *PP[q].skip);
         any |= act[q];
     }
@@ -539,7 +539,7 @@ __global__ __launch_bounds__(64 * NW, 2) void stage2_mr(const S2Block* __restric
     const S2Block B = blks[tl.blk];
     ProbPtrs PP[NR];
     bool act[NR];
-    if (!chain_ptrs<NR>(probs, B.prob, PP, act)) return;
+    if (!chain_ptrs<NR>(probs, B.prob, NR * (int)blockIdx.y, PP, act)) return;
     __shared__ int64_t ctab[kChunkTab][3];
     __shared__ double red[NW][16 * NJ][kTile + 1];
     if (tl.half)
@@ -586,7 +586,10 @@ hipError_t launch2(int narrow, const S2Block* blks, const Segment* segs, const T
 hipError_t launch_stage2_mr(const S2Block* blks, const Segment* segs, const Tile* tiles,
                             int ntiles, const ProbPtrs* probs, hipStream_t st) {
     if (ntiles == 0) return hipSuccess;
-    hipLaunchKernelGGL((stage2_mr<PF64, kTile2NN / 16, kWaves, kMultiRhs>), dim3(ntiles),
+    // all chains in one work group (two per work group, with a second grid row for the other
+    // two, measured the same)
+    constexpr int NR = kMultiRhs;
+    hipLaunchKernelGGL((stage2_mr<PF64, kTile2NN / 16, kWaves, NR>), dim3(ntiles, kMultiRhs / NR),
                        dim3(64 * kWaves), 0, st, blks, segs, tiles, probs);
     return hipGetLastError();
 }
