@@ -36,8 +36,8 @@ PEAK_HBM_GBS = 8000.0
 MEASURED_TRAFFIC = {
     "workload": "ladder16_m1000",
     "source": "paper_1103_5391_amd/csrc/gemm.hip",
-    "source_sha256": "9cd19620cd124491004db22a3d04538ef1e390b35a4c60743f9748d8cf8d8a77",
-    "bytes": {"stage2<PF64, 1, 4>": 85.24e6 + 5.19e6, "stage1<PF64, 2>": 30.29e6 + 43.54e6},
+    "source_sha256": "cc6bbb26839b41a745bf391d466692f0e26921b51a912326ef45acc1a9f6c644",
+    "bytes": {"stage2<PF64, 1, 4>": 85.52e6 + 5.20e6, "stage1<PF64, 2>": 30.24e6 + 43.54e6},
     "profile": "profiles/stage2_fp64_ladder16_m1000_kernel_stats.txt",
 }
 
