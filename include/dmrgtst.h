@@ -264,7 +264,7 @@ int dmrg_autotune(dmrg_handle h, int32_t reps, double* out);
  * under the key (an entry of the same key is replaced).  out: NULL or 10 doubles receiving the
  * timings as in dmrg_autotune (those stored with the entry on a hit); hit: NULL or receives 1
  * on a hit, else 0.  The file is replaced by renaming a complete temporary file
- * (path.tmp.<pid>), so concurrent readers see the old or the new file; concurrent writers may
+ * (path.tmp.<pid>.<n>), so concurrent readers see the old or the new file; concurrent writers may
  * drop each other's new entries, which are timed again on their next miss.  Returns DMRG_EIO
  * (with the reason in dmrg_last_error) when the file exists but cannot be read or is not a
  * cache of this format (it is then left untouched), or when it cannot be written (the tuned

@@ -9,6 +9,7 @@
 #include <unistd.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cerrno>
 #include <charconv>
 #include <cmath>
@@ -389,7 +390,11 @@ std::string tune_cache_put(const std::string& path, const TuneEntry& e) {
              es.end());
     es.push_back(e);
     const std::string text = serialise(es);
-    const std::string tmp = path + ".tmp." + std::to_string((long)getpid());
+    // unique per process and per call, so concurrent stores (other processes, other threads)
+    // never share a temporary file
+    static std::atomic<unsigned> seq{0};
+    const std::string tmp = path + ".tmp." + std::to_string((long)getpid()) + "." +
+                            std::to_string(seq.fetch_add(1));
     FILE* f = std::fopen(tmp.c_str(), "wb");
     if (!f) return "cannot write " + tmp + ": " + std::strerror(errno);
     const bool ok = std::fwrite(text.data(), 1, text.size(), f) == text.size() &&

@@ -36,9 +36,10 @@ std::string tune_cache_find(const std::string& path, const std::string& key, Tun
                             bool& found);
 
 // Stores one entry (replacing an entry of the same key): the file is read, updated and written
-// to a temporary file in the same directory that is then renamed over it, so readers never see
-// a partial file.  Writers that overlap may drop each other's new entries (the lost key is timed
-// again on its next lookup).  Returns the reason on error.
+// to a temporary file in the same directory (path.tmp.<pid>.<n>, n counting this process's
+// stores) that is then renamed over it, so readers never see a partial file.  Writers that
+// overlap may drop each other's new entries (the lost key is timed again on its next lookup).
+// Returns the reason on error.
 std::string tune_cache_put(const std::string& path, const TuneEntry& e);
 
 }  // namespace dmrg

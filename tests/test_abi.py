@@ -257,3 +257,31 @@ def test_tune_cache_write_errors(lib, tmp_path):
     assert lib.dmrg_tune_cache_store(None, b"a", 0, None) == -1
     assert lib.dmrg_autotune_cached(None, b"x", 1, None, None) == -1
     assert lib.dmrg_batch_autotune_cached(None, b"x", 1, None, None) == -1
+
+
+def test_tune_cache_concurrent_stores_leave_a_valid_file(lib, tmp_path):
+    """Threads storing different keys at once: every rename installs a complete file (some
+    entries may be lost to overlapping writers, never the file's integrity), and no temporary
+    file is left behind."""
+    import json
+    import threading
+    path = tmp_path / "tune.json"
+    errors = []
+
+    def worker(t):
+        try:
+            for i in range(20):
+                L.tune_cache_store(path, f"k{t}-{i}", 0, [float(i)] * 10)
+        except Exception as e:  # noqa: BLE001 - reported below
+            errors.append(e)
+
+    threads = [threading.Thread(target=worker, args=(t,)) for t in range(4)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    doc = json.loads(path.read_text(encoding="utf-8"))
+    keys = [e["key"] for e in doc["entries"]]
+    assert len(keys) == len(set(keys)) and len(keys) >= 1
+    assert not list(tmp_path.glob("*.tmp.*"))
