@@ -22,6 +22,12 @@ namespace dmrg {
 namespace {
 
 typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d4u __attribute__((ext_vector_type(4), aligned(8)));   // 8-byte aligned
+
+// Four consecutive doubles from global memory at an 8-byte aligned address.
+__device__ __forceinline__ d4 ld4u(const double* p) {
+    return *((const __attribute__((address_space(1))) d4u*)p);
+}
 
 // Both planes of one operand element (zero outside the matrix; imaginary part zero for real
 // operands); the access mode is a template parameter.
@@ -100,6 +106,31 @@ __global__ __launch_bounds__(64) void k_zgemm(const ZTile* __restrict__ tiles, Z
         }
     double ar[2][2][4], ai[2][2][4], br[2][2][4], bi[2][2][4];   // [buffer][half][u]
     auto load = [&](int buf, int k0) {
+        if constexpr (AM == ZM_CT && BM == ZM_COL) {
+            // both operands run along K in memory: a chunk inside K is four consecutive values
+            // per lane and plane, one vector load each (rows and columns outside the matrix
+            // read row or column 0 and are zeroed)
+            if (k0 + 16 <= t.K) {
+                const int kk = k0 + 4 * g;
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int i = t.m0 + 16 * h + r, j = t.n0 + 16 * h + r;
+                    const bool oi = i < t.M, oj = j < t.N;
+                    const int64_t at = t.aoff + (int64_t)(oi ? i : 0) * t.lda + kk;
+                    const int64_t bt = t.boff + (int64_t)(oj ? j : 0) * t.ldb + kk;
+                    const d4 are = ld4u(A + at), aim = ld4u(A + at + t.aim);
+                    const d4 bre = ld4u(B + bt), bim = ld4u(B + bt + t.bim);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        ar[buf][h][u] = oi ? are[u] : 0.0;
+                        ai[buf][h][u] = oi ? -aim[u] : 0.0;   // conjugate transpose
+                        br[buf][h][u] = oj ? bre[u] : 0.0;
+                        bi[buf][h][u] = oj ? bim[u] : 0.0;
+                    }
+                }
+                return;
+            }
+        }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int k = k0 + 4 * g + u;
