@@ -553,6 +553,44 @@ __device__ __forceinline__ void hh_regs(const int d, dv2* __restrict__ a, double
     }
 }
 
+// The Sturm count of T - x I (the number of negative pivots of its L D L^T, that is of the
+// eigenvalues below x), with the arithmetic of the multisection rounds in heig: the hardware
+// reciprocal with one Newton step, runs of kSturmRun steps without the tiny-pivot guard, a run
+// that ends in a NaN taken again with it.
+__device__ __forceinline__ int sturm_count(int d, const double* __restrict__ dg,
+                                           const double* __restrict__ e2, double x) {
+    double q = dg[0] - x;
+    int cnt = q < 0.0;
+    auto step = [&](double di, double ei, bool guard) {
+        if (guard && fabs(q) < 1e-300) q = -1e-300;
+        const double r0 = __builtin_amdgcn_rcp(q);
+        const double r = fma(fma(-q, r0, 1.0), r0, r0);
+        q = (di - x) - ei * r;
+        cnt += q < 0.0;
+    };
+    int i = 1;
+    for (; i + kSturmRun <= d; i += kSturmRun) {
+        double dr[kSturmRun], er[kSturmRun];
+#pragma unroll
+        for (int t = 0; t < kSturmRun; ++t) {
+            dr[t] = dg[i + t];
+            er[t] = e2[i - 1 + t];
+        }
+        const double q0 = q;
+        const int c0 = cnt;
+#pragma unroll
+        for (int t = 0; t < kSturmRun; ++t) step(dr[t], er[t], false);
+        if (__builtin_isnan(q)) {
+            q = q0;
+            cnt = c0;
+#pragma unroll
+            for (int t = 0; t < kSturmRun; ++t) step(dr[t], er[t], true);
+        }
+    }
+    for (; i < d; ++i) step(dg[i], e2[i - 1], true);
+    return cnt;
+}
+
 // Eigen-decomposition of rho_p up to the back-transformation, one work group per sector
 // (LAPACK's path for Hermitian matrices):
 //   1. Householder reduction to a real tridiagonal matrix: step k takes the reflector
@@ -745,6 +783,15 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
         s_tn = fmax(tn, 1e-300);
     }
     __syncthreads();
+    // one shared round: the counts at NT equally spaced interior points of the interval (every
+    // thread one point, the arithmetic of the rounds below), from which each eigenvalue starts:
+    // the first point whose count exceeds its index and the point before it (a binary search
+    // for a change of the predicate count > j, which brackets eigenvalue j whatever the counts
+    // do in between)
+    __shared__ int s_cnt0[NT];
+    const double w0 = (s_hi - s_lo) / (NT + 1);
+    s_cnt0[tid] = sturm_count(d, dg, e2, s_lo + w0 * (tid + 1));
+    __syncthreads();
     {
         // GB lanes per eigenvalue (a power of two inside a wavefront), kSturmPts points per lane
         // (independent Sturm sequences interleaved in one pass over T): the lanes count at
@@ -760,7 +807,13 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
         const int jend = (d + jslots - 1) / jslots * jslots;
         for (int j0 = tid / GB; tid < nact && j0 < jend; j0 += jslots) {
             const int j = j0 < d ? j0 : d - 1;
-            double lo = s_lo, hi = s_hi;
+            int a = -1, b = NT;                         // count(a) <= j < count(b) (virtual ends)
+            while (b - a > 1) {
+                const int m = (a + b) >> 1;
+                if (s_cnt0[m] > j) b = m; else a = m;
+            }
+            double lo = a < 0 ? s_lo : s_lo + w0 * (a + 1);
+            double hi = b >= NT ? s_hi : s_lo + w0 * (b + 1);
             for (int it = 0; it < 256; ++it) {
                 if (hi - lo <= 4.440892098500626e-16 * s_tn) break;
                 const double step = (hi - lo) / (GB * P + 1);
