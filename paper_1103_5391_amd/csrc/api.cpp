@@ -1763,7 +1763,7 @@ int dmrg_density_truncate(dmrg_handle h, const double* const* vecs, const double
         HIP_TRY(h, h->dDA.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDV.alloc(2 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDZ.alloc(sizeof(double) * (size_t)aoff));
-        HIP_TRY(h, h->dDS.alloc(5 * sizeof(double) * (size_t)aoff));
+        HIP_TRY(h, h->dDS.alloc(6 * sizeof(double) * (size_t)aoff));
         HIP_TRY(h, h->dDT.alloc(2 * sizeof(double) * (size_t)toff));
         HIP_TRY(h, h->dDEv.alloc(sizeof(double) * (size_t)eoff));
         HIP_TRY(h, h->dDKept.alloc(sizeof(int) * (size_t)eoff));

@@ -919,11 +919,14 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
         // to 1.  A last pass over all elements scales the
         // columns.  Z and the factors are row-major [i][j] (consecutive threads, consecutive
         // addresses).
-        double* u0 = Sb + 5 * B.aoff;                   // 1 / pivot
-        double* u1 = u0 + (int64_t)d * d;
-        double* u2 = u1 + (int64_t)d * d;
-        double* lm = u2 + (int64_t)d * d;
-        double* pv = lm + (int64_t)d * d;               // 1 where rows i, i+1 were swapped
+        // the factors of T - lam_j I, packed so that a row takes one or two wide accesses (the
+        // passes are bound by memory instructions): row i of U (1 / pivot, the superdiagonals
+        // 1 and 2, an unused slot) at fu[i d + j], row i of L and the swap flag (1 where rows
+        // i, i + 1 were exchanged) at fl[i d + j]; consecutive threads, consecutive records
+        typedef double f4u __attribute__((ext_vector_type(4), aligned(8)));
+        typedef double f2u __attribute__((ext_vector_type(2), aligned(8)));
+        f4u* fu = reinterpret_cast<f4u*>(Sb + 6 * B.aoff);
+        f2u* fl = reinterpret_cast<f2u*>(Sb + 6 * B.aoff + 4 * (int64_t)d * d);
         double* sc = reinterpret_cast<double*>(vv1);    // per eigenvector: 1 / |z|
         const double tiny = 2.220446049250313e-16 * s_tn;
         auto first_of_cluster = [&](int j) { return j == 0 || lam[j] - lam[j - 1] > kClusterGap * s_tn; };
@@ -947,9 +950,10 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
                     const int i = max(i0 - t, 0);
                     const int64_t at = (int64_t)i * d + j;
                     zv[t] = Z[at];
-                    a0[t] = u0[at];
-                    a1[t] = u1[at];
-                    a2[t] = u2[at];
+                    const f4u f = fu[at];
+                    a0[t] = f[0];
+                    a1[t] = f[1];
+                    a2[t] = f[2];
                 }
 #pragma unroll
                 for (int t = 0; t < kInvRun; ++t) {
@@ -975,8 +979,9 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
                     const int i = min(i0 + t, d - 2);
                     const int64_t at = (int64_t)i * d + j;
                     zn[t] = Z[at + d];
-                    pw[t] = pv[at];
-                    lw[t] = lm[at];
+                    const f2u f = fl[at];
+                    lw[t] = f[0];
+                    pw[t] = f[1];
                 }
 #pragma unroll
                 for (int t = 0; t < kInvRun; ++t) {
@@ -1021,21 +1026,15 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
                     const double piv = fabs(dd) >= tiny ? dd : (dd < 0.0 ? -tiny : tiny);
                     const double ip = recip(piv);
                     m = sub * ip;
-                    u0[at] = ip;
-                    u1[at] = du;
-                    u2[at] = 0.0;
-                    lm[at] = m;
-                    pv[at] = 0.0;
+                    fu[at] = (f4u){ip, du, 0.0, 0.0};
+                    fl[at] = (f2u){m, 0.0};
                     dd = nd - m * du;
                     du = nu;
                 } else {
                     const double is = recip(sub);
                     m = dd * is;
-                    u0[at] = is;
-                    u1[at] = nd;
-                    u2[at] = nu;
-                    lm[at] = m;
-                    pv[at] = 1.0;
+                    fu[at] = (f4u){is, nd, nu, 0.0};
+                    fl[at] = (f2u){m, 1.0};
                     dd = du - m * nd;
                     du = -m * nu;
                     const double tt = cur;
@@ -1048,9 +1047,7 @@ __device__ __forceinline__ void heig(const DBlock B, const int blk, dv2* __restr
             {
                 const int64_t at = (int64_t)(d - 1) * d + j;
                 const double piv = fabs(dd) >= tiny ? dd : (dd < 0.0 ? -tiny : tiny);
-                u0[at] = 1.0 / piv;
-                u1[at] = 0.0;
-                u2[at] = 0.0;
+                fu[at] = (f4u){1.0 / piv, 0.0, 0.0, 0.0};
                 Z[at] = cur;
             }
             // the first solve: backward substitution U^-1
